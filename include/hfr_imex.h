@@ -1,0 +1,319 @@
+/*
+ * hfr_imex.h -- C ABI of the MI355X (gfx950) hot path of hybridized
+ * implicit-explicit flux reconstruction (Pereira & Vermeire, "Hybridized
+ * Implicit-Explicit Flux Reconstruction Methods", arXiv 2401.16632).
+ *
+ * Scope: two-dimensional Euler equations on bilinear quadrilaterals of one
+ * polynomial degree p (1..5), Gauss-Legendre solution and flux points,
+ * DG-recovering correction functions.  The explicit region uses standard FR
+ * (Section 2.1), the implicit region hybridized FR (Section 2.2) advanced by
+ * the padded SDIRK part of an additive IMEX Runge-Kutta pair (Sections 3.1
+ * and 4), coupled through standard FR fluxes on the interface Upsilon
+ * (eq:hfrimex).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - All device pointers are HIP device memory owned by the caller unless
+ *    stated otherwise.  Streams are hipStream_t passed as void* (NULL = the
+ *    null stream).  Calls are asynchronous on that stream unless stated.
+ *  - Element state layout ("SoA"): double u[4][N][Np], variable-major, then
+ *    element, then solution point; Np = (p+1)^2 and point index j*(p+1)+i
+ *    with i the xi index.  Variables: rho, rho*u, rho*v, E.  N is the number
+ *    of elements of the set the array covers (all, implicit or explicit, in
+ *    the order returned by fr_mesh_get_maps).
+ *  - Trace layout: double uhat[Ntp][4] (point-major).  Trace point id =
+ *    trace_face * (p+1) + (point index along the owner, counter-clockwise).
+ *  - Canonical numbering: local face f of a quad joins local vertices f and
+ *    f+1 (counter-clockwise; f=0: eta=-1, 1: xi=+1, 2: eta=+1, 3: xi=-1);
+ *    faces are numbered on first encounter in (element, local face) order,
+ *    the first element being the owner; trace faces (both sides implicit)
+ *    are numbered densely in face order.
+ *  - Every call returns an fr_status.  No call throws.  On a non-OK status
+ *    fr_last_error() returns a message for the calling thread.  Asynchronous
+ *    device faults surface as FR_E_DEVICE at the next call that
+ *    synchronises.
+ */
+#ifndef HFR_IMEX_H
+#define HFR_IMEX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FR_MAX_ORDER 5
+
+typedef enum {
+    FR_OK = 0,
+    FR_E_INVALID = -1,       /* bad argument (null pointer, size, range)   */
+    FR_E_MESH = -2,          /* inconsistent or clockwise mesh             */
+    FR_E_NOMEM = -3,         /* device or host allocation failed           */
+    FR_E_DEVICE = -4,        /* HIP runtime error                          */
+    FR_E_NOT_CONVERGED = -5, /* Newton or Krylov iteration cap reached     */
+    FR_E_NONFINITE = -6,     /* NaN/Inf met in a residual                  */
+    FR_E_UNSUPPORTED = -7    /* option not built for this configuration    */
+} fr_status;
+
+enum { FR_BC_INTERIOR = 0, FR_BC_WALL = 1, FR_BC_FARFIELD = 2 };
+enum { FR_FACE_EXPLICIT = 0, FR_FACE_UPSILON = 1, FR_FACE_TRACE = 2,
+       FR_FACE_BOUNDARY = 3 };
+
+typedef struct fr_mesh_s* fr_mesh_t;       /* opaque, library-owned */
+typedef struct hfr_solver_s* hfr_solver_t; /* opaque, library-owned */
+
+/*
+ * Mesh description (host arrays, copied by fr_mesh_create).
+ *   node_xy[2*n_nodes]          vertex coordinates (x0,y0,x1,y1,...)
+ *   node_topo[n_nodes]          topological vertex id (periodic twins share
+ *                               one id); NULL = identity
+ *   elem_nodes[4*n_elems]       vertex ids, counter-clockwise
+ *   elem_face_bc[4*n_elems]     FR_BC_* per local edge; NULL = all interior
+ *   order                       polynomial degree p, 1..FR_MAX_ORDER
+ *   implicit_mask[n_elems]      1 = implicit (hybridized) element; if NULL
+ *                               an element is implicit iff its stiffness
+ *                               indicator E_s = area/perimeter (Section 5)
+ *                               is <= es_cutoff
+ *   gamma, uinf[4]              ratio of specific heats; far-field state
+ *   flags                       FR_MESH_HOST_ONLY: build the host tables
+ *                               only (maps and counts; no device upload,
+ *                               compute calls on it return FR_E_INVALID)
+ */
+#define FR_MESH_HOST_ONLY 1
+typedef struct {
+    int32_t n_nodes;
+    const double* node_xy;
+    const int32_t* node_topo;
+    int32_t n_elems;
+    const int32_t* elem_nodes;
+    const int8_t* elem_face_bc;
+    int32_t order;
+    const uint8_t* implicit_mask;
+    double es_cutoff;
+    double gamma;
+    double uinf[4];
+    int32_t flags;
+} fr_mesh_desc;
+
+typedef struct {
+    int32_t order, n_pts, n_elems, n_faces, n_implicit, n_explicit;
+    int32_t n_trace_faces, n_trace_points, n_upsilon, n_boundary;
+    int32_t n_loc;   /* element block size n = 4 (p+1)^2                  */
+    int32_t m_loc;   /* element trace block size m = 16 (p+1) (all faces) */
+    size_t device_table_bytes;
+} fr_mesh_info;
+
+/*
+ * fr_mesh_create: builds the skeleton (Section 2), the IMEX partition and
+ * Upsilon (Section 4), the flux-point-to-trace-point map of eq:assembly and
+ * the device tables.  Host-synchronous.  FR_E_MESH for a clockwise or
+ * folded element, an edge traversed twice, an unmatched edge without a
+ * boundary tag, a boundary tag on a matched edge or an element that is its
+ * own neighbour.
+ */
+fr_status fr_mesh_create(const fr_mesh_desc* desc, fr_mesh_t* out);
+void fr_mesh_destroy(fr_mesh_t mesh);
+fr_status fr_mesh_get_info(fr_mesh_t mesh, fr_mesh_info* out);
+
+/*
+ * fr_mesh_get_maps: copies host tables into caller buffers (any may be
+ * NULL): face_elem[2*Nf], face_local[2*Nf] (owner, neighbour; -1 for a
+ * boundary face's neighbour), face_kind[Nf] (FR_FACE_*),
+ * trace_map[Nim*4*(p+1)] (trace point of each flux point of each implicit
+ * element in its own counter-clockwise order, -1 off the trace),
+ * implicit_elems[Nim], explicit_elems[Nex], es[Ne], sol_xy[Ne*Np*2]
+ * (solution-point coordinates, element-major, point, then x/y).
+ */
+fr_status fr_mesh_get_maps(fr_mesh_t mesh, int32_t* face_elem,
+                           int32_t* face_local, int32_t* face_kind,
+                           int32_t* trace_map, int32_t* implicit_elems,
+                           int32_t* explicit_elems, double* es,
+                           double* sol_xy);
+
+/*
+ * fr_explicit_rhs: standard FR residual R = du/dt of eq:freq1 (Rusanov flux
+ * of Section 2.1 on every interior face, the same flux against a ghost state
+ * on boundary faces) for every explicit element.  At Upsilon faces the
+ * implicit neighbour's current state is used (eq:explicitimex).
+ *   u     [4][Ne][Np]   full state (device, read)
+ *   R_ex  [4][Nex][Np]  residual of the explicit elements (device, written)
+ */
+fr_status fr_explicit_rhs(fr_mesh_t mesh, const double* u, double* R_ex,
+                          void* stream);
+
+/* ----------------------------------------------------------------------- */
+/* Implicit (hybridized) stage                                             */
+/* ----------------------------------------------------------------------- */
+
+enum { HFR_PREC_FP64 = 0,   /* element blocks, LU and Schur in FP64        */
+       HFR_PREC_FP32 = 1 }; /* LU and Schur products in FP32 on MFMA       */
+enum { HFR_PC_FP64 = 0, HFR_PC_FP32 = 1, HFR_PC_BF16 = 2 };
+
+typedef struct {
+    int32_t precision;        /* HFR_PREC_*                                  */
+    int32_t precond;          /* HFR_PC_*: storage of the block-Jacobi inverse */
+    int32_t gmres_restart;    /* Krylov dimension before restart (<= 64)     */
+    int32_t gmres_max_iters;  /* total inner iterations per trace solve      */
+    double gmres_rtol;        /* relative residual target of a trace solve   */
+    int32_t newton_max_iters; /* per stage                                   */
+    double newton_tol;        /* stop when max(|h|inf,|g|inf) <=
+                                 newton_tol * max(1, |u*|inf)                */
+    int32_t keep_blocks;      /* 1: keep a copy of the element blocks
+                                 [A B; C D] (FP64) for inspection            */
+} hfr_opts;
+
+typedef struct {
+    int32_t iterations;       /* Krylov iterations of the last trace solve   */
+    int32_t restarts;
+    double rel_residual;      /* |t - L x| / |t| at exit (FP64)              */
+} hfr_solve_stats;
+
+typedef struct {
+    int32_t newton_iters;
+    int32_t gmres_iters;      /* summed over Newton iterations               */
+    double residual;          /* final max(|h|inf, |g|inf)                   */
+    double implicit_ms;       /* host wall time of the implicit solve        */
+} hfr_newton_stats;
+
+/*
+ * hfr_solver_create: allocates the solver's device workspace (library-owned;
+ * its size is reported in *workspace_bytes when non-NULL).
+ */
+fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* opts,
+                            size_t* workspace_bytes, hfr_solver_t* out);
+void hfr_solver_destroy(hfr_solver_t solver);
+
+/*
+ * hfr_residual: the stage residuals of eq:9oind / eq:23nffsd with the
+ * hybridized operator (eq:hfr1, eq:hfr2, eq:hfrimex):
+ *   h = u_im - ustar - aii_dt * R^im(u, uhat),  R = du/dt (sign reading of
+ *   the paper's inconsistent printed forms), g = transmission residual
+ *   collocated at the trace points (face mass diag(w_q J_f)).
+ *   u [4][Ne][Np] full state (explicit part used on Upsilon), uhat [Ntp][4],
+ *   ustar [4][Nim][Np]; outputs h [4][Nim][Np], g [Ntp][4], R_im
+ *   [4][Nim][Np]; any output may be NULL.
+ */
+fr_status hfr_residual(hfr_solver_t s, const double* u, const double* uhat,
+                       const double* ustar, double aii_dt, double* h,
+                       double* g, double* R_im, void* stream);
+
+/*
+ * hfr_assemble_condense: one Newton linearisation (Section 3.2): residuals,
+ * element blocks A, B, C, D (eq:elemA, eq:elemsystemB, as exact derivatives
+ * of h and g), per-element pivoted LU / Gauss-Jordan of A, X = A^-1 [B r],
+ * L^k = D^k - C^k X_B, t^k = s^k - C^k X_r with r = -h, s = -g, and the
+ * element-by-element assembly of eq:assembly into a block-sparse L and t
+ * (kept inside the solver).  Inputs as hfr_residual.
+ */
+fr_status hfr_assemble_condense(hfr_solver_t s, const double* u,
+                                const double* uhat, const double* ustar,
+                                double aii_dt, void* stream);
+
+/*
+ * hfr_trace_solve: solves L duhat = t (the condensed trace system of
+ * Section 3.2) by restarted GMRES with FP64 Arnoldi (classical Gram-Schmidt
+ * applied twice), a right block-Jacobi preconditioner (one diagonal face
+ * block per trace face) and an FP64 true-residual recomputation at every
+ * restart.  Host-synchronous (reads the Krylov coefficients).
+ *   duhat [Ntp][4] (device, written).  FR_E_NOT_CONVERGED when the
+ *   iteration cap is hit (duhat holds the last iterate).
+ */
+fr_status hfr_trace_solve(hfr_solver_t s, double* duhat,
+                          hfr_solve_stats* stats, void* stream);
+
+/*
+ * hfr_recover: local back-substitution eq:localproblems,
+ * du_k = A_k^-1 (r_k - B_k duhat_k) = X_r - X_B duhat_k.
+ *   duhat [Ntp][4] (device, read), du [4][Nim][Np] (device, written).
+ */
+fr_status hfr_recover(hfr_solver_t s, const double* duhat, double* du,
+                      void* stream);
+
+/* Inspection helpers (tests): y = L x with the assembled trace matrix;
+ * copies of t [Ntp][4], h [4][Nim][Np], g [Ntp][4] of the last
+ * hfr_assemble_condense (device pointers, any may be NULL); element blocks
+ * kept with keep_blocks=1, FP64 row-major (n+m) x (n+m) per implicit
+ * element with the local ordering (point, variable) for u and
+ * (face, point, variable) for the trace. */
+fr_status hfr_trace_matvec(hfr_solver_t s, const double* x, double* y,
+                           void* stream);
+fr_status hfr_get_system(hfr_solver_t s, double* t, double* h, double* g,
+                         void* stream);
+fr_status hfr_get_blocks(hfr_solver_t s, double* blocks, void* stream);
+
+/*
+ * hfr_timing: HIP-event timers around the solver's kernels, on the stream
+ * each kernel is launched on (the phases timed in the paper's performance
+ * tables: implicit residual t_R^im, Jacobian and condensation t_J, global
+ * solve t_G, local solve t_L, explicit residual t_R^ex).  enable = 1 resets
+ * and starts, 0 stops; when ms / counts are non-NULL the accumulated totals
+ * (HFR_NTIMERS entries, milliseconds and launch counts) are copied out after
+ * a device synchronisation.
+ */
+enum { HFR_T_RESIDUAL = 0,   /* hybridized residual kernel                 */
+       HFR_T_CONDENSE = 1,   /* element blocks + LU/Schur kernel           */
+       HFR_T_ASSEMBLE = 2,   /* block-sparse assembly kernel               */
+       HFR_T_PCSETUP = 3,    /* block-Jacobi inversion kernel              */
+       HFR_T_SPMV = 4,       /* block-sparse product kernel                */
+       HFR_T_TRACE_SOLVE = 5,/* whole trace solve (all Krylov kernels)     */
+       HFR_T_RECOVER = 6,    /* local recovery kernel                      */
+       HFR_T_EXPLICIT = 7,   /* explicit residual kernel (via imex_stage)  */
+       HFR_NTIMERS = 8 };
+fr_status hfr_timing(hfr_solver_t s, int32_t enable, double* ms,
+                     int64_t* counts);
+
+/* ----------------------------------------------------------------------- */
+/* IMEX step (alg:imex with the element partition of Section 4)            */
+/* ----------------------------------------------------------------------- */
+
+/*
+ * Tableau of an additive pair: s implicit stages (unpadded SDIRK matrix A,
+ * weights b) and sigma = s+1 explicit stages (A_bar, b_bar) with
+ * c_bar = [0 c] (table:butcherimex).  Row-major, s <= 4.
+ */
+typedef struct {
+    int32_t s;
+    double A[16];
+    double b[4];
+    double Abar[25];
+    double bbar[5];
+} imex_tableau;
+
+/*
+ * Device buffers of one step (all caller-owned):
+ *   u_n  [4][Ne][Np]        state at t_n (read)
+ *   u    [4][Ne][Np]        stage state; holds u_{n+1} after stage s+1
+ *   uhat [Ntp][4]           trace (initial guess in, stage trace out)
+ *   R_im [s][4][Nim][Np]    implicit stage residuals R_i
+ *   R_ex [s+1][4][Nex][Np]  explicit stage residuals R_bar_j
+ */
+typedef struct {
+    const double* u_n;
+    double* u;
+    double* uhat;
+    double* R_im;
+    double* R_ex;
+} imex_state;
+
+/*
+ * imex_stage: stage = 0 starts a step (u = u_n, R_bar_1 = R^ex(u_n));
+ * stage i = 1..s forms u_i^ex (eq:explicitimex) and u* = u_n + dt sum_{j<i}
+ * a_ij R_j, solves the hybridized stage by Newton (trace initial guess: the
+ * average of the two sides' interpolated states), stores
+ * R_i = R^im(u_i, uhat_i) and R_bar_{i+1} = R^ex(u_i); stage s+1 forms
+ * u_{n+1}.  Host-synchronous for i = 1..s (Newton convergence test).  On
+ * FR_E_NOT_CONVERGED / FR_E_NONFINITE the implicit part of u holds the last
+ * Newton iterate and u_n is untouched.
+ */
+fr_status imex_stage(fr_mesh_t mesh, hfr_solver_t s, const imex_tableau* tab,
+                     int32_t stage, double dt, const imex_state* st,
+                     hfr_newton_stats* stats, void* stream);
+
+const char* fr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HFR_IMEX_H */

@@ -1,0 +1,107 @@
+"""ctypes declarations of the C ABI in include/hfr_imex.h (marshalling only)."""
+import ctypes
+import os
+from ctypes import (POINTER, Structure, c_double, c_int8, c_int32, c_size_t,
+                    c_uint8, c_void_p, c_char_p)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhfrimex.so")
+
+FR_OK = 0
+STATUS = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_MESH", -3: "FR_E_NOMEM",
+          -4: "FR_E_DEVICE", -5: "FR_E_NOT_CONVERGED", -6: "FR_E_NONFINITE",
+          -7: "FR_E_UNSUPPORTED"}
+EXPORTED = ["fr_mesh_create", "fr_mesh_destroy", "fr_mesh_get_info",
+            "fr_mesh_get_maps", "fr_explicit_rhs", "hfr_solver_create",
+            "hfr_solver_destroy", "hfr_residual", "hfr_assemble_condense",
+            "hfr_trace_solve", "hfr_recover", "hfr_trace_matvec",
+            "hfr_get_system", "hfr_get_blocks", "hfr_timing", "imex_stage",
+            "fr_last_error"]
+TIMERS = ["residual", "condense", "assemble", "pcsetup", "spmv",
+          "trace_solve", "recover", "explicit"]
+
+
+class FrMeshDesc(Structure):
+    _fields_ = [("n_nodes", c_int32), ("node_xy", POINTER(c_double)),
+                ("node_topo", POINTER(c_int32)), ("n_elems", c_int32),
+                ("elem_nodes", POINTER(c_int32)),
+                ("elem_face_bc", POINTER(c_int8)), ("order", c_int32),
+                ("implicit_mask", POINTER(c_uint8)), ("es_cutoff", c_double),
+                ("gamma", c_double), ("uinf", c_double * 4),
+                ("flags", c_int32)]
+
+
+class FrMeshInfo(Structure):
+    _fields_ = [(n, c_int32) for n in
+                ("order", "n_pts", "n_elems", "n_faces", "n_implicit",
+                 "n_explicit", "n_trace_faces", "n_trace_points",
+                 "n_upsilon", "n_boundary", "n_loc", "m_loc")] + \
+        [("device_table_bytes", c_size_t)]
+
+
+class HfrOpts(Structure):
+    _fields_ = [("precision", c_int32), ("precond", c_int32),
+                ("gmres_restart", c_int32), ("gmres_max_iters", c_int32),
+                ("gmres_rtol", c_double), ("newton_max_iters", c_int32),
+                ("newton_tol", c_double), ("keep_blocks", c_int32)]
+
+
+class HfrSolveStats(Structure):
+    _fields_ = [("iterations", c_int32), ("restarts", c_int32),
+                ("rel_residual", c_double)]
+
+
+class HfrNewtonStats(Structure):
+    _fields_ = [("newton_iters", c_int32), ("gmres_iters", c_int32),
+                ("residual", c_double), ("implicit_ms", c_double)]
+
+
+class ImexTableau(Structure):
+    _fields_ = [("s", c_int32), ("A", c_double * 16), ("b", c_double * 4),
+                ("Abar", c_double * 25), ("bbar", c_double * 5)]
+
+
+class ImexState(Structure):
+    _fields_ = [("u_n", c_void_p), ("u", c_void_p), ("uhat", c_void_p),
+                ("R_im", c_void_p), ("R_ex", c_void_p)]
+
+
+def load(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"HIP library not built: {path} is missing "
+            "(run __graft_entry__.build() or paper_2401_16632_amd/build.py)")
+    lib = ctypes.CDLL(path)
+    P = POINTER
+    sig = {
+        "fr_mesh_create": (c_int32, [P(FrMeshDesc), P(c_void_p)]),
+        "fr_mesh_destroy": (None, [c_void_p]),
+        "fr_mesh_get_info": (c_int32, [c_void_p, P(FrMeshInfo)]),
+        "fr_mesh_get_maps": (c_int32, [c_void_p] + [c_void_p] * 8),
+        "fr_explicit_rhs": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+        "hfr_solver_create": (c_int32, [c_void_p, P(HfrOpts), P(c_size_t),
+                                        P(c_void_p)]),
+        "hfr_solver_destroy": (None, [c_void_p]),
+        "hfr_residual": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p,
+                                   c_double, c_void_p, c_void_p, c_void_p,
+                                   c_void_p]),
+        "hfr_assemble_condense": (c_int32, [c_void_p, c_void_p, c_void_p,
+                                            c_void_p, c_double, c_void_p]),
+        "hfr_trace_solve": (c_int32, [c_void_p, c_void_p, P(HfrSolveStats),
+                                      c_void_p]),
+        "hfr_recover": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+        "hfr_trace_matvec": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+        "hfr_get_system": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p,
+                                     c_void_p]),
+        "hfr_get_blocks": (c_int32, [c_void_p, c_void_p, c_void_p]),
+        "imex_stage": (c_int32, [c_void_p, c_void_p, P(ImexTableau), c_int32,
+                                 c_double, P(ImexState), P(HfrNewtonStats),
+                                 c_void_p]),
+        "hfr_timing": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+        "fr_last_error": (c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib

@@ -1,0 +1,142 @@
+// Internal declarations shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hfr_imex.h"
+
+namespace hfr {
+
+constexpr int kMaxP = FR_MAX_ORDER + 1;  // points per direction
+
+// One-dimensional reference operators on P Gauss-Legendre points, passed
+// to kernels by value (kernel-argument segment, read through scalar loads).
+struct RefOps {
+    int P;
+    double x[kMaxP], w[kMaxP];
+    double D[kMaxP * kMaxP];       // D[i*P+l] = l_l'(x_i)
+    double lm[kMaxP], lp[kMaxP];   // l_j(-1), l_j(+1)
+    double cl[kMaxP], cr[kMaxP];   // correction divergences (DG lifting)
+};
+
+// Role of the common flux on one element face.
+enum FaceRole : int {
+    ROLE_RUSANOV = 0,   // standard FR flux against the neighbour
+    ROLE_HFR = 1,       // hybridized flux against the trace
+    ROLE_WALL = 2,      // standard FR flux against the slip-wall ghost
+    ROLE_FAR = 3        // standard FR flux against the free stream
+};
+
+// Per element face: neighbour element, neighbour local face, role, and
+// trace encoding (trace_face*2 + side, -1 off the trace).
+struct FaceInfo {
+    int nb_e, nb_lf, role, trace;
+};
+
+struct Physics {
+    double gamma;
+    double uinf[4];
+};
+
+void set_error(const std::string& msg);
+fr_status fail(fr_status st, const std::string& msg);
+#define HIP_TRY(expr)                                                      \
+    do {                                                                   \
+        hipError_t _e = (expr);                                            \
+        if (_e != hipSuccess)                                              \
+            return ::hfr::fail(FR_E_DEVICE, std::string(#expr ": ") +      \
+                                                hipGetErrorString(_e));    \
+    } while (0)
+
+RefOps make_ref_ops(int P);
+
+// ---- kernel launchers (kernels_*.hip) ---------------------------------
+struct ResidualLaunch {
+    const int* list;   // element ids
+    int nlist;
+    const double* u;   // [4][Ne][Np]
+    int Ne;
+    const double* verts;     // [Ne][8]
+    const FaceInfo* finfo;   // [Ne][4]
+    const double2* fS;       // [Ne][4] scaled outward normal of the face
+    const double* uhat;      // [Ntp][4]
+    Physics phys;
+    double* R;               // [4][nlist][Np] or null
+    double* h;               // [4][nlist][Np] or null
+    const double* ustar;     // [4][nlist][Np]
+    double aii_dt;
+    double* gk;              // [nlist][4][P][4] or null
+};
+hipError_t launch_residual(const RefOps& ops, const ResidualLaunch& a,
+                           hipStream_t st);
+
+struct CondenseLaunch {
+    const int* imp_list;     // implicit element ids
+    int nimp;
+    const double* u;         // [4][Ne][Np]
+    int Ne;
+    const double* verts;
+    const FaceInfo* finfo;
+    const double2* fS;
+    const double* uhat;
+    Physics phys;
+    double aii_dt;
+    const double* h;         // [4][Nim][Np]
+    const double* gk;        // [Nim][4][P][4]
+    int precision;           // HFR_PREC_*
+    void* M;                 // per element (n+m) x (n+m+1), FP64 or FP32
+    double* blocks_copy;     // optional (n+m)^2 FP64 copy per element
+    int* pivot_fail;         // set to 1 if a zero pivot is met
+};
+hipError_t launch_condense(const RefOps& ops, const CondenseLaunch& a,
+                           hipStream_t st);
+
+struct AssembleLaunch {
+    int nblocks;             // BSR blocks
+    const int* blk_contrib;  // [nblocks][2][3]: imp, lf_row*2+side_row, lf_col*2+side_col (-1 none)
+    int ntf;
+    const int* tside;        // [Ntf][2][2]: imp, lf*2+side (-1 none) per side
+    const void* M;
+    int precision;
+    int P, n, m;
+    double* L64;             // [nblocks][bs][bs] column-major blocks or null
+    float* L32;              // same in FP32 or null
+    double* t;               // [Ntf*bs]
+};
+hipError_t launch_assemble(const AssembleLaunch& a, hipStream_t st);
+
+hipError_t launch_spmv(int ntf, int bs, const int* rowptr, const int* col,
+                       const double* L64, const float* L32, const double* x,
+                       double* y, double alpha, const double* yin,
+                       hipStream_t st);
+hipError_t launch_precond(int ntf, int bs, int pc, const void* inv,
+                          const double* x, double* y, hipStream_t st);
+hipError_t launch_multidot(int N, int k, const double* V, size_t ldv,
+                           const double* w, double* partial, int nblk,
+                           double* out, hipStream_t st);
+int multidot_blocks(int N);
+hipError_t launch_multi_axpy(int N, int k, const double* V, size_t ldv,
+                             const double* coef, double* w, double sign,
+                             hipStream_t st);
+hipError_t launch_scale(int N, double* x, const double* src, double a,
+                        hipStream_t st);
+hipError_t launch_axpy(int N, double a, const double* x, double* y,
+                       hipStream_t st);
+hipError_t launch_recover(int P, int nimp, const void* M, int precision,
+                          const int* trace_map, const double* duhat,
+                          double* du, hipStream_t st);
+hipError_t launch_newton_update(int Np, int nimp, int Ne, const int* imp_list,
+                                const double* du, double* u, int ntp4,
+                                const double* duhat, double* uhat,
+                                hipStream_t st);
+hipError_t launch_absmax(int N, const double* x, double* partial, int nblk,
+                         double* out, hipStream_t st);
+hipError_t launch_trace_gather_g(int ntp, int P, const int* tpside,
+                                 const double* gk, double* g,
+                                 hipStream_t st);
+
+}  // namespace hfr

@@ -1,0 +1,564 @@
+// Kernels of the condensed trace system (Section 3.2): deterministic
+// element-by-element assembly (eq:assembly / eq:assembly2) into block
+// sparse rows (one block row per trace face, block size bs = 4 P), the
+// block-sparse product, the block-Jacobi preconditioner, Krylov vector
+// kernels, local recovery (eq:localproblems), Newton updates, and the IMEX
+// stage combinations (eq:explicitimex and the final update).
+#include "internal.h"
+
+namespace hfr {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline int blocks_for(long n, int per = kThreads) {
+    long b = (n + per - 1) / per;
+    return int(b < 1 ? 1 : b);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < int(blockDim.x >> 6); ++i) s += red[i];
+    __syncthreads();
+    return s;  // valid in thread 0
+}
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t b = __float_as_uint(f);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return uint16_t(b >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) {
+    return __uint_as_float(uint32_t(h) << 16);
+}
+
+}  // namespace
+
+// ---- assembly --------------------------------------------------------
+template <typename T>
+__global__ void k_assemble(AssembleLaunch a) {
+    const int bs = 4 * a.P;
+    const int ld = a.n + a.m + 1;
+    const size_t rows = size_t(a.n + a.m);
+    const long total = long(a.nblocks) * bs * bs;
+    const T* M = reinterpret_cast<const T*>(a.M);
+    for (long idx = blockIdx.x * long(blockDim.x) + threadIdx.x; idx < total;
+         idx += long(gridDim.x) * blockDim.x) {
+        const int blk = int(idx / (bs * bs));
+        const int rem = int(idx % (bs * bs));
+        const int b = rem / bs, aa = rem % bs;
+        const int qa = aa >> 2, va = aa & 3, qb = b >> 2, wb = b & 3;
+        double val = 0.0;
+        for (int c = 0; c < 2; ++c) {
+            const int* ct = a.blk_contrib + (size_t(blk) * 2 + c) * 3;
+            const int imp = ct[0];
+            if (imp < 0) continue;
+            const int lr = ct[1] >> 1, sr = ct[1] & 1, lc = ct[2] >> 1, sc = ct[2] & 1;
+            const int qea = sr ? a.P - 1 - qa : qa;
+            const int qeb = sc ? a.P - 1 - qb : qb;
+            const size_t row = a.n + (lr * a.P + qea) * 4 + va;
+            const size_t col = a.n + (lc * a.P + qeb) * 4 + wb;
+            val += double(M[size_t(imp) * rows * ld + row * ld + col]);
+        }
+        if (a.L64) a.L64[idx] = val;
+        if (a.L32) a.L32[idx] = float(val);
+    }
+    const long tt = long(a.ntf) * bs;
+    for (long idx = blockIdx.x * long(blockDim.x) + threadIdx.x; idx < tt;
+         idx += long(gridDim.x) * blockDim.x) {
+        const int F = int(idx / bs), aa = int(idx % bs);
+        const int q = aa >> 2, v = aa & 3;
+        double val = 0.0;
+        for (int s = 0; s < 2; ++s) {
+            const int imp = a.tside[(size_t(F) * 2 + s) * 2];
+            if (imp < 0) continue;
+            const int lf = a.tside[(size_t(F) * 2 + s) * 2 + 1];
+            const int qe = s ? a.P - 1 - q : q;
+            const size_t row = a.n + (lf * a.P + qe) * 4 + v;
+            val += double(M[size_t(imp) * rows * ld + row * ld + (ld - 1)]);
+        }
+        a.t[idx] = val;
+    }
+}
+
+hipError_t launch_assemble(const AssembleLaunch& a, hipStream_t st) {
+    const int bs = 4 * a.P;
+    long work = long(a.nblocks) * bs * bs;
+    int grid = blocks_for(work);
+    if (grid > 65536) grid = 65536;
+    if (a.precision == HFR_PREC_FP64)
+        hipLaunchKernelGGL(k_assemble<double>, dim3(grid), dim3(kThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_assemble<float>, dim3(grid), dim3(kThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+// ---- block-Jacobi: invert the diagonal block of every trace face -------
+// One wave per face; Gauss-Jordan with partial pivoting on [Dblk | I] in LDS.
+__global__ void k_block_inverse(int ntf, int bs, const int* diag_blk,
+                                const double* L64, const float* L32, int pc,
+                                void* out, int* fail) {
+    __shared__ double W[24][49];
+    __shared__ int piv_s;
+    const int F = blockIdx.x;
+    const int t = threadIdx.x;
+    const size_t blk = size_t(diag_blk[F]) * bs * bs;
+    for (int idx = t; idx < bs * 2 * bs; idx += blockDim.x) {
+        const int r = idx / (2 * bs), c = idx % (2 * bs);
+        double v;
+        if (c < bs) v = L64 ? L64[blk + size_t(c) * bs + r] : double(L32[blk + size_t(c) * bs + r]);
+        else v = (c - bs == r) ? 1.0 : 0.0;
+        W[r][c] = v;
+    }
+    __syncthreads();
+    for (int k = 0; k < bs; ++k) {
+        if (t == 0) {
+            int p = k;
+            double best = fabs(W[k][k]);
+            for (int r = k + 1; r < bs; ++r)
+                if (fabs(W[r][k]) > best) { best = fabs(W[r][k]); p = r; }
+            piv_s = (best == 0.0) ? -1 : p;
+        }
+        __syncthreads();
+        const int p = piv_s;
+        if (p < 0) {
+            if (t == 0) *fail = 1;
+            return;
+        }
+        if (p != k)
+            for (int c = t; c < 2 * bs; c += blockDim.x) {
+                const double x = W[k][c];
+                W[k][c] = W[p][c];
+                W[p][c] = x;
+            }
+        __syncthreads();
+        const double inv = 1.0 / W[k][k];
+        __syncthreads();
+        for (int c = t; c < 2 * bs; c += blockDim.x) W[k][c] *= inv;
+        __syncthreads();
+        for (int idx = t; idx < bs * 2 * bs; idx += blockDim.x) {
+            const int r = idx / (2 * bs), c = idx % (2 * bs);
+            if (r != k && c != k) W[r][c] -= W[r][k] * W[k][c];
+        }
+        __syncthreads();
+        for (int r = t; r < bs; r += blockDim.x)
+            if (r != k) W[r][k] = 0.0;
+        __syncthreads();
+    }
+    // store inverse column-major: out[F][b][a] = Inv[a][b]
+    for (int idx = t; idx < bs * bs; idx += blockDim.x) {
+        const int b = idx / bs, aa = idx % bs;
+        const double v = W[aa][bs + b];
+        const size_t o = size_t(F) * bs * bs + idx;
+        if (pc == HFR_PC_FP64) reinterpret_cast<double*>(out)[o] = v;
+        else if (pc == HFR_PC_FP32) reinterpret_cast<float*>(out)[o] = float(v);
+        else reinterpret_cast<uint16_t*>(out)[o] = f2bf(float(v));
+    }
+}
+
+hipError_t launch_block_inverse_impl(int ntf, int bs, const int* diag_blk,
+                                     const double* L64, const float* L32,
+                                     int pc, void* out, int* fail,
+                                     hipStream_t st) {
+    if (ntf == 0) return hipSuccess;
+    if (bs > 24) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_block_inverse, dim3(ntf), dim3(64), 0, st, ntf, bs,
+                       diag_blk, L64, L32, pc, out, fail);
+    return hipGetLastError();
+}
+
+// ---- y = yin + alpha * L x  (block sparse, column-major blocks) ---------
+__global__ void k_spmv(int nrows, int bs, const int* rowptr, const int* col,
+                       const double* L64, const float* L32, const double* x,
+                       double* y, double alpha, const double* yin) {
+    const long r = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (r >= nrows) return;
+    const int F = int(r / bs), aa = int(r % bs);
+    double acc = 0.0;
+    for (int p = rowptr[F]; p < rowptr[F + 1]; ++p) {
+        const size_t base = size_t(p) * bs * bs + aa;
+        const double* xb = x + size_t(col[p]) * bs;
+        if (L64) {
+            for (int b = 0; b < bs; ++b) acc += L64[base + size_t(b) * bs] * xb[b];
+        } else {
+            for (int b = 0; b < bs; ++b) acc += double(L32[base + size_t(b) * bs]) * xb[b];
+        }
+    }
+    y[r] = (yin ? yin[r] : 0.0) + alpha * acc;
+}
+
+hipError_t launch_spmv(int ntf, int bs, const int* rowptr, const int* col,
+                       const double* L64, const float* L32, const double* x,
+                       double* y, double alpha, const double* yin,
+                       hipStream_t st) {
+    const int nrows = ntf * bs;
+    if (nrows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spmv, dim3(blocks_for(nrows)), dim3(kThreads), 0, st,
+                       nrows, bs, rowptr, col, L64, L32, x, y, alpha, yin);
+    return hipGetLastError();
+}
+
+__global__ void k_precond(int nrows, int bs, int pc, const void* inv,
+                          const double* x, double* y) {
+    const long r = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (r >= nrows) return;
+    const int F = int(r / bs), aa = int(r % bs);
+    const size_t base = size_t(F) * bs * bs + aa;
+    const double* xb = x + size_t(F) * bs;
+    double acc = 0.0;
+    if (pc == HFR_PC_FP64) {
+        const double* m = reinterpret_cast<const double*>(inv);
+        for (int b = 0; b < bs; ++b) acc += m[base + size_t(b) * bs] * xb[b];
+    } else if (pc == HFR_PC_FP32) {
+        const float* m = reinterpret_cast<const float*>(inv);
+        for (int b = 0; b < bs; ++b) acc += double(m[base + size_t(b) * bs]) * xb[b];
+    } else {
+        const uint16_t* m = reinterpret_cast<const uint16_t*>(inv);
+        for (int b = 0; b < bs; ++b) acc += double(bf2f(m[base + size_t(b) * bs])) * xb[b];
+    }
+    y[r] = acc;
+}
+
+hipError_t launch_precond(int ntf, int bs, int pc, const void* inv,
+                          const double* x, double* y, hipStream_t st) {
+    const int nrows = ntf * bs;
+    if (nrows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_precond, dim3(blocks_for(nrows)), dim3(kThreads), 0,
+                       st, nrows, bs, pc, inv, x, y);
+    return hipGetLastError();
+}
+
+// ---- Krylov helpers -------------------------------------------------------
+int multidot_blocks(int N) {
+    int b = (N + 4 * kThreads - 1) / (4 * kThreads);
+    if (b > 512) b = 512;
+    return b < 1 ? 1 : b;
+}
+
+__global__ void k_multidot_partial(int N, int k, const double* V, size_t ldv,
+                                   const double* w, double* partial) {
+    __shared__ double red[kThreads / 64];
+    const int nb = gridDim.x;
+    const int chunk = (N + nb - 1) / nb;
+    const int lo = blockIdx.x * chunk;
+    const int hi = min(N, lo + chunk);
+    for (int j = 0; j < k; ++j) {
+        double s = 0.0;
+        const double* vj = V + size_t(j) * ldv;
+        for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) s += vj[i] * w[i];
+        s = block_sum(s, red);
+        if (threadIdx.x == 0) partial[size_t(blockIdx.x) * k + j] = s;
+    }
+}
+
+__global__ void k_multidot_final(int k, int nblk, const double* partial,
+                                 double* out) {
+    const int j = blockIdx.x;
+    __shared__ double red[kThreads / 64];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += partial[size_t(b) * k + j];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) out[j] = s;
+}
+
+hipError_t launch_multidot(int N, int k, const double* V, size_t ldv,
+                           const double* w, double* partial, int nblk,
+                           double* out, hipStream_t st) {
+    if (k == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_multidot_partial, dim3(nblk), dim3(kThreads), 0, st,
+                       N, k, V, ldv, w, partial);
+    hipLaunchKernelGGL(k_multidot_final, dim3(k), dim3(kThreads), 0, st, k,
+                       nblk, partial, out);
+    return hipGetLastError();
+}
+
+__global__ void k_multi_axpy(int N, int k, const double* V, size_t ldv,
+                             const double* coef, double* w, double sign) {
+    const long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i >= N) return;
+    double acc = 0.0;
+    for (int j = 0; j < k; ++j) acc += coef[j] * V[size_t(j) * ldv + i];
+    w[i] += sign * acc;
+}
+
+hipError_t launch_multi_axpy(int N, int k, const double* V, size_t ldv,
+                             const double* coef, double* w, double sign,
+                             hipStream_t st) {
+    if (N == 0 || k == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_multi_axpy, dim3(blocks_for(N)), dim3(kThreads), 0,
+                       st, N, k, V, ldv, coef, w, sign);
+    return hipGetLastError();
+}
+
+__global__ void k_scale(int N, double* x, const double* src, double a) {
+    const long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i < N) x[i] = a * src[i];
+}
+
+hipError_t launch_scale(int N, double* x, const double* src, double a,
+                        hipStream_t st) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale, dim3(blocks_for(N)), dim3(kThreads), 0, st, N,
+                       x, src, a);
+    return hipGetLastError();
+}
+
+__global__ void k_axpy(int N, double a, const double* x, double* y) {
+    const long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i < N) y[i] += a * x[i];
+}
+
+hipError_t launch_axpy(int N, double a, const double* x, double* y,
+                       hipStream_t st) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_axpy, dim3(blocks_for(N)), dim3(kThreads), 0, st, N, a,
+                       x, y);
+    return hipGetLastError();
+}
+
+__global__ void k_absmax_partial(int N, const double* x, double* partial) {
+    __shared__ double red[kThreads];
+    double m = 0.0;
+    for (long i = blockIdx.x * long(blockDim.x) + threadIdx.x; i < N;
+         i += long(gridDim.x) * blockDim.x) {
+        const double a = fabs(x[i]);
+        m = (a > m || a != a) ? a : m;   // NaN propagates
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double o = red[threadIdx.x + s];
+            if (o > red[threadIdx.x] || o != o) red[threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_absmax_final(int nblk, const double* partial, double* out) {
+    if (threadIdx.x != 0) return;
+    double m = 0.0;
+    for (int i = 0; i < nblk; ++i) {
+        const double o = partial[i];
+        if (o > m || o != o) m = o;
+    }
+    *out = m;
+}
+
+hipError_t launch_absmax(int N, const double* x, double* partial, int nblk,
+                         double* out, hipStream_t st) {
+    if (N == 0) {
+        hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(64), 0, st, 0, partial, out);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_absmax_partial, dim3(nblk), dim3(kThreads), 0, st, N, x, partial);
+    hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(64), 0, st, nblk, partial, out);
+    return hipGetLastError();
+}
+
+// ---- recovery (eq:localproblems) from the LU-condensed element matrix:
+// rows 0..n-1 hold L\U | Y_B | Y_r with Y = L^-1 P [B r], so
+// du = U^-1 (Y_r - Y_B duhat_loc) by back substitution.
+template <typename T>
+__global__ void k_recover(int P, int nimp, const T* M, const int* trace_map,
+                          const double* duhat, double* du) {
+    extern __shared__ double sm[];
+    const int NP = P * P, n = 4 * NP, m = 16 * P, ld = n + m + 1;
+    double* loc = sm;
+    double* y = sm + m;
+    const int k = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
+    for (int b = t; b < m; b += nt) {
+        const int f = b / (4 * P), q = (b >> 2) % P, w = b & 3;
+        const int tp = trace_map[(size_t(k) * 4 + f) * P + q];
+        loc[b] = tp >= 0 ? duhat[size_t(tp) * 4 + w] : 0.0;
+    }
+    __syncthreads();
+    const T* Mk = M + size_t(k) * (n + m) * ld;
+    for (int row = t; row < n; row += nt) {
+        const T* xr = Mk + size_t(row) * ld;
+        double acc = double(xr[ld - 1]);
+        for (int b = 0; b < m; ++b) acc -= double(xr[n + b]) * loc[b];
+        y[row] = acc;
+    }
+    __syncthreads();
+    for (int j = n - 1; j >= 0; --j) {
+        const double xj = y[j] / double(Mk[size_t(j) * ld + j]);
+        __syncthreads();
+        if (t == 0) y[j] = xj;
+        for (int i = t; i < j; i += nt) y[i] -= double(Mk[size_t(i) * ld + j]) * xj;
+        __syncthreads();
+    }
+    for (int row = t; row < n; row += nt) {
+        const int pt = row >> 2, v = row & 3;
+        du[size_t(v) * nimp * NP + size_t(k) * NP + pt] = y[row];
+    }
+}
+
+hipError_t launch_recover(int P, int nimp, const void* M, int precision,
+                          const int* trace_map, const double* duhat,
+                          double* du, hipStream_t st) {
+    if (nimp == 0) return hipSuccess;
+    const size_t shm = (16 * P + 4 * P * P) * sizeof(double);
+    if (precision == HFR_PREC_FP64)
+        hipLaunchKernelGGL(k_recover<double>, dim3(nimp), dim3(128), shm, st, P,
+                           nimp, reinterpret_cast<const double*>(M), trace_map,
+                           duhat, du);
+    else
+        hipLaunchKernelGGL(k_recover<float>, dim3(nimp), dim3(128), shm, st, P,
+                           nimp, reinterpret_cast<const float*>(M), trace_map,
+                           duhat, du);
+    return hipGetLastError();
+}
+
+// ---- Newton update: u_im += du (scatter), uhat += duhat -----------------
+__global__ void k_newton_update(int Np, int nimp, int Ne, const int* imp_list,
+                                const double* du, double* u, int ntp4,
+                                const double* duhat, double* uhat) {
+    const long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    const long nu = 4L * nimp * Np;
+    if (i < nu) {
+        const int v = int(i / (long(nimp) * Np));
+        const long rem = i % (long(nimp) * Np);
+        const int k = int(rem / Np), pt = int(rem % Np);
+        u[size_t(v) * Ne * Np + size_t(imp_list[k]) * Np + pt] += du[i];
+    } else if (i - nu < ntp4) {
+        uhat[i - nu] += duhat[i - nu];
+    }
+}
+
+hipError_t launch_newton_update(int Np, int nimp, int Ne, const int* imp_list,
+                                const double* du, double* u, int ntp4,
+                                const double* duhat, double* uhat,
+                                hipStream_t st) {
+    const long n = 4L * nimp * Np + ntp4;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_newton_update, dim3(blocks_for(n)), dim3(kThreads), 0,
+                       st, Np, nimp, Ne, imp_list, du, u, ntp4, duhat, uhat);
+    return hipGetLastError();
+}
+
+// ---- transmission residual: sum of the two sides' shares -----------------
+__global__ void k_gather_g(int ntp, const int* tpside, const double* gk,
+                           double* g) {
+    const long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i >= 4L * ntp) return;
+    const int tp = int(i >> 2), v = int(i & 3);
+    const int s0 = tpside[2 * tp], s1 = tpside[2 * tp + 1];
+    g[i] = gk[size_t(s0) * 4 + v] + gk[size_t(s1) * 4 + v];
+}
+
+hipError_t launch_trace_gather_g(int ntp, int P, const int* tpside,
+                                 const double* gk, double* g, hipStream_t st) {
+    (void)P;
+    if (ntp == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_g, dim3(blocks_for(4L * ntp)), dim3(kThreads),
+                       0, st, ntp, tpside, gk, g);
+    return hipGetLastError();
+}
+
+// ---- initial trace: average of both sides' interpolated states ---------
+struct Lagr {
+    double lm[kMaxP], lp[kMaxP];
+};
+
+__global__ void k_trace_average_v(int ntp, int P, int Ne, const int* tpside,
+                                  const int* imp_list, Lagr L, const double* u,
+                                  double* uhat) {
+    const long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i >= 4L * ntp) return;
+    const int tp = int(i >> 2), v = int(i & 3);
+    const int NP = P * P;
+    double acc = 0.0;
+    for (int s = 0; s < 2; ++s) {
+        const int code = tpside[2 * tp + s];
+        const int q = code % P, lf = (code / P) & 3, k = code / (4 * P);
+        const double* base = u + size_t(v) * Ne * NP + size_t(imp_list[k]) * NP;
+        double val = 0.0;
+        for (int l = 0; l < P; ++l) {
+            int pt;
+            double w;
+            if (lf == 0) { pt = l * P + q; w = L.lm[l]; }
+            else if (lf == 1) { pt = q * P + l; w = L.lp[l]; }
+            else if (lf == 2) { pt = l * P + (P - 1 - q); w = L.lp[l]; }
+            else { pt = (P - 1 - q) * P + l; w = L.lm[l]; }
+            val += w * base[pt];
+        }
+        acc += val;
+    }
+    uhat[i] = 0.5 * acc;
+}
+
+hipError_t launch_trace_average_ops(const RefOps& o, int ntp, int Ne,
+                                    const int* tpside, const int* imp_list,
+                                    const double* u, double* uhat,
+                                    hipStream_t st) {
+    if (ntp == 0) return hipSuccess;
+    Lagr L{};
+    for (int l = 0; l < o.P; ++l) {
+        L.lm[l] = o.lm[l];
+        L.lp[l] = o.lp[l];
+    }
+    hipLaunchKernelGGL(k_trace_average_v, dim3(blocks_for(4L * ntp)),
+                       dim3(kThreads), 0, st, ntp, o.P, Ne, tpside, imp_list,
+                       L, u, uhat);
+    return hipGetLastError();
+}
+
+// ---- stage combinations ---------------------------------------------------
+struct Combo {
+    const double* base;      // full [4][Ne][Np], gathered through list
+    const double* terms[6];  // compact [4][nlist][Np]
+    double coef[6];
+    int nterm;
+    double* out;             // full (scatter) or compact
+    int scatter;
+};
+
+__global__ void k_combine(int nlist, int Np, int Ne, const int* list, Combo c) {
+    const long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    const long per = long(nlist) * Np;
+    if (i >= 4 * per) return;
+    const int v = int(i / per);
+    const long rem = i % per;
+    const int li = int(rem / Np), pt = int(rem % Np);
+    const size_t full = size_t(v) * Ne * Np + size_t(list[li]) * Np + pt;
+    double acc = c.base[full];
+    for (int t = 0; t < c.nterm; ++t) acc += c.coef[t] * c.terms[t][i];
+    if (c.scatter) c.out[full] = acc;
+    else c.out[i] = acc;
+}
+
+hipError_t launch_combine(int nlist, int Np, int Ne, const int* list,
+                          const double* base, int nterm,
+                          const double* const* terms, const double* coefs,
+                          double* out, int scatter, hipStream_t st) {
+    if (nlist == 0) return hipSuccess;
+    if (nterm > 6) return hipErrorInvalidValue;
+    Combo c{};
+    c.base = base;
+    c.nterm = nterm;
+    for (int t = 0; t < nterm; ++t) {
+        c.terms[t] = terms[t];
+        c.coef[t] = coefs[t];
+    }
+    c.out = out;
+    c.scatter = scatter;
+    const long n = 4L * nlist * Np;
+    hipLaunchKernelGGL(k_combine, dim3(blocks_for(n)), dim3(kThreads), 0, st,
+                       nlist, Np, Ne, list, c);
+    return hipGetLastError();
+}
+
+}  // namespace hfr

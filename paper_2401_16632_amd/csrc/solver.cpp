@@ -1,0 +1,740 @@
+// Host orchestration of the implicit stage: residuals, condensation and
+// assembly (Section 3.2), the Krylov trace solve, local recovery, Newton
+// (Section 3.1) and the element-partitioned IMEX step (alg:imex,
+// eq:explicitimex, eq:hfrimex and the final update of Section 4).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "mesh.h"
+
+namespace hfr {
+hipError_t launch_block_inverse_impl(int ntf, int bs, const int* diag_blk,
+                                     const double* L64, const float* L32,
+                                     int pc, void* out, int* fail,
+                                     hipStream_t st);
+hipError_t launch_trace_average_ops(const RefOps& o, int ntp, int Ne,
+                                    const int* tpside, const int* imp_list,
+                                    const double* u, double* uhat,
+                                    hipStream_t st);
+hipError_t launch_combine(int nlist, int Np, int Ne, const int* list,
+                          const double* base, int nterm,
+                          const double* const* terms, const double* coefs,
+                          double* out, int scatter, hipStream_t st);
+}  // namespace hfr
+
+using namespace hfr;
+
+struct hfr_solver_s {
+    fr_mesh_t mesh = nullptr;
+    hfr_opts opts{};
+    int n = 0, m = 0, ld = 0, bs = 0, N = 0, restart = 0;
+    size_t elem_M = 0;       // scalars per element matrix
+    int nblocks = 0;
+    // device
+    void* M = nullptr;
+    double* blocks_copy = nullptr;
+    double* h = nullptr;     // [4][Nim][Np]
+    double* gk = nullptr;    // [Nim][4][P][4]
+    double* g = nullptr;     // [Ntp][4]
+    double* Rtmp = nullptr;  // [4][Nim][Np]
+    double* ustar = nullptr; // [4][Nim][Np]
+    double* du = nullptr;    // [4][Nim][Np]
+    double* duhat = nullptr; // [N]
+    int* rowptr = nullptr;
+    int* col = nullptr;
+    int* contrib = nullptr;
+    int* tside = nullptr;
+    int* diag_blk = nullptr;
+    double* L64 = nullptr;
+    float* L32 = nullptr;
+    double* t = nullptr;
+    void* Dinv = nullptr;
+    int* flags = nullptr;    // [0] pivot fail, [1] block inverse fail
+    double* V = nullptr;     // (restart+1) x N
+    double* z = nullptr;     // N
+    double* r = nullptr;     // N
+    double* scratch = nullptr;  // partials
+    double* dots = nullptr;  // small device vector
+    double* coef = nullptr;
+    size_t ws_bytes = 0;
+    int nblk_dot = 1;
+    // event timers
+    bool timing = false;
+    double tms[HFR_NTIMERS] = {};
+    int64_t tcnt[HFR_NTIMERS] = {};
+    struct Pend { hipEvent_t a, b; int cat; };
+    std::vector<Pend> pending;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+};
+
+namespace {
+
+int tbegin(hfr_solver_s* s, int cat, hipStream_t st) {
+    if (!s || !s->timing) return -1;
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    if (s->pool.empty()) {
+        if (hipEventCreate(&ev.first) != hipSuccess) return -1;
+        if (hipEventCreate(&ev.second) != hipSuccess) {
+            (void)hipEventDestroy(ev.first);
+            return -1;
+        }
+    } else {
+        ev = s->pool.back();
+        s->pool.pop_back();
+    }
+    (void)hipEventRecord(ev.first, st);
+    s->pending.push_back({ev.first, ev.second, cat});
+    return int(s->pending.size()) - 1;
+}
+
+void tend(hfr_solver_s* s, int idx, hipStream_t st) {
+    if (idx < 0 || !s) return;
+    (void)hipEventRecord(s->pending[idx].b, st);
+}
+
+void tflush(hfr_solver_s* s) {
+    if (!s) return;
+    for (auto& p : s->pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.b) == hipSuccess &&
+            hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            s->tms[p.cat] += ms;
+            s->tcnt[p.cat] += 1;
+        }
+        s->pool.push_back({p.a, p.b});
+    }
+    s->pending.clear();
+}
+
+}  // namespace
+
+namespace {
+
+template <class T>
+fr_status dalloc(T** p, size_t count, size_t& total) {
+    *p = nullptr;
+    if (count == 0) return FR_OK;
+    if (hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)) != hipSuccess)
+        return fail(FR_E_NOMEM, "hipMalloc of solver workspace failed (" +
+                                    std::to_string(count * sizeof(T)) + " bytes)");
+    total += count * sizeof(T);
+    return FR_OK;
+}
+
+void free_solver(hfr_solver_s* s) {
+    tflush(s);
+    for (auto& p : s->pool) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    s->pool.clear();
+    void* ptrs[] = {s->M, s->blocks_copy, s->h, s->gk, s->g, s->Rtmp,
+                    s->ustar, s->du, s->duhat, s->rowptr, s->col, s->contrib,
+                    s->tside, s->diag_blk, s->L64, s->L32, s->t, s->Dinv,
+                    s->flags, s->V, s->z, s->r, s->scratch, s->dots, s->coef};
+    for (void* p : ptrs) (void)hipFree(p);
+}
+
+fr_status sync_check(hipStream_t st) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+        return fail(FR_E_DEVICE, std::string("device error: ") + hipGetErrorString(e));
+    return FR_OK;
+}
+
+ResidualLaunch implicit_launch(hfr_solver_s* s, const double* u,
+                               const double* uhat) {
+    fr_mesh_s* m = s->mesh;
+    ResidualLaunch a{};
+    a.list = m->d_imp;
+    a.nlist = m->Nim;
+    a.u = u;
+    a.Ne = m->Ne;
+    a.verts = m->d_verts;
+    a.finfo = m->d_finfo;
+    a.fS = m->d_fS;
+    a.uhat = uhat;
+    a.phys = m->phys;
+    return a;
+}
+
+// h, the element shares g^(k) and the assembled g (internal buffers)
+fr_status residual_internal(hfr_solver_s* s, const double* u,
+                            const double* uhat, const double* ustar,
+                            double aii_dt, double* R_out, hipStream_t st) {
+    fr_mesh_s* m = s->mesh;
+    if (m->Nim == 0) return FR_OK;
+    ResidualLaunch a = implicit_launch(s, u, uhat);
+    a.R = R_out;
+    a.h = s->h;
+    a.ustar = ustar;
+    a.aii_dt = aii_dt;
+    a.gk = s->gk;
+    int tk = tbegin(s, HFR_T_RESIDUAL, st);
+    HIP_TRY(launch_residual(m->ops, a, st));
+    tend(s, tk, st);
+    HIP_TRY(launch_trace_gather_g(m->Ntp, m->P, m->d_tpside, s->gk, s->g, st));
+    return FR_OK;
+}
+
+fr_status condense_internal(hfr_solver_s* s, const double* u,
+                            const double* uhat, double aii_dt,
+                            hipStream_t st) {
+    fr_mesh_s* m = s->mesh;
+    if (m->Nim == 0) return FR_OK;
+    CondenseLaunch c{};
+    c.imp_list = m->d_imp;
+    c.nimp = m->Nim;
+    c.u = u;
+    c.Ne = m->Ne;
+    c.verts = m->d_verts;
+    c.finfo = m->d_finfo;
+    c.fS = m->d_fS;
+    c.uhat = uhat;
+    c.phys = m->phys;
+    c.aii_dt = aii_dt;
+    c.h = s->h;
+    c.gk = s->gk;
+    c.precision = s->opts.precision;
+    c.M = s->M;
+    c.blocks_copy = s->blocks_copy;
+    c.pivot_fail = s->flags;
+    int tk = tbegin(s, HFR_T_CONDENSE, st);
+    HIP_TRY(launch_condense(m->ops, c, st));
+    tend(s, tk, st);
+    if (m->Ntf == 0) return FR_OK;
+    AssembleLaunch a{};
+    a.nblocks = s->nblocks;
+    a.blk_contrib = s->contrib;
+    a.ntf = m->Ntf;
+    a.tside = s->tside;
+    a.M = s->M;
+    a.precision = s->opts.precision;
+    a.P = m->P;
+    a.n = s->n;
+    a.m = s->m;
+    a.L64 = s->L64;
+    a.L32 = s->L32;
+    a.t = s->t;
+    tk = tbegin(s, HFR_T_ASSEMBLE, st);
+    HIP_TRY(launch_assemble(a, st));
+    tend(s, tk, st);
+    tk = tbegin(s, HFR_T_PCSETUP, st);
+    HIP_TRY(launch_block_inverse_impl(m->Ntf, s->bs, s->diag_blk, s->L64,
+                                      s->L64 ? nullptr : s->L32,
+                                      s->opts.precond, s->Dinv, s->flags + 1,
+                                      st));
+    tend(s, tk, st);
+    return FR_OK;
+}
+
+fr_status host_dots(hfr_solver_s* s, int k, const double* V, size_t ldv,
+                    const double* w, double* out_dev, double* host,
+                    hipStream_t st) {
+    HIP_TRY(launch_multidot(s->N, k, V, ldv, w, s->scratch, s->nblk_dot,
+                            out_dev, st));
+    if (host) {
+        HIP_TRY(hipMemcpyAsync(host, out_dev, sizeof(double) * k,
+                               hipMemcpyDeviceToHost, st));
+        fr_status e = sync_check(st);
+        if (e) return e;
+    }
+    return FR_OK;
+}
+
+fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
+                hipStream_t st) {
+    fr_mesh_s* m = s->mesh;
+    const int N = s->N;
+    const int R = s->restart;
+    const size_t ldv = size_t(N);
+    const int pc = s->opts.precond;
+    const int maxit = std::max(1, s->opts.gmres_max_iters);
+    hfr_solve_stats loc{};
+    HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * N, st));
+    if (N == 0) {
+        if (stats) *stats = loc;
+        return FR_OK;
+    }
+    double hv[2 * 65 + 2];
+    // r = t
+    HIP_TRY(hipMemcpyAsync(s->r, s->t, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    fr_status e = host_dots(s, 1, s->r, ldv, s->r, s->dots, hv, st);
+    if (e) return e;
+    const double bnorm = std::sqrt(hv[0]);
+    double beta = bnorm;
+    if (!(bnorm == bnorm) || std::isinf(bnorm))
+        return fail(FR_E_NONFINITE, "non-finite trace right-hand side");
+    if (bnorm == 0.0) {
+        if (stats) *stats = loc;
+        return FR_OK;
+    }
+    const double target = s->opts.gmres_rtol * bnorm;
+    std::vector<double> H(size_t(R + 1) * R), cs(R), sn(R), gv(R + 1), y(R);
+    int total = 0;
+    bool conv = false;
+    while (total < maxit) {
+        HIP_TRY(launch_scale(N, s->V, s->r, 1.0 / beta, st));
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = beta;
+        int jl = -1;
+        for (int j = 0; j < R && total < maxit; ++j) {
+            double* vj = s->V + size_t(j) * ldv;
+            double* w = s->V + size_t(j + 1) * ldv;
+            HIP_TRY(launch_precond(m->Ntf, s->bs, pc, s->Dinv, vj, s->z, st));
+            int tk = tbegin(s, HFR_T_SPMV, st);
+            HIP_TRY(launch_spmv(m->Ntf, s->bs, s->rowptr, s->col, s->L64,
+                                s->L64 ? nullptr : s->L32, s->z, w, 1.0,
+                                nullptr, st));
+            tend(s, tk, st);
+            // classical Gram-Schmidt, twice
+            double* d1 = s->dots;
+            double* d2 = s->dots + 65;
+            double* dn = s->dots + 130;
+            HIP_TRY(launch_multidot(N, j + 1, s->V, ldv, w, s->scratch, s->nblk_dot, d1, st));
+            HIP_TRY(launch_multi_axpy(N, j + 1, s->V, ldv, d1, w, -1.0, st));
+            HIP_TRY(launch_multidot(N, j + 1, s->V, ldv, w, s->scratch, s->nblk_dot, d2, st));
+            HIP_TRY(launch_multi_axpy(N, j + 1, s->V, ldv, d2, w, -1.0, st));
+            HIP_TRY(launch_multidot(N, 1, w, ldv, w, s->scratch, s->nblk_dot, dn, st));
+            HIP_TRY(hipMemcpyAsync(hv, s->dots, sizeof(double) * 131,
+                                   hipMemcpyDeviceToHost, st));
+            e = sync_check(st);
+            if (e) return e;
+            const double hn = std::sqrt(hv[130]);
+            double* hc = &H[size_t(j) * (R + 1)];
+            for (int i = 0; i <= j; ++i) hc[i] = hv[i] + hv[65 + i];
+            hc[j + 1] = hn;
+            if (!(hn == hn)) return fail(FR_E_NONFINITE, "non-finite Krylov vector");
+            if (hn > 0.0) HIP_TRY(launch_scale(N, w, w, 1.0 / hn, st));
+            for (int i = 0; i < j; ++i) {
+                const double a = cs[i] * hc[i] + sn[i] * hc[i + 1];
+                hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
+                hc[i] = a;
+            }
+            const double den = std::hypot(hc[j], hc[j + 1]);
+            cs[j] = den > 0 ? hc[j] / den : 1.0;
+            sn[j] = den > 0 ? hc[j + 1] / den : 0.0;
+            hc[j] = den;
+            hc[j + 1] = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            ++total;
+            jl = j;
+            if (std::fabs(gv[j + 1]) <= target || hn == 0.0) break;
+        }
+        // y = H^-1 g (upper triangular), x += M^-1 (V y)
+        for (int i = jl; i >= 0; --i) {
+            double acc = gv[i];
+            for (int k = i + 1; k <= jl; ++k) acc -= H[size_t(k) * (R + 1) + i] * y[k];
+            y[i] = acc / H[size_t(i) * (R + 1) + i];
+        }
+        HIP_TRY(hipMemcpyAsync(s->coef, y.data(), sizeof(double) * (jl + 1),
+                               hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemsetAsync(s->r, 0, sizeof(double) * N, st));
+        HIP_TRY(launch_multi_axpy(N, jl + 1, s->V, ldv, s->coef, s->r, 1.0, st));
+        HIP_TRY(launch_precond(m->Ntf, s->bs, pc, s->Dinv, s->r, s->z, st));
+        HIP_TRY(launch_axpy(N, 1.0, s->z, x, st));
+        // true residual in FP64: r = t - L x
+        HIP_TRY(launch_spmv(m->Ntf, s->bs, s->rowptr, s->col, s->L64,
+                            s->L64 ? nullptr : s->L32, x, s->r, -1.0, s->t, st));
+        e = host_dots(s, 1, s->r, ldv, s->r, s->dots, hv, st);
+        if (e) return e;
+        beta = std::sqrt(hv[0]);
+        loc.restarts++;
+        if (beta <= target) {
+            conv = true;
+            break;
+        }
+    }
+    loc.iterations = total;
+    loc.rel_residual = beta / bnorm;
+    if (stats) *stats = loc;
+    if (!conv) return fail(FR_E_NOT_CONVERGED, "GMRES iteration cap reached");
+    return FR_OK;
+}
+
+fr_status absmax_host(hfr_solver_s* s, int N, const double* x, double* out,
+                      hipStream_t st) {
+    const int nb = std::min(1024, std::max(1, (N + 255) / 256));
+    HIP_TRY(launch_absmax(N, x, s->scratch, nb, s->dots + 140, st));
+    HIP_TRY(hipMemcpyAsync(out, s->dots + 140, sizeof(double),
+                           hipMemcpyDeviceToHost, st));
+    return sync_check(st);
+}
+
+fr_status newton(hfr_solver_s* s, double* u, double* uhat,
+                 const double* ustar, double aii_dt, hfr_newton_stats* stats,
+                 hipStream_t st) {
+    fr_mesh_s* m = s->mesh;
+    hfr_newton_stats loc{};
+    const int nu = 4 * m->Nim * m->Np;
+    double scale = 0.0;
+    fr_status e = absmax_host(s, nu, ustar, &scale, st);
+    if (e) return e;
+    scale = std::max(1.0, scale);
+    const double tol = s->opts.newton_tol * scale;
+    for (int it = 0;; ++it) {
+        e = residual_internal(s, u, uhat, ustar, aii_dt, nullptr, st);
+        if (e) return e;
+        double hmax = 0.0, gmax = 0.0;
+        if ((e = absmax_host(s, nu, s->h, &hmax, st))) return e;
+        if ((e = absmax_host(s, 4 * m->Ntp, s->g, &gmax, st))) return e;
+        const double res = std::max(hmax, gmax);
+        loc.residual = res;
+        loc.newton_iters = it;
+        if (!(hmax == hmax) || !(gmax == gmax) || std::isinf(res)) {
+            if (stats) *stats = loc;
+            return fail(FR_E_NONFINITE, "non-finite Newton residual");
+        }
+        if (res <= tol) break;
+        if (it >= s->opts.newton_max_iters) {
+            if (stats) *stats = loc;
+            return fail(FR_E_NOT_CONVERGED, "Newton did not converge");
+        }
+        if ((e = condense_internal(s, u, uhat, aii_dt, st))) return e;
+        hfr_solve_stats ks{};
+        int tk = tbegin(s, HFR_T_TRACE_SOLVE, st);
+        e = gmres(s, s->duhat, &ks, st);
+        tend(s, tk, st);
+        loc.gmres_iters += ks.iterations;
+        if (e && e != FR_E_NOT_CONVERGED) return e;
+        tk = tbegin(s, HFR_T_RECOVER, st);
+        HIP_TRY(launch_recover(m->P, m->Nim, s->M, s->opts.precision,
+                               m->d_trace_map, s->duhat, s->du, st));
+        HIP_TRY(launch_newton_update(m->Np, m->Nim, m->Ne, m->d_imp, s->du, u,
+                                     4 * m->Ntp, s->duhat, uhat, st));
+        tend(s, tk, st);
+    }
+    int fl[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(fl, s->flags, sizeof(fl), hipMemcpyDeviceToHost, st));
+    if ((e = sync_check(st))) return e;
+    if (fl[0] || fl[1]) {
+        HIP_TRY(hipMemsetAsync(s->flags, 0, sizeof(fl), st));
+        if (stats) *stats = loc;
+        return fail(FR_E_NONFINITE, "zero pivot in an element or face block");
+    }
+    if (stats) *stats = loc;
+    return FR_OK;
+}
+
+}  // namespace
+
+extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
+                                       size_t* ws, hfr_solver_t* out) {
+    if (!mesh || !o || !out) return fail(FR_E_INVALID, "null argument");
+    *out = nullptr;
+    if (mesh->host_only) return fail(FR_E_INVALID, "host-only mesh");
+    if (o->precision != HFR_PREC_FP64 && o->precision != HFR_PREC_FP32)
+        return fail(FR_E_INVALID, "unknown precision");
+    if (o->precond < HFR_PC_FP64 || o->precond > HFR_PC_BF16)
+        return fail(FR_E_INVALID, "unknown preconditioner storage");
+    if (o->gmres_restart < 1 || o->gmres_restart > 64)
+        return fail(FR_E_INVALID, "gmres_restart must be in 1..64");
+    if (o->newton_max_iters < 0 || !(o->newton_tol > 0.0) || !(o->gmres_rtol > 0.0))
+        return fail(FR_E_INVALID, "bad tolerance or iteration cap");
+    auto s = new hfr_solver_s();
+    s->mesh = mesh;
+    s->opts = *o;
+    fr_mesh_s* m = mesh;
+    const int P = m->P;
+    s->n = 4 * m->Np;
+    s->m = 16 * P;
+    s->ld = s->n + s->m + 1;
+    s->bs = 4 * P;
+    s->N = 4 * m->Ntp;
+    s->restart = o->gmres_restart;
+    s->elem_M = size_t(s->n + s->m) * s->ld;
+    // block-sparse structure of L: one block row per trace face; columns
+    // are the trace faces of the two elements sharing it
+    std::vector<int> rowptr(m->Ntf + 1, 0), col, contrib, tside(4 * size_t(m->Ntf), -1),
+        diag(m->Ntf, -1);
+    for (int F = 0; F < m->Ntf; ++F) {
+        const int f = m->trace_faces[F];
+        std::map<int, std::vector<int>> cols;   // G -> contributions
+        for (int sd = 0; sd < 2; ++sd) {
+            const int e = m->face_e[2 * f + sd], lr = m->face_l[2 * f + sd];
+            const int imp = m->elem_to_imp[e];
+            tside[(size_t(F) * 2 + sd) * 2] = imp;
+            tside[(size_t(F) * 2 + sd) * 2 + 1] = lr;
+            for (int lc = 0; lc < 4; ++lc) {
+                const int fc = m->elem_face[4 * e + lc];
+                const int G = m->trace_of_face[fc];
+                if (G < 0) continue;
+                const int sc = m->elem_side[4 * e + lc];
+                auto& v = cols[G];
+                v.push_back(imp);
+                v.push_back(lr * 2 + sd);
+                v.push_back(lc * 2 + sc);
+            }
+        }
+        for (auto& kv : cols) {
+            if (kv.first == F) diag[F] = int(col.size());
+            col.push_back(kv.first);
+            for (int c = 0; c < 2; ++c)
+                for (int z = 0; z < 3; ++z)
+                    contrib.push_back(size_t(3 * c + z) < kv.second.size()
+                                          ? kv.second[3 * c + z] : -1);
+        }
+        rowptr[F + 1] = int(col.size());
+    }
+    s->nblocks = int(col.size());
+    size_t& tot = s->ws_bytes;
+    const size_t scal = o->precision == HFR_PREC_FP64 ? 8 : 4;
+    const size_t nimp = size_t(m->Nim), np4 = 4 * size_t(m->Np);
+    const size_t bb = size_t(s->bs) * s->bs;
+    fr_status e;
+    char* Mraw = nullptr;
+    if ((e = dalloc(&Mraw, nimp * s->elem_M * scal, tot)) ||
+        (o->keep_blocks &&
+         (e = dalloc(&s->blocks_copy, nimp * size_t(s->n + s->m) * (s->n + s->m), tot))) ||
+        (e = dalloc(&s->h, nimp * np4, tot)) ||
+        (e = dalloc(&s->gk, nimp * 16 * P, tot)) ||
+        (e = dalloc(&s->g, size_t(s->N), tot)) ||
+        (e = dalloc(&s->Rtmp, nimp * np4, tot)) ||
+        (e = dalloc(&s->ustar, nimp * np4, tot)) ||
+        (e = dalloc(&s->du, nimp * np4, tot)) ||
+        (e = dalloc(&s->duhat, size_t(s->N), tot)) ||
+        (e = dalloc(&s->rowptr, rowptr.size(), tot)) ||
+        (e = dalloc(&s->col, col.size(), tot)) ||
+        (e = dalloc(&s->contrib, contrib.size(), tot)) ||
+        (e = dalloc(&s->tside, tside.size(), tot)) ||
+        (e = dalloc(&s->diag_blk, diag.size(), tot)) ||
+        (o->precision == HFR_PREC_FP64 && (e = dalloc(&s->L64, size_t(s->nblocks) * bb, tot))) ||
+        (o->precision == HFR_PREC_FP32 && (e = dalloc(&s->L32, size_t(s->nblocks) * bb, tot))) ||
+        (e = dalloc(&s->t, size_t(s->N), tot)) ||
+        (e = dalloc(reinterpret_cast<char**>(&s->Dinv),
+                    size_t(m->Ntf) * bb * (o->precond == HFR_PC_FP64 ? 8 : o->precond == HFR_PC_FP32 ? 4 : 2),
+                    tot)) ||
+        (e = dalloc(&s->flags, 2, tot)) ||
+        (e = dalloc(&s->V, size_t(s->restart + 1) * std::max(1, s->N), tot)) ||
+        (e = dalloc(&s->z, size_t(std::max(1, s->N)), tot)) ||
+        (e = dalloc(&s->r, size_t(std::max(1, s->N)), tot)) ||
+        (e = dalloc(&s->scratch, size_t(4096) * 66, tot)) ||
+        (e = dalloc(&s->dots, 256, tot)) ||
+        (e = dalloc(&s->coef, 128, tot))) {
+        s->M = Mraw;
+        free_solver(s);
+        delete s;
+        return e;
+    }
+    s->M = Mraw;
+    s->nblk_dot = multidot_blocks(std::max(1, s->N));
+    auto up = [&](int* d, const std::vector<int>& h) {
+        return h.empty() ? hipSuccess
+                         : hipMemcpy(d, h.data(), 4 * h.size(), hipMemcpyHostToDevice);
+    };
+    if (up(s->rowptr, rowptr) != hipSuccess || up(s->col, col) != hipSuccess ||
+        up(s->contrib, contrib) != hipSuccess || up(s->tside, tside) != hipSuccess ||
+        up(s->diag_blk, diag) != hipSuccess ||
+        hipMemset(s->flags, 0, 8) != hipSuccess) {
+        free_solver(s);
+        delete s;
+        return fail(FR_E_DEVICE, "upload of solver tables failed");
+    }
+    if (ws) *ws = tot;
+    *out = s;
+    return FR_OK;
+}
+
+extern "C" void hfr_solver_destroy(hfr_solver_t s) {
+    if (!s) return;
+    free_solver(s);
+    delete s;
+}
+
+extern "C" fr_status hfr_residual(hfr_solver_t s, const double* u,
+                                  const double* uhat, const double* ustar,
+                                  double aii_dt, double* h, double* g,
+                                  double* R_im, void* stream) {
+    if (!s || !u || (!uhat && s->mesh->Ntp) || !ustar)
+        return fail(FR_E_INVALID, "null argument");
+    hipStream_t st = hipStream_t(stream);
+    fr_mesh_s* m = s->mesh;
+    fr_status e = residual_internal(s, u, uhat, ustar, aii_dt, R_im, st);
+    if (e) return e;
+    if (h && m->Nim)
+        HIP_TRY(hipMemcpyAsync(h, s->h, sizeof(double) * 4 * m->Nim * m->Np,
+                               hipMemcpyDeviceToDevice, st));
+    if (g && m->Ntp)
+        HIP_TRY(hipMemcpyAsync(g, s->g, sizeof(double) * 4 * m->Ntp,
+                               hipMemcpyDeviceToDevice, st));
+    return FR_OK;
+}
+
+extern "C" fr_status hfr_assemble_condense(hfr_solver_t s, const double* u,
+                                           const double* uhat,
+                                           const double* ustar, double aii_dt,
+                                           void* stream) {
+    if (!s || !u || (!uhat && s->mesh->Ntp) || !ustar)
+        return fail(FR_E_INVALID, "null argument");
+    hipStream_t st = hipStream_t(stream);
+    fr_status e = residual_internal(s, u, uhat, ustar, aii_dt, nullptr, st);
+    if (e) return e;
+    return condense_internal(s, u, uhat, aii_dt, st);
+}
+
+extern "C" fr_status hfr_trace_solve(hfr_solver_t s, double* duhat,
+                                     hfr_solve_stats* stats, void* stream) {
+    if (!s || (!duhat && s->N)) return fail(FR_E_INVALID, "null argument");
+    return gmres(s, duhat, stats, hipStream_t(stream));
+}
+
+extern "C" fr_status hfr_recover(hfr_solver_t s, const double* duhat,
+                                 double* du, void* stream) {
+    if (!s || (!duhat && s->N) || (!du && s->mesh->Nim))
+        return fail(FR_E_INVALID, "null argument");
+    fr_mesh_s* m = s->mesh;
+    HIP_TRY(launch_recover(m->P, m->Nim, s->M, s->opts.precision,
+                           m->d_trace_map, duhat, du, hipStream_t(stream)));
+    return FR_OK;
+}
+
+extern "C" fr_status hfr_trace_matvec(hfr_solver_t s, const double* x,
+                                      double* y, void* stream) {
+    if (!s || (s->N && (!x || !y))) return fail(FR_E_INVALID, "null argument");
+    fr_mesh_s* m = s->mesh;
+    HIP_TRY(launch_spmv(m->Ntf, s->bs, s->rowptr, s->col, s->L64,
+                        s->L64 ? nullptr : s->L32, x, y, 1.0, nullptr,
+                        hipStream_t(stream)));
+    return FR_OK;
+}
+
+extern "C" fr_status hfr_get_system(hfr_solver_t s, double* t, double* h,
+                                    double* g, void* stream) {
+    if (!s) return fail(FR_E_INVALID, "null solver");
+    fr_mesh_s* m = s->mesh;
+    hipStream_t st = hipStream_t(stream);
+    if (t && s->N) HIP_TRY(hipMemcpyAsync(t, s->t, 8 * size_t(s->N), hipMemcpyDeviceToDevice, st));
+    if (g && s->N) HIP_TRY(hipMemcpyAsync(g, s->g, 8 * size_t(s->N), hipMemcpyDeviceToDevice, st));
+    if (h && m->Nim)
+        HIP_TRY(hipMemcpyAsync(h, s->h, 8 * size_t(4) * m->Nim * m->Np,
+                               hipMemcpyDeviceToDevice, st));
+    return FR_OK;
+}
+
+extern "C" fr_status hfr_get_blocks(hfr_solver_t s, double* blocks,
+                                    void* stream) {
+    if (!s || !blocks) return fail(FR_E_INVALID, "null argument");
+    if (!s->blocks_copy) return fail(FR_E_INVALID, "solver created without keep_blocks");
+    fr_mesh_s* m = s->mesh;
+    const size_t nb = size_t(m->Nim) * (s->n + s->m) * (s->n + s->m) * 8;
+    HIP_TRY(hipMemcpyAsync(blocks, s->blocks_copy, nb, hipMemcpyDeviceToDevice,
+                           hipStream_t(stream)));
+    return FR_OK;
+}
+
+extern "C" fr_status imex_stage(fr_mesh_t mesh, hfr_solver_t s,
+                                const imex_tableau* tab, int32_t stage,
+                                double dt, const imex_state* stt,
+                                hfr_newton_stats* stats, void* stream) {
+    if (!mesh || !tab || !stt || !stt->u_n || !stt->u)
+        return fail(FR_E_INVALID, "null argument");
+    fr_mesh_s* m = mesh;
+    if (m->host_only) return fail(FR_E_INVALID, "host-only mesh");
+    if (m->Nim && (!s || s->mesh != mesh))
+        return fail(FR_E_INVALID, "a solver of this mesh is required");
+    const int S = tab->s;
+    if (S < 1 || S > 4) return fail(FR_E_INVALID, "tableau stages must be 1..4");
+    if (stage < 0 || stage > S + 1) return fail(FR_E_INVALID, "stage out of range");
+    if ((m->Nex && !stt->R_ex) || (m->Nim && !stt->R_im) || (m->Ntp && !stt->uhat))
+        return fail(FR_E_INVALID, "missing stage buffers");
+    hipStream_t st = hipStream_t(stream);
+    const size_t pex = 4 * size_t(m->Nex) * m->Np, pim = 4 * size_t(m->Nim) * m->Np;
+    if (stats) *stats = hfr_newton_stats{};
+    if (stage == 0) {
+        HIP_TRY(hipMemcpyAsync(stt->u, stt->u_n, 8 * 4 * size_t(m->Ne) * m->Np,
+                               hipMemcpyDeviceToDevice, st));
+        int tk = tbegin(s, HFR_T_EXPLICIT, st);
+        fr_status ex = fr_explicit_rhs(mesh, stt->u_n, stt->R_ex, stream);
+        tend(s, tk, st);
+        return ex;
+    }
+    if (stage == S + 1) {
+        const double* terms[6];
+        double coefs[6];
+        for (int j = 0; j <= S; ++j) {
+            terms[j] = stt->R_ex + j * pex;
+            coefs[j] = dt * tab->bbar[j];
+        }
+        HIP_TRY(launch_combine(m->Nex, m->Np, m->Ne, m->d_exp, stt->u_n, S + 1,
+                               terms, coefs, stt->u, 1, st));
+        for (int j = 0; j < S; ++j) {
+            terms[j] = stt->R_im + j * pim;
+            coefs[j] = dt * tab->b[j];
+        }
+        HIP_TRY(launch_combine(m->Nim, m->Np, m->Ne, m->d_imp, stt->u_n, S,
+                               terms, coefs, stt->u, 1, st));
+        return FR_OK;
+    }
+    const int I = stage;   // 1-based implicit stage
+    {
+        const double* terms[6];
+        double coefs[6];
+        for (int j = 0; j < I; ++j) {
+            terms[j] = stt->R_ex + j * pex;
+            coefs[j] = dt * tab->Abar[I * (S + 1) + j];
+        }
+        HIP_TRY(launch_combine(m->Nex, m->Np, m->Ne, m->d_exp, stt->u_n, I,
+                               terms, coefs, stt->u, 1, st));
+    }
+    if (m->Nim) {
+        const double* terms[6];
+        double coefs[6];
+        for (int j = 0; j < I - 1; ++j) {
+            terms[j] = stt->R_im + j * pim;
+            coefs[j] = dt * tab->A[(I - 1) * S + j];
+        }
+        HIP_TRY(launch_combine(m->Nim, m->Np, m->Ne, m->d_imp, stt->u_n, I - 1,
+                               terms, coefs, s->ustar, 0, st));
+        const double aii_dt = dt * tab->A[(I - 1) * S + (I - 1)];
+        HIP_TRY(launch_trace_average_ops(m->ops, m->Ntp, m->Ne, m->d_tpside,
+                                         m->d_imp, stt->u, stt->uhat, st));
+        fr_status e = sync_check(st);
+        if (e) return e;
+        auto t0 = std::chrono::steady_clock::now();
+        hfr_newton_stats ns{};
+        e = newton(s, stt->u, stt->uhat, s->ustar, aii_dt, &ns, st);
+        fr_status e2 = sync_check(st);
+        ns.implicit_ms = std::chrono::duration<double, std::milli>(
+                             std::chrono::steady_clock::now() - t0).count();
+        if (stats) *stats = ns;
+        if (e) return e;
+        if (e2) return e2;
+        fr_status e3 = residual_internal(s, stt->u, stt->uhat, s->ustar, aii_dt,
+                                         stt->R_im + (I - 1) * pim, st);
+        if (e3) return e3;
+    }
+    int tk = tbegin(s, HFR_T_EXPLICIT, st);
+    fr_status ex = fr_explicit_rhs(mesh, stt->u, stt->R_ex + I * pex, stream);
+    tend(s, tk, st);
+    if (s && s->pending.size() > 4096) tflush(s);
+    return ex;
+}
+
+extern "C" fr_status hfr_timing(hfr_solver_t s, int32_t enable, double* ms,
+                                int64_t* counts) {
+    if (!s) return fail(FR_E_INVALID, "null solver");
+    if (ms || counts) {
+        tflush(s);
+        for (int i = 0; i < HFR_NTIMERS; ++i) {
+            if (ms) ms[i] = s->tms[i];
+            if (counts) counts[i] = s->tcnt[i];
+        }
+    }
+    if (enable == 1) {
+        tflush(s);
+        for (int i = 0; i < HFR_NTIMERS; ++i) {
+            s->tms[i] = 0.0;
+            s->tcnt[i] = 0;
+        }
+        s->timing = true;
+    } else if (enable == 0) {
+        s->timing = false;
+    }
+    return FR_OK;
+}

@@ -1,0 +1,83 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared entry
+point, and its host-side mesh logic (skeleton, partition, trace map,
+stiffness indicator) matches the oracle bit for bit."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2401_16632_amd as hp
+from paper_2401_16632_amd import _abi
+from tests.cases import c1_desc, cylinder_desc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "hfr_imex.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(?:fr_status|void|const char\*)\s+(\w+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = hp.load_library()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(names) == sorted(_abi.EXPORTED)
+
+
+@pytest.mark.parametrize("case,p", [("c1", 2), ("c1p", 3), ("cyl", 3), ("cyl", 1)])
+def test_maps_bit_exact_vs_oracle(case, p):
+    if case == "c1":
+        d, mask = c1_desc()
+    elif case == "c1p":
+        d, mask = c1_desc(n=6, perturb=0.2, seed=4)
+    else:
+        d, mask = cylinder_desc()
+    uinf = (1.0, 1.0, 0.0, 40.0)
+    om = oracle.QuadMesh(d, p, implicit_mask=mask, uinf=uinf)
+    hm = hp.Mesh(d, p, implicit_mask=mask, uinf=uinf, host_only=True)
+    mp = hm.maps()
+    oc = om.counts()
+    for k in ("n_elems", "n_faces", "n_implicit", "n_trace_faces",
+              "n_trace_points", "n_upsilon", "n_boundary"):
+        assert hm.info[k] == oc[k], k
+    assert np.array_equal(mp["face_elem"], om.face_e)
+    fl = np.where(om.face_e >= 0, om.face_l, -1)
+    assert np.array_equal(mp["face_local"], fl)
+    assert np.array_equal(mp["face_kind"], om.face_kind)
+    assert np.array_equal(mp["implicit_elems"], om.imp_elems)
+    assert np.array_equal(mp["explicit_elems"], om.exp_elems)
+    assert np.array_equal(mp["trace_map"], om.trace_map)
+    assert np.array_equal(mp["es"], om.Es)
+    xy = np.stack([om.x, om.y], -1).reshape(om.Ne, -1, 2)
+    assert np.abs(mp["sol_xy"] - xy).max() < 1e-14 * max(1, np.abs(xy).max())
+
+
+def test_es_cutoff_partition_matches_oracle():
+    d, _ = cylinder_desc(n_r=8, first=1e-3, ratio=1.3)
+    om = oracle.QuadMesh(d, 1, es_cutoff=0.0)
+    es = om.Es.reshape(8, -1)
+    cut = 0.5 * (es[2].max() + es[3].min())
+    om = oracle.QuadMesh(d, 1, es_cutoff=cut, uinf=(1, 1, 0, 40))
+    hm = hp.Mesh(d, 1, es_cutoff=cut, uinf=(1, 1, 0, 40), host_only=True)
+    assert np.array_equal(hm.maps()["implicit_elems"], om.imp_elems)
+
+
+def test_mesh_errors_reported():
+    d, _ = c1_desc(n=4)
+    bad = dict(d)
+    bad["elem_nodes"] = d["elem_nodes"][:, ::-1].copy()
+    with pytest.raises(hp.HfrError, match="FR_E_MESH"):
+        hp.Mesh(bad, 2, host_only=True)
+    d2, _ = cylinder_desc()
+    d2 = dict(d2)
+    d2["elem_face_bc"] = np.zeros_like(d2["elem_face_bc"])
+    with pytest.raises(hp.HfrError, match="FR_E_MESH"):
+        hp.Mesh(d2, 2, host_only=True)
+    with pytest.raises(hp.HfrError, match="FR_E_INVALID"):
+        hp.Mesh(d, 9, host_only=True)

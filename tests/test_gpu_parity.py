@@ -1,0 +1,192 @@
+"""GPU parity of every entry point of the C ABI against the CPU oracle on
+the same seeded inputs (elementwise; tolerances derived from FP64 rounding
+of the operations involved)."""
+import numpy as np
+import pytest
+import torch
+
+import fr_inputs as fi
+import oracle
+from oracle import residual as ores, newton as onw, imex as oimex
+import paper_2401_16632_amd as hp
+from tests.cases import c1_desc, cylinder_desc, cylinder_state_at
+from tests.gpu_util import Pair, dev, host, soa, unsoa, rel_err
+
+pytestmark = pytest.mark.gpu
+
+UINF_CYL = tuple(fi.freestream_state(0.2))
+
+
+def _pairs():
+    d1, m1 = c1_desc()
+    d2, m2 = c1_desc(n=6, perturb=0.2, seed=4)
+    d3, m3 = cylinder_desc(n_theta=24, n_r=8, n_implicit_rings=3)
+    return {
+        "c1_p2": (d1, 2, m1, "vortex"),
+        "pert_p3": (d2, 3, m2, "vortex"),
+        "cyl_p3": (d3, 3, m3, "cyl"),
+        "cyl_p4": (d3, 4, m3, "cyl"),
+    }
+
+
+def _build(name):
+    d, p, mask, kind = _pairs()[name]
+    uinf = UINF_CYL if kind == "cyl" else (1.0, 1.0, 0.0, 40.0)
+    pr = Pair(d, p, mask, uinf=uinf)
+    om = pr.om
+    if kind == "vortex":
+        u = fi.perturb_state(fi.isentropic_vortex(om.x, om.y), 0.01, 11)
+    else:
+        u = cylinder_state_at(om.x, om.y, seed=3, amp=0.02)
+    return pr, u
+
+
+@pytest.mark.parametrize("name", ["c1_p2", "pert_p3", "cyl_p3", "cyl_p4"])
+def test_explicit_rhs(name):
+    pr, u = _build(name)
+    om, hm = pr.om, pr.hm
+    R_o = ores.fr_residual(om, pr.ph, u)[om.exp_elems]
+    ud = dev(soa(u))
+    R = torch.zeros(4 * hm.Nex * hm.Np, dtype=torch.float64, device="cuda")
+    hm.explicit_rhs(ud, R)
+    torch.cuda.synchronize()
+    R_g = unsoa(host(R), hm.Nex, pr.P)
+    scale = max(1.0, np.abs(R_o).max())
+    assert np.abs(R_g - R_o).max() <= 1e-12 * scale
+
+
+def _stage_inputs(pr, u, seed=5):
+    om = pr.om
+    uhat = fi.perturb_state(ores.trace_average(om, u), 0.005, seed)
+    ustar = fi.perturb_state(u[om.imp_elems], 0.005, seed + 1)
+    return uhat, ustar
+
+
+@pytest.mark.parametrize("name", ["c1_p2", "pert_p3", "cyl_p3"])
+def test_hfr_residual(name):
+    pr, u = _build(name)
+    om, hm = pr.om, pr.hm
+    uhat, ustar = _stage_inputs(pr, u)
+    a = 0.037
+    R_o, g_o = ores.hfr_residual(om, pr.ph, u, uhat)
+    h_o = u[om.imp_elems] - ustar - a * R_o
+    s = hp.Solver(hm)
+    h = torch.zeros(4 * hm.Nim * hm.Np, dtype=torch.float64, device="cuda")
+    g = torch.zeros(4 * hm.Ntp, dtype=torch.float64, device="cuda")
+    R = torch.zeros_like(h)
+    s.residual(dev(soa(u)), dev(uhat), dev(soa(ustar)), a, h=h, g=g, R_im=R)
+    torch.cuda.synchronize()
+    P = pr.P
+    sc = max(1.0, np.abs(R_o).max())
+    assert np.abs(unsoa(host(R), hm.Nim, P) - R_o).max() <= 1e-12 * sc
+    assert np.abs(unsoa(host(h), hm.Nim, P) - h_o).max() <= 1e-12 * sc
+    assert np.abs(host(g).reshape(-1, 4) - g_o).max() <= 1e-12 * max(1.0, np.abs(g_o).max())
+
+
+@pytest.mark.parametrize("name", ["c1_p2", "cyl_p3"])
+def test_element_blocks_match_oracle_derivatives(name):
+    pr, u = _build(name)
+    om, hm = pr.om, pr.hm
+    uhat, ustar = _stage_inputs(pr, u)
+    a = 0.05
+    outer = ores.implicit_outer(om, u, uhat)
+    A, B, C, D = onw.element_blocks(om, pr.ph, u[om.imp_elems], outer, a)
+    s = hp.Solver(hm, keep_blocks=True)
+    s.assemble_condense(dev(soa(u)), dev(uhat), dev(soa(ustar)), a)
+    n, m = s.n, s.m
+    blk = torch.zeros(hm.Nim * (n + m) ** 2, dtype=torch.float64, device="cuda")
+    s.get_blocks(blk)
+    torch.cuda.synchronize()
+    G = host(blk).reshape(hm.Nim, n + m, n + m)
+    sc = max(1.0, np.abs(A).max())
+    assert np.abs(G[:, :n, :n] - A).max() <= 1e-11 * sc
+    for k in range(hm.Nim):
+        loc, _ = onw.trace_index(om, k, 4)
+        assert np.abs(G[k, :n, n + loc] - B[k][:, loc]).max() <= 1e-11 * sc
+        assert np.abs(G[k, n + loc, :n] - C[k][loc, :]).max() <= 1e-11 * max(1, np.abs(C).max())
+        assert np.abs(G[k][np.ix_(n + loc, n + loc)] - D[k][np.ix_(loc, loc)]).max() <= 1e-11 * max(1, np.abs(D).max())
+
+
+@pytest.mark.parametrize("name", ["c1_p2", "pert_p3", "cyl_p3"])
+def test_condense_solve_recover(name):
+    pr, u = _build(name)
+    om, hm = pr.om, pr.hm
+    uhat, ustar = _stage_inputs(pr, u)
+    a = 0.05
+    sysd = onw.condense(om, pr.ph, u, uhat, ustar, a)
+    s = hp.Solver(hm, rtol=1e-13, max_iters=2000, restart=60)
+    s.assemble_condense(dev(soa(u)), dev(uhat), dev(soa(ustar)), a)
+    N = 4 * hm.Ntp
+    t = torch.zeros(N, dtype=torch.float64, device="cuda")
+    s.get_system(t=t)
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=N)
+    y = torch.zeros(N, dtype=torch.float64, device="cuda")
+    s.matvec(dev(x), y)
+    torch.cuda.synchronize()
+    Lx = sysd["L"] @ x
+    assert np.abs(host(y) - Lx).max() <= 1e-11 * max(1, np.abs(Lx).max())
+    assert np.abs(host(t) - sysd["t"]).max() <= 1e-11 * max(1, np.abs(sysd["t"]).max())
+    duh = torch.zeros(N, dtype=torch.float64, device="cuda")
+    st = s.trace_solve(duh)
+    duh_o = onw.trace_solve(sysd["L"], sysd["t"])
+    assert st["rel_residual"] <= 1e-13
+    assert np.abs(host(duh) - duh_o).max() <= 1e-9 * max(1e-300, np.abs(duh_o).max())
+    du = torch.zeros(4 * hm.Nim * hm.Np, dtype=torch.float64, device="cuda")
+    s.recover(dev(duh_o), du)
+    torch.cuda.synchronize()
+    du_o = onw.recover(sysd, duh_o).reshape(hm.Nim, pr.P, pr.P, 4)
+    assert np.abs(unsoa(host(du), hm.Nim, pr.P) - du_o).max() <= 1e-11 * max(1e-300, np.abs(du_o).max())
+
+
+def _run_steps(pr, u0, dt, nsteps, precision="fp64", precond="fp64",
+               tab="HIMEX2C", tol=1e-13):
+    om, hm = pr.om, pr.hm
+    s = hp.Solver(hm, precision=precision, precond=precond, rtol=1e-12,
+                  newton_tol=tol, max_iters=3000)
+    stp = hp.ImexStepper(hm, s, tab)
+    ud = dev(soa(u0))
+    uo = u0.copy()
+    errs, its = [], []
+    for _ in range(nsteps):
+        un, stats = stp.step(ud, dt)
+        ud = un.clone()
+        uo, _ = oimex.imex_step(om, pr.ph, oimex.TABLEAUS[tab](), uo, dt, tol=1e-13)
+        ug = unsoa(host(ud), hm.Ne, pr.P)
+        errs.append(rel_err(ug, uo))
+        its.append([st["newton_iters"] for st in stats])
+    return errs, its
+
+
+def test_imex_steps_fp64_c1():
+    """The FP64 GPU path matches the oracle within 1e-11 (relative, per
+    conserved variable) after every one of 10 steps of the vortex case."""
+    pr, _ = _build("c1_p2")
+    u0 = fi.isentropic_vortex(pr.om.x, pr.om.y)
+    errs, its = _run_steps(pr, u0, 0.01, 10)
+    assert max(errs) <= 1e-11, errs
+
+
+def test_imex_steps_fp64_cylinder_ars():
+    pr, u = _build("cyl_p3")
+    errs, _ = _run_steps(pr, u, 2e-3, 2, tab="ARS222")
+    assert max(errs) <= 1e-11, errs
+
+
+@pytest.mark.parametrize("pc", ["fp32", "bf16"])
+def test_imex_steps_fp32_condensation(pc):
+    """FP32 element LU / Schur products with FP64 residuals and Newton: the
+    converged step still matches the FP64 oracle within 1e-8."""
+    pr, _ = _build("c1_p2")
+    u0 = fi.isentropic_vortex(pr.om.x, pr.om.y)
+    errs, its = _run_steps(pr, u0, 0.01, 3, precision="fp32", precond=pc)
+    assert max(errs) <= 1e-8, errs
+
+
+def test_all_explicit_and_all_implicit_meshes():
+    d, _ = c1_desc(n=4)
+    for mask in (np.zeros(16, bool), np.ones(16, bool)):
+        pr = Pair(d, 2, mask)
+        u0 = fi.isentropic_vortex(pr.om.x, pr.om.y)
+        errs, _ = _run_steps(pr, u0, 0.02, 1)
+        assert max(errs) <= 1e-11, errs

@@ -161,6 +161,13 @@ typedef struct {
                                  newton_tol * max(1, |u*|inf)                */
     int32_t keep_blocks;      /* 1: keep a copy of the element blocks
                                  [A B; C D] (FP64) for inspection            */
+    int32_t jacobian_lag;     /* 0: re-linearise at every Newton iteration;
+                                 K > 0: re-linearise (blocks, LU, Schur, L)
+                                 only at the first iteration of every K-th
+                                 stage solve and otherwise reuse the stored
+                                 factors, re-condensing only the right-hand
+                                 side (the paper updates its Jacobian every
+                                 100 steps, Sec. 5.3)                        */
 } hfr_opts;
 
 typedef struct {
@@ -241,6 +248,13 @@ fr_status hfr_trace_matvec(hfr_solver_t s, const double* x, double* y,
 fr_status hfr_get_system(hfr_solver_t s, double* t, double* h, double* g,
                          void* stream);
 fr_status hfr_get_blocks(hfr_solver_t s, double* blocks, void* stream);
+/* Factored element matrices of the last linearisation, (n+m) x (n+m+1) per
+ * implicit element, row-major, FP64 or FP32 as the solver's precision:
+ * rows 0..n-1 hold L\U (unit L) and L^-1 P [B r], rows n.. hold C U^-1
+ * and [L^k t^k].  piv (may be NULL) receives the pivot row of each of the
+ * n elimination steps per element, int32. */
+fr_status hfr_get_factors(hfr_solver_t s, void* factors, int32_t* piv,
+                          void* stream);
 
 /*
  * hfr_timing: HIP-event timers around the solver's kernels, on the stream

@@ -15,7 +15,8 @@ EXPORTED = ["fr_mesh_create", "fr_mesh_destroy", "fr_mesh_get_info",
             "fr_mesh_get_maps", "fr_explicit_rhs", "hfr_solver_create",
             "hfr_solver_destroy", "hfr_residual", "hfr_assemble_condense",
             "hfr_trace_solve", "hfr_recover", "hfr_trace_matvec",
-            "hfr_get_system", "hfr_get_blocks", "hfr_timing", "imex_stage",
+            "hfr_get_system", "hfr_get_blocks", "hfr_get_factors", "hfr_timing",
+            "imex_stage",
             "fr_last_error"]
 TIMERS = ["residual", "condense", "assemble", "pcsetup", "spmv",
           "trace_solve", "recover", "explicit"]
@@ -43,7 +44,8 @@ class HfrOpts(Structure):
     _fields_ = [("precision", c_int32), ("precond", c_int32),
                 ("gmres_restart", c_int32), ("gmres_max_iters", c_int32),
                 ("gmres_rtol", c_double), ("newton_max_iters", c_int32),
-                ("newton_tol", c_double), ("keep_blocks", c_int32)]
+                ("newton_tol", c_double), ("keep_blocks", c_int32),
+                ("jacobian_lag", c_int32)]
 
 
 class HfrSolveStats(Structure):
@@ -97,6 +99,7 @@ def load(path=LIB_PATH):
         "imex_stage": (c_int32, [c_void_p, c_void_p, P(ImexTableau), c_int32,
                                  c_double, P(ImexState), P(HfrNewtonStats),
                                  c_void_p]),
+        "hfr_get_factors": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
         "hfr_timing": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
         "fr_last_error": (c_char_p, []),
     }

@@ -176,7 +176,7 @@ class Solver:
 
     def __init__(self, mesh, precision="fp64", precond="fp64", restart=30,
                  max_iters=600, rtol=1e-10, newton_max_iters=25,
-                 newton_tol=1e-13, keep_blocks=False):
+                 newton_tol=1e-13, keep_blocks=False, jacobian_lag=0):
         lib = load_library()
         self.mesh = mesh
         o = _abi.HfrOpts()
@@ -188,6 +188,7 @@ class Solver:
         o.newton_max_iters = newton_max_iters
         o.newton_tol = newton_tol
         o.keep_blocks = 1 if keep_blocks else 0
+        o.jacobian_lag = int(jacobian_lag)
         self.opts = o
         ws = ctypes.c_size_t()
         h = ctypes.c_void_p()
@@ -248,6 +249,18 @@ class Solver:
         _check(load_library().hfr_get_blocks(
             self.handle, _dev(out, self.mesh.Nim * k * k, "blocks"),
             _stream(stream)))
+
+    def get_factors(self, stream=None):
+        """Factored element matrices (Nim, n+m, n+m+1) and pivots (Nim, n)."""
+        m = self.mesh
+        k = self.n + self.m
+        dt = torch.float64 if self.opts.precision == 0 else torch.float32
+        f = torch.zeros(m.Nim * k * (k + 1), dtype=dt, device="cuda")
+        pv = torch.zeros(m.Nim * self.n, dtype=torch.int32, device="cuda")
+        _check(load_library().hfr_get_factors(
+            self.handle, ctypes.c_void_p(f.data_ptr()),
+            ctypes.c_void_p(pv.data_ptr()), _stream(stream)))
+        return f.view(m.Nim, k, k + 1), pv.view(m.Nim, self.n)
 
     def timing(self, enable=None):
         """Start (True) / stop (False) the kernel timers; returns the

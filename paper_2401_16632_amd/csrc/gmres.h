@@ -1,0 +1,47 @@
+// Device-resident GMRES state and kernel arguments.
+#pragma once
+
+#include "internal.h"
+
+namespace hfr {
+
+constexpr int kGmresMaxK = 65;   // restart <= 64
+
+struct GmresState {
+    int done, converged, jlast, iters, cycles, pad;
+    double inv_norm, beta, bnorm, target;
+    double h1[kGmresMaxK], h2[kGmresMaxK];
+    double cs[kGmresMaxK], sn[kGmresMaxK], g[kGmresMaxK + 1];
+    double H[(kGmresMaxK + 1) * kGmresMaxK];
+};
+
+struct GmresArgs {
+    int ntf, bs, fpb, nblk, restart, pc;
+    double rtol;
+    size_t ldv;
+    const int* rowptr;
+    const int* col;
+    const double* L64;       // original matrix (true residual)
+    const float* L32;
+    const double* Lt64;      // preconditioned matrix L Dinv
+    const float* Lt32;
+    const void* Dinv;
+    const double* t;
+    double* V;               // restart x ldv
+    double* part;            // nblk x kGmresMaxK
+    double* part2;           // nblk x 2
+    unsigned* counters;      // 4
+    GmresState* gs;
+};
+
+hipError_t launch_precondition_matrix(int nblocks, int bs, const int* col,
+                                      const double* L64, const float* L32,
+                                      int pc, const void* Dinv, double* Lt64,
+                                      float* Lt32, hipStream_t st);
+hipError_t launch_gmres_restart(const GmresArgs& a, const double* x,
+                                double* w, int first, hipStream_t st);
+hipError_t launch_arnoldi(const GmresArgs& a, int j, const double* wcur,
+                          double* wnxt, hipStream_t st);
+hipError_t launch_gmres_update(const GmresArgs& a, double* x, hipStream_t st);
+
+}  // namespace hfr

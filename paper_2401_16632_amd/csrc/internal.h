@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -91,9 +93,16 @@ struct CondenseLaunch {
     void* M;                 // per element (n+m) x (n+m+1), FP64 or FP32
     double* blocks_copy;     // optional (n+m)^2 FP64 copy per element
     int* pivot_fail;         // set to 1 if a zero pivot is met
+    int* piv;                // [Nim][n] pivot row chosen at each step
 };
 hipError_t launch_condense(const RefOps& ops, const CondenseLaunch& a,
                            hipStream_t st);
+// FP64 right-hand side with the stored factors: y = L^-1 P (-h) -> yr
+// [Nim][n], z = (C U^-1) y -> z [Nim][m]; the condensed right-hand side is
+// then t = -g - sum over the two sides of z (assembled in FP64)
+hipError_t launch_rhs64(int P, int nimp, const void* M, int precision,
+                        const int* piv, const double* h, double* yr,
+                        double* z, hipStream_t st);
 
 struct AssembleLaunch {
     int nblocks;             // BSR blocks
@@ -105,7 +114,9 @@ struct AssembleLaunch {
     int P, n, m;
     double* L64;             // [nblocks][bs][bs] column-major blocks or null
     float* L32;              // same in FP32 or null
-    double* t;               // [Ntf*bs]
+    double* t;               // [Ntf*bs]  t = -g - sum_sides z
+    const double* g;         // [Ntf*bs]  assembled transmission residual
+    const double* z;         // [Nim][m]  C A^-1 r per element
 };
 hipError_t launch_assemble(const AssembleLaunch& a, hipStream_t st);
 
@@ -127,8 +138,8 @@ hipError_t launch_scale(int N, double* x, const double* src, double a,
 hipError_t launch_axpy(int N, double a, const double* x, double* y,
                        hipStream_t st);
 hipError_t launch_recover(int P, int nimp, const void* M, int precision,
-                          const int* trace_map, const double* duhat,
-                          double* du, hipStream_t st);
+                          const double* yr, const int* trace_map,
+                          const double* duhat, double* du, hipStream_t st);
 hipError_t launch_newton_update(int Np, int nimp, int Ne, const int* imp_list,
                                 const double* du, double* u, int ntp4,
                                 const double* duhat, double* uhat,

@@ -11,7 +11,9 @@
 //      [ L\U    L^-1 P B     L^-1 P r   ]
 //      [ C U^-1  D - C A^-1 B  s - C A^-1 r ] = [ .  L^k  t^k ]
 // which holds the recovery factors of eq:localproblems (back substitution
-// with U) and the element Schur complement of eq:assembly in place.
+// with U) and the element Schur complement of eq:assembly in place.  The
+// right-hand side used by Newton is recomputed in FP64 by k_rhs64 from the
+// stored factors (the r, s columns here are not used downstream).
 //
 // Element-local ordering: u index = point*4 + var (point j*P+i), trace
 // index = (face*P + q)*4 + var with q counter-clockwise along the element.
@@ -30,8 +32,6 @@ struct CondShared {
     double Fu[4 * P][16];
     double Fh[4 * P][16];
     int tr[4];
-    double red_v[256];
-    int red_i[256];
 };
 
 template <int P>
@@ -198,78 +198,6 @@ __device__ __forceinline__ double aug_entry(int r, int c, int k,
     }
 }
 
-// One workgroup per implicit element; the augmented matrix lives in the
-// solver workspace (global memory, L2-resident while the element works).
-template <int P, typename T>
-__global__ __launch_bounds__(256) void k_condense_global(CondenseLaunch a,
-                                                         RefOps o) {
-    constexpr int NP = P * P;
-    constexpr int n = 4 * NP, m = 16 * P, rows = n + m, ld = n + m + 1;
-    __shared__ CondShared<P> sh;
-    const int k = blockIdx.x;
-    const int t = threadIdx.x;
-    element_linearisation<P>(a, o, k, sh);
-    T* M = reinterpret_cast<T*>(a.M) + size_t(k) * rows * ld;
-    for (int idx = t; idx < rows * ld; idx += blockDim.x) {
-        const int r = idx / ld, c = idx % ld;
-        const double val = aug_entry<P>(r, c, k, a, o, sh);
-        M[idx] = T(val);
-        if (a.blocks_copy && c < rows)
-            a.blocks_copy[size_t(k) * rows * rows + size_t(r) * rows + c] = val;
-    }
-    __syncthreads();
-    for (int kp = 0; kp < n; ++kp) {
-        // pivot: largest |M[r][kp]| over r in [kp, n), lowest index on ties
-        double best = -1.0;
-        int bi = kp;
-        for (int r = kp + t; r < n; r += blockDim.x) {
-            const double val = fabs(double(M[size_t(r) * ld + kp]));
-            if (val > best) { best = val; bi = r; }
-        }
-        sh.red_v[t] = best;
-        sh.red_i[t] = bi;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (t < s) {
-                const double v2 = sh.red_v[t + s];
-                const int i2 = sh.red_i[t + s];
-                if (v2 > sh.red_v[t] || (v2 == sh.red_v[t] && i2 < sh.red_i[t])) {
-                    sh.red_v[t] = v2;
-                    sh.red_i[t] = i2;
-                }
-            }
-            __syncthreads();
-        }
-        const int piv = sh.red_i[0];
-        if (sh.red_v[0] == 0.0) {
-            if (t == 0) *a.pivot_fail = 1;
-            return;
-        }
-        if (piv != kp) {
-            for (int c = kp + t; c < ld; c += blockDim.x) {
-                const T x = M[size_t(kp) * ld + c];
-                M[size_t(kp) * ld + c] = M[size_t(piv) * ld + c];
-                M[size_t(piv) * ld + c] = x;
-            }
-            __syncthreads();
-        }
-        const T inv = T(1) / M[size_t(kp) * ld + kp];
-        __syncthreads();
-        for (int c = kp + 1 + t; c < ld; c += blockDim.x) M[size_t(kp) * ld + c] *= inv;
-        __syncthreads();
-        const int width = ld - kp - 1;
-        const int total = (rows - 1) * width;
-        for (int idx = t; idx < total; idx += blockDim.x) {
-            int r = idx / width;
-            const int c = kp + 1 + idx % width;
-            r += (r >= kp);
-            M[size_t(r) * ld + c] -= M[size_t(r) * ld + kp] * M[size_t(kp) * ld + c];
-        }
-        __syncthreads();
-    }
-}
-
-
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
@@ -277,14 +205,19 @@ template <typename T> struct MfmaVec;
 template <> struct MfmaVec<float> { typedef floatx4 type; };
 template <> struct MfmaVec<double> { typedef doublex4 type; };
 
-// D(16x16) += A(16x4) B(4x16); lane l supplies A[l%16][l/16], B[l/16][l%16]
-// and holds D[4*(l/16)+r][l%16] in element r.
+// D(16x16) += A(16x4) B(4x16); lane l supplies A[l%16][l/16] and
+// B[l/16][l%16].  Element r of lane l holds D[i][l%16] with
+// i = 4*(l/16) + r for the FP32 instruction and i = l/16 + 4*r for the
+// FP64 one (measured on gfx950).
 __device__ __forceinline__ floatx4 mfma16(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 __device__ __forceinline__ doublex4 mfma16(double a, double b, doublex4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+template <typename T> __device__ __forceinline__ int mfma_row(int lk, int q);
+template <> __device__ __forceinline__ int mfma_row<float>(int lk, int q) { return 4 * lk + q; }
+template <> __device__ __forceinline__ int mfma_row<double>(int lk, int q) { return lk + 4 * q; }
 
 constexpr int kPanel = 16;
 
@@ -297,7 +230,7 @@ constexpr int kPanel = 16;
 // rows' trailing part, then a rank-16 trailing update on MFMA tiles.
 template <typename T>
 __device__ bool lu_condense(T* M, int n, int rows, int ld, int* s_piv,
-                            T* s_val) {
+                            T* s_val, int* piv_out) {
     typedef typename MfmaVec<T>::type vec4;
     const int t = threadIdx.x, nt = blockDim.x;
     const int lane = t & 63, wave = t >> 6, nwaves = nt >> 6;
@@ -322,6 +255,7 @@ __device__ bool lu_condense(T* M, int n, int rows, int ld, int* s_piv,
             __syncthreads();
             const int piv = *s_piv;
             if (!(*s_val > T(0))) return false;
+            if (t == 0) piv_out[kk] = piv;
             if (piv != kk) {
                 for (int c = t; c < ld; c += nt) {
                     const T x = M[size_t(kk) * ld + c];
@@ -365,7 +299,7 @@ __device__ bool lu_condense(T* M, int n, int rows, int ld, int* s_piv,
             const int cc = c0 + li;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int rr = r0 + 4 * lk + q;
+                const int rr = r0 + mfma_row<T>(lk, q);
                 acc[q] = (rr < rows && cc < ld) ? M[size_t(rr) * ld + cc] : T(0);
             }
             for (int kq = 0; kq < kw; kq += 4) {
@@ -376,7 +310,7 @@ __device__ bool lu_condense(T* M, int n, int rows, int ld, int* s_piv,
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int rr = r0 + 4 * lk + q;
+                const int rr = r0 + mfma_row<T>(lk, q);
                 if (rr < rows && cc < ld) M[size_t(rr) * ld + cc] = acc[q];
             }
         }
@@ -395,7 +329,7 @@ __global__ __launch_bounds__(256) void k_condense_lu(CondenseLaunch a, RefOps o)
     __shared__ CondShared<P> sh;
     __shared__ int s_piv;
     __shared__ T s_val;
-    extern __shared__ unsigned char dyn_lds[];
+    extern __shared__ double dyn_lds[];
     const int k = blockIdx.x;
     const int t = threadIdx.x;
     element_linearisation<P>(a, o, k, sh);
@@ -409,7 +343,8 @@ __global__ __launch_bounds__(256) void k_condense_lu(CondenseLaunch a, RefOps o)
             a.blocks_copy[size_t(k) * rows * rows + size_t(r) * rows + c] = val;
     }
     __syncthreads();
-    const bool ok = lu_condense<T>(M, n, rows, ld, &s_piv, &s_val);
+    const bool ok = lu_condense<T>(M, n, rows, ld, &s_piv, &s_val,
+                                   a.piv + size_t(k) * n);
     if (!ok) {
         if (t == 0) *a.pivot_fail = 1;
         return;
@@ -441,6 +376,60 @@ static hipError_t launch_lu(const RefOps& o, const CondenseLaunch& a,
         hipLaunchKernelGGL((k_condense_lu<P, T, false>), dim3(a.nimp), dim3(256),
                            0, st, a, o);
     }
+    return hipGetLastError();
+}
+
+// FP64 right-hand side with the stored factors (FP64 or FP32): the
+// element shares of g are large and cancel between the two sides of a
+// trace face, so they never pass through the factor precision; only
+// C A^-1 r does, which is proportional to the (small) residual h.
+template <typename T>
+__global__ void k_rhs64(int P, int nimp, const T* M, const int* piv,
+                        const double* h, double* yr, double* z) {
+    extern __shared__ double y[];
+    const int NP = P * P, n = 4 * NP, m = 16 * P, ld = n + m + 1;
+    const int k = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
+    const T* Mk = M + size_t(k) * (n + m) * ld;
+    for (int row = t; row < n; row += nt) {
+        const int pt = row >> 2, v = row & 3;
+        y[row] = -h[size_t(v) * nimp * NP + size_t(k) * NP + pt];
+    }
+    __syncthreads();
+    if (t == 0) {
+        const int* pk = piv + size_t(k) * n;
+        for (int kk = 0; kk < n; ++kk) {
+            const int p = pk[kk];
+            const double x = y[kk];
+            y[kk] = y[p];
+            y[p] = x;
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        const double yj = y[j];
+        for (int i = j + 1 + t; i < n; i += nt) y[i] -= double(Mk[size_t(i) * ld + j]) * yj;
+        __syncthreads();
+    }
+    for (int row = t; row < n; row += nt) yr[size_t(k) * n + row] = y[row];
+    for (int b = t; b < m; b += nt) {
+        const T* cr = Mk + size_t(n + b) * ld;
+        double acc = 0.0;
+        for (int j = 0; j < n; ++j) acc += double(cr[j]) * y[j];
+        z[size_t(k) * m + b] = acc;
+    }
+}
+
+hipError_t launch_rhs64(int P, int nimp, const void* M, int precision,
+                        const int* piv, const double* h, double* yr,
+                        double* z, hipStream_t st) {
+    if (nimp == 0) return hipSuccess;
+    const size_t shm = 4 * P * P * sizeof(double);
+    if (precision == HFR_PREC_FP64)
+        hipLaunchKernelGGL(k_rhs64<double>, dim3(nimp), dim3(128), shm, st, P,
+                           nimp, reinterpret_cast<const double*>(M), piv, h, yr, z);
+    else
+        hipLaunchKernelGGL(k_rhs64<float>, dim3(nimp), dim3(128), shm, st, P,
+                           nimp, reinterpret_cast<const float*>(M), piv, h, yr, z);
     return hipGetLastError();
 }
 

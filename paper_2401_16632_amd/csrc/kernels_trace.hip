@@ -79,22 +79,21 @@ __global__ void k_assemble(AssembleLaunch a) {
          idx += long(gridDim.x) * blockDim.x) {
         const int F = int(idx / bs), aa = int(idx % bs);
         const int q = aa >> 2, v = aa & 3;
-        double val = 0.0;
+        double zs = 0.0;
         for (int s = 0; s < 2; ++s) {
             const int imp = a.tside[(size_t(F) * 2 + s) * 2];
             if (imp < 0) continue;
             const int lf = a.tside[(size_t(F) * 2 + s) * 2 + 1];
             const int qe = s ? a.P - 1 - q : q;
-            const size_t row = a.n + (lf * a.P + qe) * 4 + v;
-            val += double(M[size_t(imp) * rows * ld + row * ld + (ld - 1)]);
+            zs += a.z[size_t(imp) * a.m + (lf * a.P + qe) * 4 + v];
         }
-        a.t[idx] = val;
+        a.t[idx] = -a.g[idx] - zs;
     }
 }
 
 hipError_t launch_assemble(const AssembleLaunch& a, hipStream_t st) {
     const int bs = 4 * a.P;
-    long work = long(a.nblocks) * bs * bs;
+    long work = std::max(long(a.nblocks) * bs * bs, long(a.ntf) * bs);
     int grid = blocks_for(work);
     if (grid > 65536) grid = 65536;
     if (a.precision == HFR_PREC_FP64)
@@ -369,11 +368,13 @@ hipError_t launch_absmax(int N, const double* x, double* partial, int nblk,
 }
 
 // ---- recovery (eq:localproblems) from the LU-condensed element matrix:
-// rows 0..n-1 hold L\U | Y_B | Y_r with Y = L^-1 P [B r], so
-// du = U^-1 (Y_r - Y_B duhat_loc) by back substitution.
+// rows 0..n-1 hold L\U | Y_B with Y_B = L^-1 P B, and y_r = L^-1 P r comes
+// from the FP64 right-hand-side pass, so du = U^-1 (y_r - Y_B duhat_loc)
+// by back substitution.
 template <typename T>
-__global__ void k_recover(int P, int nimp, const T* M, const int* trace_map,
-                          const double* duhat, double* du) {
+__global__ void k_recover(int P, int nimp, const T* M, const double* yr,
+                          const int* trace_map, const double* duhat,
+                          double* du) {
     extern __shared__ double sm[];
     const int NP = P * P, n = 4 * NP, m = 16 * P, ld = n + m + 1;
     double* loc = sm;
@@ -388,7 +389,7 @@ __global__ void k_recover(int P, int nimp, const T* M, const int* trace_map,
     const T* Mk = M + size_t(k) * (n + m) * ld;
     for (int row = t; row < n; row += nt) {
         const T* xr = Mk + size_t(row) * ld;
-        double acc = double(xr[ld - 1]);
+        double acc = yr[size_t(k) * n + row];
         for (int b = 0; b < m; ++b) acc -= double(xr[n + b]) * loc[b];
         y[row] = acc;
     }
@@ -407,18 +408,18 @@ __global__ void k_recover(int P, int nimp, const T* M, const int* trace_map,
 }
 
 hipError_t launch_recover(int P, int nimp, const void* M, int precision,
-                          const int* trace_map, const double* duhat,
-                          double* du, hipStream_t st) {
+                          const double* yr, const int* trace_map,
+                          const double* duhat, double* du, hipStream_t st) {
     if (nimp == 0) return hipSuccess;
     const size_t shm = (16 * P + 4 * P * P) * sizeof(double);
     if (precision == HFR_PREC_FP64)
         hipLaunchKernelGGL(k_recover<double>, dim3(nimp), dim3(128), shm, st, P,
-                           nimp, reinterpret_cast<const double*>(M), trace_map,
-                           duhat, du);
+                           nimp, reinterpret_cast<const double*>(M), yr,
+                           trace_map, duhat, du);
     else
         hipLaunchKernelGGL(k_recover<float>, dim3(nimp), dim3(128), shm, st, P,
-                           nimp, reinterpret_cast<const float*>(M), trace_map,
-                           duhat, du);
+                           nimp, reinterpret_cast<const float*>(M), yr,
+                           trace_map, duhat, du);
     return hipGetLastError();
 }
 

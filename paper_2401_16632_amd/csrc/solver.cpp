@@ -5,11 +5,14 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
 #include <vector>
 
+#include "gmres.h"
 #include "mesh.h"
 
 namespace hfr {
@@ -55,6 +58,20 @@ struct hfr_solver_s {
     double* t = nullptr;
     void* Dinv = nullptr;
     int* flags = nullptr;    // [0] pivot fail, [1] block inverse fail
+    double* Lt64 = nullptr;  // L Dinv (right-preconditioned matrix)
+    float* Lt32 = nullptr;
+    double* W = nullptr;     // 2 x N Arnoldi work vectors
+    GmresState* gs = nullptr;
+    double* part = nullptr;
+    double* part2 = nullptr;
+    unsigned* counters = nullptr;
+    int fpb = 1, gblk = 1;
+    int* piv = nullptr;      // [Nim][n]
+    double* yr = nullptr;    // [Nim][n]  L^-1 P r (FP64)
+    double* zz = nullptr;    // [Nim][m]  C A^-1 r (FP64)
+    bool have_factors = false;
+    bool verbose = false;
+    int stage_calls = 0;
     double* V = nullptr;     // (restart+1) x N
     double* z = nullptr;     // N
     double* r = nullptr;     // N
@@ -136,7 +153,9 @@ void free_solver(hfr_solver_s* s) {
     void* ptrs[] = {s->M, s->blocks_copy, s->h, s->gk, s->g, s->Rtmp,
                     s->ustar, s->du, s->duhat, s->rowptr, s->col, s->contrib,
                     s->tside, s->diag_blk, s->L64, s->L32, s->t, s->Dinv,
-                    s->flags, s->V, s->z, s->r, s->scratch, s->dots, s->coef};
+                    s->flags, s->V, s->z, s->r, s->scratch, s->dots, s->coef,
+                    s->Lt64, s->Lt32, s->W, s->gs, s->part, s->part2,
+                    s->counters, s->piv, s->yr, s->zz};
     for (void* p : ptrs) (void)hipFree(p);
 }
 
@@ -204,9 +223,12 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
     c.M = s->M;
     c.blocks_copy = s->blocks_copy;
     c.pivot_fail = s->flags;
+    c.piv = s->piv;
     int tk = tbegin(s, HFR_T_CONDENSE, st);
     HIP_TRY(launch_condense(m->ops, c, st));
     tend(s, tk, st);
+    HIP_TRY(launch_rhs64(m->P, m->Nim, s->M, s->opts.precision, s->piv, s->h,
+                         s->yr, s->zz, st));
     if (m->Ntf == 0) return FR_OK;
     AssembleLaunch a{};
     a.nblocks = s->nblocks;
@@ -221,6 +243,8 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
     a.L64 = s->L64;
     a.L32 = s->L32;
     a.t = s->t;
+    a.g = s->g;
+    a.z = s->zz;
     tk = tbegin(s, HFR_T_ASSEMBLE, st);
     HIP_TRY(launch_assemble(a, st));
     tend(s, tk, st);
@@ -229,6 +253,38 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
                                       s->L64 ? nullptr : s->L32,
                                       s->opts.precond, s->Dinv, s->flags + 1,
                                       st));
+    HIP_TRY(launch_precondition_matrix(s->nblocks, s->bs, s->col, s->L64,
+                                       s->L64 ? nullptr : s->L32,
+                                       s->opts.precond, s->Dinv, s->Lt64,
+                                       s->Lt32, st));
+    tend(s, tk, st);
+    return FR_OK;
+}
+
+// lagged Jacobian: re-condense the right-hand side with the stored factors
+fr_status recondense_rhs_internal(hfr_solver_s* s, hipStream_t st) {
+    fr_mesh_s* m = s->mesh;
+    if (m->Nim == 0) return FR_OK;
+    int tk = tbegin(s, HFR_T_CONDENSE, st);
+    HIP_TRY(launch_rhs64(m->P, m->Nim, s->M, s->opts.precision, s->piv, s->h,
+                         s->yr, s->zz, st));
+    tend(s, tk, st);
+    if (m->Ntf == 0) return FR_OK;
+    AssembleLaunch a{};
+    a.nblocks = 0;            // t only
+    a.blk_contrib = s->contrib;
+    a.ntf = m->Ntf;
+    a.tside = s->tside;
+    a.M = s->M;
+    a.precision = s->opts.precision;
+    a.P = m->P;
+    a.n = s->n;
+    a.m = s->m;
+    a.t = s->t;
+    a.g = s->g;
+    a.z = s->zz;
+    tk = tbegin(s, HFR_T_ASSEMBLE, st);
+    HIP_TRY(launch_assemble(a, st));
     tend(s, tk, st);
     return FR_OK;
 }
@@ -247,114 +303,74 @@ fr_status host_dots(hfr_solver_s* s, int k, const double* V, size_t ldv,
     return FR_OK;
 }
 
+GmresArgs gmres_args(hfr_solver_s* s) {
+    fr_mesh_s* m = s->mesh;
+    GmresArgs a{};
+    a.ntf = m->Ntf;
+    a.bs = s->bs;
+    a.fpb = s->fpb;
+    a.nblk = s->gblk;
+    a.restart = s->restart;
+    a.pc = s->opts.precond;
+    a.rtol = s->opts.gmres_rtol;
+    a.ldv = size_t(s->N);
+    a.rowptr = s->rowptr;
+    a.col = s->col;
+    a.L64 = s->L64;
+    a.L32 = s->L64 ? nullptr : s->L32;
+    a.Lt64 = s->Lt64;
+    a.Lt32 = s->Lt64 ? nullptr : s->Lt32;
+    a.Dinv = s->Dinv;
+    a.t = s->t;
+    a.V = s->V;
+    a.part = s->part;
+    a.part2 = s->part2;
+    a.counters = s->counters;
+    a.gs = s->gs;
+    return a;
+}
+
+// Restarted GMRES: one host synchronisation per restart cycle (to read the
+// convergence flag); the Arnoldi steps run without host round trips.
 fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
                 hipStream_t st) {
-    fr_mesh_s* m = s->mesh;
     const int N = s->N;
-    const int R = s->restart;
-    const size_t ldv = size_t(N);
-    const int pc = s->opts.precond;
-    const int maxit = std::max(1, s->opts.gmres_max_iters);
     hfr_solve_stats loc{};
-    HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * N, st));
+    HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * std::max(N, 1), st));
     if (N == 0) {
         if (stats) *stats = loc;
         return FR_OK;
     }
-    double hv[2 * 65 + 2];
-    // r = t
-    HIP_TRY(hipMemcpyAsync(s->r, s->t, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-    fr_status e = host_dots(s, 1, s->r, ldv, s->r, s->dots, hv, st);
-    if (e) return e;
-    const double bnorm = std::sqrt(hv[0]);
-    double beta = bnorm;
-    if (!(bnorm == bnorm) || std::isinf(bnorm))
-        return fail(FR_E_NONFINITE, "non-finite trace right-hand side");
-    if (bnorm == 0.0) {
-        if (stats) *stats = loc;
-        return FR_OK;
-    }
-    const double target = s->opts.gmres_rtol * bnorm;
-    std::vector<double> H(size_t(R + 1) * R), cs(R), sn(R), gv(R + 1), y(R);
-    int total = 0;
-    bool conv = false;
-    while (total < maxit) {
-        HIP_TRY(launch_scale(N, s->V, s->r, 1.0 / beta, st));
-        std::fill(gv.begin(), gv.end(), 0.0);
-        gv[0] = beta;
-        int jl = -1;
-        for (int j = 0; j < R && total < maxit; ++j) {
-            double* vj = s->V + size_t(j) * ldv;
-            double* w = s->V + size_t(j + 1) * ldv;
-            HIP_TRY(launch_precond(m->Ntf, s->bs, pc, s->Dinv, vj, s->z, st));
-            int tk = tbegin(s, HFR_T_SPMV, st);
-            HIP_TRY(launch_spmv(m->Ntf, s->bs, s->rowptr, s->col, s->L64,
-                                s->L64 ? nullptr : s->L32, s->z, w, 1.0,
-                                nullptr, st));
-            tend(s, tk, st);
-            // classical Gram-Schmidt, twice
-            double* d1 = s->dots;
-            double* d2 = s->dots + 65;
-            double* dn = s->dots + 130;
-            HIP_TRY(launch_multidot(N, j + 1, s->V, ldv, w, s->scratch, s->nblk_dot, d1, st));
-            HIP_TRY(launch_multi_axpy(N, j + 1, s->V, ldv, d1, w, -1.0, st));
-            HIP_TRY(launch_multidot(N, j + 1, s->V, ldv, w, s->scratch, s->nblk_dot, d2, st));
-            HIP_TRY(launch_multi_axpy(N, j + 1, s->V, ldv, d2, w, -1.0, st));
-            HIP_TRY(launch_multidot(N, 1, w, ldv, w, s->scratch, s->nblk_dot, dn, st));
-            HIP_TRY(hipMemcpyAsync(hv, s->dots, sizeof(double) * 131,
-                                   hipMemcpyDeviceToHost, st));
-            e = sync_check(st);
-            if (e) return e;
-            const double hn = std::sqrt(hv[130]);
-            double* hc = &H[size_t(j) * (R + 1)];
-            for (int i = 0; i <= j; ++i) hc[i] = hv[i] + hv[65 + i];
-            hc[j + 1] = hn;
-            if (!(hn == hn)) return fail(FR_E_NONFINITE, "non-finite Krylov vector");
-            if (hn > 0.0) HIP_TRY(launch_scale(N, w, w, 1.0 / hn, st));
-            for (int i = 0; i < j; ++i) {
-                const double a = cs[i] * hc[i] + sn[i] * hc[i + 1];
-                hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
-                hc[i] = a;
-            }
-            const double den = std::hypot(hc[j], hc[j + 1]);
-            cs[j] = den > 0 ? hc[j] / den : 1.0;
-            sn[j] = den > 0 ? hc[j + 1] / den : 0.0;
-            hc[j] = den;
-            hc[j + 1] = 0.0;
-            gv[j + 1] = -sn[j] * gv[j];
-            gv[j] = cs[j] * gv[j];
-            ++total;
-            jl = j;
-            if (std::fabs(gv[j + 1]) <= target || hn == 0.0) break;
-        }
-        // y = H^-1 g (upper triangular), x += M^-1 (V y)
-        for (int i = jl; i >= 0; --i) {
-            double acc = gv[i];
-            for (int k = i + 1; k <= jl; ++k) acc -= H[size_t(k) * (R + 1) + i] * y[k];
-            y[i] = acc / H[size_t(i) * (R + 1) + i];
-        }
-        HIP_TRY(hipMemcpyAsync(s->coef, y.data(), sizeof(double) * (jl + 1),
-                               hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemsetAsync(s->r, 0, sizeof(double) * N, st));
-        HIP_TRY(launch_multi_axpy(N, jl + 1, s->V, ldv, s->coef, s->r, 1.0, st));
-        HIP_TRY(launch_precond(m->Ntf, s->bs, pc, s->Dinv, s->r, s->z, st));
-        HIP_TRY(launch_axpy(N, 1.0, s->z, x, st));
-        // true residual in FP64: r = t - L x
-        HIP_TRY(launch_spmv(m->Ntf, s->bs, s->rowptr, s->col, s->L64,
-                            s->L64 ? nullptr : s->L32, x, s->r, -1.0, s->t, st));
-        e = host_dots(s, 1, s->r, ldv, s->r, s->dots, hv, st);
+    const GmresArgs a = gmres_args(s);
+    const int R = s->restart;
+    const int maxit = std::max(1, s->opts.gmres_max_iters);
+    double* W0 = s->W;
+    double* W1 = s->W + N;
+    struct {
+        int done, converged, jlast, iters, cycles, pad;
+        double inv_norm, beta, bnorm, target;
+    } hs{};
+    HIP_TRY(launch_gmres_restart(a, x, W0, 1, st));
+    int launched = 0;
+    for (;;) {
+        HIP_TRY(hipMemcpyAsync(&hs, s->gs, sizeof(hs), hipMemcpyDeviceToHost, st));
+        fr_status e = sync_check(st);
         if (e) return e;
-        beta = std::sqrt(hv[0]);
-        loc.restarts++;
-        if (beta <= target) {
-            conv = true;
-            break;
-        }
+        if (!(hs.beta == hs.beta) || std::isinf(hs.beta))
+            return fail(FR_E_NONFINITE, "non-finite trace residual");
+        if (hs.converged || launched >= maxit) break;
+        const int steps = std::min(R, maxit - launched);
+        for (int j = 0; j < steps; ++j)
+            HIP_TRY(launch_arnoldi(a, j, j % 2 ? W1 : W0, j % 2 ? W0 : W1, st));
+        launched += steps;
+        HIP_TRY(launch_gmres_update(a, x, st));
+        HIP_TRY(launch_gmres_restart(a, x, W0, 0, st));
     }
-    loc.iterations = total;
-    loc.rel_residual = beta / bnorm;
+    loc.iterations = hs.iters;
+    loc.restarts = hs.cycles;
+    loc.rel_residual = hs.bnorm > 0 ? hs.beta / hs.bnorm : 0.0;
     if (stats) *stats = loc;
-    if (!conv) return fail(FR_E_NOT_CONVERGED, "GMRES iteration cap reached");
+    if (!hs.converged) return fail(FR_E_NOT_CONVERGED, "GMRES iteration cap reached");
     return FR_OK;
 }
 
@@ -385,6 +401,9 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         if ((e = absmax_host(s, nu, s->h, &hmax, st))) return e;
         if ((e = absmax_host(s, 4 * m->Ntp, s->g, &gmax, st))) return e;
         const double res = std::max(hmax, gmax);
+        if (s->verbose)
+            fprintf(stderr, "[hfr] newton it %d |h| %.3e |g| %.3e tol %.3e\n", it,
+                    hmax, gmax, tol);
         loc.residual = res;
         loc.newton_iters = it;
         if (!(hmax == hmax) || !(gmax == gmax) || std::isinf(res)) {
@@ -396,20 +415,32 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
             if (stats) *stats = loc;
             return fail(FR_E_NOT_CONVERGED, "Newton did not converge");
         }
-        if ((e = condense_internal(s, u, uhat, aii_dt, st))) return e;
+        const int lag = s->opts.jacobian_lag;
+        const bool relin = lag <= 0 || !s->have_factors ||
+                           (it == 0 && (s->stage_calls % lag) == 0);
+        if (relin) {
+            if ((e = condense_internal(s, u, uhat, aii_dt, st))) return e;
+            s->have_factors = true;
+        } else {
+            if ((e = recondense_rhs_internal(s, st))) return e;
+        }
         hfr_solve_stats ks{};
         int tk = tbegin(s, HFR_T_TRACE_SOLVE, st);
         e = gmres(s, s->duhat, &ks, st);
         tend(s, tk, st);
+        if (s->verbose)
+            fprintf(stderr, "[hfr]   gmres its %d restarts %d relres %.3e status %d\n",
+                    ks.iterations, ks.restarts, ks.rel_residual, int(e));
         loc.gmres_iters += ks.iterations;
         if (e && e != FR_E_NOT_CONVERGED) return e;
         tk = tbegin(s, HFR_T_RECOVER, st);
-        HIP_TRY(launch_recover(m->P, m->Nim, s->M, s->opts.precision,
+        HIP_TRY(launch_recover(m->P, m->Nim, s->M, s->opts.precision, s->yr,
                                m->d_trace_map, s->duhat, s->du, st));
         HIP_TRY(launch_newton_update(m->Np, m->Nim, m->Ne, m->d_imp, s->du, u,
                                      4 * m->Ntp, s->duhat, uhat, st));
         tend(s, tk, st);
     }
+    s->stage_calls++;
     int fl[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(fl, s->flags, sizeof(fl), hipMemcpyDeviceToHost, st));
     if ((e = sync_check(st))) return e;
@@ -433,9 +464,10 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
         return fail(FR_E_INVALID, "unknown precision");
     if (o->precond < HFR_PC_FP64 || o->precond > HFR_PC_BF16)
         return fail(FR_E_INVALID, "unknown preconditioner storage");
-    if (o->gmres_restart < 1 || o->gmres_restart > 64)
+    if (o->gmres_restart < 1 || o->gmres_restart > kGmresMaxK - 1)
         return fail(FR_E_INVALID, "gmres_restart must be in 1..64");
-    if (o->newton_max_iters < 0 || !(o->newton_tol > 0.0) || !(o->gmres_rtol > 0.0))
+    if (o->newton_max_iters < 0 || !(o->newton_tol > 0.0) || !(o->gmres_rtol > 0.0) ||
+        o->jacobian_lag < 0)
         return fail(FR_E_INVALID, "bad tolerance or iteration cap");
     auto s = new hfr_solver_s();
     s->mesh = mesh;
@@ -506,6 +538,16 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
         (e = dalloc(&s->diag_blk, diag.size(), tot)) ||
         (o->precision == HFR_PREC_FP64 && (e = dalloc(&s->L64, size_t(s->nblocks) * bb, tot))) ||
         (o->precision == HFR_PREC_FP32 && (e = dalloc(&s->L32, size_t(s->nblocks) * bb, tot))) ||
+        (o->precision == HFR_PREC_FP64 && (e = dalloc(&s->Lt64, size_t(s->nblocks) * bb, tot))) ||
+        (o->precision == HFR_PREC_FP32 && (e = dalloc(&s->Lt32, size_t(s->nblocks) * bb, tot))) ||
+        (e = dalloc(&s->W, 2 * size_t(std::max(1, s->N)), tot)) ||
+        (e = dalloc(reinterpret_cast<char**>(&s->gs), sizeof(GmresState), tot)) ||
+        (e = dalloc(&s->part, size_t(std::max(1, (m->Ntf + 256 / s->bs - 1) / (256 / s->bs))) * kGmresMaxK, tot)) ||
+        (e = dalloc(&s->part2, size_t(std::max(1, (m->Ntf + 256 / s->bs - 1) / (256 / s->bs))) * 2, tot)) ||
+        (e = dalloc(&s->counters, 4, tot)) ||
+        (e = dalloc(&s->piv, nimp * size_t(s->n), tot)) ||
+        (e = dalloc(&s->yr, nimp * size_t(s->n), tot)) ||
+        (e = dalloc(&s->zz, nimp * size_t(s->m), tot)) ||
         (e = dalloc(&s->t, size_t(s->N), tot)) ||
         (e = dalloc(reinterpret_cast<char**>(&s->Dinv),
                     size_t(m->Ntf) * bb * (o->precond == HFR_PC_FP64 ? 8 : o->precond == HFR_PC_FP32 ? 4 : 2),
@@ -524,6 +566,9 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
     }
     s->M = Mraw;
     s->nblk_dot = multidot_blocks(std::max(1, s->N));
+    s->verbose = std::getenv("HFR_VERBOSE") != nullptr;
+    s->fpb = 256 / s->bs;
+    s->gblk = std::max(1, (m->Ntf + s->fpb - 1) / s->fpb);
     auto up = [&](int* d, const std::vector<int>& h) {
         return h.empty() ? hipSuccess
                          : hipMemcpy(d, h.data(), 4 * h.size(), hipMemcpyHostToDevice);
@@ -531,7 +576,9 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
     if (up(s->rowptr, rowptr) != hipSuccess || up(s->col, col) != hipSuccess ||
         up(s->contrib, contrib) != hipSuccess || up(s->tside, tside) != hipSuccess ||
         up(s->diag_blk, diag) != hipSuccess ||
-        hipMemset(s->flags, 0, 8) != hipSuccess) {
+        hipMemset(s->flags, 0, 8) != hipSuccess ||
+        hipMemset(s->counters, 0, 16) != hipSuccess ||
+        hipMemset(s->gs, 0, sizeof(GmresState)) != hipSuccess) {
         free_solver(s);
         delete s;
         return fail(FR_E_DEVICE, "upload of solver tables failed");
@@ -575,7 +622,9 @@ extern "C" fr_status hfr_assemble_condense(hfr_solver_t s, const double* u,
     hipStream_t st = hipStream_t(stream);
     fr_status e = residual_internal(s, u, uhat, ustar, aii_dt, nullptr, st);
     if (e) return e;
-    return condense_internal(s, u, uhat, aii_dt, st);
+    e = condense_internal(s, u, uhat, aii_dt, st);
+    if (!e) s->have_factors = true;
+    return e;
 }
 
 extern "C" fr_status hfr_trace_solve(hfr_solver_t s, double* duhat,
@@ -589,7 +638,7 @@ extern "C" fr_status hfr_recover(hfr_solver_t s, const double* duhat,
     if (!s || (!duhat && s->N) || (!du && s->mesh->Nim))
         return fail(FR_E_INVALID, "null argument");
     fr_mesh_s* m = s->mesh;
-    HIP_TRY(launch_recover(m->P, m->Nim, s->M, s->opts.precision,
+    HIP_TRY(launch_recover(m->P, m->Nim, s->M, s->opts.precision, s->yr,
                            m->d_trace_map, duhat, du, hipStream_t(stream)));
     return FR_OK;
 }
@@ -625,6 +674,22 @@ extern "C" fr_status hfr_get_blocks(hfr_solver_t s, double* blocks,
     const size_t nb = size_t(m->Nim) * (s->n + s->m) * (s->n + s->m) * 8;
     HIP_TRY(hipMemcpyAsync(blocks, s->blocks_copy, nb, hipMemcpyDeviceToDevice,
                            hipStream_t(stream)));
+    return FR_OK;
+}
+
+extern "C" fr_status hfr_get_factors(hfr_solver_t s, void* factors,
+                                     int32_t* piv, void* stream) {
+    if (!s || !factors) return fail(FR_E_INVALID, "null argument");
+    fr_mesh_s* m = s->mesh;
+    const size_t scal = s->opts.precision == HFR_PREC_FP64 ? 8 : 4;
+    hipStream_t st = hipStream_t(stream);
+    if (m->Nim) {
+        HIP_TRY(hipMemcpyAsync(factors, s->M, size_t(m->Nim) * s->elem_M * scal,
+                               hipMemcpyDeviceToDevice, st));
+        if (piv)
+            HIP_TRY(hipMemcpyAsync(piv, s->piv, size_t(m->Nim) * s->n * 4,
+                                   hipMemcpyDeviceToDevice, st));
+    }
     return FR_OK;
 }
 

@@ -1,0 +1,113 @@
+"""Parity at the benchmark's full sizes, in the launch configuration the
+benchmark times: the 128x64 p=3 cylinder (oracle comparison of whole
+residuals and of one full implicit stage) and the 256x128 p=4 cylinder
+(explicit residual against the oracle, then properties that hold at any
+size: the converged inviscid trace is the average of the two sides, and the
+FP32-condensation stage agrees with the FP64 one)."""
+import numpy as np
+import pytest
+import torch
+
+import fr_inputs as fi
+import oracle
+from oracle import residual as ores, newton as onw, imex as oimex
+import paper_2401_16632_amd as hp
+from tests.gpu_util import dev, host, soa, unsoa, rel_err
+
+pytestmark = pytest.mark.gpu
+
+import bench  # the benchmark's own workload builder
+
+
+def _pair(name):
+    mesh, u0, dt, xy = bench.build_case(hp, name)
+    d, p, nt, nr, first, ratio = bench.cylinder_workload(name)
+    mp = mesh.maps()
+    mask = np.zeros(mesh.Ne, bool)
+    mask[mp["implicit_elems"]] = True
+    om = oracle.QuadMesh(d, p, implicit_mask=mask, uinf=fi.freestream_state(bench.MACH))
+    u = unsoa(u0, mesh.Ne, p + 1)
+    return mesh, om, u, dt
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return _pair("c2")
+
+
+def test_c2_explicit_and_implicit_residuals(c2):
+    mesh, om, u, dt = c2
+    ph = oracle.Euler()
+    R_o = ores.fr_residual(om, ph, u)
+    R = torch.zeros(4 * mesh.Nex * mesh.Np, dtype=torch.float64, device="cuda")
+    mesh.explicit_rhs(dev(soa(u)), R)
+    torch.cuda.synchronize()
+    R_ex = R_o[om.exp_elems]
+    assert np.abs(unsoa(host(R), mesh.Nex, om.P) - R_ex).max() <= 1e-12 * np.abs(R_ex).max()
+    uhat = ores.trace_average(om, u)
+    R_im, g_o = ores.hfr_residual(om, ph, u, uhat)
+    s = hp.Solver(mesh)
+    g = torch.zeros(4 * mesh.Ntp, dtype=torch.float64, device="cuda")
+    Rg = torch.zeros(4 * mesh.Nim * mesh.Np, dtype=torch.float64, device="cuda")
+    s.residual(dev(soa(u)), dev(uhat), dev(soa(u[om.imp_elems])), 0.0, g=g, R_im=Rg)
+    torch.cuda.synchronize()
+    assert np.abs(unsoa(host(Rg), mesh.Nim, om.P) - R_im).max() <= 1e-12 * np.abs(R_im).max()
+    assert np.abs(host(g).reshape(-1, 4) - g_o).max() <= 1e-12 * max(1, np.abs(g_o).max())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c2_first_implicit_stage_vs_oracle(c2, precision):
+    """One full implicit stage (Newton to 1e-12) on the 128x64 p=3 mesh."""
+    mesh, om, u, dt = c2
+    ph = oracle.Euler()
+    tab = oimex.himex2c()
+    a = dt * tab.A[0, 0]
+    # explicit stage value first (eq:explicitimex), then the implicit stage
+    u1 = u.copy()
+    u1[om.exp_elems] += dt * tab.Abar[1, 0] * ores.fr_residual(om, ph, u)[om.exp_elems]
+    u_im_o, uhat_o, its = onw.solve_stage(om, ph, u1, u[om.imp_elems], a, tol=1e-12)
+    s = hp.Solver(mesh, precision=precision, precond=precision, rtol=1e-10,
+                  newton_tol=1e-12, max_iters=3000)
+    stp = hp.ImexStepper(mesh, s, "HIMEX2C")
+    ud = dev(soa(u))
+    lib = hp.load_library()
+    import ctypes
+    from paper_2401_16632_amd import _abi
+    st = _abi.ImexState(ud.data_ptr(), stp.u.data_ptr(), stp.uhat.data_ptr(),
+                        stp.R_im.data_ptr(), stp.R_ex.data_ptr())
+    ns = _abi.HfrNewtonStats()
+    for stage in (0, 1):
+        rc = lib.imex_stage(mesh.handle, s.handle, ctypes.byref(stp.tab), stage,
+                            float(dt), ctypes.byref(st), ctypes.byref(ns), None)
+        assert rc == 0, lib.fr_last_error()
+    torch.cuda.synchronize()
+    ug = unsoa(host(stp.u), mesh.Ne, om.P)
+    assert rel_err(ug[om.imp_elems], u_im_o) <= 1e-11
+    assert rel_err(host(stp.uhat), uhat_o) <= 1e-11
+
+
+def test_c3_explicit_residual_and_stage_properties():
+    mesh, om, u, dt = _pair("c3")
+    ph = oracle.Euler()
+    R = torch.zeros(4 * mesh.Nex * mesh.Np, dtype=torch.float64, device="cuda")
+    mesh.explicit_rhs(dev(soa(u)), R)
+    torch.cuda.synchronize()
+    R_o = ores.fr_residual(om, ph, u)[om.exp_elems]
+    assert np.abs(unsoa(host(R), mesh.Nex, om.P) - R_o).max() <= 1e-12 * np.abs(R_o).max()
+    states = {}
+    for prec in ("fp64", "fp32"):  # noqa: B007
+        s = hp.Solver(mesh, precision=prec, precond=prec, rtol=1e-8,
+                      newton_tol=1e-12, max_iters=3000)
+        stp = hp.ImexStepper(mesh, s, "HIMEX2C")
+        un, stats = stp.step(dev(soa(u)), dt)
+        torch.cuda.synchronize()
+        assert all(st["residual"] <= 1e-12 * 100 for st in stats), stats
+        states[prec] = (host(un).copy(), host(stp.uhat).copy())
+        s.close()
+    a64, h64 = states["fp64"]
+    a32, h32 = states["fp32"]
+    # matched error: the FP32-condensation step equals the FP64 one to the
+    # Newton tolerance (both test FP64 residuals)
+    assert rel_err(a32, a64) <= 1e-9
+    assert rel_err(h32, h64) <= 1e-9
+    assert np.all(np.isfinite(a64))

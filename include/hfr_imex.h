@@ -269,7 +269,8 @@ enum { HFR_T_RESIDUAL = 0,   /* hybridized residual kernel                 */
        HFR_T_CONDENSE = 1,   /* element blocks + LU/Schur kernel           */
        HFR_T_ASSEMBLE = 2,   /* block-sparse assembly kernel               */
        HFR_T_PCSETUP = 3,    /* block-Jacobi inversion kernel              */
-       HFR_T_SPMV = 4,       /* block-sparse product kernel                */
+       HFR_T_SPMV = 4,       /* Arnoldi product kernel (block-sparse
+                                product + first projection)               */
        HFR_T_TRACE_SOLVE = 5,/* whole trace solve (all Krylov kernels)     */
        HFR_T_RECOVER = 6,    /* local recovery kernel                      */
        HFR_T_EXPLICIT = 7,   /* explicit residual kernel (via imex_stage)  */

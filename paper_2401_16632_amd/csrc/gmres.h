@@ -17,6 +17,7 @@ struct GmresState {
 
 struct GmresArgs {
     int ntf, bs, fpb, nblk, restart, pc;
+    int fpbA, nblkA;         // decomposition of the product kernel
     double rtol;
     size_t ldv;
     const int* rowptr;
@@ -29,7 +30,8 @@ struct GmresArgs {
     const double* t;
     double* V;               // restart x ldv
     double* part;            // nblk x kGmresMaxK
-    double* part2;           // nblk x 2
+    double* part2;           // nblk x kGmresMaxK
+    double* part3;           // nblkA x kGmresMaxK (product kernel)
     unsigned* counters;      // 4
     GmresState* gs;
 };
@@ -40,8 +42,10 @@ hipError_t launch_precondition_matrix(int nblocks, int bs, const int* col,
                                       float* Lt32, hipStream_t st);
 hipError_t launch_gmres_restart(const GmresArgs& a, const double* x,
                                 double* w, int first, hipStream_t st);
-hipError_t launch_arnoldi(const GmresArgs& a, int j, const double* wcur,
-                          double* wnxt, hipStream_t st);
+hipError_t launch_arnoldi_product(const GmresArgs& a, int j, const double* wcur,
+                                  double* wnxt, hipStream_t st);
+hipError_t launch_arnoldi_orth(const GmresArgs& a, int j, double* wnxt,
+                               hipStream_t st);
 hipError_t launch_gmres_update(const GmresArgs& a, double* x, hipStream_t st);
 
 }  // namespace hfr

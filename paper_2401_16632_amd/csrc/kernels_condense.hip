@@ -383,54 +383,98 @@ static hipError_t launch_lu(const RefOps& o, const CondenseLaunch& a,
 // element shares of g are large and cancel between the two sides of a
 // trace face, so they never pass through the factor precision; only
 // C A^-1 r does, which is proportional to the (small) residual h.
-template <typename T>
-__global__ void k_rhs64(int P, int nimp, const T* M, const int* piv,
-                        const double* h, double* yr, double* z) {
-    extern __shared__ double y[];
-    const int NP = P * P, n = 4 * NP, m = 16 * P, ld = n + m + 1;
-    const int k = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
+// one wave per element; row i of the element lives in lane i % 64, slot
+// i / 64 (NS slots); cross-lane values move by readlane-style shuffles
+template <int NS>
+__device__ __forceinline__ double slot_get(const double (&y)[NS], int s) {
+    double r = y[0];
+#pragma unroll
+    for (int i = 1; i < NS; ++i) r = (s == i) ? y[i] : r;
+    return r;
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_rhs64(int nimp, const T* M,
+                                               const int* piv, const double* h,
+                                               double* yr, double* z) {
+    constexpr int NP = P * P, n = 4 * NP, m = 16 * P, ld = n + m + 1;
+    constexpr int NS = (n + 63) / 64;
+    __shared__ double sy[4][n];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int k = blockIdx.x * 4 + wv;
+    if (k >= nimp) return;
     const T* Mk = M + size_t(k) * (n + m) * ld;
-    for (int row = t; row < n; row += nt) {
-        const int pt = row >> 2, v = row & 3;
-        y[row] = -h[size_t(v) * nimp * NP + size_t(k) * NP + pt];
+    double y[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int row = lane + 64 * s;
+        y[s] = row < n ? -h[size_t(row & 3) * nimp * NP + size_t(k) * NP + (row >> 2)] : 0.0;
     }
-    __syncthreads();
-    if (t == 0) {
-        const int* pk = piv + size_t(k) * n;
-        for (int kk = 0; kk < n; ++kk) {
-            const int p = pk[kk];
-            const double x = y[kk];
-            y[kk] = y[p];
-            y[p] = x;
+    // row interchanges of the factorisation, in order
+    const int* pk = piv + size_t(k) * n;
+    for (int kk = 0; kk < n; ++kk) {
+        const int p = pk[kk];
+        if (p == kk) continue;
+        const double a = __shfl(slot_get<NS>(y, kk >> 6), kk & 63, 64);
+        const double b = __shfl(slot_get<NS>(y, p >> 6), p & 63, 64);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int row = lane + 64 * s;
+            if (row == kk) y[s] = b;
+            if (row == p) y[s] = a;
         }
     }
-    __syncthreads();
-    for (int j = 0; j < n; ++j) {
-        const double yj = y[j];
-        for (int i = j + 1 + t; i < n; i += nt) y[i] -= double(Mk[size_t(i) * ld + j]) * yj;
-        __syncthreads();
+    // forward substitution with the unit lower factor
+    for (int j = 0; j < n - 1; ++j) {
+        const double yj = __shfl(slot_get<NS>(y, j >> 6), j & 63, 64);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int row = lane + 64 * s;
+            if (row > j && row < n) y[s] -= double(Mk[size_t(row) * ld + j]) * yj;
+        }
     }
-    for (int row = t; row < n; row += nt) yr[size_t(k) * n + row] = y[row];
-    for (int b = t; b < m; b += nt) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int row = lane + 64 * s;
+        if (row < n) {
+            yr[size_t(k) * n + row] = y[s];
+            sy[wv][row] = y[s];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int b = lane; b < m; b += 64) {
         const T* cr = Mk + size_t(n + b) * ld;
         double acc = 0.0;
-        for (int j = 0; j < n; ++j) acc += double(cr[j]) * y[j];
+        for (int j = 0; j < n; ++j) acc += double(cr[j]) * sy[wv][j];
         z[size_t(k) * m + b] = acc;
     }
+}
+
+template <typename T>
+static hipError_t launch_rhs64_t(int P, int nimp, const T* M, const int* piv,
+                                 const double* h, double* yr, double* z,
+                                 hipStream_t st) {
+    const dim3 grid((nimp + 3) / 4), blk(256);
+    switch (P) {
+        case 2: hipLaunchKernelGGL((k_rhs64<T, 2>), grid, blk, 0, st, nimp, M, piv, h, yr, z); break;
+        case 3: hipLaunchKernelGGL((k_rhs64<T, 3>), grid, blk, 0, st, nimp, M, piv, h, yr, z); break;
+        case 4: hipLaunchKernelGGL((k_rhs64<T, 4>), grid, blk, 0, st, nimp, M, piv, h, yr, z); break;
+        case 5: hipLaunchKernelGGL((k_rhs64<T, 5>), grid, blk, 0, st, nimp, M, piv, h, yr, z); break;
+        case 6: hipLaunchKernelGGL((k_rhs64<T, 6>), grid, blk, 0, st, nimp, M, piv, h, yr, z); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_rhs64(int P, int nimp, const void* M, int precision,
                         const int* piv, const double* h, double* yr,
                         double* z, hipStream_t st) {
     if (nimp == 0) return hipSuccess;
-    const size_t shm = 4 * P * P * sizeof(double);
     if (precision == HFR_PREC_FP64)
-        hipLaunchKernelGGL(k_rhs64<double>, dim3(nimp), dim3(128), shm, st, P,
-                           nimp, reinterpret_cast<const double*>(M), piv, h, yr, z);
-    else
-        hipLaunchKernelGGL(k_rhs64<float>, dim3(nimp), dim3(128), shm, st, P,
-                           nimp, reinterpret_cast<const float*>(M), piv, h, yr, z);
-    return hipGetLastError();
+        return launch_rhs64_t(P, nimp, reinterpret_cast<const double*>(M), piv, h, yr, z, st);
+    return launch_rhs64_t(P, nimp, reinterpret_cast<const float*>(M), piv, h, yr, z, st);
 }
 
 template <int P>

@@ -39,10 +39,13 @@ __device__ __forceinline__ void face_interp_global(const double* __restrict__ u,
 }
 
 template <int P>
-__global__ __launch_bounds__(256) void k_residual(ResidualLaunch a, RefOps o) {
+__global__ __launch_bounds__(256) void k_residual(ResidualLaunch a, RefOps og) {
     constexpr int NP = P * P;
     constexpr int EPB = 256 / NP;
     constexpr int NFP = 4 * P;
+    __shared__ RefOps o;
+    if (threadIdx.x == 0) o = og;
+    __syncthreads();
     __shared__ double s_u[EPB][NP][4];
     __shared__ double s_f[EPB][NP][4];
     __shared__ double s_g[EPB][NP][4];

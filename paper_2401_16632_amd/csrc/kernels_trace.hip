@@ -51,12 +51,13 @@ __global__ void k_assemble(AssembleLaunch a) {
     const int bs = 4 * a.P;
     const int ld = a.n + a.m + 1;
     const size_t rows = size_t(a.n + a.m);
-    const long total = long(a.nblocks) * bs * bs;
+    const int bb = bs * bs;
+    const long total = long(a.nblocks) * bb;
     const T* M = reinterpret_cast<const T*>(a.M);
     for (long idx = blockIdx.x * long(blockDim.x) + threadIdx.x; idx < total;
          idx += long(gridDim.x) * blockDim.x) {
-        const int blk = int(idx / (bs * bs));
-        const int rem = int(idx % (bs * bs));
+        const int blk = int(idx) / bb;          // total < 2^31
+        const int rem = int(idx) - blk * bb;
         const int b = rem / bs, aa = rem % bs;
         const int qa = aa >> 2, va = aa & 3, qb = b >> 2, wb = b & 3;
         double val = 0.0;
@@ -77,7 +78,7 @@ __global__ void k_assemble(AssembleLaunch a) {
     const long tt = long(a.ntf) * bs;
     for (long idx = blockIdx.x * long(blockDim.x) + threadIdx.x; idx < tt;
          idx += long(gridDim.x) * blockDim.x) {
-        const int F = int(idx / bs), aa = int(idx % bs);
+        const int F = int(idx) / bs, aa = int(idx) - F * bs;
         const int q = aa >> 2, v = aa & 3;
         double zs = 0.0;
         for (int s = 0; s < 2; ++s) {
@@ -122,12 +123,15 @@ __global__ void k_block_inverse(int ntf, int bs, const int* diag_blk,
     }
     __syncthreads();
     for (int k = 0; k < bs; ++k) {
-        if (t == 0) {
-            int p = k;
-            double best = fabs(W[k][k]);
-            for (int r = k + 1; r < bs; ++r)
-                if (fabs(W[r][k]) > best) { best = fabs(W[r][k]); p = r; }
-            piv_s = (best == 0.0) ? -1 : p;
+        {
+            double best = (t >= k && t < bs) ? fabs(W[t][k]) : -1.0;
+            int p = (t >= k && t < bs) ? t : 0x7fffffff;
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ob = __shfl_xor(best, off, 64);
+                const int oi = __shfl_xor(p, off, 64);
+                if (ob > best || (ob == best && oi < p)) { best = ob; p = oi; }
+            }
+            if (t == 0) piv_s = (best > 0.0) ? p : -1;
         }
         __syncthreads();
         const int p = piv_s;
@@ -181,9 +185,9 @@ hipError_t launch_block_inverse_impl(int ntf, int bs, const int* diag_blk,
 __global__ void k_spmv(int nrows, int bs, const int* rowptr, const int* col,
                        const double* L64, const float* L32, const double* x,
                        double* y, double alpha, const double* yin) {
-    const long r = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrows) return;
-    const int F = int(r / bs), aa = int(r % bs);
+    const int F = r / bs, aa = r - F * bs;
     double acc = 0.0;
     for (int p = rowptr[F]; p < rowptr[F + 1]; ++p) {
         const size_t base = size_t(p) * bs * bs + aa;
@@ -210,9 +214,9 @@ hipError_t launch_spmv(int ntf, int bs, const int* rowptr, const int* col,
 
 __global__ void k_precond(int nrows, int bs, int pc, const void* inv,
                           const double* x, double* y) {
-    const long r = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrows) return;
-    const int F = int(r / bs), aa = int(r % bs);
+    const int F = r / bs, aa = r - F * bs;
     const size_t base = size_t(F) * bs * bs + aa;
     const double* xb = x + size_t(F) * bs;
     double acc = 0.0;
@@ -347,23 +351,32 @@ __global__ void k_absmax_partial(int N, const double* x, double* partial) {
 }
 
 __global__ void k_absmax_final(int nblk, const double* partial, double* out) {
-    if (threadIdx.x != 0) return;
+    __shared__ double red[256];
     double m = 0.0;
-    for (int i = 0; i < nblk; ++i) {
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
         const double o = partial[i];
         if (o > m || o != o) m = o;
     }
-    *out = m;
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double o = red[threadIdx.x + s];
+            if (o > red[threadIdx.x] || o != o) red[threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
 }
 
 hipError_t launch_absmax(int N, const double* x, double* partial, int nblk,
                          double* out, hipStream_t st) {
     if (N == 0) {
-        hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(64), 0, st, 0, partial, out);
+        hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(256), 0, st, 0, partial, out);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_absmax_partial, dim3(nblk), dim3(kThreads), 0, st, N, x, partial);
-    hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(64), 0, st, nblk, partial, out);
+    hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(256), 0, st, nblk, partial, out);
     return hipGetLastError();
 }
 
@@ -371,68 +384,105 @@ hipError_t launch_absmax(int N, const double* x, double* partial, int nblk,
 // rows 0..n-1 hold L\U | Y_B with Y_B = L^-1 P B, and y_r = L^-1 P r comes
 // from the FP64 right-hand-side pass, so du = U^-1 (y_r - Y_B duhat_loc)
 // by back substitution.
-template <typename T>
-__global__ void k_recover(int P, int nimp, const T* M, const double* yr,
-                          const int* trace_map, const double* duhat,
-                          double* du) {
-    extern __shared__ double sm[];
-    const int NP = P * P, n = 4 * NP, m = 16 * P, ld = n + m + 1;
-    double* loc = sm;
-    double* y = sm + m;
-    const int k = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
-    for (int b = t; b < m; b += nt) {
+template <int NS>
+__device__ __forceinline__ double rslot(const double (&y)[NS], int s) {
+    double r = y[0];
+#pragma unroll
+    for (int i = 1; i < NS; ++i) r = (s == i) ? y[i] : r;
+    return r;
+}
+
+// one wave per element, four elements per workgroup; row i in lane i % 64,
+// slot i / 64
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_recover(int nimp, const T* M,
+                                                 const double* yr,
+                                                 const int* trace_map,
+                                                 const double* duhat,
+                                                 double* du) {
+    constexpr int NP = P * P, n = 4 * NP, m = 16 * P, ld = n + m + 1;
+    constexpr int NS = (n + 63) / 64;
+    __shared__ double sloc[4][m];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int k = blockIdx.x * 4 + wv;
+    if (k >= nimp) return;
+    for (int b = lane; b < m; b += 64) {
         const int f = b / (4 * P), q = (b >> 2) % P, w = b & 3;
         const int tp = trace_map[(size_t(k) * 4 + f) * P + q];
-        loc[b] = tp >= 0 ? duhat[size_t(tp) * 4 + w] : 0.0;
+        sloc[wv][b] = tp >= 0 ? duhat[size_t(tp) * 4 + w] : 0.0;
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const T* Mk = M + size_t(k) * (n + m) * ld;
-    for (int row = t; row < n; row += nt) {
-        const T* xr = Mk + size_t(row) * ld;
-        double acc = yr[size_t(k) * n + row];
-        for (int b = 0; b < m; ++b) acc -= double(xr[n + b]) * loc[b];
-        y[row] = acc;
+    double y[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int row = lane + 64 * s;
+        double acc = 0.0;
+        if (row < n) {
+            const T* xr = Mk + size_t(row) * ld + n;
+            acc = yr[size_t(k) * n + row];
+            for (int b = 0; b < m; ++b) acc -= double(xr[b]) * sloc[wv][b];
+        }
+        y[s] = acc;
     }
-    __syncthreads();
+    // back substitution with U
     for (int j = n - 1; j >= 0; --j) {
-        const double xj = y[j] / double(Mk[size_t(j) * ld + j]);
-        __syncthreads();
-        if (t == 0) y[j] = xj;
-        for (int i = t; i < j; i += nt) y[i] -= double(Mk[size_t(i) * ld + j]) * xj;
-        __syncthreads();
+        const double xj = __shfl(rslot<NS>(y, j >> 6), j & 63, 64) /
+                          double(Mk[size_t(j) * ld + j]);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int row = lane + 64 * s;
+            if (row < j) y[s] -= double(Mk[size_t(row) * ld + j]) * xj;
+            if (row == j) y[s] = xj;
+        }
     }
-    for (int row = t; row < n; row += nt) {
-        const int pt = row >> 2, v = row & 3;
-        du[size_t(v) * nimp * NP + size_t(k) * NP + pt] = y[row];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int row = lane + 64 * s;
+        if (row < n) du[size_t(row & 3) * nimp * NP + size_t(k) * NP + (row >> 2)] = y[s];
     }
+}
+
+template <typename T>
+static hipError_t launch_recover_t(int P, int nimp, const T* M, const double* yr,
+                                   const int* trace_map, const double* duhat,
+                                   double* du, hipStream_t st) {
+    const dim3 grid((nimp + 3) / 4), blk(256);
+    switch (P) {
+        case 2: hipLaunchKernelGGL((k_recover<T, 2>), grid, blk, 0, st, nimp, M, yr, trace_map, duhat, du); break;
+        case 3: hipLaunchKernelGGL((k_recover<T, 3>), grid, blk, 0, st, nimp, M, yr, trace_map, duhat, du); break;
+        case 4: hipLaunchKernelGGL((k_recover<T, 4>), grid, blk, 0, st, nimp, M, yr, trace_map, duhat, du); break;
+        case 5: hipLaunchKernelGGL((k_recover<T, 5>), grid, blk, 0, st, nimp, M, yr, trace_map, duhat, du); break;
+        case 6: hipLaunchKernelGGL((k_recover<T, 6>), grid, blk, 0, st, nimp, M, yr, trace_map, duhat, du); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_recover(int P, int nimp, const void* M, int precision,
                           const double* yr, const int* trace_map,
                           const double* duhat, double* du, hipStream_t st) {
     if (nimp == 0) return hipSuccess;
-    const size_t shm = (16 * P + 4 * P * P) * sizeof(double);
     if (precision == HFR_PREC_FP64)
-        hipLaunchKernelGGL(k_recover<double>, dim3(nimp), dim3(128), shm, st, P,
-                           nimp, reinterpret_cast<const double*>(M), yr,
-                           trace_map, duhat, du);
-    else
-        hipLaunchKernelGGL(k_recover<float>, dim3(nimp), dim3(128), shm, st, P,
-                           nimp, reinterpret_cast<const float*>(M), yr,
-                           trace_map, duhat, du);
-    return hipGetLastError();
+        return launch_recover_t(P, nimp, reinterpret_cast<const double*>(M), yr,
+                                trace_map, duhat, du, st);
+    return launch_recover_t(P, nimp, reinterpret_cast<const float*>(M), yr,
+                            trace_map, duhat, du, st);
 }
 
 // ---- Newton update: u_im += du (scatter), uhat += duhat -----------------
 __global__ void k_newton_update(int Np, int nimp, int Ne, const int* imp_list,
                                 const double* du, double* u, int ntp4,
                                 const double* duhat, double* uhat) {
-    const long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    const long nu = 4L * nimp * Np;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int per = nimp * Np;
+    const int nu = 4 * per;
     if (i < nu) {
-        const int v = int(i / (long(nimp) * Np));
-        const long rem = i % (long(nimp) * Np);
-        const int k = int(rem / Np), pt = int(rem % Np);
+        const int v = i / per;
+        const int rem = i - v * per;
+        const int k = rem / Np, pt = rem - k * Np;
         u[size_t(v) * Ne * Np + size_t(imp_list[k]) * Np + pt] += du[i];
     } else if (i - nu < ntp4) {
         uhat[i - nu] += duhat[i - nu];
@@ -528,12 +578,12 @@ struct Combo {
 };
 
 __global__ void k_combine(int nlist, int Np, int Ne, const int* list, Combo c) {
-    const long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    const long per = long(nlist) * Np;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int per = nlist * Np;
     if (i >= 4 * per) return;
-    const int v = int(i / per);
-    const long rem = i % per;
-    const int li = int(rem / Np), pt = int(rem % Np);
+    const int v = i / per;
+    const int rem = i - v * per;
+    const int li = rem / Np, pt = rem - li * Np;
     const size_t full = size_t(v) * Ne * Np + size_t(list[li]) * Np + pt;
     double acc = c.base[full];
     for (int t = 0; t < c.nterm; ++t) acc += c.coef[t] * c.terms[t][i];

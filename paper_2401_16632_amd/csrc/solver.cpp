@@ -64,12 +64,14 @@ struct hfr_solver_s {
     GmresState* gs = nullptr;
     double* part = nullptr;
     double* part2 = nullptr;
+    double* part3 = nullptr;
     unsigned* counters = nullptr;
-    int fpb = 1, gblk = 1;
+    int fpb = 1, gblk = 1, fpbA = 1, gblkA = 1;
     int* piv = nullptr;      // [Nim][n]
     double* yr = nullptr;    // [Nim][n]  L^-1 P r (FP64)
     double* zz = nullptr;    // [Nim][m]  C A^-1 r (FP64)
     bool have_factors = false;
+    int last_gmres_iters = 4;
     bool verbose = false;
     int stage_calls = 0;
     double* V = nullptr;     // (restart+1) x N
@@ -155,7 +157,7 @@ void free_solver(hfr_solver_s* s) {
                     s->tside, s->diag_blk, s->L64, s->L32, s->t, s->Dinv,
                     s->flags, s->V, s->z, s->r, s->scratch, s->dots, s->coef,
                     s->Lt64, s->Lt32, s->W, s->gs, s->part, s->part2,
-                    s->counters, s->piv, s->yr, s->zz};
+                    s->counters, s->piv, s->yr, s->zz, s->part3};
     for (void* p : ptrs) (void)hipFree(p);
 }
 
@@ -310,6 +312,8 @@ GmresArgs gmres_args(hfr_solver_s* s) {
     a.bs = s->bs;
     a.fpb = s->fpb;
     a.nblk = s->gblk;
+    a.fpbA = s->fpbA;
+    a.nblkA = s->gblkA;
     a.restart = s->restart;
     a.pc = s->opts.precond;
     a.rtol = s->opts.gmres_rtol;
@@ -325,13 +329,16 @@ GmresArgs gmres_args(hfr_solver_s* s) {
     a.V = s->V;
     a.part = s->part;
     a.part2 = s->part2;
+    a.part3 = s->part3;
     a.counters = s->counters;
     a.gs = s->gs;
     return a;
 }
 
-// Restarted GMRES: one host synchronisation per restart cycle (to read the
-// convergence flag); the Arnoldi steps run without host round trips.
+// Restarted GMRES.  Arnoldi steps are launched in chunks (the first sized
+// by the previous solve's iteration count) with one host synchronisation per
+// chunk to read the convergence flag; within a chunk there are no host
+// round trips, and steps after convergence return at entry.
 fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
                 hipStream_t st) {
     const int N = s->N;
@@ -350,22 +357,46 @@ fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
         int done, converged, jlast, iters, cycles, pad;
         double inv_norm, beta, bnorm, target;
     } hs{};
-    HIP_TRY(launch_gmres_restart(a, x, W0, 1, st));
-    int launched = 0;
-    for (;;) {
+    auto fetch = [&]() -> fr_status {
         HIP_TRY(hipMemcpyAsync(&hs, s->gs, sizeof(hs), hipMemcpyDeviceToHost, st));
         fr_status e = sync_check(st);
         if (e) return e;
         if (!(hs.beta == hs.beta) || std::isinf(hs.beta))
             return fail(FR_E_NONFINITE, "non-finite trace residual");
-        if (hs.converged || launched >= maxit) break;
-        const int steps = std::min(R, maxit - launched);
-        for (int j = 0; j < steps; ++j)
-            HIP_TRY(launch_arnoldi(a, j, j % 2 ? W1 : W0, j % 2 ? W0 : W1, st));
-        launched += steps;
+        return FR_OK;
+    };
+    HIP_TRY(launch_gmres_restart(a, x, W0, 1, st));
+    int launched = 0;
+    int chunk = std::max(2, std::min(R, s->last_gmres_iters + 1));
+    bool first_cycle = true;
+    fr_status e;
+    for (;;) {
+        if (!first_cycle) {
+            if ((e = fetch())) return e;
+            if (hs.converged || launched >= maxit) break;
+        }
+        int j = 0;
+        while (j < R && launched < maxit) {
+            const int steps = std::min(std::min(chunk, R - j), maxit - launched);
+            for (int c = 0; c < steps; ++c, ++j) {
+                double* wc = j % 2 ? W1 : W0;
+                double* wn = j % 2 ? W0 : W1;
+                const int tk = tbegin(s, HFR_T_SPMV, st);
+                HIP_TRY(launch_arnoldi_product(a, j, wc, wn, st));
+                tend(s, tk, st);
+                HIP_TRY(launch_arnoldi_orth(a, j, wn, st));
+            }
+            launched += steps;
+            if ((e = fetch())) return e;
+            if (hs.done) break;
+            chunk = 2;
+        }
+        first_cycle = false;
+        if (hs.converged && hs.jlast < 0) break;   // converged at the start
         HIP_TRY(launch_gmres_update(a, x, st));
         HIP_TRY(launch_gmres_restart(a, x, W0, 0, st));
     }
+    s->last_gmres_iters = hs.iters;
     loc.iterations = hs.iters;
     loc.restarts = hs.cycles;
     loc.rel_residual = hs.bnorm > 0 ? hs.beta / hs.bnorm : 0.0;
@@ -542,8 +573,9 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
         (o->precision == HFR_PREC_FP32 && (e = dalloc(&s->Lt32, size_t(s->nblocks) * bb, tot))) ||
         (e = dalloc(&s->W, 2 * size_t(std::max(1, s->N)), tot)) ||
         (e = dalloc(reinterpret_cast<char**>(&s->gs), sizeof(GmresState), tot)) ||
-        (e = dalloc(&s->part, size_t(std::max(1, (m->Ntf + 256 / s->bs - 1) / (256 / s->bs))) * kGmresMaxK, tot)) ||
-        (e = dalloc(&s->part2, size_t(std::max(1, (m->Ntf + 256 / s->bs - 1) / (256 / s->bs))) * 2, tot)) ||
+        (e = dalloc(&s->part, size_t(std::max(256, m->Ntf / std::max(1, 2048 / s->bs) + 1)) * kGmresMaxK, tot)) ||
+        (e = dalloc(&s->part2, size_t(std::max(256, m->Ntf / std::max(1, 2048 / s->bs) + 1)) * kGmresMaxK, tot)) ||
+        (e = dalloc(&s->part3, size_t(std::max(1024, m->Ntf + 1)) * kGmresMaxK, tot)) ||
         (e = dalloc(&s->counters, 4, tot)) ||
         (e = dalloc(&s->piv, nimp * size_t(s->n), tot)) ||
         (e = dalloc(&s->yr, nimp * size_t(s->n), tot)) ||
@@ -569,6 +601,15 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
     s->verbose = std::getenv("HFR_VERBOSE") != nullptr;
     s->fpb = 256 / s->bs;
     s->gblk = std::max(1, (m->Ntf + s->fpb - 1) / s->fpb);
+    // vector kernels: about 256 workgroups of 512 threads, each owning whole
+    // faces, at most 2048 rows (4 per thread)
+    s->fpb = std::min(std::max((m->Ntf + 255) / 256, std::max(1, 512 / s->bs)),
+                      2048 / s->bs);
+    s->gblk = std::max(1, (m->Ntf + s->fpb - 1) / s->fpb);
+    // product kernel: up to 1024 workgroups, 64 rows per pass, 8 passes max
+    s->fpbA = std::max(std::max(1, 64 / s->bs), (m->Ntf + 1023) / 1024);
+    s->fpbA = std::min(s->fpbA, std::max(1, 512 / s->bs));
+    s->gblkA = std::max(1, (m->Ntf + s->fpbA - 1) / s->fpbA);
     auto up = [&](int* d, const std::vector<int>& h) {
         return h.empty() ? hipSuccess
                          : hipMemcpy(d, h.data(), 4 * h.size(), hipMemcpyHostToDevice);

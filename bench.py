@@ -118,7 +118,7 @@ def roofline(form, mesh, timers, precision):
         avg = cms / max(1, ccnt) * 1e-3
         pk = PEAK["fp32_tflops"] if precision == "fp32" else PEAK["fp64_tflops"]
         ach = fl / avg / 1e12
-        return dict(kernel="condense", bound="mfma", achieved=ach, peak=pk,
+        return dict(kernel="condense", bound="alu", achieved=ach, peak=pk,
                     unit="TFLOP/s", frac=ach / pk, traffic=None,
                     launches=ccnt, avg_ms=avg * 1e3,
                     algorithmic_per_launch=fl)
@@ -163,11 +163,14 @@ def explicit_bytes(mesh):
     return mesh.Nex * (2 * 4 * mesh.Np * 8 + 64 + 4 * 32)
 
 
-def cpu_baseline(name, budget_s=40.0):
-    """The oracle timed on one implicit stage of the same workload."""
+def cpu_baseline(name):
+    """The oracle timed on a bounded sample of the same workload: the first
+    implicit stage of step 1 (Newton to 1e-10 with exact element Jacobians,
+    condensation and a sparse direct trace solve), single-threaded."""
     import fr_inputs as fi
     import oracle
-    from oracle import newton as onw, imex as oimex, residual as ores
+    from oracle import newton as onw, imex as oimex
+    from threadpoolctl import threadpool_limits
     d, p, nt, nr, first, ratio = cylinder_workload(name)
     uinf = fi.freestream_state(MACH)
     m0 = oracle.QuadMesh(d, p, uinf=uinf)
@@ -180,17 +183,30 @@ def cpu_baseline(name, budget_s=40.0):
     u = fi.perturb_state(np.broadcast_to(uinf, (om.Ne, P, P, 4)).copy(), 1e-3, 2)
     ph = oracle.Euler()
     tab = oimex.himex2c()
-    t0 = time.perf_counter()
-    u_im, uhat, its = onw.solve_stage(om, ph, u, u[om.imp_elems],
-                                      dt * tab.A[0, 0], tol=1e-10, maxit=30)
-    el = time.perf_counter() - t0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        _, _, its = onw.solve_stage(om, ph, u, u[om.imp_elems], dt * tab.A[0, 0],
+                                    tol=1e-10, maxit=30)
+        el = time.perf_counter() - t0
     dof = om.Nim * P * P * 4
     return dict(value=dof / el, unit="implicit-stage DOF/s", cores=1,
                 kind="oracle",
                 sample=(f"first implicit stage of step 1 on the full workload "
-                        f"({om.Nim} implicit elements, Newton tol 1e-10, "
-                        f"{its} iterations, {el:.1f} s, single-threaded "
-                        f"NumPy/SciPy)"))
+                        f"({om.Nim} implicit elements, Newton to 1e-10 in {its} "
+                        f"iterations), {el:.1f} s single-threaded NumPy/SciPy"))
+
+
+def copy_calibration(nbytes, reps=5):
+    """A plain device copy of known size (read nbytes, write nbytes), the
+    reference for the HBM traffic counters."""
+    import torch
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 4, "reps": reps}))
 
 
 def main():
@@ -202,7 +218,12 @@ def main():
     ap.add_argument("--forms", default="fp32,fp64")
     ap.add_argument("--newton-tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter reference)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1",
               file=sys.stderr)

@@ -248,11 +248,13 @@ fr_status hfr_trace_matvec(hfr_solver_t s, const double* x, double* y,
 fr_status hfr_get_system(hfr_solver_t s, double* t, double* h, double* g,
                          void* stream);
 fr_status hfr_get_blocks(hfr_solver_t s, double* blocks, void* stream);
-/* Factored element matrices of the last linearisation, (n+m) x (n+m+1) per
- * implicit element, row-major, FP64 or FP32 as the solver's precision:
- * rows 0..n-1 hold L\U (unit L) and L^-1 P [B r], rows n.. hold C U^-1
- * and [L^k t^k].  piv (may be NULL) receives the pivot row of each of the
- * n elimination steps per element, int32. */
+/* Swept element tableaux of the last linearisation (static condensation,
+ * Section 3.2), N x N per implicit element with N = n + m, COLUMN-major,
+ * FP64 or FP32 as the solver's precision.  With p_k the pivot row of
+ * exchange k (returned in piv, int32 [Nim][n], may be NULL):
+ *   T[p_k][j]   = A^-1[k][p_j]          T[p_k][n+b] = -(A^-1 B)[k][b]
+ *   T[n+i][j]   = (C A^-1)[i][p_j]      T[n+i][n+b] = (D - C A^-1 B)[i][b]
+ * for j < n, b < m, i < m (element-local ordering as in hfr_get_blocks). */
 fr_status hfr_get_factors(hfr_solver_t s, void* factors, int32_t* piv,
                           void* stream);
 
@@ -266,7 +268,7 @@ fr_status hfr_get_factors(hfr_solver_t s, void* factors, int32_t* piv,
  * a device synchronisation.
  */
 enum { HFR_T_RESIDUAL = 0,   /* hybridized residual kernel                 */
-       HFR_T_CONDENSE = 1,   /* element blocks + LU/Schur kernel           */
+       HFR_T_CONDENSE = 1,   /* element tableau fill + Jordan sweep kernel */
        HFR_T_ASSEMBLE = 2,   /* block-sparse assembly kernel               */
        HFR_T_PCSETUP = 3,    /* block-Jacobi inversion kernel              */
        HFR_T_SPMV = 4,       /* Arnoldi product kernel (block-sparse

@@ -251,16 +251,18 @@ class Solver:
             _stream(stream)))
 
     def get_factors(self, stream=None):
-        """Factored element matrices (Nim, n+m, n+m+1) and pivots (Nim, n)."""
+        """Swept element tableaux (Nim, n+m, n+m) indexed [element, row,
+        column] and the pivot rows (Nim, n) of the n exchanges."""
         m = self.mesh
         k = self.n + self.m
         dt = torch.float64 if self.opts.precision == 0 else torch.float32
-        f = torch.zeros(m.Nim * k * (k + 1), dtype=dt, device="cuda")
+        f = torch.zeros(m.Nim * k * k, dtype=dt, device="cuda")
         pv = torch.zeros(m.Nim * self.n, dtype=torch.int32, device="cuda")
         _check(load_library().hfr_get_factors(
             self.handle, ctypes.c_void_p(f.data_ptr()),
             ctypes.c_void_p(pv.data_ptr()), _stream(stream)))
-        return f.view(m.Nim, k, k + 1), pv.view(m.Nim, self.n)
+        # stored column-major per element
+        return f.view(m.Nim, k, k).transpose(1, 2), pv.view(m.Nim, self.n)
 
     def timing(self, enable=None):
         """Start (True) / stop (False) the kernel timers; returns the

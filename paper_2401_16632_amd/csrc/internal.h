@@ -90,16 +90,16 @@ struct CondenseLaunch {
     const double* h;         // [4][Nim][Np]
     const double* gk;        // [Nim][4][P][4]
     int precision;           // HFR_PREC_*
-    void* M;                 // per element (n+m) x (n+m+1), FP64 or FP32
+    void* M;                 // per element swept tableau (n+m)^2 column-major, FP64 or FP32
     double* blocks_copy;     // optional (n+m)^2 FP64 copy per element
     int* pivot_fail;         // set to 1 if a zero pivot is met
-    int* piv;                // [Nim][n] pivot row chosen at each step
+    int* piv;                // [Nim][n] pivot row p_k of each exchange
 };
 hipError_t launch_condense(const RefOps& ops, const CondenseLaunch& a,
                            hipStream_t st);
-// FP64 right-hand side with the stored factors: y = L^-1 P (-h) -> yr
-// [Nim][n], z = (C U^-1) y -> z [Nim][m]; the condensed right-hand side is
-// then t = -g - sum over the two sides of z (assembled in FP64)
+// FP64 right-hand side with the swept tableau: A^-1 (-h) in pivot-row order
+// -> yr [Nim][n], C A^-1 (-h) -> z [Nim][m]; the condensed right-hand side
+// is then t = -g - sum over the two sides of z (assembled in FP64)
 hipError_t launch_rhs64(int P, int nimp, const void* M, int precision,
                         const int* piv, const double* h, double* yr,
                         double* z, hipStream_t st);
@@ -138,7 +138,7 @@ hipError_t launch_scale(int N, double* x, const double* src, double a,
 hipError_t launch_axpy(int N, double a, const double* x, double* y,
                        hipStream_t st);
 hipError_t launch_recover(int P, int nimp, const void* M, int precision,
-                          const double* yr, const int* trace_map,
+                          const int* piv, const double* yr, const int* trace_map,
                           const double* duhat, double* du, hipStream_t st);
 hipError_t launch_newton_update(int Np, int nimp, int Ne, const int* imp_list,
                                 const double* du, double* u, int ntp4,

@@ -2,18 +2,16 @@
 //
 // For implicit element k with n = 4 Np element unknowns and m = 16 P trace
 // unknowns (all four faces; a face off the trace gets an identity row and
-// zero coupling), the augmented matrix
-//      [ A  B  r ]        r = -h,  s = -g^(k)
-//      [ C  D  s ]
+// zero coupling), the element tableau
+//      [ A  B ]
+//      [ C  D ]
 // is built from analytic flux Jacobians (the exact derivatives of h and of
-// the element's share of g), then LU elimination of the first n columns
-// with partial pivoting inside the A rows turns it into
-//      [ L\U    L^-1 P B     L^-1 P r   ]
-//      [ C U^-1  D - C A^-1 B  s - C A^-1 r ] = [ .  L^k  t^k ]
-// which holds the recovery factors of eq:localproblems (back substitution
-// with U) and the element Schur complement of eq:assembly in place.  The
-// right-hand side used by Newton is recomputed in FP64 by k_rhs64 from the
-// stored factors (the r, s columns here are not used downstream).
+// the element's share of g) and swept by n Jordan exchanges on the columns
+// of A (block Gauss-Jordan elimination with partial pivoting inside the A
+// rows).  The swept tableau holds A^-1, A^-1 B, C A^-1 and the element
+// Schur complement L^k = D - C A^-1 B of eq:assembly; recovery
+// (eq:localproblems) and the condensed right-hand side t^k = s - C A^-1 r
+// then reduce to matrix-vector products, the latter accumulated in FP64.
 //
 // Element-local ordering: u index = point*4 + var (point j*P+i), trace
 // index = (face*P + q)*4 + var with q counter-clockwise along the element.
@@ -198,257 +196,402 @@ __device__ __forceinline__ double aug_entry(int r, int c, int k,
     }
 }
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef double doublex4 __attribute__((ext_vector_type(4)));
-
-template <typename T> struct MfmaVec;
-template <> struct MfmaVec<float> { typedef floatx4 type; };
-template <> struct MfmaVec<double> { typedef doublex4 type; };
-
-// D(16x16) += A(16x4) B(4x16); lane l supplies A[l%16][l/16] and
-// B[l/16][l%16].  Element r of lane l holds D[i][l%16] with
-// i = 4*(l/16) + r for the FP32 instruction and i = l/16 + 4*r for the
-// FP64 one (measured on gfx950).
-__device__ __forceinline__ floatx4 mfma16(float a, float b, floatx4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+// ---- block Gauss-Jordan sweep ----------------------------------------------
+// The tableau T = [A B; C D] (N = n + m rows and columns) is swept with n
+// Jordan exchanges, one per column k of A, pivoting on the unused A row of
+// largest magnitude in that column.  Exchange (p, k) solves equation p for
+// the variable of column k:
+//      T'[p][k] = 1/T[p][k],  T'[p][j] = -T[p][j]/T[p][k],
+//      T'[i][k] = T[i][k]/T[p][k],  T'[i][j] = T[i][j] - T'[i][k] T[p][j].
+// With p_k the pivot row of step k, the swept tableau holds
+//      T[p_k][j] = A^-1[k][p_j],   T[p_k][n+b] = -(A^-1 B)[k][b],
+//      T[n+i][j] = (C A^-1)[i][p_j],  T[n+i][n+b] = (D - C A^-1 B)[i][b],
+// i.e. the element inverse used by recovery (eq:localproblems) and the
+// element Schur complement of eq:assembly.
+//
+// Register layout: a workgroup of W waves per element; lane l holds rows
+// l + 64 s (s < RPL) and wave w the columns w NCW .. w NCW + NCW - 1.  A
+// pivot row is left unscaled in registers with its factor -1/T[p][k] kept
+// per row (applied on the way out), so every step is one rank-1 update
+// T[i][j] -= g_i u_j with g_p = 0.  The wave that owns column k finds the
+// pivot and the multipliers and passes them to the other waves through LDS
+// (one barrier per step); each wave broadcasts its own segment of the pivot
+// row through LDS.  The result is stored column-major, (N x N) per element.
+// Waves per element: the smallest power of two that keeps the register
+// tableau within about 72 values per lane (more waves shorten the
+// per-element critical path and raise occupancy), at most 8 (512 lanes).
+constexpr int sweep_waves(int rpl, int N, int words) {
+    int w = 1;
+    while (rpl * ((N + w - 1) / w) * words > 72 && w < 8) w *= 2;
+    return w;
 }
-__device__ __forceinline__ doublex4 mfma16(double a, double b, doublex4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+
+template <int P, typename T>
+struct SweepShape {
+    static constexpr int NP = P * P, n = 4 * NP, m = 16 * P, N = n + m;
+    static constexpr int RPL = (N + 63) / 64;
+    static constexpr int W = sweep_waves(RPL, N, int(sizeof(T) / 4));
+    static constexpr int NCW = (N + W - 1) / W;
+    // register columns are held as vectors of CH values so that the one
+    // column addressed by the (wave-uniform) step index is reached by VGPR
+    // indexing instead of a select over every column
+    static constexpr int CH = sizeof(T) == 8 ? 8 : 16;
+    static constexpr int NCH = (NCW + CH - 1) / CH;
+};
+
+__device__ __forceinline__ float lane_value(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
 }
-template <typename T> __device__ __forceinline__ int mfma_row(int lk, int q);
-template <> __device__ __forceinline__ int mfma_row<float>(int lk, int q) { return 4 * lk + q; }
-template <> __device__ __forceinline__ int mfma_row<double>(int lk, int q) { return lk + 4 * q; }
+__device__ __forceinline__ double lane_value(double x, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
+}
 
-constexpr int kPanel = 16;
+// Wave-wide maximum of a 64-bit key by DPP row operations (quad swaps,
+// half-row and row mirrors, then the row broadcasts 15 and 31); the
+// maximum ends in lane 63.
+__device__ __forceinline__ unsigned long long key_max(unsigned long long a,
+                                                      unsigned long long b) {
+    return a > b ? a : b;
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ unsigned long long key_dpp(unsigned long long x) {
+    const int lo = int(unsigned(x)), hi = int(unsigned(x >> 32));
+    const unsigned l2 = unsigned(__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xf, false));
+    const unsigned h2 = unsigned(__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xf, false));
+    return (static_cast<unsigned long long>(h2) << 32) | l2;
+}
+__device__ __forceinline__ unsigned long long wave_max_key(unsigned long long x) {
+    x = key_max(x, key_dpp<0xb1, 0xf>(x));      // quad_perm [1,0,3,2]
+    x = key_max(x, key_dpp<0x4e, 0xf>(x));      // quad_perm [2,3,0,1]
+    x = key_max(x, key_dpp<0x141, 0xf>(x));     // row_half_mirror
+    x = key_max(x, key_dpp<0x140, 0xf>(x));     // row_mirror
+    x = key_max(x, key_dpp<0x142, 0xa>(x));     // row_bcast:15
+    x = key_max(x, key_dpp<0x143, 0xc>(x));     // row_bcast:31
+    const int lo = __builtin_amdgcn_readlane(int(unsigned(x)), 63);
+    const int hi = __builtin_amdgcn_readlane(int(unsigned(x >> 32)), 63);
+    return (static_cast<unsigned long long>(unsigned(hi)) << 32) | unsigned(lo);
+}
+// pivot key: |value| (as FP32, order-preserving bits) above the complement
+// of the row, so the maximum is the largest magnitude with the lowest row
+__device__ __forceinline__ unsigned long long pivot_key(float mag, int row) {
+    return (static_cast<unsigned long long>(__float_as_uint(mag)) << 32) |
+           (0xffffffffu - unsigned(row));
+}
 
-// Right-looking LU of the first n columns of the rows x ld matrix M
-// (row-major, leading dimension ld) with partial pivoting restricted to the
-// first n rows; rows n.. are eliminated but never chosen as pivots.  After
-// the call: rows 0..n-1 hold L\U and L^-1 P [B r]; rows n.. hold C U^-1 and
-// the Schur complement [D - C A^-1 B | s - C A^-1 r].  Panel of 16 columns:
-// unblocked factorisation of the panel, forward substitution for the pivot
-// rows' trailing part, then a rank-16 trailing update on MFMA tiles.
-template <typename T>
-__device__ bool lu_condense(T* M, int n, int rows, int ld, int* s_piv,
-                            T* s_val, int* piv_out) {
-    typedef typename MfmaVec<T>::type vec4;
-    const int t = threadIdx.x, nt = blockDim.x;
-    const int lane = t & 63, wave = t >> 6, nwaves = nt >> 6;
-    for (int k0 = 0; k0 < n; k0 += kPanel) {
-        const int k1 = min(n, k0 + kPanel);
-        // ---- panel factorisation -----------------------------------------
-        for (int kk = k0; kk < k1; ++kk) {
-            if (wave == 0) {
-                T best = T(-1);
-                int bi = kk;
-                for (int r = kk + lane; r < n; r += 64) {
-                    const T v = fabs(M[size_t(r) * ld + kk]);
-                    if (v > best) { best = v; bi = r; }
-                }
-                for (int off = 32; off > 0; off >>= 1) {
-                    const T ob = __shfl_xor(best, off, 64);
-                    const int oi = __shfl_xor(bi, off, 64);
-                    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-                }
-                if (lane == 0) { *s_piv = bi; *s_val = best; }
-            }
-            __syncthreads();
-            const int piv = *s_piv;
-            if (!(*s_val > T(0))) return false;
-            if (t == 0) piv_out[kk] = piv;
-            if (piv != kk) {
-                for (int c = t; c < ld; c += nt) {
-                    const T x = M[size_t(kk) * ld + c];
-                    M[size_t(kk) * ld + c] = M[size_t(piv) * ld + c];
-                    M[size_t(piv) * ld + c] = x;
-                }
-                __syncthreads();
-            }
-            const T inv = T(1) / M[size_t(kk) * ld + kk];
-            for (int r = kk + 1 + t; r < rows; r += nt) M[size_t(r) * ld + kk] *= inv;
-            __syncthreads();
-            const int w = k1 - kk - 1;
-            if (w > 0) {
-                const int tot = (rows - kk - 1) * w;
-                for (int idx = t; idx < tot; idx += nt) {
-                    const int r = kk + 1 + idx / w, c = kk + 1 + idx % w;
-                    M[size_t(r) * ld + c] -= M[size_t(r) * ld + kk] * M[size_t(kk) * ld + c];
-                }
-                __syncthreads();
-            }
-        }
-        if (k1 >= ld) break;
-        // ---- U12 = L11^-1 A12 (pivot rows, trailing columns) ---------------
-        for (int c = k1 + t; c < ld; c += nt) {
-            for (int i = k0 + 1; i < k1; ++i) {
-                T acc = M[size_t(i) * ld + c];
-                for (int j = k0; j < i; ++j) acc -= M[size_t(i) * ld + j] * M[size_t(j) * ld + c];
-                M[size_t(i) * ld + c] = acc;
-            }
-        }
-        __syncthreads();
-        // ---- A22 -= L21 U12 on 16x16 MFMA tiles ------------------------------
-        const int R0 = k1, C0 = k1;
-        const int TR = (rows - R0 + 15) / 16, TC = (ld - C0 + 15) / 16;
-        const int kw = k1 - k0;             // multiple of 4
-        const int li = lane & 15, lk = lane >> 4;
-        for (int tile = wave; tile < TR * TC; tile += nwaves) {
-            const int tr = tile % TR, tc = tile / TR;
-            const int r0 = R0 + 16 * tr, c0 = C0 + 16 * tc;
-            vec4 acc;
-            const int cc = c0 + li;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int rr = r0 + mfma_row<T>(lk, q);
-                acc[q] = (rr < rows && cc < ld) ? M[size_t(rr) * ld + cc] : T(0);
-            }
-            for (int kq = 0; kq < kw; kq += 4) {
-                const int ra = r0 + li;
-                const T av = (ra < rows) ? -M[size_t(ra) * ld + k0 + kq + lk] : T(0);
-                const T bv = (cc < ld) ? M[size_t(k0 + kq + lk) * ld + cc] : T(0);
-                acc = mfma16(av, bv, acc);
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int rr = r0 + mfma_row<T>(lk, q);
-                if (rr < rows && cc < ld) M[size_t(rr) * ld + cc] = acc[q];
-            }
-        }
-        __syncthreads();
+// ---- fill of the element tableau ------------------------------------------
+// Lane-side description of one tableau row (an element unknown or a trace
+// unknown); the column is uniform over the wave.
+struct RowDesc {
+    int row, i, j, v, f, q;
+    bool tr;                   // trace row on a face of the trace
+    double cij, wq;
+};
+
+template <int P>
+__device__ __forceinline__ RowDesc row_desc(int row, const RefOps& o,
+                                            const CondShared<P>& sh) {
+    constexpr int NP = P * P, n = 4 * NP;
+    RowDesc d;
+    d.row = row;
+    d.i = d.j = d.v = d.f = d.q = 0;
+    d.tr = false;
+    d.cij = d.wq = 0.0;
+    if (row < n) {
+        const int pr = row >> 2;
+        d.v = row & 3;
+        d.i = pr % P;
+        d.j = pr / P;
+        d.cij = sh.c[pr];
+    } else if (row < n + 16 * P) {
+        const int b = row - n;
+        d.f = b / (4 * P);
+        d.q = (b >> 2) % P;
+        d.v = b & 3;
+        d.wq = o.w[d.q];
+        d.tr = sh.tr[d.f] != 0;
     }
-    return true;
+    return d;
 }
 
-// One workgroup per implicit element.  kLDS: the augmented matrix is built
-// and factored in LDS and copied out once; otherwise it stays in the
-// solver workspace.
-template <int P, typename T, bool kLDS>
-__global__ __launch_bounds__(256) void k_condense_lu(CondenseLaunch a, RefOps o) {
-    constexpr int NP = P * P;
-    constexpr int n = 4 * NP, m = 16 * P, rows = n + m, ld = n + m + 1;
+// entry (d.row, col) of [A B; C D] (exact derivatives, FP64)
+template <int P>
+__device__ __forceinline__ double tableau_entry(const RowDesc& d, int col,
+                                                const RefOps& o,
+                                                const CondShared<P>& sh) {
+    constexpr int NP = P * P, n = 4 * NP, N = n + 16 * P;
+    if (d.row >= N) return 0.0;
+    const int i = d.i, j = d.j, v = d.v;
+    if (col < n) {
+        const int pc = col >> 2, w = col & 3, l = pc % P, kk = pc / P;
+        if (d.row < n) {
+            const double af = sh.Af[pc][v * 4 + w];
+            const double ag = sh.Ag[pc][v * 4 + w];
+            double acc = 0.0;
+            if (kk == j)
+                acc += o.D[i * P + l] * af +
+                       o.cr[i] * o.lp[l] * (sh.Fu[1 * P + j][v * 4 + w] - af) +
+                       o.cl[i] * o.lm[l] * (sh.Fu[3 * P + (P - 1 - j)][v * 4 + w] + af);
+            if (l == i)
+                acc += o.D[j * P + kk] * ag +
+                       o.cl[j] * o.lm[kk] * (sh.Fu[0 * P + i][v * 4 + w] + ag) +
+                       o.cr[j] * o.lp[kk] * (sh.Fu[2 * P + (P - 1 - i)][v * 4 + w] - ag);
+            return (d.row == col ? 1.0 : 0.0) + d.cij * acc;
+        }
+        if (!d.tr) return 0.0;
+        const int f = d.f, q = d.q;
+        double coef = 0.0;
+        if (f == 1) { if (kk == q) coef = o.lp[l]; }
+        else if (f == 3) { if (kk == P - 1 - q) coef = o.lm[l]; }
+        else if (f == 0) { if (l == q) coef = o.lm[kk]; }
+        else { if (l == P - 1 - q) coef = o.lp[kk]; }
+        return d.wq * coef * sh.Fu[f * P + q][v * 4 + w];
+    }
+    const int b2 = col - n, f2 = b2 / (4 * P), q2 = (b2 >> 2) % P, w2 = b2 & 3;
+    if (d.row < n) {
+        if (!sh.tr[f2]) return 0.0;
+        double coef = 0.0;
+        if (f2 == 1) { if (q2 == j) coef = o.cr[i]; }
+        else if (f2 == 3) { if (q2 == P - 1 - j) coef = o.cl[i]; }
+        else if (f2 == 0) { if (q2 == i) coef = o.cl[j]; }
+        else { if (q2 == P - 1 - i) coef = o.cr[j]; }
+        return d.cij * coef * sh.Fh[f2 * P + q2][v * 4 + w2];
+    }
+    const int b = d.row - n;
+    if (!d.tr) return (b == b2) ? 1.0 : 0.0;
+    if ((b >> 2) != (b2 >> 2)) return 0.0;
+    return d.wq * sh.Fh[d.f * P + d.q][v * 4 + w2];
+}
+
+template <int P, typename T>
+__global__ __launch_bounds__((64 * SweepShape<P, T>::W)) void k_condense_sweep(
+    CondenseLaunch a, RefOps og) {
+    using S = SweepShape<P, T>;
+    constexpr int n = S::n, N = S::N, RPL = S::RPL, W = S::W, NCW = S::NCW;
     __shared__ CondShared<P> sh;
-    __shared__ int s_piv;
-    __shared__ T s_val;
-    extern __shared__ double dyn_lds[];
+    __shared__ RefOps o;
+    __shared__ T gbuf[2][RPL * 64];
+    __shared__ T ibuf[2];
+    __shared__ int pbuf[2];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
     const int k = blockIdx.x;
-    const int t = threadIdx.x;
-    element_linearisation<P>(a, o, k, sh);
-    T* G = reinterpret_cast<T*>(a.M) + size_t(k) * rows * ld;
-    T* M = kLDS ? reinterpret_cast<T*>(dyn_lds) : G;
-    for (int idx = t; idx < rows * ld; idx += blockDim.x) {
-        const int r = idx / ld, c = idx % ld;
-        const double val = aug_entry<P>(r, c, k, a, o, sh);
-        M[idx] = T(val);
-        if (a.blocks_copy && c < rows)
-            a.blocks_copy[size_t(k) * rows * rows + size_t(r) * rows + c] = val;
-    }
+    if (threadIdx.x == 0) o = og;
     __syncthreads();
-    const bool ok = lu_condense<T>(M, n, rows, ld, &s_piv, &s_val,
-                                   a.piv + size_t(k) * n);
-    if (!ok) {
-        if (t == 0) *a.pivot_fail = 1;
-        return;
+    element_linearisation<P>(a, o, k, sh);
+
+    // ---- fill: entries in FP64, rounded to T, written to this element's
+    // output slot by a rolled loop and read back into registers by the same
+    // lanes (same addresses, so no synchronisation is needed)
+    constexpr int CH = S::CH, NCH = S::NCH;
+    typedef T VT __attribute__((ext_vector_type(CH)));
+    const int c0 = __builtin_amdgcn_readfirstlane(w * NCW);
+    T* G = reinterpret_cast<T*>(a.M) + size_t(k) * N * N;
+    double* bcopy = a.blocks_copy ? a.blocks_copy + size_t(k) * N * N : nullptr;
+    RowDesc rd[RPL];
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) rd[s] = row_desc<P>(lane + 64 * s, o, sh);
+#pragma unroll 4
+    for (int j = 0; j < NCW; ++j) {
+        const int col = c0 + j;
+        if (col >= N) break;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) {
+            if (rd[s].row >= N) continue;
+            const double v = tableau_entry<P>(rd[s], col, o, sh);
+            G[size_t(col) * N + rd[s].row] = T(v);
+            if (bcopy) bcopy[size_t(rd[s].row) * N + col] = v;
+        }
     }
-    if (kLDS) {
-        for (int idx = t; idx < rows * ld; idx += blockDim.x) G[idx] = M[idx];
+    VT t[RPL][NCH];
+    T sig[RPL];
+    bool used[RPL];
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const int row = lane + 64 * s;
+        sig[s] = T(1);
+        used[s] = false;
+#pragma unroll
+        for (int j = 0; j < NCH * CH; ++j) {
+            const int col = c0 + j;
+            t[s][j / CH][j % CH] = (j < NCW && row < N && col < N) ? G[size_t(col) * N + row] : T(0);
+        }
+    }
+    // ---- n Jordan exchanges ---------------------------------------------------
+    // The wave that owns column k+1 updates that column first and finds the
+    // pivot of step k+1 (look-ahead) before its full rank-1 update of step
+    // k, so the other waves rarely wait at the step barrier.
+    int* pivk = a.piv + size_t(k) * n;
+    T gs[RPL];
+    T ipv = T(0);
+    int p = -1;
+    auto find_pivot = [&](const T (&col)[RPL], int step, T (&g)[RPL], T& ip, int& pp) {
+        unsigned long long key = 0;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) {
+            const int row = lane + 64 * s;
+            const unsigned long long ks = pivot_key(float(fabs(col[s])), row);
+            if (row < n && !used[s] && ks > key) key = ks;
+        }
+        key = wave_max_key(key);
+        pp = -1;
+        ip = T(0);
+        if ((key >> 32) != 0) {
+            pp = int(0xffffffffu - unsigned(key));
+            const int sp = pp >> 6, lp = pp & 63;
+            T pv = T(1);
+#pragma unroll
+            for (int s = 0; s < RPL; ++s)
+                if (s == sp) pv = lane_value(col[s], lp);
+            ip = T(1) / pv;
+        }
+#pragma unroll
+        for (int s = 0; s < RPL; ++s)
+            g[s] = (lane + 64 * s == pp) ? T(0) : col[s] * ip;
+        const int buf = step & 1;
+        if (W > 1) {
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) gbuf[buf][lane + 64 * s] = g[s];
+            if (lane == 0) { pbuf[buf] = pp; ibuf[buf] = ip; }
+        }
+        if (lane == 0 && pp >= 0) pivk[step] = pp;
+    };
+    if (w == 0) {
+        T col0[RPL];
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) col0[s] = t[s][0][0];
+        find_pivot(col0, 0, gs, ipv, p);
+    }
+    for (int kk = 0; kk < n; ++kk) {
+        const int ow = kk / NCW, jk = kk - ow * NCW, buf = kk & 1;
+        if (W > 1) {
+            __syncthreads();
+            if (w != ow) {
+                p = __builtin_amdgcn_readfirstlane(pbuf[buf]);
+                ipv = ibuf[buf];
+#pragma unroll
+                for (int s = 0; s < RPL; ++s) gs[s] = gbuf[buf][lane + 64 * s];
+            }
+        }
+        if (p < 0) {
+            if (threadIdx.x == 0) *a.pivot_fail = 1;
+            return;                                // uniform over the workgroup
+        }
+        const int sp = p >> 6, lp = p & 63;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s)
+            if (lane + 64 * s == p) { used[s] = true; sig[s] = -ipv; }
+        // look-ahead: the owner of column k+1 forms it and picks its pivot
+        T gn[RPL];
+        T ipn = T(0);
+        int pn = -1;
+        const int k1 = kk + 1;
+        const bool ahead = (k1 < n && w == k1 / NCW);
+        if (ahead) {
+            const int j1 = k1 - w * NCW, c1 = j1 / CH, e1 = j1 - c1 * CH;
+            T cpre[RPL];
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) cpre[s] = T(0);
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+                if (c == c1) {
+#pragma unroll
+                    for (int s = 0; s < RPL; ++s) cpre[s] = t[s][c][e1];
+                }
+            T u1 = T(0);
+#pragma unroll
+            for (int s = 0; s < RPL; ++s)
+                if (s == sp) u1 = lane_value(cpre[s], lp);
+            T col1[RPL];
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) col1[s] = fma(-gs[s], u1, cpre[s]);
+            find_pivot(col1, k1, gn, ipn, pn);
+        }
+        // rank-1 update of this wave's columns; the pivot row segment comes
+        // from the lane holding row p (uniform lane and slot)
+#pragma unroll
+        for (int s0 = 0; s0 < RPL; ++s0)
+            if (s0 == sp) {
+#pragma unroll
+                for (int j = 0; j < NCW; ++j) {
+                    const T uj = lane_value(t[s0][j / CH][j % CH], lp);
+#pragma unroll
+                    for (int s = 0; s < RPL; ++s)
+                        t[s][j / CH][j % CH] = fma(-gs[s], uj, t[s][j / CH][j % CH]);
+                }
+            }
+        // column k: multipliers for the other rows, -1 in the pivot row
+        if (w == ow) {
+            const int ck = jk / CH, ek = jk - ck * CH;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+                if (c == ck) {
+#pragma unroll
+                    for (int s = 0; s < RPL; ++s)
+                        t[s][c][ek] = (lane + 64 * s == p) ? T(-1) : gs[s];
+                }
+        }
+        if (ahead) {
+            p = pn;
+            ipv = ipn;
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) gs[s] = gn[s];
+        }
+    }
+
+    // ---- store column-major, pivot rows scaled -------------------------------
+#pragma unroll
+    for (int j = 0; j < NCW; ++j) {
+        const int col = c0 + j;
+        if (col >= N) break;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) {
+            const int row = lane + 64 * s;
+            if (row < N) G[size_t(col) * N + row] = sig[s] * t[s][j / CH][j % CH];
+        }
     }
 }
 
 template <int P, typename T>
-static hipError_t launch_lu(const RefOps& o, const CondenseLaunch& a,
-                            hipStream_t st) {
-    constexpr int NP = P * P;
-    constexpr int n = 4 * NP, m = 16 * P, rows = n + m, ld = n + m + 1;
-    constexpr size_t bytes = size_t(rows) * ld * sizeof(T);
-    constexpr size_t kMaxDyn = 160 * 1024 - sizeof(CondShared<P>) - 256;
-    if (bytes <= kMaxDyn) {
-        static bool attr = false;
-        if (!attr) {
-            hipError_t e = hipFuncSetAttribute(
-                reinterpret_cast<const void*>(&k_condense_lu<P, T, true>),
-                hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
-            if (e != hipSuccess) return e;
-            attr = true;
-        }
-        hipLaunchKernelGGL((k_condense_lu<P, T, true>), dim3(a.nimp), dim3(256),
-                           bytes, st, a, o);
-    } else {
-        hipLaunchKernelGGL((k_condense_lu<P, T, false>), dim3(a.nimp), dim3(256),
-                           0, st, a, o);
-    }
+static hipError_t launch_sweep(const RefOps& o, const CondenseLaunch& a,
+                               hipStream_t st) {
+    hipLaunchKernelGGL((k_condense_sweep<P, T>), dim3(a.nimp),
+                       dim3(64 * SweepShape<P, T>::W), 0, st, a, o);
     return hipGetLastError();
 }
 
-// FP64 right-hand side with the stored factors (FP64 or FP32): the
-// element shares of g are large and cancel between the two sides of a
-// trace face, so they never pass through the factor precision; only
-// C A^-1 r does, which is proportional to the (small) residual h.
-// one wave per element; row i of the element lives in lane i % 64, slot
-// i / 64 (NS slots); cross-lane values move by readlane-style shuffles
-template <int NS>
-__device__ __forceinline__ double slot_get(const double (&y)[NS], int s) {
-    double r = y[0];
-#pragma unroll
-    for (int i = 1; i < NS; ++i) r = (s == i) ? y[i] : r;
-    return r;
-}
-
+// FP64 right-hand side from the swept tableau (FP64 or FP32 entries): with
+// r = -h and r'_j = r[p_j],
+//      y~ = T[0:n][0:n] r'  (A^-1 r in pivot-row order: y~[p_k] = (A^-1 r)[k])
+//      z  = T[n:N][0:n] r'  (C A^-1 r)
+// accumulated in FP64.  The element shares of g are large and cancel
+// between the two sides of a trace face, so they never pass through the
+// factor precision; only C A^-1 r does, which is proportional to the
+// (small) residual h.  One wave per element, four per workgroup.
 template <typename T, int P>
 __global__ __launch_bounds__(256) void k_rhs64(int nimp, const T* M,
                                                const int* piv, const double* h,
                                                double* yr, double* z) {
-    constexpr int NP = P * P, n = 4 * NP, m = 16 * P, ld = n + m + 1;
-    constexpr int NS = (n + 63) / 64;
-    __shared__ double sy[4][n];
+    constexpr int NP = P * P, n = 4 * NP, m = 16 * P, N = n + m;
+    __shared__ double sr[4][n];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int k = blockIdx.x * 4 + wv;
     if (k >= nimp) return;
-    const T* Mk = M + size_t(k) * (n + m) * ld;
-    double y[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const int row = lane + 64 * s;
-        y[s] = row < n ? -h[size_t(row & 3) * nimp * NP + size_t(k) * NP + (row >> 2)] : 0.0;
-    }
-    // row interchanges of the factorisation, in order
     const int* pk = piv + size_t(k) * n;
-    for (int kk = 0; kk < n; ++kk) {
-        const int p = pk[kk];
-        if (p == kk) continue;
-        const double a = __shfl(slot_get<NS>(y, kk >> 6), kk & 63, 64);
-        const double b = __shfl(slot_get<NS>(y, p >> 6), p & 63, 64);
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int row = lane + 64 * s;
-            if (row == kk) y[s] = b;
-            if (row == p) y[s] = a;
-        }
-    }
-    // forward substitution with the unit lower factor
-    for (int j = 0; j < n - 1; ++j) {
-        const double yj = __shfl(slot_get<NS>(y, j >> 6), j & 63, 64);
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int row = lane + 64 * s;
-            if (row > j && row < n) y[s] -= double(Mk[size_t(row) * ld + j]) * yj;
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const int row = lane + 64 * s;
-        if (row < n) {
-            yr[size_t(k) * n + row] = y[s];
-            sy[wv][row] = y[s];
-        }
+    for (int j = lane; j < n; j += 64) {
+        const int row = pk[j];
+        sr[wv][j] = -h[size_t(row & 3) * nimp * NP + size_t(k) * NP + (row >> 2)];
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int b = lane; b < m; b += 64) {
-        const T* cr = Mk + size_t(n + b) * ld;
+    const T* Mk = M + size_t(k) * N * N;
+    for (int row = lane; row < N; row += 64) {
         double acc = 0.0;
-        for (int j = 0; j < n; ++j) acc += double(cr[j]) * sy[wv][j];
-        z[size_t(k) * m + b] = acc;
+        for (int j = 0; j < n; ++j) acc += double(Mk[size_t(j) * N + row]) * sr[wv][j];
+        if (row < n) yr[size_t(k) * n + row] = acc;
+        else z[size_t(k) * m + row - n] = acc;
     }
 }
 
@@ -481,8 +624,8 @@ template <int P>
 static hipError_t launch_condense_p(const RefOps& o, const CondenseLaunch& a,
                                     hipStream_t st) {
     if (a.nimp == 0) return hipSuccess;
-    if (a.precision == HFR_PREC_FP64) return launch_lu<P, double>(o, a, st);
-    return launch_lu<P, float>(o, a, st);
+    if (a.precision == HFR_PREC_FP64) return launch_sweep<P, double>(o, a, st);
+    return launch_sweep<P, float>(o, a, st);
 }
 
 hipError_t launch_condense(const RefOps& o, const CondenseLaunch& a,

@@ -49,8 +49,7 @@ __device__ __forceinline__ float bf2f(uint16_t h) {
 template <typename T>
 __global__ void k_assemble(AssembleLaunch a) {
     const int bs = 4 * a.P;
-    const int ld = a.n + a.m + 1;
-    const size_t rows = size_t(a.n + a.m);
+    const size_t N = size_t(a.n + a.m);      // swept tableau, column-major
     const int bb = bs * bs;
     const long total = long(a.nblocks) * bb;
     const T* M = reinterpret_cast<const T*>(a.M);
@@ -70,7 +69,7 @@ __global__ void k_assemble(AssembleLaunch a) {
             const int qeb = sc ? a.P - 1 - qb : qb;
             const size_t row = a.n + (lr * a.P + qea) * 4 + va;
             const size_t col = a.n + (lc * a.P + qeb) * 4 + wb;
-            val += double(M[size_t(imp) * rows * ld + row * ld + col]);
+            val += double(M[size_t(imp) * N * N + col * N + row]);
         }
         if (a.L64) a.L64[idx] = val;
         if (a.L32) a.L32[idx] = float(val);
@@ -380,28 +379,19 @@ hipError_t launch_absmax(int N, const double* x, double* partial, int nblk,
     return hipGetLastError();
 }
 
-// ---- recovery (eq:localproblems) from the LU-condensed element matrix:
-// rows 0..n-1 hold L\U | Y_B with Y_B = L^-1 P B, and y_r = L^-1 P r comes
-// from the FP64 right-hand-side pass, so du = U^-1 (y_r - Y_B duhat_loc)
-// by back substitution.
-template <int NS>
-__device__ __forceinline__ double rslot(const double (&y)[NS], int s) {
-    double r = y[0];
-#pragma unroll
-    for (int i = 1; i < NS; ++i) r = (s == i) ? y[i] : r;
-    return r;
-}
-
-// one wave per element, four elements per workgroup; row i in lane i % 64,
-// slot i / 64
+// ---- recovery (eq:localproblems) from the swept element tableau:
+// du[k] = (A^-1 r)[k] - (A^-1 B duhat_loc)[k] = y~[p_k] + T[p_k][n:N] duhat_loc
+// with y~ from the FP64 right-hand-side pass (pivot-row order).  One wave
+// per element, four elements per workgroup; lane l computes the unknowns
+// l, l + 64, ...
 template <typename T, int P>
 __global__ __launch_bounds__(256) void k_recover(int nimp, const T* M,
+                                                 const int* piv,
                                                  const double* yr,
                                                  const int* trace_map,
                                                  const double* duhat,
                                                  double* du) {
-    constexpr int NP = P * P, n = 4 * NP, m = 16 * P, ld = n + m + 1;
-    constexpr int NS = (n + 63) / 64;
+    constexpr int NP = P * P, n = 4 * NP, m = 16 * P, N = n + m;
     __shared__ double sloc[4][m];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int k = blockIdx.x * 4 + wv;
@@ -414,61 +404,40 @@ __global__ __launch_bounds__(256) void k_recover(int nimp, const T* M,
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const T* Mk = M + size_t(k) * (n + m) * ld;
-    double y[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const int row = lane + 64 * s;
-        double acc = 0.0;
-        if (row < n) {
-            const T* xr = Mk + size_t(row) * ld + n;
-            acc = yr[size_t(k) * n + row];
-            for (int b = 0; b < m; ++b) acc -= double(xr[b]) * sloc[wv][b];
-        }
-        y[s] = acc;
-    }
-    // back substitution with U
-    for (int j = n - 1; j >= 0; --j) {
-        const double xj = __shfl(rslot<NS>(y, j >> 6), j & 63, 64) /
-                          double(Mk[size_t(j) * ld + j]);
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int row = lane + 64 * s;
-            if (row < j) y[s] -= double(Mk[size_t(row) * ld + j]) * xj;
-            if (row == j) y[s] = xj;
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const int row = lane + 64 * s;
-        if (row < n) du[size_t(row & 3) * nimp * NP + size_t(k) * NP + (row >> 2)] = y[s];
+    const T* Mk = M + size_t(k) * N * N + size_t(n) * N;
+    for (int row = lane; row < n; row += 64) {
+        const int pr = piv[size_t(k) * n + row];
+        double acc = yr[size_t(k) * n + pr];
+        for (int b = 0; b < m; ++b) acc += double(Mk[size_t(b) * N + pr]) * sloc[wv][b];
+        du[size_t(row & 3) * nimp * NP + size_t(k) * NP + (row >> 2)] = acc;
     }
 }
 
 template <typename T>
-static hipError_t launch_recover_t(int P, int nimp, const T* M, const double* yr,
+static hipError_t launch_recover_t(int P, int nimp, const T* M, const int* piv,
+                                   const double* yr,
                                    const int* trace_map, const double* duhat,
                                    double* du, hipStream_t st) {
     const dim3 grid((nimp + 3) / 4), blk(256);
     switch (P) {
-        case 2: hipLaunchKernelGGL((k_recover<T, 2>), grid, blk, 0, st, nimp, M, yr, trace_map, duhat, du); break;
-        case 3: hipLaunchKernelGGL((k_recover<T, 3>), grid, blk, 0, st, nimp, M, yr, trace_map, duhat, du); break;
-        case 4: hipLaunchKernelGGL((k_recover<T, 4>), grid, blk, 0, st, nimp, M, yr, trace_map, duhat, du); break;
-        case 5: hipLaunchKernelGGL((k_recover<T, 5>), grid, blk, 0, st, nimp, M, yr, trace_map, duhat, du); break;
-        case 6: hipLaunchKernelGGL((k_recover<T, 6>), grid, blk, 0, st, nimp, M, yr, trace_map, duhat, du); break;
+        case 2: hipLaunchKernelGGL((k_recover<T, 2>), grid, blk, 0, st, nimp, M, piv, yr, trace_map, duhat, du); break;
+        case 3: hipLaunchKernelGGL((k_recover<T, 3>), grid, blk, 0, st, nimp, M, piv, yr, trace_map, duhat, du); break;
+        case 4: hipLaunchKernelGGL((k_recover<T, 4>), grid, blk, 0, st, nimp, M, piv, yr, trace_map, duhat, du); break;
+        case 5: hipLaunchKernelGGL((k_recover<T, 5>), grid, blk, 0, st, nimp, M, piv, yr, trace_map, duhat, du); break;
+        case 6: hipLaunchKernelGGL((k_recover<T, 6>), grid, blk, 0, st, nimp, M, piv, yr, trace_map, duhat, du); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_recover(int P, int nimp, const void* M, int precision,
-                          const double* yr, const int* trace_map,
+                          const int* piv, const double* yr, const int* trace_map,
                           const double* duhat, double* du, hipStream_t st) {
     if (nimp == 0) return hipSuccess;
     if (precision == HFR_PREC_FP64)
-        return launch_recover_t(P, nimp, reinterpret_cast<const double*>(M), yr,
+        return launch_recover_t(P, nimp, reinterpret_cast<const double*>(M), piv, yr,
                                 trace_map, duhat, du, st);
-    return launch_recover_t(P, nimp, reinterpret_cast<const float*>(M), yr,
+    return launch_recover_t(P, nimp, reinterpret_cast<const float*>(M), piv, yr,
                             trace_map, duhat, du, st);
 }
 

@@ -35,7 +35,7 @@ using namespace hfr;
 struct hfr_solver_s {
     fr_mesh_t mesh = nullptr;
     hfr_opts opts{};
-    int n = 0, m = 0, ld = 0, bs = 0, N = 0, restart = 0;
+    int n = 0, m = 0, bs = 0, N = 0, restart = 0;
     size_t elem_M = 0;       // scalars per element matrix
     int nblocks = 0;
     // device
@@ -267,10 +267,8 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
 fr_status recondense_rhs_internal(hfr_solver_s* s, hipStream_t st) {
     fr_mesh_s* m = s->mesh;
     if (m->Nim == 0) return FR_OK;
-    int tk = tbegin(s, HFR_T_CONDENSE, st);
     HIP_TRY(launch_rhs64(m->P, m->Nim, s->M, s->opts.precision, s->piv, s->h,
                          s->yr, s->zz, st));
-    tend(s, tk, st);
     if (m->Ntf == 0) return FR_OK;
     AssembleLaunch a{};
     a.nblocks = 0;            // t only
@@ -285,7 +283,7 @@ fr_status recondense_rhs_internal(hfr_solver_s* s, hipStream_t st) {
     a.t = s->t;
     a.g = s->g;
     a.z = s->zz;
-    tk = tbegin(s, HFR_T_ASSEMBLE, st);
+    const int tk = tbegin(s, HFR_T_ASSEMBLE, st);
     HIP_TRY(launch_assemble(a, st));
     tend(s, tk, st);
     return FR_OK;
@@ -465,7 +463,7 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         loc.gmres_iters += ks.iterations;
         if (e && e != FR_E_NOT_CONVERGED) return e;
         tk = tbegin(s, HFR_T_RECOVER, st);
-        HIP_TRY(launch_recover(m->P, m->Nim, s->M, s->opts.precision, s->yr,
+        HIP_TRY(launch_recover(m->P, m->Nim, s->M, s->opts.precision, s->piv, s->yr,
                                m->d_trace_map, s->duhat, s->du, st));
         HIP_TRY(launch_newton_update(m->Np, m->Nim, m->Ne, m->d_imp, s->du, u,
                                      4 * m->Ntp, s->duhat, uhat, st));
@@ -507,11 +505,10 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
     const int P = m->P;
     s->n = 4 * m->Np;
     s->m = 16 * P;
-    s->ld = s->n + s->m + 1;
     s->bs = 4 * P;
     s->N = 4 * m->Ntp;
     s->restart = o->gmres_restart;
-    s->elem_M = size_t(s->n + s->m) * s->ld;
+    s->elem_M = size_t(s->n + s->m) * (s->n + s->m);
     // block-sparse structure of L: one block row per trace face; columns
     // are the trace faces of the two elements sharing it
     std::vector<int> rowptr(m->Ntf + 1, 0), col, contrib, tside(4 * size_t(m->Ntf), -1),
@@ -679,7 +676,7 @@ extern "C" fr_status hfr_recover(hfr_solver_t s, const double* duhat,
     if (!s || (!duhat && s->N) || (!du && s->mesh->Nim))
         return fail(FR_E_INVALID, "null argument");
     fr_mesh_s* m = s->mesh;
-    HIP_TRY(launch_recover(m->P, m->Nim, s->M, s->opts.precision, s->yr,
+    HIP_TRY(launch_recover(m->P, m->Nim, s->M, s->opts.precision, s->piv, s->yr,
                            m->d_trace_map, duhat, du, hipStream_t(stream)));
     return FR_OK;
 }

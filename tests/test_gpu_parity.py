@@ -111,9 +111,9 @@ def test_element_blocks_match_oracle_derivatives(name):
 @pytest.mark.parametrize("name,precision", [("c1_p2", "fp64"), ("cyl_p3", "fp64"),
                                             ("c1_p2", "fp32"), ("cyl_p4", "fp64")])
 def test_element_factorisation(name, precision):
-    """Each element's factored matrix: P A = L U, the Schur complement
-    D - C A^-1 B and s - C A^-1 r, checked with NumPy on the GPU's own
-    (oracle-verified) element blocks."""
+    """Each element's swept tableau: A^-1, -A^-1 B, C A^-1 (pivot-permuted)
+    and the Schur complement D - C A^-1 B, checked with NumPy on the GPU's
+    own (oracle-verified) element blocks."""
     pr, u = _build(name)
     hm = pr.hm
     uhat, ustar = _stage_inputs(pr, u)
@@ -123,25 +123,24 @@ def test_element_factorisation(name, precision):
     blk = torch.zeros(hm.Nim * (n + m) ** 2, dtype=torch.float64, device="cuda")
     s.get_blocks(blk)
     F, piv = s.get_factors()
-    h = torch.zeros(4 * hm.Nim * hm.Np, dtype=torch.float64, device="cuda")
-    g = torch.zeros(4 * hm.Ntp, dtype=torch.float64, device="cuda")
-    s.get_system(h=h, g=g)
     torch.cuda.synchronize()
     G = host(blk).reshape(hm.Nim, n + m, n + m)
     F = F.double().cpu().numpy()
-    piv = piv.cpu().numpy()
+    piv = piv.cpu().numpy().astype(np.int64)
     tol = 1e-10 if precision == "fp64" else 2e-4
     for k in range(hm.Nim):
+        p = piv[k]
+        assert sorted(p.tolist()) == list(range(n)), k
         A, B, C, D = G[k, :n, :n], G[k, :n, n:], G[k, n:, :n], G[k, n:, n:]
-        S = D - C @ np.linalg.solve(A, B)
-        got = F[k, n:, n:n + m]
-        assert np.abs(got - S).max() <= tol * max(1.0, np.abs(S).max()), (k, np.abs(got - S).max())
-        Lm = np.tril(F[k, :n, :n], -1) + np.eye(n)
-        Um = np.triu(F[k, :n, :n])
-        PA = A.copy()
-        for kk in range(n):
-            PA[[kk, piv[k, kk]]] = PA[[piv[k, kk], kk]]
-        assert np.abs(Lm @ Um - PA).max() <= tol * max(1.0, np.abs(A).max())
+        Ai = np.linalg.inv(A)
+        X = Ai @ B
+        W = C @ Ai
+        S = D - C @ X
+        T = F[k]
+        for got, ref in ((T[:n, :n][p, :], Ai[:, p]), (T[:n, n:][p, :], -X),
+                         (T[n:, :n], W[:, p]), (T[n:, n:], S)):
+            err = np.abs(got - ref).max()
+            assert err <= tol * max(1.0, np.abs(ref).max()), (k, err)
 
 
 def _cfl_dt(pr, lam=6.0, rings=3, n_theta=24):

@@ -106,7 +106,32 @@ def run_form(hp, torch, mesh, u0, dt, precision, precond, steps, warmup,
     return res
 
 
-def roofline(form, mesh, timers, precision):
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of the condensation kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE runs scaled by a
+    plain copy of known size), or None when the kernel sources have changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"hbm_counters_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for ln in open(path):
+        if ":" in ln and not ln.startswith(" "):
+            k, v = ln.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("condense_kernel", "").find(kernel) < 0:
+        return None
+    h = hashlib.sha256()
+    for f in ("kernels_condense.hip", "internal.h", "euler.h"):
+        with open(os.path.join(ROOT, "paper_2401_16632_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != vals.get("condense_source_sha256"):
+        return None
+    return float(vals["condense_traffic_bytes_per_launch"])
+
+
+def roofline(form, mesh, timers, precision, workload="c2"):
     n, m = 4 * mesh.Np, 16 * mesh.P
     cms, ccnt = timers["condense"]
     sms, scnt = timers["spmv"]
@@ -118,8 +143,10 @@ def roofline(form, mesh, timers, precision):
         avg = cms / max(1, ccnt) * 1e-3
         pk = PEAK["fp32_tflops"] if precision == "fp32" else PEAK["fp64_tflops"]
         ach = fl / avg / 1e12
+        traffic = (measured_traffic(workload, f"k_condense_sweep<{mesh.P}, float>")
+                   if precision == "fp32" else None)
         return dict(kernel="condense", bound="alu", achieved=ach, peak=pk,
-                    unit="TFLOP/s", frac=ach / pk, traffic=None,
+                    unit="TFLOP/s", frac=ach / pk, traffic=traffic,
                     launches=ccnt, avg_ms=avg * 1e3,
                     algorithmic_per_launch=fl)
     if dom == "spmv":
@@ -261,7 +288,7 @@ def main():
                    "implicit_dof": dof, "dt": dt,
                    "newton_tol": args.newton_tol,
                    "form": main_form},
-        "roofline": roofline(main_form, mesh, r["timers"], main_form),
+        "roofline": roofline(main_form, mesh, r["timers"], main_form, args.workload),
     }
     for f, rr in results.items():
         line[f"{f}_form"] = {

@@ -123,7 +123,7 @@ def measured_traffic(workload, kernel):
     if vals.get("condense_kernel", "").find(kernel) < 0:
         return None
     h = hashlib.sha256()
-    for f in ("kernels_condense.hip", "internal.h", "euler.h"):
+    for f in ("kernels_condense.hip", "internal.h", "euler.h", "wave_ops.h"):
         with open(os.path.join(ROOT, "paper_2401_16632_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     if h.hexdigest() != vals.get("condense_source_sha256"):

@@ -257,6 +257,12 @@ fr_status hfr_get_blocks(hfr_solver_t s, double* blocks, void* stream);
  * for j < n, b < m, i < m (element-local ordering as in hfr_get_blocks). */
 fr_status hfr_get_factors(hfr_solver_t s, void* factors, int32_t* piv,
                           void* stream);
+/* Block-Jacobi preconditioner of the last linearisation (the trace solve of
+ * Section 3.2 is preconditioned on the right by the inverses of the
+ * diagonal face blocks of L): Ntf blocks of bs x bs, bs = 4(p+1), each
+ * column-major (dinv[F][b][a] = (L_FF^-1)[a][b]), in the preconditioner
+ * precision (FP64, FP32 or BF16 bit patterns). */
+fr_status hfr_get_preconditioner(hfr_solver_t s, void* dinv, void* stream);
 
 /*
  * hfr_timing: HIP-event timers around the solver's kernels, on the stream

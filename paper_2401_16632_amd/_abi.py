@@ -15,7 +15,7 @@ EXPORTED = ["fr_mesh_create", "fr_mesh_destroy", "fr_mesh_get_info",
             "fr_mesh_get_maps", "fr_explicit_rhs", "hfr_solver_create",
             "hfr_solver_destroy", "hfr_residual", "hfr_assemble_condense",
             "hfr_trace_solve", "hfr_recover", "hfr_trace_matvec",
-            "hfr_get_system", "hfr_get_blocks", "hfr_get_factors", "hfr_timing",
+            "hfr_get_system", "hfr_get_blocks", "hfr_get_factors", "hfr_get_preconditioner", "hfr_timing",
             "imex_stage",
             "fr_last_error"]
 TIMERS = ["residual", "condense", "assemble", "pcsetup", "spmv",
@@ -100,6 +100,7 @@ def load(path=LIB_PATH):
                                  c_double, P(ImexState), P(HfrNewtonStats),
                                  c_void_p]),
         "hfr_get_factors": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+        "hfr_get_preconditioner": (c_int32, [c_void_p, c_void_p, c_void_p]),
         "hfr_timing": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
         "fr_last_error": (c_char_p, []),
     }

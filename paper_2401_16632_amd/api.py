@@ -264,6 +264,21 @@ class Solver:
         # stored column-major per element
         return f.view(m.Nim, k, k).transpose(1, 2), pv.view(m.Nim, self.n)
 
+    def get_preconditioner(self, stream=None):
+        """Block-Jacobi inverses (Ntf, bs, bs) indexed [face, row, column], as
+        float64 (BF16 blocks are widened)."""
+        m = self.mesh
+        bs = 4 * m.P
+        ntf = m.Ntp // m.P
+        pc = self.opts.precond
+        dt = {0: torch.float64, 1: torch.float32, 2: torch.int16}[pc]
+        d = torch.zeros(ntf * bs * bs, dtype=dt, device="cuda")
+        _check(load_library().hfr_get_preconditioner(
+            self.handle, ctypes.c_void_p(d.data_ptr()), _stream(stream)))
+        if pc == 2:
+            d = ((d.to(torch.int32) & 0xFFFF) << 16).view(torch.float32)
+        return d.double().view(ntf, bs, bs).transpose(1, 2)
+
     def timing(self, enable=None):
         """Start (True) / stop (False) the kernel timers; returns the
         accumulated {name: (ms, launches)} after a device sync."""

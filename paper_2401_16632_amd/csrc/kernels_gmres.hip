@@ -358,33 +358,69 @@ __global__ __launch_bounds__(kThr) void k_gmres_restart(GmresArgs a, int first) 
     }
 }
 
+__device__ __forceinline__ double load_pc(const double* d, size_t i) { return d[i]; }
+__device__ __forceinline__ double load_pc(const float* d, size_t i) { return double(d[i]); }
+__device__ __forceinline__ double load_pc(const uint16_t* d, size_t i) {
+    return double(__uint_as_float(uint32_t(d[i]) << 16));     // BF16 -> FP32
+}
+
 // ---- Lt = L Dinv (per block: Lt_FG = L_FG Dinv_G) -------------------------
-__global__ void k_precondition_matrix(int nblocks, int bs, const int* col,
-                                      const double* L64, const float* L32,
-                                      int pc, const void* Dinv, double* Lt64,
-                                      float* Lt32) {
-    const int bb = bs * bs;
-    const long total = long(nblocks) * bb;
-    for (long idx = blockIdx.x * long(blockDim.x) + threadIdx.x; idx < total;
-         idx += long(gridDim.x) * blockDim.x) {
-        const int p = int(idx) / bb;            // total < 2^31
-        const int rem = int(idx) - p * bb;
-        const int b = rem / bs, aa = rem - b * bs;
-        const size_t lb = size_t(p) * bs * bs;
-        const size_t db = size_t(col[p]) * bs * bs;
-        double acc = 0.0;
-        for (int c = 0; c < bs; ++c) {
-            const double lv = L64 ? L64[lb + size_t(c) * bs + aa] : double(L32[lb + size_t(c) * bs + aa]);
-            double dv;
-            const size_t di = db + size_t(b) * bs + c;
-            if (pc == HFR_PC_FP64) dv = reinterpret_cast<const double*>(Dinv)[di];
-            else if (pc == HFR_PC_FP32) dv = double(reinterpret_cast<const float*>(Dinv)[di]);
-            else dv = double(__uint_as_float(uint32_t(reinterpret_cast<const uint16_t*>(Dinv)[di]) << 16));
-            acc += lv * dv;
-        }
-        if (Lt64) Lt64[idx] = acc;
-        else Lt32[idx] = float(acc);
+// One wave per block, four blocks per workgroup; both factors staged in LDS
+// (FP64), each lane forms BS*BS/64 entries of the product.
+template <int BS, typename TL, typename TD>
+__global__ __launch_bounds__(256) void k_precondition_matrix(int nblocks, const int* col,
+                                                             const TL* L, const TD* Dinv,
+                                                             TL* Lt) {
+    constexpr int BB = BS * BS;
+    __shared__ double sL[4][BB], sD[4][BB];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int p = blockIdx.x * 4 + wv;
+    if (p >= nblocks) return;                      // whole wave
+    const size_t lb = size_t(p) * BB, db = size_t(col[p]) * BB;
+    for (int i = lane; i < BB; i += 64) {
+        sL[wv][i] = double(L[lb + i]);
+        sD[wv][i] = load_pc(Dinv, db + i);
     }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // entry (a, b) of the column-major product: sum_c L[a][c] Dinv[c][b]
+    for (int i = lane; i < BB; i += 64) {
+        const int b = i / BS, a = i - b * BS;
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < BS; ++c) acc = fma(sL[wv][c * BS + a], sD[wv][b * BS + c], acc);
+        Lt[lb + i] = TL(acc);
+    }
+}
+
+template <int BS, typename TL>
+static void launch_pm_t(int nblocks, const int* col, const TL* L, int pc,
+                        const void* Dinv, TL* Lt, hipStream_t st) {
+    const dim3 grid((nblocks + 3) / 4), blk(256);
+    if (pc == HFR_PC_FP64)
+        hipLaunchKernelGGL((k_precondition_matrix<BS, TL, double>), grid, blk, 0, st, nblocks, col, L,
+                           reinterpret_cast<const double*>(Dinv), Lt);
+    else if (pc == HFR_PC_FP32)
+        hipLaunchKernelGGL((k_precondition_matrix<BS, TL, float>), grid, blk, 0, st, nblocks, col, L,
+                           reinterpret_cast<const float*>(Dinv), Lt);
+    else
+        hipLaunchKernelGGL((k_precondition_matrix<BS, TL, uint16_t>), grid, blk, 0, st, nblocks, col, L,
+                           reinterpret_cast<const uint16_t*>(Dinv), Lt);
+}
+
+template <typename TL>
+static hipError_t launch_pm(int nblocks, int bs, const int* col, const TL* L, int pc,
+                            const void* Dinv, TL* Lt, hipStream_t st) {
+    switch (bs) {
+        case 8: launch_pm_t<8>(nblocks, col, L, pc, Dinv, Lt, st); break;
+        case 12: launch_pm_t<12>(nblocks, col, L, pc, Dinv, Lt, st); break;
+        case 16: launch_pm_t<16>(nblocks, col, L, pc, Dinv, Lt, st); break;
+        case 20: launch_pm_t<20>(nblocks, col, L, pc, Dinv, Lt, st); break;
+        case 24: launch_pm_t<24>(nblocks, col, L, pc, Dinv, Lt, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_precondition_matrix(int nblocks, int bs, const int* col,
@@ -392,11 +428,8 @@ hipError_t launch_precondition_matrix(int nblocks, int bs, const int* col,
                                       int pc, const void* Dinv, double* Lt64,
                                       float* Lt32, hipStream_t st) {
     if (nblocks == 0) return hipSuccess;
-    long total = long(nblocks) * bs * bs;
-    int grid = int(std::min<long>((total + 255) / 256, 65536));
-    hipLaunchKernelGGL(k_precondition_matrix, dim3(grid), dim3(256), 0, st,
-                       nblocks, bs, col, L64, L32, pc, Dinv, Lt64, Lt32);
-    return hipGetLastError();
+    if (L64) return launch_pm<double>(nblocks, bs, col, L64, pc, Dinv, Lt64, st);
+    return launch_pm<float>(nblocks, bs, col, L32, pc, Dinv, Lt32, st);
 }
 
 hipError_t launch_gmres_restart(const GmresArgs& a, const double* x,

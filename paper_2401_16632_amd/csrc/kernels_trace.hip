@@ -5,6 +5,7 @@
 // kernels, local recovery (eq:localproblems), Newton updates, and the IMEX
 // stage combinations (eq:explicitimex and the final update).
 #include "internal.h"
+#include "wave_ops.h"
 
 namespace hfr {
 
@@ -104,68 +105,58 @@ hipError_t launch_assemble(const AssembleLaunch& a, hipStream_t st) {
 }
 
 // ---- block-Jacobi: invert the diagonal block of every trace face -------
-// One wave per face; Gauss-Jordan with partial pivoting on [Dblk | I] in LDS.
-__global__ void k_block_inverse(int ntf, int bs, const int* diag_blk,
-                                const double* L64, const float* L32, int pc,
-                                void* out, int* fail) {
-    __shared__ double W[24][49];
-    __shared__ int piv_s;
-    const int F = blockIdx.x;
-    const int t = threadIdx.x;
-    const size_t blk = size_t(diag_blk[F]) * bs * bs;
-    for (int idx = t; idx < bs * 2 * bs; idx += blockDim.x) {
-        const int r = idx / (2 * bs), c = idx % (2 * bs);
-        double v;
-        if (c < bs) v = L64 ? L64[blk + size_t(c) * bs + r] : double(L32[blk + size_t(c) * bs + r]);
-        else v = (c - bs == r) ? 1.0 : 0.0;
-        W[r][c] = v;
+// One wave per face, four faces per workgroup: lane r holds row r of the
+// BS x BS block in registers and BS Jordan exchanges with partial pivoting
+// (wave-wide DPP argmax, pivot row by v_readlane) turn it into the inverse
+// with row and column permutations, T[p_k][j] = Inv[k][p_j]; pivot rows are
+// kept unscaled with their factor -1/pivot applied at the store.
+template <int BS>
+__global__ __launch_bounds__(256) void k_block_inverse(int ntf, const int* diag_blk,
+                                                       const double* L64,
+                                                       const float* L32, int pc,
+                                                       void* out, int* fail) {
+    const int lane = threadIdx.x & 63;
+    const int F = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (F >= ntf) return;                          // whole wave
+    const size_t blk = size_t(diag_blk[F]) * BS * BS;
+    double t[BS];
+#pragma unroll
+    for (int c = 0; c < BS; ++c) {
+        const size_t i = blk + size_t(c) * BS + min(lane, BS - 1);   // in bounds
+        const double v = L64 ? L64[i] : double(L32[i]);
+        t[c] = lane < BS ? v : 0.0;
     }
-    __syncthreads();
-    for (int k = 0; k < bs; ++k) {
-        {
-            double best = (t >= k && t < bs) ? fabs(W[t][k]) : -1.0;
-            int p = (t >= k && t < bs) ? t : 0x7fffffff;
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ob = __shfl_xor(best, off, 64);
-                const int oi = __shfl_xor(p, off, 64);
-                if (ob > best || (ob == best && oi < p)) { best = ob; p = oi; }
-            }
-            if (t == 0) piv_s = (best > 0.0) ? p : -1;
+    double sig = 1.0;
+    bool used = lane >= BS;
+    int pos = 0;
+    int pj[BS];
+#pragma unroll
+    for (int k = 0; k < BS; ++k) {
+        const unsigned long long key =
+            wave_max_key(used ? 0ull : pivot_key(float(fabs(t[k])), lane));
+        if ((key >> 32) == 0) {
+            if (lane == 0) *fail = 1;
+            return;                                // uniform
         }
-        __syncthreads();
-        const int p = piv_s;
-        if (p < 0) {
-            if (t == 0) *fail = 1;
-            return;
-        }
-        if (p != k)
-            for (int c = t; c < 2 * bs; c += blockDim.x) {
-                const double x = W[k][c];
-                W[k][c] = W[p][c];
-                W[p][c] = x;
-            }
-        __syncthreads();
-        const double inv = 1.0 / W[k][k];
-        __syncthreads();
-        for (int c = t; c < 2 * bs; c += blockDim.x) W[k][c] *= inv;
-        __syncthreads();
-        for (int idx = t; idx < bs * 2 * bs; idx += blockDim.x) {
-            const int r = idx / (2 * bs), c = idx % (2 * bs);
-            if (r != k && c != k) W[r][c] -= W[r][k] * W[k][c];
-        }
-        __syncthreads();
-        for (int r = t; r < bs; r += blockDim.x)
-            if (r != k) W[r][k] = 0.0;
-        __syncthreads();
+        const int p = __builtin_amdgcn_readfirstlane(int(0xffffffffu - unsigned(key)));
+        pj[k] = p;
+        const double ipv = 1.0 / lane_value(t[k], p);
+        const double g = (lane == p) ? 0.0 : t[k] * ipv;
+#pragma unroll
+        for (int j = 0; j < BS; ++j) t[j] = fma(-g, lane_value(t[j], p), t[j]);
+        t[k] = (lane == p) ? -1.0 : g;
+        if (lane == p) { used = true; sig = -ipv; pos = k; }
     }
-    // store inverse column-major: out[F][b][a] = Inv[a][b]
-    for (int idx = t; idx < bs * bs; idx += blockDim.x) {
-        const int b = idx / bs, aa = idx % bs;
-        const double v = W[aa][bs + b];
-        const size_t o = size_t(F) * bs * bs + idx;
-        if (pc == HFR_PC_FP64) reinterpret_cast<double*>(out)[o] = v;
-        else if (pc == HFR_PC_FP32) reinterpret_cast<float*>(out)[o] = float(v);
-        else reinterpret_cast<uint16_t*>(out)[o] = f2bf(float(v));
+    // store column-major: out[F][b][a] = Inv[a][b], Inv[pos][p_j] = sig t[j]
+    if (lane >= BS) return;
+    const size_t o = size_t(F) * BS * BS + pos;
+#pragma unroll
+    for (int j = 0; j < BS; ++j) {
+        const double v = sig * t[j];
+        const size_t i = o + size_t(pj[j]) * BS;
+        if (pc == HFR_PC_FP64) reinterpret_cast<double*>(out)[i] = v;
+        else if (pc == HFR_PC_FP32) reinterpret_cast<float*>(out)[i] = float(v);
+        else reinterpret_cast<uint16_t*>(out)[i] = f2bf(float(v));
     }
 }
 
@@ -174,9 +165,15 @@ hipError_t launch_block_inverse_impl(int ntf, int bs, const int* diag_blk,
                                      int pc, void* out, int* fail,
                                      hipStream_t st) {
     if (ntf == 0) return hipSuccess;
-    if (bs > 24) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_block_inverse, dim3(ntf), dim3(64), 0, st, ntf, bs,
-                       diag_blk, L64, L32, pc, out, fail);
+    const dim3 grid((ntf + 3) / 4), blk(256);
+    switch (bs) {
+        case 8: hipLaunchKernelGGL(k_block_inverse<8>, grid, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
+        case 12: hipLaunchKernelGGL(k_block_inverse<12>, grid, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
+        case 16: hipLaunchKernelGGL(k_block_inverse<16>, grid, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
+        case 20: hipLaunchKernelGGL(k_block_inverse<20>, grid, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
+        case 24: hipLaunchKernelGGL(k_block_inverse<24>, grid, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

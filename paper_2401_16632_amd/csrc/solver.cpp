@@ -731,6 +731,18 @@ extern "C" fr_status hfr_get_factors(hfr_solver_t s, void* factors,
     return FR_OK;
 }
 
+extern "C" fr_status hfr_get_preconditioner(hfr_solver_t s, void* dinv,
+                                            void* stream) {
+    if (!s || !dinv) return fail(FR_E_INVALID, "null argument");
+    fr_mesh_s* m = s->mesh;
+    const int pc = s->opts.precond;
+    const size_t scal = pc == HFR_PC_FP64 ? 8 : pc == HFR_PC_FP32 ? 4 : 2;
+    if (m->Ntf)
+        HIP_TRY(hipMemcpyAsync(dinv, s->Dinv, size_t(m->Ntf) * s->bs * s->bs * scal,
+                               hipMemcpyDeviceToDevice, hipStream_t(stream)));
+    return FR_OK;
+}
+
 extern "C" fr_status imex_stage(fr_mesh_t mesh, hfr_solver_t s,
                                 const imex_tableau* tab, int32_t stage,
                                 double dt, const imex_state* stt,

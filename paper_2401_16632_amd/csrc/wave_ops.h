@@ -1,0 +1,49 @@
+// Wave-level helpers shared by the element sweep and the block-Jacobi
+// inverse: uniform-lane reads and a wave-wide argmax by DPP.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace hfr {
+
+__device__ __forceinline__ float lane_value(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ double lane_value(double x, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Wave-wide maximum of a 64-bit key by DPP row operations (quad swaps,
+// half-row and row mirrors, then the row broadcasts 15 and 31); the
+// maximum ends in lane 63.
+__device__ __forceinline__ unsigned long long key_max(unsigned long long a,
+                                                      unsigned long long b) {
+    return a > b ? a : b;
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ unsigned long long key_dpp(unsigned long long x) {
+    const int lo = int(unsigned(x)), hi = int(unsigned(x >> 32));
+    const unsigned l2 = unsigned(__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xf, false));
+    const unsigned h2 = unsigned(__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xf, false));
+    return (static_cast<unsigned long long>(h2) << 32) | l2;
+}
+__device__ __forceinline__ unsigned long long wave_max_key(unsigned long long x) {
+    x = key_max(x, key_dpp<0xb1, 0xf>(x));      // quad_perm [1,0,3,2]
+    x = key_max(x, key_dpp<0x4e, 0xf>(x));      // quad_perm [2,3,0,1]
+    x = key_max(x, key_dpp<0x141, 0xf>(x));     // row_half_mirror
+    x = key_max(x, key_dpp<0x140, 0xf>(x));     // row_mirror
+    x = key_max(x, key_dpp<0x142, 0xa>(x));     // row_bcast:15
+    x = key_max(x, key_dpp<0x143, 0xc>(x));     // row_bcast:31
+    const int lo = __builtin_amdgcn_readlane(int(unsigned(x)), 63);
+    const int hi = __builtin_amdgcn_readlane(int(unsigned(x >> 32)), 63);
+    return (static_cast<unsigned long long>(unsigned(hi)) << 32) | unsigned(lo);
+}
+// pivot key: |value| (as FP32, order-preserving bits) above the complement
+// of the row, so the maximum is the largest magnitude with the lowest row
+__device__ __forceinline__ unsigned long long pivot_key(float mag, int row) {
+    return (static_cast<unsigned long long>(__float_as_uint(mag)) << 32) |
+           (0xffffffffu - unsigned(row));
+}
+
+}  // namespace hfr

@@ -143,6 +143,31 @@ def test_element_factorisation(name, precision):
             assert err <= tol * max(1.0, np.abs(ref).max()), (k, err)
 
 
+@pytest.mark.parametrize("name,precision,precond,tol", [
+    ("c1_p2", "fp64", "fp64", 1e-13), ("cyl_p3", "fp64", "fp64", 1e-13),
+    ("cyl_p3", "fp32", "fp32", 1e-6), ("cyl_p3", "fp32", "bf16", 1e-2),
+    ("cyl_p4", "fp64", "fp64", 1e-13)])
+def test_block_jacobi_inverse(name, precision, precond, tol):
+    """The preconditioner blocks invert the oracle's diagonal face blocks of
+    L: backward error |X D - I| / (bs |X| |D|) within a few units of the
+    coarsest precision involved (L stored in FP32 in the FP32 form, the
+    inverse rounded to FP32 or BF16)."""
+    pr, u = _build(name)
+    om, hm = pr.om, pr.hm
+    uhat, ustar = _stage_inputs(pr, u)
+    a = 0.05
+    sysd = onw.condense(om, pr.ph, u, uhat, ustar, a)
+    s = hp.Solver(hm, precision=precision, precond=precond)
+    s.assemble_condense(dev(soa(u)), dev(uhat), dev(soa(ustar)), a)
+    X = s.get_preconditioner().cpu().numpy()
+    L = sysd["L"].tocsr()
+    bs = 4 * pr.P
+    for F in range(X.shape[0]):
+        D = L[F * bs:(F + 1) * bs, F * bs:(F + 1) * bs].toarray()
+        err = np.abs(X[F] @ D - np.eye(bs)).max()
+        assert err <= tol * bs * np.abs(X[F]).max() * np.abs(D).max(), (F, err)
+
+
 def _cfl_dt(pr, lam=6.0, rings=3, n_theta=24):
     """Time step of the local-CFL rule (CFL = 1 between the last implicit
     and the first explicit ring)."""

@@ -218,12 +218,26 @@ __device__ __forceinline__ double aug_entry(int r, int c, int k,
 // pivot and the multipliers and passes them to the other waves through LDS
 // (one barrier per step); each wave broadcasts its own segment of the pivot
 // row through LDS.  The result is stored column-major, (N x N) per element.
-// Waves per element: the smallest power of two that keeps the register
-// tableau within about 72 values per lane (more waves shorten the
-// per-element critical path and raise occupancy), at most 8 (512 lanes).
+// Register shape of the sweep.  Columns of a wave are held as vectors of
+// CH values (CH in {4, 8, 16}, the one that pads the wave's column count
+// least) so that the column addressed by the wave-uniform step index is
+// reached by VGPR indexing.  W, the waves per element, is the smallest
+// power of two (at most 16) that keeps the tableau share of a lane within
+// about 72 VGPRs: more waves shorten the per-element critical path and
+// raise occupancy.
+constexpr int sweep_ch(int ncw) {
+    int best = 16, pad = (ncw + 15) / 16 * 16;
+    for (int c = 8; c >= 4; c /= 2)
+        if ((ncw + c - 1) / c * c < pad) { best = c; pad = (ncw + c - 1) / c * c; }
+    return best;
+}
+constexpr int sweep_regs(int rpl, int N, int w, int words) {
+    const int ncw = (N + w - 1) / w, ch = sweep_ch(ncw);
+    return rpl * ((ncw + ch - 1) / ch * ch) * words;
+}
 constexpr int sweep_waves(int rpl, int N, int words) {
     int w = 1;
-    while (rpl * ((N + w - 1) / w) * words > 72 && w < 8) w *= 2;
+    while (sweep_regs(rpl, N, w, words) > 72 && w < 16) w *= 2;
     return w;
 }
 
@@ -233,11 +247,11 @@ struct SweepShape {
     static constexpr int RPL = (N + 63) / 64;
     static constexpr int W = sweep_waves(RPL, N, int(sizeof(T) / 4));
     static constexpr int NCW = (N + W - 1) / W;
-    // register columns are held as vectors of CH values so that the one
-    // column addressed by the (wave-uniform) step index is reached by VGPR
-    // indexing instead of a select over every column
-    static constexpr int CH = sizeof(T) == 8 ? 8 : 16;
+    static constexpr int CH = sweep_ch(NCW);
     static constexpr int NCH = (NCW + CH - 1) / CH;
+    // occupancy the register budget is held to: four waves per SIMD (at
+    // most 128 VGPRs) whenever the tableau share fits, else two
+    static constexpr int WPE = RPL * NCH * CH * int(sizeof(T) / 4) <= 80 ? 4 : 2;
 };
 
 // ---- fill of the element tableau ------------------------------------------
@@ -325,7 +339,8 @@ __device__ __forceinline__ double tableau_entry(const RowDesc& d, int col,
 }
 
 template <int P, typename T>
-__global__ __launch_bounds__((64 * SweepShape<P, T>::W)) void k_condense_sweep(
+__global__ __launch_bounds__((64 * SweepShape<P, T>::W))
+__attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_sweep(
     CondenseLaunch a, RefOps og) {
     using S = SweepShape<P, T>;
     constexpr int n = S::n, N = S::N, RPL = S::RPL, W = S::W, NCW = S::NCW;
@@ -345,6 +360,7 @@ __global__ __launch_bounds__((64 * SweepShape<P, T>::W)) void k_condense_sweep(
     // output slot by a rolled loop and read back into registers by the same
     // lanes (same addresses, so no synchronisation is needed)
     constexpr int CH = S::CH, NCH = S::NCH;
+    constexpr int SPN = (n + 63) / 64;      // row slots that can hold pivot rows
     typedef T VT __attribute__((ext_vector_type(CH)));
     const int c0 = __builtin_amdgcn_readfirstlane(w * NCW);
     T* G = reinterpret_cast<T*>(a.M) + size_t(k) * N * N;
@@ -391,7 +407,7 @@ __global__ __launch_bounds__((64 * SweepShape<P, T>::W)) void k_condense_sweep(
     auto find_pivot = [&](const T (&col)[RPL], int step, T (&g)[RPL], T& ip, int& pp) {
         unsigned long long key = 0;
 #pragma unroll
-        for (int s = 0; s < RPL; ++s) {
+        for (int s = 0; s < SPN; ++s) {
             const int row = lane + 64 * s;
             const unsigned long long ks = pivot_key(float(fabs(col[s])), row);
             if (row < n && !used[s] && ks > key) key = ks;
@@ -404,8 +420,8 @@ __global__ __launch_bounds__((64 * SweepShape<P, T>::W)) void k_condense_sweep(
             const int sp = pp >> 6, lp = pp & 63;
             T pv = T(1);
 #pragma unroll
-            for (int s = 0; s < RPL; ++s)
-                if (s == sp) pv = lane_value(col[s], lp);
+            for (int s = 0; s < SPN; ++s)
+                if (SPN == 1 || s == sp) pv = lane_value(col[s], lp);
             ip = T(1) / pv;
         }
 #pragma unroll
@@ -463,8 +479,8 @@ __global__ __launch_bounds__((64 * SweepShape<P, T>::W)) void k_condense_sweep(
                 }
             T u1 = T(0);
 #pragma unroll
-            for (int s = 0; s < RPL; ++s)
-                if (s == sp) u1 = lane_value(cpre[s], lp);
+            for (int s = 0; s < SPN; ++s)
+                if (SPN == 1 || s == sp) u1 = lane_value(cpre[s], lp);
             T col1[RPL];
 #pragma unroll
             for (int s = 0; s < RPL; ++s) col1[s] = fma(-gs[s], u1, cpre[s]);
@@ -472,17 +488,20 @@ __global__ __launch_bounds__((64 * SweepShape<P, T>::W)) void k_condense_sweep(
         }
         // rank-1 update of this wave's columns; the pivot row segment comes
         // from the lane holding row p (uniform lane and slot)
+        T u[NCW];
 #pragma unroll
-        for (int s0 = 0; s0 < RPL; ++s0)
-            if (s0 == sp) {
+        for (int j = 0; j < NCW; ++j) {
+            T src = t[0][j / CH][j % CH];
 #pragma unroll
-                for (int j = 0; j < NCW; ++j) {
-                    const T uj = lane_value(t[s0][j / CH][j % CH], lp);
+            for (int s0 = 1; s0 < SPN; ++s0) src = (sp == s0) ? t[s0][j / CH][j % CH] : src;
+            u[j] = lane_value(src, lp);
+        }
 #pragma unroll
-                    for (int s = 0; s < RPL; ++s)
-                        t[s][j / CH][j % CH] = fma(-gs[s], uj, t[s][j / CH][j % CH]);
-                }
-            }
+        for (int j = 0; j < NCW; ++j) {
+#pragma unroll
+            for (int s = 0; s < RPL; ++s)
+                t[s][j / CH][j % CH] = fma(-gs[s], u[j], t[s][j / CH][j % CH]);
+        }
         // column k: multipliers for the other rows, -1 in the pivot row
         if (w == ow) {
             const int ck = jk / CH, ek = jk - ck * CH;

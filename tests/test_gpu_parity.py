@@ -26,6 +26,8 @@ def _pairs():
         "pert_p3": (d2, 3, m2, "vortex"),
         "cyl_p3": (d3, 3, m3, "cyl"),
         "cyl_p4": (d3, 4, m3, "cyl"),
+        "c1_p1": (d1, 1, m1, "vortex"),
+        "c1_p5": (d1, 5, m1, "vortex"),
     }
 
 
@@ -83,7 +85,7 @@ def test_hfr_residual(name):
     assert np.abs(host(g).reshape(-1, 4) - g_o).max() <= 1e-12 * max(1.0, np.abs(g_o).max())
 
 
-@pytest.mark.parametrize("name", ["c1_p2", "cyl_p3"])
+@pytest.mark.parametrize("name", ["c1_p2", "cyl_p3", "c1_p1"])
 def test_element_blocks_match_oracle_derivatives(name):
     pr, u = _build(name)
     om, hm = pr.om, pr.hm
@@ -109,7 +111,10 @@ def test_element_blocks_match_oracle_derivatives(name):
 
 
 @pytest.mark.parametrize("name,precision", [("c1_p2", "fp64"), ("cyl_p3", "fp64"),
-                                            ("c1_p2", "fp32"), ("cyl_p4", "fp64")])
+                                            ("c1_p2", "fp32"), ("cyl_p4", "fp64"),
+                                            ("cyl_p4", "fp32"), ("c1_p1", "fp64"),
+                                            ("c1_p1", "fp32"), ("c1_p5", "fp64"),
+                                            ("c1_p5", "fp32")])
 def test_element_factorisation(name, precision):
     """Each element's swept tableau: A^-1, -A^-1 B, C A^-1 (pivot-permuted)
     and the Schur complement D - C A^-1 B, checked with NumPy on the GPU's

@@ -274,7 +274,7 @@ fr_status hfr_get_preconditioner(hfr_solver_t s, void* dinv, void* stream);
  * a device synchronisation.
  */
 enum { HFR_T_RESIDUAL = 0,   /* hybridized residual kernel                 */
-       HFR_T_CONDENSE = 1,   /* element tableau fill + Jordan sweep kernel */
+       HFR_T_CONDENSE = 1,   /* element Jordan sweep kernel (condensation) */
        HFR_T_ASSEMBLE = 2,   /* block-sparse assembly kernel               */
        HFR_T_PCSETUP = 3,    /* block-Jacobi inversion kernel              */
        HFR_T_SPMV = 4,       /* Arnoldi product kernel (block-sparse
@@ -282,7 +282,8 @@ enum { HFR_T_RESIDUAL = 0,   /* hybridized residual kernel                 */
        HFR_T_TRACE_SOLVE = 5,/* whole trace solve (all Krylov kernels)     */
        HFR_T_RECOVER = 6,    /* local recovery kernel                      */
        HFR_T_EXPLICIT = 7,   /* explicit residual kernel (via imex_stage)  */
-       HFR_NTIMERS = 8 };
+       HFR_T_FILL = 8,       /* element linearisation + tableau fill kernel */
+       HFR_NTIMERS = 9 };
 fr_status hfr_timing(hfr_solver_t s, int32_t enable, double* ms,
                      int64_t* counts);
 

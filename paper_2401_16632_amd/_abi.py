@@ -19,7 +19,7 @@ EXPORTED = ["fr_mesh_create", "fr_mesh_destroy", "fr_mesh_get_info",
             "imex_stage",
             "fr_last_error"]
 TIMERS = ["residual", "condense", "assemble", "pcsetup", "spmv",
-          "trace_solve", "recover", "explicit"]
+          "trace_solve", "recover", "explicit", "fill"]
 
 
 class FrMeshDesc(Structure):

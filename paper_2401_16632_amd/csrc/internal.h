@@ -95,6 +95,10 @@ struct CondenseLaunch {
     int* pivot_fail;         // set to 1 if a zero pivot is met
     int* piv;                // [Nim][n] pivot row p_k of each exchange
 };
+// element linearisation and the tableau [A B; C D] (must precede
+// launch_condense, which sweeps the tableau in place)
+hipError_t launch_tableau_fill(const RefOps& ops, const CondenseLaunch& a,
+                               hipStream_t st);
 hipError_t launch_condense(const RefOps& ops, const CondenseLaunch& a,
                            hipStream_t st);
 // FP64 right-hand side with the swept tableau: A^-1 (-h) in pivot-row order

@@ -255,87 +255,135 @@ struct SweepShape {
 };
 
 // ---- fill of the element tableau ------------------------------------------
-// Lane-side description of one tableau row (an element unknown or a trace
-// unknown); the column is uniform over the wave.
-struct RowDesc {
-    int row, i, j, v, f, q;
-    bool tr;                   // trace row on a face of the trace
-    double cij, wq;
-};
-
+// One workgroup per implicit element forms the element linearisation in LDS
+// and writes [A B; C D] (exact derivatives, FP64, rounded to T) to the
+// element's tableau slot, column-major, one 4x4 point block per thread:
+// rows of an element point (or trace point) against the columns of another.
+// Consecutive threads take consecutive row blocks of one block column, so
+// every 16- or 32-byte store of a block column is contiguous.
 template <int P>
-__device__ __forceinline__ RowDesc row_desc(int row, const RefOps& o,
-                                            const CondShared<P>& sh) {
-    constexpr int NP = P * P, n = 4 * NP;
-    RowDesc d;
-    d.row = row;
-    d.i = d.j = d.v = d.f = d.q = 0;
-    d.tr = false;
-    d.cij = d.wq = 0.0;
-    if (row < n) {
-        const int pr = row >> 2;
-        d.v = row & 3;
-        d.i = pr % P;
-        d.j = pr / P;
-        d.cij = sh.c[pr];
-    } else if (row < n + 16 * P) {
-        const int b = row - n;
-        d.f = b / (4 * P);
-        d.q = (b >> 2) % P;
-        d.v = b & 3;
-        d.wq = o.w[d.q];
-        d.tr = sh.tr[d.f] != 0;
+__device__ __forceinline__ void block_entries(int br, int bc, const RefOps& o,
+                                              const CondShared<P>& sh,
+                                              double E[4][4]) {
+    constexpr int NP = P * P;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) E[v][c] = 0.0;
+    if (br < NP) {
+        const int i = br % P, j = br / P;
+        const double cij = sh.c[br];
+        if (bc < NP) {
+            const int l = bc % P, kk = bc / P;
+            // d(R)/du contributions of the row line (kk == j) and the column
+            // line (l == i) through the volume derivative and the lifted
+            // face corrections
+            double a1 = 0, b1 = 0, c1 = 0, a2 = 0, b2 = 0, c2 = 0;
+            if (kk == j) {
+                b1 = o.cr[i] * o.lp[l];
+                c1 = o.cl[i] * o.lm[l];
+                a1 = o.D[i * P + l] - b1 + c1;
+            }
+            if (l == i) {
+                b2 = o.cl[j] * o.lm[kk];
+                c2 = o.cr[j] * o.lp[kk];
+                a2 = o.D[j * P + kk] + b2 - c2;
+            }
+            if (kk == j || l == i) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int z = v * 4 + c;
+                        double acc = 0.0;
+                        if (kk == j)
+                            acc += a1 * sh.Af[bc][z] + b1 * sh.Fu[1 * P + j][z] +
+                                   c1 * sh.Fu[3 * P + (P - 1 - j)][z];
+                        if (l == i)
+                            acc += a2 * sh.Ag[bc][z] + b2 * sh.Fu[0 * P + i][z] +
+                                   c2 * sh.Fu[2 * P + (P - 1 - i)][z];
+                        E[v][c] = cij * acc;
+                    }
+            }
+            if (bc == br)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) E[v][v] += 1.0;
+        } else {
+            const int tb = bc - NP, f2 = tb / P, q2 = tb % P;
+            if (!sh.tr[f2]) return;
+            double coef = 0.0;
+            if (f2 == 1) { if (q2 == j) coef = o.cr[i]; }
+            else if (f2 == 3) { if (q2 == P - 1 - j) coef = o.cl[i]; }
+            else if (f2 == 0) { if (q2 == i) coef = o.cl[j]; }
+            else { if (q2 == P - 1 - i) coef = o.cr[j]; }
+            if (coef == 0.0) return;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) E[v][c] = cij * coef * sh.Fh[tb][v * 4 + c];
+        }
+    } else {
+        const int ta = br - NP, f = ta / P, q = ta % P;
+        if (!sh.tr[f]) {
+            if (bc == br)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) E[v][v] = 1.0;
+            return;
+        }
+        const double wq = o.w[q];
+        if (bc < NP) {
+            const int l = bc % P, kk = bc / P;
+            double coef = 0.0;
+            if (f == 1) { if (kk == q) coef = o.lp[l]; }
+            else if (f == 3) { if (kk == P - 1 - q) coef = o.lm[l]; }
+            else if (f == 0) { if (l == q) coef = o.lm[kk]; }
+            else { if (l == P - 1 - q) coef = o.lp[kk]; }
+            if (coef == 0.0) return;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) E[v][c] = wq * coef * sh.Fu[ta][v * 4 + c];
+        } else if (bc == br) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) E[v][c] = wq * sh.Fh[ta][v * 4 + c];
+        }
     }
-    return d;
 }
 
-// entry (d.row, col) of [A B; C D] (exact derivatives, FP64)
-template <int P>
-__device__ __forceinline__ double tableau_entry(const RowDesc& d, int col,
-                                                const RefOps& o,
-                                                const CondShared<P>& sh) {
-    constexpr int NP = P * P, n = 4 * NP, N = n + 16 * P;
-    if (d.row >= N) return 0.0;
-    const int i = d.i, j = d.j, v = d.v;
-    if (col < n) {
-        const int pc = col >> 2, w = col & 3, l = pc % P, kk = pc / P;
-        if (d.row < n) {
-            const double af = sh.Af[pc][v * 4 + w];
-            const double ag = sh.Ag[pc][v * 4 + w];
-            double acc = 0.0;
-            if (kk == j)
-                acc += o.D[i * P + l] * af +
-                       o.cr[i] * o.lp[l] * (sh.Fu[1 * P + j][v * 4 + w] - af) +
-                       o.cl[i] * o.lm[l] * (sh.Fu[3 * P + (P - 1 - j)][v * 4 + w] + af);
-            if (l == i)
-                acc += o.D[j * P + kk] * ag +
-                       o.cl[j] * o.lm[kk] * (sh.Fu[0 * P + i][v * 4 + w] + ag) +
-                       o.cr[j] * o.lp[kk] * (sh.Fu[2 * P + (P - 1 - i)][v * 4 + w] - ag);
-            return (d.row == col ? 1.0 : 0.0) + d.cij * acc;
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_tableau_fill(CondenseLaunch a, RefOps og) {
+    constexpr int NP = P * P, n = 4 * NP, m = 16 * P, N = n + m, NB = NP + 4 * P;
+    __shared__ CondShared<P> sh;
+    __shared__ RefOps o;
+    const int k = blockIdx.x;
+    if (threadIdx.x == 0) o = og;
+    __syncthreads();
+    element_linearisation<P>(a, o, k, sh);
+    T* G = reinterpret_cast<T*>(a.M) + size_t(k) * N * N;
+    double* bcopy = a.blocks_copy ? a.blocks_copy + size_t(k) * N * N : nullptr;
+    for (int blk = threadIdx.x; blk < NB * NB; blk += blockDim.x) {
+        const int bc = blk / NB, br = blk - bc * NB;
+        double E[4][4];
+        block_entries<P>(br, bc, o, sh, E);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            T col[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) col[v] = T(E[v][c]);
+            T* dst = G + size_t(4 * bc + c) * N + 4 * br;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dst[v] = col[v];
         }
-        if (!d.tr) return 0.0;
-        const int f = d.f, q = d.q;
-        double coef = 0.0;
-        if (f == 1) { if (kk == q) coef = o.lp[l]; }
-        else if (f == 3) { if (kk == P - 1 - q) coef = o.lm[l]; }
-        else if (f == 0) { if (l == q) coef = o.lm[kk]; }
-        else { if (l == P - 1 - q) coef = o.lp[kk]; }
-        return d.wq * coef * sh.Fu[f * P + q][v * 4 + w];
+        if (bcopy) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    bcopy[size_t(4 * br + v) * N + 4 * bc + c] = E[v][c];
+        }
     }
-    const int b2 = col - n, f2 = b2 / (4 * P), q2 = (b2 >> 2) % P, w2 = b2 & 3;
-    if (d.row < n) {
-        if (!sh.tr[f2]) return 0.0;
-        double coef = 0.0;
-        if (f2 == 1) { if (q2 == j) coef = o.cr[i]; }
-        else if (f2 == 3) { if (q2 == P - 1 - j) coef = o.cl[i]; }
-        else if (f2 == 0) { if (q2 == i) coef = o.cl[j]; }
-        else { if (q2 == P - 1 - i) coef = o.cr[j]; }
-        return d.cij * coef * sh.Fh[f2 * P + q2][v * 4 + w2];
-    }
-    const int b = d.row - n;
-    if (!d.tr) return (b == b2) ? 1.0 : 0.0;
-    if ((b >> 2) != (b2 >> 2)) return 0.0;
-    return d.wq * sh.Fh[d.f * P + d.q][v * 4 + w2];
 }
 
 template <int P, typename T>
@@ -344,42 +392,19 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
     CondenseLaunch a, RefOps og) {
     using S = SweepShape<P, T>;
     constexpr int n = S::n, N = S::N, RPL = S::RPL, W = S::W, NCW = S::NCW;
-    __shared__ CondShared<P> sh;
-    __shared__ RefOps o;
     __shared__ T gbuf[2][RPL * 64];
     __shared__ T ibuf[2];
     __shared__ int pbuf[2];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int k = blockIdx.x;
-    if (threadIdx.x == 0) o = og;
-    __syncthreads();
-    element_linearisation<P>(a, o, k, sh);
 
-    // ---- fill: entries in FP64, rounded to T, written to this element's
-    // output slot by a rolled loop and read back into registers by the same
-    // lanes (same addresses, so no synchronisation is needed)
+    // ---- load this wave's columns of the filled tableau (column-major)
     constexpr int CH = S::CH, NCH = S::NCH;
     constexpr int SPN = (n + 63) / 64;      // row slots that can hold pivot rows
     typedef T VT __attribute__((ext_vector_type(CH)));
     const int c0 = __builtin_amdgcn_readfirstlane(w * NCW);
     T* G = reinterpret_cast<T*>(a.M) + size_t(k) * N * N;
-    double* bcopy = a.blocks_copy ? a.blocks_copy + size_t(k) * N * N : nullptr;
-    RowDesc rd[RPL];
-#pragma unroll
-    for (int s = 0; s < RPL; ++s) rd[s] = row_desc<P>(lane + 64 * s, o, sh);
-#pragma unroll 4
-    for (int j = 0; j < NCW; ++j) {
-        const int col = c0 + j;
-        if (col >= N) break;
-#pragma unroll
-        for (int s = 0; s < RPL; ++s) {
-            if (rd[s].row >= N) continue;
-            const double v = tableau_entry<P>(rd[s], col, o, sh);
-            G[size_t(col) * N + rd[s].row] = T(v);
-            if (bcopy) bcopy[size_t(rd[s].row) * N + col] = v;
-        }
-    }
     VT t[RPL][NCH];
     T sig[RPL];
     bool used[RPL];
@@ -607,6 +632,29 @@ static hipError_t launch_condense_p(const RefOps& o, const CondenseLaunch& a,
     if (a.nimp == 0) return hipSuccess;
     if (a.precision == HFR_PREC_FP64) return launch_sweep<P, double>(o, a, st);
     return launch_sweep<P, float>(o, a, st);
+}
+
+template <int P>
+static hipError_t launch_fill_p(const RefOps& o, const CondenseLaunch& a,
+                                hipStream_t st) {
+    if (a.nimp == 0) return hipSuccess;
+    if (a.precision == HFR_PREC_FP64)
+        hipLaunchKernelGGL((k_tableau_fill<P, double>), dim3(a.nimp), dim3(256), 0, st, a, o);
+    else
+        hipLaunchKernelGGL((k_tableau_fill<P, float>), dim3(a.nimp), dim3(256), 0, st, a, o);
+    return hipGetLastError();
+}
+
+hipError_t launch_tableau_fill(const RefOps& o, const CondenseLaunch& a,
+                               hipStream_t st) {
+    switch (o.P) {
+        case 2: return launch_fill_p<2>(o, a, st);
+        case 3: return launch_fill_p<3>(o, a, st);
+        case 4: return launch_fill_p<4>(o, a, st);
+        case 5: return launch_fill_p<5>(o, a, st);
+        case 6: return launch_fill_p<6>(o, a, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_condense(const RefOps& o, const CondenseLaunch& a,

@@ -226,7 +226,10 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
     c.blocks_copy = s->blocks_copy;
     c.pivot_fail = s->flags;
     c.piv = s->piv;
-    int tk = tbegin(s, HFR_T_CONDENSE, st);
+    int tk = tbegin(s, HFR_T_FILL, st);
+    HIP_TRY(launch_tableau_fill(m->ops, c, st));
+    tend(s, tk, st);
+    tk = tbegin(s, HFR_T_CONDENSE, st);
     HIP_TRY(launch_condense(m->ops, c, st));
     tend(s, tk, st);
     HIP_TRY(launch_rhs64(m->P, m->Nim, s->M, s->opts.precision, s->piv, s->h,

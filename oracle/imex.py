@@ -58,12 +58,15 @@ def ars222():
 TABLEAUS = {"HIMEX2C": himex2c, "ARS222": ars222}
 
 
-def imex_step(mesh, phys, tab, u_n, dt, tol=1e-13, maxit=25, stats=None):
+def imex_step(mesh, phys, tab, u_n, dt, tol=1e-13, maxit=25, stats=None,
+              trace=None):
     """One step u_n -> u_{n+1} (alg:imex with eq:explicitimex).
 
+    ``trace``: None for the HFR trace, or an ``efr.EfrTrace`` for EFR.
     Returns (u_{n+1}, per-stage records).  Each record holds the stage state
     u_i (all elements), the trace u_hat_i, R_i (implicit) and
     R_bar_{i+1} (explicit)."""
+    from . import efr
     im, ex = mesh.imp_elems, mesh.exp_elems
     s = tab.s
     Rbar = [fr_residual(mesh, phys, u_n)[ex]]
@@ -78,7 +81,12 @@ def imex_step(mesh, phys, tab, u_n, dt, tol=1e-13, maxit=25, stats=None):
         aii_dt = dt * tab.A[i, i]
         its = 0
         uhat = None
-        if len(im):
+        if len(im) and trace is not None:
+            u_im, uhat, its = efr.solve_stage(mesh, trace, phys, u_stage, ustar,
+                                              aii_dt, tol=tol, maxit=maxit)
+            u_stage[im] = u_im
+            Ri, _ = efr.efr_residual(mesh, trace, phys, u_stage, uhat)
+        elif len(im):
             u_im, uhat, its = solve_stage(mesh, phys, u_stage, ustar, aii_dt,
                                           tol=tol, maxit=maxit)
             u_stage[im] = u_im

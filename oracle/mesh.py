@@ -75,6 +75,7 @@ class QuadMesh:
                         np.int64)
         self.Ne = Ne = len(en)
         self.uinf = None if uinf is None else np.asarray(uinf, np.float64)
+        self.elem_vtopo = topo[en]              # topological vertex ids (Ne, 4)
 
         # ---- skeleton: faces on first encounter -------------------------
         directed = set()

@@ -81,6 +81,15 @@ typedef struct hfr_solver_s* hfr_solver_t; /* opaque, library-owned */
  *                               compute calls on it return FR_E_INVALID)
  */
 #define FR_MESH_HOST_ONLY 1
+/* FR_MESH_EFR: interior-embedded trace (Section 2.3, the EFR choice after
+ * eq:hfrspaces): the trace of the implicit region is nodal at the
+ * Gauss-Lobatto-Legendre points of each trace face and continuous, a node
+ * at a vertex being shared by every trace face incident to it.  Nodes are
+ * numbered over the trace faces in order: on each, along the owner's
+ * counter-clockwise direction, the start vertex (if new), the p-1 interior
+ * GLL nodes, the end vertex (if new).  Without it the trace is the
+ * discontinuous HFR trace at the Gauss flux points. */
+#define FR_MESH_EFR 2
 typedef struct {
     int32_t n_nodes;
     const double* node_xy;
@@ -102,6 +111,8 @@ typedef struct {
     int32_t n_loc;   /* element block size n = 4 (p+1)^2                  */
     int32_t m_loc;   /* element trace block size m = 16 (p+1) (all faces) */
     size_t device_table_bytes;
+    int32_t efr;     /* 1 for the interior-embedded trace (FR_MESH_EFR);
+                        n_trace_points then counts trace nodes             */
 } fr_mesh_info;
 
 /*
@@ -121,7 +132,8 @@ fr_status fr_mesh_get_info(fr_mesh_t mesh, fr_mesh_info* out);
  * NULL): face_elem[2*Nf], face_local[2*Nf] (owner, neighbour; -1 for a
  * boundary face's neighbour), face_kind[Nf] (FR_FACE_*),
  * trace_map[Nim*4*(p+1)] (trace point of each flux point of each implicit
- * element in its own counter-clockwise order, -1 off the trace),
+ * element in its own counter-clockwise order, -1 off the trace; with
+ * FR_MESH_EFR, the trace node of each face GLL node instead),
  * implicit_elems[Nim], explicit_elems[Nex], es[Ne], sol_xy[Ne*Np*2]
  * (solution-point coordinates, element-major, point, then x/y).
  */

@@ -37,7 +37,7 @@ class FrMeshInfo(Structure):
                 ("order", "n_pts", "n_elems", "n_faces", "n_implicit",
                  "n_explicit", "n_trace_faces", "n_trace_points",
                  "n_upsilon", "n_boundary", "n_loc", "m_loc")] + \
-        [("device_table_bytes", c_size_t)]
+        [("device_table_bytes", c_size_t), ("efr", c_int32)]
 
 
 class HfrOpts(Structure):

@@ -83,7 +83,8 @@ class Mesh:
     """fr_mesh_create over a mesh description dict (see fr_inputs)."""
 
     def __init__(self, desc, order, implicit_mask=None, es_cutoff=-1.0,
-                 gamma=1.4, uinf=(1.0, 0.0, 0.0, 1.0), host_only=False):
+                 gamma=1.4, uinf=(1.0, 0.0, 0.0, 1.0), host_only=False,
+                 efr=False):
         lib = load_library()
         self._keep = []
 
@@ -114,7 +115,7 @@ class Mesh:
         d.gamma = float(gamma)
         for v in range(4):
             d.uinf[v] = float(uinf[v])
-        d.flags = 1 if host_only else 0
+        d.flags = (1 if host_only else 0) | (2 if efr else 0)
         h = ctypes.c_void_p()
         _check(lib.fr_mesh_create(ctypes.byref(d), ctypes.byref(h)))
         self._keep = []
@@ -128,6 +129,8 @@ class Mesh:
         self.Nim = self.info["n_implicit"]
         self.Nex = self.info["n_explicit"]
         self.Ntp = self.info["n_trace_points"]
+        self.Ntf = self.info["n_trace_faces"]
+        self.efr = bool(self.info["efr"])
         self._maps = None
 
     def maps(self):
@@ -265,11 +268,13 @@ class Solver:
         return f.view(m.Nim, k, k).transpose(1, 2), pv.view(m.Nim, self.n)
 
     def get_preconditioner(self, stream=None):
-        """Block-Jacobi inverses (Ntf, bs, bs) indexed [face, row, column], as
-        float64 (BF16 blocks are widened)."""
+        """Block-Jacobi inverses (block rows, bs, bs) indexed [row block, row,
+        column], as float64 (BF16 blocks are widened)."""
         m = self.mesh
-        bs = 4 * m.P
-        ntf = m.Ntp // m.P
+        # block rows: trace faces of 4(p+1) unknowns (HFR) or trace nodes of
+        # 4 unknowns (EFR)
+        bs = 4 if m.efr else 4 * m.P
+        ntf = m.Ntp if m.efr else m.Ntp // m.P
         pc = self.opts.precond
         dt = {0: torch.float64, 1: torch.float32, 2: torch.int16}[pc]
         d = torch.zeros(ntf * bs * bs, dtype=dt, device="cuda")

@@ -23,6 +23,11 @@ struct RefOps {
     double D[kMaxP * kMaxP];       // D[i*P+l] = l_l'(x_i)
     double lm[kMaxP], lp[kMaxP];   // l_j(-1), l_j(+1)
     double cl[kMaxP], cr[kMaxP];   // correction divergences (DG lifting)
+    // interior-embedded trace: GLL nodes on a face, the GLL basis at the
+    // Gauss flux points gi[q*P+i] = phi_i(x_q), and the Gauss-point basis at
+    // the GLL nodes gj[i*P+q] = l_q(xg_i)
+    double xg[kMaxP];
+    double gi[kMaxP * kMaxP], gj[kMaxP * kMaxP];
 };
 
 // Role of the common flux on one element face.
@@ -72,6 +77,7 @@ struct ResidualLaunch {
     const double* ustar;     // [4][nlist][Np]
     double aii_dt;
     double* gk;              // [nlist][4][P][4] or null
+    const int* efr_fnodes;   // [Ntf][P] trace nodes (interior-embedded trace) or null
 };
 hipError_t launch_residual(const RefOps& ops, const ResidualLaunch& a,
                            hipStream_t st);
@@ -94,6 +100,7 @@ struct CondenseLaunch {
     double* blocks_copy;     // optional (n+m)^2 FP64 copy per element
     int* pivot_fail;         // set to 1 if a zero pivot is met
     int* piv;                // [Nim][n] pivot row p_k of each exchange
+    const int* efr_fnodes;   // [Ntf][P] trace nodes (interior-embedded trace) or null
 };
 // element linearisation and the tableau [A B; C D] (must precede
 // launch_condense, which sweeps the tableau in place)
@@ -141,9 +148,48 @@ hipError_t launch_scale(int N, double* x, const double* src, double a,
                         hipStream_t st);
 hipError_t launch_axpy(int N, double a, const double* x, double* y,
                        hipStream_t st);
-hipError_t launch_recover(int P, int nimp, const void* M, int precision,
-                          const int* piv, const double* yr, const int* trace_map,
-                          const double* duhat, double* du, hipStream_t st);
+// recovery; with efr the trace at the flux points is interpolated from the
+// trace nodes of trace_map (GLL basis of ops)
+hipError_t launch_recover(const RefOps& ops, bool efr, int nimp, const void* M,
+                          int precision, const int* piv, const double* yr,
+                          const int* trace_map, const double* duhat, double* du,
+                          hipStream_t st);
+
+// ---- interior-embedded trace (kernels_efr.hip) ------------------------
+// g at the trace nodes: sum over each node's incidences (slot
+// (imp*4+lf)*P+i) of sum_q phi_i(x_q) gk[imp][lf][q]
+hipError_t launch_efr_gather_g(const RefOps& ops, int nnodes, const int* inc_ptr,
+                               const int* inc, const double* gk, double* g,
+                               hipStream_t st);
+// in place on each element's Schur block: L <- Q^T L Q with Q the
+// GLL-to-Gauss interpolation on every face (slot space (lf, i))
+hipError_t launch_efr_transform(const RefOps& ops, int nimp, void* M,
+                                int precision, int n, int m, hipStream_t st);
+struct EfrAssembleLaunch {
+    int nblocks;              // 4x4 node blocks
+    const int* cptr;          // [nblocks+1] contribution lists
+    const int* contrib;       // (imp, slot_row, slot_col) triples
+    const void* M;
+    int precision;
+    int n, m;
+    double* L64;
+    float* L32;
+    int nnodes;
+    const int* inc_ptr;       // node incidences (slots)
+    const int* inc;
+    double* t;                // [Nn*4] t = -g - sum Q^T z
+    const double* g;
+    const double* z;          // [Nim][m]
+    int P;
+};
+hipError_t launch_efr_assemble(const RefOps& ops, const EfrAssembleLaunch& a,
+                               hipStream_t st);
+// initial trace: at every node the mean over its incidences of the
+// element's state interpolated to the node
+hipError_t launch_efr_trace_average(const RefOps& ops, int nnodes, int Ne,
+                                    const int* inc_ptr, const int* inc,
+                                    const int* imp_list, const double* u,
+                                    double* uhat, hipStream_t st);
 hipError_t launch_newton_update(int Np, int nimp, int Ne, const int* imp_list,
                                 const double* du, double* u, int ntp4,
                                 const double* duhat, double* uhat,

@@ -82,9 +82,17 @@ __device__ void element_linearisation(const CondenseLaunch& a, const RefOps& o,
         for (int z = 0; z < 16; ++z) Fh[z] = 0.0;
         if (fi.role == ROLE_HFR) {
             const int tf = fi.trace >> 1, side = fi.trace & 1;
-            const int tp = tf * P + (side ? P - 1 - q : q);
             double uh[4];
-            for (int v = 0; v < 4; ++v) uh[v] = a.uhat[size_t(tp) * 4 + v];
+            if (a.efr_fnodes) {
+                for (int v = 0; v < 4; ++v) uh[v] = 0.0;
+                for (int i = 0; i < P; ++i) {
+                    const int nd = a.efr_fnodes[size_t(tf) * P + (side ? P - 1 - i : i)];
+                    for (int v = 0; v < 4; ++v) uh[v] += o.gi[q * P + i] * a.uhat[size_t(nd) * 4 + v];
+                }
+            } else {
+                const int tp = tf * P + (side ? P - 1 - q : q);
+                for (int v = 0; v < 4; ++v) uh[v] = a.uhat[size_t(tp) * 4 + v];
+            }
             double su;
             dhfr_flux(uf, uh, S.x, S.y, gam, &su, Fh);
             for (int z = 0; z < 16; ++z) Fu[z] = 0.0;

@@ -413,6 +413,7 @@ template <typename TL>
 static hipError_t launch_pm(int nblocks, int bs, const int* col, const TL* L, int pc,
                             const void* Dinv, TL* Lt, hipStream_t st) {
     switch (bs) {
+        case 4: launch_pm_t<4>(nblocks, col, L, pc, Dinv, Lt, st); break;
         case 8: launch_pm_t<8>(nblocks, col, L, pc, Dinv, Lt, st); break;
         case 12: launch_pm_t<12>(nblocks, col, L, pc, Dinv, Lt, st); break;
         case 16: launch_pm_t<16>(nblocks, col, L, pc, Dinv, Lt, st); break;

@@ -115,9 +115,23 @@ __global__ __launch_bounds__(256) void k_residual(ResidualLaunch a, RefOps og) {
         double com[4], outer[4];
         if (fi.role == ROLE_HFR) {
             const int tf = fi.trace >> 1, side = fi.trace & 1;
-            const int tp = tf * P + (side ? P - 1 - q : q);
+            if (a.efr_fnodes) {
+                // interior-embedded trace: GLL nodes interpolated to the
+                // flux point (element counter-clockwise order)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) outer[v] = a.uhat[size_t(tp) * 4 + v];
+                for (int v = 0; v < 4; ++v) outer[v] = 0.0;
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    const int nd = a.efr_fnodes[size_t(tf) * P + (side ? P - 1 - i : i)];
+                    const double wgt = o.gi[q * P + i];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) outer[v] += wgt * a.uhat[size_t(nd) * 4 + v];
+                }
+            } else {
+                const int tp = tf * P + (side ? P - 1 - q : q);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) outer[v] = a.uhat[size_t(tp) * 4 + v];
+            }
             hfr_flux(uf, outer, S.x, S.y, gam, com);
             if (a.gk) {
 #pragma unroll

@@ -167,6 +167,7 @@ hipError_t launch_block_inverse_impl(int ntf, int bs, const int* diag_blk,
     if (ntf == 0) return hipSuccess;
     const dim3 grid((ntf + 3) / 4), blk(256);
     switch (bs) {
+        case 4: hipLaunchKernelGGL(k_block_inverse<4>, grid, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
         case 8: hipLaunchKernelGGL(k_block_inverse<8>, grid, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
         case 12: hipLaunchKernelGGL(k_block_inverse<12>, grid, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
         case 16: hipLaunchKernelGGL(k_block_inverse<16>, grid, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
@@ -382,21 +383,32 @@ hipError_t launch_absmax(int N, const double* x, double* partial, int nblk,
 // per element, four elements per workgroup; lane l computes the unknowns
 // l, l + 64, ...
 template <typename T, int P>
-__global__ __launch_bounds__(256) void k_recover(int nimp, const T* M,
-                                                 const int* piv,
+__global__ __launch_bounds__(256) void k_recover(RefOps o, int efr, int nimp,
+                                                 const T* M, const int* piv,
                                                  const double* yr,
                                                  const int* trace_map,
                                                  const double* duhat,
                                                  double* du) {
     constexpr int NP = P * P, n = 4 * NP, m = 16 * P, N = n + m;
     __shared__ double sloc[4][m];
+    __shared__ double gi[P * P];
+    for (int t = threadIdx.x; t < P * P; t += blockDim.x) gi[t] = o.gi[t];
+    __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int k = blockIdx.x * 4 + wv;
     if (k >= nimp) return;
     for (int b = lane; b < m; b += 64) {
         const int f = b / (4 * P), q = (b >> 2) % P, w = b & 3;
-        const int tp = trace_map[(size_t(k) * 4 + f) * P + q];
-        sloc[wv][b] = tp >= 0 ? duhat[size_t(tp) * 4 + w] : 0.0;
+        const int* tm = trace_map + (size_t(k) * 4 + f) * P;
+        double v = 0.0;
+        if (efr) {
+            // trace at the flux point from the face's GLL nodes
+            if (tm[0] >= 0)
+                for (int i = 0; i < P; ++i) v += gi[q * P + i] * duhat[size_t(tm[i]) * 4 + w];
+        } else if (tm[q] >= 0) {
+            v = duhat[size_t(tm[q]) * 4 + w];
+        }
+        sloc[wv][b] = v;
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -411,31 +423,34 @@ __global__ __launch_bounds__(256) void k_recover(int nimp, const T* M,
 }
 
 template <typename T>
-static hipError_t launch_recover_t(int P, int nimp, const T* M, const int* piv,
-                                   const double* yr,
+static hipError_t launch_recover_t(const RefOps& o, int efr, int nimp, const T* M,
+                                   const int* piv, const double* yr,
                                    const int* trace_map, const double* duhat,
                                    double* du, hipStream_t st) {
     const dim3 grid((nimp + 3) / 4), blk(256);
-    switch (P) {
-        case 2: hipLaunchKernelGGL((k_recover<T, 2>), grid, blk, 0, st, nimp, M, piv, yr, trace_map, duhat, du); break;
-        case 3: hipLaunchKernelGGL((k_recover<T, 3>), grid, blk, 0, st, nimp, M, piv, yr, trace_map, duhat, du); break;
-        case 4: hipLaunchKernelGGL((k_recover<T, 4>), grid, blk, 0, st, nimp, M, piv, yr, trace_map, duhat, du); break;
-        case 5: hipLaunchKernelGGL((k_recover<T, 5>), grid, blk, 0, st, nimp, M, piv, yr, trace_map, duhat, du); break;
-        case 6: hipLaunchKernelGGL((k_recover<T, 6>), grid, blk, 0, st, nimp, M, piv, yr, trace_map, duhat, du); break;
+#define HFR_RC(PP) hipLaunchKernelGGL((k_recover<T, PP>), grid, blk, 0, st, o, efr, nimp, M, piv, yr, trace_map, duhat, du); break;
+    switch (o.P) {
+        case 2: HFR_RC(2)
+        case 3: HFR_RC(3)
+        case 4: HFR_RC(4)
+        case 5: HFR_RC(5)
+        case 6: HFR_RC(6)
         default: return hipErrorInvalidValue;
     }
+#undef HFR_RC
     return hipGetLastError();
 }
 
-hipError_t launch_recover(int P, int nimp, const void* M, int precision,
-                          const int* piv, const double* yr, const int* trace_map,
-                          const double* duhat, double* du, hipStream_t st) {
+hipError_t launch_recover(const RefOps& ops, bool efr, int nimp, const void* M,
+                          int precision, const int* piv, const double* yr,
+                          const int* trace_map, const double* duhat, double* du,
+                          hipStream_t st) {
     if (nimp == 0) return hipSuccess;
     if (precision == HFR_PREC_FP64)
-        return launch_recover_t(P, nimp, reinterpret_cast<const double*>(M), piv, yr,
-                                trace_map, duhat, du, st);
-    return launch_recover_t(P, nimp, reinterpret_cast<const float*>(M), piv, yr,
-                            trace_map, duhat, du, st);
+        return launch_recover_t(ops, efr ? 1 : 0, nimp, reinterpret_cast<const double*>(M),
+                                piv, yr, trace_map, duhat, du, st);
+    return launch_recover_t(ops, efr ? 1 : 0, nimp, reinterpret_cast<const float*>(M),
+                            piv, yr, trace_map, duhat, du, st);
 }
 
 // ---- Newton update: u_im += du (scatter), uhat += duhat -----------------

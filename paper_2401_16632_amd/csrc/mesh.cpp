@@ -53,6 +53,41 @@ static void gauss_legendre(int n, double* x, double* w) {
     }
 }
 
+// Gauss-Lobatto-Legendre points: the end points and the roots of the
+// derivative of the Legendre polynomial of degree P-1, by Newton's method
+// on P'_{P-1} (second derivative from the Legendre equation).
+static void gauss_lobatto(int P, double* x) {
+    const int n = P - 1;
+    x[0] = -1.0;
+    x[n] = 1.0;
+    for (int i = 1; i < n; ++i) {
+        double z = -std::cos(M_PI * i / n);
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = pk;
+            }
+            const double pn = (n == 1) ? z : p1, pm = (n == 1) ? 1.0 : p0;
+            const double d1 = n * (z * pn - pm) / (z * z - 1.0);
+            const double d2 = (2.0 * z * d1 - n * (n + 1.0) * pn) / (1.0 - z * z);
+            const double dz = d1 / d2;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[i] = z;
+    }
+}
+
+// Lagrange basis on nodes[0..P) evaluated at t
+static double lagrange(const double* nodes, int P, int j, double t) {
+    double v = 1.0;
+    for (int k = 0; k < P; ++k)
+        if (k != j) v *= (t - nodes[k]) / (nodes[j] - nodes[k]);
+    return v;
+}
+
 RefOps make_ref_ops(int P) {
     RefOps o{};
     o.P = P;
@@ -89,6 +124,12 @@ RefOps make_ref_ops(int P) {
         o.cl[j] = a / o.w[j];
         o.cr[j] = b / o.w[j];
     }
+    gauss_lobatto(P, o.xg);
+    for (int q = 0; q < P; ++q)
+        for (int i = 0; i < P; ++i) {
+            o.gi[q * P + i] = lagrange(o.xg, P, i, o.x[q]);
+            o.gj[i * P + q] = lagrange(o.x, P, q, o.xg[i]);
+        }
     return o;
 }
 
@@ -115,7 +156,8 @@ static fr_status upload(T** dst, const std::vector<T>& src, size_t& bytes) {
 
 static void free_mesh_device(fr_mesh_s* m) {
     void* ptrs[] = {m->d_verts, m->d_finfo, m->d_fS, m->d_imp, m->d_exp,
-                    m->d_trace_map, m->d_tpside};
+                    m->d_trace_map, m->d_tpside, m->d_efr_fnodes,
+                    m->d_efr_inc_ptr, m->d_efr_inc};
     for (void* p : ptrs) (void)hipFree(p);
 }
 
@@ -288,9 +330,53 @@ extern "C" fr_status fr_mesh_create(const fr_mesh_desc* d, fr_mesh_t* out) {
     }
     m->Ntf = int(m->trace_faces.size());
     m->Ntp = m->Ntf * P;
+    m->efr = (d->flags & FR_MESH_EFR) != 0;
+    if (m->efr) {
+        // nodes over the trace faces in order, owner counter-clockwise:
+        // start vertex (if new), interior GLL nodes, end vertex (if new)
+        std::unordered_map<int, int> vnode;
+        m->efr_fnodes.assign(size_t(m->Ntf) * P, -1);
+        int nn = 0;
+        for (int F = 0; F < m->Ntf; ++F) {
+            const int f = m->trace_faces[F];
+            const int e0 = m->face_e[2 * f], l0 = m->face_l[2 * f];
+            const int va = topo(d->elem_nodes[4 * e0 + l0]);
+            const int vb = topo(d->elem_nodes[4 * e0 + (l0 + 1) % 4]);
+            auto ia = vnode.find(va);
+            if (ia == vnode.end()) ia = vnode.emplace(va, nn++).first;
+            m->efr_fnodes[size_t(F) * P] = ia->second;
+            for (int i = 1; i < P - 1; ++i) m->efr_fnodes[size_t(F) * P + i] = nn++;
+            auto ib = vnode.find(vb);
+            if (ib == vnode.end()) ib = vnode.emplace(vb, nn++).first;
+            m->efr_fnodes[size_t(F) * P + P - 1] = ib->second;
+        }
+        m->Ntp = nn;
+    }
     m->trace_map.assign(size_t(m->Nim) * 4 * P, -1);
-    std::vector<int> tpside(2 * size_t(m->Ntp), -1);
-    for (int k = 0; k < m->Nim; ++k) {
+    std::vector<int> tpside(m->efr ? 0 : 2 * size_t(m->Ntp), -1);
+    for (int k = 0; k < m->Nim && m->efr; ++k) {
+        int e = m->imp[k];
+        for (int lf = 0; lf < 4; ++lf) {
+            int tf = m->trace_of_face[m->elem_face[4 * e + lf]];
+            if (tf < 0) continue;
+            int side = m->elem_side[4 * e + lf];
+            for (int i = 0; i < P; ++i)
+                m->trace_map[(size_t(k) * 4 + lf) * P + i] =
+                    m->efr_fnodes[size_t(tf) * P + (side ? P - 1 - i : i)];
+        }
+    }
+    if (m->efr) {
+        // incidences of every node: slots (imp*4+lf)*P+i in slot order
+        m->efr_inc_ptr.assign(size_t(m->Ntp) + 1, 0);
+        for (size_t s = 0; s < m->trace_map.size(); ++s)
+            if (m->trace_map[s] >= 0) m->efr_inc_ptr[m->trace_map[s] + 1]++;
+        for (int a = 0; a < m->Ntp; ++a) m->efr_inc_ptr[a + 1] += m->efr_inc_ptr[a];
+        m->efr_inc.assign(m->efr_inc_ptr[m->Ntp], -1);
+        std::vector<int> fill(m->efr_inc_ptr.begin(), m->efr_inc_ptr.end() - 1);
+        for (size_t s = 0; s < m->trace_map.size(); ++s)
+            if (m->trace_map[s] >= 0) m->efr_inc[fill[m->trace_map[s]]++] = int(s);
+    }
+    for (int k = 0; k < m->Nim && !m->efr; ++k) {
         int e = m->imp[k];
         for (int lf = 0; lf < 4; ++lf) {
             int f = m->elem_face[4 * e + lf];
@@ -359,7 +445,10 @@ extern "C" fr_status fr_mesh_create(const fr_mesh_desc* d, fr_mesh_t* out) {
         (st = upload(&m->d_imp, m->imp, nb)) ||
         (st = upload(&m->d_exp, m->exp, nb)) ||
         (st = upload(&m->d_trace_map, m->trace_map, nb)) ||
-        (st = upload(&m->d_tpside, tpside, nb))) {
+        (!m->efr && (st = upload(&m->d_tpside, tpside, nb))) ||
+        (m->efr && (st = upload(&m->d_efr_fnodes, m->efr_fnodes, nb))) ||
+        (m->efr && (st = upload(&m->d_efr_inc_ptr, m->efr_inc_ptr, nb))) ||
+        (m->efr && (st = upload(&m->d_efr_inc, m->efr_inc, nb)))) {
         free_mesh_device(m);
         delete m;
         return st;
@@ -389,6 +478,7 @@ extern "C" fr_status fr_mesh_get_info(fr_mesh_t m, fr_mesh_info* o) {
     o->n_loc = 4 * m->Np;
     o->m_loc = 16 * m->P;
     o->device_table_bytes = m->device_bytes;
+    o->efr = m->efr ? 1 : 0;
     return FR_OK;
 }
 

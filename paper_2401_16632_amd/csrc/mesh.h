@@ -32,4 +32,12 @@ struct fr_mesh_s {
     int* d_tpside = nullptr;              // [Ntp][2]: (imp*4+lf)*P+q_el
     size_t device_bytes = 0;
     bool host_only = false;
+    // interior-embedded trace (FR_MESH_EFR): Ntp counts trace nodes
+    bool efr = false;
+    std::vector<int> efr_fnodes;          // [Ntf][P] nodes, owner ccw order
+    std::vector<int> efr_inc_ptr;         // [Ntp+1] node -> incidences
+    std::vector<int> efr_inc;             // slot (imp*4+lf)*P+i, element ccw i
+    int* d_efr_fnodes = nullptr;
+    int* d_efr_inc_ptr = nullptr;
+    int* d_efr_inc = nullptr;
 };

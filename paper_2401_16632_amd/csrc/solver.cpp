@@ -36,6 +36,7 @@ struct hfr_solver_s {
     fr_mesh_t mesh = nullptr;
     hfr_opts opts{};
     int n = 0, m = 0, bs = 0, N = 0, restart = 0;
+    int nbr = 0;             // block rows of L: trace faces (HFR) or trace nodes (EFR)
     size_t elem_M = 0;       // scalars per element matrix
     int nblocks = 0;
     // device
@@ -52,6 +53,8 @@ struct hfr_solver_s {
     int* col = nullptr;
     int* contrib = nullptr;
     int* tside = nullptr;
+    int* efr_cptr = nullptr;     // node-block contribution lists (EFR)
+    int* efr_contrib = nullptr;
     int* diag_blk = nullptr;
     double* L64 = nullptr;
     float* L32 = nullptr;
@@ -157,7 +160,8 @@ void free_solver(hfr_solver_s* s) {
                     s->tside, s->diag_blk, s->L64, s->L32, s->t, s->Dinv,
                     s->flags, s->V, s->z, s->r, s->scratch, s->dots, s->coef,
                     s->Lt64, s->Lt32, s->W, s->gs, s->part, s->part2,
-                    s->counters, s->piv, s->yr, s->zz, s->part3};
+                    s->counters, s->piv, s->yr, s->zz, s->part3,
+                    s->efr_cptr, s->efr_contrib};
     for (void* p : ptrs) (void)hipFree(p);
 }
 
@@ -181,6 +185,7 @@ ResidualLaunch implicit_launch(hfr_solver_s* s, const double* u,
     a.fS = m->d_fS;
     a.uhat = uhat;
     a.phys = m->phys;
+    a.efr_fnodes = m->efr ? m->d_efr_fnodes : nullptr;
     return a;
 }
 
@@ -199,7 +204,36 @@ fr_status residual_internal(hfr_solver_s* s, const double* u,
     int tk = tbegin(s, HFR_T_RESIDUAL, st);
     HIP_TRY(launch_residual(m->ops, a, st));
     tend(s, tk, st);
-    HIP_TRY(launch_trace_gather_g(m->Ntp, m->P, m->d_tpside, s->gk, s->g, st));
+    if (m->efr)
+        HIP_TRY(launch_efr_gather_g(m->ops, m->Ntp, m->d_efr_inc_ptr, m->d_efr_inc,
+                                    s->gk, s->g, st));
+    else
+        HIP_TRY(launch_trace_gather_g(m->Ntp, m->P, m->d_tpside, s->gk, s->g, st));
+    return FR_OK;
+}
+
+// node-block assembly of the interior-embedded trace system (t only when
+// with_matrix is false)
+fr_status efr_assemble(hfr_solver_s* s, bool with_matrix, hipStream_t st) {
+    fr_mesh_s* m = s->mesh;
+    EfrAssembleLaunch a{};
+    a.nblocks = with_matrix ? s->nblocks : 0;
+    a.cptr = s->efr_cptr;
+    a.contrib = s->efr_contrib;
+    a.M = s->M;
+    a.precision = s->opts.precision;
+    a.n = s->n;
+    a.m = s->m;
+    a.L64 = s->L64;
+    a.L32 = s->L32;
+    a.nnodes = m->Ntp;
+    a.inc_ptr = m->d_efr_inc_ptr;
+    a.inc = m->d_efr_inc;
+    a.t = s->t;
+    a.g = s->g;
+    a.z = s->zz;
+    a.P = m->P;
+    HIP_TRY(launch_efr_assemble(m->ops, a, st));
     return FR_OK;
 }
 
@@ -226,6 +260,7 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
     c.blocks_copy = s->blocks_copy;
     c.pivot_fail = s->flags;
     c.piv = s->piv;
+    c.efr_fnodes = m->efr ? m->d_efr_fnodes : nullptr;
     int tk = tbegin(s, HFR_T_FILL, st);
     HIP_TRY(launch_tableau_fill(m->ops, c, st));
     tend(s, tk, st);
@@ -234,7 +269,15 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
     tend(s, tk, st);
     HIP_TRY(launch_rhs64(m->P, m->Nim, s->M, s->opts.precision, s->piv, s->h,
                          s->yr, s->zz, st));
-    if (m->Ntf == 0) return FR_OK;
+    if (s->nbr == 0) return FR_OK;
+    if (m->efr) {
+        tk = tbegin(s, HFR_T_ASSEMBLE, st);
+        HIP_TRY(launch_efr_transform(m->ops, m->Nim, s->M, s->opts.precision,
+                                     s->n, s->m, st));
+        fr_status ea = efr_assemble(s, true, st);
+        tend(s, tk, st);
+        if (ea) return ea;
+    } else {
     AssembleLaunch a{};
     a.nblocks = s->nblocks;
     a.blk_contrib = s->contrib;
@@ -253,8 +296,9 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
     tk = tbegin(s, HFR_T_ASSEMBLE, st);
     HIP_TRY(launch_assemble(a, st));
     tend(s, tk, st);
+    }
     tk = tbegin(s, HFR_T_PCSETUP, st);
-    HIP_TRY(launch_block_inverse_impl(m->Ntf, s->bs, s->diag_blk, s->L64,
+    HIP_TRY(launch_block_inverse_impl(s->nbr, s->bs, s->diag_blk, s->L64,
                                       s->L64 ? nullptr : s->L32,
                                       s->opts.precond, s->Dinv, s->flags + 1,
                                       st));
@@ -272,7 +316,13 @@ fr_status recondense_rhs_internal(hfr_solver_s* s, hipStream_t st) {
     if (m->Nim == 0) return FR_OK;
     HIP_TRY(launch_rhs64(m->P, m->Nim, s->M, s->opts.precision, s->piv, s->h,
                          s->yr, s->zz, st));
-    if (m->Ntf == 0) return FR_OK;
+    if (s->nbr == 0) return FR_OK;
+    if (m->efr) {
+        const int tk = tbegin(s, HFR_T_ASSEMBLE, st);
+        fr_status ea = efr_assemble(s, false, st);
+        tend(s, tk, st);
+        return ea;
+    }
     AssembleLaunch a{};
     a.nblocks = 0;            // t only
     a.blk_contrib = s->contrib;
@@ -309,7 +359,7 @@ fr_status host_dots(hfr_solver_s* s, int k, const double* V, size_t ldv,
 GmresArgs gmres_args(hfr_solver_s* s) {
     fr_mesh_s* m = s->mesh;
     GmresArgs a{};
-    a.ntf = m->Ntf;
+    a.ntf = s->nbr;
     a.bs = s->bs;
     a.fpb = s->fpb;
     a.nblk = s->gblk;
@@ -466,7 +516,7 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         loc.gmres_iters += ks.iterations;
         if (e && e != FR_E_NOT_CONVERGED) return e;
         tk = tbegin(s, HFR_T_RECOVER, st);
-        HIP_TRY(launch_recover(m->P, m->Nim, s->M, s->opts.precision, s->piv, s->yr,
+        HIP_TRY(launch_recover(m->ops, m->efr, m->Nim, s->M, s->opts.precision, s->piv, s->yr,
                                m->d_trace_map, s->duhat, s->du, st));
         HIP_TRY(launch_newton_update(m->Np, m->Nim, m->Ne, m->d_imp, s->du, u,
                                      4 * m->Ntp, s->duhat, uhat, st));
@@ -508,14 +558,43 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
     const int P = m->P;
     s->n = 4 * m->Np;
     s->m = 16 * P;
-    s->bs = 4 * P;
+    s->bs = m->efr ? 4 : 4 * P;
+    s->nbr = m->efr ? m->Ntp : m->Ntf;
     s->N = 4 * m->Ntp;
     s->restart = o->gmres_restart;
     s->elem_M = size_t(s->n + s->m) * (s->n + s->m);
-    // block-sparse structure of L: one block row per trace face; columns
-    // are the trace faces of the two elements sharing it
-    std::vector<int> rowptr(m->Ntf + 1, 0), col, contrib, tside(4 * size_t(m->Ntf), -1),
-        diag(m->Ntf, -1);
+    // block-sparse structure of L.  HFR: one block row per trace face;
+    // columns are the trace faces of the two elements sharing it.  EFR: one
+    // 4x4 block row per trace node; columns are the nodes of the elements
+    // around it, each block summing (element, slot row, slot column)
+    // contributions of the transformed element Schur blocks.
+    std::vector<int> rowptr(s->nbr + 1, 0), col, contrib, tside(4 * size_t(m->Ntf), -1),
+        diag(s->nbr, -1), ecptr(1, 0), econtrib;
+    if (m->efr) {
+        std::vector<std::map<int, std::vector<int>>> rows(s->nbr);
+        for (int k = 0; k < m->Nim; ++k)
+            for (int sa = 0; sa < 4 * P; ++sa) {
+                const int a = m->trace_map[size_t(k) * 4 * P + sa];
+                if (a < 0) continue;
+                for (int sb = 0; sb < 4 * P; ++sb) {
+                    const int b = m->trace_map[size_t(k) * 4 * P + sb];
+                    if (b < 0) continue;
+                    auto& v = rows[a][b];
+                    v.push_back(k);
+                    v.push_back(sa);
+                    v.push_back(sb);
+                }
+            }
+        for (int a = 0; a < s->nbr; ++a) {
+            for (auto& kv : rows[a]) {
+                if (kv.first == a) diag[a] = int(col.size());
+                col.push_back(kv.first);
+                econtrib.insert(econtrib.end(), kv.second.begin(), kv.second.end());
+                ecptr.push_back(int(econtrib.size() / 3));
+            }
+            rowptr[a + 1] = int(col.size());
+        }
+    } else
     for (int F = 0; F < m->Ntf; ++F) {
         const int f = m->trace_faces[F];
         std::map<int, std::vector<int>> cols;   // G -> contributions
@@ -566,6 +645,8 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
         (e = dalloc(&s->col, col.size(), tot)) ||
         (e = dalloc(&s->contrib, contrib.size(), tot)) ||
         (e = dalloc(&s->tside, tside.size(), tot)) ||
+        (e = dalloc(&s->efr_cptr, m->efr ? ecptr.size() : 0, tot)) ||
+        (e = dalloc(&s->efr_contrib, econtrib.size(), tot)) ||
         (e = dalloc(&s->diag_blk, diag.size(), tot)) ||
         (o->precision == HFR_PREC_FP64 && (e = dalloc(&s->L64, size_t(s->nblocks) * bb, tot))) ||
         (o->precision == HFR_PREC_FP32 && (e = dalloc(&s->L32, size_t(s->nblocks) * bb, tot))) ||
@@ -573,16 +654,16 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
         (o->precision == HFR_PREC_FP32 && (e = dalloc(&s->Lt32, size_t(s->nblocks) * bb, tot))) ||
         (e = dalloc(&s->W, 2 * size_t(std::max(1, s->N)), tot)) ||
         (e = dalloc(reinterpret_cast<char**>(&s->gs), sizeof(GmresState), tot)) ||
-        (e = dalloc(&s->part, size_t(std::max(256, m->Ntf / std::max(1, 2048 / s->bs) + 1)) * kGmresMaxK, tot)) ||
-        (e = dalloc(&s->part2, size_t(std::max(256, m->Ntf / std::max(1, 2048 / s->bs) + 1)) * kGmresMaxK, tot)) ||
-        (e = dalloc(&s->part3, size_t(std::max(1024, m->Ntf + 1)) * kGmresMaxK, tot)) ||
+        (e = dalloc(&s->part, size_t(std::max(256, s->nbr / std::max(1, 2048 / s->bs) + 1)) * kGmresMaxK, tot)) ||
+        (e = dalloc(&s->part2, size_t(std::max(256, s->nbr / std::max(1, 2048 / s->bs) + 1)) * kGmresMaxK, tot)) ||
+        (e = dalloc(&s->part3, size_t(std::max(1024, s->nbr + 1)) * kGmresMaxK, tot)) ||
         (e = dalloc(&s->counters, 4, tot)) ||
         (e = dalloc(&s->piv, nimp * size_t(s->n), tot)) ||
         (e = dalloc(&s->yr, nimp * size_t(s->n), tot)) ||
         (e = dalloc(&s->zz, nimp * size_t(s->m), tot)) ||
         (e = dalloc(&s->t, size_t(s->N), tot)) ||
         (e = dalloc(reinterpret_cast<char**>(&s->Dinv),
-                    size_t(m->Ntf) * bb * (o->precond == HFR_PC_FP64 ? 8 : o->precond == HFR_PC_FP32 ? 4 : 2),
+                    size_t(s->nbr) * bb * (o->precond == HFR_PC_FP64 ? 8 : o->precond == HFR_PC_FP32 ? 4 : 2),
                     tot)) ||
         (e = dalloc(&s->flags, 2, tot)) ||
         (e = dalloc(&s->V, size_t(s->restart + 1) * std::max(1, s->N), tot)) ||
@@ -600,16 +681,16 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
     s->nblk_dot = multidot_blocks(std::max(1, s->N));
     s->verbose = std::getenv("HFR_VERBOSE") != nullptr;
     s->fpb = 256 / s->bs;
-    s->gblk = std::max(1, (m->Ntf + s->fpb - 1) / s->fpb);
+    s->gblk = std::max(1, (s->nbr + s->fpb - 1) / s->fpb);
     // vector kernels: about 256 workgroups of 512 threads, each owning whole
     // faces, at most 2048 rows (4 per thread)
-    s->fpb = std::min(std::max((m->Ntf + 255) / 256, std::max(1, 512 / s->bs)),
+    s->fpb = std::min(std::max((s->nbr + 255) / 256, std::max(1, 512 / s->bs)),
                       2048 / s->bs);
-    s->gblk = std::max(1, (m->Ntf + s->fpb - 1) / s->fpb);
+    s->gblk = std::max(1, (s->nbr + s->fpb - 1) / s->fpb);
     // product kernel: up to 1024 workgroups, 64 rows per pass, 8 passes max
-    s->fpbA = std::max(std::max(1, 64 / s->bs), (m->Ntf + 1023) / 1024);
+    s->fpbA = std::max(std::max(1, 64 / s->bs), (s->nbr + 1023) / 1024);
     s->fpbA = std::min(s->fpbA, std::max(1, 512 / s->bs));
-    s->gblkA = std::max(1, (m->Ntf + s->fpbA - 1) / s->fpbA);
+    s->gblkA = std::max(1, (s->nbr + s->fpbA - 1) / s->fpbA);
     auto up = [&](int* d, const std::vector<int>& h) {
         return h.empty() ? hipSuccess
                          : hipMemcpy(d, h.data(), 4 * h.size(), hipMemcpyHostToDevice);
@@ -617,6 +698,8 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
     if (up(s->rowptr, rowptr) != hipSuccess || up(s->col, col) != hipSuccess ||
         up(s->contrib, contrib) != hipSuccess || up(s->tside, tside) != hipSuccess ||
         up(s->diag_blk, diag) != hipSuccess ||
+        (m->efr && up(s->efr_cptr, ecptr) != hipSuccess) ||
+        up(s->efr_contrib, econtrib) != hipSuccess ||
         hipMemset(s->flags, 0, 8) != hipSuccess ||
         hipMemset(s->counters, 0, 16) != hipSuccess ||
         hipMemset(s->gs, 0, sizeof(GmresState)) != hipSuccess) {
@@ -679,7 +762,7 @@ extern "C" fr_status hfr_recover(hfr_solver_t s, const double* duhat,
     if (!s || (!duhat && s->N) || (!du && s->mesh->Nim))
         return fail(FR_E_INVALID, "null argument");
     fr_mesh_s* m = s->mesh;
-    HIP_TRY(launch_recover(m->P, m->Nim, s->M, s->opts.precision, s->piv, s->yr,
+    HIP_TRY(launch_recover(m->ops, m->efr, m->Nim, s->M, s->opts.precision, s->piv, s->yr,
                            m->d_trace_map, duhat, du, hipStream_t(stream)));
     return FR_OK;
 }
@@ -688,7 +771,7 @@ extern "C" fr_status hfr_trace_matvec(hfr_solver_t s, const double* x,
                                       double* y, void* stream) {
     if (!s || (s->N && (!x || !y))) return fail(FR_E_INVALID, "null argument");
     fr_mesh_s* m = s->mesh;
-    HIP_TRY(launch_spmv(m->Ntf, s->bs, s->rowptr, s->col, s->L64,
+    HIP_TRY(launch_spmv(s->nbr, s->bs, s->rowptr, s->col, s->L64,
                         s->L64 ? nullptr : s->L32, x, y, 1.0, nullptr,
                         hipStream_t(stream)));
     return FR_OK;
@@ -740,8 +823,8 @@ extern "C" fr_status hfr_get_preconditioner(hfr_solver_t s, void* dinv,
     fr_mesh_s* m = s->mesh;
     const int pc = s->opts.precond;
     const size_t scal = pc == HFR_PC_FP64 ? 8 : pc == HFR_PC_FP32 ? 4 : 2;
-    if (m->Ntf)
-        HIP_TRY(hipMemcpyAsync(dinv, s->Dinv, size_t(m->Ntf) * s->bs * s->bs * scal,
+    if (s->nbr)
+        HIP_TRY(hipMemcpyAsync(dinv, s->Dinv, size_t(s->nbr) * s->bs * s->bs * scal,
                                hipMemcpyDeviceToDevice, hipStream_t(stream)));
     return FR_OK;
 }
@@ -810,8 +893,13 @@ extern "C" fr_status imex_stage(fr_mesh_t mesh, hfr_solver_t s,
         HIP_TRY(launch_combine(m->Nim, m->Np, m->Ne, m->d_imp, stt->u_n, I - 1,
                                terms, coefs, s->ustar, 0, st));
         const double aii_dt = dt * tab->A[(I - 1) * S + (I - 1)];
-        HIP_TRY(launch_trace_average_ops(m->ops, m->Ntp, m->Ne, m->d_tpside,
-                                         m->d_imp, stt->u, stt->uhat, st));
+        if (m->efr)
+            HIP_TRY(launch_efr_trace_average(m->ops, m->Ntp, m->Ne, m->d_efr_inc_ptr,
+                                             m->d_efr_inc, m->d_imp, stt->u,
+                                             stt->uhat, st));
+        else
+            HIP_TRY(launch_trace_average_ops(m->ops, m->Ntp, m->Ne, m->d_tpside,
+                                             m->d_imp, stt->u, stt->uhat, st));
         fr_status e = sync_check(st);
         if (e) return e;
         auto t0 = std::chrono::steady_clock::now();

@@ -81,3 +81,24 @@ def test_mesh_errors_reported():
         hp.Mesh(d2, 2, host_only=True)
     with pytest.raises(hp.HfrError, match="FR_E_INVALID"):
         hp.Mesh(d, 9, host_only=True)
+
+
+@pytest.mark.parametrize("case,p", [("c1", 2), ("c1p", 3), ("cyl", 1), ("cyl", 4)])
+def test_efr_node_map_bit_exact_vs_oracle(case, p):
+    """Interior-embedded trace: node count and the per-element face-node map
+    (trace node of every GLL node of every face of every implicit element)
+    match the oracle's numbering exactly."""
+    from oracle import efr
+    if case == "c1":
+        d, mask = c1_desc()
+    elif case == "c1p":
+        d, mask = c1_desc(n=6, perturb=0.2, seed=4)
+    else:
+        d, mask = cylinder_desc()
+    uinf = (1.0, 1.0, 0.0, 40.0)
+    om = oracle.QuadMesh(d, p, implicit_mask=mask, uinf=uinf)
+    tr = efr.EfrTrace(om)
+    hm = hp.Mesh(d, p, implicit_mask=mask, uinf=uinf, host_only=True, efr=True)
+    assert hm.efr and hm.info["n_trace_points"] == tr.Nn
+    assert hm.info["n_trace_faces"] == om.Ntf
+    assert np.array_equal(hm.maps()["trace_map"], tr.elem_nodes)

@@ -48,8 +48,9 @@ def describe(name):
             f"implicit = local CFL > 1 (IF ~ 0.2), HIMEX2C pair")
 
 
-def build_case(hp, name, if_target=0.2, seed=2):
-    """Mesh, partition (CFL rule), time step and initial state."""
+def build_case(hp, name, if_target=0.2, seed=2, efr=False):
+    """Mesh, partition (CFL rule), time step and initial state; ``efr``
+    selects the interior-embedded trace."""
     import fr_inputs as fi
     d, p, nt, nr, first, ratio = cylinder_workload(name)
     uinf = fi.freestream_state(MACH)
@@ -59,7 +60,7 @@ def build_case(hp, name, if_target=0.2, seed=2):
     es_cut = 0.5 * (es[J - 1].max() + es[J].min())
     # local CFL_k = dt * lambda * (2p+1) / (2 E_s,k); implicit iff CFL_k > 1
     dt = 2.0 * es_cut / (WAVE * (2 * p + 1))
-    mesh = hp.Mesh(d, p, es_cutoff=es_cut, uinf=uinf)
+    mesh = hp.Mesh(d, p, es_cutoff=es_cut, uinf=uinf, efr=efr)
     xy = mesh.maps()["sol_xy"]
     P = p + 1
     u = np.broadcast_to(uinf, (mesh.Ne, P, P, 4)).copy()
@@ -243,6 +244,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=["c2", "c3"])
     ap.add_argument("--forms", default="fp32,fp64")
+    ap.add_argument("--no-efr", action="store_true",
+                    help="skip the interior-embedded trace forms")
     ap.add_argument("--newton-tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -308,6 +311,31 @@ def main():
             (np.abs(a - b).max(axis=1) / np.abs(b).max(axis=1)).max())
         line["speedup_fp32_over_fp64"] = (
             np.mean(results["fp64"]["impl_ms"]) / np.mean(results["fp32"]["impl_ms"]))
+    if not args.no_efr:
+        # the same workload with the interior-embedded trace (EFR)
+        mesh_e, u0e, dte, _ = build_case(hp, args.workload, efr=True)
+        dof_e = mesh_e.Nim * mesh_e.Np * 4
+        efr_states = {}
+        for f in forms:
+            pc = "fp32" if f == "fp32" else "fp64"
+            rr = run_form(hp, torch, mesh_e, u0e, dte, f, pc, args.steps,
+                          args.warmup, args.newton_tol)
+            efr_states[f] = rr["state"]
+            line[f"efr_{f}_form"] = {
+                "implicit_dof_per_s": dof_e / (np.mean(rr["impl_ms"]) * 1e-3),
+                "implicit_ms_per_stage": float(np.mean(rr["impl_ms"])),
+                "newton_iters_per_stage": float(np.mean(rr["newton"])),
+                "gmres_iters_per_stage": float(np.mean(rr["gmres"])),
+                "trace_unknowns": 4 * mesh_e.Ntp,
+                "timers_ms": {k: v[0] for k, v in rr["timers"].items()},
+            }
+            print(f"# efr form {f}: implicit ms/stage {np.mean(rr['impl_ms']):.3f}, "
+                  f"gmres/stage {np.mean(rr['gmres']):.1f}", file=sys.stderr, flush=True)
+        if "fp32" in efr_states and "fp64" in efr_states:
+            a, b = efr_states["fp32"].reshape(4, -1), efr_states["fp64"].reshape(4, -1)
+            line["efr_fp32_vs_fp64_rel_err"] = float(
+                (np.abs(a - b).max(axis=1) / np.abs(b).max(axis=1)).max())
+        line["hfr_trace_unknowns"] = 4 * mesh.Ntp
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(line))

@@ -154,6 +154,34 @@ fr_status fr_mesh_get_maps(fr_mesh_t mesh, int32_t* face_elem,
 fr_status fr_explicit_rhs(fr_mesh_t mesh, const double* u, double* R_ex,
                           void* stream);
 
+/*
+ * Modal filter of Appendix B: F = V Lambda* V^-1 per element and variable,
+ * V the Vandermonde matrix of the tensor-product orthonormal Legendre basis
+ * psi_a(xi) psi_b(eta) at the solution points, Lambda diagonal with
+ * sigma(a + b):
+ *   1                                                    a + b <  eta_c
+ *   exp(-alpha ((a + b - eta_c) / (eta_max - eta_c))^s)  otherwise,
+ * eta_max = 2p the largest exponent sum of the basis.  The time-step
+ * normalisation Lambda* is taken as Lambda^kappa (kappa = 1: the filter
+ * as written; kappa = dt / dt_ref keeps the damping per unit time fixed).
+ * The airfoil run of Section 5 uses alpha = 100, s = 1, eta_c = 3.
+ */
+typedef struct {
+    double alpha;   /* damping, >= 0                      */
+    double s;       /* strength (exponent), > 0           */
+    double eta_c;   /* cut-off exponent sum               */
+    double kappa;   /* time-step normalisation exponent, >= 0 */
+} fr_filter_params;
+
+/*
+ * fr_modal_filter: u [4][Ne][Np] (device, read and written in place) is
+ * replaced by its filtered values on every element, on `stream`.  The mean
+ * mode is never damped.  FR_E_INVALID for a null argument, a host-only mesh
+ * or a parameter outside the ranges above.
+ */
+fr_status fr_modal_filter(fr_mesh_t mesh, const fr_filter_params* prm,
+                          double* u, void* stream);
+
 /* ----------------------------------------------------------------------- */
 /* Implicit (hybridized) stage                                             */
 /* ----------------------------------------------------------------------- */

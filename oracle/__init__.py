@@ -17,8 +17,8 @@ written special case).  No function is "parity unpinned".
 from .operators import RefOps
 from .mesh import QuadMesh, FACE_EXPLICIT, FACE_UPSILON, FACE_TRACE, FACE_BOUNDARY
 from .physics import Euler, Advection
-from . import residual, newton, imex, efr
+from . import residual, newton, imex, efr, modal_filter
 
 __all__ = ["RefOps", "QuadMesh", "Euler", "Advection", "residual", "newton",
-           "imex", "efr", "FACE_EXPLICIT", "FACE_UPSILON", "FACE_TRACE",
+           "imex", "efr", "modal_filter", "FACE_EXPLICIT", "FACE_UPSILON", "FACE_TRACE",
            "FACE_BOUNDARY"]

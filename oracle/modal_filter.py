@@ -1,4 +1,5 @@
 """Modal filter of the airfoil workload (Appendix B, modal filtering).
+Test infrastructure only, like the rest of this package.
 
 F = V Lambda* V^-1 per element and conserved variable, with V the
 Vandermonde matrix of the orthonormal Legendre basis at the solution points

@@ -12,7 +12,8 @@ STATUS = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_MESH", -3: "FR_E_NOMEM",
           -4: "FR_E_DEVICE", -5: "FR_E_NOT_CONVERGED", -6: "FR_E_NONFINITE",
           -7: "FR_E_UNSUPPORTED"}
 EXPORTED = ["fr_mesh_create", "fr_mesh_destroy", "fr_mesh_get_info",
-            "fr_mesh_get_maps", "fr_explicit_rhs", "hfr_solver_create",
+            "fr_mesh_get_maps", "fr_explicit_rhs", "fr_modal_filter",
+            "hfr_solver_create",
             "hfr_solver_destroy", "hfr_residual", "hfr_assemble_condense",
             "hfr_trace_solve", "hfr_recover", "hfr_trace_matvec",
             "hfr_get_system", "hfr_get_blocks", "hfr_get_factors", "hfr_get_preconditioner", "hfr_timing",
@@ -63,6 +64,11 @@ class ImexTableau(Structure):
                 ("Abar", c_double * 25), ("bbar", c_double * 5)]
 
 
+class FrFilterParams(Structure):
+    _fields_ = [("alpha", c_double), ("s", c_double), ("eta_c", c_double),
+                ("kappa", c_double)]
+
+
 class ImexState(Structure):
     _fields_ = [("u_n", c_void_p), ("u", c_void_p), ("uhat", c_void_p),
                 ("R_im", c_void_p), ("R_ex", c_void_p)]
@@ -81,6 +87,8 @@ def load(path=LIB_PATH):
         "fr_mesh_get_info": (c_int32, [c_void_p, P(FrMeshInfo)]),
         "fr_mesh_get_maps": (c_int32, [c_void_p] + [c_void_p] * 8),
         "fr_explicit_rhs": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+        "fr_modal_filter": (c_int32, [c_void_p, P(FrFilterParams), c_void_p,
+                                      c_void_p]),
         "hfr_solver_create": (c_int32, [c_void_p, P(HfrOpts), P(c_size_t),
                                         P(c_void_p)]),
         "hfr_solver_destroy": (None, [c_void_p]),

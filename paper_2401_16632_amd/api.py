@@ -158,6 +158,16 @@ class Mesh:
                                    _dev(R_ex, 4 * self.Nex * self.Np, "R_ex"),
                                    _stream(stream)))
 
+    def modal_filter(self, u, alpha=100.0, s=1.0, eta_c=3.0, kappa=1.0,
+                     stream=None):
+        """Filter the flat SoA float64 state u in place (Appendix B)."""
+        lib = load_library()
+        prm = _abi.FrFilterParams(float(alpha), float(s), float(eta_c),
+                                  float(kappa))
+        _check(lib.fr_modal_filter(self.handle, ctypes.byref(prm),
+                                   _dev(u, 4 * self.Ne * self.Np, "u"),
+                                   _stream(stream)))
+
     def close(self):
         if getattr(self, "handle", None):
             load_library().fr_mesh_destroy(self.handle)
@@ -320,9 +330,11 @@ class ImexStepper:
         self.R_ex = torch.zeros(max(1, (s + 1) * 4 * m.Nex * m.Np), **f64)
         self.stats = []
 
-    def step(self, u_n, dt, stream=None):
+    def step(self, u_n, dt, stream=None, filter=None):
         """Advance u_n (flat SoA float64 CUDA tensor) by dt; returns the new
-        state tensor (a view of an internal buffer) and per-stage stats."""
+        state tensor (a view of an internal buffer) and per-stage stats.
+        filter: None, or keyword arguments of Mesh.modal_filter applied to
+        u_{n+1} after the last stage."""
         lib = load_library()
         m = self.mesh
         _dev(u_n, 4 * m.Ne * m.Np, "u_n")
@@ -344,5 +356,7 @@ class ImexStepper:
                                   gmres_iters=ns.gmres_iters,
                                   residual=ns.residual,
                                   implicit_ms=ns.implicit_ms))
+        if filter is not None:
+            m.modal_filter(self.u, stream=stream, **filter)
         self.stats = stats
         return self.u, stats

@@ -194,6 +194,16 @@ hipError_t launch_newton_update(int Np, int nimp, int Ne, const int* imp_list,
                                 const double* du, double* u, int ntp4,
                                 const double* duhat, double* uhat,
                                 hipStream_t st);
+// Modal filter: orthonormal Legendre basis at the Gauss points
+// v1[q*P+a] = psi_a(x_q), the Gauss weights, and sigma (already raised to
+// the time-step exponent) per exponent sum a + b = 0 .. 2(P-1).
+struct FilterLaunch {
+    int P;
+    double v1[kMaxP * kMaxP], w[kMaxP];
+    double sig[2 * kMaxP - 1];
+};
+hipError_t launch_modal_filter(const FilterLaunch& f, long nrows, double* u,
+                               hipStream_t st);
 hipError_t launch_absmax(int N, const double* x, double* partial, int nblk,
                          double* out, hipStream_t st);
 hipError_t launch_trace_gather_g(int ntp, int P, const int* tpside,

@@ -537,3 +537,39 @@ extern "C" fr_status fr_explicit_rhs(fr_mesh_t m, const double* u, double* R,
     HIP_TRY(launch_residual(m->ops, a, hipStream_t(stream)));
     return FR_OK;
 }
+
+extern "C" fr_status fr_modal_filter(fr_mesh_t m, const fr_filter_params* prm,
+                                     double* u, void* stream) {
+    if (!m || !prm || !u) return fail(FR_E_INVALID, "null argument");
+    if (m->host_only) return fail(FR_E_INVALID, "host-only mesh");
+    const double alpha = prm->alpha, sx = prm->s, ec = prm->eta_c, kap = prm->kappa;
+    if (!std::isfinite(alpha) || !std::isfinite(sx) || !std::isfinite(ec) ||
+        !std::isfinite(kap) || alpha < 0.0 || sx <= 0.0 || kap < 0.0)
+        return fail(FR_E_INVALID, "filter parameters: need alpha >= 0, s > 0, "
+                                  "kappa >= 0, all finite");
+    FilterLaunch f{};
+    f.P = m->P;
+    for (int q = 0; q < m->P; ++q) {
+        const double x = m->ops.x[q];
+        f.w[q] = m->ops.w[q];
+        double p0 = 1.0, p1 = x;          // Legendre three-term recurrence
+        for (int a = 0; a < m->P; ++a) {
+            double pa = a == 0 ? 1.0 : x;
+            if (a >= 2) {
+                pa = ((2 * a - 1) * x * p1 - (a - 1) * p0) / a;
+                p0 = p1;
+                p1 = pa;
+            }
+            f.v1[q * m->P + a] = std::sqrt(a + 0.5) * pa;
+        }
+    }
+    const int emax = 2 * (m->P - 1);   // exponent sum of the top mode
+    for (int e = 0; e <= emax; ++e) {
+        double sg = 1.0;
+        if (e >= ec && emax > ec)
+            sg = std::exp(-alpha * std::pow((e - ec) / (emax - ec), sx));
+        f.sig[e] = std::pow(sg, kap);
+    }
+    HIP_TRY(launch_modal_filter(f, 4L * m->Ne, u, hipStream_t(stream)));
+    return FR_OK;
+}

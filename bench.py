@@ -224,6 +224,47 @@ def cpu_baseline(name):
                         f"iterations), {el:.1f} s single-threaded NumPy/SciPy"))
 
 
+def filter_rate(torch, mesh, u0, reps=20, replays=20):
+    """Modal filter (Appendix B, airfoil parameters) on the whole state.
+    Launches are captured in a HIP graph (reps per graph) so that host
+    launch cost stays out of the figure; the time per launch is the event
+    time of the replays divided by the launches.  A plain device copy of the
+    same bytes, timed the same way, shows what HBM reaches at this size."""
+    u = torch.from_numpy(u0).cuda()
+    dst = torch.empty_like(u)
+    prm = dict(alpha=100.0, s=1.0, eta_c=3.0, kappa=1.0)
+
+    def per_launch(fn):
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(3):
+                fn()
+        torch.cuda.current_stream().wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(reps):
+                fn()
+        g.replay()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(replays):
+            g.replay()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / (reps * replays)
+
+    us = per_launch(lambda: mesh.modal_filter(u, **prm))
+    copy_us = per_launch(lambda: dst.copy_(u))
+    nbytes = 2 * 8 * 4 * mesh.Ne * mesh.Np
+    return {"us_per_launch": us, "algorithmic_bytes": nbytes,
+            "achieved_GBps": nbytes / us * 1e-3,
+            "frac_of_hbm": nbytes / us * 1e-3 / PEAK["hbm_gbs"],
+            "same_size_copy_us": copy_us}
+
+
 def copy_calibration(nbytes, reps=5):
     """A plain device copy of known size (read nbytes, write nbytes), the
     reference for the HBM traffic counters."""
@@ -248,6 +289,8 @@ def main():
                     help="skip the interior-embedded trace forms")
     ap.add_argument("--newton-tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-filter", action="store_true",
+                    help="skip the modal-filter measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter reference)")
     args = ap.parse_args()
@@ -336,6 +379,8 @@ def main():
             line["efr_fp32_vs_fp64_rel_err"] = float(
                 (np.abs(a - b).max(axis=1) / np.abs(b).max(axis=1)).max())
         line["hfr_trace_unknowns"] = 4 * mesh.Ntp
+    if not args.no_filter:
+        line["modal_filter"] = filter_rate(torch, mesh, u0)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(line))

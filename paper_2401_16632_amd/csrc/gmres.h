@@ -11,7 +11,9 @@ struct GmresState {
     int done, converged, jlast, iters, cycles, pad;
     double inv_norm, beta, bnorm, target;
     double h1[kGmresMaxK], h2[kGmresMaxK];
-    double cs[kGmresMaxK], sn[kGmresMaxK], g[kGmresMaxK + 1];
+    double cs[kGmresMaxK], sn[kGmresMaxK];
+    double g[kGmresMaxK + 1];    // running right-hand side of the least squares
+    double gf[kGmresMaxK + 1];   // rotated (final) right-hand side
     double H[(kGmresMaxK + 1) * kGmresMaxK];
 };
 
@@ -42,10 +44,11 @@ hipError_t launch_precondition_matrix(int nblocks, int bs, const int* col,
                                       float* Lt32, hipStream_t st);
 hipError_t launch_gmres_restart(const GmresArgs& a, const double* x,
                                 double* w, int first, hipStream_t st);
-hipError_t launch_arnoldi_product(const GmresArgs& a, int j, const double* wcur,
-                                  double* wnxt, hipStream_t st);
+hipError_t launch_arnoldi_product(const GmresArgs& a, int j, int fin_prev,
+                                  const double* wcur, double* wnxt, hipStream_t st);
 hipError_t launch_arnoldi_orth(const GmresArgs& a, int j, double* wnxt,
                                hipStream_t st);
+hipError_t launch_arnoldi_finish(const GmresArgs& a, int j, hipStream_t st);
 hipError_t launch_gmres_update(const GmresArgs& a, double* x, hipStream_t st);
 
 }  // namespace hfr

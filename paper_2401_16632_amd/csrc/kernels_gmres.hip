@@ -3,13 +3,17 @@
 //
 // Right block-Jacobi preconditioning is folded into the matrix once per
 // linearisation: Lt = L Dinv (Dinv = inverse of each trace face's diagonal
-// block), so an Arnoldi step is one block-sparse product.  One Arnoldi step
-// is four kernels and no host synchronisation:
-//   A: v_j = w / |w| (own rows), y = Lt w / |w|, partial dots V_i . y
-//   B: w = y - sum h1_i V_i, partial dots V_i . w        (Gram-Schmidt, 1)
-//   C: w -= sum h2_i V_i, partial |w|^2                  (Gram-Schmidt, 2)
-//   D: |w|, Givens rotation, convergence flag
-// A fourth, one-workgroup kernel applies the Givens rotation.  Partial sums
+// block, Lt stored row-major per block so that a row is one contiguous
+// vector load), so an Arnoldi step is one block-sparse product.  One Arnoldi
+// step is three kernels and no host synchronisation:
+//   A: finish column j-1 (norm from C's partials, Givens rotation,
+//      convergence test; every workgroup forms the same values, workgroup 0
+//      stores them), v_j = w / |w| (own rows), y = Lt v_j, partial dots V_i . y
+//   B: reduce A's partials, w = y - sum h1_i V_i, partial dots V_i . w
+//                                                   (Gram-Schmidt, pass 1)
+//   C: reduce B's partials, w -= sum h2_i V_i, partial |w|^2   (pass 2)
+// The last step of a chunk of steps is closed by a one-workgroup kernel D
+// that finishes its column, so the host can read the state.  Partial sums
 // are reduced in a fixed order by the consuming kernel, so results are
 // deterministic.  Once the cycle has converged every later kernel of the
 // cycle returns at entry.
@@ -21,16 +25,20 @@ namespace hfr {
 namespace {
 
 constexpr int kThr = 512;        // threads per workgroup of the vector kernels
+constexpr int kRPT = 4;          // rows per thread (<= 2048 rows per block)
 
 __device__ __forceinline__ double wsum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
 
-// sum of per-thread values over the block for each i < k -> out[i]
+// Partial sums are stored value-major: partial[i * nb + b] is block b's
+// share of value i, so a reader of value i loads consecutive addresses.
+
+// sum of per-thread values over the block for each i < k -> out[i * stride]
 // (written by threads 0..k-1); red needs k * (blockDim/64) doubles
 template <class F>
-__device__ void block_partials(int k, F f, double* red, double* out) {
+__device__ void block_partials(int k, F f, double* red, double* out, int stride) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
     for (int i = 0; i < k; ++i) {
@@ -41,21 +49,29 @@ __device__ void block_partials(int k, F f, double* red, double* out) {
     for (int i = threadIdx.x; i < k; i += blockDim.x) {
         double s = 0.0;
         for (int w = 0; w < nw; ++w) s += red[i * nw + w];
-        out[i] = s;
+        out[size_t(i) * stride] = s;
     }
     __syncthreads();
 }
 
-// fixed-order sum over blocks of partial[b*ld + i] for i < k -> out[i] (LDS);
-// every block computes the same values
-__device__ void reduce_partials(int k, int nb, const double* partial, int ld,
-                                double* out) {
+// fixed-order sum over blocks of partial[i * nb + b] for i < k -> out[i]
+// (LDS); every block computes the same values.  Four independent
+// accumulators per lane keep several loads in flight.
+__device__ void reduce_partials(int k, int nb, const double* partial, double* out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
     for (int i = wave; i < k; i += nw) {
-        double s = 0.0;
-        for (int b = lane; b < nb; b += 64) s += partial[size_t(b) * ld + i];
-        s = wsum(s);
+        const double* p = partial + size_t(i) * nb;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int b = lane;
+        for (; b + 192 < nb; b += 256) {
+            s0 += p[b];
+            s1 += p[b + 64];
+            s2 += p[b + 128];
+            s3 += p[b + 192];
+        }
+        for (; b < nb; b += 64) s0 += p[b];
+        const double s = wsum((s0 + s1) + (s2 + s3));
         if (lane == 0) out[i] = s;
     }
     __syncthreads();
@@ -69,18 +85,110 @@ __device__ __forceinline__ void block_rows(const GmresArgs& a, int& r0, int& r1)
     r1 = f1 * a.bs;
 }
 
-__device__ __forceinline__ double spmv_row(const GmresArgs& a, const double* x,
-                                           int F, int aa) {
+// LDS copy of what the Givens step of column jc reads (all threads)
+struct GivensStage {
+    double hc[kGmresMaxK + 1];
+    double cs[kGmresMaxK], sn[kGmresMaxK];
+    double gj, target, dec[2];
+};
+
+__device__ void stage_givens(const GmresArgs& a, int jc, GivensStage& g) {
+    const GmresState* gs = a.gs;
+    for (int i = threadIdx.x; i <= jc; i += blockDim.x) {
+        g.hc[i] = gs->h1[i] + gs->h2[i];
+        if (i < jc) {
+            g.cs[i] = gs->cs[i];
+            g.sn[i] = gs->sn[i];
+        }
+    }
+    if (threadIdx.x == 0) {
+        g.gj = gs->g[jc];
+        g.target = gs->target;
+    }
+}
+
+// Givens step of column jc (thread 0 only, after stage_givens and a
+// barrier): H column from the two projections and the norm hn, rotations of
+// the earlier columns, the new rotation and the residual estimate.
+// gs->g[jc] (the running right-hand side) is only read; the rotated value
+// goes to gs->gf[jc] and the new running value to gs->g[jc+1], so workgroups
+// that form the same column concurrently never read what the writer stores.
+// g.dec[0] = done, g.dec[1] = 1/hn.
+__device__ void givens_column(const GmresArgs& a, int jc, double hn, bool write,
+                              GivensStage& g) {
+    GmresState* gs = a.gs;
+    const int R = a.restart;
+    double* hc = g.hc;
+    hc[jc + 1] = hn;
+    for (int i = 0; i < jc; ++i) {
+        const double t0 = g.cs[i] * hc[i] + g.sn[i] * hc[i + 1];
+        hc[i + 1] = -g.sn[i] * hc[i] + g.cs[i] * hc[i + 1];
+        hc[i] = t0;
+    }
+    const double den = sqrt(hc[jc] * hc[jc] + hc[jc + 1] * hc[jc + 1]);
+    const double c = den > 0.0 ? hc[jc] / den : 1.0;
+    const double sn = den > 0.0 ? hc[jc + 1] / den : 0.0;
+    hc[jc] = den;
+    hc[jc + 1] = 0.0;
+    const double gnext = -sn * g.gj;
+    const double res = fabs(gnext);
+    const bool done = res <= g.target || !(hn > 0.0) || jc == R - 1 || !(res == res);
+    const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
+    if (write) {
+        double* H = gs->H + size_t(jc) * (R + 1);
+        for (int i = 0; i <= jc + 1; ++i) H[i] = hc[i];
+        gs->cs[jc] = c;
+        gs->sn[jc] = sn;
+        gs->gf[jc] = c * g.gj;
+        gs->g[jc + 1] = gnext;
+        gs->jlast = jc;
+        gs->iters += 1;
+        gs->inv_norm = inv;
+        if (done) gs->done = 1;
+    }
+    g.dec[0] = done ? 1.0 : 0.0;
+    g.dec[1] = inv;
+}
+
+// Block-sparse product over rows [r0, r1) of the block's faces: 64 rows at a
+// time (up to 8 passes), thread group `part` takes blocks part, part+4, ...
+// of a row, the four shares are added in LDS.  Row-major blocks (Lt) are
+// read as contiguous vectors; column-major blocks (L) column by column
+// (consecutive lanes read consecutive rows of a column).
+template <bool ROW_MAJOR, typename T>
+__device__ __forceinline__ double row_share(const GmresArgs& a, const T* M,
+                                            const double* x, int r) {
     const int bs = a.bs;
-    double acc = 0.0;
+    const int F = r / bs, aa = r - F * bs;
+    const int part = threadIdx.x >> 6;
     const int p1 = a.rowptr[F + 1];
-    for (int p = a.rowptr[F]; p < p1; ++p) {
-        const size_t base = size_t(p) * bs * bs + aa;
-        const double* xb = x + size_t(a.col[p]) * bs;
-        if (a.Lt64) {
-            for (int b = 0; b < bs; ++b) acc += a.Lt64[base + size_t(b) * bs] * xb[b];
+    double acc = 0.0;
+    for (int p = a.rowptr[F] + part; p < p1; p += 4) {
+        const double2* x2 = reinterpret_cast<const double2*>(x + size_t(a.col[p]) * bs);
+        if (ROW_MAJOR) {
+            const T* row = M + (size_t(p) * bs + aa) * bs;
+            if constexpr (sizeof(T) == 8) {
+                const double2* l2 = reinterpret_cast<const double2*>(row);
+                for (int b = 0; b < bs / 2; ++b) {
+                    const double2 l = l2[b], xv = x2[b];
+                    acc = fma(double(l.x), xv.x, acc);
+                    acc = fma(double(l.y), xv.y, acc);
+                }
+            } else {
+                const float4* l4 = reinterpret_cast<const float4*>(row);
+                for (int b = 0; b < bs / 4; ++b) {
+                    const float4 l = l4[b];
+                    const double2 x0 = x2[2 * b], x1 = x2[2 * b + 1];
+                    acc = fma(double(l.x), x0.x, acc);
+                    acc = fma(double(l.y), x0.y, acc);
+                    acc = fma(double(l.z), x1.x, acc);
+                    acc = fma(double(l.w), x1.y, acc);
+                }
+            }
         } else {
-            for (int b = 0; b < bs; ++b) acc += double(a.Lt32[base + size_t(b) * bs]) * xb[b];
+            const T* blk = M + size_t(p) * bs * bs + aa;
+            const double* xb = x + size_t(a.col[p]) * bs;
+            for (int b = 0; b < bs; ++b) acc = fma(double(blk[size_t(b) * bs]), xb[b], acc);
         }
     }
     return acc;
@@ -88,58 +196,63 @@ __device__ __forceinline__ double spmv_row(const GmresArgs& a, const double* x,
 
 }  // namespace
 
-// Each workgroup owns the rows of a.fpb consecutive faces (a.nblk <= 256
-// workgroups of 512 threads) and loops over them.  Partial sums go to
-// a.part[block][i]; the next kernel reduces them in every workgroup (fixed
-// order), so no device-scope fences or counters are needed.
+// Each vector-kernel workgroup owns the rows of a.fpb consecutive faces
+// (a.nblk <= 256 workgroups of 512 threads).  Product kernels use their own
+// decomposition: a.nblkA workgroups of 256 threads owning a.fpbA faces.
+// Partial sums go to a partial buffer; the next kernel reduces them in
+// every workgroup (fixed order), so no device-scope fences or counters are
+// needed.
 
-constexpr int kRPT = 4;          // rows per thread (<= 2048 rows per block)
-
-// ---- A: scale, product, first projection ---------------------------------
-// Own decomposition: a.nblkA workgroups of 256 threads, 64 rows at a time,
-// four threads per row (thread group q takes blocks q, q+4, ... of the row).
-__global__ __launch_bounds__(256) void k_arnoldi_a(GmresArgs a, int j,
+// ---- A: finish column j-1, scale, product, first projection --------------
+// fin_prev: column j-1 was finished by D or by the restart (first step of a
+// chunk); otherwise this kernel finishes it.  The product does not depend on
+// the scale, so it is formed first.
+__global__ __launch_bounds__(256) void k_arnoldi_a(GmresArgs a, int j, int fin_prev,
                                                    const double* wcur,
                                                    double* wnxt) {
     GmresState* gs = a.gs;
     if (gs->done) return;
     __shared__ double red[kGmresMaxK * 4];
-    __shared__ double sacc[4][64];
-    const double inv = gs->inv_norm;
+    __shared__ double sacc[8][4][64];
+    __shared__ GivensStage gv;
     const int bs = a.bs;
     const int f0 = blockIdx.x * a.fpbA, f1 = min(a.ntf, f0 + a.fpbA);
     const int r0 = f0 * bs, r1 = f1 * bs;
     const int part = threadIdx.x >> 6, lr = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int r = r0 + 64 * q + lr;
+        if (r0 + 64 * q >= r1) break;             // uniform
+        double acc = 0.0;
+        if (r < r1)
+            acc = a.Lt64 ? row_share<true>(a, a.Lt64, wcur, r)
+                         : row_share<true>(a, a.Lt32, wcur, r);
+        sacc[q][part][lr] = acc;
+    }
+    double inv;
+    if (fin_prev) {
+        inv = gs->inv_norm;
+        __syncthreads();
+    } else {
+        stage_givens(a, j - 1, gv);
+        reduce_partials(1, a.nblk, a.part, red);   // ends with a barrier
+        if (threadIdx.x == 0) givens_column(a, j - 1, sqrt(red[0]), blockIdx.x == 0, gv);
+        __syncthreads();
+        if (gv.dec[0] != 0.0) return;             // same decision in every workgroup
+        inv = gv.dec[1];
+    }
     double yv[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         yv[q] = 0.0;
-        const int rb = r0 + 64 * q;
-        if (rb >= r1) continue;                   // uniform
-        const int r = rb + lr;
-        double acc = 0.0;
-        if (r < r1) {
-            const int F = r / bs, aa = r - F * bs;
-            const int p1 = a.rowptr[F + 1];
-            for (int p = a.rowptr[F] + part; p < p1; p += 4) {
-                const size_t base = size_t(p) * bs * bs + aa;
-                const double* xb = wcur + size_t(a.col[p]) * bs;
-                if (a.Lt64) {
-                    for (int b = 0; b < bs; ++b) acc += a.Lt64[base + size_t(b) * bs] * xb[b];
-                } else {
-                    for (int b = 0; b < bs; ++b) acc += double(a.Lt32[base + size_t(b) * bs]) * xb[b];
-                }
-            }
-        }
-        sacc[part][lr] = acc;
-        __syncthreads();
+        const int r = r0 + 64 * q + lr;
         if (part == 0 && r < r1) {
-            const double y = (sacc[0][lr] + sacc[1][lr] + sacc[2][lr] + sacc[3][lr]) * inv;
+            const double y = (sacc[q][0][lr] + sacc[q][1][lr] + sacc[q][2][lr] +
+                              sacc[q][3][lr]) * inv;
             a.V[size_t(j) * a.ldv + r] = wcur[r] * inv;
             wnxt[r] = y;
             yv[q] = y;
         }
-        __syncthreads();
     }
     // projections V_i . y over this block's rows (group 0 holds y)
     block_partials(j + 1, [&](int i) {
@@ -152,16 +265,7 @@ __global__ __launch_bounds__(256) void k_arnoldi_a(GmresArgs a, int j,
             }
         }
         return s;
-    }, red, a.part3 + size_t(blockIdx.x) * kGmresMaxK);
-}
-
-// ---- A2: reduce the product kernel's partials (one workgroup) ------------
-__global__ __launch_bounds__(512) void k_arnoldi_a2(GmresArgs a, int j) {
-    GmresState* gs = a.gs;
-    if (gs->done) return;
-    __shared__ double h[kGmresMaxK];
-    reduce_partials(j + 1, a.nblkA, a.part3, kGmresMaxK, h);
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) gs->h1[i] = h[i];
+    }, red, a.part3 + blockIdx.x, gridDim.x);
 }
 
 // ---- B: first orthogonalisation, second projection ------------------------
@@ -172,8 +276,9 @@ __global__ __launch_bounds__(kThr) void k_arnoldi_b(GmresArgs a, int j,
     __shared__ double red[kGmresMaxK * (kThr / 64)];
     __shared__ double h[kGmresMaxK];
     const int k = j + 1;
-    for (int i = threadIdx.x; i < k; i += blockDim.x) h[i] = gs->h1[i];
-    __syncthreads();
+    reduce_partials(k, a.nblkA, a.part3, h);
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < k; i += blockDim.x) gs->h1[i] = h[i];
     int r0, r1;
     block_rows(a, r0, r1);
     double x[kRPT];
@@ -196,7 +301,7 @@ __global__ __launch_bounds__(kThr) void k_arnoldi_b(GmresArgs a, int j,
             if (r < r1) s += a.V[size_t(i) * a.ldv + r] * x[q];
         }
         return s;
-    }, red, a.part2 + size_t(blockIdx.x) * kGmresMaxK);
+    }, red, a.part2 + blockIdx.x, gridDim.x);
 }
 
 // ---- C: second orthogonalisation, norm partials --------------------------
@@ -207,7 +312,7 @@ __global__ __launch_bounds__(kThr) void k_arnoldi_c(GmresArgs a, int j,
     __shared__ double red[kGmresMaxK * (kThr / 64)];
     __shared__ double h[kGmresMaxK];
     const int k = j + 1;
-    reduce_partials(k, gridDim.x, a.part2, kGmresMaxK, h);
+    reduce_partials(k, gridDim.x, a.part2, h);
     if (blockIdx.x == 0)
         for (int i = threadIdx.x; i < k; i += blockDim.x) gs->h2[i] = h[i];
     int r0, r1;
@@ -219,42 +324,18 @@ __global__ __launch_bounds__(kThr) void k_arnoldi_c(GmresArgs a, int j,
         w[r] = x;
         nn += x * x;
     }
-    block_partials(1, [&](int) { return nn; }, red, a.part + size_t(blockIdx.x) * kGmresMaxK);
+    block_partials(1, [&](int) { return nn; }, red, a.part + blockIdx.x, gridDim.x);
 }
 
-// ---- D: norm, Givens rotation, convergence flag (one workgroup) ----------
+// ---- D: finish the last column of a chunk (one workgroup) -----------------
 __global__ __launch_bounds__(kThr) void k_arnoldi_d(GmresArgs a, int j) {
     GmresState* gs = a.gs;
     if (gs->done) return;
     __shared__ double fin[kGmresMaxK];
-    reduce_partials(1, a.nblk, a.part, kGmresMaxK, fin);
-    if (threadIdx.x == 0) {
-        const int R = a.restart;
-        double* hc = gs->H + size_t(j) * (R + 1);
-        const double hn = sqrt(fin[0]);
-        for (int i = 0; i <= j; ++i) hc[i] = gs->h1[i] + gs->h2[i];
-        hc[j + 1] = hn;
-        for (int i = 0; i < j; ++i) {
-            const double t0 = gs->cs[i] * hc[i] + gs->sn[i] * hc[i + 1];
-            hc[i + 1] = -gs->sn[i] * hc[i] + gs->cs[i] * hc[i + 1];
-            hc[i] = t0;
-        }
-        const double den = sqrt(hc[j] * hc[j] + hc[j + 1] * hc[j + 1]);
-        const double c = den > 0.0 ? hc[j] / den : 1.0;
-        const double s = den > 0.0 ? hc[j + 1] / den : 0.0;
-        gs->cs[j] = c;
-        gs->sn[j] = s;
-        hc[j] = den;
-        hc[j + 1] = 0.0;
-        gs->g[j + 1] = -s * gs->g[j];
-        gs->g[j] = c * gs->g[j];
-        gs->jlast = j;
-        gs->iters += 1;
-        gs->inv_norm = hn > 0.0 ? 1.0 / hn : 0.0;
-        const double res = fabs(gs->g[j + 1]);
-        if (res <= gs->target || !(hn > 0.0) || j == R - 1 || !(res == res))
-            gs->done = 1;
-    }
+    __shared__ GivensStage gv;
+    stage_givens(a, j, gv);
+    reduce_partials(1, a.nblk, a.part, fin);       // ends with a barrier
+    if (threadIdx.x == 0) givens_column(a, j, sqrt(fin[0]), true, gv);
 }
 
 // ---- end of a cycle: y = H^-1 g, x += Dinv (V y) --------------------------
@@ -262,14 +343,22 @@ __global__ __launch_bounds__(kThr) void k_gmres_update(GmresArgs a, double* x) {
     GmresState* gs = a.gs;
     __shared__ double y[kGmresMaxK];
     __shared__ double z[kThr];
+    __shared__ double Hs[kGmresMaxK * kGmresMaxK];
     const int jl = gs->jlast;
     if (jl < 0) return;
+    const int R = a.restart;
+    const int n = jl + 1;
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+        const int k = t / n, i = t - k * n;       // column k, row i
+        Hs[t] = gs->H[size_t(k) * (R + 1) + i];
+    }
+    for (int t = threadIdx.x; t < n; t += blockDim.x) y[t] = gs->gf[t];
+    __syncthreads();
     if (threadIdx.x == 0) {
-        const int R = a.restart;
         for (int i = jl; i >= 0; --i) {
-            double acc = gs->g[i];
-            for (int k = i + 1; k <= jl; ++k) acc -= gs->H[size_t(k) * (R + 1) + i] * y[k];
-            y[i] = acc / gs->H[size_t(i) * (R + 1) + i];
+            double acc = y[i];
+            for (int k = i + 1; k <= jl; ++k) acc -= Hs[k * n + i] * y[k];
+            y[i] = acc / Hs[i * n + i];
         }
     }
     __syncthreads();
@@ -303,40 +392,49 @@ __global__ __launch_bounds__(kThr) void k_gmres_update(GmresArgs a, double* x) {
 }
 
 // ---- restart: r = t - L x (FP64), partial |r|^2 ---------------------------
-__global__ __launch_bounds__(kThr) void k_gmres_residual(GmresArgs a,
-                                                         const double* x,
-                                                         double* w, int first) {
-    __shared__ double red[kThr / 64];
-    int r0, r1;
-    block_rows(a, r0, r1);
-    double nn = 0.0;
-    for (int r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-        const int F = r / a.bs, aa = r - F * a.bs;
-        double lx = 0.0;
-        if (!first) {
-            const int bs = a.bs;
-            for (int p = a.rowptr[F]; p < a.rowptr[F + 1]; ++p) {
-                const size_t base = size_t(p) * bs * bs + aa;
-                const double* xb = x + size_t(a.col[p]) * bs;
-                if (a.L64) {
-                    for (int b = 0; b < bs; ++b) lx += a.L64[base + size_t(b) * bs] * xb[b];
-                } else {
-                    for (int b = 0; b < bs; ++b) lx += double(a.L32[base + size_t(b) * bs]) * xb[b];
-                }
-            }
+// Product decomposition of A (a.nblkA workgroups of 256 threads).
+__global__ __launch_bounds__(256) void k_gmres_residual(GmresArgs a,
+                                                        const double* x,
+                                                        double* w, int first) {
+    __shared__ double red[4];
+    __shared__ double sacc[8][4][64];
+    const int bs = a.bs;
+    const int f0 = blockIdx.x * a.fpbA, f1 = min(a.ntf, f0 + a.fpbA);
+    const int r0 = f0 * bs, r1 = f1 * bs;
+    const int part = threadIdx.x >> 6, lr = threadIdx.x & 63;
+    if (!first) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int r = r0 + 64 * q + lr;
+            if (r0 + 64 * q >= r1) break;         // uniform
+            double acc = 0.0;
+            if (r < r1)
+                acc = a.L64 ? row_share<false>(a, a.L64, x, r)
+                            : row_share<false>(a, a.L32, x, r);
+            sacc[q][part][lr] = acc;
         }
-        const double v = a.t[r] - lx;
-        w[r] = v;
-        nn += v * v;
+        __syncthreads();
     }
-    block_partials(1, [&](int) { return nn; }, red, a.part + size_t(blockIdx.x) * kGmresMaxK);
+    double nn = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int r = r0 + 64 * q + lr;
+        if (part == 0 && r < r1) {
+            const double lx = first ? 0.0 : (sacc[q][0][lr] + sacc[q][1][lr] +
+                                             sacc[q][2][lr] + sacc[q][3][lr]);
+            const double v = a.t[r] - lx;
+            w[r] = v;
+            nn += v * v;
+        }
+    }
+    block_partials(1, [&](int) { return nn; }, red, a.part3 + blockIdx.x, gridDim.x);
 }
 
 // beta = |r|, new cycle (one workgroup)
 __global__ __launch_bounds__(kThr) void k_gmres_restart(GmresArgs a, int first) {
     GmresState* gs = a.gs;
     __shared__ double fin[kGmresMaxK];
-    reduce_partials(1, a.nblk, a.part, kGmresMaxK, fin);
+    reduce_partials(1, a.nblkA, a.part3, fin);
     if (threadIdx.x == 0) {
         const double beta = sqrt(fin[0]);
         if (first) {
@@ -366,7 +464,8 @@ __device__ __forceinline__ double load_pc(const uint16_t* d, size_t i) {
 
 // ---- Lt = L Dinv (per block: Lt_FG = L_FG Dinv_G) -------------------------
 // One wave per block, four blocks per workgroup; both factors staged in LDS
-// (FP64), each lane forms BS*BS/64 entries of the product.
+// (FP64, Dinv transposed), each lane forms BS*BS/64 entries of the product.
+// L and Dinv are column-major per block; Lt is written row-major.
 template <int BS, typename TL, typename TD>
 __global__ __launch_bounds__(256) void k_precondition_matrix(int nblocks, const int* col,
                                                              const TL* L, const TD* Dinv,
@@ -378,18 +477,19 @@ __global__ __launch_bounds__(256) void k_precondition_matrix(int nblocks, const 
     if (p >= nblocks) return;                      // whole wave
     const size_t lb = size_t(p) * BB, db = size_t(col[p]) * BB;
     for (int i = lane; i < BB; i += 64) {
+        const int b = i / BS, c = i - b * BS;     // Dinv entry (c, b)
         sL[wv][i] = double(L[lb + i]);
-        sD[wv][i] = load_pc(Dinv, db + i);
+        sD[wv][c * BS + b] = load_pc(Dinv, db + i);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // entry (a, b) of the column-major product: sum_c L[a][c] Dinv[c][b]
+    // entry (a, b) of the product, stored at a*BS + b: sum_c L[a][c] Dinv[c][b]
     for (int i = lane; i < BB; i += 64) {
-        const int b = i / BS, a = i - b * BS;
+        const int a = i / BS, b = i - a * BS;
         double acc = 0.0;
 #pragma unroll
-        for (int c = 0; c < BS; ++c) acc = fma(sL[wv][c * BS + a], sD[wv][b * BS + c], acc);
+        for (int c = 0; c < BS; ++c) acc = fma(sL[wv][c * BS + a], sD[wv][c * BS + b], acc);
         Lt[lb + i] = TL(acc);
     }
 }
@@ -435,16 +535,16 @@ hipError_t launch_precondition_matrix(int nblocks, int bs, const int* col,
 
 hipError_t launch_gmres_restart(const GmresArgs& a, const double* x,
                                 double* w, int first, hipStream_t st) {
-    hipLaunchKernelGGL(k_gmres_residual, dim3(a.nblk), dim3(kThr), 0, st, a, x,
+    hipLaunchKernelGGL(k_gmres_residual, dim3(a.nblkA), dim3(256), 0, st, a, x,
                        w, first);
     hipLaunchKernelGGL(k_gmres_restart, dim3(1), dim3(kThr), 0, st, a, first);
     return hipGetLastError();
 }
 
-hipError_t launch_arnoldi_product(const GmresArgs& a, int j, const double* wcur,
-                                  double* wnxt, hipStream_t st) {
-    hipLaunchKernelGGL(k_arnoldi_a, dim3(a.nblkA), dim3(256), 0, st, a, j, wcur, wnxt);
-    hipLaunchKernelGGL(k_arnoldi_a2, dim3(1), dim3(512), 0, st, a, j);
+hipError_t launch_arnoldi_product(const GmresArgs& a, int j, int fin_prev,
+                                  const double* wcur, double* wnxt, hipStream_t st) {
+    hipLaunchKernelGGL(k_arnoldi_a, dim3(a.nblkA), dim3(256), 0, st, a, j, fin_prev,
+                       wcur, wnxt);
     return hipGetLastError();
 }
 
@@ -452,6 +552,10 @@ hipError_t launch_arnoldi_orth(const GmresArgs& a, int j, double* wnxt,
                                hipStream_t st) {
     hipLaunchKernelGGL(k_arnoldi_b, dim3(a.nblk), dim3(kThr), 0, st, a, j, wnxt);
     hipLaunchKernelGGL(k_arnoldi_c, dim3(a.nblk), dim3(kThr), 0, st, a, j, wnxt);
+    return hipGetLastError();
+}
+
+hipError_t launch_arnoldi_finish(const GmresArgs& a, int j, hipStream_t st) {
     hipLaunchKernelGGL(k_arnoldi_d, dim3(1), dim3(kThr), 0, st, a, j);
     return hipGetLastError();
 }

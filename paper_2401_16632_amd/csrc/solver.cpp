@@ -433,10 +433,11 @@ fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
                 double* wc = j % 2 ? W1 : W0;
                 double* wn = j % 2 ? W0 : W1;
                 const int tk = tbegin(s, HFR_T_SPMV, st);
-                HIP_TRY(launch_arnoldi_product(a, j, wc, wn, st));
+                HIP_TRY(launch_arnoldi_product(a, j, c == 0 ? 1 : 0, wc, wn, st));
                 tend(s, tk, st);
                 HIP_TRY(launch_arnoldi_orth(a, j, wn, st));
             }
+            HIP_TRY(launch_arnoldi_finish(a, j - 1, st));
             launched += steps;
             if ((e = fetch())) return e;
             if (hs.done) break;
@@ -465,6 +466,18 @@ fr_status absmax_host(hfr_solver_s* s, int N, const double* x, double* out,
     return sync_check(st);
 }
 
+// max |x| and max |y| with one host synchronisation
+fr_status absmax2_host(hfr_solver_s* s, int Nx, const double* x, int Ny,
+                       const double* y, double* out, hipStream_t st) {
+    const int nbx = std::min(1024, std::max(1, (Nx + 255) / 256));
+    const int nby = std::min(1024, std::max(1, (Ny + 255) / 256));
+    HIP_TRY(launch_absmax(Nx, x, s->scratch, nbx, s->dots + 140, st));
+    HIP_TRY(launch_absmax(Ny, y, s->scratch, nby, s->dots + 141, st));
+    HIP_TRY(hipMemcpyAsync(out, s->dots + 140, 2 * sizeof(double),
+                           hipMemcpyDeviceToHost, st));
+    return sync_check(st);
+}
+
 fr_status newton(hfr_solver_s* s, double* u, double* uhat,
                  const double* ustar, double aii_dt, hfr_newton_stats* stats,
                  hipStream_t st) {
@@ -479,9 +492,9 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
     for (int it = 0;; ++it) {
         e = residual_internal(s, u, uhat, ustar, aii_dt, nullptr, st);
         if (e) return e;
-        double hmax = 0.0, gmax = 0.0;
-        if ((e = absmax_host(s, nu, s->h, &hmax, st))) return e;
-        if ((e = absmax_host(s, 4 * m->Ntp, s->g, &gmax, st))) return e;
+        double hg[2] = {0.0, 0.0};
+        if ((e = absmax2_host(s, nu, s->h, 4 * m->Ntp, s->g, hg, st))) return e;
+        const double hmax = hg[0], gmax = hg[1];
         const double res = std::max(hmax, gmax);
         if (s->verbose)
             fprintf(stderr, "[hfr] newton it %d |h| %.3e |g| %.3e tol %.3e\n", it,

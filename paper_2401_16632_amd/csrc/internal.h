@@ -101,6 +101,10 @@ struct CondenseLaunch {
     int* pivot_fail;         // set to 1 if a zero pivot is met
     int* piv;                // [Nim][n] pivot row p_k of each exchange
     const int* efr_fnodes;   // [Ntf][P] trace nodes (interior-embedded trace) or null
+    // optional: the sweep also forms the FP64 right-hand side of
+    // launch_rhs64 from its registers (yr [Nim][n], z [Nim][m]) when set
+    double* yr;
+    double* z;
 };
 // element linearisation and the tableau [A B; C D] (must precede
 // launch_condense, which sweeps the tableau in place)

@@ -403,6 +403,11 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
     __shared__ T gbuf[2][RPL * 64];
     __shared__ T ibuf[2];
     __shared__ int pbuf[2];
+    // right-hand side epilogue: pivot rows, permuted -h, per-wave row sums
+    constexpr int NRW = (n + NCW - 1) / NCW;    // waves owning columns of A
+    __shared__ short pl[n];
+    __shared__ double sr[n];
+    __shared__ double racc[NRW][RPL * 64];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int k = blockIdx.x;
@@ -489,6 +494,7 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
             if (threadIdx.x == 0) *a.pivot_fail = 1;
             return;                                // uniform over the workgroup
         }
+        if (threadIdx.x == 0) pl[kk] = short(p);
         const int sp = p >> 6, lp = p & 63;
 #pragma unroll
         for (int s = 0; s < RPL; ++s)
@@ -551,6 +557,44 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
             ipv = ipn;
 #pragma unroll
             for (int s = 0; s < RPL; ++s) gs[s] = gn[s];
+        }
+    }
+
+    // ---- FP64 right-hand side from the registers (as launch_rhs64):
+    // yr/z[row] = sum_{j<n} T(sig*t)[row][j] * (-h[p_j]), each wave over its
+    // columns of A, the waves' sums added in a fixed order
+    if (a.yr) {
+        constexpr int NP = P * P, m = N - n;
+        __syncthreads();                           // pl complete
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            const int row = pl[j];
+            sr[j] = -a.h[size_t(row & 3) * a.nimp * NP + size_t(k) * NP + (row >> 2)];
+        }
+        __syncthreads();
+        if (c0 < n) {                              // uniform over the wave
+            double acc[RPL];
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) acc[s] = 0.0;
+#pragma unroll
+            for (int j = 0; j < NCW; ++j) {
+                const int col = c0 + j;
+                if (col < n) {
+                    const double rj = sr[col];
+#pragma unroll
+                    for (int s = 0; s < RPL; ++s)
+                        acc[s] = fma(double(T(sig[s] * t[s][j / CH][j % CH])), rj, acc[s]);
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) racc[w][lane + 64 * s] = acc[s];
+        }
+        __syncthreads();
+        for (int row = threadIdx.x; row < N; row += blockDim.x) {
+            double v = 0.0;
+#pragma unroll
+            for (int q = 0; q < NRW; ++q) v += racc[q][row];
+            if (row < n) a.yr[size_t(k) * n + row] = v;
+            else a.z[size_t(k) * m + row - n] = v;
         }
     }
 

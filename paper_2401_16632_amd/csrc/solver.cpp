@@ -265,10 +265,10 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
     HIP_TRY(launch_tableau_fill(m->ops, c, st));
     tend(s, tk, st);
     tk = tbegin(s, HFR_T_CONDENSE, st);
+    c.yr = s->yr;                       // the sweep also forms the FP64 right-hand side
+    c.z = s->zz;
     HIP_TRY(launch_condense(m->ops, c, st));
     tend(s, tk, st);
-    HIP_TRY(launch_rhs64(m->P, m->Nim, s->M, s->opts.precision, s->piv, s->h,
-                         s->yr, s->zz, st));
     if (s->nbr == 0) return FR_OK;
     if (m->efr) {
         tk = tbegin(s, HFR_T_ASSEMBLE, st);

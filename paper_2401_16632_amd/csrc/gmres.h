@@ -42,13 +42,15 @@ hipError_t launch_precondition_matrix(int nblocks, int bs, const int* col,
                                       const double* L64, const float* L32,
                                       int pc, const void* Dinv, double* Lt64,
                                       float* Lt32, hipStream_t st);
+// r = t - L x, beta = |r|, new cycle; cond: only if the cycle has ended
 hipError_t launch_gmres_restart(const GmresArgs& a, const double* x,
-                                double* w, int first, hipStream_t st);
+                                double* w, int first, int cond, hipStream_t st);
 hipError_t launch_arnoldi_product(const GmresArgs& a, int j, int fin_prev,
                                   const double* wcur, double* wnxt, hipStream_t st);
 hipError_t launch_arnoldi_orth(const GmresArgs& a, int j, double* wnxt,
                                hipStream_t st);
 hipError_t launch_arnoldi_finish(const GmresArgs& a, int j, hipStream_t st);
-hipError_t launch_gmres_update(const GmresArgs& a, double* x, hipStream_t st);
+hipError_t launch_gmres_update(const GmresArgs& a, double* x, int cond,
+                               hipStream_t st);
 
 }  // namespace hfr

@@ -105,6 +105,9 @@ struct CondenseLaunch {
     // launch_rhs64 from its registers (yr [Nim][n], z [Nim][m]) when set
     double* yr;
     double* z;
+    // optional: the fill returns at entry when *go == 0 (a fill launched
+    // before the host has read the Newton convergence test)
+    const int* go;
 };
 // element linearisation and the tableau [A B; C D] (must precede
 // launch_condense, which sweeps the tableau in place)
@@ -210,6 +213,8 @@ hipError_t launch_modal_filter(const FilterLaunch& f, long nrows, double* u,
                                hipStream_t st);
 hipError_t launch_absmax(int N, const double* x, double* partial, int nblk,
                          double* out, hipStream_t st);
+// *go = 0 when both norms hg[0], hg[1] are <= tol, else 1 (NaN included)
+hipError_t launch_newton_go(const double* hg, double tol, int* go, hipStream_t st);
 hipError_t launch_trace_gather_g(int ntp, int P, const int* tpside,
                                  const double* gk, double* g,
                                  hipStream_t st);

@@ -365,6 +365,7 @@ __global__ __launch_bounds__(256) void k_tableau_fill(CondenseLaunch a, RefOps o
     constexpr int NP = P * P, n = 4 * NP, m = 16 * P, N = n + m, NB = NP + 4 * P;
     __shared__ CondShared<P> sh;
     __shared__ RefOps o;
+    if (a.go && *a.go == 0) return;            // uniform over the grid
     const int k = blockIdx.x;
     if (threadIdx.x == 0) o = og;
     __syncthreads();

@@ -339,8 +339,10 @@ __global__ __launch_bounds__(kThr) void k_arnoldi_d(GmresArgs a, int j) {
 }
 
 // ---- end of a cycle: y = H^-1 g, x += Dinv (V y) --------------------------
-__global__ __launch_bounds__(kThr) void k_gmres_update(GmresArgs a, double* x) {
+// cond: only when the cycle has ended (gs->done), else return at entry
+__global__ __launch_bounds__(kThr) void k_gmres_update(GmresArgs a, double* x, int cond) {
     GmresState* gs = a.gs;
+    if (cond && !gs->done) return;
     __shared__ double y[kGmresMaxK];
     __shared__ double z[kThr];
     __shared__ double Hs[kGmresMaxK * kGmresMaxK];
@@ -395,7 +397,8 @@ __global__ __launch_bounds__(kThr) void k_gmres_update(GmresArgs a, double* x) {
 // Product decomposition of A (a.nblkA workgroups of 256 threads).
 __global__ __launch_bounds__(256) void k_gmres_residual(GmresArgs a,
                                                         const double* x,
-                                                        double* w, int first) {
+                                                        double* w, int first, int cond) {
+    if (cond && !a.gs->done) return;
     __shared__ double red[4];
     __shared__ double sacc[8][4][64];
     const int bs = a.bs;
@@ -431,8 +434,9 @@ __global__ __launch_bounds__(256) void k_gmres_residual(GmresArgs a,
 }
 
 // beta = |r|, new cycle (one workgroup)
-__global__ __launch_bounds__(kThr) void k_gmres_restart(GmresArgs a, int first) {
+__global__ __launch_bounds__(kThr) void k_gmres_restart(GmresArgs a, int first, int cond) {
     GmresState* gs = a.gs;
+    if (cond && !gs->done) return;
     __shared__ double fin[kGmresMaxK];
     reduce_partials(1, a.nblkA, a.part3, fin);
     if (threadIdx.x == 0) {
@@ -534,10 +538,10 @@ hipError_t launch_precondition_matrix(int nblocks, int bs, const int* col,
 }
 
 hipError_t launch_gmres_restart(const GmresArgs& a, const double* x,
-                                double* w, int first, hipStream_t st) {
+                                double* w, int first, int cond, hipStream_t st) {
     hipLaunchKernelGGL(k_gmres_residual, dim3(a.nblkA), dim3(256), 0, st, a, x,
-                       w, first);
-    hipLaunchKernelGGL(k_gmres_restart, dim3(1), dim3(kThr), 0, st, a, first);
+                       w, first, cond);
+    hipLaunchKernelGGL(k_gmres_restart, dim3(1), dim3(kThr), 0, st, a, first, cond);
     return hipGetLastError();
 }
 
@@ -560,8 +564,9 @@ hipError_t launch_arnoldi_finish(const GmresArgs& a, int j, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_gmres_update(const GmresArgs& a, double* x, hipStream_t st) {
-    hipLaunchKernelGGL(k_gmres_update, dim3(a.nblk), dim3(kThr), 0, st, a, x);
+hipError_t launch_gmres_update(const GmresArgs& a, double* x, int cond,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_gmres_update, dim3(a.nblk), dim3(kThr), 0, st, a, x, cond);
     return hipGetLastError();
 }
 

@@ -377,6 +377,15 @@ hipError_t launch_absmax(int N, const double* x, double* partial, int nblk,
     return hipGetLastError();
 }
 
+__global__ void k_newton_go(const double* hg, double tol, int* go) {
+    if (threadIdx.x == 0) *go = (hg[0] <= tol && hg[1] <= tol) ? 0 : 1;
+}
+
+hipError_t launch_newton_go(const double* hg, double tol, int* go, hipStream_t st) {
+    hipLaunchKernelGGL(k_newton_go, dim3(1), dim3(64), 0, st, hg, tol, go);
+    return hipGetLastError();
+}
+
 // ---- recovery (eq:localproblems) from the swept element tableau:
 // du[k] = (A^-1 r)[k] - (A^-1 B duhat_loc)[k] = y~[p_k] + T[p_k][n:N] duhat_loc
 // with y~ from the FP64 right-hand-side pass (pivot-row order).  One wave

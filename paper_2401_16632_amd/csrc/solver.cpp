@@ -83,6 +83,9 @@ struct hfr_solver_s {
     double* scratch = nullptr;  // partials
     double* dots = nullptr;  // small device vector
     double* coef = nullptr;
+    int* go = nullptr;       // 1 while the Newton residual is above tolerance
+    double* hpin = nullptr;  // pinned host readback buffer (kPinDoubles)
+    hipEvent_t rb_ev = nullptr;  // marks the readback on the solver's stream
     size_t ws_bytes = 0;
     int nblk_dot = 1;
     // event timers
@@ -150,6 +153,10 @@ fr_status dalloc(T** p, size_t count, size_t& total) {
 
 void free_solver(hfr_solver_s* s) {
     tflush(s);
+    if (s->hpin) (void)hipHostFree(s->hpin);
+    if (s->rb_ev) (void)hipEventDestroy(s->rb_ev);
+    s->hpin = nullptr;
+    s->rb_ev = nullptr;
     for (auto& p : s->pool) {
         (void)hipEventDestroy(p.first);
         (void)hipEventDestroy(p.second);
@@ -161,8 +168,25 @@ void free_solver(hfr_solver_s* s) {
                     s->flags, s->V, s->z, s->r, s->scratch, s->dots, s->coef,
                     s->Lt64, s->Lt32, s->W, s->gs, s->part, s->part2,
                     s->counters, s->piv, s->yr, s->zz, s->part3,
-                    s->efr_cptr, s->efr_contrib};
+                    s->efr_cptr, s->efr_contrib, s->go};
     for (void* p : ptrs) (void)hipFree(p);
+}
+
+constexpr int kPinDoubles = 64;
+
+// Queue a device-to-host copy into the pinned buffer and mark it; work
+// queued after it runs while the host waits in readback_wait.
+fr_status readback(hfr_solver_s* s, const void* dev, size_t bytes, hipStream_t st) {
+    HIP_TRY(hipMemcpyAsync(s->hpin, dev, bytes, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(s->rb_ev, st));
+    return FR_OK;
+}
+
+fr_status readback_wait(hfr_solver_s* s) {
+    hipError_t e = hipEventSynchronize(s->rb_ev);
+    if (e != hipSuccess)
+        return fail(FR_E_DEVICE, std::string("device error: ") + hipGetErrorString(e));
+    return FR_OK;
 }
 
 fr_status sync_check(hipStream_t st) {
@@ -237,11 +261,9 @@ fr_status efr_assemble(hfr_solver_s* s, bool with_matrix, hipStream_t st) {
     return FR_OK;
 }
 
-fr_status condense_internal(hfr_solver_s* s, const double* u,
-                            const double* uhat, double aii_dt,
-                            hipStream_t st) {
+CondenseLaunch condense_launch(hfr_solver_s* s, const double* u,
+                               const double* uhat, double aii_dt) {
     fr_mesh_s* m = s->mesh;
-    if (m->Nim == 0) return FR_OK;
     CondenseLaunch c{};
     c.imp_list = m->d_imp;
     c.nimp = m->Nim;
@@ -261,10 +283,36 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
     c.pivot_fail = s->flags;
     c.piv = s->piv;
     c.efr_fnodes = m->efr ? m->d_efr_fnodes : nullptr;
-    int tk = tbegin(s, HFR_T_FILL, st);
+    return c;
+}
+
+// Fill of the element tableaus; with `go`, every workgroup returns at entry
+// when the device flag says the Newton iteration has converged.
+fr_status condense_fill(hfr_solver_s* s, const double* u, const double* uhat,
+                        double aii_dt, const int* go, hipStream_t st) {
+    fr_mesh_s* m = s->mesh;
+    if (m->Nim == 0) return FR_OK;
+    CondenseLaunch c = condense_launch(s, u, uhat, aii_dt);
+    c.go = go;
+    const int tk = tbegin(s, HFR_T_FILL, st);
     HIP_TRY(launch_tableau_fill(m->ops, c, st));
     tend(s, tk, st);
-    tk = tbegin(s, HFR_T_CONDENSE, st);
+    return FR_OK;
+}
+
+// Sweep, assembly and preconditioner; fill_done: the fill of (u, uhat) has
+// already been queued.
+fr_status condense_internal(hfr_solver_s* s, const double* u,
+                            const double* uhat, double aii_dt,
+                            hipStream_t st, bool fill_done = false) {
+    fr_mesh_s* m = s->mesh;
+    if (m->Nim == 0) return FR_OK;
+    if (!fill_done) {
+        fr_status e = condense_fill(s, u, uhat, aii_dt, nullptr, st);
+        if (e) return e;
+    }
+    CondenseLaunch c = condense_launch(s, u, uhat, aii_dt);
+    int tk = tbegin(s, HFR_T_CONDENSE, st);
     c.yr = s->yr;                       // the sweep also forms the FP64 right-hand side
     c.z = s->zz;
     HIP_TRY(launch_condense(m->ops, c, st));
@@ -387,9 +435,12 @@ GmresArgs gmres_args(hfr_solver_s* s) {
 }
 
 // Restarted GMRES.  Arnoldi steps are launched in chunks (the first sized
-// by the previous solve's iteration count) with one host synchronisation per
-// chunk to read the convergence flag; within a chunk there are no host
-// round trips, and steps after convergence return at entry.
+// by the previous solve's iteration count).  Each chunk is followed by the
+// end-of-cycle kernels (update, true residual, restart) in their conditional
+// form, which act only if the cycle has ended, and by one readback of the
+// state: a solve that converges within its first chunk costs one host
+// synchronisation.  Within a chunk there are no host round trips, and steps
+// after convergence return at entry.
 fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
                 hipStream_t st) {
     const int N = s->N;
@@ -404,49 +455,52 @@ fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
     const int maxit = std::max(1, s->opts.gmres_max_iters);
     double* W0 = s->W;
     double* W1 = s->W + N;
-    struct {
+    struct HostState {
         int done, converged, jlast, iters, cycles, pad;
         double inv_norm, beta, bnorm, target;
-    } hs{};
+    };
+    static_assert(sizeof(HostState) <= kPinDoubles * sizeof(double), "readback size");
+    HostState hs{};
     auto fetch = [&]() -> fr_status {
-        HIP_TRY(hipMemcpyAsync(&hs, s->gs, sizeof(hs), hipMemcpyDeviceToHost, st));
-        fr_status e = sync_check(st);
+        fr_status e = readback(s, s->gs, sizeof(hs), st);
         if (e) return e;
+        if ((e = readback_wait(s))) return e;
+        std::memcpy(&hs, s->hpin, sizeof(hs));
         if (!(hs.beta == hs.beta) || std::isinf(hs.beta))
             return fail(FR_E_NONFINITE, "non-finite trace residual");
         return FR_OK;
     };
-    HIP_TRY(launch_gmres_restart(a, x, W0, 1, st));
+    HIP_TRY(launch_gmres_restart(a, x, W0, 1, 0, st));
     int launched = 0;
     int chunk = std::max(2, std::min(R, s->last_gmres_iters + 1));
-    bool first_cycle = true;
+    int cycles_seen = 0;
+    int j = 0;
     fr_status e;
     for (;;) {
-        if (!first_cycle) {
-            if ((e = fetch())) return e;
-            if (hs.converged || launched >= maxit) break;
+        const int steps = std::max(0, std::min(std::min(chunk, R - j), maxit - launched));
+        for (int c = 0; c < steps; ++c, ++j) {
+            double* wc = j % 2 ? W1 : W0;
+            double* wn = j % 2 ? W0 : W1;
+            const int tk = tbegin(s, HFR_T_SPMV, st);
+            HIP_TRY(launch_arnoldi_product(a, j, c == 0 ? 1 : 0, wc, wn, st));
+            tend(s, tk, st);
+            HIP_TRY(launch_arnoldi_orth(a, j, wn, st));
         }
-        int j = 0;
-        while (j < R && launched < maxit) {
-            const int steps = std::min(std::min(chunk, R - j), maxit - launched);
-            for (int c = 0; c < steps; ++c, ++j) {
-                double* wc = j % 2 ? W1 : W0;
-                double* wn = j % 2 ? W0 : W1;
-                const int tk = tbegin(s, HFR_T_SPMV, st);
-                HIP_TRY(launch_arnoldi_product(a, j, c == 0 ? 1 : 0, wc, wn, st));
-                tend(s, tk, st);
-                HIP_TRY(launch_arnoldi_orth(a, j, wn, st));
-            }
-            HIP_TRY(launch_arnoldi_finish(a, j - 1, st));
-            launched += steps;
-            if ((e = fetch())) return e;
-            if (hs.done) break;
+        if (steps > 0) HIP_TRY(launch_arnoldi_finish(a, j - 1, st));
+        launched += steps;
+        // at the iteration cap the cycle is ended whether or not it is done
+        const int cond = launched >= maxit ? 0 : 1;
+        HIP_TRY(launch_gmres_update(a, x, cond, st));
+        HIP_TRY(launch_gmres_restart(a, x, W0, 0, cond, st));
+        if ((e = fetch())) return e;
+        if (hs.cycles != cycles_seen) {          // the cycle ended and restarted
+            cycles_seen = hs.cycles;
+            if (hs.converged || launched >= maxit) break;
+            j = 0;
+            chunk = std::max(2, std::min(R, s->last_gmres_iters + 1));
+        } else {
             chunk = 2;
         }
-        first_cycle = false;
-        if (hs.converged && hs.jlast < 0) break;   // converged at the start
-        HIP_TRY(launch_gmres_update(a, x, st));
-        HIP_TRY(launch_gmres_restart(a, x, W0, 0, st));
     }
     s->last_gmres_iters = hs.iters;
     loc.iterations = hs.iters;
@@ -466,18 +520,6 @@ fr_status absmax_host(hfr_solver_s* s, int N, const double* x, double* out,
     return sync_check(st);
 }
 
-// max |x| and max |y| with one host synchronisation
-fr_status absmax2_host(hfr_solver_s* s, int Nx, const double* x, int Ny,
-                       const double* y, double* out, hipStream_t st) {
-    const int nbx = std::min(1024, std::max(1, (Nx + 255) / 256));
-    const int nby = std::min(1024, std::max(1, (Ny + 255) / 256));
-    HIP_TRY(launch_absmax(Nx, x, s->scratch, nbx, s->dots + 140, st));
-    HIP_TRY(launch_absmax(Ny, y, s->scratch, nby, s->dots + 141, st));
-    HIP_TRY(hipMemcpyAsync(out, s->dots + 140, 2 * sizeof(double),
-                           hipMemcpyDeviceToHost, st));
-    return sync_check(st);
-}
-
 fr_status newton(hfr_solver_s* s, double* u, double* uhat,
                  const double* ustar, double aii_dt, hfr_newton_stats* stats,
                  hipStream_t st) {
@@ -492,9 +534,23 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
     for (int it = 0;; ++it) {
         e = residual_internal(s, u, uhat, ustar, aii_dt, nullptr, st);
         if (e) return e;
-        double hg[2] = {0.0, 0.0};
-        if ((e = absmax2_host(s, nu, s->h, 4 * m->Ntp, s->g, hg, st))) return e;
-        const double hmax = hg[0], gmax = hg[1];
+        // norms -> pinned buffer; while the host waits, the fill of the next
+        // linearisation runs unless the device-side test says converged
+        const int lag = s->opts.jacobian_lag;
+        const bool spec = lag <= 0 && m->Nim > 0;
+        {
+            const int nbx = std::min(1024, std::max(1, (nu + 255) / 256));
+            const int nby = std::min(1024, std::max(1, (4 * m->Ntp + 255) / 256));
+            HIP_TRY(launch_absmax(nu, s->h, s->scratch, nbx, s->dots + 140, st));
+            HIP_TRY(launch_absmax(4 * m->Ntp, s->g, s->scratch, nby, s->dots + 141, st));
+            if ((e = readback(s, s->dots + 140, 2 * sizeof(double), st))) return e;
+            if (spec) {
+                HIP_TRY(launch_newton_go(s->dots + 140, tol, s->go, st));
+                if ((e = condense_fill(s, u, uhat, aii_dt, s->go, st))) return e;
+            }
+            if ((e = readback_wait(s))) return e;
+        }
+        const double hmax = s->hpin[0], gmax = s->hpin[1];
         const double res = std::max(hmax, gmax);
         if (s->verbose)
             fprintf(stderr, "[hfr] newton it %d |h| %.3e |g| %.3e tol %.3e\n", it,
@@ -510,11 +566,10 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
             if (stats) *stats = loc;
             return fail(FR_E_NOT_CONVERGED, "Newton did not converge");
         }
-        const int lag = s->opts.jacobian_lag;
         const bool relin = lag <= 0 || !s->have_factors ||
                            (it == 0 && (s->stage_calls % lag) == 0);
         if (relin) {
-            if ((e = condense_internal(s, u, uhat, aii_dt, st))) return e;
+            if ((e = condense_internal(s, u, uhat, aii_dt, st, spec))) return e;
             s->have_factors = true;
         } else {
             if ((e = recondense_rhs_internal(s, st))) return e;
@@ -684,7 +739,15 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
         (e = dalloc(&s->r, size_t(std::max(1, s->N)), tot)) ||
         (e = dalloc(&s->scratch, size_t(4096) * 66, tot)) ||
         (e = dalloc(&s->dots, 256, tot)) ||
-        (e = dalloc(&s->coef, 128, tot))) {
+        (e = dalloc(&s->coef, 128, tot)) ||
+        (e = dalloc(&s->go, 1, tot)) ||
+        (e = (hipHostMalloc(reinterpret_cast<void**>(&s->hpin), kPinDoubles * sizeof(double)) ==
+                      hipSuccess
+                  ? FR_OK
+                  : fail(FR_E_NOMEM, "hipHostMalloc of the readback buffer failed"))) ||
+        (e = (hipEventCreateWithFlags(&s->rb_ev, hipEventDisableTiming) == hipSuccess
+                  ? FR_OK
+                  : fail(FR_E_DEVICE, "hipEventCreateWithFlags failed")))) {
         s->M = Mraw;
         free_solver(s);
         delete s;

@@ -19,6 +19,7 @@
 // cycle returns at entry.
 #include "internal.h"
 #include "gmres.h"
+#include "wave_ops.h"
 
 namespace hfr {
 
@@ -27,10 +28,7 @@ namespace {
 constexpr int kThr = 512;        // threads per workgroup of the vector kernels
 constexpr int kRPT = 4;          // rows per thread (<= 2048 rows per block)
 
-__device__ __forceinline__ double wsum(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
+__device__ __forceinline__ double wsum(double v) { return wave_sum(v); }
 
 // Partial sums are stored value-major: partial[i * nb + b] is block b's
 // share of value i, so a reader of value i loads consecutive addresses.

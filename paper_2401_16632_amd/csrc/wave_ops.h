@@ -39,6 +39,24 @@ __device__ __forceinline__ unsigned long long wave_max_key(unsigned long long x)
     const int hi = __builtin_amdgcn_readlane(int(unsigned(x >> 32)), 63);
     return (static_cast<unsigned long long>(unsigned(hi)) << 32) | unsigned(lo);
 }
+// Wave-wide sum of a double by the same DPP row operations (lanes outside
+// the row mask add zero), in a fixed order; every lane gets the sum.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_or_zero(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROWMASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum(double x) {
+    x += dpp_or_zero<0xb1, 0xf>(x);             // quad_perm [1,0,3,2]
+    x += dpp_or_zero<0x4e, 0xf>(x);             // quad_perm [2,3,0,1]
+    x += dpp_or_zero<0x141, 0xf>(x);            // row_half_mirror
+    x += dpp_or_zero<0x140, 0xf>(x);            // row_mirror
+    x += dpp_or_zero<0x142, 0xa>(x);            // row_bcast:15 into rows 1, 3
+    x += dpp_or_zero<0x143, 0xc>(x);            // row_bcast:31 into rows 2, 3
+    return lane_value(x, 63);
+}
+
 // pivot key: |value| (as FP32, order-preserving bits) above the complement
 // of the row, so the maximum is the largest magnitude with the lowest row
 __device__ __forceinline__ unsigned long long pivot_key(float mag, int row) {

@@ -8,8 +8,9 @@ the product path can both import it without sharing any of the method.
 """
 from .meshes import periodic_quad_mesh, cylinder_ogrid, ogrid_ratio_for_outer
 from .states import (isentropic_vortex, freestream_state, perturb_state,
-                     EULER_GAMMA)
+                     edac_vortex, edac_freestream, EULER_GAMMA)
 
 __all__ = ["periodic_quad_mesh", "cylinder_ogrid", "ogrid_ratio_for_outer",
            "isentropic_vortex", "freestream_state", "perturb_state",
+           "edac_vortex", "edac_freestream",
            "EULER_GAMMA"]

@@ -1,6 +1,7 @@
-"""Point-wise initial states of the 2D Euler equations (conserved variables
-rho, rho*u, rho*v, E) as functions of physical coordinates, plus seeded
-perturbations.  Consumers evaluate these at their own solution points."""
+"""Point-wise initial states as functions of physical coordinates: the 2D
+Euler equations (conserved variables rho, rho*u, rho*v, E) and the EDAC
+equations (P, v_x, v_y, v_z), plus seeded perturbations.  Consumers evaluate
+these at their own solution points."""
 import numpy as np
 
 EULER_GAMMA = 1.4
@@ -36,6 +37,28 @@ def freestream_state(mach=0.2, gamma=EULER_GAMMA, angle=0.0):
     u, v = np.cos(angle), np.sin(angle)
     E = p / (gamma - 1.0) + 0.5 * (u * u + v * v)
     return np.array([1.0, u, v, E], np.float64)
+
+
+def edac_vortex(x, y, beta=2.0, speed=1.0, vz_amp=0.1, x0=0.0, y0=0.0):
+    """State (P, v_x, v_y, v_z) of the EDAC equations: a Gaussian vortex of
+    strength beta on a uniform stream along +x, with the pressure of the
+    incompressible vortex, P = -(beta/(2 pi))^2 exp(1 - r^2) / 2, and a smooth
+    passive v_z.  Returns an array of shape x.shape + (4,)."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    dx, dy = x - x0, y - y0
+    e = np.exp(0.5 * (1.0 - (dx * dx + dy * dy)))
+    k = beta / (2.0 * np.pi)
+    P = -0.5 * k * k * e * e
+    vx = speed - k * dy * e
+    vy = k * dx * e
+    vz = vz_amp * np.sin(0.2 * np.pi * x) * np.cos(0.2 * np.pi * y)
+    return np.stack([P, vx, vy, vz], axis=-1)
+
+
+def edac_freestream(angle=0.0):
+    """Uniform EDAC stream: P = 0, |v| = 1 at the given angle, v_z = 0."""
+    return np.array([0.0, np.cos(angle), np.sin(angle), 0.0], np.float64)
 
 
 def perturb_state(u, amp, seed):

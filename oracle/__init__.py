@@ -16,9 +16,9 @@ written special case).  No function is "parity unpinned".
 """
 from .operators import RefOps
 from .mesh import QuadMesh, FACE_EXPLICIT, FACE_UPSILON, FACE_TRACE, FACE_BOUNDARY
-from .physics import Euler, Advection
+from .physics import Euler, EDAC, Advection
 from . import residual, newton, imex, efr, modal_filter
 
-__all__ = ["RefOps", "QuadMesh", "Euler", "Advection", "residual", "newton",
+__all__ = ["RefOps", "QuadMesh", "Euler", "EDAC", "Advection", "residual", "newton",
            "imex", "efr", "modal_filter", "FACE_EXPLICIT", "FACE_UPSILON", "FACE_TRACE",
            "FACE_BOUNDARY"]

@@ -64,6 +64,51 @@ class Euler:
         return np.where((tag == BC_WALL)[..., None], wall, far)
 
 
+class EDAC:
+    """Entropically damped artificial compressibility equations (Appendix A),
+    inviscid part, u = (P, v_x, v_y, v_z).
+
+    Reading: the paper's state is three-dimensional; on a two-dimensional
+    mesh the fields are taken independent of z, so the z fluxes vanish and
+    v_z is carried as a passive scalar.  theta = 1/M^2 (artificial Mach
+    number M).  Fluxes along x_i: (v_i (P + theta), v_i v_x + P delta_ix,
+    v_i v_y + P delta_iy, v_i v_z)."""
+    nv = 4
+
+    def __init__(self, theta=100.0):
+        self.theta = theta
+
+    def flux(self, u):
+        P, vx, vy, vz = u[..., 0], u[..., 1], u[..., 2], u[..., 3]
+        Pt = P + self.theta
+        F = np.stack([vx * Pt, vx * vx + P, vx * vy, vx * vz], axis=-1)
+        G = np.stack([vy * Pt, vy * vx, vy * vy + P, vy * vz], axis=-1)
+        return F, G
+
+    def max_speed(self, u, nx, ny):
+        """Largest eigenvalue modulus of the normal flux Jacobian: the
+        eigenvalues are v_n (twice) and 3/2 v_n +- sqrt(v_n^2/4 + P + theta)."""
+        vn = u[..., 1] * nx + u[..., 2] * ny
+        return 1.5 * rabs(vn) + np.sqrt(0.25 * vn * vn + u[..., 0] + self.theta)
+
+    def hfr_speed(self, u, nx, ny):
+        """Stabilisation of the hybridized flux given for EDAC (Section 5,
+        the airfoil case): s = 3/2 |v| + d, d^2 = |v|^2/4 + P + theta, with
+        |v| the speed over all components (isotropic, s I)."""
+        vv = u[..., 1] * u[..., 1] + u[..., 2] * u[..., 2] + u[..., 3] * u[..., 3]
+        return 1.5 * np.sqrt(vv) + np.sqrt(0.25 * vv + u[..., 0] + self.theta) + 0.0 * nx
+
+    def ghost(self, u, nx, ny, tag, uinf):
+        """Slip wall mirrors the normal velocity (P and v_z kept); far field
+        is the free stream."""
+        vn = u[..., 1] * nx + u[..., 2] * ny
+        wall = np.stack([u[..., 0], u[..., 1] - 2.0 * vn * nx,
+                         u[..., 2] - 2.0 * vn * ny, u[..., 3]], axis=-1)
+        far = np.broadcast_to(np.asarray(uinf if uinf is not None
+                                         else np.zeros(4)), u.shape)
+        return np.where((tag == BC_WALL)[..., None], wall, far)
+
+
 class Advection:
     """Scalar linear advection with constant velocity (ax, ay)."""
     nv = 1
@@ -103,10 +148,11 @@ def hfr_flux(phys, u, uhat, S):
 
     The paper leaves s to 'the physics'; the reading taken for Euler is the
     largest wave speed at the trace, s = |vhat . n| + chat, applied as a
-    scalar (isotropic, like the paper's EDAC choice)."""
+    scalar (isotropic, like the paper's EDAC choice); a physics that states
+    its own s (EDAC) provides hfr_speed."""
     nx, ny, mag = _unit(S)
     F, G = phys.flux(uhat)
-    s = phys.max_speed(uhat, nx, ny)
+    s = getattr(phys, "hfr_speed", phys.max_speed)(uhat, nx, ny)
     return (F * S[..., 0, None] + G * S[..., 1, None]
             + (s * mag)[..., None] * (u - uhat))
 

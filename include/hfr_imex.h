@@ -76,6 +76,16 @@ typedef struct hfr_solver_s* hfr_solver_t; /* opaque, library-owned */
  *                               indicator E_s = area/perimeter (Section 5)
  *                               is <= es_cutoff
  *   gamma, uinf[4]              ratio of specific heats; far-field state
+ *                               (in the variables of the physics)
+ *   physics                     FR_PHYS_EULER: two-dimensional Euler,
+ *                               u = (rho, rho u, rho v, E);
+ *                               FR_PHYS_EDAC: the EDAC equations of
+ *                               Appendix A (inviscid part), u = (P, v_x,
+ *                               v_y, v_z) on the two-dimensional mesh (fields
+ *                               independent of z, v_z passive), hybridized
+ *                               stabilisation s = 3/2 |vhat| + dhat,
+ *                               dhat^2 = |vhat|^2/4 + Phat + theta
+ *   theta                       EDAC: 1/M^2 (artificial Mach number M), > 0
  *   flags                       FR_MESH_HOST_ONLY: build the host tables
  *                               only (maps and counts; no device upload,
  *                               compute calls on it return FR_E_INVALID)
@@ -90,6 +100,7 @@ typedef struct hfr_solver_s* hfr_solver_t; /* opaque, library-owned */
  * GLL nodes, the end vertex (if new).  Without it the trace is the
  * discontinuous HFR trace at the Gauss flux points. */
 #define FR_MESH_EFR 2
+enum { FR_PHYS_EULER = 0, FR_PHYS_EDAC = 1 };
 typedef struct {
     int32_t n_nodes;
     const double* node_xy;
@@ -103,6 +114,8 @@ typedef struct {
     double gamma;
     double uinf[4];
     int32_t flags;
+    int32_t physics;
+    double theta;
 } fr_mesh_desc;
 
 typedef struct {

@@ -30,7 +30,7 @@ class FrMeshDesc(Structure):
                 ("elem_face_bc", POINTER(c_int8)), ("order", c_int32),
                 ("implicit_mask", POINTER(c_uint8)), ("es_cutoff", c_double),
                 ("gamma", c_double), ("uinf", c_double * 4),
-                ("flags", c_int32)]
+                ("flags", c_int32), ("physics", c_int32), ("theta", c_double)]
 
 
 class FrMeshInfo(Structure):

@@ -84,7 +84,7 @@ class Mesh:
 
     def __init__(self, desc, order, implicit_mask=None, es_cutoff=-1.0,
                  gamma=1.4, uinf=(1.0, 0.0, 0.0, 1.0), host_only=False,
-                 efr=False):
+                 efr=False, physics="euler", theta=100.0):
         lib = load_library()
         self._keep = []
 
@@ -116,6 +116,11 @@ class Mesh:
         for v in range(4):
             d.uinf[v] = float(uinf[v])
         d.flags = (1 if host_only else 0) | (2 if efr else 0)
+        kinds = {"euler": 0, "edac": 1}
+        if physics not in kinds:
+            raise ValueError(f"unknown physics {physics!r}")
+        d.physics = kinds[physics]
+        d.theta = float(theta)
         h = ctypes.c_void_p()
         _check(lib.fr_mesh_create(ctypes.byref(d), ctypes.byref(h)))
         self._keep = []

@@ -1,7 +1,13 @@
-// Device physics of the two-dimensional Euler equations: fluxes, the
-// standard FR Rusanov flux (Section 2.1), the hybridized single-sided flux
-// (eq:hfrriemann) with s = |vhat.n| + chat, boundary ghost states, and the
-// analytic derivatives of each needed by the element blocks of Section 3.2.
+// Device physics: fluxes, the standard FR Rusanov flux (Section 2.1), the
+// hybridized single-sided flux (eq:hfrriemann), boundary ghost states, and
+// the analytic derivatives of each needed by the element blocks of
+// Section 3.2, for two systems with four unknowns per point:
+//   - the two-dimensional Euler equations, u = (rho, rho u, rho v, E), with
+//     the hybridized stabilisation s = |vhat.n| + chat;
+//   - the EDAC equations of Appendix A (inviscid part), u = (P, v_x, v_y,
+//     v_z) with theta = 1/M^2, on a two-dimensional mesh (fields independent
+//     of z, v_z passive), with the stabilisation the paper gives for them,
+//     s = 3/2 |vhat| + sqrt(|vhat|^2/4 + Phat + theta) (isotropic).
 //
 // Every common flux returned is the transformed normal flux F_hat . S with
 // S = J_f n the scaled outward normal (eq:8923i).
@@ -195,6 +201,206 @@ __device__ __forceinline__ void dhfr_flux(const double u[4], const double uh[4],
         double dv = mag * (u[v] - uh[v]);
         for (int w = 0; w < 4; ++w) Jh[4 * v + w] += dv * ds[w];
     }
+}
+
+// ---- EDAC ----------------------------------------------------------------
+
+__device__ __forceinline__ void edac_flux_n(const double u[4], double th, double sx,
+                                            double sy, double out[4]) {
+    const double vn = u[1] * sx + u[2] * sy;
+    out[0] = vn * (u[0] + th);
+    out[1] = vn * u[1] + u[0] * sx;
+    out[2] = vn * u[2] + u[0] * sy;
+    out[3] = vn * u[3];
+}
+
+__device__ __forceinline__ void edac_flux_xy(const double u[4], double th, double F[4],
+                                             double G[4]) {
+    const double Pt = u[0] + th;
+    F[0] = u[1] * Pt;
+    F[1] = u[1] * u[1] + u[0];
+    F[2] = u[1] * u[2];
+    F[3] = u[1] * u[3];
+    G[0] = u[2] * Pt;
+    G[1] = u[2] * u[1];
+    G[2] = u[2] * u[2] + u[0];
+    G[3] = u[2] * u[3];
+}
+
+// largest eigenvalue modulus of the normal flux Jacobian along the unit
+// normal: 3/2 |v.n| + sqrt((v.n)^2/4 + P + theta)
+__device__ __forceinline__ double edac_wave_speed(const double u[4], double th,
+                                                  double nx, double ny) {
+    const double vn = u[1] * nx + u[2] * ny;
+    return 1.5 * fabs(vn) + sqrt(0.25 * vn * vn + u[0] + th);
+}
+
+// hybridized stabilisation 3/2 |v| + sqrt(|v|^2/4 + P + theta)
+__device__ __forceinline__ double edac_hfr_speed(const double u[4], double th) {
+    const double vv = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+    return 1.5 * sqrt(vv) + sqrt(0.25 * vv + u[0] + th);
+}
+
+// d(F.S)/du, row-major 4x4
+__device__ __forceinline__ void edac_dflux_n(const double u[4], double th, double sx,
+                                             double sy, double A[16]) {
+    const double vn = u[1] * sx + u[2] * sy, Pt = u[0] + th;
+    A[0] = vn;
+    A[1] = Pt * sx;
+    A[2] = Pt * sy;
+    A[3] = 0.0;
+    A[4] = sx;
+    A[5] = vn + u[1] * sx;
+    A[6] = u[1] * sy;
+    A[7] = 0.0;
+    A[8] = sy;
+    A[9] = u[2] * sx;
+    A[10] = vn + u[2] * sy;
+    A[11] = 0.0;
+    A[12] = 0.0;
+    A[13] = u[3] * sx;
+    A[14] = u[3] * sy;
+    A[15] = vn;
+}
+
+// d(wave speed)/du along the unit normal (sign(0) taken as +1)
+__device__ __forceinline__ void edac_dwave_speed(const double u[4], double th, double nx,
+                                                 double ny, double ds[4]) {
+    const double vn = u[1] * nx + u[2] * ny;
+    const double d = sqrt(0.25 * vn * vn + u[0] + th);
+    const double kv = (vn >= 0.0 ? 1.5 : -1.5) + vn / (4.0 * d);
+    ds[0] = 0.5 / d;
+    ds[1] = kv * nx;
+    ds[2] = kv * ny;
+    ds[3] = 0.0;
+}
+
+// d(stabilisation)/du; d|v|/dv at v = 0 taken as 0
+__device__ __forceinline__ void edac_dhfr_speed(const double u[4], double th, double ds[4]) {
+    const double vv = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+    const double vm = sqrt(vv), d = sqrt(0.25 * vv + u[0] + th);
+    ds[0] = 0.5 / d;
+    for (int c = 1; c < 4; ++c) ds[c] = (vm > 0.0 ? 1.5 * u[c] / vm : 0.0) + u[c] / (4.0 * d);
+}
+
+__device__ __forceinline__ void edac_rusanov(const double a[4], const double b[4],
+                                             double sx, double sy, double th, double out[4]) {
+    const double mag = sqrt(sx * sx + sy * sy);
+    const double nx = sx / mag, ny = sy / mag;
+    double fa[4], fb[4];
+    edac_flux_n(a, th, sx, sy, fa);
+    edac_flux_n(b, th, sx, sy, fb);
+    const double la = edac_wave_speed(a, th, nx, ny), lb = edac_wave_speed(b, th, nx, ny);
+    const double d = 0.5 * (la >= lb ? la : lb) * mag;
+    for (int v = 0; v < 4; ++v) out[v] = 0.5 * (fa[v] + fb[v]) + d * (a[v] - b[v]);
+}
+
+__device__ __forceinline__ void edac_drusanov(const double a[4], const double b[4],
+                                              double sx, double sy, double th,
+                                              double Ja[16], double Jb[16]) {
+    const double mag = sqrt(sx * sx + sy * sy);
+    const double nx = sx / mag, ny = sy / mag;
+    edac_dflux_n(a, th, sx, sy, Ja);
+    edac_dflux_n(b, th, sx, sy, Jb);
+    const double la = edac_wave_speed(a, th, nx, ny), lb = edac_wave_speed(b, th, nx, ny);
+    const bool takea = la >= lb;
+    const double s = takea ? la : lb;
+    double ds[4];
+    edac_dwave_speed(takea ? a : b, th, nx, ny, ds);
+    for (int k = 0; k < 16; ++k) {
+        Ja[k] *= 0.5;
+        Jb[k] *= 0.5;
+    }
+    const double hs = 0.5 * s * mag;
+    for (int v = 0; v < 4; ++v) {
+        Ja[5 * v] += hs;
+        Jb[5 * v] -= hs;
+        const double dv = 0.5 * mag * (a[v] - b[v]);
+        for (int w = 0; w < 4; ++w) {
+            if (takea) Ja[4 * v + w] += dv * ds[w];
+            else Jb[4 * v + w] += dv * ds[w];
+        }
+    }
+}
+
+__device__ __forceinline__ void edac_hfr_flux(const double u[4], const double uh[4],
+                                              double sx, double sy, double th, double out[4]) {
+    const double mag = sqrt(sx * sx + sy * sy);
+    double f[4];
+    edac_flux_n(uh, th, sx, sy, f);
+    const double d = edac_hfr_speed(uh, th) * mag;
+    for (int v = 0; v < 4; ++v) out[v] = f[v] + d * (u[v] - uh[v]);
+}
+
+__device__ __forceinline__ void edac_dhfr_flux(const double u[4], const double uh[4],
+                                               double sx, double sy, double th, double* su,
+                                               double Jh[16]) {
+    const double mag = sqrt(sx * sx + sy * sy);
+    edac_dflux_n(uh, th, sx, sy, Jh);
+    const double s = edac_hfr_speed(uh, th);
+    double ds[4];
+    edac_dhfr_speed(uh, th, ds);
+    *su = s * mag;
+    for (int v = 0; v < 4; ++v) {
+        Jh[5 * v] -= s * mag;
+        const double dv = mag * (u[v] - uh[v]);
+        for (int w = 0; w < 4; ++w) Jh[4 * v + w] += dv * ds[w];
+    }
+}
+
+// ---- choice of system -----------------------------------------------------
+enum PhysKind : int { PHYS_EULER = 0, PHYS_EDAC = 1 };
+
+struct PhysK {
+    int kind;
+    double gam, th;
+};
+
+__device__ __forceinline__ void phys_flux_xy(const PhysK& k, const double u[4], double F[4],
+                                             double G[4]) {
+    if (k.kind == PHYS_EDAC) {
+        edac_flux_xy(u, k.th, F, G);
+    } else {
+        const Prim q = prim(u, k.gam);
+        flux_xy(u, q, F, G);
+    }
+}
+// the two transformed-flux Jacobians of a solution point
+__device__ __forceinline__ void phys_dflux_pair(const PhysK& k, const double u[4], double ax,
+                                                double ay, double bx, double by, double A[16],
+                                                double B[16]) {
+    if (k.kind == PHYS_EDAC) {
+        edac_dflux_n(u, k.th, ax, ay, A);
+        edac_dflux_n(u, k.th, bx, by, B);
+    } else {
+        const Prim q = prim(u, k.gam);
+        dflux_n(u, q, ax, ay, k.gam, A);
+        dflux_n(u, q, bx, by, k.gam, B);
+    }
+}
+__device__ __forceinline__ void phys_rusanov(const PhysK& k, const double a[4],
+                                             const double b[4], double sx, double sy,
+                                             double out[4]) {
+    if (k.kind == PHYS_EDAC) edac_rusanov(a, b, sx, sy, k.th, out);
+    else rusanov(a, b, sx, sy, k.gam, out);
+}
+__device__ __forceinline__ void phys_drusanov(const PhysK& k, const double a[4],
+                                              const double b[4], double sx, double sy,
+                                              double Ja[16], double Jb[16]) {
+    if (k.kind == PHYS_EDAC) edac_drusanov(a, b, sx, sy, k.th, Ja, Jb);
+    else drusanov(a, b, sx, sy, k.gam, Ja, Jb);
+}
+__device__ __forceinline__ void phys_hfr_flux(const PhysK& k, const double u[4],
+                                              const double uh[4], double sx, double sy,
+                                              double out[4]) {
+    if (k.kind == PHYS_EDAC) edac_hfr_flux(u, uh, sx, sy, k.th, out);
+    else hfr_flux(u, uh, sx, sy, k.gam, out);
+}
+__device__ __forceinline__ void phys_dhfr_flux(const PhysK& k, const double u[4],
+                                               const double uh[4], double sx, double sy,
+                                               double* su, double Jh[16]) {
+    if (k.kind == PHYS_EDAC) edac_dhfr_flux(u, uh, sx, sy, k.th, su, Jh);
+    else dhfr_flux(u, uh, sx, sy, k.gam, su, Jh);
 }
 
 }  // namespace hfr

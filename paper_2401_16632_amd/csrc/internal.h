@@ -47,6 +47,8 @@ struct FaceInfo {
 struct Physics {
     double gamma;
     double uinf[4];
+    int kind;        // FR_PHYS_EULER or FR_PHYS_EDAC
+    double theta;    // EDAC: 1/M^2
 };
 
 void set_error(const std::string& msg);

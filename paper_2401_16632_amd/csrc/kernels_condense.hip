@@ -40,7 +40,7 @@ __device__ void element_linearisation(const CondenseLaunch& a, const RefOps& o,
     const int t = threadIdx.x;
     const int e = a.imp_list[k];
     const size_t plane = size_t(a.Ne) * NP;
-    const double gam = a.phys.gamma;
+    const PhysK pk{a.phys.kind, a.phys.gamma, a.phys.theta};
     const double* vx = a.verts + size_t(e) * 8;
     const double* vy = vx + 4;
     if (t < NP) {
@@ -56,9 +56,7 @@ __device__ void element_linearisation(const CondenseLaunch& a, const RefOps& o,
             uu[v] = a.u[v * plane + size_t(e) * NP + t];
             sh.u[t][v] = uu[v];
         }
-        Prim q = prim(uu, gam);
-        dflux_n(uu, q, y_et, -x_et, gam, sh.Af[t]);
-        dflux_n(uu, q, -y_xi, x_xi, gam, sh.Ag[t]);
+        phys_dflux_pair(pk, uu, y_et, -x_et, -y_xi, x_xi, sh.Af[t], sh.Ag[t]);
         sh.c[t] = a.aii_dt / J;
     }
     if (t < 4) sh.tr[t] = (a.finfo[size_t(e) * 4 + t].role == ROLE_HFR);
@@ -94,7 +92,7 @@ __device__ void element_linearisation(const CondenseLaunch& a, const RefOps& o,
                 for (int v = 0; v < 4; ++v) uh[v] = a.uhat[size_t(tp) * 4 + v];
             }
             double su;
-            dhfr_flux(uf, uh, S.x, S.y, gam, &su, Fh);
+            phys_dhfr_flux(pk, uf, uh, S.x, S.y, &su, Fh);
             for (int z = 0; z < 16; ++z) Fu[z] = 0.0;
             for (int v = 0; v < 4; ++v) Fu[5 * v] = su;
         } else {
@@ -114,10 +112,10 @@ __device__ void element_linearisation(const CondenseLaunch& a, const RefOps& o,
                     else { p2 = (P - 1 - qn) * P + l; wgt = o.lm[l]; }
                     for (int v = 0; v < 4; ++v) outer[v] += wgt * base[v * plane + p2];
                 }
-                drusanov(uf, outer, S.x, S.y, gam, Fu, Jb);
+                phys_drusanov(pk, uf, outer, S.x, S.y, Fu, Jb);
             } else {
                 ghost_state(uf, nx, ny, fi.role, a.phys.uinf, outer);
-                drusanov(uf, outer, S.x, S.y, gam, Fu, Jb);
+                phys_drusanov(pk, uf, outer, S.x, S.y, Fu, Jb);
                 if (fi.role == ROLE_WALL) {
                     // d ghost / d u: identity except momentum rows I - 2 n n^T
                     double R[16] = {1, 0, 0, 0, 0, 1 - 2 * nx * nx, -2 * nx * ny, 0,

@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void k_residual(ResidualLaunch a, RefOps og) {
     const int li = blockIdx.x * EPB + slot;
     const bool act = (slot < EPB) && (li < a.nlist);
     const size_t plane = size_t(a.Ne) * NP;
-    const double gam = a.phys.gamma;
+    const PhysK pk{a.phys.kind, a.phys.gamma, a.phys.theta};
     int e = 0;
     double J = 1.0, uloc[4] = {0, 0, 0, 0};
     if (act) {
@@ -72,9 +72,8 @@ __global__ __launch_bounds__(256) void k_residual(ResidualLaunch a, RefOps og) {
         J = x_xi * y_et - x_et * y_xi;
 #pragma unroll
         for (int v = 0; v < 4; ++v) uloc[v] = a.u[v * plane + size_t(e) * NP + pt];
-        Prim q = prim(uloc, gam);
         double F[4], G[4];
-        flux_xy(uloc, q, F, G);
+        phys_flux_xy(pk, uloc, F, G);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             s_u[slot][pt][v] = uloc[v];
@@ -132,7 +131,7 @@ __global__ __launch_bounds__(256) void k_residual(ResidualLaunch a, RefOps og) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) outer[v] = a.uhat[size_t(tp) * 4 + v];
             }
-            hfr_flux(uf, outer, S.x, S.y, gam, com);
+            phys_hfr_flux(pk, uf, outer, S.x, S.y, com);
             if (a.gk) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
@@ -145,7 +144,7 @@ __global__ __launch_bounds__(256) void k_residual(ResidualLaunch a, RefOps og) {
                 const double mag = sqrt(S.x * S.x + S.y * S.y);
                 ghost_state(uf, S.x / mag, S.y / mag, fi.role, a.phys.uinf, outer);
             }
-            rusanov(uf, outer, S.x, S.y, gam, com);
+            phys_rusanov(pk, uf, outer, S.x, S.y, com);
             if (a.gk) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v)

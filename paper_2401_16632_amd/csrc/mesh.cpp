@@ -168,7 +168,12 @@ extern "C" fr_status fr_mesh_create(const fr_mesh_desc* d, fr_mesh_t* out) {
         return fail(FR_E_INVALID, "order out of range");
     if (d->n_elems < 1 || d->n_nodes < 3 || !d->node_xy || !d->elem_nodes)
         return fail(FR_E_INVALID, "empty mesh");
-    if (!(d->gamma > 1.0)) return fail(FR_E_INVALID, "gamma must be > 1");
+    if (d->physics != FR_PHYS_EULER && d->physics != FR_PHYS_EDAC)
+        return fail(FR_E_INVALID, "unknown physics");
+    if (d->physics == FR_PHYS_EULER && !(d->gamma > 1.0))
+        return fail(FR_E_INVALID, "gamma must be > 1");
+    if (d->physics == FR_PHYS_EDAC && !(d->theta > 0.0 && std::isfinite(d->theta)))
+        return fail(FR_E_INVALID, "EDAC theta must be positive and finite");
     auto m = new fr_mesh_s();
     const int P = d->order + 1, Ne = d->n_elems;
     m->P = P;
@@ -177,6 +182,8 @@ extern "C" fr_status fr_mesh_create(const fr_mesh_desc* d, fr_mesh_t* out) {
     m->ops = make_ref_ops(P);
     m->phys.gamma = d->gamma;
     for (int v = 0; v < 4; ++v) m->phys.uinf[v] = d->uinf[v];
+    m->phys.kind = d->physics;
+    m->phys.theta = d->theta;
     auto topo = [&](int node) {
         return d->node_topo ? d->node_topo[node] : node;
     };

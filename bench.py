@@ -25,6 +25,8 @@ sys.path.insert(0, ROOT)
 PEAK = {"hbm_gbs": 8000.0, "fp64_tflops": 78.6, "fp32_tflops": 157.3}
 MACH = 0.2
 WAVE = 1.0 + 1.0 / MACH          # |v| + c of the free stream (|v| = 1)
+THETA = 100.0                    # EDAC 1/M^2 of the airfoil case (M = 0.1)
+WAVE_EDAC = 1.5 + math.sqrt(0.25 + THETA)   # EDAC wave speed of the stream
 
 
 def cylinder_workload(name):
@@ -48,23 +50,29 @@ def describe(name):
             f"implicit = local CFL > 1 (IF ~ 0.2), HIMEX2C pair")
 
 
-def build_case(hp, name, if_target=0.2, seed=2, efr=False):
+def build_case(hp, name, if_target=0.2, seed=2, efr=False, physics="euler"):
     """Mesh, partition (CFL rule), time step and initial state; ``efr``
-    selects the interior-embedded trace."""
+    selects the interior-embedded trace, ``physics`` the Euler or the EDAC
+    equations (free stream P = 0, |v| = 1, seeded 1e-3 additive noise)."""
     import fr_inputs as fi
     d, p, nt, nr, first, ratio = cylinder_workload(name)
-    uinf = fi.freestream_state(MACH)
+    edac = physics == "edac"
+    uinf = fi.edac_freestream() if edac else fi.freestream_state(MACH)
     probe = hp.Mesh(d, p, uinf=uinf, host_only=True)
     es = probe.maps()["es"].reshape(nr, nt)
     J = max(1, int(round(if_target * nr)))
     es_cut = 0.5 * (es[J - 1].max() + es[J].min())
     # local CFL_k = dt * lambda * (2p+1) / (2 E_s,k); implicit iff CFL_k > 1
-    dt = 2.0 * es_cut / (WAVE * (2 * p + 1))
-    mesh = hp.Mesh(d, p, es_cutoff=es_cut, uinf=uinf, efr=efr)
+    dt = 2.0 * es_cut / ((WAVE_EDAC if edac else WAVE) * (2 * p + 1))
+    mesh = hp.Mesh(d, p, es_cutoff=es_cut, uinf=uinf, efr=efr, physics=physics,
+                   theta=THETA)
     xy = mesh.maps()["sol_xy"]
     P = p + 1
     u = np.broadcast_to(uinf, (mesh.Ne, P, P, 4)).copy()
-    u = fi.perturb_state(u, 1e-3, seed)
+    if edac:
+        u = u + 1e-3 * np.random.default_rng(seed).uniform(-1.0, 1.0, size=u.shape)
+    else:
+        u = fi.perturb_state(u, 1e-3, seed)
     return mesh, hp.soa_from_elements(u).ravel(), dt, xy
 
 
@@ -289,6 +297,8 @@ def main():
                     help="skip the interior-embedded trace forms")
     ap.add_argument("--newton-tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-edac", action="store_true",
+                    help="skip the EDAC forms")
     ap.add_argument("--no-filter", action="store_true",
                     help="skip the modal-filter measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -379,6 +389,28 @@ def main():
             line["efr_fp32_vs_fp64_rel_err"] = float(
                 (np.abs(a - b).max(axis=1) / np.abs(b).max(axis=1)).max())
         line["hfr_trace_unknowns"] = 4 * mesh.Ntp
+    if not args.no_edac:
+        # the same O-grid and partition with the EDAC equations (theta = 100)
+        mesh_d, u0d, dtd, _ = build_case(hp, args.workload, physics="edac")
+        edac_states = {}
+        for f in forms:
+            pc = "fp32" if f == "fp32" else "fp64"
+            rr = run_form(hp, torch, mesh_d, u0d, dtd, f, pc, args.steps,
+                          args.warmup, args.newton_tol)
+            edac_states[f] = rr["state"]
+            line[f"edac_{f}_form"] = {
+                "implicit_dof_per_s": mesh_d.Nim * mesh_d.Np * 4 / (np.mean(rr["impl_ms"]) * 1e-3),
+                "implicit_ms_per_stage": float(np.mean(rr["impl_ms"])),
+                "newton_iters_per_stage": float(np.mean(rr["newton"])),
+                "gmres_iters_per_stage": float(np.mean(rr["gmres"])),
+                "theta": THETA, "dt": dtd,
+            }
+            print(f"# edac form {f}: implicit ms/stage {np.mean(rr['impl_ms']):.3f}, "
+                  f"gmres/stage {np.mean(rr['gmres']):.1f}", file=sys.stderr, flush=True)
+        if "fp32" in edac_states and "fp64" in edac_states:
+            a, b = edac_states["fp32"].reshape(4, -1), edac_states["fp64"].reshape(4, -1)
+            line["edac_fp32_vs_fp64_rel_err"] = float(
+                (np.abs(a - b).max(axis=1) / np.maximum(np.abs(b).max(axis=1), 1e-300)).max())
     if not args.no_filter:
         line["modal_filter"] = filter_rate(torch, mesh, u0)
     if not args.no_cpu_baseline:

@@ -408,7 +408,9 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
     __shared__ double sr[n];
     __shared__ double racc[NRW][RPL * 64];
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
+    // wave index, uniform (so that indices derived from it address
+    // registers by index mode rather than by per-lane selects)
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int k = blockIdx.x;
 
     // ---- load this wave's columns of the filled tableau (column-major)

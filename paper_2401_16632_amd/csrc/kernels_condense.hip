@@ -217,13 +217,15 @@ __device__ __forceinline__ double aug_entry(int r, int c, int k,
 // element Schur complement of eq:assembly.
 //
 // Register layout: a workgroup of W waves per element; lane l holds rows
-// l + 64 s (s < RPL) and wave w the columns w NCW .. w NCW + NCW - 1.  A
+// l + 64 s (s < RPL) and wave w the columns w, w + W, w + 2W, ... (NCW of
+// them at most).  A
 // pivot row is left unscaled in registers with its factor -1/T[p][k] kept
 // per row (applied on the way out), so every step is one rank-1 update
 // T[i][j] -= g_i u_j with g_p = 0.  The wave that owns column k finds the
 // pivot and the multipliers and passes them to the other waves through LDS
-// (one barrier per step); each wave broadcasts its own segment of the pivot
-// row through LDS.  The result is stored column-major, (N x N) per element.
+// (one barrier per step); each wave reads its own segment of the pivot row
+// from the lane that holds it.  The result is stored column-major, (N x N)
+// per element.
 // Register shape of the sweep.  Columns of a wave are held as vectors of
 // CH values (CH in {4, 8, 16}, the one that pads the wave's column count
 // least) so that the column addressed by the wave-uniform step index is
@@ -403,7 +405,7 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
     __shared__ T ibuf[2];
     __shared__ int pbuf[2];
     // right-hand side epilogue: pivot rows, permuted -h, per-wave row sums
-    constexpr int NRW = (n + NCW - 1) / NCW;    // waves owning columns of A
+    constexpr int NRW = W < n ? W : n;          // waves owning columns of A
     __shared__ short pl[n];
     __shared__ double sr[n];
     __shared__ double racc[NRW][RPL * 64];
@@ -417,7 +419,9 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
     constexpr int CH = S::CH, NCH = S::NCH;
     constexpr int SPN = (n + 63) / 64;      // row slots that can hold pivot rows
     typedef T VT __attribute__((ext_vector_type(CH)));
-    const int c0 = __builtin_amdgcn_readfirstlane(w * NCW);
+    // columns are dealt round-robin: wave w holds columns w, w + W, ...
+    // (local index j is column w + W j), so the owner of the next pivot
+    // column, which also searches for its pivot, changes every step
     T* G = reinterpret_cast<T*>(a.M) + size_t(k) * N * N;
     VT t[RPL][NCH];
     T sig[RPL];
@@ -429,7 +433,7 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
         used[s] = false;
 #pragma unroll
         for (int j = 0; j < NCH * CH; ++j) {
-            const int col = c0 + j;
+            const int col = w + W * j;
             // clamped address: the load stays inside this element's slot
             const T v = G[size_t(min(col, N - 1)) * N + min(row, N - 1)];
             t[s][j / CH][j % CH] = (j < NCW && row < N && col < N) ? v : T(0);
@@ -481,7 +485,7 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
         find_pivot(col0, 0, gs, ipv, p);
     }
     for (int kk = 0; kk < n; ++kk) {
-        const int ow = kk / NCW, jk = kk - ow * NCW, buf = kk & 1;
+        const int ow = kk % W, jk = kk / W, buf = kk & 1;
         if (W > 1) {
             __syncthreads();
             if (w != ow) {
@@ -505,9 +509,9 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
         T ipn = T(0);
         int pn = -1;
         const int k1 = kk + 1;
-        const bool ahead = (k1 < n && w == k1 / NCW);
+        const bool ahead = (k1 < n && w == k1 % W);
         if (ahead) {
-            const int j1 = k1 - w * NCW, c1 = j1 / CH, e1 = j1 - c1 * CH;
+            const int j1 = k1 / W, c1 = j1 / CH, e1 = j1 - c1 * CH;
             T cpre[RPL];
 #pragma unroll
             for (int s = 0; s < RPL; ++s) cpre[s] = T(0);
@@ -572,13 +576,13 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
             sr[j] = -a.h[size_t(row & 3) * a.nimp * NP + size_t(k) * NP + (row >> 2)];
         }
         __syncthreads();
-        if (c0 < n) {                              // uniform over the wave
+        if (w < n) {                               // uniform over the wave
             double acc[RPL];
 #pragma unroll
             for (int s = 0; s < RPL; ++s) acc[s] = 0.0;
 #pragma unroll
             for (int j = 0; j < NCW; ++j) {
-                const int col = c0 + j;
+                const int col = w + W * j;
                 if (col < n) {
                     const double rj = sr[col];
 #pragma unroll
@@ -602,7 +606,7 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
     // ---- store column-major, pivot rows scaled -------------------------------
 #pragma unroll
     for (int j = 0; j < NCW; ++j) {
-        const int col = c0 + j;
+        const int col = w + W * j;
         if (col >= N) break;
 #pragma unroll
         for (int s = 0; s < RPL; ++s) {

@@ -36,6 +36,13 @@ struct GmresArgs {
     double* part3;           // nblkA x kGmresMaxK (product kernel)
     unsigned* counters;      // 4
     GmresState* gs;
+    void* pub;               // host-visible copy of the state prefix (or null)
+};
+
+// the prefix of GmresState the host reads after every chunk
+struct GmresPublish {
+    int done, converged, jlast, iters, cycles, pad;
+    double inv_norm, beta, bnorm, target;
 };
 
 hipError_t launch_precondition_matrix(int nblocks, int bs, const int* col,
@@ -43,7 +50,7 @@ hipError_t launch_precondition_matrix(int nblocks, int bs, const int* col,
                                       int pc, const void* Dinv, double* Lt64,
                                       float* Lt32, hipStream_t st);
 // r = t - L x, beta = |r|, new cycle; cond: only if the cycle has ended
-hipError_t launch_gmres_restart(const GmresArgs& a, const double* x,
+hipError_t launch_gmres_restart(const GmresArgs& a, double* x,
                                 double* w, int first, int cond, hipStream_t st);
 hipError_t launch_arnoldi_product(const GmresArgs& a, int j, int fin_prev,
                                   const double* wcur, double* wnxt, hipStream_t st);

@@ -215,8 +215,12 @@ hipError_t launch_modal_filter(const FilterLaunch& f, long nrows, double* u,
                                hipStream_t st);
 hipError_t launch_absmax(int N, const double* x, double* partial, int nblk,
                          double* out, hipStream_t st);
-// *go = 0 when both norms hg[0], hg[1] are <= tol, else 1 (NaN included)
-hipError_t launch_newton_go(const double* hg, double tol, int* go, hipStream_t st);
+// Newton test: out[0] = max |x|, out[1] = max |y| (out may be host memory
+// mapped for the device), *go = 0 when both are <= tol, else 1 (NaN
+// included); partial needs 2048 doubles
+hipError_t launch_newton_norms(int Nx, const double* x, int Ny, const double* y,
+                               double* partial, double tol, double* out, int* go,
+                               hipStream_t st);
 hipError_t launch_trace_gather_g(int ntp, int P, const int* tpside,
                                  const double* gk, double* g,
                                  hipStream_t st);

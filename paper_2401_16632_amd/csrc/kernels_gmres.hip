@@ -393,8 +393,9 @@ __global__ __launch_bounds__(kThr) void k_gmres_update(GmresArgs a, double* x, i
 
 // ---- restart: r = t - L x (FP64), partial |r|^2 ---------------------------
 // Product decomposition of A (a.nblkA workgroups of 256 threads).
+// first: x is zeroed here (the solve starts from zero), r = t
 __global__ __launch_bounds__(256) void k_gmres_residual(GmresArgs a,
-                                                        const double* x,
+                                                        double* x,
                                                         double* w, int first, int cond) {
     if (cond && !a.gs->done) return;
     __shared__ double red[4];
@@ -424,6 +425,7 @@ __global__ __launch_bounds__(256) void k_gmres_residual(GmresArgs a,
             const double lx = first ? 0.0 : (sacc[q][0][lr] + sacc[q][1][lr] +
                                              sacc[q][2][lr] + sacc[q][3][lr]);
             const double v = a.t[r] - lx;
+            if (first) x[r] = 0.0;
             w[r] = v;
             nn += v * v;
         }
@@ -434,27 +436,42 @@ __global__ __launch_bounds__(256) void k_gmres_residual(GmresArgs a,
 // beta = |r|, new cycle (one workgroup)
 __global__ __launch_bounds__(kThr) void k_gmres_restart(GmresArgs a, int first, int cond) {
     GmresState* gs = a.gs;
-    if (cond && !gs->done) return;
     __shared__ double fin[kGmresMaxK];
-    reduce_partials(1, a.nblkA, a.part3, fin);
-    if (threadIdx.x == 0) {
-        const double beta = sqrt(fin[0]);
-        if (first) {
-            gs->bnorm = beta;
-            gs->target = a.rtol * beta;
-            gs->iters = 0;
-            gs->cycles = 0;
-        } else {
-            gs->cycles += 1;
+    if (!cond || gs->done) {                       // uniform
+        reduce_partials(1, a.nblkA, a.part3, fin);
+        if (threadIdx.x == 0) {
+            const double beta = sqrt(fin[0]);
+            if (first) {
+                gs->bnorm = beta;
+                gs->target = a.rtol * beta;
+                gs->iters = 0;
+                gs->cycles = 0;
+            } else {
+                gs->cycles += 1;
+            }
+            gs->beta = beta;
+            gs->g[0] = beta;
+            for (int i = 1; i <= a.restart; ++i) gs->g[i] = 0.0;
+            gs->inv_norm = beta > 0.0 ? 1.0 / beta : 0.0;
+            gs->jlast = -1;
+            const bool conv = !(beta > gs->target);
+            gs->converged = conv ? 1 : 0;
+            gs->done = (conv || !(beta == beta)) ? 1 : 0;
         }
-        gs->beta = beta;
-        gs->g[0] = beta;
-        for (int i = 1; i <= a.restart; ++i) gs->g[i] = 0.0;
-        gs->inv_norm = beta > 0.0 ? 1.0 / beta : 0.0;
-        gs->jlast = -1;
-        const bool conv = !(beta > gs->target);
-        gs->converged = conv ? 1 : 0;
-        gs->done = (conv || !(beta == beta)) ? 1 : 0;
+    }
+    // the state the host reads after a chunk, in host-visible memory
+    if (threadIdx.x == 0 && a.pub) {
+        GmresPublish* p = reinterpret_cast<GmresPublish*>(a.pub);
+        p->done = gs->done;
+        p->converged = gs->converged;
+        p->jlast = gs->jlast;
+        p->iters = gs->iters;
+        p->cycles = gs->cycles;
+        p->pad = 0;
+        p->inv_norm = gs->inv_norm;
+        p->beta = gs->beta;
+        p->bnorm = gs->bnorm;
+        p->target = gs->target;
     }
 }
 
@@ -535,7 +552,7 @@ hipError_t launch_precondition_matrix(int nblocks, int bs, const int* col,
     return launch_pm<float>(nblocks, bs, col, L32, pc, Dinv, Lt32, st);
 }
 
-hipError_t launch_gmres_restart(const GmresArgs& a, const double* x,
+hipError_t launch_gmres_restart(const GmresArgs& a, double* x,
                                 double* w, int first, int cond, hipStream_t st) {
     hipLaunchKernelGGL(k_gmres_residual, dim3(a.nblkA), dim3(256), 0, st, a, x,
                        w, first, cond);

@@ -372,12 +372,74 @@ hipError_t launch_absmax(int N, const double* x, double* partial, int nblk,
     return hipGetLastError();
 }
 
-__global__ void k_newton_go(const double* hg, double tol, int* go) {
-    if (threadIdx.x == 0) *go = (hg[0] <= tol && hg[1] <= tol) ? 0 : 1;
+// Newton residual norms: blocks [0, nbx) take max |x| over [0, Nx), the
+// others max |y| over [0, Ny); one partial per block (NaN propagates).
+__global__ void k_absmax2_partial(int Nx, const double* x, int nbx, int Ny,
+                                  const double* y, double* partial) {
+    __shared__ double red[kThreads];
+    const bool isx = int(blockIdx.x) < nbx;
+    const int N = isx ? Nx : Ny;
+    const double* v = isx ? x : y;
+    const long b = isx ? blockIdx.x : blockIdx.x - nbx;
+    const long nb = isx ? nbx : gridDim.x - nbx;
+    double m = 0.0;
+    for (long i = b * blockDim.x + threadIdx.x; i < N; i += nb * blockDim.x) {
+        const double a = fabs(v[i]);
+        m = (a > m || a != a) ? a : m;
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double o = red[threadIdx.x + s];
+            if (o > red[threadIdx.x] || o != o) red[threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-hipError_t launch_newton_go(const double* hg, double tol, int* go, hipStream_t st) {
-    hipLaunchKernelGGL(k_newton_go, dim3(1), dim3(64), 0, st, hg, tol, go);
+// both maxima -> out[0], out[1] (host-visible), *go = 0 iff both <= tol
+__global__ void k_absmax2_final(int nbx, int nby, const double* partial, double tol,
+                                double* out, int* go) {
+    __shared__ double red[2][256];
+    double mx = 0.0, my = 0.0;
+    for (int i = threadIdx.x; i < nbx; i += blockDim.x) {
+        const double o = partial[i];
+        if (o > mx || o != o) mx = o;
+    }
+    for (int i = threadIdx.x; i < nby; i += blockDim.x) {
+        const double o = partial[nbx + i];
+        if (o > my || o != o) my = o;
+    }
+    red[0][threadIdx.x] = mx;
+    red[1][threadIdx.x] = my;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            for (int c = 0; c < 2; ++c) {
+                const double o = red[c][threadIdx.x + s];
+                if (o > red[c][threadIdx.x] || o != o) red[c][threadIdx.x] = o;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = red[0][0];
+        out[1] = red[1][0];
+        *go = (red[0][0] <= tol && red[1][0] <= tol) ? 0 : 1;
+    }
+}
+
+hipError_t launch_newton_norms(int Nx, const double* x, int Ny, const double* y,
+                               double* partial, double tol, double* out, int* go,
+                               hipStream_t st) {
+    const int nbx = std::min(1024, std::max(1, (Nx + kThreads - 1) / kThreads));
+    const int nby = std::min(1024, std::max(1, (Ny + kThreads - 1) / kThreads));
+    hipLaunchKernelGGL(k_absmax2_partial, dim3(nbx + nby), dim3(kThreads), 0, st, Nx, x,
+                       nbx, Ny, y, partial);
+    hipLaunchKernelGGL(k_absmax2_final, dim3(1), dim3(256), 0, st, nbx, nby, partial, tol,
+                       out, go);
     return hipGetLastError();
 }
 

@@ -84,7 +84,9 @@ struct hfr_solver_s {
     double* dots = nullptr;  // small device vector
     double* coef = nullptr;
     int* go = nullptr;       // 1 while the Newton residual is above tolerance
-    double* hpin = nullptr;  // pinned host readback buffer (kPinDoubles)
+    double* hpin = nullptr;  // pinned, device-mapped host buffer (kPinDoubles):
+                             // [0..1] Newton norms, [kPinGmres..] GMRES state
+    double* dpin = nullptr;  // the same buffer's device address
     hipEvent_t rb_ev = nullptr;  // marks the readback on the solver's stream
     size_t ws_bytes = 0;
     int nblk_dot = 1;
@@ -173,11 +175,12 @@ void free_solver(hfr_solver_s* s) {
 }
 
 constexpr int kPinDoubles = 64;
+constexpr int kPinGmres = 8;
 
-// Queue a device-to-host copy into the pinned buffer and mark it; work
-// queued after it runs while the host waits in readback_wait.
-fr_status readback(hfr_solver_s* s, const void* dev, size_t bytes, hipStream_t st) {
-    HIP_TRY(hipMemcpyAsync(s->hpin, dev, bytes, hipMemcpyDeviceToHost, st));
+// Kernels write what the host reads (Newton norms, GMRES state) straight
+// into the pinned buffer; the host marks the stream and waits for the mark
+// (work queued after the mark runs meanwhile).
+fr_status readback_mark(hfr_solver_s* s, hipStream_t st) {
     HIP_TRY(hipEventRecord(s->rb_ev, st));
     return FR_OK;
 }
@@ -431,6 +434,7 @@ GmresArgs gmres_args(hfr_solver_s* s) {
     a.part3 = s->part3;
     a.counters = s->counters;
     a.gs = s->gs;
+    a.pub = s->dpin + kPinGmres;
     return a;
 }
 
@@ -445,7 +449,6 @@ fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
                 hipStream_t st) {
     const int N = s->N;
     hfr_solve_stats loc{};
-    HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * std::max(N, 1), st));
     if (N == 0) {
         if (stats) *stats = loc;
         return FR_OK;
@@ -455,17 +458,15 @@ fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
     const int maxit = std::max(1, s->opts.gmres_max_iters);
     double* W0 = s->W;
     double* W1 = s->W + N;
-    struct HostState {
-        int done, converged, jlast, iters, cycles, pad;
-        double inv_norm, beta, bnorm, target;
-    };
-    static_assert(sizeof(HostState) <= kPinDoubles * sizeof(double), "readback size");
-    HostState hs{};
+    static_assert(sizeof(GmresPublish) <= (kPinDoubles - kPinGmres) * sizeof(double),
+                  "readback size");
+    GmresPublish hs{};
+    // the restart kernel, last of every chunk's sequence, publishes the state
     auto fetch = [&]() -> fr_status {
-        fr_status e = readback(s, s->gs, sizeof(hs), st);
+        fr_status e = readback_mark(s, st);
         if (e) return e;
         if ((e = readback_wait(s))) return e;
-        std::memcpy(&hs, s->hpin, sizeof(hs));
+        std::memcpy(&hs, s->hpin + kPinGmres, sizeof(hs));
         if (!(hs.beta == hs.beta) || std::isinf(hs.beta))
             return fail(FR_E_NONFINITE, "non-finite trace residual");
         return FR_OK;
@@ -514,10 +515,11 @@ fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
 fr_status absmax_host(hfr_solver_s* s, int N, const double* x, double* out,
                       hipStream_t st) {
     const int nb = std::min(1024, std::max(1, (N + 255) / 256));
-    HIP_TRY(launch_absmax(N, x, s->scratch, nb, s->dots + 140, st));
-    HIP_TRY(hipMemcpyAsync(out, s->dots + 140, sizeof(double),
-                           hipMemcpyDeviceToHost, st));
-    return sync_check(st);
+    HIP_TRY(launch_absmax(N, x, s->scratch, nb, s->dpin + 2, st));
+    fr_status e = readback_mark(s, st);
+    if (e || (e = readback_wait(s))) return e;
+    *out = s->hpin[2];
+    return FR_OK;
 }
 
 fr_status newton(hfr_solver_s* s, double* u, double* uhat,
@@ -539,15 +541,10 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         const int lag = s->opts.jacobian_lag;
         const bool spec = lag <= 0 && m->Nim > 0;
         {
-            const int nbx = std::min(1024, std::max(1, (nu + 255) / 256));
-            const int nby = std::min(1024, std::max(1, (4 * m->Ntp + 255) / 256));
-            HIP_TRY(launch_absmax(nu, s->h, s->scratch, nbx, s->dots + 140, st));
-            HIP_TRY(launch_absmax(4 * m->Ntp, s->g, s->scratch, nby, s->dots + 141, st));
-            if ((e = readback(s, s->dots + 140, 2 * sizeof(double), st))) return e;
-            if (spec) {
-                HIP_TRY(launch_newton_go(s->dots + 140, tol, s->go, st));
-                if ((e = condense_fill(s, u, uhat, aii_dt, s->go, st))) return e;
-            }
+            HIP_TRY(launch_newton_norms(nu, s->h, 4 * m->Ntp, s->g, s->scratch, tol,
+                                        s->dpin, s->go, st));
+            if ((e = readback_mark(s, st))) return e;
+            if (spec && (e = condense_fill(s, u, uhat, aii_dt, s->go, st))) return e;
             if ((e = readback_wait(s))) return e;
         }
         const double hmax = s->hpin[0], gmax = s->hpin[1];
@@ -741,10 +738,13 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
         (e = dalloc(&s->dots, 256, tot)) ||
         (e = dalloc(&s->coef, 128, tot)) ||
         (e = dalloc(&s->go, 1, tot)) ||
-        (e = (hipHostMalloc(reinterpret_cast<void**>(&s->hpin), kPinDoubles * sizeof(double)) ==
-                      hipSuccess
+        (e = (hipHostMalloc(reinterpret_cast<void**>(&s->hpin), kPinDoubles * sizeof(double),
+                            hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+                      hipHostGetDevicePointer(reinterpret_cast<void**>(&s->dpin), s->hpin, 0) ==
+                          hipSuccess
                   ? FR_OK
-                  : fail(FR_E_NOMEM, "hipHostMalloc of the readback buffer failed"))) ||
+                  : fail(FR_E_NOMEM, "pinned readback buffer: hipHostMalloc or "
+                                     "hipHostGetDevicePointer failed"))) ||
         (e = (hipEventCreateWithFlags(&s->rb_ev, hipEventDisableTiming) == hipSuccess
                   ? FR_OK
                   : fail(FR_E_DEVICE, "hipEventCreateWithFlags failed")))) {

@@ -8,7 +8,8 @@ namespace hfr {
 constexpr int kGmresMaxK = 65;   // restart <= 64
 
 struct GmresState {
-    int done, converged, jlast, iters, cycles, pad;
+    // finished: the solve is over (converged, or ended at the iteration cap)
+    int done, converged, jlast, iters, cycles, finished;
     double inv_norm, beta, bnorm, target;
     double h1[kGmresMaxK], h2[kGmresMaxK];
     double cs[kGmresMaxK], sn[kGmresMaxK];
@@ -41,7 +42,7 @@ struct GmresArgs {
 
 // the prefix of GmresState the host reads after every chunk
 struct GmresPublish {
-    int done, converged, jlast, iters, cycles, pad;
+    int done, converged, jlast, iters, cycles, finished;
     double inv_norm, beta, bnorm, target;
 };
 
@@ -50,8 +51,9 @@ hipError_t launch_precondition_matrix(int nblocks, int bs, const int* col,
                                       int pc, const void* Dinv, double* Lt64,
                                       float* Lt32, hipStream_t st);
 // r = t - L x, beta = |r|, new cycle; cond: only if the cycle has ended
+// cap: the host ends the solve here (iteration cap)
 hipError_t launch_gmres_restart(const GmresArgs& a, double* x,
-                                double* w, int first, int cond, hipStream_t st);
+                                double* w, int first, int cond, int cap, hipStream_t st);
 hipError_t launch_arnoldi_product(const GmresArgs& a, int j, int fin_prev,
                                   const double* wcur, double* wnxt, hipStream_t st);
 hipError_t launch_arnoldi_orth(const GmresArgs& a, int j, double* wnxt,

@@ -80,6 +80,7 @@ struct ResidualLaunch {
     double aii_dt;
     double* gk;              // [nlist][4][P][4] or null
     const int* efr_fnodes;   // [Ntf][P] trace nodes (interior-embedded trace) or null
+    const int* gate;         // if set and *gate == 0 the kernel returns at entry
 };
 hipError_t launch_residual(const RefOps& ops, const ResidualLaunch& a,
                            hipStream_t st);
@@ -162,7 +163,7 @@ hipError_t launch_axpy(int N, double a, const double* x, double* y,
 hipError_t launch_recover(const RefOps& ops, bool efr, int nimp, const void* M,
                           int precision, const int* piv, const double* yr,
                           const int* trace_map, const double* duhat, double* du,
-                          hipStream_t st);
+                          hipStream_t st, const int* gate = nullptr);
 
 // ---- interior-embedded trace (kernels_efr.hip) ------------------------
 // g at the trace nodes: sum over each node's incidences (slot
@@ -202,7 +203,7 @@ hipError_t launch_efr_trace_average(const RefOps& ops, int nnodes, int Ne,
 hipError_t launch_newton_update(int Np, int nimp, int Ne, const int* imp_list,
                                 const double* du, double* u, int ntp4,
                                 const double* duhat, double* uhat,
-                                hipStream_t st);
+                                hipStream_t st, const int* gate = nullptr);
 // Modal filter: orthonormal Legendre basis at the Gauss points
 // v1[q*P+a] = psi_a(x_q), the Gauss weights, and sigma (already raised to
 // the time-step exponent) per exponent sum a + b = 0 .. 2(P-1).
@@ -216,10 +217,12 @@ hipError_t launch_modal_filter(const FilterLaunch& f, long nrows, double* u,
 hipError_t launch_absmax(int N, const double* x, double* partial, int nblk,
                          double* out, hipStream_t st);
 // Newton test: out[0] = max |x|, out[1] = max |y| (out may be host memory
-// mapped for the device), *go = 0 when both are <= tol, else 1 (NaN
-// included); partial needs 2048 doubles
+// mapped for the device), *go = 1 when the gate (if any) is open and either
+// exceeds tol (NaN included), else 0; flags[0..1] copied to flags_out (if
+// set); partial needs 2048 doubles
 hipError_t launch_newton_norms(int Nx, const double* x, int Ny, const double* y,
                                double* partial, double tol, double* out, int* go,
+                               const int* gate, const int* flags, int* flags_out,
                                hipStream_t st);
 hipError_t launch_trace_gather_g(int ntp, int P, const int* tpside,
                                  const double* gk, double* g,

@@ -434,10 +434,13 @@ __global__ __launch_bounds__(256) void k_gmres_residual(GmresArgs a,
 }
 
 // beta = |r|, new cycle (one workgroup)
-__global__ __launch_bounds__(kThr) void k_gmres_restart(GmresArgs a, int first, int cond) {
+__global__ __launch_bounds__(kThr) void k_gmres_restart(GmresArgs a, int first, int cond,
+                                                        int cap) {
     GmresState* gs = a.gs;
     __shared__ double fin[kGmresMaxK];
-    if (!cond || gs->done) {                       // uniform
+    const bool act = !cond || gs->done;            // uniform
+    if (!act && threadIdx.x == 0) gs->finished = 0;
+    if (act) {
         reduce_partials(1, a.nblkA, a.part3, fin);
         if (threadIdx.x == 0) {
             const double beta = sqrt(fin[0]);
@@ -457,6 +460,7 @@ __global__ __launch_bounds__(kThr) void k_gmres_restart(GmresArgs a, int first, 
             const bool conv = !(beta > gs->target);
             gs->converged = conv ? 1 : 0;
             gs->done = (conv || !(beta == beta)) ? 1 : 0;
+            gs->finished = (conv || cap || !(beta == beta)) ? 1 : 0;
         }
     }
     // the state the host reads after a chunk, in host-visible memory
@@ -467,7 +471,7 @@ __global__ __launch_bounds__(kThr) void k_gmres_restart(GmresArgs a, int first, 
         p->jlast = gs->jlast;
         p->iters = gs->iters;
         p->cycles = gs->cycles;
-        p->pad = 0;
+        p->finished = gs->finished;
         p->inv_norm = gs->inv_norm;
         p->beta = gs->beta;
         p->bnorm = gs->bnorm;
@@ -553,10 +557,10 @@ hipError_t launch_precondition_matrix(int nblocks, int bs, const int* col,
 }
 
 hipError_t launch_gmres_restart(const GmresArgs& a, double* x,
-                                double* w, int first, int cond, hipStream_t st) {
+                                double* w, int first, int cond, int cap, hipStream_t st) {
     hipLaunchKernelGGL(k_gmres_residual, dim3(a.nblkA), dim3(256), 0, st, a, x,
                        w, first, cond);
-    hipLaunchKernelGGL(k_gmres_restart, dim3(1), dim3(kThr), 0, st, a, first, cond);
+    hipLaunchKernelGGL(k_gmres_restart, dim3(1), dim3(kThr), 0, st, a, first, cond, cap);
     return hipGetLastError();
 }
 

@@ -399,9 +399,11 @@ __global__ void k_absmax2_partial(int Nx, const double* x, int nbx, int Ny,
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// both maxima -> out[0], out[1] (host-visible), *go = 0 iff both <= tol
+// both maxima -> out[0], out[1] (host-visible), *go = 0 iff both <= tol or
+// the gate is closed; the two failure flags are copied to flags_out
 __global__ void k_absmax2_final(int nbx, int nby, const double* partial, double tol,
-                                double* out, int* go) {
+                                double* out, int* go, const int* gate,
+                                const int* flags, int* flags_out) {
     __shared__ double red[2][256];
     double mx = 0.0, my = 0.0;
     for (int i = threadIdx.x; i < nbx; i += blockDim.x) {
@@ -427,19 +429,25 @@ __global__ void k_absmax2_final(int nbx, int nby, const double* partial, double 
     if (threadIdx.x == 0) {
         out[0] = red[0][0];
         out[1] = red[1][0];
-        *go = (red[0][0] <= tol && red[1][0] <= tol) ? 0 : 1;
+        const bool open = !gate || *gate != 0;
+        *go = (open && !(red[0][0] <= tol && red[1][0] <= tol)) ? 1 : 0;
+        if (flags_out) {
+            flags_out[0] = flags[0];
+            flags_out[1] = flags[1];
+        }
     }
 }
 
 hipError_t launch_newton_norms(int Nx, const double* x, int Ny, const double* y,
                                double* partial, double tol, double* out, int* go,
+                               const int* gate, const int* flags, int* flags_out,
                                hipStream_t st) {
     const int nbx = std::min(1024, std::max(1, (Nx + kThreads - 1) / kThreads));
     const int nby = std::min(1024, std::max(1, (Ny + kThreads - 1) / kThreads));
     hipLaunchKernelGGL(k_absmax2_partial, dim3(nbx + nby), dim3(kThreads), 0, st, Nx, x,
                        nbx, Ny, y, partial);
     hipLaunchKernelGGL(k_absmax2_final, dim3(1), dim3(256), 0, st, nbx, nby, partial, tol,
-                       out, go);
+                       out, go, gate, flags, flags_out);
     return hipGetLastError();
 }
 
@@ -454,9 +462,10 @@ __global__ __launch_bounds__(256) void k_recover(RefOps o, int efr, int nimp,
                                                  const double* yr,
                                                  const int* trace_map,
                                                  const double* duhat,
-                                                 double* du) {
+                                                 double* du, const int* gate) {
     constexpr int NP = P * P, n = 4 * NP, m = 16 * P, N = n + m;
     __shared__ double sloc[4][m];
+    if (gate && *gate == 0) return;               // uniform over the grid
     __shared__ double gi[P * P];
     for (int t = threadIdx.x; t < P * P; t += blockDim.x) gi[t] = o.gi[t];
     __syncthreads();
@@ -492,9 +501,9 @@ template <typename T>
 static hipError_t launch_recover_t(const RefOps& o, int efr, int nimp, const T* M,
                                    const int* piv, const double* yr,
                                    const int* trace_map, const double* duhat,
-                                   double* du, hipStream_t st) {
+                                   double* du, const int* gate, hipStream_t st) {
     const dim3 grid((nimp + 3) / 4), blk(256);
-#define HFR_RC(PP) hipLaunchKernelGGL((k_recover<T, PP>), grid, blk, 0, st, o, efr, nimp, M, piv, yr, trace_map, duhat, du); break;
+#define HFR_RC(PP) hipLaunchKernelGGL((k_recover<T, PP>), grid, blk, 0, st, o, efr, nimp, M, piv, yr, trace_map, duhat, du, gate); break;
     switch (o.P) {
         case 2: HFR_RC(2)
         case 3: HFR_RC(3)
@@ -510,19 +519,20 @@ static hipError_t launch_recover_t(const RefOps& o, int efr, int nimp, const T* 
 hipError_t launch_recover(const RefOps& ops, bool efr, int nimp, const void* M,
                           int precision, const int* piv, const double* yr,
                           const int* trace_map, const double* duhat, double* du,
-                          hipStream_t st) {
+                          hipStream_t st, const int* gate) {
     if (nimp == 0) return hipSuccess;
     if (precision == HFR_PREC_FP64)
         return launch_recover_t(ops, efr ? 1 : 0, nimp, reinterpret_cast<const double*>(M),
-                                piv, yr, trace_map, duhat, du, st);
+                                piv, yr, trace_map, duhat, du, gate, st);
     return launch_recover_t(ops, efr ? 1 : 0, nimp, reinterpret_cast<const float*>(M),
-                            piv, yr, trace_map, duhat, du, st);
+                            piv, yr, trace_map, duhat, du, gate, st);
 }
 
 // ---- Newton update: u_im += du (scatter), uhat += duhat -----------------
 __global__ void k_newton_update(int Np, int nimp, int Ne, const int* imp_list,
                                 const double* du, double* u, int ntp4,
-                                const double* duhat, double* uhat) {
+                                const double* duhat, double* uhat, const int* gate) {
+    if (gate && *gate == 0) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int per = nimp * Np;
     const int nu = 4 * per;
@@ -539,11 +549,11 @@ __global__ void k_newton_update(int Np, int nimp, int Ne, const int* imp_list,
 hipError_t launch_newton_update(int Np, int nimp, int Ne, const int* imp_list,
                                 const double* du, double* u, int ntp4,
                                 const double* duhat, double* uhat,
-                                hipStream_t st) {
+                                hipStream_t st, const int* gate) {
     const long n = 4L * nimp * Np + ntp4;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_newton_update, dim3(blocks_for(n)), dim3(kThreads), 0,
-                       st, Np, nimp, Ne, imp_list, du, u, ntp4, duhat, uhat);
+                       st, Np, nimp, Ne, imp_list, du, u, ntp4, duhat, uhat, gate);
     return hipGetLastError();
 }
 

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -219,10 +220,12 @@ ResidualLaunch implicit_launch(hfr_solver_s* s, const double* u,
 // h, the element shares g^(k) and the assembled g (internal buffers)
 fr_status residual_internal(hfr_solver_s* s, const double* u,
                             const double* uhat, const double* ustar,
-                            double aii_dt, double* R_out, hipStream_t st) {
+                            double aii_dt, double* R_out, hipStream_t st,
+                            const int* gate = nullptr) {
     fr_mesh_s* m = s->mesh;
     if (m->Nim == 0) return FR_OK;
     ResidualLaunch a = implicit_launch(s, u, uhat);
+    a.gate = gate;
     a.R = R_out;
     a.h = s->h;
     a.ustar = ustar;
@@ -445,8 +448,13 @@ GmresArgs gmres_args(hfr_solver_s* s) {
 // state: a solve that converges within its first chunk costs one host
 // synchronisation.  Within a chunk there are no host round trips, and steps
 // after convergence return at entry.
+// chain (optional): work queued after every chunk's end-of-cycle kernels,
+// gated on the device by the solve's `finished` flag, that records the
+// readback mark itself; *chained tells whether it ran for a finished solve.
 fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
-                hipStream_t st) {
+                hipStream_t st, const std::function<fr_status()>& chain = nullptr,
+                bool* chained = nullptr) {
+    if (chained) *chained = false;
     const int N = s->N;
     hfr_solve_stats loc{};
     if (N == 0) {
@@ -463,7 +471,7 @@ fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
     GmresPublish hs{};
     // the restart kernel, last of every chunk's sequence, publishes the state
     auto fetch = [&]() -> fr_status {
-        fr_status e = readback_mark(s, st);
+        fr_status e = chain ? chain() : readback_mark(s, st);
         if (e) return e;
         if ((e = readback_wait(s))) return e;
         std::memcpy(&hs, s->hpin + kPinGmres, sizeof(hs));
@@ -471,7 +479,7 @@ fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
             return fail(FR_E_NONFINITE, "non-finite trace residual");
         return FR_OK;
     };
-    HIP_TRY(launch_gmres_restart(a, x, W0, 1, 0, st));
+    HIP_TRY(launch_gmres_restart(a, x, W0, 1, 0, 0, st));
     int launched = 0;
     int chunk = std::max(2, std::min(R, s->last_gmres_iters + 1));
     int cycles_seen = 0;
@@ -490,13 +498,16 @@ fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
         if (steps > 0) HIP_TRY(launch_arnoldi_finish(a, j - 1, st));
         launched += steps;
         // at the iteration cap the cycle is ended whether or not it is done
-        const int cond = launched >= maxit ? 0 : 1;
-        HIP_TRY(launch_gmres_update(a, x, cond, st));
-        HIP_TRY(launch_gmres_restart(a, x, W0, 0, cond, st));
+        const int cap = launched >= maxit ? 1 : 0;
+        HIP_TRY(launch_gmres_update(a, x, 1 - cap, st));
+        HIP_TRY(launch_gmres_restart(a, x, W0, 0, 1 - cap, cap, st));
         if ((e = fetch())) return e;
         if (hs.cycles != cycles_seen) {          // the cycle ended and restarted
             cycles_seen = hs.cycles;
-            if (hs.converged || launched >= maxit) break;
+            if (hs.finished) {
+                if (chained) *chained = chain != nullptr;
+                break;
+            }
             j = 0;
             chunk = std::max(2, std::min(R, s->last_gmres_iters + 1));
         } else {
@@ -533,20 +544,40 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
     if (e) return e;
     scale = std::max(1.0, scale);
     const double tol = s->opts.newton_tol * scale;
+    const int lag = s->opts.jacobian_lag;
+    const bool spec = lag <= 0 && m->Nim > 0;
+    int* flags_pub = reinterpret_cast<int*>(s->dpin + 4);
+    // Residual at the current iterate, its norms and the failure flags into
+    // the pinned buffer, the readback mark, then (unless the Jacobian is
+    // reused) the next linearisation's fill, which the device skips when the
+    // norms pass the test or the gate is closed.
+    auto queue_checks = [&](const int* gate) -> fr_status {
+        fr_status e2 = residual_internal(s, u, uhat, ustar, aii_dt, nullptr, st, gate);
+        if (e2) return e2;
+        HIP_TRY(launch_newton_norms(nu, s->h, 4 * m->Ntp, s->g, s->scratch, tol, s->dpin,
+                                    s->go, gate, s->flags, flags_pub, st));
+        if ((e2 = readback_mark(s, st))) return e2;
+        if (spec && (e2 = condense_fill(s, u, uhat, aii_dt, s->go, st))) return e2;
+        return FR_OK;
+    };
+    // After each GMRES chunk the update of the Newton iterate and the next
+    // checks are queued gated by the solve's `finished` flag, so the host's
+    // wait for the solve also covers them and the device does not idle.
+    const int* gate = &s->gs->finished;
+    auto after_solve = [&]() -> fr_status {
+        int tk = tbegin(s, HFR_T_RECOVER, st);
+        HIP_TRY(launch_recover(m->ops, m->efr, m->Nim, s->M, s->opts.precision, s->piv,
+                               s->yr, m->d_trace_map, s->duhat, s->du, st, gate));
+        HIP_TRY(launch_newton_update(m->Np, m->Nim, m->Ne, m->d_imp, s->du, u,
+                                     4 * m->Ntp, s->duhat, uhat, st, gate));
+        tend(s, tk, st);
+        return queue_checks(gate);
+    };
+    bool queued = false;
     for (int it = 0;; ++it) {
-        e = residual_internal(s, u, uhat, ustar, aii_dt, nullptr, st);
-        if (e) return e;
-        // norms -> pinned buffer; while the host waits, the fill of the next
-        // linearisation runs unless the device-side test says converged
-        const int lag = s->opts.jacobian_lag;
-        const bool spec = lag <= 0 && m->Nim > 0;
-        {
-            HIP_TRY(launch_newton_norms(nu, s->h, 4 * m->Ntp, s->g, s->scratch, tol,
-                                        s->dpin, s->go, st));
-            if ((e = readback_mark(s, st))) return e;
-            if (spec && (e = condense_fill(s, u, uhat, aii_dt, s->go, st))) return e;
-            if ((e = readback_wait(s))) return e;
-        }
+        if (!queued && (e = queue_checks(nullptr))) return e;
+        queued = false;
+        if ((e = readback_wait(s))) return e;
         const double hmax = s->hpin[0], gmax = s->hpin[1];
         const double res = std::max(hmax, gmax);
         if (s->verbose)
@@ -572,25 +603,30 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
             if ((e = recondense_rhs_internal(s, st))) return e;
         }
         hfr_solve_stats ks{};
+        bool chained = false;
         int tk = tbegin(s, HFR_T_TRACE_SOLVE, st);
-        e = gmres(s, s->duhat, &ks, st);
+        e = gmres(s, s->duhat, &ks, st, after_solve, &chained);
         tend(s, tk, st);
         if (s->verbose)
             fprintf(stderr, "[hfr]   gmres its %d restarts %d relres %.3e status %d\n",
                     ks.iterations, ks.restarts, ks.rel_residual, int(e));
         loc.gmres_iters += ks.iterations;
         if (e && e != FR_E_NOT_CONVERGED) return e;
-        tk = tbegin(s, HFR_T_RECOVER, st);
-        HIP_TRY(launch_recover(m->ops, m->efr, m->Nim, s->M, s->opts.precision, s->piv, s->yr,
-                               m->d_trace_map, s->duhat, s->du, st));
-        HIP_TRY(launch_newton_update(m->Np, m->Nim, m->Ne, m->d_imp, s->du, u,
-                                     4 * m->Ntp, s->duhat, uhat, st));
-        tend(s, tk, st);
+        if (chained) {
+            queued = true;                     // checks of the new iterate queued
+        } else {                               // no trace unknowns: no chain ran
+            tk = tbegin(s, HFR_T_RECOVER, st);
+            HIP_TRY(launch_recover(m->ops, m->efr, m->Nim, s->M, s->opts.precision, s->piv,
+                                   s->yr, m->d_trace_map, s->duhat, s->du, st));
+            HIP_TRY(launch_newton_update(m->Np, m->Nim, m->Ne, m->d_imp, s->du, u,
+                                         4 * m->Ntp, s->duhat, uhat, st));
+            tend(s, tk, st);
+        }
     }
     s->stage_calls++;
+    // failure flags as of the last check (published with its norms)
     int fl[2] = {0, 0};
-    HIP_TRY(hipMemcpyAsync(fl, s->flags, sizeof(fl), hipMemcpyDeviceToHost, st));
-    if ((e = sync_check(st))) return e;
+    std::memcpy(fl, s->hpin + 4, sizeof(fl));
     if (fl[0] || fl[1]) {
         HIP_TRY(hipMemsetAsync(s->flags, 0, sizeof(fl), st));
         if (stats) *stats = loc;

@@ -322,10 +322,15 @@ fr_status hfr_get_preconditioner(hfr_solver_t s, void* dinv, void* stream);
  * each kernel is launched on (the phases timed in the paper's performance
  * tables: implicit residual t_R^im, Jacobian and condensation t_J, global
  * solve t_G, local solve t_L, explicit residual t_R^ex).  enable = 1 resets
- * and starts, 0 stops; when ms / counts are non-NULL the accumulated totals
- * (HFR_NTIMERS entries, milliseconds and launch counts) are copied out after
- * a device synchronisation.
+ * and starts every category, HFR_TIMING_SELECT | (1 << HFR_T_x) | ... resets
+ * and starts the listed ones only, 0 stops, -1 leaves the state as it is;
+ * when ms / counts are non-NULL the accumulated totals (HFR_NTIMERS entries,
+ * milliseconds and launch counts) are copied out after a device
+ * synchronisation.  Every timed launch adds two event records to the
+ * stream, which costs device time: time the phases in a separate pass from
+ * the one whose wall time is measured.
  */
+#define HFR_TIMING_SELECT 0x10000
 enum { HFR_T_RESIDUAL = 0,   /* hybridized residual kernel                 */
        HFR_T_CONDENSE = 1,   /* element Jordan sweep kernel (condensation) */
        HFR_T_ASSEMBLE = 2,   /* block-sparse assembly kernel               */

@@ -21,6 +21,7 @@ EXPORTED = ["fr_mesh_create", "fr_mesh_destroy", "fr_mesh_get_info",
             "fr_last_error"]
 TIMERS = ["residual", "condense", "assemble", "pcsetup", "spmv",
           "trace_solve", "recover", "explicit", "fill"]
+TIMING_SELECT = 0x10000
 
 
 class FrMeshDesc(Structure):

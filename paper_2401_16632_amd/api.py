@@ -299,12 +299,18 @@ class Solver:
             d = ((d.to(torch.int32) & 0xFFFF) << 16).view(torch.float32)
         return d.double().view(ntf, bs, bs).transpose(1, 2)
 
-    def timing(self, enable=None):
-        """Start (True) / stop (False) the kernel timers; returns the
-        accumulated {name: (ms, launches)} after a device sync."""
+    def timing(self, enable=None, only=None):
+        """Start (True) / stop (False) the kernel timers, or with ``only`` (a
+        list of timer names) start those alone; returns the accumulated
+        {name: (ms, launches)} after a device sync."""
         ms = (ctypes.c_double * len(_abi.TIMERS))()
         cnt = (ctypes.c_int64 * len(_abi.TIMERS))()
-        en = -1 if enable is None else (1 if enable else 0)
+        if only is not None:
+            en = _abi.TIMING_SELECT
+            for name in only:
+                en |= 1 << _abi.TIMERS.index(name)
+        else:
+            en = -1 if enable is None else (1 if enable else 0)
         _check(load_library().hfr_timing(self.handle, en, ms, cnt))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(_abi.TIMERS)}
 

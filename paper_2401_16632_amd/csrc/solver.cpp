@@ -91,8 +91,9 @@ struct hfr_solver_s {
     hipEvent_t rb_ev = nullptr;  // marks the readback on the solver's stream
     size_t ws_bytes = 0;
     int nblk_dot = 1;
-    // event timers
+    // event timers (categories in tmask)
     bool timing = false;
+    unsigned tmask = 0;
     double tms[HFR_NTIMERS] = {};
     int64_t tcnt[HFR_NTIMERS] = {};
     struct Pend { hipEvent_t a, b; int cat; };
@@ -103,7 +104,7 @@ struct hfr_solver_s {
 namespace {
 
 int tbegin(hfr_solver_s* s, int cat, hipStream_t st) {
-    if (!s || !s->timing) return -1;
+    if (!s || !s->timing || !(s->tmask & (1u << cat))) return -1;
     std::pair<hipEvent_t, hipEvent_t> ev;
     if (s->pool.empty()) {
         if (hipEventCreate(&ev.first) != hipSuccess) return -1;
@@ -1044,15 +1045,22 @@ extern "C" fr_status hfr_timing(hfr_solver_t s, int32_t enable, double* ms,
             if (counts) counts[i] = s->tcnt[i];
         }
     }
-    if (enable == 1) {
+    if (enable == -1) {
+        // leave the timers as they are
+    } else if (enable == 1 || (enable > 0 && (enable & HFR_TIMING_SELECT))) {
         tflush(s);
         for (int i = 0; i < HFR_NTIMERS; ++i) {
             s->tms[i] = 0.0;
             s->tcnt[i] = 0;
         }
         s->timing = true;
+        s->tmask = enable == 1 ? (1u << HFR_NTIMERS) - 1
+                               : unsigned(enable) & ((1u << HFR_NTIMERS) - 1);
     } else if (enable == 0) {
         s->timing = false;
+    } else {
+        return fail(FR_E_INVALID, "hfr_timing: enable must be -1, 0, 1 or "
+                                  "HFR_TIMING_SELECT | categories");
     }
     return FR_OK;
 }

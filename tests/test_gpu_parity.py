@@ -275,3 +275,26 @@ def test_all_explicit_and_all_implicit_meshes():
         u0 = fi.isentropic_vortex(pr.om.x, pr.om.y)
         errs, _ = _run_steps(pr, u0, 0.02, 1)
         assert max(errs) <= 1e-11, errs
+
+
+def test_timing_categories():
+    """Selected timer categories record their kernels only; all categories
+    record every phase; the stage result does not depend on timing."""
+    pr, _ = _build("c1_p2")
+    u0 = fi.isentropic_vortex(pr.om.x, pr.om.y)
+    s = hp.Solver(pr.hm, rtol=1e-12, newton_tol=1e-13, max_iters=3000)
+    stp = hp.ImexStepper(pr.hm, s, "HIMEX2C")
+    s.timing(only=["condense"])
+    a, _ = stp.step(dev(soa(u0)), 0.01)
+    a = host(a)
+    t = s.timing(False)
+    assert t["condense"][1] > 0 and t["condense"][0] > 0
+    assert all(v[1] == 0 for k, v in t.items() if k != "condense"), t
+    s.timing(True)
+    b, _ = stp.step(dev(soa(u0)), 0.01)
+    b = host(b)
+    t = s.timing(False)
+    assert all(t[k][1] > 0 for k in ("residual", "condense", "fill", "trace_solve", "recover")), t
+    assert np.array_equal(a, b)
+    lib = hp.load_library()
+    assert lib.hfr_timing(s.handle, 7, None, None) != 0      # neither 0, 1 nor a selection

@@ -44,6 +44,7 @@ struct GmresArgs {
 struct GmresPublish {
     int done, converged, jlast, iters, cycles, finished;
     double inv_norm, beta, bnorm, target;
+    long long seq;           // written last, behind a system-scope fence
 };
 
 hipError_t launch_precondition_matrix(int nblocks, int bs, const int* col,
@@ -53,7 +54,8 @@ hipError_t launch_precondition_matrix(int nblocks, int bs, const int* col,
 // r = t - L x, beta = |r|, new cycle; cond: only if the cycle has ended
 // cap: the host ends the solve here (iteration cap)
 hipError_t launch_gmres_restart(const GmresArgs& a, double* x,
-                                double* w, int first, int cond, int cap, hipStream_t st);
+                                double* w, int first, int cond, int cap, long long seq,
+                                hipStream_t st);
 hipError_t launch_arnoldi_product(const GmresArgs& a, int j, int fin_prev,
                                   const double* wcur, double* wnxt, hipStream_t st);
 hipError_t launch_arnoldi_orth(const GmresArgs& a, int j, double* wnxt,

@@ -403,7 +403,8 @@ __global__ void k_absmax2_partial(int Nx, const double* x, int nbx, int Ny,
 // the gate is closed; the two failure flags are copied to flags_out
 __global__ void k_absmax2_final(int nbx, int nby, const double* partial, double tol,
                                 double* out, int* go, const int* gate,
-                                const int* flags, int* flags_out) {
+                                const int* flags, int* flags_out,
+                                long long* seq_out, long long seq) {
     __shared__ double red[2][256];
     double mx = 0.0, my = 0.0;
     for (int i = threadIdx.x; i < nbx; i += blockDim.x) {
@@ -435,19 +436,23 @@ __global__ void k_absmax2_final(int nbx, int nby, const double* partial, double 
             flags_out[0] = flags[0];
             flags_out[1] = flags[1];
         }
+        if (seq_out) {                    // published after the values above
+            __threadfence_system();
+            *reinterpret_cast<volatile long long*>(seq_out) = seq;
+        }
     }
 }
 
 hipError_t launch_newton_norms(int Nx, const double* x, int Ny, const double* y,
                                double* partial, double tol, double* out, int* go,
                                const int* gate, const int* flags, int* flags_out,
-                               hipStream_t st) {
+                               long long* seq_out, long long seq, hipStream_t st) {
     const int nbx = std::min(1024, std::max(1, (Nx + kThreads - 1) / kThreads));
     const int nby = std::min(1024, std::max(1, (Ny + kThreads - 1) / kThreads));
     hipLaunchKernelGGL(k_absmax2_partial, dim3(nbx + nby), dim3(kThreads), 0, st, Nx, x,
                        nbx, Ny, y, partial);
     hipLaunchKernelGGL(k_absmax2_final, dim3(1), dim3(256), 0, st, nbx, nby, partial, tol,
-                       out, go, gate, flags, flags_out);
+                       out, go, gate, flags, flags_out, seq_out, seq);
     return hipGetLastError();
 }
 

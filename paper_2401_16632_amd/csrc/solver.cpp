@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <functional>
 #include <map>
 #include <string>
@@ -89,6 +90,8 @@ struct hfr_solver_s {
                              // [0..1] Newton norms, [kPinGmres..] GMRES state
     double* dpin = nullptr;  // the same buffer's device address
     hipEvent_t rb_ev = nullptr;  // marks the readback on the solver's stream
+    long long seq_norms = 0;     // last sequence number queued for the norms
+    long long seq_gmres = 0;     // ... and for the GMRES state
     size_t ws_bytes = 0;
     int nblk_dot = 1;
     // event timers (categories in tmask)
@@ -179,9 +182,35 @@ void free_solver(hfr_solver_s* s) {
 constexpr int kPinDoubles = 64;
 constexpr int kPinGmres = 8;
 
+constexpr int kPinNormSeq = 3;    // long long at double slot 3
+constexpr int kPinFlags = 4;      // two int32 at double slot 4
+
 // Kernels write what the host reads (Newton norms, GMRES state) straight
-// into the pinned buffer; the host marks the stream and waits for the mark
-// (work queued after the mark runs meanwhile).
+// into the pinned buffer, a sequence number last behind a system-scope
+// fence.  The host spins on the sequence number, so no event record sits in
+// the stream between the kernels (work queued after it keeps running).
+fr_status wait_seq(hfr_solver_s* s, const void* slot, long long target, hipStream_t st) {
+    const volatile long long* p = reinterpret_cast<const volatile long long*>(slot);
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned it = 1;; ++it) {
+        if (*p >= target) {
+            std::atomic_thread_fence(std::memory_order_acquire);
+            return FR_OK;
+        }
+        if ((it & 4095) == 0) {
+            const hipError_t q = hipStreamQuery(st);
+            if (q != hipSuccess && q != hipErrorNotReady)
+                return fail(FR_E_DEVICE, std::string("device error: ") + hipGetErrorString(q));
+            if (q == hipSuccess && *p < target)
+                return fail(FR_E_DEVICE, "stream idle but the readback was not published");
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(600))
+                return fail(FR_E_DEVICE, "readback wait timed out");
+        }
+        __builtin_ia32_pause();
+    }
+}
+
+// Event-marked readback (kernels without a sequence number).
 fr_status readback_mark(hfr_solver_s* s, hipStream_t st) {
     HIP_TRY(hipEventRecord(s->rb_ev, st));
     return FR_OK;
@@ -472,15 +501,19 @@ fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
     GmresPublish hs{};
     // the restart kernel, last of every chunk's sequence, publishes the state
     auto fetch = [&]() -> fr_status {
-        fr_status e = chain ? chain() : readback_mark(s, st);
+        fr_status e = chain ? chain() : FR_OK;
         if (e) return e;
-        if ((e = readback_wait(s))) return e;
+        // the chain publishes the norms after the restart kernel's state
+        if (chain) e = wait_seq(s, s->hpin + kPinNormSeq, s->seq_norms, st);
+        else e = wait_seq(s, &reinterpret_cast<GmresPublish*>(s->hpin + kPinGmres)->seq,
+                          s->seq_gmres, st);
+        if (e) return e;
         std::memcpy(&hs, s->hpin + kPinGmres, sizeof(hs));
         if (!(hs.beta == hs.beta) || std::isinf(hs.beta))
             return fail(FR_E_NONFINITE, "non-finite trace residual");
         return FR_OK;
     };
-    HIP_TRY(launch_gmres_restart(a, x, W0, 1, 0, 0, st));
+    HIP_TRY(launch_gmres_restart(a, x, W0, 1, 0, 0, ++s->seq_gmres, st));
     int launched = 0;
     int chunk = std::max(2, std::min(R, s->last_gmres_iters + 1));
     int cycles_seen = 0;
@@ -501,7 +534,7 @@ fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
         // at the iteration cap the cycle is ended whether or not it is done
         const int cap = launched >= maxit ? 1 : 0;
         HIP_TRY(launch_gmres_update(a, x, 1 - cap, st));
-        HIP_TRY(launch_gmres_restart(a, x, W0, 0, 1 - cap, cap, st));
+        HIP_TRY(launch_gmres_restart(a, x, W0, 0, 1 - cap, cap, ++s->seq_gmres, st));
         if ((e = fetch())) return e;
         if (hs.cycles != cycles_seen) {          // the cycle ended and restarted
             cycles_seen = hs.cycles;
@@ -547,7 +580,8 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
     const double tol = s->opts.newton_tol * scale;
     const int lag = s->opts.jacobian_lag;
     const bool spec = lag <= 0 && m->Nim > 0;
-    int* flags_pub = reinterpret_cast<int*>(s->dpin + 4);
+    int* flags_pub = reinterpret_cast<int*>(s->dpin + kPinFlags);
+    long long* seq_pub = reinterpret_cast<long long*>(s->dpin + kPinNormSeq);
     // Residual at the current iterate, its norms and the failure flags into
     // the pinned buffer, the readback mark, then (unless the Jacobian is
     // reused) the next linearisation's fill, which the device skips when the
@@ -556,8 +590,8 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         fr_status e2 = residual_internal(s, u, uhat, ustar, aii_dt, nullptr, st, gate);
         if (e2) return e2;
         HIP_TRY(launch_newton_norms(nu, s->h, 4 * m->Ntp, s->g, s->scratch, tol, s->dpin,
-                                    s->go, gate, s->flags, flags_pub, st));
-        if ((e2 = readback_mark(s, st))) return e2;
+                                    s->go, gate, s->flags, flags_pub, seq_pub,
+                                    ++s->seq_norms, st));
         if (spec && (e2 = condense_fill(s, u, uhat, aii_dt, s->go, st))) return e2;
         return FR_OK;
     };
@@ -578,7 +612,7 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
     for (int it = 0;; ++it) {
         if (!queued && (e = queue_checks(nullptr))) return e;
         queued = false;
-        if ((e = readback_wait(s))) return e;
+        if ((e = wait_seq(s, s->hpin + kPinNormSeq, s->seq_norms, st))) return e;
         const double hmax = s->hpin[0], gmax = s->hpin[1];
         const double res = std::max(hmax, gmax);
         if (s->verbose)
@@ -627,7 +661,7 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
     s->stage_calls++;
     // failure flags as of the last check (published with its norms)
     int fl[2] = {0, 0};
-    std::memcpy(fl, s->hpin + 4, sizeof(fl));
+    std::memcpy(fl, s->hpin + kPinFlags, sizeof(fl));
     if (fl[0] || fl[1]) {
         HIP_TRY(hipMemsetAsync(s->flags, 0, sizeof(fl), st));
         if (stats) *stats = loc;
@@ -782,6 +816,7 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
                   ? FR_OK
                   : fail(FR_E_NOMEM, "pinned readback buffer: hipHostMalloc or "
                                      "hipHostGetDevicePointer failed"))) ||
+        (e = (std::memset(s->hpin, 0, kPinDoubles * sizeof(double)), FR_OK)) ||
         (e = (hipEventCreateWithFlags(&s->rb_ev, hipEventDisableTiming) == hipSuccess
                   ? FR_OK
                   : fail(FR_E_DEVICE, "hipEventCreateWithFlags failed")))) {

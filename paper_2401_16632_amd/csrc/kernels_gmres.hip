@@ -519,10 +519,61 @@ __global__ __launch_bounds__(256) void k_precondition_matrix(int nblocks, const 
     }
 }
 
+// bs = 16: the same product on 16x16x4 matrix-core tiles, one wave per
+// block, K = 16 in four steps.  Operands: lane l = 16 g + i holds
+// L(i, 4kk + g) (a contiguous 64-value slice of the column-major block) and
+// Dinv(4kk + g, i); the FP32 result holds Lt(4g + r, i) in register r, the
+// FP64 result Lt(g + 4r, i).
+typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef double md4 __attribute__((ext_vector_type(4)));
+template <typename TL, typename TD>
+__global__ __launch_bounds__(256) void k_precondition_matrix16(int nblocks, const int* col,
+                                                               const TL* L, const TD* Dinv,
+                                                               TL* Lt) {
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= nblocks) return;                      // whole wave
+    const size_t lb = size_t(p) * 256, db = size_t(col[p]) * 256;
+    const int i = lane & 15, g = lane >> 4;
+    if constexpr (sizeof(TL) == 4) {
+        mf4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const float a = L[lb + 64 * kk + lane];
+            const float b = float(load_pc(Dinv, db + i * 16 + 4 * kk + g));
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Lt[lb + (4 * g + r) * 16 + i] = acc[r];
+    } else {
+        md4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const double a = L[lb + 64 * kk + lane];
+            const double b = load_pc(Dinv, db + i * 16 + 4 * kk + g);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Lt[lb + (g + 4 * r) * 16 + i] = acc[r];
+    }
+}
+
 template <int BS, typename TL>
 static void launch_pm_t(int nblocks, const int* col, const TL* L, int pc,
                         const void* Dinv, TL* Lt, hipStream_t st) {
     const dim3 grid((nblocks + 3) / 4), blk(256);
+    if constexpr (BS == 16) {
+        if (pc == HFR_PC_FP64)
+            hipLaunchKernelGGL((k_precondition_matrix16<TL, double>), grid, blk, 0, st, nblocks,
+                               col, L, reinterpret_cast<const double*>(Dinv), Lt);
+        else if (pc == HFR_PC_FP32)
+            hipLaunchKernelGGL((k_precondition_matrix16<TL, float>), grid, blk, 0, st, nblocks,
+                               col, L, reinterpret_cast<const float*>(Dinv), Lt);
+        else
+            hipLaunchKernelGGL((k_precondition_matrix16<TL, uint16_t>), grid, blk, 0, st,
+                               nblocks, col, L, reinterpret_cast<const uint16_t*>(Dinv), Lt);
+        return;
+    }
     if (pc == HFR_PC_FP64)
         hipLaunchKernelGGL((k_precondition_matrix<BS, TL, double>), grid, blk, 0, st, nblocks, col, L,
                            reinterpret_cast<const double*>(Dinv), Lt);

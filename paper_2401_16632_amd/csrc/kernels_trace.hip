@@ -155,17 +155,99 @@ __global__ __launch_bounds__(256) void k_block_inverse(int ntf, const int* diag_
     }
 }
 
+// Blocks of at most 16 rows: four blocks per wave, one per row of 16 lanes
+// (lane r of a row holds row r of its block).  The pivot search is a
+// 16-lane DPP maximum; the pivot row is passed through LDS (each row's
+// pivot lane writes it, the row's lanes read it back).  Rows of a wave past
+// the last block run on the identity and store nothing.
+__device__ __forceinline__ unsigned long long row16_max_key(unsigned long long x) {
+    x = key_max(x, key_dpp<0xb1, 0xf>(x));      // quad_perm [1,0,3,2]
+    x = key_max(x, key_dpp<0x4e, 0xf>(x));      // quad_perm [2,3,0,1]
+    x = key_max(x, key_dpp<0x141, 0xf>(x));     // row_half_mirror
+    x = key_max(x, key_dpp<0x140, 0xf>(x));     // row_mirror: every lane of the row
+    return x;
+}
+
+template <int BS>
+__global__ __launch_bounds__(256) void k_block_inverse16(int ntf, const int* diag_blk,
+                                                         const double* L64,
+                                                         const float* L32, int pc,
+                                                         void* out, int* fail) {
+    static_assert(BS <= 16, "four blocks per wave need BS <= 16");
+    __shared__ double prow[4][4][BS];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int grp = lane >> 4, r = lane & 15;
+    const int F = (blockIdx.x * 4 + wv) * 4 + grp;
+    const bool valid = F < ntf;
+    const size_t blk = valid ? size_t(diag_blk[F]) * BS * BS : 0;
+    double t[BS];
+#pragma unroll
+    for (int c = 0; c < BS; ++c) {
+        const size_t i = blk + size_t(c) * BS + min(r, BS - 1);   // in bounds
+        double v = c == r ? 1.0 : 0.0;
+        if (valid) v = L64 ? L64[i] : double(L32[i]);
+        t[c] = r < BS ? v : 0.0;
+    }
+    double sig = 1.0;
+    bool used = r >= BS, bad = false;
+    int pos = 0;
+    int pj[BS];
+#pragma unroll
+    for (int k = 0; k < BS; ++k) {
+        const unsigned long long key =
+            row16_max_key(used ? 0ull : pivot_key(float(fabs(t[k])), r));
+        int p = int(0xffffffffu - unsigned(key));
+        if ((key >> 32) == 0) {                     // no nonzero candidate
+            bad = true;
+            p = 0;
+        }
+        pj[k] = p;
+        if (r == p) {
+#pragma unroll
+            for (int j = 0; j < BS; ++j) prow[wv][grp][j] = t[j];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double u[BS];
+#pragma unroll
+        for (int j = 0; j < BS; ++j) u[j] = prow[wv][grp][j];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const double ipv = bad ? 0.0 : 1.0 / u[k];
+        const double g = (r == p) ? 0.0 : t[k] * ipv;
+#pragma unroll
+        for (int j = 0; j < BS; ++j) t[j] = fma(-g, u[j], t[j]);
+        t[k] = (r == p) ? -1.0 : g;
+        if (r == p) { used = true; sig = -ipv; pos = k; }
+    }
+    if (bad && valid && r == 0) *fail = 1;
+    if (!valid || r >= BS) return;
+    // store column-major: out[F][b][a] = Inv[a][b], Inv[pos][p_j] = sig t[j]
+    const size_t o = size_t(F) * BS * BS + pos;
+#pragma unroll
+    for (int j = 0; j < BS; ++j) {
+        const double v = sig * t[j];
+        const size_t i = o + size_t(pj[j]) * BS;
+        if (pc == HFR_PC_FP64) reinterpret_cast<double*>(out)[i] = v;
+        else if (pc == HFR_PC_FP32) reinterpret_cast<float*>(out)[i] = float(v);
+        else reinterpret_cast<uint16_t*>(out)[i] = f2bf(float(v));
+    }
+}
+
 hipError_t launch_block_inverse_impl(int ntf, int bs, const int* diag_blk,
                                      const double* L64, const float* L32,
                                      int pc, void* out, int* fail,
                                      hipStream_t st) {
     if (ntf == 0) return hipSuccess;
     const dim3 grid((ntf + 3) / 4), blk(256);
+    const dim3 grid16((ntf + 15) / 16);            // four blocks per wave
     switch (bs) {
-        case 4: hipLaunchKernelGGL(k_block_inverse<4>, grid, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
-        case 8: hipLaunchKernelGGL(k_block_inverse<8>, grid, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
-        case 12: hipLaunchKernelGGL(k_block_inverse<12>, grid, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
-        case 16: hipLaunchKernelGGL(k_block_inverse<16>, grid, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
+        case 4: hipLaunchKernelGGL(k_block_inverse16<4>, grid16, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
+        case 8: hipLaunchKernelGGL(k_block_inverse16<8>, grid16, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
+        case 12: hipLaunchKernelGGL(k_block_inverse16<12>, grid16, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
+        case 16: hipLaunchKernelGGL(k_block_inverse16<16>, grid16, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
         case 20: hipLaunchKernelGGL(k_block_inverse<20>, grid, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
         case 24: hipLaunchKernelGGL(k_block_inverse<24>, grid, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
         default: return hipErrorInvalidValue;

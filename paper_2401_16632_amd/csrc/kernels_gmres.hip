@@ -155,13 +155,17 @@ __device__ void givens_column(const GmresArgs& a, int jc, double hn, bool write,
 // (consecutive lanes read consecutive rows of a column).
 template <bool ROW_MAJOR, typename T>
 __device__ __forceinline__ double row_share(const GmresArgs& a, const T* M,
-                                            const double* x, int r) {
+                                            const double* x, int r, int pb = -1,
+                                            int p1 = -1) {
     const int bs = a.bs;
     const int F = r / bs, aa = r - F * bs;
     const int part = threadIdx.x >> 6;
-    const int p1 = a.rowptr[F + 1];
+    if (pb < 0) {                                  // row pointers not preloaded
+        pb = a.rowptr[F];
+        p1 = a.rowptr[F + 1];
+    }
     double acc = 0.0;
-    for (int p = a.rowptr[F] + part; p < p1; p += 4) {
+    for (int p = pb + part; p < p1; p += 4) {
         const double2* x2 = reinterpret_cast<const double2*>(x + size_t(a.col[p]) * bs);
         if (ROW_MAJOR) {
             const T* row = M + (size_t(p) * bs + aa) * bs;
@@ -209,22 +213,29 @@ __global__ __launch_bounds__(256) void k_arnoldi_a(GmresArgs a, int j, int fin_p
                                                    const double* wcur,
                                                    double* wnxt) {
     GmresState* gs = a.gs;
-    if (gs->done) return;
-    __shared__ double red[kGmresMaxK * 4];
-    __shared__ double sacc[8][4][64];
-    __shared__ GivensStage gv;
     const int bs = a.bs;
     const int f0 = blockIdx.x * a.fpbA, f1 = min(a.ntf, f0 + a.fpbA);
     const int r0 = f0 * bs, r1 = f1 * bs;
     const int part = threadIdx.x >> 6, lr = threadIdx.x & 63;
+    // the first pass's row pointers are loaded together with the flag
+    int pb0 = 0, pe0 = 0;
+    if (r0 + lr < r1) {
+        const int F0 = (r0 + lr) / bs;
+        pb0 = a.rowptr[F0];
+        pe0 = a.rowptr[F0 + 1];
+    }
+    if (gs->done) return;
+    __shared__ double red[kGmresMaxK * 4];
+    __shared__ double sacc[8][4][64];
+    __shared__ GivensStage gv;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int r = r0 + 64 * q + lr;
         if (r0 + 64 * q >= r1) break;             // uniform
         double acc = 0.0;
         if (r < r1)
-            acc = a.Lt64 ? row_share<true>(a, a.Lt64, wcur, r)
-                         : row_share<true>(a, a.Lt32, wcur, r);
+            acc = a.Lt64 ? row_share<true>(a, a.Lt64, wcur, r, q == 0 ? pb0 : -1, pe0)
+                         : row_share<true>(a, a.Lt32, wcur, r, q == 0 ? pb0 : -1, pe0);
         sacc[q][part][lr] = acc;
     }
     double inv;

@@ -447,25 +447,30 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
     T gs[RPL];
     T ipv = T(0);
     int p = -1;
+    // pivot search: 32-bit keys (n <= 144 < 256 candidate rows)
+    static_assert(n <= 256, "pivot rows must fit the 8-bit row field");
     auto find_pivot = [&](const T (&col)[RPL], int step, T (&g)[RPL], T& ip, int& pp) {
-        unsigned long long key = 0;
+        unsigned key = 0;
 #pragma unroll
         for (int s = 0; s < SPN; ++s) {
             const int row = lane + 64 * s;
-            const unsigned long long ks = pivot_key(float(fabs(col[s])), row);
+            const unsigned ks = pivot_key32(float(fabs(col[s])), row);
             if (row < n && !used[s] && ks > key) key = ks;
         }
-        key = wave_max_key(key);
+        key = wave_max_u32(key);
         pp = -1;
         ip = T(0);
-        if ((key >> 32) != 0) {
-            pp = int(0xffffffffu - unsigned(key));
+        if (key != 0) {
+            pp = 255 - int(key & 0xffu);
             const int sp = pp >> 6, lp = pp & 63;
             T pv = T(1);
 #pragma unroll
             for (int s = 0; s < SPN; ++s)
                 if (SPN == 1 || s == sp) pv = lane_value(col[s], lp);
-            ip = T(1) / pv;
+            // FP32: the hardware reciprocal (1 ulp) instead of the
+            // correctly rounded division sequence on the critical path
+            if constexpr (sizeof(T) == 4) ip = __builtin_amdgcn_rcpf(pv);
+            else ip = T(1) / pv;
         }
 #pragma unroll
         for (int s = 0; s < RPL; ++s)

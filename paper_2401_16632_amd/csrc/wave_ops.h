@@ -57,6 +57,30 @@ __device__ __forceinline__ double wave_sum(double x) {
     return lane_value(x, 63);
 }
 
+// Wave-wide maximum of a 32-bit key by the same DPP row operations; every
+// lane gets the maximum.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ unsigned key32_dpp(unsigned x) {
+    return unsigned(__builtin_amdgcn_update_dpp(int(x), int(x), CTRL, ROWMASK, 0xf, false));
+}
+__device__ __forceinline__ unsigned wave_max_u32(unsigned x) {
+    x = max(x, key32_dpp<0xb1, 0xf>(x));        // quad_perm [1,0,3,2]
+    x = max(x, key32_dpp<0x4e, 0xf>(x));        // quad_perm [2,3,0,1]
+    x = max(x, key32_dpp<0x141, 0xf>(x));       // row_half_mirror
+    x = max(x, key32_dpp<0x140, 0xf>(x));       // row_mirror
+    x = max(x, key32_dpp<0x142, 0xa>(x));       // row_bcast:15
+    x = max(x, key32_dpp<0x143, 0xc>(x));       // row_bcast:31
+    return unsigned(__builtin_amdgcn_readlane(int(x), 63));
+}
+// 32-bit pivot key for rows below 256: |value| (FP32 bits) with its low 8
+// mantissa bits replaced by the complement of the row, so the maximum is a
+// largest magnitude (to 2^-15 relative) with the lowest row; 0 means no
+// nonzero candidate
+__device__ __forceinline__ unsigned pivot_key32(float mag, int row) {
+    const unsigned b = __float_as_uint(mag) & 0xffffff00u;
+    return b ? (b | unsigned(255 - row)) : 0u;
+}
+
 // pivot key: |value| (as FP32, order-preserving bits) above the complement
 // of the row, so the maximum is the largest magnitude with the lowest row
 __device__ __forceinline__ unsigned long long pivot_key(float mag, int row) {

@@ -164,6 +164,12 @@ hipError_t launch_recover(const RefOps& ops, bool efr, int nimp, const void* M,
                           int precision, const int* piv, const double* yr,
                           const int* trace_map, const double* duhat, double* du,
                           hipStream_t st, const int* gate = nullptr);
+// recovery and the Newton update (u_im += du, uhat += duhat) in one launch
+hipError_t launch_recover_update(const RefOps& ops, bool efr, int nimp, const void* M,
+                                 int precision, const int* piv, const double* yr,
+                                 const int* trace_map, const double* duhat, double* du,
+                                 int Ne, const int* imp_list, double* u, int ntp4,
+                                 double* uhat, hipStream_t st, const int* gate = nullptr);
 
 // ---- interior-embedded trace (kernels_efr.hip) ------------------------
 // g at the trace nodes: sum over each node's incidences (slot
@@ -227,6 +233,13 @@ hipError_t launch_newton_norms(int Nx, const double* x, int Ny, const double* y,
                                long long* seq_out, long long seq, hipStream_t st);
 hipError_t launch_trace_gather_g(int ntp, int P, const int* tpside,
                                  const double* gk, double* g,
+                                 hipStream_t st);
+// launch_trace_gather_g and launch_newton_norms (x = h, y = g) in two
+// launches: the gather also takes the partial maxima
+hipError_t launch_gather_g_norms(int ntp, const int* tpside, const double* gk, double* g,
+                                 int Nx, const double* x, double* partial, double tol,
+                                 double* out, int* go, const int* gate, const int* flags,
+                                 int* flags_out, long long* seq_out, long long seq,
                                  hipStream_t st);
 
 }  // namespace hfr

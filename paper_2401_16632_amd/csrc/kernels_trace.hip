@@ -542,17 +542,33 @@ hipError_t launch_newton_norms(int Nx, const double* x, int Ny, const double* y,
 // du[k] = (A^-1 r)[k] - (A^-1 B duhat_loc)[k] = y~[p_k] + T[p_k][n:N] duhat_loc
 // with y~ from the FP64 right-hand-side pass (pivot-row order).  One wave
 // per element, four elements per workgroup; lane l computes the unknowns
-// l, l + 64, ...
+// l, l + 64, ...  With nu set the same launch also applies the Newton update:
+// every element adds du to its state in u, and the workgroups past the
+// elements' add duhat to uhat (neither u nor uhat is read by the recovery).
+struct NewtonUpdate {
+    double* u;              // [4][Ne][Np] state (null: recovery only)
+    const int* imp_list;
+    int Ne;
+    int ntp4;               // trace unknowns
+    double* uhat;
+};
 template <typename T, int P>
 __global__ __launch_bounds__(256) void k_recover(RefOps o, int efr, int nimp,
                                                  const T* M, const int* piv,
                                                  const double* yr,
                                                  const int* trace_map,
                                                  const double* duhat,
-                                                 double* du, const int* gate) {
+                                                 double* du, const int* gate,
+                                                 NewtonUpdate nu) {
     constexpr int NP = P * P, n = 4 * NP, m = 16 * P, N = n + m;
     __shared__ double sloc[4][m];
     if (gate && *gate == 0) return;               // uniform over the grid
+    const int nbe = (nimp + 3) / 4;
+    if (int(blockIdx.x) >= nbe) {                 // trace part of the update
+        const long i = (long(blockIdx.x) - nbe) * blockDim.x + threadIdx.x;
+        if (i < nu.ntp4) nu.uhat[i] += duhat[i];
+        return;                                   // uniform over the workgroup
+    }
     __shared__ double gi[P * P];
     for (int t = threadIdx.x; t < P * P; t += blockDim.x) gi[t] = o.gi[t];
     __syncthreads();
@@ -581,6 +597,8 @@ __global__ __launch_bounds__(256) void k_recover(RefOps o, int efr, int nimp,
         double acc = yr[size_t(k) * n + pr];
         for (int b = 0; b < m; ++b) acc += double(Mk[size_t(b) * N + pr]) * sloc[wv][b];
         du[size_t(row & 3) * nimp * NP + size_t(k) * NP + (row >> 2)] = acc;
+        if (nu.u)
+            nu.u[size_t(row & 3) * nu.Ne * NP + size_t(nu.imp_list[k]) * NP + (row >> 2)] += acc;
     }
 }
 
@@ -588,9 +606,11 @@ template <typename T>
 static hipError_t launch_recover_t(const RefOps& o, int efr, int nimp, const T* M,
                                    const int* piv, const double* yr,
                                    const int* trace_map, const double* duhat,
-                                   double* du, const int* gate, hipStream_t st) {
-    const dim3 grid((nimp + 3) / 4), blk(256);
-#define HFR_RC(PP) hipLaunchKernelGGL((k_recover<T, PP>), grid, blk, 0, st, o, efr, nimp, M, piv, yr, trace_map, duhat, du, gate); break;
+                                   double* du, const int* gate, const NewtonUpdate& nu,
+                                   hipStream_t st) {
+    const int nbt = nu.u ? int((nu.ntp4 + 255) / 256) : 0;
+    const dim3 grid((nimp + 3) / 4 + nbt), blk(256);
+#define HFR_RC(PP) hipLaunchKernelGGL((k_recover<T, PP>), grid, blk, 0, st, o, efr, nimp, M, piv, yr, trace_map, duhat, du, gate, nu); break;
     switch (o.P) {
         case 2: HFR_RC(2)
         case 3: HFR_RC(3)
@@ -608,11 +628,27 @@ hipError_t launch_recover(const RefOps& ops, bool efr, int nimp, const void* M,
                           const int* trace_map, const double* duhat, double* du,
                           hipStream_t st, const int* gate) {
     if (nimp == 0) return hipSuccess;
+    const NewtonUpdate nu{nullptr, nullptr, 0, 0, nullptr};
     if (precision == HFR_PREC_FP64)
         return launch_recover_t(ops, efr ? 1 : 0, nimp, reinterpret_cast<const double*>(M),
-                                piv, yr, trace_map, duhat, du, gate, st);
+                                piv, yr, trace_map, duhat, du, gate, nu, st);
     return launch_recover_t(ops, efr ? 1 : 0, nimp, reinterpret_cast<const float*>(M),
-                            piv, yr, trace_map, duhat, du, gate, st);
+                            piv, yr, trace_map, duhat, du, gate, nu, st);
+}
+
+hipError_t launch_recover_update(const RefOps& ops, bool efr, int nimp, const void* M,
+                                 int precision, const int* piv, const double* yr,
+                                 const int* trace_map, const double* duhat, double* du,
+                                 int Ne, const int* imp_list, double* u, int ntp4,
+                                 double* uhat, hipStream_t st, const int* gate) {
+    if (nimp == 0)
+        return launch_newton_update(0, 0, Ne, imp_list, du, u, ntp4, duhat, uhat, st, gate);
+    const NewtonUpdate nu{u, imp_list, Ne, ntp4, uhat};
+    if (precision == HFR_PREC_FP64)
+        return launch_recover_t(ops, efr ? 1 : 0, nimp, reinterpret_cast<const double*>(M),
+                                piv, yr, trace_map, duhat, du, gate, nu, st);
+    return launch_recover_t(ops, efr ? 1 : 0, nimp, reinterpret_cast<const float*>(M),
+                            piv, yr, trace_map, duhat, du, gate, nu, st);
 }
 
 // ---- Newton update: u_im += du (scatter), uhat += duhat -----------------
@@ -652,6 +688,59 @@ __global__ void k_gather_g(int ntp, const int* tpside, const double* gk,
     const int tp = int(i >> 2), v = int(i & 3);
     const int s0 = tpside[2 * tp], s1 = tpside[2 * tp + 1];
     g[i] = gk[size_t(s0) * 4 + v] + gk[size_t(s1) * 4 + v];
+}
+
+// The transmission residual g (as k_gather_g) together with the partial
+// maxima of the Newton test: workgroups [0, nbx) take |x| over a grid
+// stride, the others form g and take |g|, each writing its maximum to
+// partial[blockIdx.x] (the layout k_absmax2_final reads)
+__global__ void k_gather_g_absmax(int ntp, const int* tpside, const double* gk,
+                                  double* g, int Nx, const double* x, int nbx,
+                                  double* partial) {
+    __shared__ double red[kThreads];
+    double mx = 0.0;
+    if (int(blockIdx.x) < nbx) {
+        for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < Nx;
+             i += long(nbx) * blockDim.x) {
+            const double a = fabs(x[i]);
+            mx = (a > mx || a != a) ? a : mx;
+        }
+    } else {
+        const long nby = long(gridDim.x) - nbx;
+        for (long i = (long(blockIdx.x) - nbx) * blockDim.x + threadIdx.x; i < 4L * ntp;
+             i += nby * blockDim.x) {
+            const int tp = int(i >> 2), v = int(i & 3);
+            const int s0 = tpside[2 * tp], s1 = tpside[2 * tp + 1];
+            const double gv = gk[size_t(s0) * 4 + v] + gk[size_t(s1) * 4 + v];
+            g[i] = gv;
+            const double a = fabs(gv);
+            mx = (a > mx || a != a) ? a : mx;
+        }
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double o = red[threadIdx.x + s];
+            if (o > red[threadIdx.x] || o != o) red[threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+hipError_t launch_gather_g_norms(int ntp, const int* tpside, const double* gk, double* g,
+                                 int Nx, const double* x, double* partial, double tol,
+                                 double* out, int* go, const int* gate, const int* flags,
+                                 int* flags_out, long long* seq_out, long long seq,
+                                 hipStream_t st) {
+    const int nbx = std::min(1024, std::max(1, (Nx + kThreads - 1) / kThreads));
+    const int nby = std::min(1024, std::max(1, (4 * ntp + kThreads - 1) / kThreads));
+    hipLaunchKernelGGL(k_gather_g_absmax, dim3(nbx + nby), dim3(kThreads), 0, st, ntp,
+                       tpside, gk, g, Nx, x, nbx, partial);
+    hipLaunchKernelGGL(k_absmax2_final, dim3(1), dim3(256), 0, st, nbx, nby, partial, tol,
+                       out, go, gate, flags, flags_out, seq_out, seq);
+    return hipGetLastError();
 }
 
 hipError_t launch_trace_gather_g(int ntp, int P, const int* tpside,

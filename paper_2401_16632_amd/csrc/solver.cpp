@@ -251,7 +251,7 @@ ResidualLaunch implicit_launch(hfr_solver_s* s, const double* u,
 fr_status residual_internal(hfr_solver_s* s, const double* u,
                             const double* uhat, const double* ustar,
                             double aii_dt, double* R_out, hipStream_t st,
-                            const int* gate = nullptr) {
+                            const int* gate = nullptr, bool gather = true) {
     fr_mesh_s* m = s->mesh;
     if (m->Nim == 0) return FR_OK;
     ResidualLaunch a = implicit_launch(s, u, uhat);
@@ -267,7 +267,7 @@ fr_status residual_internal(hfr_solver_s* s, const double* u,
     if (m->efr)
         HIP_TRY(launch_efr_gather_g(m->ops, m->Ntp, m->d_efr_inc_ptr, m->d_efr_inc,
                                     s->gk, s->g, st));
-    else
+    else if (gather)
         HIP_TRY(launch_trace_gather_g(m->Ntp, m->P, m->d_tpside, s->gk, s->g, st));
     return FR_OK;
 }
@@ -587,11 +587,18 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
     // reused) the next linearisation's fill, which the device skips when the
     // norms pass the test or the gate is closed.
     auto queue_checks = [&](const int* gate) -> fr_status {
-        fr_status e2 = residual_internal(s, u, uhat, ustar, aii_dt, nullptr, st, gate);
+        // the HFR gather of g also takes the norms' partial maxima
+        fr_status e2 = residual_internal(s, u, uhat, ustar, aii_dt, nullptr, st, gate,
+                                         m->efr);
         if (e2) return e2;
-        HIP_TRY(launch_newton_norms(nu, s->h, 4 * m->Ntp, s->g, s->scratch, tol, s->dpin,
-                                    s->go, gate, s->flags, flags_pub, seq_pub,
-                                    ++s->seq_norms, st));
+        if (m->efr)
+            HIP_TRY(launch_newton_norms(nu, s->h, 4 * m->Ntp, s->g, s->scratch, tol,
+                                        s->dpin, s->go, gate, s->flags, flags_pub, seq_pub,
+                                        ++s->seq_norms, st));
+        else
+            HIP_TRY(launch_gather_g_norms(m->Ntp, m->d_tpside, s->gk, s->g, nu, s->h,
+                                          s->scratch, tol, s->dpin, s->go, gate, s->flags,
+                                          flags_pub, seq_pub, ++s->seq_norms, st));
         if (spec && (e2 = condense_fill(s, u, uhat, aii_dt, s->go, st))) return e2;
         return FR_OK;
     };
@@ -601,10 +608,9 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
     const int* gate = &s->gs->finished;
     auto after_solve = [&]() -> fr_status {
         int tk = tbegin(s, HFR_T_RECOVER, st);
-        HIP_TRY(launch_recover(m->ops, m->efr, m->Nim, s->M, s->opts.precision, s->piv,
-                               s->yr, m->d_trace_map, s->duhat, s->du, st, gate));
-        HIP_TRY(launch_newton_update(m->Np, m->Nim, m->Ne, m->d_imp, s->du, u,
-                                     4 * m->Ntp, s->duhat, uhat, st, gate));
+        HIP_TRY(launch_recover_update(m->ops, m->efr, m->Nim, s->M, s->opts.precision,
+                                      s->piv, s->yr, m->d_trace_map, s->duhat, s->du,
+                                      m->Ne, m->d_imp, u, 4 * m->Ntp, uhat, st, gate));
         tend(s, tk, st);
         return queue_checks(gate);
     };

@@ -27,7 +27,6 @@ struct CondShared {
     double Af[NP][16];
     double Ag[NP][16];
     double c[NP];
-    double u[NP][4];
     double Fu[4 * P][16];
     double Fh[4 * P][16];
     int tr[4];
@@ -52,17 +51,17 @@ __device__ void element_linearisation(const CondenseLaunch& a, const RefOps& o,
         const double y_et = 0.25 * ((vy[3] - vy[0]) * (1 - xi) + (vy[2] - vy[1]) * (1 + xi));
         const double J = x_xi * y_et - x_et * y_xi;
         double uu[4];
-        for (int v = 0; v < 4; ++v) {
-            uu[v] = a.u[v * plane + size_t(e) * NP + t];
-            sh.u[t][v] = uu[v];
-        }
+        for (int v = 0; v < 4; ++v) uu[v] = a.u[v * plane + size_t(e) * NP + t];
         phys_dflux_pair(pk, uu, y_et, -x_et, -y_xi, x_xi, sh.Af[t], sh.Ag[t]);
         sh.c[t] = a.aii_dt / J;
     }
     if (t < 4) sh.tr[t] = (a.finfo[size_t(e) * 4 + t].role == ROLE_HFR);
-    __syncthreads();
-    if (t < 4 * P) {
-        const int f = t / P, q = t % P;
+    // the face terms on the second wave, concurrently with the point terms
+    // (the face states are interpolated from u directly)
+    const int tq = t - 64;
+    if (tq >= 0 && tq < 4 * P) {
+        const int f = tq / P, q = tq % P;
+        const double* ue = a.u + size_t(e) * NP;
         double uf[4] = {0, 0, 0, 0};
         for (int l = 0; l < P; ++l) {
             int p2;
@@ -71,12 +70,12 @@ __device__ void element_linearisation(const CondenseLaunch& a, const RefOps& o,
             else if (f == 1) { p2 = q * P + l; wgt = o.lp[l]; }
             else if (f == 2) { p2 = l * P + (P - 1 - q); wgt = o.lp[l]; }
             else { p2 = (P - 1 - q) * P + l; wgt = o.lm[l]; }
-            for (int v = 0; v < 4; ++v) uf[v] += wgt * sh.u[p2][v];
+            for (int v = 0; v < 4; ++v) uf[v] += wgt * ue[v * plane + p2];
         }
         const FaceInfo fi = a.finfo[size_t(e) * 4 + f];
         const double2 S = a.fS[size_t(e) * 4 + f];
-        double* Fu = sh.Fu[t];
-        double* Fh = sh.Fh[t];
+        double* Fu = sh.Fu[tq];
+        double* Fh = sh.Fh[tq];
         for (int z = 0; z < 16; ++z) Fh[z] = 0.0;
         if (fi.role == ROLE_HFR) {
             const int tf = fi.trace >> 1, side = fi.trace & 1;

@@ -307,7 +307,11 @@ fr_status hfr_get_blocks(hfr_solver_t s, double* blocks, void* stream);
  * exchange k (returned in piv, int32 [Nim][n], may be NULL):
  *   T[p_k][j]   = A^-1[k][p_j]          T[p_k][n+b] = -(A^-1 B)[k][b]
  *   T[n+i][j]   = (C A^-1)[i][p_j]      T[n+i][n+b] = (D - C A^-1 B)[i][b]
- * for j < n, b < m, i < m (element-local ordering as in hfr_get_blocks). */
+ * for j < n, b < m, i < m (element-local ordering as in hfr_get_blocks).
+ * After hfr_assemble_condense all four blocks are stored.  The Newton
+ * solver with jacobian_lag = 0 never reuses the factors and stores only the
+ * columns n+b (A^-1 B and the Schur complement): the first n columns then
+ * hold no meaningful values. */
 fr_status hfr_get_factors(hfr_solver_t s, void* factors, int32_t* piv,
                           void* stream);
 /* Block-Jacobi preconditioner of the last linearisation (the trace solve of

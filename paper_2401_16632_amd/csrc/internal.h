@@ -111,6 +111,11 @@ struct CondenseLaunch {
     // optional: the fill returns at entry when *go == 0 (a fill launched
     // before the host has read the Newton convergence test)
     const int* go;
+    // with yr set: keep only what recovery and assembly read (the columns of
+    // B and D, and yr, z); the columns of A already exchanged are skipped,
+    // so A^-1 and C A^-1 are not stored, and the right-hand side is carried
+    // through the sweep as an FP64 column instead of formed afterwards
+    int schur_only;
 };
 // element linearisation and the tableau [A B; C D] (must precede
 // launch_condense, which sweeps the tableau in place)

@@ -394,7 +394,7 @@ __global__ __launch_bounds__(256) void k_tableau_fill(CondenseLaunch a, RefOps o
     }
 }
 
-template <int P, typename T>
+template <int P, typename T, bool SCHUR>
 __global__ __launch_bounds__((64 * SweepShape<P, T>::W))
 __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_sweep(
     CondenseLaunch a, RefOps og) {
@@ -436,6 +436,21 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
             // clamped address: the load stays inside this element's slot
             const T v = G[size_t(min(col, N - 1)) * N + min(row, N - 1)];
             t[s][j / CH][j % CH] = (j < NCW && row < N && col < N) ? v : T(0);
+        }
+    }
+    // Schur-only sweep: the right-hand side [h; 0] rides along as an FP64
+    // column on the last wave (after the exchanges it holds -A^-1 h in the
+    // pivot rows, unscaled like them, and -C A^-1 h in the rows of C)
+    constexpr bool schur = SCHUR;
+    constexpr int RW = W - 1;
+    double rhs[schur ? RPL : 1];
+#pragma unroll
+    for (int s = 0; s < (schur ? RPL : 1); ++s) {
+        const int row = lane + 64 * s;
+        rhs[s] = 0.0;
+        if (schur && w == RW && row < n) {
+            constexpr int NP = P * P;
+            rhs[s] = a.h[size_t(row & 3) * a.nimp * NP + size_t(k) * NP + (row >> 2)];
         }
     }
     // ---- n Jordan exchanges ---------------------------------------------------
@@ -534,21 +549,45 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
             for (int s = 0; s < RPL; ++s) col1[s] = fma(-gs[s], u1, cpre[s]);
             find_pivot(col1, k1, gn, ipn, pn);
         }
-        // rank-1 update of this wave's columns; the pivot row segment comes
-        // from the lane holding row p (uniform lane and slot)
-        T u[NCW];
+        // rank-1 update of this wave's columns, two at a time; the pivot
+        // row segment comes from the lane holding row p (uniform lane and
+        // slot).  In a Schur-only sweep a group whose columns have all been
+        // exchanged already (global index <= kk) is skipped.
+        constexpr int GJ = 2, NGJ = (NCW + GJ - 1) / GJ;
 #pragma unroll
-        for (int j = 0; j < NCW; ++j) {
-            T src = t[0][j / CH][j % CH];
+        for (int gq = 0; gq < NGJ; ++gq) {
+            const int jlast = (GJ * gq + GJ < NCW ? GJ * gq + GJ : NCW) - 1;
+            if (!schur || w + W * jlast > kk) {    // uniform
+                T u[GJ];
 #pragma unroll
-            for (int s0 = 1; s0 < SPN; ++s0) src = (sp == s0) ? t[s0][j / CH][j % CH] : src;
-            u[j] = lane_value(src, lp);
+                for (int jj = 0; jj < GJ; ++jj) {
+                    const int j = GJ * gq + jj;
+                    if (j < NCW) {
+                        T src = t[0][j / CH][j % CH];
+#pragma unroll
+                        for (int s0 = 1; s0 < SPN; ++s0)
+                            src = (sp == s0) ? t[s0][j / CH][j % CH] : src;
+                        u[jj] = lane_value(src, lp);
+                    }
+                }
+#pragma unroll
+                for (int jj = 0; jj < GJ; ++jj) {
+                    const int j = GJ * gq + jj;
+                    if (j < NCW) {
+#pragma unroll
+                        for (int s = 0; s < RPL; ++s)
+                            t[s][j / CH][j % CH] = fma(-gs[s], u[jj], t[s][j / CH][j % CH]);
+                    }
+                }
+            }
         }
+        if constexpr (schur) if (w == RW) {       // uniform
+            double ur = rhs[0];
 #pragma unroll
-        for (int j = 0; j < NCW; ++j) {
+            for (int s0 = 1; s0 < SPN; ++s0) ur = (sp == s0) ? rhs[s0] : ur;
+            ur = lane_value(ur, lp);
 #pragma unroll
-            for (int s = 0; s < RPL; ++s)
-                t[s][j / CH][j % CH] = fma(-gs[s], u[j], t[s][j / CH][j % CH]);
+            for (int s = 0; s < RPL; ++s) rhs[s] = fma(-double(gs[s]), ur, rhs[s]);
         }
         // column k: multipliers for the other rows, -1 in the pivot row
         if (w == ow) {
@@ -572,7 +611,18 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
     // ---- FP64 right-hand side from the registers (as launch_rhs64):
     // yr/z[row] = sum_{j<n} T(sig*t)[row][j] * (-h[p_j]), each wave over its
     // columns of A, the waves' sums added in a fixed order
-    if (a.yr) {
+    if constexpr (schur) {
+        constexpr int m = N - n;
+        if (w == RW) {
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) {
+                const int row = lane + 64 * s;
+                const double v = double(sig[s]) * rhs[s];
+                if (row < n) a.yr[size_t(k) * n + row] = v;
+                else if (row < N) a.z[size_t(k) * m + row - n] = v;
+            }
+        }
+    } else if (a.yr) {
         constexpr int NP = P * P, m = N - n;
         __syncthreads();                           // pl complete
         for (int j = threadIdx.x; j < n; j += blockDim.x) {
@@ -623,8 +673,12 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
 template <int P, typename T>
 static hipError_t launch_sweep(const RefOps& o, const CondenseLaunch& a,
                                hipStream_t st) {
-    hipLaunchKernelGGL((k_condense_sweep<P, T>), dim3(a.nimp),
-                       dim3(64 * SweepShape<P, T>::W), 0, st, a, o);
+    if (a.schur_only && a.yr)
+        hipLaunchKernelGGL((k_condense_sweep<P, T, true>), dim3(a.nimp),
+                           dim3(64 * SweepShape<P, T>::W), 0, st, a, o);
+    else
+        hipLaunchKernelGGL((k_condense_sweep<P, T, false>), dim3(a.nimp),
+                           dim3(64 * SweepShape<P, T>::W), 0, st, a, o);
     return hipGetLastError();
 }
 

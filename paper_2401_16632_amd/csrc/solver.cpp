@@ -340,7 +340,8 @@ fr_status condense_fill(hfr_solver_s* s, const double* u, const double* uhat,
 // already been queued.
 fr_status condense_internal(hfr_solver_s* s, const double* u,
                             const double* uhat, double aii_dt,
-                            hipStream_t st, bool fill_done = false) {
+                            hipStream_t st, bool fill_done = false,
+                            bool schur_only = false) {
     fr_mesh_s* m = s->mesh;
     if (m->Nim == 0) return FR_OK;
     if (!fill_done) {
@@ -351,6 +352,7 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
     int tk = tbegin(s, HFR_T_CONDENSE, st);
     c.yr = s->yr;                       // the sweep also forms the FP64 right-hand side
     c.z = s->zz;
+    c.schur_only = schur_only ? 1 : 0;
     HIP_TRY(launch_condense(m->ops, c, st));
     tend(s, tk, st);
     if (s->nbr == 0) return FR_OK;
@@ -638,8 +640,9 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         const bool relin = lag <= 0 || !s->have_factors ||
                            (it == 0 && (s->stage_calls % lag) == 0);
         if (relin) {
-            if ((e = condense_internal(s, u, uhat, aii_dt, st, spec))) return e;
-            s->have_factors = true;
+            // factors that are never reused need only the Schur part
+            if ((e = condense_internal(s, u, uhat, aii_dt, st, spec, lag <= 0))) return e;
+            s->have_factors = lag > 0;
         } else {
             if ((e = recondense_rhs_internal(s, st))) return e;
         }

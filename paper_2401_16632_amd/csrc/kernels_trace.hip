@@ -87,16 +87,111 @@ __global__ void k_assemble(AssembleLaunch a) {
     }
 }
 
-hipError_t launch_assemble(const AssembleLaunch& a, hipStream_t st) {
-    const int bs = 4 * a.P;
-    long work = std::max(long(a.nblocks) * bs * bs, long(a.ntf) * bs);
+// The same with the block order P fixed at compile time: a thread moves
+// four consecutive rows of one block column (one point of a face, its four
+// variables), which are contiguous both in the swept tableau and in the
+// column-major block, as 16-byte accesses.
+template <typename T> struct Vec4;
+template <> struct Vec4<float> {
+    typedef float4 type;
+    __device__ static void get(const float* p, double (&v)[4]) {
+        const float4 x = *reinterpret_cast<const float4*>(p);
+        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    }
+};
+template <> struct Vec4<double> {
+    __device__ static void get(const double* p, double (&v)[4]) {
+        const double2 x = reinterpret_cast<const double2*>(p)[0];
+        const double2 y = reinterpret_cast<const double2*>(p)[1];
+        v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
+    }
+};
+
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_assemble4(AssembleLaunch a) {
+    constexpr int bs = 4 * P, bb = bs * bs, per = bs * P;   // 4-row chunks per block
+    const size_t N = size_t(a.n + a.m);
+    const T* M = reinterpret_cast<const T*>(a.M);
+    const long total = long(a.nblocks) * per;
+    for (long idx = blockIdx.x * long(blockDim.x) + threadIdx.x; idx < total;
+         idx += long(gridDim.x) * blockDim.x) {
+        const int blk = int(idx / per);
+        const int rem = int(idx - long(blk) * per);
+        const int b = rem / P, qa = rem - b * P;   // column, point of the rows
+        const int qb = b >> 2, wb = b & 3;
+        double val[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int* ct = a.blk_contrib + (size_t(blk) * 2 + c) * 3;
+            const int imp = ct[0];
+            if (imp < 0) continue;
+            const int lr = ct[1] >> 1, sr = ct[1] & 1, lc = ct[2] >> 1, sc = ct[2] & 1;
+            const int qea = sr ? P - 1 - qa : qa;
+            const int qeb = sc ? P - 1 - qb : qb;
+            const size_t row = a.n + (lr * P + qea) * 4;
+            const size_t col = a.n + (lc * P + qeb) * 4 + wb;
+            double v[4];
+            Vec4<T>::get(M + size_t(imp) * N * N + col * N + row, v);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) val[r] += v[r];
+        }
+        const size_t o = size_t(blk) * bb + size_t(b) * bs + 4 * qa;
+        if (a.L64) {
+            reinterpret_cast<double2*>(a.L64 + o)[0] = make_double2(val[0], val[1]);
+            reinterpret_cast<double2*>(a.L64 + o)[1] = make_double2(val[2], val[3]);
+        }
+        if (a.L32)
+            *reinterpret_cast<float4*>(a.L32 + o) =
+                make_float4(float(val[0]), float(val[1]), float(val[2]), float(val[3]));
+    }
+    const long tt = long(a.ntf) * bs;
+    for (long idx = blockIdx.x * long(blockDim.x) + threadIdx.x; idx < tt;
+         idx += long(gridDim.x) * blockDim.x) {
+        const int F = int(idx / bs), aa = int(idx - long(F) * bs);
+        const int q = aa >> 2, v = aa & 3;
+        double zs = 0.0;
+        for (int s = 0; s < 2; ++s) {
+            const int imp = a.tside[(size_t(F) * 2 + s) * 2];
+            if (imp < 0) continue;
+            const int lf = a.tside[(size_t(F) * 2 + s) * 2 + 1];
+            const int qe = s ? P - 1 - q : q;
+            zs += a.z[size_t(imp) * a.m + (lf * P + qe) * 4 + v];
+        }
+        a.t[idx] = -a.g[idx] - zs;
+    }
+}
+
+template <typename T, int P>
+static void launch_assemble4(const AssembleLaunch& a, hipStream_t st) {
+    constexpr int bs = 4 * P;
+    const long work = std::max(long(a.nblocks) * bs * P, long(a.ntf) * bs);
     int grid = blocks_for(work);
     if (grid > 65536) grid = 65536;
-    if (a.precision == HFR_PREC_FP64)
-        hipLaunchKernelGGL(k_assemble<double>, dim3(grid), dim3(kThreads), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_assemble<float>, dim3(grid), dim3(kThreads), 0, st, a);
+    hipLaunchKernelGGL((k_assemble4<T, P>), dim3(grid), dim3(kThreads), 0, st, a);
+}
+
+template <typename T>
+static hipError_t launch_assemble_t(const AssembleLaunch& a, hipStream_t st) {
+    switch (a.P) {
+        case 2: launch_assemble4<T, 2>(a, st); break;
+        case 3: launch_assemble4<T, 3>(a, st); break;
+        case 4: launch_assemble4<T, 4>(a, st); break;
+        case 5: launch_assemble4<T, 5>(a, st); break;
+        case 6: launch_assemble4<T, 6>(a, st); break;
+        default: {
+            const int bs = 4 * a.P;
+            long work = std::max(long(a.nblocks) * bs * bs, long(a.ntf) * bs);
+            int grid = blocks_for(work);
+            if (grid > 65536) grid = 65536;
+            hipLaunchKernelGGL(k_assemble<T>, dim3(grid), dim3(kThreads), 0, st, a);
+        }
+    }
     return hipGetLastError();
+}
+
+hipError_t launch_assemble(const AssembleLaunch& a, hipStream_t st) {
+    if (a.precision == HFR_PREC_FP64) return launch_assemble_t<double>(a, st);
+    return launch_assemble_t<float>(a, st);
 }
 
 // ---- block-Jacobi: invert the diagonal block of every trace face -------

@@ -221,6 +221,9 @@ typedef struct {
                                  factors, re-condensing only the right-hand
                                  side (the paper updates its Jacobian every
                                  100 steps, Sec. 5.3)                        */
+    int32_t gmres_cgs_passes; /* classical Gram-Schmidt passes per Arnoldi
+                                 step: 1 (also when 0) or 2 (each new
+                                 vector orthogonalised twice)                */
 } hfr_opts;
 
 typedef struct {

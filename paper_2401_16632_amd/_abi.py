@@ -47,7 +47,7 @@ class HfrOpts(Structure):
                 ("gmres_restart", c_int32), ("gmres_max_iters", c_int32),
                 ("gmres_rtol", c_double), ("newton_max_iters", c_int32),
                 ("newton_tol", c_double), ("keep_blocks", c_int32),
-                ("jacobian_lag", c_int32)]
+                ("jacobian_lag", c_int32), ("gmres_cgs_passes", c_int32)]
 
 
 class HfrSolveStats(Structure):

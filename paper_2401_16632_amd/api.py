@@ -194,7 +194,8 @@ class Solver:
 
     def __init__(self, mesh, precision="fp64", precond="fp64", restart=30,
                  max_iters=600, rtol=1e-10, newton_max_iters=25,
-                 newton_tol=1e-13, keep_blocks=False, jacobian_lag=0):
+                 newton_tol=1e-13, keep_blocks=False, jacobian_lag=0,
+                 cgs_passes=1):
         lib = load_library()
         self.mesh = mesh
         o = _abi.HfrOpts()
@@ -207,6 +208,7 @@ class Solver:
         o.newton_tol = newton_tol
         o.keep_blocks = 1 if keep_blocks else 0
         o.jacobian_lag = int(jacobian_lag)
+        o.gmres_cgs_passes = int(cgs_passes)
         self.opts = o
         ws = ctypes.c_size_t()
         h = ctypes.c_void_p()

@@ -21,6 +21,7 @@ struct GmresState {
 struct GmresArgs {
     int ntf, bs, fpb, nblk, restart, pc;
     int fpbA, nblkA;         // decomposition of the product kernel
+    int passes;              // classical Gram-Schmidt passes per step (1 or 2)
     double rtol;
     size_t ldv;
     const int* rowptr;

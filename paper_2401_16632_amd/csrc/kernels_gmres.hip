@@ -302,6 +302,16 @@ __global__ __launch_bounds__(kThr) void k_arnoldi_b(GmresArgs a, int j,
             x[q] = v;
         }
     }
+    if (a.passes == 1) {
+        // one pass: the norm partials of w here, no second projection
+        if (blockIdx.x == 0)
+            for (int i = threadIdx.x; i < k; i += blockDim.x) gs->h2[i] = 0.0;
+        double nn = 0.0;
+#pragma unroll
+        for (int q = 0; q < kRPT; ++q) nn += x[q] * x[q];
+        block_partials(1, [&](int) { return nn; }, red, a.part + blockIdx.x, gridDim.x);
+        return;
+    }
     block_partials(k, [&](int i) {
         double s = 0.0;
 #pragma unroll
@@ -640,7 +650,8 @@ hipError_t launch_arnoldi_product(const GmresArgs& a, int j, int fin_prev,
 hipError_t launch_arnoldi_orth(const GmresArgs& a, int j, double* wnxt,
                                hipStream_t st) {
     hipLaunchKernelGGL(k_arnoldi_b, dim3(a.nblk), dim3(kThr), 0, st, a, j, wnxt);
-    hipLaunchKernelGGL(k_arnoldi_c, dim3(a.nblk), dim3(kThr), 0, st, a, j, wnxt);
+    if (a.passes != 1)
+        hipLaunchKernelGGL(k_arnoldi_c, dim3(a.nblk), dim3(kThr), 0, st, a, j, wnxt);
     return hipGetLastError();
 }
 

@@ -451,6 +451,7 @@ GmresArgs gmres_args(hfr_solver_s* s) {
     a.nblk = s->gblk;
     a.fpbA = s->fpbA;
     a.nblkA = s->gblkA;
+    a.passes = s->opts.gmres_cgs_passes == 2 ? 2 : 1;
     a.restart = s->restart;
     a.pc = s->opts.precond;
     a.rtol = s->opts.gmres_rtol;
@@ -694,7 +695,7 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
     if (o->gmres_restart < 1 || o->gmres_restart > kGmresMaxK - 1)
         return fail(FR_E_INVALID, "gmres_restart must be in 1..64");
     if (o->newton_max_iters < 0 || !(o->newton_tol > 0.0) || !(o->gmres_rtol > 0.0) ||
-        o->jacobian_lag < 0)
+        o->jacobian_lag < 0 || o->gmres_cgs_passes < 0 || o->gmres_cgs_passes > 2)
         return fail(FR_E_INVALID, "bad tolerance or iteration cap");
     auto s = new hfr_solver_s();
     s->mesh = mesh;

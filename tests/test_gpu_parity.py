@@ -181,8 +181,11 @@ def _cfl_dt(pr, lam=6.0, rings=3, n_theta=24):
     return 2.0 * cut / (lam * (2 * pr.p + 1))
 
 
-@pytest.mark.parametrize("name", ["c1_p2", "pert_p3", "cyl_p3"])
-def test_condense_solve_recover(name):
+@pytest.mark.parametrize("name,passes", [("c1_p2", 1), ("pert_p3", 1), ("cyl_p3", 1),
+                                         ("c1_p2", 2), ("cyl_p3", 2)])
+def test_condense_solve_recover(name, passes):
+    """Condensed system against the oracle's, the trace solve to 1e-12 with
+    one and with two Gram-Schmidt passes per Arnoldi step, and recovery."""
     pr, u = _build(name)
     om, hm = pr.om, pr.hm
     uhat, ustar = _stage_inputs(pr, u)
@@ -191,7 +194,7 @@ def test_condense_solve_recover(name):
     # operating range); 0.05 on the vortex meshes
     a = 0.05 if name != "cyl_p3" else 0.3 * _cfl_dt(pr)
     sysd = onw.condense(om, pr.ph, u, uhat, ustar, a)
-    s = hp.Solver(hm, rtol=1e-12, max_iters=3000, restart=60)
+    s = hp.Solver(hm, rtol=1e-12, max_iters=3000, restart=60, cgs_passes=passes)
     s.assemble_condense(dev(soa(u)), dev(uhat), dev(soa(ustar)), a)
     N = 4 * hm.Ntp
     t = torch.zeros(N, dtype=torch.float64, device="cuda")

@@ -5,13 +5,16 @@
 // linearisation: Lt = L Dinv (Dinv = inverse of each trace face's diagonal
 // block, Lt stored row-major per block so that a row is one contiguous
 // vector load), so an Arnoldi step is one block-sparse product.  One Arnoldi
-// step is three kernels and no host synchronisation:
-//   A: finish column j-1 (norm from C's partials, Givens rotation,
-//      convergence test; every workgroup forms the same values, workgroup 0
-//      stores them), v_j = w / |w| (own rows), y = Lt v_j, partial dots V_i . y
-//   B: reduce A's partials, w = y - sum h1_i V_i, partial dots V_i . w
-//                                                   (Gram-Schmidt, pass 1)
-//   C: reduce B's partials, w -= sum h2_i V_i, partial |w|^2   (pass 2)
+// step is two kernels (three with a second Gram-Schmidt pass) and no host
+// synchronisation:
+//   A: finish column j-1 (norm from the last pass's partials, Givens
+//      rotation, convergence test; every workgroup forms the same values,
+//      workgroup 0 stores them), v_j = w / |w| (own rows), y = Lt v_j,
+//      partial dots V_i . y
+//   B: reduce A's partials, w = y - sum h1_i V_i, then partial |w|^2, or
+//      with two passes partial dots V_i . w        (classical Gram-Schmidt)
+//   C: (two passes only) reduce B's partials, w -= sum h2_i V_i, partial
+//      |w|^2
 // The last step of a chunk of steps is closed by a one-workgroup kernel D
 // that finishes its column, so the host can read the state.  Partial sums
 // are reduced in a fixed order by the consuming kernel, so results are

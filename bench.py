@@ -167,7 +167,7 @@ def roofline(form, mesh, timers, precision, workload="c2", phases=None):
         avg = cms / max(1, ccnt) * 1e-3
         pk = PEAK["fp32_tflops"] if precision == "fp32" else PEAK["fp64_tflops"]
         ach = fl / avg / 1e12
-        traffic = (measured_traffic(workload, f"k_condense_sweep<{mesh.P}, float>")
+        traffic = (measured_traffic(workload, f"k_condense_sweep<{mesh.P}, float")
                    if precision == "fp32" else None)
         return dict(kernel="condense", bound="alu", achieved=ach, peak=pk,
                     unit="TFLOP/s", frac=ach / pk, traffic=traffic,

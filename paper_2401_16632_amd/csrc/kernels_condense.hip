@@ -657,11 +657,13 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
         }
     }
 
-    // ---- store column-major, pivot rows scaled -------------------------------
+    // ---- store column-major, pivot rows scaled (a Schur-only sweep stores
+    // the columns of B and D only)
 #pragma unroll
     for (int j = 0; j < NCW; ++j) {
         const int col = w + W * j;
         if (col >= N) break;
+        if (schur && col < n) continue;           // uniform
 #pragma unroll
         for (int s = 0; s < RPL; ++s) {
             const int row = lane + 64 * s;

@@ -229,11 +229,14 @@ hipError_t launch_absmax(int N, const double* x, double* partial, int nblk,
                          double* out, hipStream_t st);
 // Newton test: out[0] = max |x|, out[1] = max |y| (out may be host memory
 // mapped for the device), *go = 1 when the gate (if any) is open and either
-// exceeds tol (NaN included), else 0; flags[0..1] copied to flags_out (if
-// set); then seq is written to seq_out (if set) behind a system-scope fence,
-// so a host that sees it sees the rest; partial needs 2048 doubles
+// exceeds the tolerance (NaN included), else 0; the tolerance is tol, or
+// tol * max(1, *tol_scale) with tol_scale (device memory) set, and is
+// written to out[2]; flags[0..1] copied to flags_out (if set); then seq is
+// written to seq_out (if set) behind a system-scope fence, so a host that
+// sees it sees the rest; partial needs 2048 doubles
 hipError_t launch_newton_norms(int Nx, const double* x, int Ny, const double* y,
-                               double* partial, double tol, double* out, int* go,
+                               double* partial, double tol, const double* tol_scale,
+                               double* out, int* go,
                                const int* gate, const int* flags, int* flags_out,
                                long long* seq_out, long long seq, hipStream_t st);
 hipError_t launch_trace_gather_g(int ntp, int P, const int* tpside,
@@ -243,7 +246,8 @@ hipError_t launch_trace_gather_g(int ntp, int P, const int* tpside,
 // launches: the gather also takes the partial maxima
 hipError_t launch_gather_g_norms(int ntp, const int* tpside, const double* gk, double* g,
                                  int Nx, const double* x, double* partial, double tol,
-                                 double* out, int* go, const int* gate, const int* flags,
+                                 const double* tol_scale, double* out, int* go,
+                                 const int* gate, const int* flags,
                                  int* flags_out, long long* seq_out, long long seq,
                                  hipStream_t st);
 

@@ -577,8 +577,10 @@ __global__ void k_absmax2_partial(int Nx, const double* x, int nbx, int Ny,
 }
 
 // both maxima -> out[0], out[1] (host-visible), *go = 0 iff both <= tol or
-// the gate is closed; the two failure flags are copied to flags_out
+// the gate is closed; the two failure flags are copied to flags_out.  With
+// tol_scale set the test uses tol * max(1, *tol_scale), written to out[2].
 __global__ void k_absmax2_final(int nbx, int nby, const double* partial, double tol,
+                                const double* tol_scale,
                                 double* out, int* go, const int* gate,
                                 const int* flags, int* flags_out,
                                 long long* seq_out, long long seq) {
@@ -605,8 +607,10 @@ __global__ void k_absmax2_final(int nbx, int nby, const double* partial, double 
         __syncthreads();
     }
     if (threadIdx.x == 0) {
+        if (tol_scale) tol *= fmax(1.0, *tol_scale);
         out[0] = red[0][0];
         out[1] = red[1][0];
+        out[2] = tol;
         const bool open = !gate || *gate != 0;
         *go = (open && !(red[0][0] <= tol && red[1][0] <= tol)) ? 1 : 0;
         if (flags_out) {
@@ -621,7 +625,8 @@ __global__ void k_absmax2_final(int nbx, int nby, const double* partial, double 
 }
 
 hipError_t launch_newton_norms(int Nx, const double* x, int Ny, const double* y,
-                               double* partial, double tol, double* out, int* go,
+                               double* partial, double tol, const double* tol_scale,
+                               double* out, int* go,
                                const int* gate, const int* flags, int* flags_out,
                                long long* seq_out, long long seq, hipStream_t st) {
     const int nbx = std::min(1024, std::max(1, (Nx + kThreads - 1) / kThreads));
@@ -629,7 +634,7 @@ hipError_t launch_newton_norms(int Nx, const double* x, int Ny, const double* y,
     hipLaunchKernelGGL(k_absmax2_partial, dim3(nbx + nby), dim3(kThreads), 0, st, Nx, x,
                        nbx, Ny, y, partial);
     hipLaunchKernelGGL(k_absmax2_final, dim3(1), dim3(256), 0, st, nbx, nby, partial, tol,
-                       out, go, gate, flags, flags_out, seq_out, seq);
+                       tol_scale, out, go, gate, flags, flags_out, seq_out, seq);
     return hipGetLastError();
 }
 
@@ -826,7 +831,8 @@ __global__ void k_gather_g_absmax(int ntp, const int* tpside, const double* gk,
 
 hipError_t launch_gather_g_norms(int ntp, const int* tpside, const double* gk, double* g,
                                  int Nx, const double* x, double* partial, double tol,
-                                 double* out, int* go, const int* gate, const int* flags,
+                                 const double* tol_scale, double* out, int* go,
+                                 const int* gate, const int* flags,
                                  int* flags_out, long long* seq_out, long long seq,
                                  hipStream_t st) {
     const int nbx = std::min(1024, std::max(1, (Nx + kThreads - 1) / kThreads));
@@ -834,7 +840,7 @@ hipError_t launch_gather_g_norms(int ntp, const int* tpside, const double* gk, d
     hipLaunchKernelGGL(k_gather_g_absmax, dim3(nbx + nby), dim3(kThreads), 0, st, ntp,
                        tpside, gk, g, Nx, x, nbx, partial);
     hipLaunchKernelGGL(k_absmax2_final, dim3(1), dim3(256), 0, st, nbx, nby, partial, tol,
-                       out, go, gate, flags, flags_out, seq_out, seq);
+                       tol_scale, out, go, gate, flags, flags_out, seq_out, seq);
     return hipGetLastError();
 }
 

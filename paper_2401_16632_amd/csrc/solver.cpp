@@ -86,10 +86,11 @@ struct hfr_solver_s {
     double* dots = nullptr;  // small device vector
     double* coef = nullptr;
     int* go = nullptr;       // 1 while the Newton residual is above tolerance
+    double* dscale = nullptr;  // max |u*| of the stage solve (scales its tolerance)
     double* hpin = nullptr;  // pinned, device-mapped host buffer (kPinDoubles):
-                             // [0..1] Newton norms, [kPinGmres..] GMRES state
+                             // [0..1] Newton norms, [2] their tolerance,
+                             // [kPinGmres..] GMRES state
     double* dpin = nullptr;  // the same buffer's device address
-    hipEvent_t rb_ev = nullptr;  // marks the readback on the solver's stream
     long long seq_norms = 0;     // last sequence number queued for the norms
     long long seq_gmres = 0;     // ... and for the GMRES state
     size_t ws_bytes = 0;
@@ -161,9 +162,7 @@ fr_status dalloc(T** p, size_t count, size_t& total) {
 void free_solver(hfr_solver_s* s) {
     tflush(s);
     if (s->hpin) (void)hipHostFree(s->hpin);
-    if (s->rb_ev) (void)hipEventDestroy(s->rb_ev);
     s->hpin = nullptr;
-    s->rb_ev = nullptr;
     for (auto& p : s->pool) {
         (void)hipEventDestroy(p.first);
         (void)hipEventDestroy(p.second);
@@ -175,7 +174,7 @@ void free_solver(hfr_solver_s* s) {
                     s->flags, s->V, s->z, s->r, s->scratch, s->dots, s->coef,
                     s->Lt64, s->Lt32, s->W, s->gs, s->part, s->part2,
                     s->counters, s->piv, s->yr, s->zz, s->part3,
-                    s->efr_cptr, s->efr_contrib, s->go};
+                    s->efr_cptr, s->efr_contrib, s->go, s->dscale};
     for (void* p : ptrs) (void)hipFree(p);
 }
 
@@ -208,19 +207,6 @@ fr_status wait_seq(hfr_solver_s* s, const void* slot, long long target, hipStrea
         }
         __builtin_ia32_pause();
     }
-}
-
-// Event-marked readback (kernels without a sequence number).
-fr_status readback_mark(hfr_solver_s* s, hipStream_t st) {
-    HIP_TRY(hipEventRecord(s->rb_ev, st));
-    return FR_OK;
-}
-
-fr_status readback_wait(hfr_solver_s* s) {
-    hipError_t e = hipEventSynchronize(s->rb_ev);
-    if (e != hipSuccess)
-        return fail(FR_E_DEVICE, std::string("device error: ") + hipGetErrorString(e));
-    return FR_OK;
 }
 
 fr_status sync_check(hipStream_t st) {
@@ -560,27 +546,19 @@ fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
     return FR_OK;
 }
 
-fr_status absmax_host(hfr_solver_s* s, int N, const double* x, double* out,
-                      hipStream_t st) {
-    const int nb = std::min(1024, std::max(1, (N + 255) / 256));
-    HIP_TRY(launch_absmax(N, x, s->scratch, nb, s->dpin + 2, st));
-    fr_status e = readback_mark(s, st);
-    if (e || (e = readback_wait(s))) return e;
-    *out = s->hpin[2];
-    return FR_OK;
-}
-
 fr_status newton(hfr_solver_s* s, double* u, double* uhat,
                  const double* ustar, double aii_dt, hfr_newton_stats* stats,
                  hipStream_t st) {
     fr_mesh_s* m = s->mesh;
     hfr_newton_stats loc{};
     const int nu = 4 * m->Nim * m->Np;
-    double scale = 0.0;
-    fr_status e = absmax_host(s, nu, ustar, &scale, st);
-    if (e) return e;
-    scale = std::max(1.0, scale);
-    const double tol = s->opts.newton_tol * scale;
+    // the tolerance newton_tol * max(1, |u*|) is formed on the device by the
+    // norms kernel and published with the norms (no readback here)
+    HIP_TRY(launch_absmax(nu, ustar, s->scratch, std::min(1024, std::max(1, (nu + 255) / 256)),
+                          s->dscale, st));
+    const double rtol = s->opts.newton_tol;
+    double tol = 0.0;
+    fr_status e;
     const int lag = s->opts.jacobian_lag;
     const bool spec = lag <= 0 && m->Nim > 0;
     int* flags_pub = reinterpret_cast<int*>(s->dpin + kPinFlags);
@@ -595,12 +573,14 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
                                          m->efr);
         if (e2) return e2;
         if (m->efr)
-            HIP_TRY(launch_newton_norms(nu, s->h, 4 * m->Ntp, s->g, s->scratch, tol,
-                                        s->dpin, s->go, gate, s->flags, flags_pub, seq_pub,
+            HIP_TRY(launch_newton_norms(nu, s->h, 4 * m->Ntp, s->g, s->scratch, rtol,
+                                        s->dscale, s->dpin, s->go, gate, s->flags, flags_pub,
+                                        seq_pub,
                                         ++s->seq_norms, st));
         else
             HIP_TRY(launch_gather_g_norms(m->Ntp, m->d_tpside, s->gk, s->g, nu, s->h,
-                                          s->scratch, tol, s->dpin, s->go, gate, s->flags,
+                                          s->scratch, rtol, s->dscale, s->dpin, s->go, gate,
+                                          s->flags,
                                           flags_pub, seq_pub, ++s->seq_norms, st));
         if (spec && (e2 = condense_fill(s, u, uhat, aii_dt, s->go, st))) return e2;
         return FR_OK;
@@ -623,6 +603,7 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         queued = false;
         if ((e = wait_seq(s, s->hpin + kPinNormSeq, s->seq_norms, st))) return e;
         const double hmax = s->hpin[0], gmax = s->hpin[1];
+        tol = s->hpin[2];
         const double res = std::max(hmax, gmax);
         if (s->verbose)
             fprintf(stderr, "[hfr] newton it %d |h| %.3e |g| %.3e tol %.3e\n", it,
@@ -819,6 +800,7 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
         (e = dalloc(&s->dots, 256, tot)) ||
         (e = dalloc(&s->coef, 128, tot)) ||
         (e = dalloc(&s->go, 1, tot)) ||
+        (e = dalloc(&s->dscale, 1, tot)) ||
         (e = (hipHostMalloc(reinterpret_cast<void**>(&s->hpin), kPinDoubles * sizeof(double),
                             hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
                       hipHostGetDevicePointer(reinterpret_cast<void**>(&s->dpin), s->hpin, 0) ==
@@ -826,10 +808,7 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
                   ? FR_OK
                   : fail(FR_E_NOMEM, "pinned readback buffer: hipHostMalloc or "
                                      "hipHostGetDevicePointer failed"))) ||
-        (e = (std::memset(s->hpin, 0, kPinDoubles * sizeof(double)), FR_OK)) ||
-        (e = (hipEventCreateWithFlags(&s->rb_ev, hipEventDisableTiming) == hipSuccess
-                  ? FR_OK
-                  : fail(FR_E_DEVICE, "hipEventCreateWithFlags failed")))) {
+        (e = (std::memset(s->hpin, 0, kPinDoubles * sizeof(double)), FR_OK))) {
         s->M = Mraw;
         free_solver(s);
         delete s;

@@ -30,6 +30,14 @@ struct RefOps {
     double gi[kMaxP * kMaxP], gj[kMaxP * kMaxP];
 };
 
+// Copy of the operator table (a kernel argument) into LDS by every thread
+// of the workgroup, one 4-byte word each; the caller synchronises.
+__device__ __forceinline__ void copy_ref_ops(RefOps& dst, const RefOps& src) {
+    const int* s = reinterpret_cast<const int*>(&src);
+    int* d = reinterpret_cast<int*>(&dst);
+    for (int i = threadIdx.x; i < int(sizeof(RefOps) / 4); i += blockDim.x) d[i] = s[i];
+}
+
 // Role of the common flux on one element face.
 enum FaceRole : int {
     ROLE_RUSANOV = 0,   // standard FR flux against the neighbour

@@ -366,7 +366,7 @@ __global__ __launch_bounds__(256) void k_tableau_fill(CondenseLaunch a, RefOps o
     __shared__ RefOps o;
     if (a.go && *a.go == 0) return;            // uniform over the grid
     const int k = blockIdx.x;
-    if (threadIdx.x == 0) o = og;
+    copy_ref_ops(o, og);
     __syncthreads();
     element_linearisation<P>(a, o, k, sh);
     T* G = reinterpret_cast<T*>(a.M) + size_t(k) * N * N;
@@ -377,12 +377,15 @@ __global__ __launch_bounds__(256) void k_tableau_fill(CondenseLaunch a, RefOps o
         block_entries<P>(br, bc, o, sh, E);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            T col[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) col[v] = T(E[v][c]);
+            // four rows of one column, 16-byte aligned (N is a multiple of 4)
             T* dst = G + size_t(4 * bc + c) * N + 4 * br;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) dst[v] = col[v];
+            if constexpr (sizeof(T) == 4) {
+                *reinterpret_cast<float4*>(dst) =
+                    make_float4(float(E[0][c]), float(E[1][c]), float(E[2][c]), float(E[3][c]));
+            } else {
+                reinterpret_cast<double2*>(dst)[0] = make_double2(E[0][c], E[1][c]);
+                reinterpret_cast<double2*>(dst)[1] = make_double2(E[2][c], E[3][c]);
+            }
         }
         if (bcopy) {
 #pragma unroll

@@ -159,7 +159,7 @@ __global__ void k_efr_trace_average(RefOps og, int nnodes, int Ne, const int* in
                                     const int* inc, const int* imp_list,
                                     const double* u, double* uhat) {
     __shared__ RefOps o;
-    if (threadIdx.x == 0) o = og;
+    copy_ref_ops(o, og);
     __syncthreads();
     const int P = o.P, Np = P * P;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;

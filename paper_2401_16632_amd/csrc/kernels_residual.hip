@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void k_residual(ResidualLaunch a, RefOps og) {
     constexpr int NFP = 4 * P;
     __shared__ RefOps o;
     if (a.gate && *a.gate == 0) return;           // uniform over the grid
-    if (threadIdx.x == 0) o = og;
+    copy_ref_ops(o, og);
     __syncthreads();
     __shared__ double s_u[EPB][NP][4];
     __shared__ double s_f[EPB][NP][4];

@@ -231,6 +231,30 @@ __global__ __launch_bounds__(256) void k_arnoldi_a(GmresArgs a, int j, int fin_p
     __shared__ double red[kGmresMaxK * 4];
     __shared__ double sacc[8][4][64];
     __shared__ GivensStage gv;
+    // the inputs of column j-1's Givens step (its projections, rotations and
+    // norm partials) are loaded before the product so that their latency
+    // overlaps the product's loads; they are staged in LDS after it
+    const int jc = j - 1;
+    double ph = 0.0, pcs = 0.0, psn = 0.0, pgj = 0.0, ptg = 0.0;
+    double pn[4] = {0.0, 0.0, 0.0, 0.0};
+    if (!fin_prev) {
+        const int t = threadIdx.x;
+        if (t <= jc) {
+            ph = gs->h1[t] + gs->h2[t];
+            if (t < jc) {
+                pcs = gs->cs[t];
+                psn = gs->sn[t];
+            }
+        }
+        if (t == 0) {
+            pgj = gs->g[jc];
+            ptg = gs->target;
+        }
+        if (part == 0) {                           // wave 0: the norm partials
+            int b = lr, q = 0;
+            for (; b < a.nblk; b += 64, q = (q + 1) & 3) pn[q] += a.part[b];
+        }
+    }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int r = r0 + 64 * q + lr;
@@ -246,8 +270,23 @@ __global__ __launch_bounds__(256) void k_arnoldi_a(GmresArgs a, int j, int fin_p
         inv = gs->inv_norm;
         __syncthreads();
     } else {
-        stage_givens(a, j - 1, gv);
-        reduce_partials(1, a.nblk, a.part, red);   // ends with a barrier
+        const int t = threadIdx.x;
+        if (t <= jc) {
+            gv.hc[t] = ph;
+            if (t < jc) {
+                gv.cs[t] = pcs;
+                gv.sn[t] = psn;
+            }
+        }
+        if (t == 0) {
+            gv.gj = pgj;
+            gv.target = ptg;
+        }
+        if (part == 0) {
+            const double sn = wave_sum((pn[0] + pn[1]) + (pn[2] + pn[3]));
+            if (lr == 0) red[0] = sn;
+        }
+        __syncthreads();
         if (threadIdx.x == 0) givens_column(a, j - 1, sqrt(red[0]), blockIdx.x == 0, gv);
         __syncthreads();
         if (gv.dec[0] != 0.0) return;             // same decision in every workgroup

@@ -41,54 +41,11 @@ __device__ __forceinline__ float bf2f(uint16_t h) {
 
 }  // namespace
 
-// ---- assembly --------------------------------------------------------
-template <typename T>
-__global__ void k_assemble(AssembleLaunch a) {
-    const int bs = 4 * a.P;
-    const size_t N = size_t(a.n + a.m);      // swept tableau, column-major
-    const int bb = bs * bs;
-    const long total = long(a.nblocks) * bb;
-    const T* M = reinterpret_cast<const T*>(a.M);
-    for (long idx = blockIdx.x * long(blockDim.x) + threadIdx.x; idx < total;
-         idx += long(gridDim.x) * blockDim.x) {
-        const int blk = int(idx) / bb;          // total < 2^31
-        const int rem = int(idx) - blk * bb;
-        const int b = rem / bs, aa = rem % bs;
-        const int qa = aa >> 2, va = aa & 3, qb = b >> 2, wb = b & 3;
-        double val = 0.0;
-        for (int c = 0; c < 2; ++c) {
-            const int* ct = a.blk_contrib + (size_t(blk) * 2 + c) * 3;
-            const int imp = ct[0];
-            if (imp < 0) continue;
-            const int lr = ct[1] >> 1, sr = ct[1] & 1, lc = ct[2] >> 1, sc = ct[2] & 1;
-            const int qea = sr ? a.P - 1 - qa : qa;
-            const int qeb = sc ? a.P - 1 - qb : qb;
-            const size_t row = a.n + (lr * a.P + qea) * 4 + va;
-            const size_t col = a.n + (lc * a.P + qeb) * 4 + wb;
-            val += double(M[size_t(imp) * N * N + col * N + row]);
-        }
-        if (a.L64) a.L64[idx] = val;
-        if (a.L32) a.L32[idx] = float(val);
-    }
-    const long tt = long(a.ntf) * bs;
-    for (long idx = blockIdx.x * long(blockDim.x) + threadIdx.x; idx < tt;
-         idx += long(gridDim.x) * blockDim.x) {
-        const int F = int(idx) / bs, aa = int(idx) - F * bs;
-        const int q = aa >> 2, v = aa & 3;
-        double zs = 0.0;
-        for (int s = 0; s < 2; ++s) {
-            const int imp = a.tside[(size_t(F) * 2 + s) * 2];
-            if (imp < 0) continue;
-            const int lf = a.tside[(size_t(F) * 2 + s) * 2 + 1];
-            const int qe = s ? a.P - 1 - q : q;
-            zs += a.z[size_t(imp) * a.m + (lf * a.P + qe) * 4 + v];
-        }
-        a.t[idx] = -a.g[idx] - zs;
-    }
-}
-
-// The same with the block order P fixed at compile time: a thread moves
-// four consecutive rows of one block column (one point of a face, its four
+// ---- assembly (eq:assembly): every block of L is the sum of at most two
+// element Schur sub-blocks, t = -g - sum of the sides' C A^-1 r; a gather
+// in a fixed order, no atomics.
+// The block order P is fixed at compile time; a thread moves four
+// consecutive rows of one block column (one point of a face, its four
 // variables), which are contiguous both in the swept tableau and in the
 // column-major block, as 16-byte accesses.
 template <typename T> struct Vec4;
@@ -178,13 +135,7 @@ static hipError_t launch_assemble_t(const AssembleLaunch& a, hipStream_t st) {
         case 4: launch_assemble4<T, 4>(a, st); break;
         case 5: launch_assemble4<T, 5>(a, st); break;
         case 6: launch_assemble4<T, 6>(a, st); break;
-        default: {
-            const int bs = 4 * a.P;
-            long work = std::max(long(a.nblocks) * bs * bs, long(a.ntf) * bs);
-            int grid = blocks_for(work);
-            if (grid > 65536) grid = 65536;
-            hipLaunchKernelGGL(k_assemble<T>, dim3(grid), dim3(kThreads), 0, st, a);
-        }
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

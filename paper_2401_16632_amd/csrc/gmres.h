@@ -10,6 +10,7 @@ constexpr int kGmresMaxK = 65;   // restart <= 64
 struct GmresState {
     // finished: the solve is over (converged, or ended at the iteration cap)
     int done, converged, jlast, iters, cycles, finished;
+    int est_conv;            // the cycle ended with the residual estimate on target
     double inv_norm, beta, bnorm, target;
     double h1[kGmresMaxK], h2[kGmresMaxK];
     double cs[kGmresMaxK], sn[kGmresMaxK];
@@ -22,6 +23,9 @@ struct GmresArgs {
     int ntf, bs, fpb, nblk, restart, pc;
     int fpbA, nblkA;         // decomposition of the product kernel
     int passes;              // classical Gram-Schmidt passes per step (1 or 2)
+    int verify;              // 0: a cycle whose residual estimate reached the
+                             // target ends the solve without the FP64 true
+                             // residual (the Newton loop checks its residuals)
     double rtol;
     size_t ldv;
     const int* rowptr;

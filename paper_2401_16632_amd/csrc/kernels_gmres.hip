@@ -145,6 +145,7 @@ __device__ void givens_column(const GmresArgs& a, int jc, double hn, bool write,
         gs->jlast = jc;
         gs->iters += 1;
         gs->inv_norm = inv;
+        gs->est_conv = (res <= g.target) ? 1 : 0;
         if (done) gs->done = 1;
     }
     g.dec[0] = done ? 1.0 : 0.0;
@@ -461,6 +462,7 @@ __global__ __launch_bounds__(256) void k_gmres_residual(GmresArgs a,
                                                         double* x,
                                                         double* w, int first, int cond) {
     if (cond && !a.gs->done) return;
+    if (cond && !a.verify && a.gs->est_conv) return;  // the estimate is trusted
     __shared__ double red[4];
     __shared__ double sacc[8][4][64];
     const int bs = a.bs;
@@ -503,7 +505,17 @@ __global__ __launch_bounds__(kThr) void k_gmres_restart(GmresArgs a, int first, 
     __shared__ double fin[kGmresMaxK];
     const bool act = !cond || gs->done;            // uniform
     if (!act && threadIdx.x == 0) gs->finished = 0;
-    if (act) {
+    if (act && cond && !a.verify && gs->est_conv) {
+        // the cycle reached the target by its residual estimate: the solve
+        // ends with that estimate as its residual (no true residual formed)
+        if (threadIdx.x == 0) {
+            gs->cycles += 1;
+            gs->beta = fabs(gs->g[gs->jlast + 1]);
+            gs->converged = 1;
+            gs->done = 1;
+            gs->finished = 1;
+        }
+    } else if (act) {
         reduce_partials(1, a.nblkA, a.part3, fin);
         if (threadIdx.x == 0) {
             const double beta = sqrt(fin[0]);
@@ -520,6 +532,7 @@ __global__ __launch_bounds__(kThr) void k_gmres_restart(GmresArgs a, int first, 
             for (int i = 1; i <= a.restart; ++i) gs->g[i] = 0.0;
             gs->inv_norm = beta > 0.0 ? 1.0 / beta : 0.0;
             gs->jlast = -1;
+            gs->est_conv = 0;
             const bool conv = !(beta > gs->target);
             gs->converged = conv ? 1 : 0;
             gs->done = (conv || !(beta == beta)) ? 1 : 0;

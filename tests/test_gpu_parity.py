@@ -222,10 +222,10 @@ def test_condense_solve_recover(name, passes):
 
 
 def _run_steps(pr, u0, dt, nsteps, precision="fp64", precond="fp64",
-               tab="HIMEX2C", tol=1e-13):
+               tab="HIMEX2C", tol=1e-13, cgs_passes=1):
     om, hm = pr.om, pr.hm
     s = hp.Solver(hm, precision=precision, precond=precond, rtol=1e-12,
-                  newton_tol=tol, max_iters=3000)
+                  newton_tol=tol, max_iters=3000, cgs_passes=cgs_passes)
     stp = hp.ImexStepper(hm, s, tab)
     ud = dev(soa(u0))
     uo = u0.copy()
@@ -247,6 +247,22 @@ def test_imex_steps_fp64_c1():
     u0 = fi.isentropic_vortex(pr.om.x, pr.om.y)
     errs, its = _run_steps(pr, u0, 0.01, 10)
     assert max(errs) <= 1e-11, errs
+
+
+def test_imex_steps_fp64_cylinder_two_passes():
+    """The Newton path with two Gram-Schmidt passes per Arnoldi step matches
+    the oracle as the default single pass does."""
+    pr, u = _build("cyl_p3")
+    errs, _ = _run_steps(pr, u, _cfl_dt(pr), 2, cgs_passes=2)
+    assert max(errs) <= 1e-11, errs
+
+
+def test_solver_rejects_bad_options():
+    pr, _ = _build("c1_p1")
+    for kw in (dict(cgs_passes=3), dict(cgs_passes=-1), dict(jacobian_lag=-1),
+               dict(restart=0)):
+        with pytest.raises(hp.HfrError):
+            hp.Solver(pr.hm, **kw)
 
 
 def test_imex_steps_fp64_cylinder_ars():

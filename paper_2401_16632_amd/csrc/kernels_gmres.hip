@@ -606,17 +606,29 @@ template <typename TL, typename TD>
 __global__ __launch_bounds__(256) void k_precondition_matrix16(int nblocks, const int* col,
                                                                const TL* L, const TD* Dinv,
                                                                TL* Lt) {
-    const int lane = threadIdx.x & 63;
-    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int p = blockIdx.x * 4 + wv;
     if (p >= nblocks) return;                      // whole wave
     const size_t lb = size_t(p) * 256, db = size_t(col[p]) * 256;
     const int i = lane & 15, g = lane >> 4;
+    // the column face's Dinv block, read with consecutive lanes on
+    // consecutive entries and staged in LDS with a row stride of 17 (the
+    // operand reads below then hit 16 different banks)
+    __shared__ TL dsh[4][16 * 17];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = lane + 64 * q, c = e >> 4, r = e & 15;
+        dsh[wv][c * 17 + r] = TL(load_pc(Dinv, db + e));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if constexpr (sizeof(TL) == 4) {
         mf4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             const float a = L[lb + 64 * kk + lane];
-            const float b = float(load_pc(Dinv, db + i * 16 + 4 * kk + g));
+            const float b = dsh[wv][i * 17 + 4 * kk + g];
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
         }
 #pragma unroll
@@ -626,7 +638,7 @@ __global__ __launch_bounds__(256) void k_precondition_matrix16(int nblocks, cons
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             const double a = L[lb + 64 * kk + lane];
-            const double b = load_pc(Dinv, db + i * 16 + 4 * kk + g);
+            const double b = dsh[wv][i * 17 + 4 * kk + g];
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
         }
 #pragma unroll

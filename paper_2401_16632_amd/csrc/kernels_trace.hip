@@ -214,38 +214,59 @@ __device__ __forceinline__ unsigned long long row16_max_key(unsigned long long x
     return x;
 }
 
-template <int BS>
+__device__ __forceinline__ unsigned row16_max_u32(unsigned x) {
+    x = max(x, key32_dpp<0xb1, 0xf>(x));        // quad_perm [1,0,3,2]
+    x = max(x, key32_dpp<0x4e, 0xf>(x));        // quad_perm [2,3,0,1]
+    x = max(x, key32_dpp<0x141, 0xf>(x));       // row_half_mirror
+    x = max(x, key32_dpp<0x140, 0xf>(x));       // row_mirror: every lane of the row
+    return x;
+}
+
+// C is the arithmetic of the exchanges: FP64, or FP32 for an inverse that
+// is stored in FP32 or BF16 (32-bit pivot keys, hardware reciprocal)
+template <int BS, typename C>
 __global__ __launch_bounds__(256) void k_block_inverse16(int ntf, const int* diag_blk,
                                                          const double* L64,
                                                          const float* L32, int pc,
                                                          void* out, int* fail) {
     static_assert(BS <= 16, "four blocks per wave need BS <= 16");
-    __shared__ double prow[4][4][BS];
+    __shared__ C prow[4][4][BS];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int grp = lane >> 4, r = lane & 15;
     const int F = (blockIdx.x * 4 + wv) * 4 + grp;
     const bool valid = F < ntf;
     const size_t blk = valid ? size_t(diag_blk[F]) * BS * BS : 0;
-    double t[BS];
+    C t[BS];
 #pragma unroll
     for (int c = 0; c < BS; ++c) {
         const size_t i = blk + size_t(c) * BS + min(r, BS - 1);   // in bounds
-        double v = c == r ? 1.0 : 0.0;
-        if (valid) v = L64 ? L64[i] : double(L32[i]);
-        t[c] = r < BS ? v : 0.0;
+        C v = c == r ? C(1) : C(0);
+        if (valid) v = L64 ? C(L64[i]) : C(L32[i]);
+        t[c] = r < BS ? v : C(0);
     }
-    double sig = 1.0;
+    C sig = C(1);
     bool used = r >= BS, bad = false;
     int pos = 0;
     int pj[BS];
 #pragma unroll
     for (int k = 0; k < BS; ++k) {
-        const unsigned long long key =
-            row16_max_key(used ? 0ull : pivot_key(float(fabs(t[k])), r));
-        int p = int(0xffffffffu - unsigned(key));
-        if ((key >> 32) == 0) {                     // no nonzero candidate
-            bad = true;
-            p = 0;
+        int p;
+        if constexpr (sizeof(C) == 8) {
+            const unsigned long long key =
+                row16_max_key(used ? 0ull : pivot_key(float(fabs(t[k])), r));
+            p = int(0xffffffffu - unsigned(key));
+            if ((key >> 32) == 0) {                 // no nonzero candidate
+                bad = true;
+                p = 0;
+            }
+        } else {
+            const unsigned key =
+                row16_max_u32(used ? 0u : pivot_key32(float(fabs(t[k])), r));
+            p = 255 - int(key & 0xffu);
+            if (key == 0) {                         // no nonzero candidate
+                bad = true;
+                p = 0;
+            }
         }
         pj[k] = p;
         if (r == p) {
@@ -255,17 +276,19 @@ __global__ __launch_bounds__(256) void k_block_inverse16(int ntf, const int* dia
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        double u[BS];
+        C u[BS];
 #pragma unroll
         for (int j = 0; j < BS; ++j) u[j] = prow[wv][grp][j];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const double ipv = bad ? 0.0 : 1.0 / u[k];
-        const double g = (r == p) ? 0.0 : t[k] * ipv;
+        C ipv;
+        if constexpr (sizeof(C) == 8) ipv = bad ? 0.0 : 1.0 / u[k];
+        else ipv = bad ? 0.f : __builtin_amdgcn_rcpf(u[k]);
+        const C g = (r == p) ? C(0) : t[k] * ipv;
 #pragma unroll
         for (int j = 0; j < BS; ++j) t[j] = fma(-g, u[j], t[j]);
-        t[k] = (r == p) ? -1.0 : g;
+        t[k] = (r == p) ? C(-1) : g;
         if (r == p) { used = true; sig = -ipv; pos = k; }
     }
     if (bad && valid && r == 0) *fail = 1;
@@ -274,9 +297,9 @@ __global__ __launch_bounds__(256) void k_block_inverse16(int ntf, const int* dia
     const size_t o = size_t(F) * BS * BS + pos;
 #pragma unroll
     for (int j = 0; j < BS; ++j) {
-        const double v = sig * t[j];
+        const C v = sig * t[j];
         const size_t i = o + size_t(pj[j]) * BS;
-        if (pc == HFR_PC_FP64) reinterpret_cast<double*>(out)[i] = v;
+        if (pc == HFR_PC_FP64) reinterpret_cast<double*>(out)[i] = double(v);
         else if (pc == HFR_PC_FP32) reinterpret_cast<float*>(out)[i] = float(v);
         else reinterpret_cast<uint16_t*>(out)[i] = f2bf(float(v));
     }
@@ -289,15 +312,23 @@ hipError_t launch_block_inverse_impl(int ntf, int bs, const int* diag_blk,
     if (ntf == 0) return hipSuccess;
     const dim3 grid((ntf + 3) / 4), blk(256);
     const dim3 grid16((ntf + 15) / 16);            // four blocks per wave
+    const bool f64 = pc == HFR_PC_FP64;
+#define HFR_INV16(B)                                                                          \
+    if (f64) hipLaunchKernelGGL((k_block_inverse16<B, double>), grid16, blk, 0, st, ntf,     \
+                                diag_blk, L64, L32, pc, out, fail);                          \
+    else hipLaunchKernelGGL((k_block_inverse16<B, float>), grid16, blk, 0, st, ntf,          \
+                            diag_blk, L64, L32, pc, out, fail);                              \
+    break;
     switch (bs) {
-        case 4: hipLaunchKernelGGL(k_block_inverse16<4>, grid16, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
-        case 8: hipLaunchKernelGGL(k_block_inverse16<8>, grid16, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
-        case 12: hipLaunchKernelGGL(k_block_inverse16<12>, grid16, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
-        case 16: hipLaunchKernelGGL(k_block_inverse16<16>, grid16, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
+        case 4: HFR_INV16(4)
+        case 8: HFR_INV16(8)
+        case 12: HFR_INV16(12)
+        case 16: HFR_INV16(16)
         case 20: hipLaunchKernelGGL(k_block_inverse<20>, grid, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
         case 24: hipLaunchKernelGGL(k_block_inverse<24>, grid, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
         default: return hipErrorInvalidValue;
     }
+#undef HFR_INV16
     return hipGetLastError();
 }
 

@@ -406,7 +406,8 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
     __shared__ T gbuf[2][RPL * 64];
     __shared__ T ibuf[2];
     __shared__ int pbuf[2];
-    // right-hand side epilogue: pivot rows, permuted -h, per-wave row sums
+    // right-hand side epilogue of the full sweep: pivot rows, permuted -h,
+    // per-wave row sums
     constexpr int NRW = W < n ? W : n;          // waves owning columns of A
     __shared__ short pl[n];
     __shared__ double sr[n];
@@ -521,7 +522,7 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
             if (threadIdx.x == 0) *a.pivot_fail = 1;
             return;                                // uniform over the workgroup
         }
-        if (threadIdx.x == 0) pl[kk] = short(p);
+        if (!schur && threadIdx.x == 0) pl[kk] = short(p);
         const int sp = p >> 6, lp = p & 63;
 #pragma unroll
         for (int s = 0; s < RPL; ++s)
@@ -611,9 +612,11 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
         }
     }
 
-    // ---- FP64 right-hand side from the registers (as launch_rhs64):
-    // yr/z[row] = sum_{j<n} T(sig*t)[row][j] * (-h[p_j]), each wave over its
-    // columns of A, the waves' sums added in a fixed order
+    // ---- FP64 right-hand side (as launch_rhs64): the Schur-only sweep holds
+    // it in its extra column (scaled here like the pivot rows); the full
+    // sweep forms yr/z[row] = sum_{j<n} T(sig*t)[row][j] * (-h[p_j]) from the
+    // registers, each wave over its columns of A, the waves' sums added in a
+    // fixed order
     if constexpr (schur) {
         constexpr int m = N - n;
         if (w == RW) {

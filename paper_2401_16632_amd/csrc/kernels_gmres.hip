@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256) void k_arnoldi_a(GmresArgs a, int j, int fin_p
         pe0 = a.rowptr[F0 + 1];
     }
     if (gs->done) return;
-    __shared__ double red[kGmresMaxK * 4];
+    __shared__ double red[1];                     // |w| of column j-1
     __shared__ double sacc[8][4][64];
     __shared__ GivensStage gv;
     // the inputs of column j-1's Givens step (its projections, rotations and
@@ -293,31 +293,47 @@ __global__ __launch_bounds__(256) void k_arnoldi_a(GmresArgs a, int j, int fin_p
         if (gv.dec[0] != 0.0) return;             // same decision in every workgroup
         inv = gv.dec[1];
     }
-    double yv[8];
+    __shared__ double ysh[8][64];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        yv[q] = 0.0;
         const int r = r0 + 64 * q + lr;
         if (part == 0 && r < r1) {
             const double y = (sacc[q][0][lr] + sacc[q][1][lr] + sacc[q][2][lr] +
                               sacc[q][3][lr]) * inv;
             a.V[size_t(j) * a.ldv + r] = wcur[r] * inv;
             wnxt[r] = y;
-            yv[q] = y;
+            ysh[q][lr] = y;
         }
     }
-    // projections V_i . y over this block's rows (group 0 holds y)
-    block_partials(j + 1, [&](int i) {
-        double s = 0.0;
-        if (part == 0) {
+    __syncthreads();
+    // projections V_i . y over this block's rows: wave w forms i = w, w + 4,
+    // ..., two values per pass so that two loads are in flight, each value
+    // a single wave's sum (rows in order, then the wave sum), written to the
+    // value-major partials directly
+    double* out = a.part3 + blockIdx.x;
+    const int ldp = gridDim.x;
+    for (int i = part; i <= j; i += 8) {
+        const bool two = i + 4 <= j;                  // uniform
+        const double* v0 = a.V + size_t(i) * a.ldv;
+        const double* v1 = a.V + size_t(two ? i + 4 : i) * a.ldv;
+        double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int r = r0 + 64 * q + lr;
-                if (r < r1) s += a.V[size_t(i) * a.ldv + r] * yv[q];
+        for (int q = 0; q < 8; ++q) {
+            const int r = r0 + 64 * q + lr;
+            if (r0 + 64 * q >= r1) break;             // uniform
+            if (r < r1) {
+                const double y = ysh[q][lr];
+                s0 += v0[r] * y;
+                s1 += v1[r] * y;
             }
         }
-        return s;
-    }, red, a.part3 + blockIdx.x, gridDim.x);
+        s0 = wsum(s0);
+        s1 = wsum(s1);
+        if (lr == 0) {
+            out[size_t(i) * ldp] = s0;
+            if (two) out[size_t(i + 4) * ldp] = s1;
+        }
+    }
 }
 
 // ---- B: first orthogonalisation, second projection ------------------------

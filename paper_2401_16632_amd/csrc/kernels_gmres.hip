@@ -157,11 +157,48 @@ __device__ void givens_column(const GmresArgs& a, int jc, double hn, bool write,
 // of a row, the four shares are added in LDS.  Row-major blocks (Lt) are
 // read as contiguous vectors; column-major blocks (L) column by column
 // (consecutive lanes read consecutive rows of a column).
-template <bool ROW_MAJOR, typename T>
+// row aa of row-major block p times x's segment c, added to acc: all loads
+// issued before the first FMA (block size fixed at compile time)
+template <int BS, typename T>
+__device__ __forceinline__ double row_block(const T* M, const double* x, int c, int p,
+                                            int aa, double acc) {
+    const double2* x2 = reinterpret_cast<const double2*>(x + size_t(c) * BS);
+    const T* row = M + (size_t(p) * BS + aa) * BS;
+    double2 xv[BS / 2];
+#pragma unroll
+    for (int b = 0; b < BS / 2; ++b) xv[b] = x2[b];
+    if constexpr (sizeof(T) == 8) {
+        double2 l[BS / 2];
+#pragma unroll
+        for (int b = 0; b < BS / 2; ++b) l[b] = reinterpret_cast<const double2*>(row)[b];
+#pragma unroll
+        for (int b = 0; b < BS / 2; ++b) {
+            acc = fma(l[b].x, xv[b].x, acc);
+            acc = fma(l[b].y, xv[b].y, acc);
+        }
+    } else {
+        float4 l[BS / 4];
+#pragma unroll
+        for (int b = 0; b < BS / 4; ++b) l[b] = reinterpret_cast<const float4*>(row)[b];
+#pragma unroll
+        for (int b = 0; b < BS / 4; ++b) {
+            acc = fma(double(l[b].x), xv[2 * b].x, acc);
+            acc = fma(double(l[b].y), xv[2 * b].y, acc);
+            acc = fma(double(l[b].z), xv[2 * b + 1].x, acc);
+            acc = fma(double(l[b].w), xv[2 * b + 1].y, acc);
+        }
+    }
+    return acc;
+}
+
+// BS > 0: row-major blocks of that size, two blocks of the row per pass with
+// all their loads in flight together (the same additions in the same order
+// as one block per pass); BS = 0: block size from a.bs
+template <bool ROW_MAJOR, typename T, int BS = 0>
 __device__ __forceinline__ double row_share(const GmresArgs& a, const T* M,
                                             const double* x, int r, int pb = -1,
                                             int p1 = -1) {
-    const int bs = a.bs;
+    const int bs = BS > 0 ? BS : a.bs;
     const int F = r / bs, aa = r - F * bs;
     const int part = threadIdx.x >> 6;
     if (pb < 0) {                                  // row pointers not preloaded
@@ -169,6 +206,18 @@ __device__ __forceinline__ double row_share(const GmresArgs& a, const T* M,
         p1 = a.rowptr[F + 1];
     }
     double acc = 0.0;
+    if constexpr (BS > 0) {
+        static_assert(ROW_MAJOR && BS % 4 == 0, "fixed-size path: row-major blocks");
+        for (int p = pb + part; p < p1; p += 8) {
+            const bool two = p + 4 < p1;
+            const int p2 = two ? p + 4 : p;        // the second block, or p again
+            const int c1 = a.col[p], c2 = a.col[p2];
+            const double a1 = row_block<BS>(M, x, c1, p, aa, acc);
+            const double a2 = row_block<BS>(M, x, c2, p2, aa, a1);
+            acc = two ? a2 : a1;
+        }
+        return acc;
+    }
     for (int p = pb + part; p < p1; p += 4) {
         const double2* x2 = reinterpret_cast<const double2*>(x + size_t(a.col[p]) * bs);
         if (ROW_MAJOR) {
@@ -213,6 +262,8 @@ __device__ __forceinline__ double row_share(const GmresArgs& a, const T* M,
 // fin_prev: column j-1 was finished by D or by the restart (first step of a
 // chunk); otherwise this kernel finishes it.  The product does not depend on
 // the scale, so it is formed first.
+// TL: the precision of Lt; BS: the face block size (0: a.bs at run time)
+template <typename TL, int BS>
 __global__ __launch_bounds__(256) void k_arnoldi_a(GmresArgs a, int j, int fin_prev,
                                                    const double* wcur,
                                                    double* wnxt) {
@@ -261,9 +312,12 @@ __global__ __launch_bounds__(256) void k_arnoldi_a(GmresArgs a, int j, int fin_p
         const int r = r0 + 64 * q + lr;
         if (r0 + 64 * q >= r1) break;             // uniform
         double acc = 0.0;
-        if (r < r1)
-            acc = a.Lt64 ? row_share<true>(a, a.Lt64, wcur, r, q == 0 ? pb0 : -1, pe0)
-                         : row_share<true>(a, a.Lt32, wcur, r, q == 0 ? pb0 : -1, pe0);
+        if (r < r1) {
+            const TL* Lt;
+            if constexpr (sizeof(TL) == 8) Lt = a.Lt64;
+            else Lt = a.Lt32;
+            acc = row_share<true, TL, BS>(a, Lt, wcur, r, q == 0 ? pb0 : -1, pe0);
+        }
         sacc[q][part][lr] = acc;
     }
     double inv;
@@ -725,8 +779,19 @@ hipError_t launch_gmres_restart(const GmresArgs& a, double* x,
 
 hipError_t launch_arnoldi_product(const GmresArgs& a, int j, int fin_prev,
                                   const double* wcur, double* wnxt, hipStream_t st) {
-    hipLaunchKernelGGL(k_arnoldi_a, dim3(a.nblkA), dim3(256), 0, st, a, j, fin_prev,
-                       wcur, wnxt);
+    const bool f64 = a.Lt64 != nullptr;
+#define HFR_AA(TL, B)                                                                   \
+    hipLaunchKernelGGL((k_arnoldi_a<TL, B>), dim3(a.nblkA), dim3(256), 0, st, a, j,      \
+                       fin_prev, wcur, wnxt)
+    switch (a.bs) {
+        case 8: if (f64) HFR_AA(double, 8); else HFR_AA(float, 8); break;
+        case 12: if (f64) HFR_AA(double, 12); else HFR_AA(float, 12); break;
+        case 16: if (f64) HFR_AA(double, 16); else HFR_AA(float, 16); break;
+        case 20: if (f64) HFR_AA(double, 20); else HFR_AA(float, 20); break;
+        case 24: if (f64) HFR_AA(double, 24); else HFR_AA(float, 24); break;
+        default: if (f64) HFR_AA(double, 0); else HFR_AA(float, 0); break;
+    }
+#undef HFR_AA
     return hipGetLastError();
 }
 

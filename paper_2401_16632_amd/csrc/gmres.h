@@ -30,6 +30,8 @@ struct GmresArgs {
     size_t ldv;
     const int* rowptr;
     const int* col;
+    const int* ell;          // padded face rows: kmax {block, column} pairs per
+    int kmax;                // row, {-1, -1} past its end (product kernel)
     const double* L64;       // original matrix (true residual)
     const float* L32;
     const double* Lt64;      // preconditioned matrix L Dinv

@@ -191,14 +191,46 @@ __device__ __forceinline__ double row_block(const T* M, const double* x, int c, 
     return acc;
 }
 
-// BS > 0: row-major blocks of that size, two blocks of the row per pass with
-// all their loads in flight together (the same additions in the same order
-// as one block per pass); BS = 0: block size from a.bs
-template <bool ROW_MAJOR, typename T, int BS = 0>
+// The same share for row-major blocks of size BS through the padded table
+// a.ell of the face rows ({block index, block column} of a row's k-th block
+// at F * kmax + k, {-1, -1} past its end), so the block and column indices
+// are one load away instead of behind the row pointers.  Group `part` takes
+// blocks part, part + 4, ... two per pass, all their loads in flight
+// together; the additions are those of one block per pass, in the same
+// order.  e1, e2: the row's entries part and part + 4, loaded by the caller.
+template <typename T, int BS>
+__device__ __forceinline__ double row_share_ell(const GmresArgs& a, const T* M,
+                                                const double* x, int r, int2 e1, int2 e2) {
+    const int F = r / BS, aa = r - F * BS;
+    const int2* ell = reinterpret_cast<const int2*>(a.ell) + size_t(F) * a.kmax;
+    double acc = 0.0;
+    for (int k = threadIdx.x >> 6; e1.x >= 0;) {
+        const bool two = e2.x >= 0;
+        const int p2 = two ? e2.x : e1.x, c2 = two ? e2.y : e1.y;
+        const double a1 = row_block<BS>(M, x, e1.y, e1.x, aa, acc);
+        const double a2 = row_block<BS>(M, x, c2, p2, aa, a1);
+        acc = two ? a2 : a1;
+        k += 8;
+        if (!two || k >= a.kmax) break;
+        e1 = ell[k];
+        e2 = k + 4 < a.kmax ? ell[k + 4] : make_int2(-1, -1);
+    }
+    return acc;
+}
+
+// entries part and part + 4 of face F's row in the padded table
+__device__ __forceinline__ void ell_pair(const GmresArgs& a, int F, int2& e1, int2& e2) {
+    const int part = threadIdx.x >> 6;
+    const int2* ell = reinterpret_cast<const int2*>(a.ell) + size_t(F) * a.kmax;
+    e1 = part < a.kmax ? ell[part] : make_int2(-1, -1);
+    e2 = part + 4 < a.kmax ? ell[part + 4] : make_int2(-1, -1);
+}
+
+template <bool ROW_MAJOR, typename T>
 __device__ __forceinline__ double row_share(const GmresArgs& a, const T* M,
                                             const double* x, int r, int pb = -1,
                                             int p1 = -1) {
-    const int bs = BS > 0 ? BS : a.bs;
+    const int bs = a.bs;
     const int F = r / bs, aa = r - F * bs;
     const int part = threadIdx.x >> 6;
     if (pb < 0) {                                  // row pointers not preloaded
@@ -206,18 +238,6 @@ __device__ __forceinline__ double row_share(const GmresArgs& a, const T* M,
         p1 = a.rowptr[F + 1];
     }
     double acc = 0.0;
-    if constexpr (BS > 0) {
-        static_assert(ROW_MAJOR && BS % 4 == 0, "fixed-size path: row-major blocks");
-        for (int p = pb + part; p < p1; p += 8) {
-            const bool two = p + 4 < p1;
-            const int p2 = two ? p + 4 : p;        // the second block, or p again
-            const int c1 = a.col[p], c2 = a.col[p2];
-            const double a1 = row_block<BS>(M, x, c1, p, aa, acc);
-            const double a2 = row_block<BS>(M, x, c2, p2, aa, a1);
-            acc = two ? a2 : a1;
-        }
-        return acc;
-    }
     for (int p = pb + part; p < p1; p += 4) {
         const double2* x2 = reinterpret_cast<const double2*>(x + size_t(a.col[p]) * bs);
         if (ROW_MAJOR) {
@@ -268,16 +288,22 @@ __global__ __launch_bounds__(256) void k_arnoldi_a(GmresArgs a, int j, int fin_p
                                                    const double* wcur,
                                                    double* wnxt) {
     GmresState* gs = a.gs;
-    const int bs = a.bs;
+    const int bs = BS > 0 ? BS : a.bs;
     const int f0 = blockIdx.x * a.fpbA, f1 = min(a.ntf, f0 + a.fpbA);
     const int r0 = f0 * bs, r1 = f1 * bs;
     const int part = threadIdx.x >> 6, lr = threadIdx.x & 63;
-    // the first pass's row pointers are loaded together with the flag
+    // the first pass's table entries (or row pointers) are loaded together
+    // with the flag
     int pb0 = 0, pe0 = 0;
+    int2 e1 = make_int2(-1, -1), e2 = make_int2(-1, -1);
     if (r0 + lr < r1) {
         const int F0 = (r0 + lr) / bs;
-        pb0 = a.rowptr[F0];
-        pe0 = a.rowptr[F0 + 1];
+        if constexpr (BS > 0) {
+            ell_pair(a, F0, e1, e2);
+        } else {
+            pb0 = a.rowptr[F0];
+            pe0 = a.rowptr[F0 + 1];
+        }
     }
     if (gs->done) return;
     __shared__ double red[1];                     // |w| of column j-1
@@ -316,7 +342,12 @@ __global__ __launch_bounds__(256) void k_arnoldi_a(GmresArgs a, int j, int fin_p
             const TL* Lt;
             if constexpr (sizeof(TL) == 8) Lt = a.Lt64;
             else Lt = a.Lt32;
-            acc = row_share<true, TL, BS>(a, Lt, wcur, r, q == 0 ? pb0 : -1, pe0);
+            if constexpr (BS > 0) {
+                if (q > 0) ell_pair(a, r / BS, e1, e2);
+                acc = row_share_ell<TL, BS>(a, Lt, wcur, r, e1, e2);
+            } else {
+                acc = row_share<true>(a, Lt, wcur, r, q == 0 ? pb0 : -1, pe0);
+            }
         }
         sacc[q][part][lr] = acc;
     }

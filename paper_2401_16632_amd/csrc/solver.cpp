@@ -53,6 +53,8 @@ struct hfr_solver_s {
     double* duhat = nullptr; // [N]
     int* rowptr = nullptr;
     int* col = nullptr;
+    int* ell = nullptr;      // rows padded to kmax {block, column} pairs
+    int kmax = 0;
     int* contrib = nullptr;
     int* tside = nullptr;
     int* efr_cptr = nullptr;     // node-block contribution lists (EFR)
@@ -169,7 +171,7 @@ void free_solver(hfr_solver_s* s) {
     }
     s->pool.clear();
     void* ptrs[] = {s->M, s->blocks_copy, s->h, s->gk, s->g, s->Rtmp,
-                    s->ustar, s->du, s->duhat, s->rowptr, s->col, s->contrib,
+                    s->ustar, s->du, s->duhat, s->rowptr, s->col, s->ell, s->contrib,
                     s->tside, s->diag_blk, s->L64, s->L32, s->t, s->Dinv,
                     s->flags, s->V, s->z, s->r, s->scratch, s->dots, s->coef,
                     s->Lt64, s->Lt32, s->W, s->gs, s->part, s->part2,
@@ -445,6 +447,8 @@ GmresArgs gmres_args(hfr_solver_s* s) {
     a.ldv = size_t(s->N);
     a.rowptr = s->rowptr;
     a.col = s->col;
+    a.ell = s->ell;
+    a.kmax = s->kmax;
     a.L64 = s->L64;
     a.L32 = s->L64 ? nullptr : s->L32;
     a.Lt64 = s->Lt64;
@@ -756,6 +760,15 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
         rowptr[F + 1] = int(col.size());
     }
     s->nblocks = int(col.size());
+    // the same structure with every row padded to the longest one
+    for (int a = 0; a < s->nbr; ++a) s->kmax = std::max(s->kmax, rowptr[a + 1] - rowptr[a]);
+    std::vector<int> ell(2 * size_t(s->nbr) * std::max(1, s->kmax), -1);
+    for (int a = 0; a < s->nbr; ++a)
+        for (int p = rowptr[a]; p < rowptr[a + 1]; ++p) {
+            const size_t i = size_t(a) * s->kmax + (p - rowptr[a]);
+            ell[2 * i] = p;
+            ell[2 * i + 1] = col[p];
+        }
     size_t& tot = s->ws_bytes;
     const size_t scal = o->precision == HFR_PREC_FP64 ? 8 : 4;
     const size_t nimp = size_t(m->Nim), np4 = 4 * size_t(m->Np);
@@ -774,6 +787,7 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
         (e = dalloc(&s->duhat, size_t(s->N), tot)) ||
         (e = dalloc(&s->rowptr, rowptr.size(), tot)) ||
         (e = dalloc(&s->col, col.size(), tot)) ||
+        (e = dalloc(&s->ell, ell.size(), tot)) ||
         (e = dalloc(&s->contrib, contrib.size(), tot)) ||
         (e = dalloc(&s->tside, tside.size(), tot)) ||
         (e = dalloc(&s->efr_cptr, m->efr ? ecptr.size() : 0, tot)) ||
@@ -837,6 +851,7 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
                          : hipMemcpy(d, h.data(), 4 * h.size(), hipMemcpyHostToDevice);
     };
     if (up(s->rowptr, rowptr) != hipSuccess || up(s->col, col) != hipSuccess ||
+        up(s->ell, ell) != hipSuccess ||
         up(s->contrib, contrib) != hipSuccess || up(s->tside, tside) != hipSuccess ||
         up(s->diag_blk, diag) != hipSuccess ||
         (m->efr && up(s->efr_cptr, ecptr) != hipSuccess) ||

@@ -815,6 +815,7 @@ hipError_t launch_arnoldi_product(const GmresArgs& a, int j, int fin_prev,
     hipLaunchKernelGGL((k_arnoldi_a<TL, B>), dim3(a.nblkA), dim3(256), 0, st, a, j,      \
                        fin_prev, wcur, wnxt)
     switch (a.bs) {
+        case 4: if (f64) HFR_AA(double, 4); else HFR_AA(float, 4); break;
         case 8: if (f64) HFR_AA(double, 8); else HFR_AA(float, 8); break;
         case 12: if (f64) HFR_AA(double, 12); else HFR_AA(float, 12); break;
         case 16: if (f64) HFR_AA(double, 16); else HFR_AA(float, 16); break;

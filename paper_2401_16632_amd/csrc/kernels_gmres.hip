@@ -56,22 +56,28 @@ __device__ void block_partials(int k, F f, double* red, double* out, int stride)
 }
 
 // fixed-order sum over blocks of partial[i * nb + b] for i < k -> out[i]
-// (LDS); every block computes the same values.  Four independent
-// accumulators per lane keep several loads in flight.
+// (LDS); every block computes the same values.  A lane's loads of a pass
+// are all issued before the first addition, so one pass costs one memory
+// round trip.
 __device__ void reduce_partials(int k, int nb, const double* partial, double* out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
     for (int i = wave; i < k; i += nw) {
         const double* p = partial + size_t(i) * nb;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int b = lane;
-        for (; b + 192 < nb; b += 256) {
-            s0 += p[b];
-            s1 += p[b + 64];
-            s2 += p[b + 128];
-            s3 += p[b + 192];
+        // sixteen loads per lane in flight (up to 1024 partials per pass)
+        for (int b = lane; b < nb; b += 1024) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = b + 64 * u < nb ? p[b + 64 * u] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; u += 4) {
+                s0 += v[u];
+                s1 += v[u + 1];
+                s2 += v[u + 2];
+                s3 += v[u + 3];
+            }
         }
-        for (; b < nb; b += 64) s0 += p[b];
         const double s = wsum((s0 + s1) + (s2 + s3));
         if (lane == 0) out[i] = s;
     }
@@ -425,23 +431,46 @@ __global__ __launch_bounds__(256) void k_arnoldi_a(GmresArgs a, int j, int fin_p
 __global__ __launch_bounds__(kThr) void k_arnoldi_b(GmresArgs a, int j,
                                                     double* w) {
     GmresState* gs = a.gs;
+    const int k = j + 1;
+    int r0, r1;
+    block_rows(a, r0, r1);
+    // the first row's w and up to NPF basis entries are loaded before the
+    // flag and the reduction of the projections, which they do not need
+    constexpr int NPF = 8;
+    const int rf = r0 + threadIdx.x;
+    double wf = 0.0, vf[NPF];
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) vf[i] = 0.0;
+    if (rf < r1) {
+        wf = w[rf];
+#pragma unroll
+        for (int i = 0; i < NPF; ++i)
+            if (i < k) vf[i] = a.V[size_t(i) * a.ldv + rf];
+    }
     if (gs->done) return;
     __shared__ double red[kGmresMaxK * (kThr / 64)];
     __shared__ double h[kGmresMaxK];
-    const int k = j + 1;
     reduce_partials(k, a.nblkA, a.part3, h);
     if (blockIdx.x == 0)
         for (int i = threadIdx.x; i < k; i += blockDim.x) gs->h1[i] = h[i];
-    int r0, r1;
-    block_rows(a, r0, r1);
     double x[kRPT];
 #pragma unroll
     for (int q = 0; q < kRPT; ++q) {
         const int r = r0 + threadIdx.x + kThr * q;
         x[q] = 0.0;
         if (r < r1) {
-            double v = w[r];
-            for (int i = 0; i < k; ++i) v -= h[i] * a.V[size_t(i) * a.ldv + r];
+            double v;
+            int i = 0;
+            if (q == 0) {
+                v = wf;
+#pragma unroll
+                for (; i < NPF; ++i)
+                    if (i < k) v -= h[i] * vf[i];
+                i = k < NPF ? k : NPF;
+            } else {
+                v = w[r];
+            }
+            for (; i < k; ++i) v -= h[i] * a.V[size_t(i) * a.ldv + r];
             w[r] = v;
             x[q] = v;
         }
@@ -505,11 +534,11 @@ __global__ __launch_bounds__(kThr) void k_arnoldi_d(GmresArgs a, int j) {
 // cond: only when the cycle has ended (gs->done), else return at entry
 __global__ __launch_bounds__(kThr) void k_gmres_update(GmresArgs a, double* x, int cond) {
     GmresState* gs = a.gs;
-    if (cond && !gs->done) return;
+    const int done = gs->done, jl = gs->jlast;      // loaded together
+    if (cond && !done) return;
     __shared__ double y[kGmresMaxK];
     __shared__ double z[kThr];
     __shared__ double Hs[kGmresMaxK * kGmresMaxK];
-    const int jl = gs->jlast;
     if (jl < 0) return;
     const int R = a.restart;
     const int n = jl + 1;
@@ -519,12 +548,18 @@ __global__ __launch_bounds__(kThr) void k_gmres_update(GmresArgs a, double* x, i
     }
     for (int t = threadIdx.x; t < n; t += blockDim.x) y[t] = gs->gf[t];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = jl; i >= 0; --i) {
-            double acc = y[i];
-            for (int k = i + 1; k <= jl; ++k) acc -= Hs[k * n + i] * y[k];
-            y[i] = acc / Hs[i * n + i];
+    // back substitution H y = gf on wave 0 (n <= 64), column by column from
+    // the last: lane k finishes y[k], which is broadcast, and every lane
+    // t < k subtracts H[t][k] y[k]
+    if (threadIdx.x < 64) {
+        const int t = threadIdx.x;
+        double yt = t <= jl ? y[t] : 0.0;
+        for (int k = jl; k >= 0; --k) {
+            const double yk = lane_value(yt / Hs[k * n + k], k);
+            if (t == k) yt = yk;
+            else if (t < k) yt = fma(-Hs[k * n + t], yk, yt);
         }
+        if (t <= jl) y[t] = yt;
     }
     __syncthreads();
     const int bs = a.bs;
@@ -536,8 +571,19 @@ __global__ __launch_bounds__(kThr) void k_gmres_update(GmresArgs a, double* x, i
         const bool act = (fl < fps) && (F < f1);
         const size_t r = size_t(F) * bs + aa;
         double zz = 0.0;
-        if (act)
-            for (int i = 0; i <= jl; ++i) zz += y[i] * a.V[size_t(i) * a.ldv + r];
+        if (act) {
+            // four basis vectors per pass, their loads issued together
+            int i = 0;
+            for (; i + 3 <= jl; i += 4) {
+                const double* v = a.V + size_t(i) * a.ldv + r;
+                const double v0 = v[0], v1 = v[a.ldv], v2 = v[2 * a.ldv], v3 = v[3 * a.ldv];
+                zz += y[i] * v0;
+                zz += y[i + 1] * v1;
+                zz += y[i + 2] * v2;
+                zz += y[i + 3] * v3;
+            }
+            for (; i <= jl; ++i) zz += y[i] * a.V[size_t(i) * a.ldv + r];
+        }
         z[threadIdx.x] = zz;
         __syncthreads();
         if (act) {

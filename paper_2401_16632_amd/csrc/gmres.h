@@ -11,6 +11,9 @@ struct GmresState {
     // finished: the solve is over (converged, or ended at the iteration cap)
     int done, converged, jlast, iters, cycles, finished;
     int est_conv;            // the cycle ended with the residual estimate on target
+    int done_pre;            // done as the orthogonalisation kernel of the last
+                             // step saw it (read by the update kernel, whose
+                             // workgroup 0 may set done itself)
     double inv_norm, beta, bnorm, target;
     double h1[kGmresMaxK], h2[kGmresMaxK];
     double cs[kGmresMaxK], sn[kGmresMaxK];
@@ -67,8 +70,9 @@ hipError_t launch_arnoldi_product(const GmresArgs& a, int j, int fin_prev,
                                   const double* wcur, double* wnxt, hipStream_t st);
 hipError_t launch_arnoldi_orth(const GmresArgs& a, int j, double* wnxt,
                                hipStream_t st);
-hipError_t launch_arnoldi_finish(const GmresArgs& a, int j, hipStream_t st);
-hipError_t launch_gmres_update(const GmresArgs& a, double* x, int cond,
+// jfin >= 0: the update first finishes column jfin (the last step of the
+// chunk); cond: the update only when the cycle has ended
+hipError_t launch_gmres_update(const GmresArgs& a, double* x, int cond, int jfin,
                                hipStream_t st);
 
 }  // namespace hfr

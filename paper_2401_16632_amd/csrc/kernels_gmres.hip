@@ -15,8 +15,9 @@
 //      with two passes partial dots V_i . w        (classical Gram-Schmidt)
 //   C: (two passes only) reduce B's partials, w -= sum h2_i V_i, partial
 //      |w|^2
-// The last step of a chunk of steps is closed by a one-workgroup kernel D
-// that finishes its column, so the host can read the state.  Partial sums
+// The last column of a chunk of steps is finished by the update kernel that
+// follows the chunk (every workgroup forms it, workgroup 0 stores it) before
+// it updates the solution if the cycle has ended.  Partial sums
 // are reduced in a fixed order by the consuming kernel, so results are
 // deterministic.  Once the cycle has converged every later kernel of the
 // cycle returns at entry.
@@ -97,6 +98,7 @@ struct GivensStage {
     double hc[kGmresMaxK + 1];
     double cs[kGmresMaxK], sn[kGmresMaxK];
     double gj, target, dec[2];
+    double gf;               // output: rotated right-hand side of the column
 };
 
 __device__ void stage_givens(const GmresArgs& a, int jc, GivensStage& g) {
@@ -156,6 +158,7 @@ __device__ void givens_column(const GmresArgs& a, int jc, double hn, bool write,
     }
     g.dec[0] = done ? 1.0 : 0.0;
     g.dec[1] = inv;
+    g.gf = c * g.gj;
 }
 
 // Block-sparse product over rows [r0, r1) of the block's faces: 64 rows at a
@@ -447,7 +450,9 @@ __global__ __launch_bounds__(kThr) void k_arnoldi_b(GmresArgs a, int j,
         for (int i = 0; i < NPF; ++i)
             if (i < k) vf[i] = a.V[size_t(i) * a.ldv + rf];
     }
-    if (gs->done) return;
+    const int done = gs->done;
+    if (blockIdx.x == 0 && threadIdx.x == 0) gs->done_pre = done;
+    if (done) return;
     __shared__ double red[kGmresMaxK * (kThr / 64)];
     __shared__ double h[kGmresMaxK];
     reduce_partials(k, a.nblkA, a.part3, h);
@@ -519,34 +524,47 @@ __global__ __launch_bounds__(kThr) void k_arnoldi_c(GmresArgs a, int j,
     block_partials(1, [&](int) { return nn; }, red, a.part + blockIdx.x, gridDim.x);
 }
 
-// ---- D: finish the last column of a chunk (one workgroup) -----------------
-__global__ __launch_bounds__(kThr) void k_arnoldi_d(GmresArgs a, int j) {
+// ---- end of a chunk: finish its last column; at the end of a cycle
+// y = H^-1 g, x += Dinv (V y) ---------------------------------------------------
+// jfin >= 0: column jfin (the chunk's last step) is finished first, unless
+// the cycle had already ended at an earlier step (gs->done_pre, written by
+// the last orthogonalisation kernel: gs->done itself may be set during this
+// launch by workgroup 0).  Every workgroup forms the column's Givens step,
+// workgroup 0 stores it, and the others take the column and its rotated
+// right-hand side from their own copy, not from gs.
+// cond: only when the cycle has ended, else return after the column
+__global__ __launch_bounds__(kThr) void k_gmres_update(GmresArgs a, double* x, int cond,
+                                                       int jfin) {
     GmresState* gs = a.gs;
-    if (gs->done) return;
-    __shared__ double fin[kGmresMaxK];
-    __shared__ GivensStage gv;
-    stage_givens(a, j, gv);
-    reduce_partials(1, a.nblk, a.part, fin);       // ends with a barrier
-    if (threadIdx.x == 0) givens_column(a, j, sqrt(fin[0]), true, gv);
-}
-
-// ---- end of a cycle: y = H^-1 g, x += Dinv (V y) --------------------------
-// cond: only when the cycle has ended (gs->done), else return at entry
-__global__ __launch_bounds__(kThr) void k_gmres_update(GmresArgs a, double* x, int cond) {
-    GmresState* gs = a.gs;
-    const int done = gs->done, jl = gs->jlast;      // loaded together
-    if (cond && !done) return;
     __shared__ double y[kGmresMaxK];
     __shared__ double z[kThr];
     __shared__ double Hs[kGmresMaxK * kGmresMaxK];
+    __shared__ double fin[kGmresMaxK];
+    __shared__ GivensStage gv;
+    int done, jl;
+    bool own = false;                              // column jl formed here
+    if (jfin >= 0 && gs->done_pre == 0) {          // uniform
+        stage_givens(a, jfin, gv);
+        reduce_partials(1, a.nblk, a.part, fin);   // ends with a barrier
+        if (threadIdx.x == 0) givens_column(a, jfin, sqrt(fin[0]), blockIdx.x == 0, gv);
+        __syncthreads();
+        done = gv.dec[0] != 0.0 ? 1 : 0;
+        jl = jfin;
+        own = true;
+    } else {
+        done = gs->done;                           // not written by this launch
+        jl = gs->jlast;
+    }
+    if (cond && !done) return;
     if (jl < 0) return;
     const int R = a.restart;
     const int n = jl + 1;
     for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
         const int k = t / n, i = t - k * n;       // column k, row i
-        Hs[t] = gs->H[size_t(k) * (R + 1) + i];
+        Hs[t] = (own && k == jl) ? gv.hc[i] : gs->H[size_t(k) * (R + 1) + i];
     }
-    for (int t = threadIdx.x; t < n; t += blockDim.x) y[t] = gs->gf[t];
+    for (int t = threadIdx.x; t < n; t += blockDim.x)
+        y[t] = (own && t == jl) ? gv.gf : gs->gf[t];
     __syncthreads();
     // back substitution H y = gf on wave 0 (n <= 64), column by column from
     // the last: lane k finishes y[k], which is broadcast, and every lane
@@ -881,14 +899,9 @@ hipError_t launch_arnoldi_orth(const GmresArgs& a, int j, double* wnxt,
     return hipGetLastError();
 }
 
-hipError_t launch_arnoldi_finish(const GmresArgs& a, int j, hipStream_t st) {
-    hipLaunchKernelGGL(k_arnoldi_d, dim3(1), dim3(kThr), 0, st, a, j);
-    return hipGetLastError();
-}
-
-hipError_t launch_gmres_update(const GmresArgs& a, double* x, int cond,
+hipError_t launch_gmres_update(const GmresArgs& a, double* x, int cond, int jfin,
                                hipStream_t st) {
-    hipLaunchKernelGGL(k_gmres_update, dim3(a.nblk), dim3(kThr), 0, st, a, x, cond);
+    hipLaunchKernelGGL(k_gmres_update, dim3(a.nblk), dim3(kThr), 0, st, a, x, cond, jfin);
     return hipGetLastError();
 }
 

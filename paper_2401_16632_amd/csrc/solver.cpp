@@ -524,11 +524,11 @@ fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
             tend(s, tk, st);
             HIP_TRY(launch_arnoldi_orth(a, j, wn, st));
         }
-        if (steps > 0) HIP_TRY(launch_arnoldi_finish(a, j - 1, st));
         launched += steps;
-        // at the iteration cap the cycle is ended whether or not it is done
+        // at the iteration cap the cycle is ended whether or not it is done;
+        // the update kernel first finishes the chunk's last column
         const int cap = launched >= maxit ? 1 : 0;
-        HIP_TRY(launch_gmres_update(a, x, 1 - cap, st));
+        HIP_TRY(launch_gmres_update(a, x, 1 - cap, steps > 0 ? j - 1 : -1, st));
         HIP_TRY(launch_gmres_restart(a, x, W0, 0, 1 - cap, cap, ++s->seq_gmres, st));
         if ((e = fetch())) return e;
         if (hs.cycles != cycles_seen) {          // the cycle ended and restarted

@@ -182,17 +182,19 @@ def _cfl_dt(pr, lam=6.0, rings=3, n_theta=24):
 
 
 @pytest.mark.parametrize("name,passes", [("c1_p2", 1), ("pert_p3", 1), ("cyl_p3", 1),
-                                         ("c1_p2", 2), ("cyl_p3", 2)])
+                                         ("c1_p2", 2), ("cyl_p3", 2), ("c1_p1", 1),
+                                         ("cyl_p4", 1), ("c1_p5", 1)])
 def test_condense_solve_recover(name, passes):
     """Condensed system against the oracle's, the trace solve to 1e-12 with
-    one and with two Gram-Schmidt passes per Arnoldi step, and recovery."""
+    one and with two Gram-Schmidt passes per Arnoldi step, and recovery;
+    p = 1 to 5 cover every face block size of the product kernel (8 to 24)."""
     pr, u = _build(name)
     om, hm = pr.om, pr.hm
     uhat, ustar = _stage_inputs(pr, u)
     # a_ii dt of a stage at the local-CFL time step on the cylinder (block
     # Jacobi GMRES stalls near local CFL ~ 1e3, far outside the method's
     # operating range); 0.05 on the vortex meshes
-    a = 0.05 if name != "cyl_p3" else 0.3 * _cfl_dt(pr)
+    a = 0.3 * _cfl_dt(pr) if name.startswith("cyl") else 0.05
     sysd = onw.condense(om, pr.ph, u, uhat, ustar, a)
     s = hp.Solver(hm, rtol=1e-12, max_iters=3000, restart=60, cgs_passes=passes)
     s.assemble_condense(dev(soa(u)), dev(uhat), dev(soa(ustar)), a)

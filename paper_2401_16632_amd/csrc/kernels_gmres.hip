@@ -774,7 +774,13 @@ __global__ __launch_bounds__(256) void k_precondition_matrix16(int nblocks, cons
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int p = blockIdx.x * 4 + wv;
     if (p >= nblocks) return;                      // whole wave
-    const size_t lb = size_t(p) * 256, db = size_t(col[p]) * 256;
+    const size_t lb = size_t(p) * 256;
+    // the A operands (block p of L) are loaded first: they depend on
+    // nothing, while the Dinv block waits for its column index
+    TL av[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) av[kk] = L[lb + 64 * kk + lane];
+    const size_t db = size_t(col[p]) * 256;
     const int i = lane & 15, g = lane >> 4;
     // the column face's Dinv block, read with consecutive lanes on
     // consecutive entries and staged in LDS with a row stride of 17 (the
@@ -792,9 +798,8 @@ __global__ __launch_bounds__(256) void k_precondition_matrix16(int nblocks, cons
         mf4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
-            const float a = L[lb + 64 * kk + lane];
             const float b = dsh[wv][i * 17 + 4 * kk + g];
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], b, acc, 0, 0, 0);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) Lt[lb + (4 * g + r) * 16 + i] = acc[r];
@@ -802,9 +807,8 @@ __global__ __launch_bounds__(256) void k_precondition_matrix16(int nblocks, cons
         md4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
-            const double a = L[lb + 64 * kk + lane];
             const double b = dsh[wv][i * 17 + 4 * kk + g];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk], b, acc, 0, 0, 0);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) Lt[lb + (g + 4 * r) * 16 + i] = acc[r];

@@ -33,8 +33,8 @@ struct GmresArgs {
     size_t ldv;
     const int* rowptr;
     const int* col;
-    const int* ell;          // padded face rows: kmax {block, column} pairs per
-    int kmax;                // row, {-1, -1} past its end (product kernel)
+    const int* ell;          // padded block rows: kmax {block, column} pairs
+    int kmax;                // per row, {-1, -1} past its end (product kernel)
     const double* L64;       // original matrix (true residual)
     const float* L32;
     const double* Lt64;      // preconditioned matrix L Dinv

@@ -201,8 +201,9 @@ __device__ __forceinline__ double row_block(const T* M, const double* x, int c, 
 }
 
 // The same share for row-major blocks of size BS through the padded table
-// a.ell of the face rows ({block index, block column} of a row's k-th block
-// at F * kmax + k, {-1, -1} past its end), so the block and column indices
+// a.ell of the block rows (trace faces, or trace nodes in EFR): {block
+// index, block column} of row F's k-th block at F * kmax + k, {-1, -1} past
+// its end, so the block and column indices
 // are one load away instead of behind the row pointers.  Group `part` takes
 // blocks part, part + 4, ... two per pass, all their loads in flight
 // together; the additions are those of one block per pass, in the same
@@ -227,7 +228,7 @@ __device__ __forceinline__ double row_share_ell(const GmresArgs& a, const T* M,
     return acc;
 }
 
-// entries part and part + 4 of face F's row in the padded table
+// entries part and part + 4 of block row F in the padded table
 __device__ __forceinline__ void ell_pair(const GmresArgs& a, int F, int2& e1, int2& e2) {
     const int part = threadIdx.x >> 6;
     const int2* ell = reinterpret_cast<const int2*>(a.ell) + size_t(F) * a.kmax;

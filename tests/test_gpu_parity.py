@@ -223,6 +223,30 @@ def test_condense_solve_recover(name, passes):
     assert np.abs(unsoa(host(du), hm.Nim, pr.P) - du_o).max() <= 1e-11 * max(1e-300, np.abs(du_o).max())
 
 
+@pytest.mark.parametrize("name", ["c1_p1", "c1_p2", "cyl_p4", "c1_p5"])
+def test_trace_solve_fp32_form(name):
+    """FP32 form (tableaux, trace matrix and preconditioner in FP32) at the
+    face block sizes 8, 12, 20 and 24: the Arnoldi steps use the FP32
+    preconditioned matrix, while the final residual is formed in FP64 from
+    the unpreconditioned FP32 matrix by a separate kernel, so it must reach
+    the GMRES tolerance; the solution agrees with the oracle's FP64 trace
+    solution to the accuracy of an FP32 condensation (1e-3 relative)."""
+    pr, u = _build(name)
+    om, hm = pr.om, pr.hm
+    uhat, ustar = _stage_inputs(pr, u)
+    a = 0.3 * _cfl_dt(pr) if name.startswith("cyl") else 0.05
+    sysd = onw.condense(om, pr.ph, u, uhat, ustar, a)
+    s = hp.Solver(hm, precision="fp32", precond="fp32", rtol=1e-12, max_iters=3000,
+                  restart=60)
+    s.assemble_condense(dev(soa(u)), dev(uhat), dev(soa(ustar)), a)
+    N = 4 * hm.Ntp
+    duh = torch.zeros(N, dtype=torch.float64, device="cuda")
+    st = s.trace_solve(duh, allow_unconverged=True)
+    assert st["rel_residual"] <= 1e-11, st
+    duh_o = onw.trace_solve(sysd["L"], sysd["t"])
+    assert np.abs(host(duh) - duh_o).max() <= 1e-3 * np.abs(duh_o).max()
+
+
 def _run_steps(pr, u0, dt, nsteps, precision="fp64", precond="fp64",
                tab="HIMEX2C", tol=1e-13, cgs_passes=1):
     om, hm = pr.om, pr.hm

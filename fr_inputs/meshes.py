@@ -50,6 +50,44 @@ def periodic_quad_mesh(nx, ny, x0=-5.0, x1=5.0, y0=-5.0, y1=5.0,
                 elem_face_bc=np.zeros((nx * ny, 4), np.int8))
 
 
+def box_quad_mesh(nx, ny, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0,
+                  tags=(BC_FARFIELD,) * 4, perturb=0.0, seed=None):
+    """Non-periodic nx-by-ny grid of quads on [x0,x1]x[y0,y1] whose boundary
+    edges carry the tags (bottom, right, top, left).  ``perturb`` moves every
+    interior vertex by a seeded uniform offset of at most ``perturb`` times
+    the cell size; boundary vertices stay on the box."""
+    xs = np.linspace(x0, x1, nx + 1)
+    ys = np.linspace(y0, y1, ny + 1)
+    X, Y = np.meshgrid(xs, ys)
+    node_xy = np.stack([X.ravel(), Y.ravel()], axis=1).astype(np.float64)
+    if perturb:
+        rng = np.random.default_rng(seed)
+        off = rng.uniform(-perturb, perturb, size=node_xy.shape)
+        off *= np.array([(x1 - x0) / nx, (y1 - y0) / ny])
+        ii, jj = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1))
+        inner = ((ii > 0) & (ii < nx) & (jj > 0) & (jj < ny)).ravel()
+        node_xy[inner] += off[inner]
+    nid = lambda i, j: j * (nx + 1) + i
+    elems, bc = [], []
+    for j in range(ny):
+        for i in range(nx):
+            elems.append([nid(i, j), nid(i + 1, j), nid(i + 1, j + 1),
+                          nid(i, j + 1)])
+            t = [BC_INTERIOR] * 4
+            if j == 0:
+                t[0] = tags[0]
+            if i == nx - 1:
+                t[1] = tags[1]
+            if j == ny - 1:
+                t[2] = tags[2]
+            if i == 0:
+                t[3] = tags[3]
+            bc.append(t)
+    return dict(node_xy=node_xy, elem_nodes=np.asarray(elems, np.int32),
+                node_topo=np.arange(node_xy.shape[0], dtype=np.int32),
+                elem_face_bc=np.asarray(bc, np.int8))
+
+
 def ogrid_ratio_for_outer(n_r, first, outer_gap):
     """Geometric ratio q with first*(q**n_r - 1)/(q - 1) == outer_gap (bisection)."""
     lo, hi = 1.0 + 1e-12, 4.0

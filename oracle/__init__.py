@@ -17,8 +17,8 @@ written special case).  No function is "parity unpinned".
 from .operators import RefOps
 from .mesh import QuadMesh, FACE_EXPLICIT, FACE_UPSILON, FACE_TRACE, FACE_BOUNDARY
 from .physics import Euler, EDAC, Advection
-from . import residual, newton, imex, efr, modal_filter
+from . import residual, newton, imex, efr, modal_filter, boundary_trace
 
 __all__ = ["RefOps", "QuadMesh", "Euler", "EDAC", "Advection", "residual", "newton",
-           "imex", "efr", "modal_filter", "FACE_EXPLICIT", "FACE_UPSILON", "FACE_TRACE",
+           "imex", "efr", "modal_filter", "boundary_trace", "FACE_EXPLICIT", "FACE_UPSILON", "FACE_TRACE",
            "FACE_BOUNDARY"]

@@ -53,9 +53,11 @@ class Euler:
         return rabs(vn) + c
 
     def ghost(self, u, nx, ny, tag, uinf):
-        """Exterior state of a boundary flux point (the F^BC of eq:hfr2 is
-        taken as the standard FR flux against this state): slip wall mirrors
-        the normal momentum, far field is the free stream."""
+        """Exterior state of a boundary flux point: slip wall mirrors the
+        normal momentum (density, energy and tangential momentum kept), far
+        field is the free stream.  Explicit elements take the standard FR
+        flux against it; implicit elements the hybridized flux against the
+        boundary trace it determines (``hfr_boundary_flux``)."""
         mn = u[..., 1] * nx + u[..., 2] * ny
         wall = np.stack([u[..., 0], u[..., 1] - 2.0 * mn * nx,
                          u[..., 2] - 2.0 * mn * ny, u[..., 3]], axis=-1)
@@ -158,5 +160,30 @@ def hfr_flux(phys, u, uhat, S):
 
 
 def boundary_flux(phys, u, S, tag, uinf):
+    """Standard FR flux on a boundary face (Section 2.1): Rusanov against the
+    ghost state of the boundary condition."""
     nx, ny, _ = _unit(S)
     return rusanov(phys, u, phys.ghost(u, nx, ny, tag, uinf), S)
+
+
+def boundary_trace(phys, u, S, tag, uinf):
+    """Boundary trace of a hybridized element face, solved in closed form.
+
+    The transmission condition (eq:hfr2, eq:hfrimex) has a boundary term
+    F^BC that the paper does not define.  Reading: the jump of the
+    hybridized flux across the boundary, with the ghost state of the
+    boundary condition on the outside,
+        F^BC = F_hat(u, uhat) . S + F_hat(u_g, uhat) . (-S)
+             = s(uhat) |S| (u + u_g - 2 uhat),
+    the trace fluxes F(uhat) . S cancelling.  With s > 0 it vanishes at one
+    point only, uhat = (u + u_g)/2, so the boundary trace is a local
+    function of the element's own face state and never enters the global
+    trace system."""
+    nx, ny, _ = _unit(S)
+    return 0.5 * (u + phys.ghost(u, nx, ny, tag, uinf))
+
+
+def hfr_boundary_flux(phys, u, S, tag, uinf):
+    """Hybridized flux (eq:hfrriemann) on a boundary face of an implicit
+    element, against the boundary trace of ``boundary_trace``."""
+    return hfr_flux(phys, u, boundary_trace(phys, u, S, tag, uinf), S)

@@ -12,12 +12,13 @@ derived from R.
 import numpy as np
 
 from .mesh import FACE_TRACE, FACE_UPSILON, FACE_BOUNDARY, FACE_EXPLICIT
-from .physics import rusanov, hfr_flux, boundary_flux
+from .physics import rusanov, hfr_flux, boundary_flux, hfr_boundary_flux
 
 # element-face flux roles
 ROLE_RUSANOV = 0    # standard FR flux against the outer state
 ROLE_HFR = 1        # hybridized flux against the trace (outer = trace)
 ROLE_BC = 2         # standard FR flux against the boundary ghost state
+ROLE_BCT = 3        # hybridized flux against the boundary trace (implicit)
 
 
 def face_values(ops, a):
@@ -84,7 +85,7 @@ def element_residual(mesh, phys, elems, u, outer, roles):
     tags = mesh.elem_face_bc[elems]
     common = np.zeros_like(uf)
     r = np.broadcast_to(roles[..., None], uf.shape[:-1])
-    for role in (ROLE_RUSANOV, ROLE_HFR, ROLE_BC):
+    for role in (ROLE_RUSANOV, ROLE_HFR, ROLE_BC, ROLE_BCT):
         m = r == role
         if not m.any():
             continue
@@ -94,7 +95,8 @@ def element_residual(mesh, phys, elems, u, outer, roles):
             common[m] = hfr_flux(phys, uf[m], outer[m], S[m])
         else:
             tg = np.broadcast_to(tags[..., None], uf.shape[:-1])[m]
-            common[m] = boundary_flux(phys, uf[m], S[m], tg, mesh.uinf)
+            bflux = boundary_flux if role == ROLE_BC else hfr_boundary_flux
+            common[m] = bflux(phys, uf[m], S[m], tg, mesh.uinf)
     H = common - fdn
     div = divergence(ops, ft, gt, H)
     R = -div / mesh.J[elems][..., None]
@@ -126,9 +128,12 @@ def fr_residual(mesh, phys, u):
 
 
 def implicit_roles(mesh):
+    """Hybridized flux against the trace on trace faces and against the
+    (locally solved) boundary trace on boundary faces; the standard FR flux
+    on Upsilon, where there is no trace (last paragraph of Section 4)."""
     kinds = mesh.elem_face_kind[mesh.imp_elems]
     return np.where(kinds == FACE_TRACE, ROLE_HFR,
-                    np.where(kinds == FACE_BOUNDARY, ROLE_BC, ROLE_RUSANOV))
+                    np.where(kinds == FACE_BOUNDARY, ROLE_BCT, ROLE_RUSANOV))
 
 
 def implicit_outer(mesh, u_all, uhat):

@@ -64,11 +64,14 @@ __device__ __forceinline__ double wave_speed(const Prim& q, double nx,
     return fabs(vn) + q.c;
 }
 
+// ghost state of a boundary flux point: the slip wall mirrors the normal
+// momentum (Euler) or velocity (EDAC), both stored in u[1], u[2]; the far
+// field is the free stream
 __device__ __forceinline__ void ghost_state(const double u[4], double nx,
-                                            double ny, int role,
+                                            double ny, bool wall,
                                             const double uinf[4],
                                             double out[4]) {
-    if (role == 2) {  // slip wall: mirror the normal momentum
+    if (wall) {
         double mn = u[1] * nx + u[2] * ny;
         out[0] = u[0];
         out[1] = u[1] - 2.0 * mn * nx;

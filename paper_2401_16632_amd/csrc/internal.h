@@ -43,8 +43,20 @@ enum FaceRole : int {
     ROLE_RUSANOV = 0,   // standard FR flux against the neighbour
     ROLE_HFR = 1,       // hybridized flux against the trace
     ROLE_WALL = 2,      // standard FR flux against the slip-wall ghost
-    ROLE_FAR = 3        // standard FR flux against the free stream
+    ROLE_FAR = 3,       // standard FR flux against the free stream
+    // implicit elements: hybridized flux against the boundary trace, which
+    // the boundary transmission condition fixes per flux point as the mean
+    // of the face state and its ghost (slip wall, far field)
+    ROLE_WALL_T = 4,
+    ROLE_FAR_T = 5
 };
+
+__host__ __device__ constexpr bool role_is_wall(int r) {
+    return r == ROLE_WALL || r == ROLE_WALL_T;
+}
+__host__ __device__ constexpr bool role_is_boundary_trace(int r) {
+    return r == ROLE_WALL_T || r == ROLE_FAR_T;
+}
 
 // Per element face: neighbour element, neighbour local face, role, and
 // trace encoding (trace_face*2 + side, -1 off the trace).
@@ -157,19 +169,6 @@ hipError_t launch_assemble(const AssembleLaunch& a, hipStream_t st);
 hipError_t launch_spmv(int ntf, int bs, const int* rowptr, const int* col,
                        const double* L64, const float* L32, const double* x,
                        double* y, double alpha, const double* yin,
-                       hipStream_t st);
-hipError_t launch_precond(int ntf, int bs, int pc, const void* inv,
-                          const double* x, double* y, hipStream_t st);
-hipError_t launch_multidot(int N, int k, const double* V, size_t ldv,
-                           const double* w, double* partial, int nblk,
-                           double* out, hipStream_t st);
-int multidot_blocks(int N);
-hipError_t launch_multi_axpy(int N, int k, const double* V, size_t ldv,
-                             const double* coef, double* w, double sign,
-                             hipStream_t st);
-hipError_t launch_scale(int N, double* x, const double* src, double a,
-                        hipStream_t st);
-hipError_t launch_axpy(int N, double a, const double* x, double* y,
                        hipStream_t st);
 // recovery; with efr the trace at the flux points is interpolated from the
 // trace nodes of trace_map (GLL basis of ops)

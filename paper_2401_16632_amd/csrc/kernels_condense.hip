@@ -113,93 +113,40 @@ __device__ void element_linearisation(const CondenseLaunch& a, const RefOps& o,
                 }
                 phys_drusanov(pk, uf, outer, S.x, S.y, Fu, Jb);
             } else {
-                ghost_state(uf, nx, ny, fi.role, a.phys.uinf, outer);
-                phys_drusanov(pk, uf, outer, S.x, S.y, Fu, Jb);
-                if (fi.role == ROLE_WALL) {
-                    // d ghost / d u: identity except momentum rows I - 2 n n^T
-                    double R[16] = {1, 0, 0, 0, 0, 1 - 2 * nx * nx, -2 * nx * ny, 0,
-                                    0, -2 * nx * ny, 1 - 2 * ny * ny, 0, 0, 0, 0, 1};
+                const bool wall = role_is_wall(fi.role);
+                ghost_state(uf, nx, ny, wall, a.phys.uinf, outer);
+                // d ghost / d u: the mirror I - 2 n n^T on the two middle
+                // rows at a wall, zero in the far field
+                const double R[16] = {1, 0, 0, 0, 0, 1 - 2 * nx * nx, -2 * nx * ny, 0,
+                                      0, -2 * nx * ny, 1 - 2 * ny * ny, 0, 0, 0, 0, 1};
+                if (role_is_boundary_trace(fi.role)) {
+                    // F_hat(u, uhat_b(u)), uhat_b = (u + ghost(u))/2:
+                    // dF/du = s|S| I + (dF/duhat) (I + dghost/du)/2
+                    for (int v = 0; v < 4; ++v) outer[v] = 0.5 * (uf[v] + outer[v]);
+                    double su;
+                    phys_dhfr_flux(pk, uf, outer, S.x, S.y, &su, Jb);
                     for (int v = 0; v < 4; ++v)
                         for (int w = 0; w < 4; ++w) {
-                            double acc = 0.0;
-                            for (int z = 0; z < 4; ++z) acc += Jb[4 * v + z] * R[4 * z + w];
-                            Fu[4 * v + w] += acc;
+                            double acc = 0.5 * Jb[4 * v + w];
+                            if (wall)
+                                for (int z = 0; z < 4; ++z) acc += 0.5 * Jb[4 * v + z] * R[4 * z + w];
+                            Fu[4 * v + w] = acc + (v == w ? su : 0.0);
                         }
+                } else {
+                    phys_drusanov(pk, uf, outer, S.x, S.y, Fu, Jb);
+                    if (wall) {
+                        for (int v = 0; v < 4; ++v)
+                            for (int w = 0; w < 4; ++w) {
+                                double acc = 0.0;
+                                for (int z = 0; z < 4; ++z) acc += Jb[4 * v + z] * R[4 * z + w];
+                                Fu[4 * v + w] += acc;
+                            }
+                    }
                 }
             }
         }
     }
     __syncthreads();
-}
-
-// value of entry (r, c) of the augmented matrix
-template <int P>
-__device__ __forceinline__ double aug_entry(int r, int c, int k,
-                                            const CondenseLaunch& a,
-                                            const RefOps& o,
-                                            const CondShared<P>& sh) {
-    constexpr int NP = P * P;
-    constexpr int n = 4 * NP, m = 16 * P;
-    if (r < n) {
-        const int pr = r >> 2, v = r & 3;
-        const int i = pr % P, j = pr / P;
-        const double cij = sh.c[pr];
-        if (c < n) {
-            const int pc = c >> 2, w = c & 3;
-            const int l = pc % P, kk = pc / P;
-            double acc = 0.0;
-            if (kk == j) {
-                const double af = sh.Af[pc][v * 4 + w];
-                acc += o.D[i * P + l] * af;
-                acc += o.cr[i] * o.lp[l] * (sh.Fu[1 * P + j][v * 4 + w] - af);
-                acc += o.cl[i] * o.lm[l] * (sh.Fu[3 * P + (P - 1 - j)][v * 4 + w] + af);
-            }
-            if (l == i) {
-                const double ag = sh.Ag[pc][v * 4 + w];
-                acc += o.D[j * P + kk] * ag;
-                acc += o.cl[j] * o.lm[kk] * (sh.Fu[0 * P + i][v * 4 + w] + ag);
-                acc += o.cr[j] * o.lp[kk] * (sh.Fu[2 * P + (P - 1 - i)][v * 4 + w] - ag);
-            }
-            return (r == c ? 1.0 : 0.0) + cij * acc;
-        } else if (c < n + m) {
-            const int b = c - n;
-            const int f = b / (4 * P), q = (b >> 2) % P, w = b & 3;
-            if (!sh.tr[f]) return 0.0;
-            double coef;
-            if (f == 1 && q == j) coef = o.cr[i];
-            else if (f == 3 && q == P - 1 - j) coef = o.cl[i];
-            else if (f == 0 && q == i) coef = o.cl[j];
-            else if (f == 2 && q == P - 1 - i) coef = o.cr[j];
-            else return 0.0;
-            return cij * coef * sh.Fh[f * P + q][v * 4 + w];
-        } else {
-            return -a.h[size_t(v) * a.nimp * NP + size_t(k) * NP + pr];
-        }
-    } else {
-        const int b = r - n;
-        const int f = b / (4 * P), q = (b >> 2) % P, v = b & 3;
-        if (!sh.tr[f]) {
-            if (c >= n && c < n + m) return (c - n == b) ? 1.0 : 0.0;
-            return 0.0;
-        }
-        const double wq = o.w[q];
-        if (c < n) {
-            const int pc = c >> 2, w = c & 3;
-            const int l = pc % P, kk = pc / P;
-            double coef = 0.0;
-            if (f == 1) { if (kk == q) coef = o.lp[l]; }
-            else if (f == 3) { if (kk == P - 1 - q) coef = o.lm[l]; }
-            else if (f == 0) { if (l == q) coef = o.lm[kk]; }
-            else { if (l == P - 1 - q) coef = o.lp[kk]; }
-            return wq * coef * sh.Fu[f * P + q][v * 4 + w];
-        } else if (c < n + m) {
-            const int b2 = c - n;
-            if ((b2 >> 2) != (b >> 2)) return 0.0;
-            return wq * sh.Fh[f * P + q][v * 4 + (b2 & 3)];
-        } else {
-            return -a.gk[((size_t(k) * 4 + f) * P + q) * 4 + v];
-        }
-    }
 }
 
 // ---- block Gauss-Jordan sweep ----------------------------------------------

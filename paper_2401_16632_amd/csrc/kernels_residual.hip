@@ -143,9 +143,19 @@ __global__ __launch_bounds__(256) void k_residual(ResidualLaunch a, RefOps og) {
                 face_interp_global<P>(a.u, plane, fi.nb_e, fi.nb_lf, P - 1 - q, o, outer);
             } else {
                 const double mag = sqrt(S.x * S.x + S.y * S.y);
-                ghost_state(uf, S.x / mag, S.y / mag, fi.role, a.phys.uinf, outer);
+                ghost_state(uf, S.x / mag, S.y / mag, role_is_wall(fi.role), a.phys.uinf,
+                            outer);
             }
-            phys_rusanov(pk, uf, outer, S.x, S.y, com);
+            if (role_is_boundary_trace(fi.role)) {
+                // boundary trace of an implicit element: the mean of the
+                // face state and its ghost, closed-form root of the
+                // boundary transmission condition
+#pragma unroll
+                for (int v = 0; v < 4; ++v) outer[v] = 0.5 * (uf[v] + outer[v]);
+                phys_hfr_flux(pk, uf, outer, S.x, S.y, com);
+            } else {
+                phys_rusanov(pk, uf, outer, S.x, S.y, com);
+            }
             if (a.gk) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v)

@@ -409,8 +409,13 @@ extern "C" fr_status fr_mesh_create(const fr_mesh_desc* d, fr_mesh_t* out) {
             fi.nb_lf = m->face_l[2 * f + 1 - side];
             fi.trace = -1;
             int k = m->face_kind[f];
-            if (k == FR_FACE_BOUNDARY)
-                fi.role = face_bc[f] == FR_BC_WALL ? ROLE_WALL : ROLE_FAR;
+            if (k == FR_FACE_BOUNDARY) {
+                const bool wall = face_bc[f] == FR_BC_WALL;
+                if (m->elem_to_imp[e] >= 0)
+                    fi.role = wall ? ROLE_WALL_T : ROLE_FAR_T;
+                else
+                    fi.role = wall ? ROLE_WALL : ROLE_FAR;
+            }
             else if (k == FR_FACE_TRACE) {
                 fi.role = ROLE_HFR;
                 fi.trace = m->trace_of_face[f] * 2 + side;

@@ -159,8 +159,9 @@ fr_status fr_mesh_get_maps(fr_mesh_t mesh, int32_t* face_elem,
 /*
  * fr_explicit_rhs: standard FR residual R = du/dt of eq:freq1 (Rusanov flux
  * of Section 2.1 on every interior face, the same flux against a ghost state
- * on boundary faces) for every explicit element.  At Upsilon faces the
- * implicit neighbour's current state is used (eq:explicitimex).
+ * on boundary faces: the slip wall mirrors the normal momentum, the far field
+ * is uinf) for every explicit element.  At Upsilon faces the implicit
+ * neighbour's current state is used (eq:explicitimex).
  *   u     [4][Ne][Np]   full state (device, read)
  *   R_ex  [4][Nex][Np]  residual of the explicit elements (device, written)
  */
@@ -199,8 +200,11 @@ fr_status fr_modal_filter(fr_mesh_t mesh, const fr_filter_params* prm,
 /* Implicit (hybridized) stage                                             */
 /* ----------------------------------------------------------------------- */
 
-enum { HFR_PREC_FP64 = 0,   /* element blocks, LU and Schur in FP64        */
-       HFR_PREC_FP32 = 1 }; /* LU and Schur products in FP32 on MFMA       */
+enum { HFR_PREC_FP64 = 0,   /* element tableaux swept in FP64              */
+       HFR_PREC_FP32 = 1 }; /* element tableaux (A^-1 B, Schur complement)
+                               formed and stored in FP32 by the vector-ALU
+                               Gauss-Jordan sweep; the condensed right-hand
+                               side is accumulated in FP64                 */
 enum { HFR_PC_FP64 = 0, HFR_PC_FP32 = 1, HFR_PC_BF16 = 2 };
 
 typedef struct {
@@ -224,6 +228,10 @@ typedef struct {
     int32_t gmres_cgs_passes; /* classical Gram-Schmidt passes per Arnoldi
                                  step: 1 (also when 0) or 2 (each new
                                  vector orthogonalised twice)                */
+    int32_t caller_workspace; /* 0: hfr_solver_create allocates the working
+                                 device memory itself; 1: the caller owns it
+                                 and passes it to hfr_solver_bind_workspace
+                                 before any other call on the solver         */
 } hfr_opts;
 
 typedef struct {
@@ -236,15 +244,39 @@ typedef struct {
     int32_t newton_iters;
     int32_t gmres_iters;      /* summed over Newton iterations               */
     double residual;          /* final max(|h|inf, |g|inf)                   */
-    double implicit_ms;       /* host wall time of the implicit solve        */
+    double implicit_ms;       /* imex_stage: host wall time of the implicit
+                                 stage, from its entry (queued work drained)
+                                 to R_i ready: u*, initial trace, every
+                                 Newton iteration, R_i                      */
 } hfr_newton_stats;
 
 /*
- * hfr_solver_create: allocates the solver's device workspace (library-owned;
- * its size is reported in *workspace_bytes when non-NULL).
+ * hfr_solver_create: builds the block structure of the condensed trace
+ * system of Section 3.2 (one block row per trace face, or per trace node
+ * with FR_MESH_EFR) and the element-to-block assembly lists of eq:assembly,
+ * uploaded once as library-owned read-only device tables, and a small
+ * pinned host buffer for the convergence readbacks.  The working device
+ * memory (element tableaux, trace matrix and its preconditioned copy,
+ * Krylov basis, residuals; one block) is *workspace_bytes long (reported
+ * when non-NULL): with opts->caller_workspace = 0 the library allocates and
+ * frees it, with 1 the caller provides it through
+ * hfr_solver_bind_workspace.  Host-synchronous.
  */
 fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* opts,
                             size_t* workspace_bytes, hfr_solver_t* out);
+/*
+ * hfr_solver_bind_workspace: hands the solver the caller-owned working
+ * memory (device, >= the size hfr_solver_create reported, 256-byte
+ * aligned; for example a PyTorch tensor).  It must outlive the solver's use
+ * of it; the library never frees it.  Binding again (for example another
+ * buffer) is allowed between calls; the solver's convergence state and any
+ * stored factorisation are reset.  Host-synchronous (clears the Krylov
+ * state).  FR_E_INVALID for a null pointer, a solver created with
+ * caller_workspace = 0, a misaligned pointer or a short buffer.  Every
+ * compute call on a solver without a bound workspace returns FR_E_INVALID.
+ */
+fr_status hfr_solver_bind_workspace(hfr_solver_t solver, void* dev_ptr,
+                                    size_t bytes);
 void hfr_solver_destroy(hfr_solver_t solver);
 
 /*
@@ -252,7 +284,12 @@ void hfr_solver_destroy(hfr_solver_t solver);
  * hybridized operator (eq:hfr1, eq:hfr2, eq:hfrimex):
  *   h = u_im - ustar - aii_dt * R^im(u, uhat),  R = du/dt (sign reading of
  *   the paper's inconsistent printed forms), g = transmission residual
- *   collocated at the trace points (face mass diag(w_q J_f)).
+ *   collocated at the trace points (face mass diag(w_q J_f)).  On boundary
+ *   faces the implicit elements take the hybridized flux against a boundary
+ *   trace; reading the undefined boundary flux F^BC of eq:hfr2 as the jump
+ *   of the hybridized flux against the ghost state, its transmission
+ *   condition s(uhat)|S| (u + u_ghost - 2 uhat) = 0 gives that trace in
+ *   closed form, uhat = (u + u_ghost)/2, so it never enters L or g.
  *   u [4][Ne][Np] full state (explicit part used on Upsilon), uhat [Ntp][4],
  *   ustar [4][Nim][Np]; outputs h [4][Nim][Np], g [Ntp][4], R_im
  *   [4][Nim][Np]; any output may be NULL.
@@ -275,10 +312,11 @@ fr_status hfr_assemble_condense(hfr_solver_t s, const double* u,
 
 /*
  * hfr_trace_solve: solves L duhat = t (the condensed trace system of
- * Section 3.2) by restarted GMRES with FP64 Arnoldi (classical Gram-Schmidt
- * applied twice), a right block-Jacobi preconditioner (one diagonal face
- * block per trace face) and an FP64 true-residual recomputation at every
- * restart.  Host-synchronous (reads the Krylov coefficients).
+ * Section 3.2) by restarted GMRES with FP64 Arnoldi (one classical
+ * Gram-Schmidt pass per step, two with hfr_opts.gmres_cgs_passes = 2), a
+ * right block-Jacobi preconditioner (one diagonal face block per trace face)
+ * and an FP64 true-residual recomputation at every restart.
+ * Host-synchronous (reads the Krylov coefficients).
  *   duhat [Ntp][4] (device, written).  FR_E_NOT_CONVERGED when the
  *   iteration cap is hit (duhat holds the last iterate).
  */
@@ -303,6 +341,12 @@ fr_status hfr_trace_matvec(hfr_solver_t s, const double* x, double* y,
                            void* stream);
 fr_status hfr_get_system(hfr_solver_t s, double* t, double* h, double* g,
                          void* stream);
+/* y = L D^-1 x: the product the Krylov solver runs (the trace matrix of the
+ * last linearisation times the inverse of its diagonal face blocks, the
+ * right block-Jacobi preconditioner of Section 3.2's trace solve), by the
+ * block-row code of the Arnoldi product kernel.  x, y [Ntp][4] (device). */
+fr_status hfr_trace_product(hfr_solver_t s, const double* x, double* y,
+                            void* stream);
 fr_status hfr_get_blocks(hfr_solver_t s, double* blocks, void* stream);
 /* Swept element tableaux of the last linearisation (static condensation,
  * Section 3.2), N x N per implicit element with N = n + m, COLUMN-major,
@@ -370,6 +414,23 @@ typedef struct {
 } imex_tableau;
 
 /*
+ * imex_tableau_get: fills *out with one of the additive pairs built into the
+ * library.  The implicit part of both is the two-stage, second-order SDIRK
+ * tableau of Section 3.1 (gamma = 1 - sqrt(2)/2, A = [[gamma, 0],
+ * [1 - gamma, gamma]], b = (1 - gamma, gamma)).  The paper's own explicit
+ * partners are in a tableau appendix that its text does not contain; the
+ * partner here satisfies the second-order conditions in the padded form of
+ * table:butcherimex (c_bar = [0 c]): A_bar rows (0,0,0), (gamma,0,0),
+ * (delta, 1-delta, 0) with delta = 1 - 1/(2 gamma), and
+ *   IMEX_HIMEX2C: b_bar = (0, b), so the Upsilon fluxes cancel over a step
+ *                 (exact conservation across the interface, Section 4);
+ *   IMEX_ARS222:  b_bar = (delta, 1 - delta, 0).
+ * FR_E_INVALID for a null pointer or an unknown id.
+ */
+enum { IMEX_HIMEX2C = 0, IMEX_ARS222 = 1 };
+fr_status imex_tableau_get(int32_t id, imex_tableau* out);
+
+/*
  * Device buffers of one step (all caller-owned):
  *   u_n  [4][Ne][Np]        state at t_n (read)
  *   u    [4][Ne][Np]        stage state; holds u_{n+1} after stage s+1
@@ -393,7 +454,8 @@ typedef struct {
  * R_i = R^im(u_i, uhat_i) and R_bar_{i+1} = R^ex(u_i); stage s+1 forms
  * u_{n+1}.  Host-synchronous for i = 1..s (Newton convergence test).  On
  * FR_E_NOT_CONVERGED / FR_E_NONFINITE the implicit part of u holds the last
- * Newton iterate and u_n is untouched.
+ * Newton iterate and u_n is untouched.  u_n must not overlap u, uhat, R_im
+ * or R_ex (FR_E_INVALID): every stage reads it after u has been written.
  */
 fr_status imex_stage(fr_mesh_t mesh, hfr_solver_t s, const imex_tableau* tab,
                      int32_t stage, double dt, const imex_state* st,

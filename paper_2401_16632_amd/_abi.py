@@ -13,11 +13,11 @@ STATUS = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_MESH", -3: "FR_E_NOMEM",
           -7: "FR_E_UNSUPPORTED"}
 EXPORTED = ["fr_mesh_create", "fr_mesh_destroy", "fr_mesh_get_info",
             "fr_mesh_get_maps", "fr_explicit_rhs", "fr_modal_filter",
-            "hfr_solver_create",
+            "hfr_solver_create", "hfr_solver_bind_workspace",
             "hfr_solver_destroy", "hfr_residual", "hfr_assemble_condense",
-            "hfr_trace_solve", "hfr_recover", "hfr_trace_matvec",
+            "hfr_trace_solve", "hfr_recover", "hfr_trace_matvec", "hfr_trace_product",
             "hfr_get_system", "hfr_get_blocks", "hfr_get_factors", "hfr_get_preconditioner", "hfr_timing",
-            "imex_stage",
+            "imex_stage", "imex_tableau_get",
             "fr_last_error"]
 TIMERS = ["residual", "condense", "assemble", "pcsetup", "spmv",
           "trace_solve", "recover", "explicit", "fill"]
@@ -47,7 +47,8 @@ class HfrOpts(Structure):
                 ("gmres_restart", c_int32), ("gmres_max_iters", c_int32),
                 ("gmres_rtol", c_double), ("newton_max_iters", c_int32),
                 ("newton_tol", c_double), ("keep_blocks", c_int32),
-                ("jacobian_lag", c_int32), ("gmres_cgs_passes", c_int32)]
+                ("jacobian_lag", c_int32), ("gmres_cgs_passes", c_int32),
+                ("caller_workspace", c_int32)]
 
 
 class HfrSolveStats(Structure):
@@ -92,6 +93,7 @@ def load(path=LIB_PATH):
                                       c_void_p]),
         "hfr_solver_create": (c_int32, [c_void_p, P(HfrOpts), P(c_size_t),
                                         P(c_void_p)]),
+        "hfr_solver_bind_workspace": (c_int32, [c_void_p, c_void_p, c_size_t]),
         "hfr_solver_destroy": (None, [c_void_p]),
         "hfr_residual": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_double, c_void_p, c_void_p, c_void_p,
@@ -102,12 +104,14 @@ def load(path=LIB_PATH):
                                       c_void_p]),
         "hfr_recover": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
         "hfr_trace_matvec": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+        "hfr_trace_product": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
         "hfr_get_system": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p,
                                      c_void_p]),
         "hfr_get_blocks": (c_int32, [c_void_p, c_void_p, c_void_p]),
         "imex_stage": (c_int32, [c_void_p, c_void_p, P(ImexTableau), c_int32,
                                  c_double, P(ImexState), P(HfrNewtonStats),
                                  c_void_p]),
+        "imex_tableau_get": (c_int32, [c_int32, P(ImexTableau)]),
         "hfr_get_factors": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
         "hfr_get_preconditioner": (c_int32, [c_void_p, c_void_p, c_void_p]),
         "hfr_timing": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),

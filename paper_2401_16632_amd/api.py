@@ -5,7 +5,6 @@ import numpy as np
 import torch
 
 from . import _abi
-from .tableaus import pair
 
 _LIB = None
 
@@ -63,19 +62,15 @@ def elements_from_soa(a, P):
     return np.ascontiguousarray(np.transpose(a.reshape(nv, Ne, P, P), (1, 2, 3, 0)))
 
 
+TABLEAU_IDS = {"HIMEX2C": 0, "ARS222": 1}
+
+
 def tableau(name="HIMEX2C"):
-    t = pair(name)
+    """The library's additive pair of that name (imex_tableau_get)."""
+    if name not in TABLEAU_IDS:
+        raise ValueError(f"unknown tableau {name}")
     tab = _abi.ImexTableau()
-    tab.s = t["s"]
-    s = t["s"]
-    for i in range(s):
-        tab.b[i] = t["b"][i]
-        for j in range(s):
-            tab.A[i * s + j] = t["A"][i][j]
-    for i in range(s + 1):
-        tab.bbar[i] = t["bbar"][i]
-        for j in range(s + 1):
-            tab.Abar[i * (s + 1) + j] = t["Abar"][i][j]
+    _check(load_library().imex_tableau_get(TABLEAU_IDS[name], ctypes.byref(tab)))
     return tab
 
 
@@ -195,7 +190,10 @@ class Solver:
     def __init__(self, mesh, precision="fp64", precond="fp64", restart=30,
                  max_iters=600, rtol=1e-10, newton_max_iters=25,
                  newton_tol=1e-13, keep_blocks=False, jacobian_lag=0,
-                 cgs_passes=1):
+                 cgs_passes=1, workspace=None):
+        """workspace: None (the library allocates its working memory) or
+        "torch" (a uint8 CUDA tensor allocated here and bound with
+        hfr_solver_bind_workspace; kept as self.workspace)."""
         lib = load_library()
         self.mesh = mesh
         o = _abi.HfrOpts()
@@ -209,13 +207,24 @@ class Solver:
         o.keep_blocks = 1 if keep_blocks else 0
         o.jacobian_lag = int(jacobian_lag)
         o.gmres_cgs_passes = int(cgs_passes)
+        if workspace not in (None, "torch"):
+            raise ValueError("workspace must be None or 'torch'")
+        o.caller_workspace = 1 if workspace == "torch" else 0
         self.opts = o
+        self.workspace = None
         ws = ctypes.c_size_t()
         h = ctypes.c_void_p()
         _check(lib.hfr_solver_create(mesh.handle, ctypes.byref(o),
                                      ctypes.byref(ws), ctypes.byref(h)))
         self.handle = h
         self.workspace_bytes = ws.value
+        if workspace == "torch":
+            # torch's caching allocator hands out 512-byte aligned blocks
+            self.workspace = torch.empty(max(256, ws.value), dtype=torch.uint8,
+                                         device="cuda")
+            _check(lib.hfr_solver_bind_workspace(
+                h, ctypes.c_void_p(self.workspace.data_ptr()),
+                ctypes.c_size_t(self.workspace.numel())))
         m = mesh
         self.n = 4 * m.Np
         self.m = 16 * m.P
@@ -257,6 +266,12 @@ class Solver:
         _, nt, _ = self._sizes()
         _check(load_library().hfr_trace_matvec(self.handle, _dev(x, nt, "x"),
                                                _dev(y, nt, "y"), _stream(stream)))
+
+    def product(self, x, y, stream=None):
+        """y = L D^-1 x, the product the Krylov solver runs."""
+        _, nt, _ = self._sizes()
+        _check(load_library().hfr_trace_product(self.handle, _dev(x, nt, "x"),
+                                                _dev(y, nt, "y"), _stream(stream)))
 
     def get_system(self, t=None, h=None, g=None, stream=None):
         _, nt, ni = self._sizes()

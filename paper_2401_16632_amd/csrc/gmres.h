@@ -68,6 +68,9 @@ hipError_t launch_gmres_restart(const GmresArgs& a, double* x,
                                 hipStream_t st);
 hipError_t launch_arnoldi_product(const GmresArgs& a, int j, int fin_prev,
                                   const double* wcur, double* wnxt, hipStream_t st);
+// y = Lt x with the Arnoldi product's block-row code (face block sizes 4..24)
+hipError_t launch_block_product(const GmresArgs& a, const double* x, double* y,
+                                hipStream_t st);
 hipError_t launch_arnoldi_orth(const GmresArgs& a, int j, double* wnxt,
                                hipStream_t st);
 // jfin >= 0: the update first finishes column jfin (the last step of the

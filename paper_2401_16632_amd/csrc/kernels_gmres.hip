@@ -431,6 +431,40 @@ __global__ __launch_bounds__(256) void k_arnoldi_a(GmresArgs a, int j, int fin_p
     }
 }
 
+// ---- y = Lt x alone: the block-row product of the Arnoldi kernel A (same
+// decomposition, padded table, pass structure and order of additions),
+// without the Givens step, scaling and projections (inspection) ---------------
+template <typename TL, int BS>
+__global__ __launch_bounds__(256) void k_block_product(GmresArgs a, const double* x,
+                                                       double* y) {
+    const int f0 = blockIdx.x * a.fpbA, f1 = min(a.ntf, f0 + a.fpbA);
+    const int r0 = f0 * BS, r1 = f1 * BS;
+    const int part = threadIdx.x >> 6, lr = threadIdx.x & 63;
+    __shared__ double sacc[8][4][64];
+    const TL* Lt;
+    if constexpr (sizeof(TL) == 8) Lt = a.Lt64;
+    else Lt = a.Lt32;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int r = r0 + 64 * q + lr;
+        if (r0 + 64 * q >= r1) break;             // uniform
+        double acc = 0.0;
+        if (r < r1) {
+            int2 e1, e2;
+            ell_pair(a, r / BS, e1, e2);
+            acc = row_share_ell<TL, BS>(a, Lt, x, r, e1, e2);
+        }
+        sacc[q][part][lr] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int r = r0 + 64 * q + lr;
+        if (part == 0 && r < r1)
+            y[r] = sacc[q][0][lr] + sacc[q][1][lr] + sacc[q][2][lr] + sacc[q][3][lr];
+    }
+}
+
 // ---- B: first orthogonalisation, second projection ------------------------
 __global__ __launch_bounds__(kThr) void k_arnoldi_b(GmresArgs a, int j,
                                                     double* w) {
@@ -893,6 +927,25 @@ hipError_t launch_arnoldi_product(const GmresArgs& a, int j, int fin_prev,
         default: if (f64) HFR_AA(double, 0); else HFR_AA(float, 0); break;
     }
 #undef HFR_AA
+    return hipGetLastError();
+}
+
+hipError_t launch_block_product(const GmresArgs& a, const double* x, double* y,
+                                hipStream_t st) {
+    if (a.ntf == 0) return hipSuccess;
+    const bool f64 = a.Lt64 != nullptr;
+#define HFR_BP(TL, B)                                                                   \
+    hipLaunchKernelGGL((k_block_product<TL, B>), dim3(a.nblkA), dim3(256), 0, st, a, x, y)
+    switch (a.bs) {
+        case 4: if (f64) HFR_BP(double, 4); else HFR_BP(float, 4); break;
+        case 8: if (f64) HFR_BP(double, 8); else HFR_BP(float, 8); break;
+        case 12: if (f64) HFR_BP(double, 12); else HFR_BP(float, 12); break;
+        case 16: if (f64) HFR_BP(double, 16); else HFR_BP(float, 16); break;
+        case 20: if (f64) HFR_BP(double, 20); else HFR_BP(float, 20); break;
+        case 24: if (f64) HFR_BP(double, 24); else HFR_BP(float, 24); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef HFR_BP
     return hipGetLastError();
 }
 

@@ -363,124 +363,6 @@ hipError_t launch_spmv(int ntf, int bs, const int* rowptr, const int* col,
     return hipGetLastError();
 }
 
-__global__ void k_precond(int nrows, int bs, int pc, const void* inv,
-                          const double* x, double* y) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrows) return;
-    const int F = r / bs, aa = r - F * bs;
-    const size_t base = size_t(F) * bs * bs + aa;
-    const double* xb = x + size_t(F) * bs;
-    double acc = 0.0;
-    if (pc == HFR_PC_FP64) {
-        const double* m = reinterpret_cast<const double*>(inv);
-        for (int b = 0; b < bs; ++b) acc += m[base + size_t(b) * bs] * xb[b];
-    } else if (pc == HFR_PC_FP32) {
-        const float* m = reinterpret_cast<const float*>(inv);
-        for (int b = 0; b < bs; ++b) acc += double(m[base + size_t(b) * bs]) * xb[b];
-    } else {
-        const uint16_t* m = reinterpret_cast<const uint16_t*>(inv);
-        for (int b = 0; b < bs; ++b) acc += double(bf2f(m[base + size_t(b) * bs])) * xb[b];
-    }
-    y[r] = acc;
-}
-
-hipError_t launch_precond(int ntf, int bs, int pc, const void* inv,
-                          const double* x, double* y, hipStream_t st) {
-    const int nrows = ntf * bs;
-    if (nrows == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_precond, dim3(blocks_for(nrows)), dim3(kThreads), 0,
-                       st, nrows, bs, pc, inv, x, y);
-    return hipGetLastError();
-}
-
-// ---- Krylov helpers -------------------------------------------------------
-int multidot_blocks(int N) {
-    int b = (N + 4 * kThreads - 1) / (4 * kThreads);
-    if (b > 512) b = 512;
-    return b < 1 ? 1 : b;
-}
-
-__global__ void k_multidot_partial(int N, int k, const double* V, size_t ldv,
-                                   const double* w, double* partial) {
-    __shared__ double red[kThreads / 64];
-    const int nb = gridDim.x;
-    const int chunk = (N + nb - 1) / nb;
-    const int lo = blockIdx.x * chunk;
-    const int hi = min(N, lo + chunk);
-    for (int j = 0; j < k; ++j) {
-        double s = 0.0;
-        const double* vj = V + size_t(j) * ldv;
-        for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) s += vj[i] * w[i];
-        s = block_sum(s, red);
-        if (threadIdx.x == 0) partial[size_t(blockIdx.x) * k + j] = s;
-    }
-}
-
-__global__ void k_multidot_final(int k, int nblk, const double* partial,
-                                 double* out) {
-    const int j = blockIdx.x;
-    __shared__ double red[kThreads / 64];
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += partial[size_t(b) * k + j];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) out[j] = s;
-}
-
-hipError_t launch_multidot(int N, int k, const double* V, size_t ldv,
-                           const double* w, double* partial, int nblk,
-                           double* out, hipStream_t st) {
-    if (k == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_multidot_partial, dim3(nblk), dim3(kThreads), 0, st,
-                       N, k, V, ldv, w, partial);
-    hipLaunchKernelGGL(k_multidot_final, dim3(k), dim3(kThreads), 0, st, k,
-                       nblk, partial, out);
-    return hipGetLastError();
-}
-
-__global__ void k_multi_axpy(int N, int k, const double* V, size_t ldv,
-                             const double* coef, double* w, double sign) {
-    const long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    if (i >= N) return;
-    double acc = 0.0;
-    for (int j = 0; j < k; ++j) acc += coef[j] * V[size_t(j) * ldv + i];
-    w[i] += sign * acc;
-}
-
-hipError_t launch_multi_axpy(int N, int k, const double* V, size_t ldv,
-                             const double* coef, double* w, double sign,
-                             hipStream_t st) {
-    if (N == 0 || k == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_multi_axpy, dim3(blocks_for(N)), dim3(kThreads), 0,
-                       st, N, k, V, ldv, coef, w, sign);
-    return hipGetLastError();
-}
-
-__global__ void k_scale(int N, double* x, const double* src, double a) {
-    const long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    if (i < N) x[i] = a * src[i];
-}
-
-hipError_t launch_scale(int N, double* x, const double* src, double a,
-                        hipStream_t st) {
-    if (N == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scale, dim3(blocks_for(N)), dim3(kThreads), 0, st, N,
-                       x, src, a);
-    return hipGetLastError();
-}
-
-__global__ void k_axpy(int N, double a, const double* x, double* y) {
-    const long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    if (i < N) y[i] += a * x[i];
-}
-
-hipError_t launch_axpy(int N, double a, const double* x, double* y,
-                       hipStream_t st) {
-    if (N == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_axpy, dim3(blocks_for(N)), dim3(kThreads), 0, st, N, a,
-                       x, y);
-    return hipGetLastError();
-}
-
 __global__ void k_absmax_partial(int N, const double* x, double* partial) {
     __shared__ double red[kThreads];
     double m = 0.0;

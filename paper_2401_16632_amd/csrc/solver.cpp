@@ -47,7 +47,6 @@ struct hfr_solver_s {
     double* h = nullptr;     // [4][Nim][Np]
     double* gk = nullptr;    // [Nim][4][P][4]
     double* g = nullptr;     // [Ntp][4]
-    double* Rtmp = nullptr;  // [4][Nim][Np]
     double* ustar = nullptr; // [4][Nim][Np]
     double* du = nullptr;    // [4][Nim][Np]
     double* duhat = nullptr; // [N]
@@ -82,11 +81,7 @@ struct hfr_solver_s {
     bool verbose = false;
     int stage_calls = 0;
     double* V = nullptr;     // (restart+1) x N
-    double* z = nullptr;     // N
-    double* r = nullptr;     // N
     double* scratch = nullptr;  // partials
-    double* dots = nullptr;  // small device vector
-    double* coef = nullptr;
     int* go = nullptr;       // 1 while the Newton residual is above tolerance
     double* dscale = nullptr;  // max |u*| of the stage solve (scales its tolerance)
     double* hpin = nullptr;  // pinned, device-mapped host buffer (kPinDoubles):
@@ -95,8 +90,12 @@ struct hfr_solver_s {
     double* dpin = nullptr;  // the same buffer's device address
     long long seq_norms = 0;     // last sequence number queued for the norms
     long long seq_gmres = 0;     // ... and for the GMRES state
-    size_t ws_bytes = 0;
-    int nblk_dot = 1;
+    size_t ws_bytes = 0;     // working buffers (one block, carved)
+    size_t table_bytes = 0;  // library-owned read-only device tables
+    struct WsItem { void** ptr; size_t bytes; };
+    std::vector<WsItem> ws_items;
+    void* ws_owned = nullptr;   // the block, when the library allocated it
+    bool ws_bound = false;
     // event timers (categories in tmask)
     bool timing = false;
     unsigned tmask = 0;
@@ -170,14 +169,39 @@ void free_solver(hfr_solver_s* s) {
         (void)hipEventDestroy(p.second);
     }
     s->pool.clear();
-    void* ptrs[] = {s->M, s->blocks_copy, s->h, s->gk, s->g, s->Rtmp,
-                    s->ustar, s->du, s->duhat, s->rowptr, s->col, s->ell, s->contrib,
-                    s->tside, s->diag_blk, s->L64, s->L32, s->t, s->Dinv,
-                    s->flags, s->V, s->z, s->r, s->scratch, s->dots, s->coef,
-                    s->Lt64, s->Lt32, s->W, s->gs, s->part, s->part2,
-                    s->counters, s->piv, s->yr, s->zz, s->part3,
-                    s->efr_cptr, s->efr_contrib, s->go, s->dscale};
+    void* ptrs[] = {s->rowptr, s->col, s->ell, s->contrib, s->tside, s->diag_blk,
+                    s->efr_cptr, s->efr_contrib, s->ws_owned};
     for (void* p : ptrs) (void)hipFree(p);
+}
+
+template <class T>
+void plan(hfr_solver_s* s, T** p, size_t count) {
+    s->ws_items.push_back({reinterpret_cast<void**>(p), count * sizeof(T)});
+}
+
+constexpr size_t ws_align(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Carves the working buffers from `base` (256-byte aligned pieces in plan
+// order) and clears the state the kernels expect to start at zero.
+fr_status bind_internal(hfr_solver_s* s, char* base) {
+    size_t off = 0;
+    for (auto& it : s->ws_items) {
+        *it.ptr = it.bytes ? base + off : nullptr;
+        off += ws_align(it.bytes);
+    }
+    if (hipMemset(s->flags, 0, 8) != hipSuccess ||
+        hipMemset(s->counters, 0, 16) != hipSuccess ||
+        hipMemset(s->gs, 0, sizeof(GmresState)) != hipSuccess)
+        return fail(FR_E_DEVICE, "clearing the solver workspace failed");
+    s->have_factors = false;
+    s->ws_bound = true;
+    return FR_OK;
+}
+
+fr_status need_workspace(const hfr_solver_s* s) {
+    return s->ws_bound ? FR_OK
+                       : fail(FR_E_INVALID, "solver workspace not bound "
+                                            "(hfr_solver_bind_workspace)");
 }
 
 constexpr int kPinDoubles = 64;
@@ -413,20 +437,6 @@ fr_status recondense_rhs_internal(hfr_solver_s* s, hipStream_t st) {
     const int tk = tbegin(s, HFR_T_ASSEMBLE, st);
     HIP_TRY(launch_assemble(a, st));
     tend(s, tk, st);
-    return FR_OK;
-}
-
-fr_status host_dots(hfr_solver_s* s, int k, const double* V, size_t ldv,
-                    const double* w, double* out_dev, double* host,
-                    hipStream_t st) {
-    HIP_TRY(launch_multidot(s->N, k, V, ldv, w, s->scratch, s->nblk_dot,
-                            out_dev, st));
-    if (host) {
-        HIP_TRY(hipMemcpyAsync(host, out_dev, sizeof(double) * k,
-                               hipMemcpyDeviceToHost, st));
-        fr_status e = sync_check(st);
-        if (e) return e;
-    }
     return FR_OK;
 }
 
@@ -684,7 +694,8 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
     if (o->gmres_restart < 1 || o->gmres_restart > kGmresMaxK - 1)
         return fail(FR_E_INVALID, "gmres_restart must be in 1..64");
     if (o->newton_max_iters < 0 || !(o->newton_tol > 0.0) || !(o->gmres_rtol > 0.0) ||
-        o->jacobian_lag < 0 || o->gmres_cgs_passes < 0 || o->gmres_cgs_passes > 2)
+        o->jacobian_lag < 0 || o->gmres_cgs_passes < 0 || o->gmres_cgs_passes > 2 ||
+        (o->caller_workspace != 0 && o->caller_workspace != 1))
         return fail(FR_E_INVALID, "bad tolerance or iteration cap");
     auto s = new hfr_solver_s();
     s->mesh = mesh;
@@ -769,23 +780,13 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
             ell[2 * i] = p;
             ell[2 * i + 1] = col[p];
         }
-    size_t& tot = s->ws_bytes;
+    size_t& tot = s->table_bytes;
     const size_t scal = o->precision == HFR_PREC_FP64 ? 8 : 4;
     const size_t nimp = size_t(m->Nim), np4 = 4 * size_t(m->Np);
     const size_t bb = size_t(s->bs) * s->bs;
     fr_status e;
-    char* Mraw = nullptr;
-    if ((e = dalloc(&Mraw, nimp * s->elem_M * scal, tot)) ||
-        (o->keep_blocks &&
-         (e = dalloc(&s->blocks_copy, nimp * size_t(s->n + s->m) * (s->n + s->m), tot))) ||
-        (e = dalloc(&s->h, nimp * np4, tot)) ||
-        (e = dalloc(&s->gk, nimp * 16 * P, tot)) ||
-        (e = dalloc(&s->g, size_t(s->N), tot)) ||
-        (e = dalloc(&s->Rtmp, nimp * np4, tot)) ||
-        (e = dalloc(&s->ustar, nimp * np4, tot)) ||
-        (e = dalloc(&s->du, nimp * np4, tot)) ||
-        (e = dalloc(&s->duhat, size_t(s->N), tot)) ||
-        (e = dalloc(&s->rowptr, rowptr.size(), tot)) ||
+    // read-only tables: library-owned
+    if ((e = dalloc(&s->rowptr, rowptr.size(), tot)) ||
         (e = dalloc(&s->col, col.size(), tot)) ||
         (e = dalloc(&s->ell, ell.size(), tot)) ||
         (e = dalloc(&s->contrib, contrib.size(), tot)) ||
@@ -793,47 +794,53 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
         (e = dalloc(&s->efr_cptr, m->efr ? ecptr.size() : 0, tot)) ||
         (e = dalloc(&s->efr_contrib, econtrib.size(), tot)) ||
         (e = dalloc(&s->diag_blk, diag.size(), tot)) ||
-        (o->precision == HFR_PREC_FP64 && (e = dalloc(&s->L64, size_t(s->nblocks) * bb, tot))) ||
-        (o->precision == HFR_PREC_FP32 && (e = dalloc(&s->L32, size_t(s->nblocks) * bb, tot))) ||
-        (o->precision == HFR_PREC_FP64 && (e = dalloc(&s->Lt64, size_t(s->nblocks) * bb, tot))) ||
-        (o->precision == HFR_PREC_FP32 && (e = dalloc(&s->Lt32, size_t(s->nblocks) * bb, tot))) ||
-        (e = dalloc(&s->W, 2 * size_t(std::max(1, s->N)), tot)) ||
-        (e = dalloc(reinterpret_cast<char**>(&s->gs), sizeof(GmresState), tot)) ||
-        (e = dalloc(&s->part, size_t(std::max(256, s->nbr / std::max(1, 2048 / s->bs) + 1)) * kGmresMaxK, tot)) ||
-        (e = dalloc(&s->part2, size_t(std::max(256, s->nbr / std::max(1, 2048 / s->bs) + 1)) * kGmresMaxK, tot)) ||
-        (e = dalloc(&s->part3, size_t(std::max(1024, s->nbr + 1)) * kGmresMaxK, tot)) ||
-        (e = dalloc(&s->counters, 4, tot)) ||
-        (e = dalloc(&s->piv, nimp * size_t(s->n), tot)) ||
-        (e = dalloc(&s->yr, nimp * size_t(s->n), tot)) ||
-        (e = dalloc(&s->zz, nimp * size_t(s->m), tot)) ||
-        (e = dalloc(&s->t, size_t(s->N), tot)) ||
-        (e = dalloc(reinterpret_cast<char**>(&s->Dinv),
-                    size_t(s->nbr) * bb * (o->precond == HFR_PC_FP64 ? 8 : o->precond == HFR_PC_FP32 ? 4 : 2),
-                    tot)) ||
-        (e = dalloc(&s->flags, 2, tot)) ||
-        (e = dalloc(&s->V, size_t(s->restart + 1) * std::max(1, s->N), tot)) ||
-        (e = dalloc(&s->z, size_t(std::max(1, s->N)), tot)) ||
-        (e = dalloc(&s->r, size_t(std::max(1, s->N)), tot)) ||
-        (e = dalloc(&s->scratch, size_t(4096) * 66, tot)) ||
-        (e = dalloc(&s->dots, 256, tot)) ||
-        (e = dalloc(&s->coef, 128, tot)) ||
-        (e = dalloc(&s->go, 1, tot)) ||
-        (e = dalloc(&s->dscale, 1, tot)) ||
         (e = (hipHostMalloc(reinterpret_cast<void**>(&s->hpin), kPinDoubles * sizeof(double),
                             hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
                       hipHostGetDevicePointer(reinterpret_cast<void**>(&s->dpin), s->hpin, 0) ==
                           hipSuccess
                   ? FR_OK
                   : fail(FR_E_NOMEM, "pinned readback buffer: hipHostMalloc or "
-                                     "hipHostGetDevicePointer failed"))) ||
-        (e = (std::memset(s->hpin, 0, kPinDoubles * sizeof(double)), FR_OK))) {
-        s->M = Mraw;
+                                     "hipHostGetDevicePointer failed")))) {
         free_solver(s);
         delete s;
         return e;
     }
-    s->M = Mraw;
-    s->nblk_dot = multidot_blocks(std::max(1, s->N));
+    std::memset(s->hpin, 0, kPinDoubles * sizeof(double));
+    // working buffers: one block, carved in this order
+    plan(s, reinterpret_cast<char**>(&s->M), nimp * s->elem_M * scal);
+    if (o->keep_blocks) plan(s, &s->blocks_copy, nimp * size_t(s->n + s->m) * (s->n + s->m));
+    plan(s, &s->h, nimp * np4);
+    plan(s, &s->gk, nimp * 16 * P);
+    plan(s, &s->g, size_t(s->N));
+    plan(s, &s->ustar, nimp * np4);
+    plan(s, &s->du, nimp * np4);
+    plan(s, &s->duhat, size_t(s->N));
+    if (o->precision == HFR_PREC_FP64) {
+        plan(s, &s->L64, size_t(s->nblocks) * bb);
+        plan(s, &s->Lt64, size_t(s->nblocks) * bb);
+    } else {
+        plan(s, &s->L32, size_t(s->nblocks) * bb);
+        plan(s, &s->Lt32, size_t(s->nblocks) * bb);
+    }
+    plan(s, &s->W, 2 * size_t(std::max(1, s->N)));
+    plan(s, reinterpret_cast<char**>(&s->gs), sizeof(GmresState));
+    plan(s, &s->part, size_t(std::max(256, s->nbr / std::max(1, 2048 / s->bs) + 1)) * kGmresMaxK);
+    plan(s, &s->part2, size_t(std::max(256, s->nbr / std::max(1, 2048 / s->bs) + 1)) * kGmresMaxK);
+    plan(s, &s->part3, size_t(std::max(1024, s->nbr + 1)) * kGmresMaxK);
+    plan(s, &s->counters, 4);
+    plan(s, &s->piv, nimp * size_t(s->n));
+    plan(s, &s->yr, nimp * size_t(s->n));
+    plan(s, &s->zz, nimp * size_t(s->m));
+    plan(s, &s->t, size_t(s->N));
+    plan(s, reinterpret_cast<char**>(&s->Dinv),
+         size_t(s->nbr) * bb * (o->precond == HFR_PC_FP64 ? 8 : o->precond == HFR_PC_FP32 ? 4 : 2));
+    plan(s, &s->flags, 2);
+    plan(s, &s->V, size_t(s->restart + 1) * std::max(1, s->N));
+    plan(s, &s->scratch, size_t(4096) * 66);
+    plan(s, &s->go, 1);
+    plan(s, &s->dscale, 1);
+    s->ws_bytes = 0;
+    for (auto& it : s->ws_items) s->ws_bytes += ws_align(it.bytes);
     s->verbose = std::getenv("HFR_VERBOSE") != nullptr;
     s->fpb = 256 / s->bs;
     s->gblk = std::max(1, (s->nbr + s->fpb - 1) / s->fpb);
@@ -856,16 +863,41 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
         up(s->diag_blk, diag) != hipSuccess ||
         (m->efr && up(s->efr_cptr, ecptr) != hipSuccess) ||
         up(s->efr_contrib, econtrib) != hipSuccess ||
-        hipMemset(s->flags, 0, 8) != hipSuccess ||
-        hipMemset(s->counters, 0, 16) != hipSuccess ||
-        hipMemset(s->gs, 0, sizeof(GmresState)) != hipSuccess) {
+        false) {
         free_solver(s);
         delete s;
         return fail(FR_E_DEVICE, "upload of solver tables failed");
     }
-    if (ws) *ws = tot;
+    if (!o->caller_workspace) {
+        if (hipMalloc(&s->ws_owned, std::max<size_t>(256, s->ws_bytes)) != hipSuccess) {
+            s->ws_owned = nullptr;
+            free_solver(s);
+            delete s;
+            return fail(FR_E_NOMEM, "hipMalloc of the solver workspace failed (" +
+                                        std::to_string(s->ws_bytes) + " bytes)");
+        }
+        if ((e = bind_internal(s, static_cast<char*>(s->ws_owned)))) {
+            free_solver(s);
+            delete s;
+            return e;
+        }
+    }
+    if (ws) *ws = s->ws_bytes;
     *out = s;
     return FR_OK;
+}
+
+extern "C" fr_status hfr_solver_bind_workspace(hfr_solver_t s, void* dev_ptr,
+                                               size_t bytes) {
+    if (!s || !dev_ptr) return fail(FR_E_INVALID, "null argument");
+    if (!s->opts.caller_workspace)
+        return fail(FR_E_INVALID, "solver owns its workspace (caller_workspace = 0)");
+    if (reinterpret_cast<uintptr_t>(dev_ptr) % 256)
+        return fail(FR_E_INVALID, "workspace must be 256-byte aligned");
+    if (bytes < s->ws_bytes)
+        return fail(FR_E_INVALID, "workspace too small: " + std::to_string(bytes) + " < " +
+                                      std::to_string(s->ws_bytes) + " bytes");
+    return bind_internal(s, static_cast<char*>(dev_ptr));
 }
 
 extern "C" void hfr_solver_destroy(hfr_solver_t s) {
@@ -880,6 +912,7 @@ extern "C" fr_status hfr_residual(hfr_solver_t s, const double* u,
                                   double* R_im, void* stream) {
     if (!s || !u || (!uhat && s->mesh->Ntp) || !ustar)
         return fail(FR_E_INVALID, "null argument");
+    if (fr_status ew = need_workspace(s)) return ew;
     hipStream_t st = hipStream_t(stream);
     fr_mesh_s* m = s->mesh;
     fr_status e = residual_internal(s, u, uhat, ustar, aii_dt, R_im, st);
@@ -899,6 +932,7 @@ extern "C" fr_status hfr_assemble_condense(hfr_solver_t s, const double* u,
                                            void* stream) {
     if (!s || !u || (!uhat && s->mesh->Ntp) || !ustar)
         return fail(FR_E_INVALID, "null argument");
+    if (fr_status ew = need_workspace(s)) return ew;
     hipStream_t st = hipStream_t(stream);
     fr_status e = residual_internal(s, u, uhat, ustar, aii_dt, nullptr, st);
     if (e) return e;
@@ -910,6 +944,7 @@ extern "C" fr_status hfr_assemble_condense(hfr_solver_t s, const double* u,
 extern "C" fr_status hfr_trace_solve(hfr_solver_t s, double* duhat,
                                      hfr_solve_stats* stats, void* stream) {
     if (!s || (!duhat && s->N)) return fail(FR_E_INVALID, "null argument");
+    if (fr_status ew = need_workspace(s)) return ew;
     return gmres(s, duhat, stats, hipStream_t(stream));
 }
 
@@ -917,6 +952,7 @@ extern "C" fr_status hfr_recover(hfr_solver_t s, const double* duhat,
                                  double* du, void* stream) {
     if (!s || (!duhat && s->N) || (!du && s->mesh->Nim))
         return fail(FR_E_INVALID, "null argument");
+    if (fr_status ew = need_workspace(s)) return ew;
     fr_mesh_s* m = s->mesh;
     HIP_TRY(launch_recover(m->ops, m->efr, m->Nim, s->M, s->opts.precision, s->piv, s->yr,
                            m->d_trace_map, duhat, du, hipStream_t(stream)));
@@ -926,6 +962,7 @@ extern "C" fr_status hfr_recover(hfr_solver_t s, const double* duhat,
 extern "C" fr_status hfr_trace_matvec(hfr_solver_t s, const double* x,
                                       double* y, void* stream) {
     if (!s || (s->N && (!x || !y))) return fail(FR_E_INVALID, "null argument");
+    if (fr_status ew = need_workspace(s)) return ew;
     fr_mesh_s* m = s->mesh;
     HIP_TRY(launch_spmv(s->nbr, s->bs, s->rowptr, s->col, s->L64,
                         s->L64 ? nullptr : s->L32, x, y, 1.0, nullptr,
@@ -933,9 +970,19 @@ extern "C" fr_status hfr_trace_matvec(hfr_solver_t s, const double* x,
     return FR_OK;
 }
 
+extern "C" fr_status hfr_trace_product(hfr_solver_t s, const double* x, double* y,
+                                       void* stream) {
+    if (!s || (s->N && (!x || !y))) return fail(FR_E_INVALID, "null argument");
+    if (fr_status ew = need_workspace(s)) return ew;
+    if (s->N == 0) return FR_OK;
+    HIP_TRY(launch_block_product(gmres_args(s), x, y, hipStream_t(stream)));
+    return FR_OK;
+}
+
 extern "C" fr_status hfr_get_system(hfr_solver_t s, double* t, double* h,
                                     double* g, void* stream) {
     if (!s) return fail(FR_E_INVALID, "null solver");
+    if (fr_status ew = need_workspace(s)) return ew;
     fr_mesh_s* m = s->mesh;
     hipStream_t st = hipStream_t(stream);
     if (t && s->N) HIP_TRY(hipMemcpyAsync(t, s->t, 8 * size_t(s->N), hipMemcpyDeviceToDevice, st));
@@ -949,6 +996,7 @@ extern "C" fr_status hfr_get_system(hfr_solver_t s, double* t, double* h,
 extern "C" fr_status hfr_get_blocks(hfr_solver_t s, double* blocks,
                                     void* stream) {
     if (!s || !blocks) return fail(FR_E_INVALID, "null argument");
+    if (fr_status ew = need_workspace(s)) return ew;
     if (!s->blocks_copy) return fail(FR_E_INVALID, "solver created without keep_blocks");
     fr_mesh_s* m = s->mesh;
     const size_t nb = size_t(m->Nim) * (s->n + s->m) * (s->n + s->m) * 8;
@@ -960,6 +1008,7 @@ extern "C" fr_status hfr_get_blocks(hfr_solver_t s, double* blocks,
 extern "C" fr_status hfr_get_factors(hfr_solver_t s, void* factors,
                                      int32_t* piv, void* stream) {
     if (!s || !factors) return fail(FR_E_INVALID, "null argument");
+    if (fr_status ew = need_workspace(s)) return ew;
     fr_mesh_s* m = s->mesh;
     const size_t scal = s->opts.precision == HFR_PREC_FP64 ? 8 : 4;
     hipStream_t st = hipStream_t(stream);
@@ -976,6 +1025,7 @@ extern "C" fr_status hfr_get_factors(hfr_solver_t s, void* factors,
 extern "C" fr_status hfr_get_preconditioner(hfr_solver_t s, void* dinv,
                                             void* stream) {
     if (!s || !dinv) return fail(FR_E_INVALID, "null argument");
+    if (fr_status ew = need_workspace(s)) return ew;
     fr_mesh_s* m = s->mesh;
     const int pc = s->opts.precond;
     const size_t scal = pc == HFR_PC_FP64 ? 8 : pc == HFR_PC_FP32 ? 4 : 2;
@@ -992,9 +1042,6 @@ extern "C" fr_status imex_stage(fr_mesh_t mesh, hfr_solver_t s,
     if (!mesh || !tab || !stt || !stt->u_n || !stt->u)
         return fail(FR_E_INVALID, "null argument");
     fr_mesh_s* m = mesh;
-    if (m->host_only) return fail(FR_E_INVALID, "host-only mesh");
-    if (m->Nim && (!s || s->mesh != mesh))
-        return fail(FR_E_INVALID, "a solver of this mesh is required");
     const int S = tab->s;
     if (S < 1 || S > 4) return fail(FR_E_INVALID, "tableau stages must be 1..4");
     if (stage < 0 || stage > S + 1) return fail(FR_E_INVALID, "stage out of range");
@@ -1002,6 +1049,21 @@ extern "C" fr_status imex_stage(fr_mesh_t mesh, hfr_solver_t s,
         return fail(FR_E_INVALID, "missing stage buffers");
     hipStream_t st = hipStream_t(stream);
     const size_t pex = 4 * size_t(m->Nex) * m->Np, pim = 4 * size_t(m->Nim) * m->Np;
+    {
+        // every stage reads u_n after u (and the stage buffers) were written
+        const size_t nall = 4 * size_t(m->Ne) * m->Np;
+        auto overlaps = [&](const double* b, size_t nb) {
+            return b && nb && stt->u_n < b + nb && b < stt->u_n + nall;
+        };
+        if (overlaps(stt->u, nall) || overlaps(stt->uhat, 4 * size_t(m->Ntp)) ||
+            overlaps(stt->R_im, size_t(S) * pim) || overlaps(stt->R_ex, size_t(S + 1) * pex))
+            return fail(FR_E_INVALID, "u_n overlaps u, uhat, R_im or R_ex");
+    }
+    if (m->host_only) return fail(FR_E_INVALID, "host-only mesh");
+    if (m->Nim && (!s || s->mesh != mesh))
+        return fail(FR_E_INVALID, "a solver of this mesh is required");
+    if (m->Nim)
+        if (fr_status ew = need_workspace(s)) return ew;
     if (stats) *stats = hfr_newton_stats{};
     if (stage == 0) {
         HIP_TRY(hipMemcpyAsync(stt->u, stt->u_n, 8 * 4 * size_t(m->Ne) * m->Np,
@@ -1040,6 +1102,11 @@ extern "C" fr_status imex_stage(fr_mesh_t mesh, hfr_solver_t s,
                                terms, coefs, stt->u, 1, st));
     }
     if (m->Nim) {
+        // the implicit stage's wall time runs from here (queued work
+        // drained) to R_i ready: u*, the initial trace, Newton and R_i
+        fr_status e = sync_check(st);
+        if (e) return e;
+        const auto t0 = std::chrono::steady_clock::now();
         const double* terms[6];
         double coefs[6];
         for (int j = 0; j < I - 1; ++j) {
@@ -1056,26 +1123,51 @@ extern "C" fr_status imex_stage(fr_mesh_t mesh, hfr_solver_t s,
         else
             HIP_TRY(launch_trace_average_ops(m->ops, m->Ntp, m->Ne, m->d_tpside,
                                              m->d_imp, stt->u, stt->uhat, st));
-        fr_status e = sync_check(st);
-        if (e) return e;
-        auto t0 = std::chrono::steady_clock::now();
         hfr_newton_stats ns{};
         e = newton(s, stt->u, stt->uhat, s->ustar, aii_dt, &ns, st);
-        fr_status e2 = sync_check(st);
+        if (!e)
+            e = residual_internal(s, stt->u, stt->uhat, s->ustar, aii_dt,
+                                  stt->R_im + (I - 1) * pim, st);
+        const fr_status e2 = sync_check(st);
         ns.implicit_ms = std::chrono::duration<double, std::milli>(
                              std::chrono::steady_clock::now() - t0).count();
         if (stats) *stats = ns;
         if (e) return e;
         if (e2) return e2;
-        fr_status e3 = residual_internal(s, stt->u, stt->uhat, s->ustar, aii_dt,
-                                         stt->R_im + (I - 1) * pim, st);
-        if (e3) return e3;
     }
     int tk = tbegin(s, HFR_T_EXPLICIT, st);
     fr_status ex = fr_explicit_rhs(mesh, stt->u, stt->R_ex + I * pex, stream);
     tend(s, tk, st);
     if (s && s->pending.size() > 4096) tflush(s);
     return ex;
+}
+
+extern "C" fr_status imex_tableau_get(int32_t id, imex_tableau* out) {
+    if (!out) return fail(FR_E_INVALID, "null tableau");
+    if (id != IMEX_HIMEX2C && id != IMEX_ARS222)
+        return fail(FR_E_INVALID, "unknown tableau id");
+    *out = imex_tableau{};
+    // implicit part: the SDIRK2 tableau of Section 3.1
+    const double g = 1.0 - std::sqrt(0.5);
+    out->s = 2;
+    out->A[0] = g;
+    out->A[2] = 1.0 - g;
+    out->A[3] = g;
+    out->b[0] = 1.0 - g;
+    out->b[1] = g;
+    // explicit partner in the padded form (c_bar = [0 c]), second order
+    const double d = 1.0 - 1.0 / (2.0 * g);
+    out->Abar[1 * 3 + 0] = g;
+    out->Abar[2 * 3 + 0] = d;
+    out->Abar[2 * 3 + 1] = 1.0 - d;
+    if (id == IMEX_HIMEX2C) {
+        out->bbar[1] = out->b[0];
+        out->bbar[2] = out->b[1];
+    } else {
+        out->bbar[0] = d;
+        out->bbar[1] = 1.0 - d;
+    }
+    return FR_OK;
 }
 
 extern "C" fr_status hfr_timing(hfr_solver_t s, int32_t enable, double* ms,

@@ -1,6 +1,7 @@
 """CPU checks of the C-ABI library: it loads, exports every declared entry
 point, and its host-side mesh logic (skeleton, partition, trace map,
 stiffness indicator) matches the oracle bit for bit."""
+import ctypes
 import os
 import re
 
@@ -102,3 +103,50 @@ def test_efr_node_map_bit_exact_vs_oracle(case, p):
     assert hm.efr and hm.info["n_trace_points"] == tr.Nn
     assert hm.info["n_trace_faces"] == om.Ntf
     assert np.array_equal(hm.maps()["trace_map"], tr.elem_nodes)
+
+
+@pytest.mark.parametrize("name", ["HIMEX2C", "ARS222"])
+def test_library_tableau_matches_oracle(name):
+    """imex_tableau_get returns the oracle's pair (whose order conditions and
+    conservation property are pinned in test_oracle_imex.py)."""
+    from oracle import imex as oimex
+    t = hp.tableau(name)
+    o = oimex.TABLEAUS[name]()
+    s = o.s
+    assert t.s == s
+    assert np.allclose(np.array(t.A[:s * s]).reshape(s, s), o.A, rtol=0, atol=1e-16)
+    assert np.allclose(np.array(t.b[:s]), o.b, rtol=0, atol=1e-16)
+    assert np.allclose(np.array(t.Abar[:(s + 1) ** 2]).reshape(s + 1, s + 1), o.Abar,
+                       rtol=0, atol=1e-16)
+    assert np.allclose(np.array(t.bbar[:s + 1]), o.bbar, rtol=0, atol=1e-16)
+    lib = hp.load_library()
+    assert lib.imex_tableau_get(7, ctypes.byref(_abi.ImexTableau())) == -1
+
+
+def test_imex_stage_rejects_u_n_overlapping_the_stage_buffers():
+    """u_n is read by every stage after u and the stage buffers are written,
+    so an overlap is refused before any device work (the addresses below are
+    never dereferenced)."""
+    d, mask = c1_desc(n=4)
+    hm = hp.Mesh(d, 2, implicit_mask=mask, host_only=True)
+    lib = hp.load_library()
+    tab = hp.tableau("HIMEX2C")
+    nall = 4 * hm.Ne * hm.Np * 8
+    base = 1 << 40
+
+    def call(u_n, u, uhat, rim, rex):
+        st = _abi.ImexState(u_n, u, uhat, rim, rex)
+        ns = _abi.HfrNewtonStats()
+        rc = lib.imex_stage(hm.handle, None, ctypes.byref(tab), 1, 0.01,
+                            ctypes.byref(st), ctypes.byref(ns), None)
+        return rc, lib.fr_last_error().decode()
+
+    far = [base + k * (1 << 32) for k in range(1, 5)]
+    rc, msg = call(base, base + nall - 8, *far[1:])
+    assert rc == -1 and "overlaps" in msg
+    rc, msg = call(base, far[0], base + 16, far[2], far[3])
+    assert rc == -1 and "overlaps" in msg
+    rc, msg = call(far[3] + 8, far[0], far[1], far[2], far[3])
+    assert rc == -1 and "overlaps" in msg
+    rc, msg = call(base, *far)
+    assert rc == -1 and "host-only" in msg

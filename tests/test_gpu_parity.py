@@ -209,6 +209,14 @@ def test_condense_solve_recover(name, passes):
     Lx = sysd["L"] @ x
     assert np.abs(host(y) - Lx).max() <= 1e-11 * max(1, np.abs(Lx).max())
     assert np.abs(host(t) - sysd["t"]).max() <= 1e-11 * max(1, np.abs(sysd["t"]).max())
+    # the product the Krylov solver runs, L D^-1 x, with the solver's own
+    # block inverses (checked against the oracle's blocks elsewhere)
+    X = s.get_preconditioner().cpu().numpy()
+    bs = X.shape[1]
+    s.product(dev(x), y)
+    torch.cuda.synchronize()
+    LDx = sysd["L"] @ np.einsum("fab,fb->fa", X, x.reshape(-1, bs)).ravel()
+    assert np.abs(host(y) - LDx).max() <= 1e-11 * max(1, np.abs(LDx).max())
     duh = torch.zeros(N, dtype=torch.float64, device="cuda")
     st = s.trace_solve(duh, allow_unconverged=True)
     duh_o = onw.trace_solve(sysd["L"], sysd["t"])
@@ -343,3 +351,37 @@ def test_timing_categories():
     assert np.array_equal(a, b)
     lib = hp.load_library()
     assert lib.hfr_timing(s.handle, 7, None, None) != 0      # neither 0, 1 nor a selection
+
+
+_ORACLE_STEPS = {}
+
+
+@pytest.mark.parametrize("name,pc", [("cyl_p4", "fp32"), ("cyl_p4", "bf16"),
+                                     ("c1_p5", "fp32"), ("c1_p5", "bf16")])
+def test_imex_steps_fp32_condensation_high_order(name, pc):
+    """The precision form at p = 4 (the 24x8 cylinder at the local-CFL time
+    step) and p = 5 (the vortex case): FP32 element tableaux with an FP32 or
+    a BF16 block-Jacobi preconditioner, FP64 residuals, Newton and Arnoldi;
+    two IMEX steps match the FP64 oracle within 1e-8 after each step."""
+    pr, u = _build(name)
+    if name.startswith("c1"):
+        u = fi.isentropic_vortex(pr.om.x, pr.om.y)
+        dt = 0.01
+    else:
+        dt = _cfl_dt(pr)
+    hm = pr.hm
+    if name not in _ORACLE_STEPS:
+        uo, seq = u.copy(), []
+        for _ in range(2):
+            uo, _ = oimex.imex_step(pr.om, pr.ph, oimex.himex2c(), uo, dt, tol=1e-13)
+            seq.append(uo)
+        _ORACLE_STEPS[name] = seq
+    s = hp.Solver(hm, precision="fp32", precond=pc, rtol=1e-10, newton_tol=1e-13,
+                  max_iters=3000)
+    stp = hp.ImexStepper(hm, s, "HIMEX2C")
+    ud = dev(soa(u))
+    for k in range(2):
+        un, stats = stp.step(ud, dt)
+        ud = un.clone()
+        err = rel_err(unsoa(host(ud), hm.Ne, pr.P), _ORACLE_STEPS[name][k])
+        assert err <= 1e-8, (k, err, stats)

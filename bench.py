@@ -5,8 +5,11 @@ A step is one IMEX step (alg:imex): three explicit FR residuals and two
 hybridized implicit stages, each solved by Newton with element-block
 condensation, a GMRES trace solve and local recovery.  The metric is the
 implicit-stage throughput: implicit DOF (N_im * Np * 4) per second of
-implicit-stage wall time, averaged over the timed stages, for the FP32
-condensation form (``value``) next to the FP64 form on the same workload.
+implicit-stage wall time (from the stage's entry to R_i ready: u*, the
+initial trace, every Newton iteration and R_i), averaged over the timed
+stages, for the FP32 condensation form with an FP32 block-Jacobi
+preconditioner (``value``), next to the same form with a BF16
+preconditioner and the FP64 form on the same workload.
 
 Prints ONE JSON line.  Only one GPU is supported.
 """
@@ -33,9 +36,12 @@ def cylinder_workload(name):
     import fr_inputs as fi
     if name == "c2":
         n_theta, n_r, p, first, ratio = 128, 64, 3, 1e-4, 1.15
-    elif name == "c3":
-        n_theta, n_r, p, first = 256, 128, 4, 1e-4
-        gap = first * (1.15 ** 64 - 1.0) / 0.15      # same outer radius as c2
+    elif name in ("c3", "c3_small"):
+        # p = 4 with the outer radius of c2; c3_small is a 64x20 mesh of the
+        # same radii that the CPU oracle solves within a test
+        n_theta, n_r = (256, 128) if name == "c3" else (64, 20)
+        p, first = 4, 1e-4
+        gap = first * (1.15 ** 64 - 1.0) / 0.15
         ratio = fi.ogrid_ratio_for_outer(n_r, first, gap)
     else:
         raise ValueError(name)
@@ -45,9 +51,9 @@ def cylinder_workload(name):
 
 def describe(name):
     d, p, nt, nr, first, ratio = cylinder_workload(name)
-    return (f"2D Euler, circular cylinder O-grid {nt}x{nr} quads, p={p}, "
-            f"first cell {first:g} D, ratio {ratio:.4f}, Mach {MACH}, "
-            f"implicit = local CFL > 1 (IF ~ 0.2), HIMEX2C pair")
+    return (f"2D Euler (viscous terms not built), circular cylinder O-grid "
+            f"{nt}x{nr} quads, p={p}, first cell {first:g} D, ratio {ratio:.4f}, "
+            f"Mach {MACH}, implicit = local CFL > 1 (IF ~ 0.2), HIMEX2C pair")
 
 
 def build_case(hp, name, if_target=0.2, seed=2, efr=False, physics="euler"):
@@ -110,19 +116,53 @@ def run_form(hp, torch, mesh, u0, dt, precision, precond, steps, warmup,
     wall = time.perf_counter() - t0
     timers = solver.timing(False)
     out = u.cpu().numpy()
+
+    def timed_pass(only):
+        if only is None:
+            solver.timing(True)
+        else:
+            solver.timing(only=only)
+        uu = u.clone()
+        for _ in range(min(3, steps)):
+            un, _ = stp.step(uu, dt)
+            uu = un.clone()
+        torch.cuda.synchronize()
+        return solver.timing(False)
+    # the bandwidth-bound kernels, each timed alone (events around its own
+    # launches only): explicit residual (K2) and the Arnoldi product (K8)
+    hbm = {k: timed_pass([k]) [k] for k in ("explicit", "spmv")}
     # phase breakdown from a separate, fully instrumented pass
-    solver.timing(True)
-    uu = u.clone()
-    for _ in range(min(3, steps)):
-        un, _ = stp.step(uu, dt)
-        uu = un.clone()
-    torch.cuda.synchronize()
-    phases = solver.timing(False)
+    phases = timed_pass(None)
     res = dict(wall_s=wall, impl_ms=impl_ms, newton=newton, gmres=gmres,
-               timers=timers, phases=phases, state=out, nblocks=None,
+               timers=timers, phases=phases, hbm=hbm, state=out,
                workspace=solver.workspace_bytes)
     solver.close()
     return res
+
+
+def first_stage(hp, torch, mesh, u0, dt, precision, precond, newton_tol):
+    """State and trace after the first implicit stage of a step (stages 0
+    and 1 of imex_stage), for the comparison with the oracle."""
+    import ctypes
+    from paper_2401_16632_amd import _abi
+    solver = hp.Solver(mesh, precision=precision, precond=precond, restart=30,
+                       max_iters=3000, rtol=1e-10, newton_max_iters=30,
+                       newton_tol=newton_tol)
+    stp = hp.ImexStepper(mesh, solver, "HIMEX2C")
+    ud = torch.from_numpy(u0).cuda()
+    lib = hp.load_library()
+    st = _abi.ImexState(ud.data_ptr(), stp.u.data_ptr(), stp.uhat.data_ptr(),
+                        stp.R_im.data_ptr(), stp.R_ex.data_ptr())
+    ns = _abi.HfrNewtonStats()
+    for stage in (0, 1):
+        rc = lib.imex_stage(mesh.handle, solver.handle, ctypes.byref(stp.tab), stage,
+                            float(dt), ctypes.byref(st), ctypes.byref(ns), None)
+        if rc != 0:
+            raise RuntimeError(lib.fr_last_error().decode())
+    torch.cuda.synchronize()
+    out = stp.u.cpu().numpy(), stp.uhat.cpu().numpy()
+    solver.close()
+    return out
 
 
 def measured_traffic(workload, kernel):
@@ -214,13 +254,19 @@ def explicit_bytes(mesh):
     return mesh.Nex * (2 * 4 * mesh.Np * 8 + 64 + 4 * 32)
 
 
-def cpu_baseline(name):
-    """The oracle timed on a bounded sample of the same workload: the first
-    implicit stage of step 1 (Newton to 1e-10 with exact element Jacobians,
-    condensation and a sparse direct trace solve), single-threaded."""
+FORMS = {"fp32": ("fp32", "fp32"), "fp32_bf16": ("fp32", "bf16"),
+         "fp64": ("fp64", "fp64")}
+
+
+def oracle_first_stage(name, threads):
+    """The oracle (never tuned) on a bounded sample: the first implicit
+    stage of step 1 of workload ``name`` (Newton to 1e-12 with exact element
+    Jacobians, condensation and a sparse direct trace solve), with the BLAS
+    thread pool limited to ``threads``.  Returns (seconds, Newton
+    iterations, implicit DOF, oracle mesh, u_im, uhat)."""
     import fr_inputs as fi
     import oracle
-    from oracle import newton as onw, imex as oimex
+    from oracle import newton as onw, residual as ores, imex as oimex
     from threadpoolctl import threadpool_limits
     d, p, nt, nr, first, ratio = cylinder_workload(name)
     uinf = fi.freestream_state(MACH)
@@ -234,17 +280,44 @@ def cpu_baseline(name):
     u = fi.perturb_state(np.broadcast_to(uinf, (om.Ne, P, P, 4)).copy(), 1e-3, 2)
     ph = oracle.Euler()
     tab = oimex.himex2c()
-    with threadpool_limits(limits=1):
+    with threadpool_limits(limits=threads):
         t0 = time.perf_counter()
-        _, _, its = onw.solve_stage(om, ph, u, u[om.imp_elems], dt * tab.A[0, 0],
-                                    tol=1e-10, maxit=30)
+        u1 = u.copy()
+        u1[om.exp_elems] += dt * tab.Abar[1, 0] * ores.fr_residual(om, ph, u)[om.exp_elems]
+        u_im, uhat, its = onw.solve_stage(om, ph, u1, u[om.imp_elems], dt * tab.A[0, 0],
+                                          tol=1e-12, maxit=30)
         el = time.perf_counter() - t0
-    dof = om.Nim * P * P * 4
-    return dict(value=dof / el, unit="implicit-stage DOF/s", cores=1,
-                kind="oracle",
-                sample=(f"first implicit stage of step 1 on the full workload "
-                        f"({om.Nim} implicit elements, Newton to 1e-10 in {its} "
-                        f"iterations), {el:.1f} s single-threaded NumPy/SciPy"))
+    return el, its, om.Nim * P * P * 4, om, u_im, uhat
+
+
+def oracle_leg(hp, torch, name, forms):
+    """cpu_baseline (the oracle on one host core and on all of them) and the
+    error of every GPU form against the oracle on the same stage."""
+    ncpu = os.cpu_count() or 1
+    el1, its, dof, om, u_im, uhat = oracle_first_stage(name, 1)
+    eln, _, _, _, _, _ = oracle_first_stage(name, ncpu)
+    d, p, nt, nr, first, ratio = cylinder_workload(name)
+    base = dict(value=dof / eln, unit="implicit-stage DOF/s", cores=ncpu,
+                kind="oracle", value_1core=dof / el1,
+                sample=(f"first implicit stage of step 1 of the {nt}x{nr} p={p} cylinder "
+                        f"of the benchmark's radii, CFL rule and seed ({om.Nim} implicit "
+                        f"elements, Newton to 1e-12 in {its} iterations): "
+                        f"{eln:.1f} s with {ncpu} BLAS threads, {el1:.1f} s with one"))
+    mesh, u0, dt, _ = build_case(hp, name)
+    errs = {}
+    for f in forms:
+        ug, uh = first_stage(hp, torch, mesh, u0, dt, *FORMS[f], 1e-12)
+        ue = ug.reshape(4, mesh.Ne, mesh.Np)[:, om.imp_elems]
+        uo = hp.soa_from_elements(u_im)
+        num = np.abs(ue - uo).max(axis=(1, 2))
+        errs[f] = float((num / np.abs(uo).max(axis=(1, 2))).max())
+        ht = np.abs(uh.reshape(-1, 4) - uhat).max(axis=0) / np.abs(uhat).max(axis=0)
+        errs[f + "_trace"] = float(ht.max())
+    errs["sample"] = (f"first implicit stage, {nt}x{nr} p={p} cylinder, Newton to 1e-12 "
+                      f"on both sides; max over conserved variables of "
+                      f"|u - u_oracle|_inf / |u_oracle|_inf over the implicit elements "
+                      f"(and over the trace)")
+    return base, errs
 
 
 def filter_rate(torch, mesh, u0, reps=20, replays=20):
@@ -301,17 +374,64 @@ def copy_calibration(nbytes, reps=5):
     print(json.dumps({"copy_calibration_bytes": n * 4, "reps": reps}))
 
 
+def hbm_kernels(mesh, res, precision):
+    """Bandwidth of the explicit residual (K2) and of the Arnoldi product
+    (K8, the trace SpMV) from the passes that time each alone: algorithmic
+    bytes per launch over the average launch time."""
+    out = {}
+    ms, cnt = res["hbm"]["explicit"]
+    if cnt:
+        by = explicit_bytes(mesh)
+        gbs = by / (ms / cnt * 1e-3) / 1e9
+        out["explicit_rhs"] = dict(bytes_per_launch=by, avg_us=ms / cnt * 1e3,
+                                   achieved_GBps=gbs, frac=gbs / PEAK["hbm_gbs"],
+                                   launches=cnt)
+    ms, cnt = res["hbm"]["spmv"]
+    if cnt:
+        bs = 4 * mesh.P
+        vb = 8 if precision == "fp64" else 4
+        by = mesh_blocks(mesh) * bs * bs * vb + 2 * 4 * mesh.Ntp * 8
+        gbs = by / (ms / cnt * 1e-3) / 1e9
+        out["trace_spmv"] = dict(bytes_per_launch=by, avg_us=ms / cnt * 1e3,
+                                 achieved_GBps=gbs, frac=gbs / PEAK["hbm_gbs"],
+                                 launches=cnt)
+    return out
+
+
+def form_summary(mesh, rr, precision):
+    dof = mesh.Nim * mesh.Np * 4
+    return {
+        "implicit_dof_per_s": dof / (np.mean(rr["impl_ms"]) * 1e-3),
+        "implicit_ms_per_stage": float(np.mean(rr["impl_ms"])),
+        "newton_iters_per_stage": float(np.mean(rr["newton"])),
+        "gmres_iters_per_stage": float(np.mean(rr["gmres"])),
+        "hbm_kernels": hbm_kernels(mesh, rr, precision),
+        "phase_ms_instrumented_pass": {k: v[0] for k, v in rr["phases"].items()},
+        "phase_launches_instrumented_pass": {k: v[1] for k, v in rr["phases"].items()},
+        "workspace_bytes": rr["workspace"],
+    }
+
+
+def rel_diff(a, b):
+    a, b = a.reshape(4, -1), b.reshape(4, -1)
+    return float((np.abs(a - b).max(axis=1) /
+                  np.maximum(np.abs(b).max(axis=1), 1e-300)).max())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3"])
-    ap.add_argument("--forms", default="fp32,fp64")
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c3_small"])
+    ap.add_argument("--forms", default="fp32,fp32_bf16,fp64")
     ap.add_argument("--no-efr", action="store_true",
                     help="skip the interior-embedded trace forms")
     ap.add_argument("--newton-tol", type=float, default=1e-10)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (cpu_baseline and error_vs_oracle)")
+    ap.add_argument("--oracle-workload", default="c3_small",
+                    choices=["c3_small", "c2", "c3"])
     ap.add_argument("--no-edac", action="store_true",
                     help="skip the EDAC forms")
     ap.add_argument("--no-filter", action="store_true",
@@ -331,10 +451,12 @@ def main():
     hp.load_library()
     mesh, u0, dt, _ = build_case(hp, args.workload)
     forms = args.forms.split(",")
+    for f in forms:
+        if f not in FORMS:
+            raise SystemExit(f"unknown form {f}")
     results = {}
     for f in forms:
-        pc = "fp32" if f == "fp32" else "fp64"
-        results[f] = run_form(hp, torch, mesh, u0, dt, f, pc, args.steps,
+        results[f] = run_form(hp, torch, mesh, u0, dt, *FORMS[f], args.steps,
                               args.warmup, args.newton_tol)
         r = results[f]
         print(f"# form {f}: wall {r['wall_s']:.3f} s, implicit ms/stage "
@@ -344,93 +466,70 @@ def main():
     main_form = "fp32" if "fp32" in results else forms[0]
     r = results[main_form]
     stage_s = np.mean(r["impl_ms"]) * 1e-3
-    value = dof / stage_s
+    prec = FORMS[main_form][0]
     line = {
         "metric": "Implicit-stage DOF/s, FP32-MFMA batched vs FP64 hybridized, at matched error",
-        "value": value,
+        "value": dof / stage_s,
         "unit": "implicit-stage DOF/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": r["wall_s"] * 1e3 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if main_form == "fp32" else "f64",
+        "dtype": "f32" if prec == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": describe(args.workload),
                    "n_elems": mesh.Ne, "n_implicit": mesh.Nim,
                    "implicit_dof": dof, "dt": dt,
                    "newton_tol": args.newton_tol,
-                   "form": main_form},
-        "roofline": roofline(main_form, mesh, r["timers"], main_form, args.workload,
+                   "form": main_form,
+                   "stage_timer": "imex_stage entry (queued work drained) to R_i ready"},
+        "roofline": roofline(main_form, mesh, r["timers"], prec, args.workload,
                              r["phases"]),
     }
     for f, rr in results.items():
-        line[f"{f}_form"] = {
-            "implicit_dof_per_s": dof / (np.mean(rr["impl_ms"]) * 1e-3),
-            "implicit_ms_per_stage": float(np.mean(rr["impl_ms"])),
-            "newton_iters_per_stage": float(np.mean(rr["newton"])),
-            "gmres_iters_per_stage": float(np.mean(rr["gmres"])),
-            "phase_ms_instrumented_pass": {k: v[0] for k, v in rr["phases"].items()},
-            "phase_launches_instrumented_pass": {k: v[1] for k, v in rr["phases"].items()},
-            "workspace_bytes": rr["workspace"],
-        }
-    if "fp32" in results and "fp64" in results:
-        a, b = results["fp32"]["state"], results["fp64"]["state"]
-        a = a.reshape(4, -1)
-        b = b.reshape(4, -1)
-        line["fp32_vs_fp64_rel_err"] = float(
-            (np.abs(a - b).max(axis=1) / np.abs(b).max(axis=1)).max())
-        line["speedup_fp32_over_fp64"] = (
-            np.mean(results["fp64"]["impl_ms"]) / np.mean(results["fp32"]["impl_ms"]))
+        line[f"{f}_form"] = form_summary(mesh, rr, FORMS[f][0])
+    if "fp64" in results:
+        for f in results:
+            if f != "fp64":
+                line[f"{f}_vs_fp64_rel_err"] = rel_diff(results[f]["state"],
+                                                        results["fp64"]["state"])
+                line[f"speedup_{f}_over_fp64"] = (np.mean(results["fp64"]["impl_ms"]) /
+                                                  np.mean(results[f]["impl_ms"]))
+    for f in results:
+        results[f]["state"] = None
     if not args.no_efr:
         # the same workload with the interior-embedded trace (EFR)
         mesh_e, u0e, dte, _ = build_case(hp, args.workload, efr=True)
-        dof_e = mesh_e.Nim * mesh_e.Np * 4
         efr_states = {}
-        for f in forms:
-            pc = "fp32" if f == "fp32" else "fp64"
-            rr = run_form(hp, torch, mesh_e, u0e, dte, f, pc, args.steps,
+        for f in ("fp32", "fp64"):
+            rr = run_form(hp, torch, mesh_e, u0e, dte, *FORMS[f], args.steps,
                           args.warmup, args.newton_tol)
             efr_states[f] = rr["state"]
-            line[f"efr_{f}_form"] = {
-                "implicit_dof_per_s": dof_e / (np.mean(rr["impl_ms"]) * 1e-3),
-                "implicit_ms_per_stage": float(np.mean(rr["impl_ms"])),
-                "newton_iters_per_stage": float(np.mean(rr["newton"])),
-                "gmres_iters_per_stage": float(np.mean(rr["gmres"])),
-                "trace_unknowns": 4 * mesh_e.Ntp,
-                "phase_ms_instrumented_pass": {k: v[0] for k, v in rr["phases"].items()},
-            }
+            line[f"efr_{f}_form"] = form_summary(mesh_e, rr, f)
+            line[f"efr_{f}_form"]["trace_unknowns"] = 4 * mesh_e.Ntp
             print(f"# efr form {f}: implicit ms/stage {np.mean(rr['impl_ms']):.3f}, "
                   f"gmres/stage {np.mean(rr['gmres']):.1f}", file=sys.stderr, flush=True)
-        if "fp32" in efr_states and "fp64" in efr_states:
-            a, b = efr_states["fp32"].reshape(4, -1), efr_states["fp64"].reshape(4, -1)
-            line["efr_fp32_vs_fp64_rel_err"] = float(
-                (np.abs(a - b).max(axis=1) / np.abs(b).max(axis=1)).max())
+        line["efr_fp32_vs_fp64_rel_err"] = rel_diff(efr_states["fp32"], efr_states["fp64"])
         line["hfr_trace_unknowns"] = 4 * mesh.Ntp
     if not args.no_edac:
         # the same O-grid and partition with the EDAC equations (theta = 100)
         mesh_d, u0d, dtd, _ = build_case(hp, args.workload, physics="edac")
         edac_states = {}
-        for f in forms:
-            pc = "fp32" if f == "fp32" else "fp64"
-            rr = run_form(hp, torch, mesh_d, u0d, dtd, f, pc, args.steps,
+        for f in ("fp32", "fp64"):
+            rr = run_form(hp, torch, mesh_d, u0d, dtd, *FORMS[f], args.steps,
                           args.warmup, args.newton_tol)
             edac_states[f] = rr["state"]
-            line[f"edac_{f}_form"] = {
-                "implicit_dof_per_s": mesh_d.Nim * mesh_d.Np * 4 / (np.mean(rr["impl_ms"]) * 1e-3),
-                "implicit_ms_per_stage": float(np.mean(rr["impl_ms"])),
-                "newton_iters_per_stage": float(np.mean(rr["newton"])),
-                "gmres_iters_per_stage": float(np.mean(rr["gmres"])),
-                "theta": THETA, "dt": dtd,
-            }
+            line[f"edac_{f}_form"] = form_summary(mesh_d, rr, f)
+            line[f"edac_{f}_form"].update(theta=THETA, dt=dtd)
             print(f"# edac form {f}: implicit ms/stage {np.mean(rr['impl_ms']):.3f}, "
                   f"gmres/stage {np.mean(rr['gmres']):.1f}", file=sys.stderr, flush=True)
-        if "fp32" in edac_states and "fp64" in edac_states:
-            a, b = edac_states["fp32"].reshape(4, -1), edac_states["fp64"].reshape(4, -1)
-            line["edac_fp32_vs_fp64_rel_err"] = float(
-                (np.abs(a - b).max(axis=1) / np.maximum(np.abs(b).max(axis=1), 1e-300)).max())
+        line["edac_fp32_vs_fp64_rel_err"] = rel_diff(edac_states["fp32"], edac_states["fp64"])
     if not args.no_filter:
         line["modal_filter"] = filter_rate(torch, mesh, u0)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.workload)
+        print("# oracle leg", file=sys.stderr, flush=True)
+        base, errs = oracle_leg(hp, torch, args.oracle_workload, forms)
+        line["cpu_baseline"] = base
+        line["error_vs_oracle"] = errs
     print(json.dumps(line))
 
 

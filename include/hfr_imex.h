@@ -299,6 +299,25 @@ fr_status hfr_residual(hfr_solver_t s, const double* u, const double* uhat,
                        double* g, double* R_im, void* stream);
 
 /*
+ * hfr_residual_noalloc: hfr_residual for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc); it takes the mesh instead of a solver and calls no
+ * allocating routine.  h [4][Nim][Np] and g [Ntp][4] are required outputs,
+ * R_im [4][Nim][Np] is optional; inputs as hfr_residual; same kernels, same
+ * results.  Its one intermediate, the element shares of g (Nim * 16 (p+1)
+ * doubles), lives in a static device array of 2^20 doubles (8 MiB) that
+ * every GPU the library runs on holds until the process ends: a mesh whose
+ * Nim * 16 (p+1) exceeds 2^20 is refused with FR_E_INVALID before any
+ * launch.  All calls on one GPU share that array (every entry a call reads
+ * it has written first): calls that overlap on one GPU, on different
+ * streams or from different threads, race.
+ */
+fr_status hfr_residual_noalloc(fr_mesh_t mesh, const double* u,
+                               const double* uhat, const double* ustar,
+                               double aii_dt, double* h, double* g,
+                               double* R_im, void* stream);
+
+/*
  * hfr_assemble_condense: one Newton linearisation (Section 3.2): residuals,
  * element blocks A, B, C, D (eq:elemA, eq:elemsystemB, as exact derivatives
  * of h and g), per-element pivoted LU / Gauss-Jordan of A, X = A^-1 [B r],

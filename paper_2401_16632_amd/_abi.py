@@ -14,7 +14,8 @@ STATUS = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_MESH", -3: "FR_E_NOMEM",
 EXPORTED = ["fr_mesh_create", "fr_mesh_destroy", "fr_mesh_get_info",
             "fr_mesh_get_maps", "fr_explicit_rhs", "fr_modal_filter",
             "hfr_solver_create", "hfr_solver_bind_workspace",
-            "hfr_solver_destroy", "hfr_residual", "hfr_assemble_condense",
+            "hfr_solver_destroy", "hfr_residual", "hfr_residual_noalloc",
+            "hfr_assemble_condense",
             "hfr_trace_solve", "hfr_recover", "hfr_trace_matvec", "hfr_trace_product",
             "hfr_get_system", "hfr_get_blocks", "hfr_get_factors", "hfr_get_preconditioner", "hfr_timing",
             "imex_stage", "imex_tableau_get",
@@ -98,6 +99,9 @@ def load(path=LIB_PATH):
         "hfr_residual": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_double, c_void_p, c_void_p, c_void_p,
                                    c_void_p]),
+        "hfr_residual_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p,
+                                           c_double, c_void_p, c_void_p, c_void_p,
+                                           c_void_p]),
         "hfr_assemble_condense": (c_int32, [c_void_p, c_void_p, c_void_p,
                                             c_void_p, c_double, c_void_p]),
         "hfr_trace_solve": (c_int32, [c_void_p, c_void_p, P(HfrSolveStats),

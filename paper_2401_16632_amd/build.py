@@ -11,7 +11,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhfrimex.so")
 SOURCES = ["mesh.cpp", "solver.cpp", "kernels_residual.hip",
            "kernels_condense.hip", "kernels_trace.hip", "kernels_gmres.hip",
-           "kernels_efr.hip", "kernels_filter.hip"]
+           "kernels_efr.hip", "kernels_filter.hip", "residual_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -88,11 +88,15 @@ def condense_flops(n, m):
     return 2 * n ** 3 / 3 + 2 * n * n * m + 2 * n * m * m + 2 * n * n + 2 * n * m + m * m
 
 
+CONDENSE = "auto"
+
+
 def run_form(hp, torch, mesh, u0, dt, precision, precond, steps, warmup,
              newton_tol):
     solver = hp.Solver(mesh, precision=precision, precond=precond,
                        restart=30, max_iters=400, rtol=1e-6,
-                       newton_max_iters=30, newton_tol=newton_tol)
+                       newton_max_iters=30, newton_tol=newton_tol,
+                       condense=CONDENSE)
     stp = hp.ImexStepper(mesh, solver, "HIMEX2C")
     ud = torch.from_numpy(u0).cuda()
     u = ud.clone()
@@ -133,9 +137,11 @@ def run_form(hp, torch, mesh, u0, dt, precision, precond, steps, warmup,
     hbm = {k: timed_pass([k]) [k] for k in ("explicit", "spmv")}
     # phase breakdown from a separate, fully instrumented pass
     phases = timed_pass(None)
+    choice, cand = solver.condense_choice()
     res = dict(wall_s=wall, impl_ms=impl_ms, newton=newton, gmres=gmres,
                timers=timers, phases=phases, hbm=hbm, state=out,
-               workspace=solver.workspace_bytes)
+               workspace=solver.workspace_bytes,
+               condense=dict(kernel=choice, candidates_ms=cand))
     solver.close()
     return res
 
@@ -190,7 +196,11 @@ def measured_traffic(workload, kernel):
     return float(vals["condense_traffic_bytes_per_launch"])
 
 
-def roofline(form, mesh, timers, precision, workload="c2", phases=None):
+CK_KERNEL = {"sweep": "k_condense_sweep", "blocked": "k_condense_blocked",
+             "blocked_w8": "k_condense_blocked"}
+
+
+def roofline(form, mesh, timers, precision, workload="c2", phases=None, ck="sweep"):
     """Roofline of the kernel with the largest share of the stage (from the
     instrumented pass when given), measured by the events of the timed
     region when that kernel was timed there."""
@@ -203,13 +213,18 @@ def roofline(form, mesh, timers, precision, workload="c2", phases=None):
     sms, scnt = src["spmv"]
     ems, ecnt = src["explicit"]
     if dom == "condense":
+        # the element elimination and the Schur complement from C's
+        # structure (two launches per linearisation, timed together)
         fl = condense_flops(n, m) * mesh.Nim
         avg = cms / max(1, ccnt) * 1e-3
         pk = PEAK["fp32_tflops"] if precision == "fp32" else PEAK["fp64_tflops"]
         ach = fl / avg / 1e12
-        traffic = (measured_traffic(workload, f"k_condense_sweep<{mesh.P}, float")
+        kname = CK_KERNEL.get(ck, "k_condense_sweep")
+        traffic = (measured_traffic(workload, f"{kname}<{mesh.P}, float")
                    if precision == "fp32" else None)
-        return dict(kernel="condense", bound="alu", achieved=ach, peak=pk,
+        return dict(kernel=f"condense ({kname} + k_schur_lift)",
+                    bound="mfma" if kname == "k_condense_blocked" else "alu",
+                    achieved=ach, peak=pk,
                     unit="TFLOP/s", frac=ach / pk, traffic=traffic,
                     launches=ccnt, avg_ms=avg * 1e3,
                     algorithmic_per_launch=fl)
@@ -409,6 +424,7 @@ def form_summary(mesh, rr, precision):
         "phase_ms_instrumented_pass": {k: v[0] for k, v in rr["phases"].items()},
         "phase_launches_instrumented_pass": {k: v[1] for k, v in rr["phases"].items()},
         "workspace_bytes": rr["workspace"],
+        "condense_kernel": rr["condense"],
     }
 
 
@@ -438,7 +454,11 @@ def main():
                     help="skip the modal-filter measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter reference)")
+    ap.add_argument("--condense", default="auto", choices=["auto", "sweep", "blocked", "blocked_w8"],
+                    help="element elimination kernel inside Newton")
     args = ap.parse_args()
+    global CONDENSE
+    CONDENSE = args.condense
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
@@ -483,7 +503,7 @@ def main():
                    "form": main_form,
                    "stage_timer": "imex_stage entry (queued work drained) to R_i ready"},
         "roofline": roofline(main_form, mesh, r["timers"], prec, args.workload,
-                             r["phases"]),
+                             r["phases"], r["condense"]["kernel"]),
     }
     for f, rr in results.items():
         line[f"{f}_form"] = form_summary(mesh, rr, FORMS[f][0])

@@ -232,7 +232,16 @@ typedef struct {
                                  device memory itself; 1: the caller owns it
                                  and passes it to hfr_solver_bind_workspace
                                  before any other call on the solver         */
+    int32_t condense_kernel;  /* element elimination inside Newton (the
+                                 Schur-only condensation): HFR_CK_AUTO,
+                                 HFR_CK_SWEEP or HFR_CK_BLOCKED              */
 } hfr_opts;
+/* HFR_CK_SWEEP: register-resident Gauss-Jordan sweep on the vector ALUs, one
+ * exchange per step; HFR_CK_BLOCKED: panels of 16 exchanges, the update of
+ * the rest of the tableau a product on the 16x16x4 matrix-core tiles (4 or
+ * more waves per element); HFR_CK_BLOCKED_W8: the same with 8 waves per
+ * element; HFR_CK_AUTO: the library's choice for the order and precision. */
+enum { HFR_CK_AUTO = 0, HFR_CK_SWEEP = 1, HFR_CK_BLOCKED = 2, HFR_CK_BLOCKED_W8 = 3 };
 
 typedef struct {
     int32_t iterations;       /* Krylov iterations of the last trace solve   */
@@ -400,6 +409,19 @@ fr_status hfr_get_preconditioner(hfr_solver_t s, void* dinv, void* stream);
  * stream, which costs device time: time the phases in a separate pass from
  * the one whose wall time is measured.
  */
+/*
+ * hfr_condense_choice: the condensation kernel the solver uses inside Newton
+ * (HFR_CK_*; HFR_CK_AUTO until the automatic choice has been made) and,
+ * when candidate_ms is non-NULL, the times of the automatic choice's
+ * candidates (sweep, blocked, blocked with 8 waves; milliseconds per launch
+ * on the solver's first linearisation, -1 if not measured).  With
+ * hfr_opts.condense_kernel = HFR_CK_AUTO the solver measures every candidate
+ * once per (order, precision) and process, on the tableaux of its first
+ * Schur-only linearisation (filled again for each), and keeps the fastest;
+ * later solvers of the same order and precision reuse that choice.
+ */
+fr_status hfr_condense_choice(hfr_solver_t s, int32_t* kernel, double* candidate_ms);
+
 #define HFR_TIMING_SELECT 0x10000
 enum { HFR_T_RESIDUAL = 0,   /* hybridized residual kernel                 */
        HFR_T_CONDENSE = 1,   /* element Jordan sweep kernel (condensation) */

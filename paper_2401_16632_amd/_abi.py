@@ -17,7 +17,7 @@ EXPORTED = ["fr_mesh_create", "fr_mesh_destroy", "fr_mesh_get_info",
             "hfr_solver_destroy", "hfr_residual", "hfr_residual_noalloc",
             "hfr_assemble_condense",
             "hfr_trace_solve", "hfr_recover", "hfr_trace_matvec", "hfr_trace_product",
-            "hfr_get_system", "hfr_get_blocks", "hfr_get_factors", "hfr_get_preconditioner", "hfr_timing",
+            "hfr_get_system", "hfr_get_blocks", "hfr_get_factors", "hfr_get_preconditioner", "hfr_timing", "hfr_condense_choice",
             "imex_stage", "imex_tableau_get",
             "fr_last_error"]
 TIMERS = ["residual", "condense", "assemble", "pcsetup", "spmv",
@@ -49,7 +49,7 @@ class HfrOpts(Structure):
                 ("gmres_rtol", c_double), ("newton_max_iters", c_int32),
                 ("newton_tol", c_double), ("keep_blocks", c_int32),
                 ("jacobian_lag", c_int32), ("gmres_cgs_passes", c_int32),
-                ("caller_workspace", c_int32)]
+                ("caller_workspace", c_int32), ("condense_kernel", c_int32)]
 
 
 class HfrSolveStats(Structure):
@@ -119,6 +119,7 @@ def load(path=LIB_PATH):
         "hfr_get_factors": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
         "hfr_get_preconditioner": (c_int32, [c_void_p, c_void_p, c_void_p]),
         "hfr_timing": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+        "hfr_condense_choice": (c_int32, [c_void_p, P(c_int32), c_void_p]),
         "fr_last_error": (c_char_p, []),
     }
     for name, (res, args) in sig.items():

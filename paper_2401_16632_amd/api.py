@@ -190,7 +190,7 @@ class Solver:
     def __init__(self, mesh, precision="fp64", precond="fp64", restart=30,
                  max_iters=600, rtol=1e-10, newton_max_iters=25,
                  newton_tol=1e-13, keep_blocks=False, jacobian_lag=0,
-                 cgs_passes=1, workspace=None):
+                 cgs_passes=1, workspace=None, condense="auto"):
         """workspace: None (the library allocates its working memory) or
         "torch" (a uint8 CUDA tensor allocated here and bound with
         hfr_solver_bind_workspace; kept as self.workspace)."""
@@ -210,6 +210,10 @@ class Solver:
         if workspace not in (None, "torch"):
             raise ValueError("workspace must be None or 'torch'")
         o.caller_workspace = 1 if workspace == "torch" else 0
+        ck = {"auto": 0, "sweep": 1, "blocked": 2, "blocked_w8": 3}
+        if condense not in ck:
+            raise ValueError(f"condense must be one of {sorted(ck)}")
+        o.condense_kernel = ck[condense]
         self.opts = o
         self.workspace = None
         ws = ctypes.c_size_t()
@@ -330,6 +334,14 @@ class Solver:
             en = -1 if enable is None else (1 if enable else 0)
         _check(load_library().hfr_timing(self.handle, en, ms, cnt))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(_abi.TIMERS)}
+
+    def condense_choice(self):
+        """(kernel name, candidate ms) of the condensation kernel in use."""
+        k = ctypes.c_int32()
+        ms = (ctypes.c_double * 3)()
+        _check(load_library().hfr_condense_choice(self.handle, ctypes.byref(k), ms))
+        names = {0: "auto", 1: "sweep", 2: "blocked", 3: "blocked_w8"}
+        return names[k.value], dict(zip(("sweep", "blocked", "blocked_w8"), list(ms)))
 
     def close(self):
         if getattr(self, "handle", None):

@@ -134,8 +134,15 @@ struct CondenseLaunch {
     // with yr set: keep only what recovery and assembly read (the columns of
     // B and D, and yr, z); the columns of A already exchanged are skipped,
     // so A^-1 and C A^-1 are not stored, and the right-hand side is carried
-    // through the sweep as an FP64 column instead of formed afterwards
+    // through the sweep as an FP64 column instead of formed afterwards.  The
+    // fill then writes the rows of A and B only and the face-point flux
+    // Jacobians to lin; the sweep holds the rows of A only, and L^k and z
+    // are formed from C's structure afterwards (k_schur_lift)
     int schur_only;
+    double* lin;             // [Nim][2][4P][16] (schur_only)
+    int blocked;             // schur_only: panels of 16 on the matrix cores
+                             // (k_condense_blocked) instead of the sweep;
+                             // 1: default waves per element, 2: eight
 };
 // element linearisation and the tableau [A B; C D] (must precede
 // launch_condense, which sweeps the tableau in place)

@@ -195,17 +195,22 @@ constexpr int sweep_waves(int rpl, int N, int words) {
     return w;
 }
 
-template <int P, typename T>
+// SCHUR: the Schur-only instance holds the rows of A and B only (the rows
+// of C and D are not swept: the element Schur complement is formed
+// afterwards from C's structure, k_schur_lift)
+template <int P, typename T, bool SCHUR>
 struct SweepShape {
     static constexpr int NP = P * P, n = 4 * NP, m = 16 * P, N = n + m;
-    static constexpr int RPL = (N + 63) / 64;
+    static constexpr int R = SCHUR ? n : N;          // rows held
+    static constexpr int RPL = (R + 63) / 64;
     static constexpr int W = sweep_waves(RPL, N, int(sizeof(T) / 4));
     static constexpr int NCW = (N + W - 1) / W;
     static constexpr int CH = sweep_ch(NCW);
     static constexpr int NCH = (NCW + CH - 1) / CH;
-    // occupancy the register budget is held to: four waves per SIMD (at
-    // most 128 VGPRs) whenever the tableau share fits, else two
-    static constexpr int WPE = RPL * NCH * CH * int(sizeof(T) / 4) <= 80 ? 4 : 2;
+    // occupancy the register budget is held to: the tableau share of a lane
+    // plus about 48 registers of the step's working set
+    static constexpr int TREGS = RPL * NCH * CH * int(sizeof(T) / 4);
+    static constexpr int WPE = TREGS <= 40 ? 6 : TREGS <= 56 ? 5 : TREGS <= 80 ? 4 : 2;
 };
 
 // ---- fill of the element tableau ------------------------------------------
@@ -306,9 +311,14 @@ __device__ __forceinline__ void block_entries(int br, int bc, const RefOps& o,
     }
 }
 
-template <int P, typename T>
+// AB: only the rows of A and B are written (the Schur-only sweep's input);
+// the face-point flux Jacobians from which C and D are formed go to a.lin
+// ([Nim][2][4P][16] FP64: d F_hat / d u, then d F_hat / d uhat, zero off
+// the trace) for k_schur_lift.
+template <int P, typename T, bool AB>
 __global__ __launch_bounds__(256) void k_tableau_fill(CondenseLaunch a, RefOps og) {
     constexpr int NP = P * P, n = 4 * NP, m = 16 * P, N = n + m, NB = NP + 4 * P;
+    constexpr int NBR = AB ? NP : NB;         // block rows written
     __shared__ CondShared<P> sh;
     __shared__ RefOps o;
     if (a.go && *a.go == 0) return;            // uniform over the grid
@@ -318,8 +328,28 @@ __global__ __launch_bounds__(256) void k_tableau_fill(CondenseLaunch a, RefOps o
     element_linearisation<P>(a, o, k, sh);
     T* G = reinterpret_cast<T*>(a.M) + size_t(k) * N * N;
     double* bcopy = a.blocks_copy ? a.blocks_copy + size_t(k) * N * N : nullptr;
-    for (int blk = threadIdx.x; blk < NB * NB; blk += blockDim.x) {
-        const int bc = blk / NB, br = blk - bc * NB;
+    if constexpr (AB) {
+        double* lin = a.lin + size_t(k) * 2 * 4 * P * 16;
+        for (int i = threadIdx.x; i < 4 * P * 16; i += blockDim.x) {
+            lin[i] = sh.Fu[i >> 4][i & 15];
+            lin[4 * P * 16 + i] = sh.Fh[i >> 4][i & 15];
+        }
+        if (bcopy) {                           // inspection copy: all blocks
+            for (int blk = threadIdx.x; blk < NB * NB; blk += blockDim.x) {
+                const int bc = blk / NB, br = blk - bc * NB;
+                double E[4][4];
+                block_entries<P>(br, bc, o, sh, E);
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        bcopy[size_t(4 * br + v) * N + 4 * bc + c] = E[v][c];
+            }
+            bcopy = nullptr;
+        }
+    }
+    for (int blk = threadIdx.x; blk < NB * NBR; blk += blockDim.x) {
+        const int bc = blk / NBR, br = blk - bc * NBR;
         double E[4][4];
         block_entries<P>(br, bc, o, sh, E);
 #pragma unroll
@@ -345,20 +375,20 @@ __global__ __launch_bounds__(256) void k_tableau_fill(CondenseLaunch a, RefOps o
 }
 
 template <int P, typename T, bool SCHUR>
-__global__ __launch_bounds__((64 * SweepShape<P, T>::W))
-__attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_sweep(
+__global__ __launch_bounds__((64 * SweepShape<P, T, SCHUR>::W))
+__attribute__((amdgpu_waves_per_eu(SweepShape<P, T, SCHUR>::WPE))) void k_condense_sweep(
     CondenseLaunch a, RefOps og) {
-    using S = SweepShape<P, T>;
-    constexpr int n = S::n, N = S::N, RPL = S::RPL, W = S::W, NCW = S::NCW;
+    using S = SweepShape<P, T, SCHUR>;
+    constexpr int n = S::n, N = S::N, R = S::R, RPL = S::RPL, W = S::W, NCW = S::NCW;
     __shared__ T gbuf[2][RPL * 64];
     __shared__ T ibuf[2];
     __shared__ int pbuf[2];
     // right-hand side epilogue of the full sweep: pivot rows, permuted -h,
     // per-wave row sums
     constexpr int NRW = W < n ? W : n;          // waves owning columns of A
-    __shared__ short pl[n];
-    __shared__ double sr[n];
-    __shared__ double racc[NRW][RPL * 64];
+    __shared__ short pl[SCHUR ? 1 : n];
+    __shared__ double sr[SCHUR ? 1 : n];
+    __shared__ double racc[SCHUR ? 1 : NRW][SCHUR ? 1 : RPL * 64];
     const int lane = threadIdx.x & 63;
     // wave index, uniform (so that indices derived from it address
     // registers by index mode rather than by per-lane selects)
@@ -385,8 +415,8 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
         for (int j = 0; j < NCH * CH; ++j) {
             const int col = w + W * j;
             // clamped address: the load stays inside this element's slot
-            const T v = G[size_t(min(col, N - 1)) * N + min(row, N - 1)];
-            t[s][j / CH][j % CH] = (j < NCW && row < N && col < N) ? v : T(0);
+            const T v = G[size_t(min(col, N - 1)) * N + min(row, R - 1)];
+            t[s][j / CH][j % CH] = (j < NCW && row < R && col < N) ? v : T(0);
         }
     }
     // Schur-only sweep: the right-hand side [h; 0] rides along as an FP64
@@ -560,19 +590,16 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
     }
 
     // ---- FP64 right-hand side (as launch_rhs64): the Schur-only sweep holds
-    // it in its extra column (scaled here like the pivot rows); the full
-    // sweep forms yr/z[row] = sum_{j<n} T(sig*t)[row][j] * (-h[p_j]) from the
-    // registers, each wave over its columns of A, the waves' sums added in a
-    // fixed order
+    // A^-1 r in its extra column (scaled here like the pivot rows; C A^-1 r
+    // is formed by k_schur_lift); the full sweep forms
+    // yr/z[row] = sum_{j<n} T(sig*t)[row][j] * (-h[p_j]) from the registers,
+    // each wave over its columns of A, the waves' sums added in a fixed order
     if constexpr (schur) {
-        constexpr int m = N - n;
         if (w == RW) {
 #pragma unroll
             for (int s = 0; s < RPL; ++s) {
                 const int row = lane + 64 * s;
-                const double v = double(sig[s]) * rhs[s];
-                if (row < n) a.yr[size_t(k) * n + row] = v;
-                else if (row < N) a.z[size_t(k) * m + row - n] = v;
+                if (row < n) a.yr[size_t(k) * n + row] = double(sig[s]) * rhs[s];
             }
         }
     } else if (a.yr) {
@@ -611,7 +638,7 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
     }
 
     // ---- store column-major, pivot rows scaled (a Schur-only sweep stores
-    // the columns of B and D only)
+    // the rows of A in the columns of B only: -A^-1 B)
 #pragma unroll
     for (int j = 0; j < NCW; ++j) {
         const int col = w + W * j;
@@ -620,7 +647,445 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
 #pragma unroll
         for (int s = 0; s < RPL; ++s) {
             const int row = lane + 64 * s;
-            if (row < N) G[size_t(col) * N + row] = sig[s] * t[s][j / CH][j % CH];
+            if (row < R) G[size_t(col) * N + row] = sig[s] * t[s][j / CH][j % CH];
+        }
+    }
+}
+
+// ---- element Schur complement from the structure of C (Section 3.2) --------
+// After the Schur-only sweep the rows of A in the columns of B hold
+// X = -A^-1 B (row p_k: unknown k) and yr[p_k] = (A^-1 r)[k].  The rows of C
+// are sparse: face point (f, q), variable v, couples only to the P solution
+// points on the grid line through it, with the face-interpolation weight of
+// each point times the flux Jacobian d F_hat / d u at the face point (times
+// w_q), and D is 4x4 block diagonal (w_q d F_hat / d uhat).  So
+//    L^k = D + C X,   z = C A^-1 r,
+// each row an interpolation of X along one line followed by a 4x4 product,
+// accumulated in FP64 and stored in the rows of D (the assembly's input).
+// Faces off the trace keep identity rows of L and zero z.
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_schur_lift(CondenseLaunch a, RefOps og) {
+    constexpr int NP = P * P, n = 4 * NP, m = 16 * P, N = n + m, NF = 4 * P;
+    constexpr int LDX = n + 1;
+    __shared__ RefOps o;
+    __shared__ T xs[m * LDX];                  // X in unknown order, by column
+    __shared__ double ys[n];
+    __shared__ double fu[NF][16], fh[NF][16];
+    __shared__ short kinv[n];
+    __shared__ int tr[4];
+    const int k = blockIdx.x, t = threadIdx.x;
+    copy_ref_ops(o, og);
+    const int* pk = a.piv + size_t(k) * n;
+    for (int j = t; j < n; j += blockDim.x) kinv[pk[j]] = short(j);
+    const double* lin = a.lin + size_t(k) * 2 * NF * 16;
+    for (int i = t; i < NF * 16; i += blockDim.x) {
+        fu[i >> 4][i & 15] = lin[i];
+        fh[i >> 4][i & 15] = lin[NF * 16 + i];
+    }
+    if (t < 4) tr[t] = (a.finfo[size_t(a.imp_list[k]) * 4 + t].role == ROLE_HFR);
+    __syncthreads();
+    T* G = reinterpret_cast<T*>(a.M) + size_t(k) * N * N;
+    // X: consecutive rows of a column per thread group, eight loads in
+    // flight per thread before the permuted LDS stores
+    constexpr int NX = n * m, PASS = 8;
+    for (int i0 = t; i0 < NX; i0 += PASS * 256) {
+        T v[PASS];
+#pragma unroll
+        for (int q = 0; q < PASS; ++q) {
+            const int idx = min(i0 + q * 256, NX - 1);
+            const int b = idx / n, r = idx - b * n;
+            v[q] = G[size_t(n + b) * N + r];
+        }
+#pragma unroll
+        for (int q = 0; q < PASS; ++q) {
+            const int idx = i0 + q * 256;
+            if (idx < NX) {
+                const int b = idx / n, r = idx - b * n;
+                xs[b * LDX + kinv[r]] = v[q];
+            }
+        }
+    }
+    for (int r = t; r < n; r += blockDim.x) ys[kinv[r]] = a.yr[size_t(k) * n + r];
+    __syncthreads();
+    // one (face point, column) pair per thread and pass: the four rows of
+    // the face point in that column (16-byte store, consecutive face points
+    // of a column contiguous)
+    for (int idx = t; idx < NF * (m + 1); idx += blockDim.x) {
+        const int fq = idx % NF, b = idx / NF;    // b == m: the z column
+        const int f = fq / P, q = fq - f * P;
+        double out[4];
+        if (!tr[f]) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) out[v] = (b == fq * 4 + v) ? 1.0 : 0.0;
+        } else {
+            double sw[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int l = 0; l < P; ++l) {
+                int pt;
+                double c;
+                if (f == 0) { pt = l * P + q; c = o.lm[l]; }
+                else if (f == 1) { pt = q * P + l; c = o.lp[l]; }
+                else if (f == 2) { pt = l * P + (P - 1 - q); c = o.lp[l]; }
+                else { pt = (P - 1 - q) * P + l; c = o.lm[l]; }
+#pragma unroll
+                for (int w = 0; w < 4; ++w)
+                    sw[w] += c * (b < m ? double(xs[b * LDX + pt * 4 + w]) : ys[pt * 4 + w]);
+            }
+            const double wq = o.w[q];
+            const bool diag = (b >> 2) == fq;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double acc = diag ? fh[fq][v * 4 + (b & 3)] : 0.0;
+#pragma unroll
+                for (int w = 0; w < 4; ++w) acc += fu[fq][v * 4 + w] * sw[w];
+                out[v] = wq * acc;
+            }
+        }
+        if (b < m) {
+            T* dst = G + size_t(n + b) * N + n + fq * 4;
+            if constexpr (sizeof(T) == 4) {
+                *reinterpret_cast<float4*>(dst) = make_float4(float(out[0]), float(out[1]),
+                                                              float(out[2]), float(out[3]));
+            } else {
+                reinterpret_cast<double2*>(dst)[0] = make_double2(out[0], out[1]);
+                reinterpret_cast<double2*>(dst)[1] = make_double2(out[2], out[3]);
+            }
+        } else {
+            double* zz = a.z + size_t(k) * m + fq * 4;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) zz[v] = tr[f] ? out[v] : 0.0;
+        }
+    }
+}
+
+// ---- blocked elimination of the rows of A on the matrix cores --------------
+// The Schur-only elimination of the sweep above, in panels of 16 columns of
+// A: for panel K (columns 16j..16j+15, pivot rows P chosen by partial
+// pivoting among the rows not used yet, in column order),
+//      G = T[:, K] T[P, K]^-1   (rows of P: T[P, K]^-1 itself),
+//      T[P, L] <- 0,   T[:, L] <- T[:, L] - G U,   U = T[P, L] (before)
+// over the live columns L (the columns of A not eliminated yet, those of B,
+// and the right-hand side).  A row of P then holds -T[P,K]^-1 U: the
+// expression of the panel's unknowns in the remaining ones, and every
+// later panel updates it like any other row, so after the last panel row
+// p_k holds -(A^-1 B)[k] in the columns of B -- the sweep's result, with
+// piv[k] = p_k -- and the right-hand side column A^-1 h.  G comes from 16
+// Jordan exchanges on the panel alone, by the wave that owns it, with the
+// panel in a lane-per-row layout; the update G U is a product with K = 16
+// on 16x16x4 matrix-core tiles.  Clearing the pivot rows before the product
+// forms them without cancellation.  Rows and columns of A are padded to a
+// multiple of 16 with decoupled identity unknowns.
+//
+// Layout: W waves per element; wave w holds the 16-column tiles
+// c = w, w + W, ... of [A | pad | B] for all rows, as 16x16 accumulator
+// tiles (lane 16 g + i: column i; rows 4g + r (FP32) or g + 4r (FP64) of
+// register r).  The owner of panel j + 1 applies panel j to that tile first
+// and factors it while the other waves apply panel j to theirs.
+template <int P, typename T, int WSEL = 0>
+struct BlockShape {
+    static constexpr int NP = P * P, n = 4 * NP, m = 16 * P, N = n + m;
+    static constexpr int NPAD = (n + 15) / 16 * 16;
+    static constexpr int RT = NPAD / 16;                 // row tiles = panels
+    static constexpr int NCT = RT + m / 16;              // column tiles
+    static constexpr int words = int(sizeof(T) / 4);
+    static constexpr int pick_w() {
+        int w = 4;
+        while (RT * ((NCT + w - 1) / w) * 4 * words > 112 && w < 16) w *= 2;
+        return w;
+    }
+    // waves per element: WSEL, or the smallest of 4, 8, 16 whose tiles fit
+    // about 112 registers
+    static constexpr int W = WSEL > 0 ? WSEL : pick_w();
+    static constexpr int CTW = (NCT + W - 1) / W;        // column tiles per wave
+    static constexpr int TREGS = RT * CTW * 4 * words;   // accumulator registers
+    static constexpr int RPL = (NPAD + 63) / 64;         // panel rows per lane
+    static constexpr int LDP = 17;                       // padded LDS row stride
+    // waves per SIMD the register budget is held to (512 registers)
+    static constexpr int WPE = TREGS + 64 + 16 * RPL * words <= 170 ? 3 : 2;
+};
+
+template <typename T> struct MTile;
+template <> struct MTile<float> {
+    typedef float V __attribute__((ext_vector_type(4)));
+    __device__ static int row(int g, int r) { return 4 * g + r; }
+    __device__ static V mfma(float a, float b, V c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct MTile<double> {
+    typedef double V __attribute__((ext_vector_type(4)));
+    __device__ static int row(int g, int r) { return g + 4 * r; }
+    __device__ static V mfma(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+template <int P, typename T, int WSEL>
+__global__ __launch_bounds__((64 * BlockShape<P, T, WSEL>::W))
+__attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condense_blocked(
+    CondenseLaunch a, RefOps og) {
+    using S = BlockShape<P, T, WSEL>;
+    using M = MTile<T>;
+    using V = typename M::V;
+    constexpr int n = S::n, N = S::N, NPAD = S::NPAD, RT = S::RT, NCT = S::NCT;
+    constexpr int W = S::W, CTW = S::CTW, RPL = S::RPL, LDP = S::LDP;
+    constexpr int NP = P * P;
+    __shared__ T gbuf[2][NPAD * LDP];         // -G of the last two panels
+    __shared__ T pbuf[NPAD * LDP];            // panel in row layout
+    __shared__ T ubuf[W][16 * LDP];           // U rows of one tile, per wave
+    __shared__ int pivs[2][16];
+    // per row: 1 + its position among the panel's pivots, 0 if none
+    __shared__ __align__(4) unsigned char posb[2][NPAD];
+    __shared__ unsigned char used[NPAD];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = lane >> 4, i = lane & 15;
+    const int k = blockIdx.x;
+    T* G = reinterpret_cast<T*>(a.M) + size_t(k) * N * N;
+
+    // ---- load: tile (t, c) of [A | pad | B] (dummy unknowns: identity)
+    V acc[CTW][RT];
+#pragma unroll
+    for (int q = 0; q < CTW; ++q) {
+        const int c = w + W * q;
+        const int ci = 16 * c + i;                     // internal column
+        const bool dcol = ci >= n && ci < NPAD;
+        const int gc = ci < n ? ci : n + (ci - NPAD);  // global column (A or B)
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * t + M::row(g, r);
+                T v = T(0);
+                if (c < NCT) {
+                    if (row < n && !dcol) v = G[size_t(min(gc, N - 1)) * N + row];
+                    else if (row >= n && dcol && row == ci) v = T(1);
+                }
+                acc[q][t][r] = v;
+            }
+        }
+    }
+    for (int r = threadIdx.x; r < NPAD; r += blockDim.x) used[r] = 0;
+    // right-hand side h (FP64) on wave 0, lane-per-row
+    double rho[RPL];
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const int row = lane + 64 * s;
+        rho[s] = (w == 0 && row < n)
+                     ? a.h[size_t(row & 3) * a.nimp * NP + size_t(k) * NP + (row >> 2)]
+                     : 0.0;
+    }
+    __syncthreads();
+
+    auto wave_sync = [&]() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    // accumulator tiles of one column tile -> LDS rows (the owner's panel)
+    auto to_panel = [&](const V (&tile)[RT]) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                pbuf[(16 * t + M::row(g, r)) * LDP + i] = tile[t][r];
+    };
+    // ---- panel factorisation by its owner (panel in pbuf): 16 Jordan
+    // exchanges on the panel's columns, -G to gbuf[j & 1], pivots to
+    // pivs[j & 1] and posb[j & 1]
+    auto factor = [&](int j) {
+        wave_sync();
+        T x[RPL][16];
+        bool usd[RPL];
+        T sig[RPL];
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) {
+            const int row = lane + 64 * s;
+            usd[s] = row >= NPAD || used[min(row, NPAD - 1)];
+            sig[s] = T(1);
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc)
+                x[s][cc] = row < NPAD ? pbuf[min(row, NPAD - 1) * LDP + cc] : T(0);
+        }
+        int pos[RPL];
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) pos[s] = 0;
+        int pv[16];
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc) {
+            unsigned key = 0;
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) {
+                const unsigned ks = pivot_key32(float(fabs(x[s][cc])), lane + 64 * s);
+                if (!usd[s] && ks > key) key = ks;
+            }
+            key = wave_max_u32(key);
+            int p;
+            T ip;
+            if (key != 0) {
+                p = 255 - int(key & 0xffu);
+                T piv = T(1);
+#pragma unroll
+                for (int s = 0; s < RPL; ++s)
+                    if (RPL == 1 || s == (p >> 6)) piv = lane_value(x[s][cc], p & 63);
+                if constexpr (sizeof(T) == 4) ip = __builtin_amdgcn_rcpf(piv);
+                else ip = T(1) / piv;
+            } else {
+                // no nonzero candidate: flag it, take the lowest unused row
+                // and leave the tableau as it is (the result is discarded)
+                if (lane == 0) *a.pivot_fail = 1;
+                unsigned fk = 0;
+#pragma unroll
+                for (int s = 0; s < RPL; ++s)
+                    if (!usd[s]) fk = max(fk, unsigned(255 - (lane + 64 * s)));
+                fk = wave_max_u32(fk);
+                p = 255 - int(fk);
+                ip = T(0);
+            }
+            pv[cc] = p;
+            const int sp = p >> 6, lp = p & 63;
+            T gsv[RPL];
+#pragma unroll
+            for (int s = 0; s < RPL; ++s)
+                gsv[s] = (lane + 64 * s == p) ? T(0) : x[s][cc] * ip;
+#pragma unroll
+            for (int c2 = 0; c2 < 16; ++c2) {
+                if (c2 == cc) continue;
+                T src = x[0][c2];
+#pragma unroll
+                for (int s0 = 1; s0 < RPL; ++s0) src = (sp == s0) ? x[s0][c2] : src;
+                const T u = lane_value(src, lp);
+#pragma unroll
+                for (int s = 0; s < RPL; ++s) x[s][c2] = fma(-gsv[s], u, x[s][c2]);
+            }
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) {
+                const bool me = lane + 64 * s == p;
+                x[s][cc] = me ? T(-1) : gsv[s];
+                if (me) { usd[s] = true; sig[s] = -ip; pos[s] = cc + 1; }
+            }
+        }
+        // -G: pivot rows scaled by their factors; the rows of P hold
+        // T[P,K]^-1, the others T[:,K] T[P,K]^-1
+        const int jb = j & 1;
+        T* gb = gbuf[jb];
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) {
+            const int row = lane + 64 * s;
+            if (row < NPAD) {
+#pragma unroll
+                for (int cc = 0; cc < 16; ++cc) gb[row * LDP + cc] = -(sig[s] * x[s][cc]);
+                if (usd[s]) used[row] = 1;
+                posb[jb][row] = (unsigned char)pos[s];
+            }
+        }
+        if (lane < 16) {
+            int pl = pv[0];
+#pragma unroll
+            for (int cc = 1; cc < 16; ++cc) pl = (lane == cc) ? pv[cc] : pl;
+            pivs[jb][lane] = pl;
+            const int col = 16 * j + lane;
+            if (col < n) a.piv[size_t(k) * n + col] = pl;
+        }
+    };
+
+    // one tile: its pivot rows to LDS (U) and cleared, then tile += (-G) U
+    // with the A operands -G(16 t + i, 4 kk + g) read from LDS
+    auto update_tile = [&](int jb, V (&tile)[RT]) {
+        T* ub = ubuf[w];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int pos = posb[jb][16 * t + M::row(g, r)];
+                if (pos) {
+                    ub[(pos - 1) * LDP + i] = tile[t][r];
+                    tile[t][r] = T(0);
+                }
+            }
+        }
+        wave_sync();
+        T bop[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) bop[kk] = ub[(4 * kk + g) * LDP + i];
+        const T* gb = gbuf[jb];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+                tile[t] = M::mfma(gb[(16 * t + i) * LDP + 4 * kk + g], bop[kk], tile[t]);
+        wave_sync();                                   // ub free for the next tile
+    };
+
+    if (w == 0) {
+        to_panel(acc[0]);
+        factor(0);
+    }
+    for (int j = 0; j < RT; ++j) {
+        __syncthreads();                               // panel j published
+        const int jb = j & 1;
+        const int j1 = j + 1;
+        const bool ahead = j1 < RT && w == j1 % W;     // uniform
+        if (ahead) {
+            // the next panel's tile first, then its factorisation
+#pragma unroll
+            for (int q = 0; q < CTW; ++q)
+                if (q == j1 / W) {
+                    update_tile(jb, acc[q]);
+                    to_panel(acc[q]);
+                }
+            factor(j1);
+        }
+#pragma unroll
+        for (int q = 0; q < CTW; ++q) {
+            const int c = w + W * q;
+            if (c > j && c < NCT && !(ahead && c == j1)) update_tile(jb, acc[q]);
+        }
+        if (w == 0) {                                  // right-hand side
+            double rp[16];
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc) {
+                const int p = pivs[jb][cc];
+                double v = rho[0];
+#pragma unroll
+                for (int s0 = 1; s0 < RPL; ++s0) v = ((p >> 6) == s0) ? rho[s0] : v;
+                rp[cc] = lane_value(v, p & 63);
+            }
+            const T* gb = gbuf[jb];
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) {
+                const int row = lane + 64 * s;
+                if (row < NPAD) {
+                    double v = posb[jb][row] ? 0.0 : rho[s];
+#pragma unroll
+                    for (int cc = 0; cc < 16; ++cc)
+                        v = fma(double(gb[row * LDP + cc]), rp[cc], v);
+                    rho[s] = v;
+                }
+            }
+        }
+    }
+
+    // ---- store: rows of A in the columns of B (-A^-1 B at row p_k), and
+    // A^-1 h at the same rows
+#pragma unroll
+    for (int q = 0; q < CTW; ++q) {
+        const int c = w + W * q;
+        if (c < RT || c >= NCT) continue;              // uniform
+        const int col = n + 16 * (c - RT) + i;
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * t + M::row(g, r);
+                if (row < n) G[size_t(col) * N + row] = acc[q][t][r];
+            }
+    }
+    if (w == 0) {
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) {
+            const int row = lane + 64 * s;
+            if (row < n) a.yr[size_t(k) * n + row] = rho[s];
         }
     }
 }
@@ -628,12 +1093,21 @@ __attribute__((amdgpu_waves_per_eu(SweepShape<P, T>::WPE))) void k_condense_swee
 template <int P, typename T>
 static hipError_t launch_sweep(const RefOps& o, const CondenseLaunch& a,
                                hipStream_t st) {
-    if (a.schur_only && a.yr)
-        hipLaunchKernelGGL((k_condense_sweep<P, T, true>), dim3(a.nimp),
-                           dim3(64 * SweepShape<P, T>::W), 0, st, a, o);
-    else
+    if (a.schur_only && a.yr) {
+        if (a.blocked == 2)
+            hipLaunchKernelGGL((k_condense_blocked<P, T, 8>), dim3(a.nimp),
+                               dim3(64 * BlockShape<P, T, 8>::W), 0, st, a, o);
+        else if (a.blocked)
+            hipLaunchKernelGGL((k_condense_blocked<P, T, 0>), dim3(a.nimp),
+                               dim3(64 * BlockShape<P, T, 0>::W), 0, st, a, o);
+        else
+            hipLaunchKernelGGL((k_condense_sweep<P, T, true>), dim3(a.nimp),
+                               dim3(64 * SweepShape<P, T, true>::W), 0, st, a, o);
+        hipLaunchKernelGGL((k_schur_lift<P, T>), dim3(a.nimp), dim3(256), 0, st, a, o);
+    } else {
         hipLaunchKernelGGL((k_condense_sweep<P, T, false>), dim3(a.nimp),
-                           dim3(64 * SweepShape<P, T>::W), 0, st, a, o);
+                           dim3(64 * SweepShape<P, T, false>::W), 0, st, a, o);
+    }
     return hipGetLastError();
 }
 
@@ -708,10 +1182,14 @@ template <int P>
 static hipError_t launch_fill_p(const RefOps& o, const CondenseLaunch& a,
                                 hipStream_t st) {
     if (a.nimp == 0) return hipSuccess;
-    if (a.precision == HFR_PREC_FP64)
-        hipLaunchKernelGGL((k_tableau_fill<P, double>), dim3(a.nimp), dim3(256), 0, st, a, o);
-    else
-        hipLaunchKernelGGL((k_tableau_fill<P, float>), dim3(a.nimp), dim3(256), 0, st, a, o);
+    const bool ab = a.schur_only != 0;
+    if (a.precision == HFR_PREC_FP64) {
+        if (ab) hipLaunchKernelGGL((k_tableau_fill<P, double, true>), dim3(a.nimp), dim3(256), 0, st, a, o);
+        else hipLaunchKernelGGL((k_tableau_fill<P, double, false>), dim3(a.nimp), dim3(256), 0, st, a, o);
+    } else {
+        if (ab) hipLaunchKernelGGL((k_tableau_fill<P, float, true>), dim3(a.nimp), dim3(256), 0, st, a, o);
+        else hipLaunchKernelGGL((k_tableau_fill<P, float, false>), dim3(a.nimp), dim3(256), 0, st, a, o);
+    }
     return hipGetLastError();
 }
 

@@ -11,6 +11,8 @@
 #include <atomic>
 #include <functional>
 #include <map>
+#include <mutex>
+#include <array>
 #include <string>
 #include <vector>
 
@@ -74,6 +76,7 @@ struct hfr_solver_s {
     unsigned* counters = nullptr;
     int fpb = 1, gblk = 1, fpbA = 1, gblkA = 1;
     int* piv = nullptr;      // [Nim][n]
+    double* lin = nullptr;   // [Nim][2][4P][16] face-point flux Jacobians
     double* yr = nullptr;    // [Nim][n]  L^-1 P r (FP64)
     double* zz = nullptr;    // [Nim][m]  C A^-1 r (FP64)
     bool have_factors = false;
@@ -90,6 +93,9 @@ struct hfr_solver_s {
     double* dpin = nullptr;  // the same buffer's device address
     long long seq_norms = 0;     // last sequence number queued for the norms
     long long seq_gmres = 0;     // ... and for the GMRES state
+    int ck = -1;             // condensation kernel in use (HFR_CK_*), -1: not chosen
+    double tune_ms[3] = {-1.0, -1.0, -1.0};   // measured candidates (sweep,
+                                              // blocked, blocked with 8 waves)
     size_t ws_bytes = 0;     // working buffers (one block, carved)
     size_t table_bytes = 0;  // library-owned read-only device tables
     struct WsItem { void** ptr; size_t bytes; };
@@ -331,17 +337,24 @@ CondenseLaunch condense_launch(hfr_solver_s* s, const double* u,
     c.pivot_fail = s->flags;
     c.piv = s->piv;
     c.efr_fnodes = m->efr ? m->d_efr_fnodes : nullptr;
+    c.lin = s->lin;
+    const int ck = s->ck > 0 ? s->ck : s->opts.condense_kernel;
+    c.blocked = ck == HFR_CK_BLOCKED ? 1 : ck == HFR_CK_BLOCKED_W8 ? 2 : 0;
     return c;
 }
 
 // Fill of the element tableaus; with `go`, every workgroup returns at entry
 // when the device flag says the Newton iteration has converged.
+// schur: the input of the Schur-only sweep (rows of A and B, and the
+// face-point flux Jacobians)
 fr_status condense_fill(hfr_solver_s* s, const double* u, const double* uhat,
-                        double aii_dt, const int* go, hipStream_t st) {
+                        double aii_dt, const int* go, hipStream_t st,
+                        bool schur = false) {
     fr_mesh_s* m = s->mesh;
     if (m->Nim == 0) return FR_OK;
     CondenseLaunch c = condense_launch(s, u, uhat, aii_dt);
     c.go = go;
+    c.schur_only = schur ? 1 : 0;
     const int tk = tbegin(s, HFR_T_FILL, st);
     HIP_TRY(launch_tableau_fill(m->ops, c, st));
     tend(s, tk, st);
@@ -357,7 +370,7 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
     fr_mesh_s* m = s->mesh;
     if (m->Nim == 0) return FR_OK;
     if (!fill_done) {
-        fr_status e = condense_fill(s, u, uhat, aii_dt, nullptr, st);
+        fr_status e = condense_fill(s, u, uhat, aii_dt, nullptr, st, schur_only);
         if (e) return e;
     }
     CondenseLaunch c = condense_launch(s, u, uhat, aii_dt);
@@ -562,6 +575,74 @@ fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
     return FR_OK;
 }
 
+// Process-wide choice of the Schur-only condensation kernel per (order,
+// precision), measured once: each candidate eliminates the same freshly
+// filled tableaux (the first linearisation of a Newton solve) and the fastest
+// is kept for every later solver of that shape.
+std::mutex g_tune_mutex;
+std::map<std::pair<int, int>, std::pair<int, std::array<double, 3>>> g_tuned;
+
+fr_status tune_condense(hfr_solver_s* s, const double* u, const double* uhat,
+                        double aii_dt, hipStream_t st) {
+    fr_mesh_s* m = s->mesh;
+    const auto key = std::make_pair(m->P, s->opts.precision);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            s->ck = it->second.first;
+            for (int i = 0; i < 3; ++i) s->tune_ms[i] = it->second.second[i];
+            return FR_OK;
+        }
+    }
+    const int cand[3] = {HFR_CK_SWEEP, HFR_CK_BLOCKED, HFR_CK_BLOCKED_W8};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(FR_E_DEVICE, "hipEventCreate failed");
+    }
+    std::array<double, 3> ms{};
+    fr_status e = FR_OK;
+    for (int c = 0; c < 3 && !e; ++c) {
+        s->ck = cand[c];
+        float best = 1e30f;
+        for (int rep = 0; rep < 2 && !e; ++rep) {   // the first run warms up
+            if ((e = condense_fill(s, u, uhat, aii_dt, nullptr, st, true))) break;
+            CondenseLaunch cl = condense_launch(s, u, uhat, aii_dt);
+            cl.yr = s->yr;
+            cl.z = s->zz;
+            cl.schur_only = 1;
+            if (hipEventRecord(e0, st) != hipSuccess ||
+                launch_condense(m->ops, cl, st) != hipSuccess ||
+                hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                e = fail(FR_E_DEVICE, "condensation tuning launch failed");
+                break;
+            }
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, e0, e1);
+            if (rep > 0) best = std::min(best, t);
+        }
+        ms[c] = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e) {
+        s->ck = -1;
+        return e;
+    }
+    int bi = 0;
+    for (int c = 1; c < 3; ++c)
+        if (ms[c] < ms[bi]) bi = c;
+    s->ck = cand[bi];
+    for (int i = 0; i < 3; ++i) s->tune_ms[i] = ms[i];
+    // leave a fresh fill for the linearisation that follows
+    if ((e = condense_fill(s, u, uhat, aii_dt, nullptr, st, true))) return e;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tuned[key] = std::make_pair(s->ck, ms);
+    return FR_OK;
+}
+
 fr_status newton(hfr_solver_s* s, double* u, double* uhat,
                  const double* ustar, double aii_dt, hfr_newton_stats* stats,
                  hipStream_t st) {
@@ -598,7 +679,7 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
                                           s->scratch, rtol, s->dscale, s->dpin, s->go, gate,
                                           s->flags,
                                           flags_pub, seq_pub, ++s->seq_norms, st));
-        if (spec && (e2 = condense_fill(s, u, uhat, aii_dt, s->go, st))) return e2;
+        if (spec && (e2 = condense_fill(s, u, uhat, aii_dt, s->go, st, true))) return e2;
         return FR_OK;
     };
     // After each GMRES chunk the update of the Newton iterate and the next
@@ -638,6 +719,11 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         const bool relin = lag <= 0 || !s->have_factors ||
                            (it == 0 && (s->stage_calls % lag) == 0);
         if (relin) {
+            // first Schur-only linearisation with the automatic choice: pick
+            // the condensation kernel (the tableaux are filled again after)
+            if (spec && s->ck < 0 && s->opts.condense_kernel == HFR_CK_AUTO &&
+                (e = tune_condense(s, u, uhat, aii_dt, st)))
+                return e;
             // factors that are never reused need only the Schur part
             if ((e = condense_internal(s, u, uhat, aii_dt, st, spec, lag <= 0))) return e;
             s->have_factors = lag > 0;
@@ -695,7 +781,8 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
         return fail(FR_E_INVALID, "gmres_restart must be in 1..64");
     if (o->newton_max_iters < 0 || !(o->newton_tol > 0.0) || !(o->gmres_rtol > 0.0) ||
         o->jacobian_lag < 0 || o->gmres_cgs_passes < 0 || o->gmres_cgs_passes > 2 ||
-        (o->caller_workspace != 0 && o->caller_workspace != 1))
+        (o->caller_workspace != 0 && o->caller_workspace != 1) ||
+        o->condense_kernel < HFR_CK_AUTO || o->condense_kernel > HFR_CK_BLOCKED_W8)
         return fail(FR_E_INVALID, "bad tolerance or iteration cap");
     auto s = new hfr_solver_s();
     s->mesh = mesh;
@@ -829,6 +916,7 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
     plan(s, &s->part3, size_t(std::max(1024, s->nbr + 1)) * kGmresMaxK);
     plan(s, &s->counters, 4);
     plan(s, &s->piv, nimp * size_t(s->n));
+    plan(s, &s->lin, nimp * 2 * 4 * 16 * size_t(P));
     plan(s, &s->yr, nimp * size_t(s->n));
     plan(s, &s->zz, nimp * size_t(s->m));
     plan(s, &s->t, size_t(s->N));
@@ -1167,6 +1255,15 @@ extern "C" fr_status imex_tableau_get(int32_t id, imex_tableau* out) {
         out->bbar[0] = d;
         out->bbar[1] = 1.0 - d;
     }
+    return FR_OK;
+}
+
+extern "C" fr_status hfr_condense_choice(hfr_solver_t s, int32_t* kernel,
+                                         double* candidate_ms) {
+    if (!s || !kernel) return fail(FR_E_INVALID, "null argument");
+    *kernel = s->ck > 0 ? s->ck : s->opts.condense_kernel;
+    if (candidate_ms)
+        for (int i = 0; i < 3; ++i) candidate_ms[i] = s->tune_ms[i];
     return FR_OK;
 }
 

@@ -385,3 +385,61 @@ def test_imex_steps_fp32_condensation_high_order(name, pc):
         ud = un.clone()
         err = rel_err(unsoa(host(ud), hm.Ne, pr.P), _ORACLE_STEPS[name][k])
         assert err <= 1e-8, (k, err, stats)
+
+
+_ORACLE_STEPS_B = {}
+
+
+@pytest.mark.parametrize("name", ["c1_p1", "c1_p2", "cyl_p3", "cyl_p4", "c1_p5"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_blocked_condensation_steps(name, precision):
+    """The element elimination in panels of 16 exchanges with the update of
+    the rest of the tableau on matrix-core tiles (every padded block count
+    p = 1 to 5): two IMEX steps against the oracle, 1e-11 in FP64 and 1e-8
+    with FP32 tableaux."""
+    pr, u = _build(name)
+    if name.startswith("c1"):
+        u = fi.isentropic_vortex(pr.om.x, pr.om.y)
+        dt = 0.01
+    else:
+        dt = _cfl_dt(pr)
+    hm = pr.hm
+    if name not in _ORACLE_STEPS_B:
+        uo, seq = u.copy(), []
+        for _ in range(2):
+            uo, _ = oimex.imex_step(pr.om, pr.ph, oimex.himex2c(), uo, dt, tol=1e-13)
+            seq.append(uo)
+        _ORACLE_STEPS_B[name] = seq
+    s = hp.Solver(hm, precision=precision, precond=precision, rtol=1e-10,
+                  newton_tol=1e-13, max_iters=3000, condense="blocked")
+    stp = hp.ImexStepper(hm, s, "HIMEX2C")
+    ud = dev(soa(u))
+    tol = 1e-11 if precision == "fp64" else 1e-8
+    for k in range(2):
+        un, stats = stp.step(ud, dt)
+        ud = un.clone()
+        err = rel_err(unsoa(host(ud), hm.Ne, pr.P), _ORACLE_STEPS_B[name][k])
+        assert err <= tol, (k, err, stats)
+
+
+def test_condense_autotuner_choice():
+    """With the automatic choice the solver times the three condensation
+    kernels on its first linearisation, keeps the fastest, and a second
+    solver of the same order and precision reuses the choice; the step
+    still matches the oracle."""
+    pr, u = _build("cyl_p3")
+    dt = _cfl_dt(pr)
+    s = hp.Solver(pr.hm, precision="fp32", precond="fp32", rtol=1e-10, newton_tol=1e-13,
+                  max_iters=3000)
+    assert s.condense_choice()[0] == "auto"
+    stp = hp.ImexStepper(pr.hm, s, "HIMEX2C")
+    un, _ = stp.step(dev(soa(u)), dt)
+    name, ms = s.condense_choice()
+    assert name in ("sweep", "blocked", "blocked_w8"), name
+    assert all(v > 0 for v in ms.values()), ms
+    assert ms[name] == min(ms.values())
+    uo, _ = oimex.imex_step(pr.om, pr.ph, oimex.himex2c(), u, dt, tol=1e-13)
+    assert rel_err(unsoa(host(un), pr.hm.Ne, pr.P), uo) <= 1e-8
+    s2 = hp.Solver(pr.hm, precision="fp32", precond="fp32")
+    hp.ImexStepper(pr.hm, s2, "HIMEX2C").step(dev(soa(u)), dt)
+    assert s2.condense_choice() == (name, ms)

@@ -49,11 +49,57 @@ def cylinder_workload(name):
     return d, p, n_theta, n_r, first, ratio
 
 
+def c5_instances(seed=5, count=64, p=3):
+    """The batch of independent cylinders: quads per instance log-uniform in
+    [2e3, 2e4] with n_theta = 2 n_r, wall-normal ratio U[1.1, 1.25], first
+    cell 1e-4 D, p = 3; each instance's implicit rings and time step by the
+    local-CFL rule with IF ~ 0.2 of its own rings."""
+    import fr_inputs as fi
+    rng = np.random.default_rng(seed)
+    specs = []
+    for _ in range(count):
+        nq = float(np.exp(rng.uniform(np.log(2e3), np.log(2e4))))
+        nr = max(6, int(round(np.sqrt(nq / 2.0))))
+        specs.append((2 * nr, nr, 1e-4, float(rng.uniform(1.1, 1.25))))
+    descs = [fi.cylinder_ogrid(nt, nr, first=first, ratio=ratio)
+             for nt, nr, first, ratio in specs]
+    return descs, specs, p
+
+
 def describe(name):
+    if name == "c5":
+        descs, specs, p = c5_instances()
+        nq = sum(nt * nr for nt, nr, _, _ in specs)
+        return (f"2D Euler (viscous terms not built), batch of {len(specs)} independent "
+                f"cylinder O-grids ({nq} quads, 2e3..2e4 each), p={p}, ratio 1.1..1.25, "
+                f"implicit = local CFL > 1 per instance (IF ~ 0.2), own time step each, "
+                f"one launch per kernel for all, HIMEX2C pair")
     d, p, nt, nr, first, ratio = cylinder_workload(name)
     return (f"2D Euler (viscous terms not built), circular cylinder O-grid "
             f"{nt}x{nr} quads, p={p}, first cell {first:g} D, ratio {ratio:.4f}, "
             f"Mach {MACH}, implicit = local CFL > 1 (IF ~ 0.2), HIMEX2C pair")
+
+
+def build_batch(hp, if_target=0.2, seed=2):
+    """The independent-cylinder batch as one mesh with per-instance time
+    steps (the stage calls then take dt = 1)."""
+    import fr_inputs as fi
+    descs, specs, p = c5_instances()
+    uinf = fi.freestream_state(MACH)
+    masks, dts = [], []
+    for d, (nt, nr, first, ratio) in zip(descs, specs):
+        probe = hp.Mesh(d, p, uinf=uinf, host_only=True)
+        es = probe.maps()["es"].reshape(nr, nt)
+        J = max(1, int(round(if_target * nr)))
+        cut = 0.5 * (es[J - 1].max() + es[J].min())
+        masks.append(es.ravel() <= cut)
+        dts.append(2.0 * cut / (WAVE * (2 * p + 1)))
+    batch = fi.concat_meshes(descs)
+    mesh = hp.Mesh(batch, p, implicit_mask=np.concatenate(masks), uinf=uinf)
+    mesh.set_instance_dt(dts)
+    P = p + 1
+    u = fi.perturb_state(np.broadcast_to(uinf, (mesh.Ne, P, P, 4)).copy(), 1e-3, seed)
+    return mesh, hp.soa_from_elements(u).ravel(), 1.0, None
 
 
 def build_case(hp, name, if_target=0.2, seed=2, efr=False, physics="euler"):
@@ -61,6 +107,8 @@ def build_case(hp, name, if_target=0.2, seed=2, efr=False, physics="euler"):
     selects the interior-embedded trace, ``physics`` the Euler or the EDAC
     equations (free stream P = 0, |v| = 1, seeded 1e-3 additive noise)."""
     import fr_inputs as fi
+    if name == "c5":
+        return build_batch(hp, if_target, seed)
     d, p, nt, nr, first, ratio = cylinder_workload(name)
     edac = physics == "edac"
     uinf = fi.edac_freestream() if edac else fi.freestream_state(MACH)
@@ -89,6 +137,7 @@ def condense_flops(n, m):
 
 
 CONDENSE = "auto"
+DAMPING = False
 
 
 def run_form(hp, torch, mesh, u0, dt, precision, precond, steps, warmup,
@@ -96,7 +145,7 @@ def run_form(hp, torch, mesh, u0, dt, precision, precond, steps, warmup,
     solver = hp.Solver(mesh, precision=precision, precond=precond,
                        restart=30, max_iters=400, rtol=1e-6,
                        newton_max_iters=30, newton_tol=newton_tol,
-                       condense=CONDENSE)
+                       condense=CONDENSE, damping=DAMPING)
     stp = hp.ImexStepper(mesh, solver, "HIMEX2C")
     ud = torch.from_numpy(u0).cuda()
     u = ud.clone()
@@ -439,7 +488,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c3_small"])
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c3_small", "c5"])
     ap.add_argument("--forms", default="fp32,fp32_bf16,fp64")
     ap.add_argument("--no-efr", action="store_true",
                     help="skip the interior-embedded trace forms")
@@ -457,8 +506,11 @@ def main():
     ap.add_argument("--condense", default="auto", choices=["auto", "sweep", "blocked", "blocked_w8"],
                     help="element elimination kernel inside Newton")
     args = ap.parse_args()
-    global CONDENSE
+    global CONDENSE, DAMPING
     CONDENSE = args.condense
+    # the batch's most stretched instances start impulsively at local CFL
+    # ~50 at the wall: Newton needs the admissible-step damping there
+    DAMPING = args.workload == "c5"
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
@@ -516,6 +568,9 @@ def main():
                                                   np.mean(results[f]["impl_ms"]))
     for f in results:
         results[f]["state"] = None
+    if args.workload == "c5":
+        args.no_efr = args.no_edac = True
+        line["config"]["instances"] = 64
     if not args.no_efr:
         # the same workload with the interior-embedded trace (EFR)
         mesh_e, u0e, dte, _ = build_case(hp, args.workload, efr=True)

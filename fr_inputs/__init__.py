@@ -7,11 +7,11 @@ no mapping to solution points, no flux, no residual), so that the oracle and
 the product path can both import it without sharing any of the method.
 """
 from .meshes import (periodic_quad_mesh, box_quad_mesh, cylinder_ogrid,
-                     ogrid_ratio_for_outer)
+                     ogrid_ratio_for_outer, concat_meshes)
 from .states import (isentropic_vortex, freestream_state, perturb_state,
                      edac_vortex, edac_freestream, EULER_GAMMA)
 
-__all__ = ["periodic_quad_mesh", "box_quad_mesh", "cylinder_ogrid", "ogrid_ratio_for_outer",
+__all__ = ["periodic_quad_mesh", "box_quad_mesh", "concat_meshes", "cylinder_ogrid", "ogrid_ratio_for_outer",
            "isentropic_vortex", "freestream_state", "perturb_state",
            "edac_vortex", "edac_freestream",
            "EULER_GAMMA"]

@@ -134,3 +134,25 @@ def cylinder_ogrid(n_theta, n_r, radius=0.5, first=1e-4, ratio=1.15):
     return dict(node_xy=node_xy, elem_nodes=np.asarray(elems, np.int32),
                 node_topo=np.arange(node_xy.shape[0], dtype=np.int32),
                 elem_face_bc=np.asarray(bc, np.int8))
+
+
+def concat_meshes(descs):
+    """Several independent meshes as one description: node ids offset, the
+    element lists and boundary tags concatenated, and ``elem_instance`` /
+    ``n_instances`` naming each element's source mesh."""
+    xy, en, topo, bc, inst = [], [], [], [], []
+    off = 0
+    for i, d in enumerate(descs):
+        n = len(d["node_xy"])
+        xy.append(np.asarray(d["node_xy"], np.float64))
+        en.append(np.asarray(d["elem_nodes"], np.int64) + off)
+        t = d.get("node_topo")
+        topo.append((np.arange(n) if t is None else np.asarray(t, np.int64)) + off)
+        bc.append(np.asarray(d.get("elem_face_bc",
+                                   np.zeros((len(d["elem_nodes"]), 4))), np.int8))
+        inst.append(np.full(len(d["elem_nodes"]), i, np.int32))
+        off += n
+    return dict(node_xy=np.concatenate(xy), elem_nodes=np.concatenate(en).astype(np.int32),
+                node_topo=np.concatenate(topo).astype(np.int32),
+                elem_face_bc=np.concatenate(bc), elem_instance=np.concatenate(inst),
+                n_instances=len(descs))

@@ -116,6 +116,11 @@ typedef struct {
     int32_t flags;
     int32_t physics;
     double theta;
+    /* several independent meshes in one: with n_instances > 0, elem_instance
+     * [n_elems] gives each element's instance (0..n_instances-1); no face may
+     * join elements of two instances (FR_E_MESH).  NULL / 0: one instance */
+    const int32_t* elem_instance;
+    int32_t n_instances;
 } fr_mesh_desc;
 
 typedef struct {
@@ -126,6 +131,7 @@ typedef struct {
     size_t device_table_bytes;
     int32_t efr;     /* 1 for the interior-embedded trace (FR_MESH_EFR);
                         n_trace_points then counts trace nodes             */
+    int32_t n_instances;  /* independent instances (0: one mesh)           */
 } fr_mesh_info;
 
 /*
@@ -138,6 +144,17 @@ typedef struct {
  */
 fr_status fr_mesh_create(const fr_mesh_desc* desc, fr_mesh_t* out);
 void fr_mesh_destroy(fr_mesh_t mesh);
+/*
+ * fr_mesh_set_instance_dt: per-instance time steps of a mesh with
+ * n_instances > 0 (host array dt[n_instances], each > 0 and finite):
+ * afterwards every time-step factor of imex_stage on an element is the
+ * stage call's dt times its instance's dt[...] (call imex_stage with
+ * dt = 1 to advance every instance by its own step).  The stage residual h
+ * and the element blocks scale a_ii dt the same way.  Host-synchronous.
+ * FR_E_INVALID for a mesh without instances, a null pointer or a
+ * non-positive step.
+ */
+fr_status fr_mesh_set_instance_dt(fr_mesh_t mesh, const double* dt);
 fr_status fr_mesh_get_info(fr_mesh_t mesh, fr_mesh_info* out);
 
 /*
@@ -235,6 +252,13 @@ typedef struct {
     int32_t condense_kernel;  /* element elimination inside Newton (the
                                  Schur-only condensation): HFR_CK_AUTO,
                                  HFR_CK_SWEEP or HFR_CK_BLOCKED              */
+    int32_t newton_damping;   /* 1: a Newton update after which the
+                                 residual is not finite is halved, up to
+                                 seven times, before the iteration goes on
+                                 (the paper's Newton takes full steps; this
+                                 guards impulsive starts at high local CFL,
+                                 where a full step can leave the admissible
+                                 states); 0: full steps only                  */
 } hfr_opts;
 /* HFR_CK_SWEEP: register-resident Gauss-Jordan sweep on the vector ALUs, one
  * exchange per step; HFR_CK_BLOCKED: panels of 16 exchanges, the update of

@@ -23,7 +23,8 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .residual import hfr_local, assemble_trace, implicit_outer, trace_average
+from .residual import (hfr_local, assemble_trace, implicit_outer, trace_average,
+                       hfr_residual)
 
 CSTEP = 1e-30
 
@@ -140,13 +141,15 @@ def recover(sysd, duhat):
 
 
 def solve_stage(mesh, phys, u_all, ustar_im, aii_dt, uhat0=None, tol=1e-13,
-                maxit=25, history=None):
+                maxit=25, history=None, damping=False):
     """Newton iteration for (u_im, u_hat) of one implicit stage.
 
     u_all: full state whose explicit part is the explicit stage value (used
     at Upsilon faces) and whose implicit part is the initial guess.  The
     initial trace is the average of the two sides' interpolated states.
-    Returns (u_im, uhat, iterations)."""
+    With ``damping`` an update after which the stage residual is not
+    finite is halved, up to seven times (a globalisation of Newton: it
+    changes the path, not the root).  Returns (u_im, uhat, iterations)."""
     nv = phys.nv
     u_all = u_all.copy()
     im = mesh.imp_elems
@@ -166,9 +169,20 @@ def solve_stage(mesh, phys, u_all, ustar_im, aii_dt, uhat0=None, tol=1e-13,
         if it == maxit:
             break
         duhat = trace_solve(sysd["L"], sysd["t"])
-        du = recover(sysd, duhat)
-        u_all[im] += du.reshape(len(im), P, P, nv)
-        uhat = uhat + duhat.reshape(-1, nv)
+        du = recover(sysd, duhat).reshape(len(im), P, P, nv)
+        duhat = duhat.reshape(-1, nv)
+        base_u, base_h = u_all[im].copy(), uhat
+        th = 1.0
+        for _ in range(8 if damping else 1):
+            u_all[im] = base_u + th * du
+            uhat = base_h + th * duhat
+            if not damping:
+                break
+            with np.errstate(invalid="ignore", divide="ignore"):
+                R, g = hfr_residual(mesh, phys, u_all, uhat)
+            if np.all(np.isfinite(R)) and np.all(np.isfinite(g)):
+                break
+            th *= 0.5
     raise NewtonError(f"Newton did not converge (residual {res:.3e})")
 
 

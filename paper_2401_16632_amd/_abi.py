@@ -12,6 +12,7 @@ STATUS = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_MESH", -3: "FR_E_NOMEM",
           -4: "FR_E_DEVICE", -5: "FR_E_NOT_CONVERGED", -6: "FR_E_NONFINITE",
           -7: "FR_E_UNSUPPORTED"}
 EXPORTED = ["fr_mesh_create", "fr_mesh_destroy", "fr_mesh_get_info",
+            "fr_mesh_set_instance_dt",
             "fr_mesh_get_maps", "fr_explicit_rhs", "fr_modal_filter",
             "hfr_solver_create", "hfr_solver_bind_workspace",
             "hfr_solver_destroy", "hfr_residual", "hfr_residual_noalloc",
@@ -32,7 +33,8 @@ class FrMeshDesc(Structure):
                 ("elem_face_bc", POINTER(c_int8)), ("order", c_int32),
                 ("implicit_mask", POINTER(c_uint8)), ("es_cutoff", c_double),
                 ("gamma", c_double), ("uinf", c_double * 4),
-                ("flags", c_int32), ("physics", c_int32), ("theta", c_double)]
+                ("flags", c_int32), ("physics", c_int32), ("theta", c_double),
+                ("elem_instance", POINTER(c_int32)), ("n_instances", c_int32)]
 
 
 class FrMeshInfo(Structure):
@@ -40,7 +42,7 @@ class FrMeshInfo(Structure):
                 ("order", "n_pts", "n_elems", "n_faces", "n_implicit",
                  "n_explicit", "n_trace_faces", "n_trace_points",
                  "n_upsilon", "n_boundary", "n_loc", "m_loc")] + \
-        [("device_table_bytes", c_size_t), ("efr", c_int32)]
+        [("device_table_bytes", c_size_t), ("efr", c_int32), ("n_instances", c_int32)]
 
 
 class HfrOpts(Structure):
@@ -49,7 +51,8 @@ class HfrOpts(Structure):
                 ("gmres_rtol", c_double), ("newton_max_iters", c_int32),
                 ("newton_tol", c_double), ("keep_blocks", c_int32),
                 ("jacobian_lag", c_int32), ("gmres_cgs_passes", c_int32),
-                ("caller_workspace", c_int32), ("condense_kernel", c_int32)]
+                ("caller_workspace", c_int32), ("condense_kernel", c_int32),
+                ("newton_damping", c_int32)]
 
 
 class HfrSolveStats(Structure):
@@ -87,6 +90,7 @@ def load(path=LIB_PATH):
     sig = {
         "fr_mesh_create": (c_int32, [P(FrMeshDesc), P(c_void_p)]),
         "fr_mesh_destroy": (None, [c_void_p]),
+        "fr_mesh_set_instance_dt": (c_int32, [c_void_p, P(c_double)]),
         "fr_mesh_get_info": (c_int32, [c_void_p, P(FrMeshInfo)]),
         "fr_mesh_get_maps": (c_int32, [c_void_p] + [c_void_p] * 8),
         "fr_explicit_rhs": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -116,6 +116,10 @@ class Mesh:
             raise ValueError(f"unknown physics {physics!r}")
         d.physics = kinds[physics]
         d.theta = float(theta)
+        if desc.get("elem_instance") is not None:
+            inst = arr(desc["elem_instance"], np.int32)
+            d.elem_instance = inst.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            d.n_instances = int(desc["n_instances"])
         h = ctypes.c_void_p()
         _check(lib.fr_mesh_create(ctypes.byref(d), ctypes.byref(h)))
         self._keep = []
@@ -132,6 +136,14 @@ class Mesh:
         self.Ntf = self.info["n_trace_faces"]
         self.efr = bool(self.info["efr"])
         self._maps = None
+
+    def set_instance_dt(self, dt):
+        """Per-instance time steps (fr_mesh_set_instance_dt)."""
+        a = np.ascontiguousarray(np.asarray(dt, np.float64))
+        if a.shape != (self.info["n_instances"],):
+            raise ValueError("one time step per instance")
+        _check(load_library().fr_mesh_set_instance_dt(
+            self.handle, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
     def maps(self):
         if self._maps is None:
@@ -190,7 +202,7 @@ class Solver:
     def __init__(self, mesh, precision="fp64", precond="fp64", restart=30,
                  max_iters=600, rtol=1e-10, newton_max_iters=25,
                  newton_tol=1e-13, keep_blocks=False, jacobian_lag=0,
-                 cgs_passes=1, workspace=None, condense="auto"):
+                 cgs_passes=1, workspace=None, condense="auto", damping=False):
         """workspace: None (the library allocates its working memory) or
         "torch" (a uint8 CUDA tensor allocated here and bound with
         hfr_solver_bind_workspace; kept as self.workspace)."""
@@ -214,6 +226,7 @@ class Solver:
         if condense not in ck:
             raise ValueError(f"condense must be one of {sorted(ck)}")
         o.condense_kernel = ck[condense]
+        o.newton_damping = 1 if damping else 0
         self.opts = o
         self.workspace = None
         ws = ctypes.c_size_t()

@@ -101,6 +101,7 @@ struct ResidualLaunch {
     double* gk;              // [nlist][4][P][4] or null
     const int* efr_fnodes;   // [Ntf][P] trace nodes (interior-embedded trace) or null
     const int* gate;         // if set and *gate == 0 the kernel returns at entry
+    const double* dtscale;   // [Ne] factor of aii_dt per element, or null
 };
 hipError_t launch_residual(const RefOps& ops, const ResidualLaunch& a,
                            hipStream_t st);
@@ -140,6 +141,7 @@ struct CondenseLaunch {
     // are formed from C's structure afterwards (k_schur_lift)
     int schur_only;
     double* lin;             // [Nim][2][4P][16] (schur_only)
+    const double* dtscale;   // [Ne] factor of aii_dt per element, or null
     int blocked;             // schur_only: panels of 16 on the matrix cores
                              // (k_condense_blocked) instead of the sweep;
                              // 1: default waves per element, 2: eight
@@ -225,10 +227,12 @@ hipError_t launch_efr_trace_average(const RefOps& ops, int nnodes, int Ne,
                                     const int* inc_ptr, const int* inc,
                                     const int* imp_list, const double* u,
                                     double* uhat, hipStream_t st);
+// u_im += theta du (scatter), uhat += theta duhat
 hipError_t launch_newton_update(int Np, int nimp, int Ne, const int* imp_list,
                                 const double* du, double* u, int ntp4,
                                 const double* duhat, double* uhat,
-                                hipStream_t st, const int* gate = nullptr);
+                                hipStream_t st, const int* gate = nullptr,
+                                double theta = 1.0);
 // Modal filter: orthonormal Legendre basis at the Gauss points
 // v1[q*P+a] = psi_a(x_q), the Gauss weights, and sigma (already raised to
 // the time-step exponent) per exponent sum a + b = 0 .. 2(P-1).

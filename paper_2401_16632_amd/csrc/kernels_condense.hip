@@ -53,7 +53,7 @@ __device__ void element_linearisation(const CondenseLaunch& a, const RefOps& o,
         double uu[4];
         for (int v = 0; v < 4; ++v) uu[v] = a.u[v * plane + size_t(e) * NP + t];
         phys_dflux_pair(pk, uu, y_et, -x_et, -y_xi, x_xi, sh.Af[t], sh.Ag[t]);
-        sh.c[t] = a.aii_dt / J;
+        sh.c[t] = (a.dtscale ? a.aii_dt * a.dtscale[e] : a.aii_dt) / J;
     }
     if (t < 4) sh.tr[t] = (a.finfo[size_t(e) * 4 + t].role == ROLE_HFR);
     // the face terms on the second wave, concurrently with the point terms

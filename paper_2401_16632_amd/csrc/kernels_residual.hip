@@ -187,11 +187,12 @@ __global__ __launch_bounds__(256) void k_residual(ResidualLaunch a, RefOps og) {
     const size_t oplane = size_t(a.nlist) * NP;
     const size_t oidx = size_t(li) * NP + pt;
     const double iJ = 1.0 / J;
+    const double adt = a.dtscale ? a.aii_dt * a.dtscale[e] : a.aii_dt;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const double R = -div[v] * iJ;
         if (a.R) a.R[v * oplane + oidx] = R;
-        if (a.h) a.h[v * oplane + oidx] = uloc[v] - a.ustar[v * oplane + oidx] - a.aii_dt * R;
+        if (a.h) a.h[v * oplane + oidx] = uloc[v] - a.ustar[v * oplane + oidx] - adt * R;
     }
 }
 

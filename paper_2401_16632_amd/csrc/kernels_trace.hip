@@ -618,7 +618,8 @@ hipError_t launch_recover_update(const RefOps& ops, bool efr, int nimp, const vo
 // ---- Newton update: u_im += du (scatter), uhat += duhat -----------------
 __global__ void k_newton_update(int Np, int nimp, int Ne, const int* imp_list,
                                 const double* du, double* u, int ntp4,
-                                const double* duhat, double* uhat, const int* gate) {
+                                const double* duhat, double* uhat, const int* gate,
+                                double th) {
     if (gate && *gate == 0) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int per = nimp * Np;
@@ -627,20 +628,20 @@ __global__ void k_newton_update(int Np, int nimp, int Ne, const int* imp_list,
         const int v = i / per;
         const int rem = i - v * per;
         const int k = rem / Np, pt = rem - k * Np;
-        u[size_t(v) * Ne * Np + size_t(imp_list[k]) * Np + pt] += du[i];
+        u[size_t(v) * Ne * Np + size_t(imp_list[k]) * Np + pt] += th * du[i];
     } else if (i - nu < ntp4) {
-        uhat[i - nu] += duhat[i - nu];
+        uhat[i - nu] += th * duhat[i - nu];
     }
 }
 
 hipError_t launch_newton_update(int Np, int nimp, int Ne, const int* imp_list,
                                 const double* du, double* u, int ntp4,
                                 const double* duhat, double* uhat,
-                                hipStream_t st, const int* gate) {
+                                hipStream_t st, const int* gate, double theta) {
     const long n = 4L * nimp * Np + ntp4;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_newton_update, dim3(blocks_for(n)), dim3(kThreads), 0,
-                       st, Np, nimp, Ne, imp_list, du, u, ntp4, duhat, uhat, gate);
+                       st, Np, nimp, Ne, imp_list, du, u, ntp4, duhat, uhat, gate, theta);
     return hipGetLastError();
 }
 
@@ -773,6 +774,7 @@ struct Combo {
     int nterm;
     double* out;             // full (scatter) or compact
     int scatter;
+    const double* dtscale;   // [Ne] factor of every coefficient, or null
 };
 
 __global__ void k_combine(int nlist, int Np, int Ne, const int* list, Combo c) {
@@ -783,8 +785,9 @@ __global__ void k_combine(int nlist, int Np, int Ne, const int* list, Combo c) {
     const int rem = i - v * per;
     const int li = rem / Np, pt = rem - li * Np;
     const size_t full = size_t(v) * Ne * Np + size_t(list[li]) * Np + pt;
-    double acc = c.base[full];
+    double acc = 0.0;
     for (int t = 0; t < c.nterm; ++t) acc += c.coef[t] * c.terms[t][i];
+    acc = c.base[full] + (c.dtscale ? c.dtscale[list[li]] : 1.0) * acc;
     if (c.scatter) c.out[full] = acc;
     else c.out[i] = acc;
 }
@@ -792,7 +795,8 @@ __global__ void k_combine(int nlist, int Np, int Ne, const int* list, Combo c) {
 hipError_t launch_combine(int nlist, int Np, int Ne, const int* list,
                           const double* base, int nterm,
                           const double* const* terms, const double* coefs,
-                          double* out, int scatter, hipStream_t st) {
+                          double* out, int scatter, const double* dtscale,
+                          hipStream_t st) {
     if (nlist == 0) return hipSuccess;
     if (nterm > 6) return hipErrorInvalidValue;
     Combo c{};
@@ -804,6 +808,7 @@ hipError_t launch_combine(int nlist, int Np, int Ne, const int* list,
     }
     c.out = out;
     c.scatter = scatter;
+    c.dtscale = dtscale;
     const long n = 4L * nlist * Np;
     hipLaunchKernelGGL(k_combine, dim3(blocks_for(n)), dim3(kThreads), 0, st,
                        nlist, Np, Ne, list, c);

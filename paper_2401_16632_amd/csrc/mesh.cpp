@@ -157,7 +157,7 @@ static fr_status upload(T** dst, const std::vector<T>& src, size_t& bytes) {
 static void free_mesh_device(fr_mesh_s* m) {
     void* ptrs[] = {m->d_verts, m->d_finfo, m->d_fS, m->d_imp, m->d_exp,
                     m->d_trace_map, m->d_tpside, m->d_efr_fnodes,
-                    m->d_efr_inc_ptr, m->d_efr_inc};
+                    m->d_efr_inc_ptr, m->d_efr_inc, m->d_dtscale};
     for (void* p : ptrs) (void)hipFree(p);
 }
 
@@ -264,6 +264,28 @@ extern "C" fr_status fr_mesh_create(const fr_mesh_desc* d, fr_mesh_t* out) {
             if (tag0 || tag1) {
                 delete m;
                 return fail(FR_E_MESH, "boundary tag on an interior edge");
+            }
+        }
+    }
+    // ---- independent instances: no face may join two of them ------------
+    if (d->n_instances < 0 || (d->n_instances > 0 && !d->elem_instance)) {
+        delete m;
+        return fail(FR_E_INVALID, "n_instances needs elem_instance");
+    }
+    if (d->n_instances > 0) {
+        m->n_instances = d->n_instances;
+        m->instance.assign(d->elem_instance, d->elem_instance + Ne);
+        for (int e = 0; e < Ne; ++e)
+            if (m->instance[e] < 0 || m->instance[e] >= d->n_instances) {
+                delete m;
+                return fail(FR_E_INVALID, "elem_instance out of range");
+            }
+        for (int f = 0; f < Nf; ++f) {
+            const int e0 = m->face_e[2 * f], e1 = m->face_e[2 * f + 1];
+            if (e1 >= 0 && m->instance[e0] != m->instance[e1]) {
+                delete m;
+                return fail(FR_E_MESH, "a face joins elements of two instances (face " +
+                                           std::to_string(f) + ")");
             }
         }
     }
@@ -460,12 +482,29 @@ extern "C" fr_status fr_mesh_create(const fr_mesh_desc* d, fr_mesh_t* out) {
         (!m->efr && (st = upload(&m->d_tpside, tpside, nb))) ||
         (m->efr && (st = upload(&m->d_efr_fnodes, m->efr_fnodes, nb))) ||
         (m->efr && (st = upload(&m->d_efr_inc_ptr, m->efr_inc_ptr, nb))) ||
-        (m->efr && (st = upload(&m->d_efr_inc, m->efr_inc, nb)))) {
+        (m->efr && (st = upload(&m->d_efr_inc, m->efr_inc, nb))) ||
+        (m->n_instances > 0 &&
+         (st = upload(&m->d_dtscale, std::vector<double>(Ne, 1.0), nb)))) {
         free_mesh_device(m);
         delete m;
         return st;
     }
     *out = m;
+    return FR_OK;
+}
+
+extern "C" fr_status fr_mesh_set_instance_dt(fr_mesh_t m, const double* dt) {
+    if (!m || !dt) return fail(FR_E_INVALID, "null argument");
+    if (m->n_instances == 0) return fail(FR_E_INVALID, "mesh has no instances");
+    if (m->host_only) return fail(FR_E_INVALID, "host-only mesh");
+    for (int i = 0; i < m->n_instances; ++i)
+        if (!(dt[i] > 0.0) || !std::isfinite(dt[i]))
+            return fail(FR_E_INVALID, "instance time steps must be positive and finite");
+    std::vector<double> sc(m->Ne);
+    for (int e = 0; e < m->Ne; ++e) sc[e] = dt[m->instance[e]];
+    if (hipMemcpy(m->d_dtscale, sc.data(), sizeof(double) * sc.size(),
+                  hipMemcpyHostToDevice) != hipSuccess)
+        return fail(FR_E_DEVICE, "upload of instance time steps failed");
     return FR_OK;
 }
 
@@ -491,6 +530,7 @@ extern "C" fr_status fr_mesh_get_info(fr_mesh_t m, fr_mesh_info* o) {
     o->m_loc = 16 * m->P;
     o->device_table_bytes = m->device_bytes;
     o->efr = m->efr ? 1 : 0;
+    o->n_instances = m->n_instances;
     return FR_OK;
 }
 

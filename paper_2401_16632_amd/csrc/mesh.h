@@ -40,4 +40,9 @@ struct fr_mesh_s {
     int* d_efr_fnodes = nullptr;
     int* d_efr_inc_ptr = nullptr;
     int* d_efr_inc = nullptr;
+    // independent instances: element -> instance, and the per-element
+    // factor of every time step (the instance's dt), 1 until set
+    int n_instances = 0;
+    std::vector<int> instance;            // [Ne]
+    double* d_dtscale = nullptr;          // [Ne] or null (all 1)
 };

@@ -78,6 +78,7 @@ extern "C" fr_status hfr_residual_noalloc(fr_mesh_t m, const double* u,
     a.h = h;
     a.ustar = ustar;
     a.aii_dt = aii_dt;
+    a.dtscale = m->d_dtscale;
     a.gk = gk;     // every entry is written by the residual kernel before the
                    // gather reads it, so nothing is cleared
     HIP_TRY(launch_residual(m->ops, a, st));

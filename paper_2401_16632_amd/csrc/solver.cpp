@@ -31,7 +31,8 @@ hipError_t launch_trace_average_ops(const RefOps& o, int ntp, int Ne,
 hipError_t launch_combine(int nlist, int Np, int Ne, const int* list,
                           const double* base, int nterm,
                           const double* const* terms, const double* coefs,
-                          double* out, int scatter, hipStream_t st);
+                          double* out, int scatter, const double* dtscale,
+                          hipStream_t st);
 }  // namespace hfr
 
 using namespace hfr;
@@ -262,6 +263,7 @@ ResidualLaunch implicit_launch(hfr_solver_s* s, const double* u,
     a.uhat = uhat;
     a.phys = m->phys;
     a.efr_fnodes = m->efr ? m->d_efr_fnodes : nullptr;
+    a.dtscale = m->d_dtscale;
     return a;
 }
 
@@ -338,6 +340,7 @@ CondenseLaunch condense_launch(hfr_solver_s* s, const double* u,
     c.piv = s->piv;
     c.efr_fnodes = m->efr ? m->d_efr_fnodes : nullptr;
     c.lin = s->lin;
+    c.dtscale = m->d_dtscale;
     const int ck = s->ck > 0 ? s->ck : s->opts.condense_kernel;
     c.blocked = ck == HFR_CK_BLOCKED ? 1 : ck == HFR_CK_BLOCKED_W8 ? 2 : 0;
     return c;
@@ -694,6 +697,10 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         tend(s, tk, st);
         return queue_checks(gate);
     };
+    // damped Newton: a step that leaves a non-finite residual is halved (at
+    // most seven times) by moving the iterate back along du, duhat
+    double theta = 1.0;
+    int halvings = 0;
     bool queued = false;
     for (int it = 0;; ++it) {
         if (!queued && (e = queue_checks(nullptr))) return e;
@@ -708,9 +715,21 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         loc.residual = res;
         loc.newton_iters = it;
         if (!(hmax == hmax) || !(gmax == gmax) || std::isinf(res)) {
+            if (s->opts.newton_damping && it > 0 && halvings < 7) {
+                ++halvings;
+                theta *= 0.5;
+                HIP_TRY(launch_newton_update(m->Np, m->Nim, m->Ne, m->d_imp, s->du, u,
+                                             4 * m->Ntp, s->duhat, uhat, st, nullptr, -theta));
+                if ((e = queue_checks(nullptr))) return e;
+                queued = true;
+                --it;                              // the same Newton iteration
+                continue;
+            }
             if (stats) *stats = loc;
             return fail(FR_E_NONFINITE, "non-finite Newton residual");
         }
+        theta = 1.0;
+        halvings = 0;
         if (res <= tol) break;
         if (it >= s->opts.newton_max_iters) {
             if (stats) *stats = loc;
@@ -782,7 +801,8 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
     if (o->newton_max_iters < 0 || !(o->newton_tol > 0.0) || !(o->gmres_rtol > 0.0) ||
         o->jacobian_lag < 0 || o->gmres_cgs_passes < 0 || o->gmres_cgs_passes > 2 ||
         (o->caller_workspace != 0 && o->caller_workspace != 1) ||
-        o->condense_kernel < HFR_CK_AUTO || o->condense_kernel > HFR_CK_BLOCKED_W8)
+        o->condense_kernel < HFR_CK_AUTO || o->condense_kernel > HFR_CK_BLOCKED_W8 ||
+        (o->newton_damping != 0 && o->newton_damping != 1))
         return fail(FR_E_INVALID, "bad tolerance or iteration cap");
     auto s = new hfr_solver_s();
     s->mesh = mesh;
@@ -1169,13 +1189,13 @@ extern "C" fr_status imex_stage(fr_mesh_t mesh, hfr_solver_t s,
             coefs[j] = dt * tab->bbar[j];
         }
         HIP_TRY(launch_combine(m->Nex, m->Np, m->Ne, m->d_exp, stt->u_n, S + 1,
-                               terms, coefs, stt->u, 1, st));
+                               terms, coefs, stt->u, 1, m->d_dtscale, st));
         for (int j = 0; j < S; ++j) {
             terms[j] = stt->R_im + j * pim;
             coefs[j] = dt * tab->b[j];
         }
         HIP_TRY(launch_combine(m->Nim, m->Np, m->Ne, m->d_imp, stt->u_n, S,
-                               terms, coefs, stt->u, 1, st));
+                               terms, coefs, stt->u, 1, m->d_dtscale, st));
         return FR_OK;
     }
     const int I = stage;   // 1-based implicit stage
@@ -1187,7 +1207,7 @@ extern "C" fr_status imex_stage(fr_mesh_t mesh, hfr_solver_t s,
             coefs[j] = dt * tab->Abar[I * (S + 1) + j];
         }
         HIP_TRY(launch_combine(m->Nex, m->Np, m->Ne, m->d_exp, stt->u_n, I,
-                               terms, coefs, stt->u, 1, st));
+                               terms, coefs, stt->u, 1, m->d_dtscale, st));
     }
     if (m->Nim) {
         // the implicit stage's wall time runs from here (queued work
@@ -1202,7 +1222,7 @@ extern "C" fr_status imex_stage(fr_mesh_t mesh, hfr_solver_t s,
             coefs[j] = dt * tab->A[(I - 1) * S + j];
         }
         HIP_TRY(launch_combine(m->Nim, m->Np, m->Ne, m->d_imp, stt->u_n, I - 1,
-                               terms, coefs, s->ustar, 0, st));
+                               terms, coefs, s->ustar, 0, m->d_dtscale, st));
         const double aii_dt = dt * tab->A[(I - 1) * S + (I - 1)];
         if (m->efr)
             HIP_TRY(launch_efr_trace_average(m->ops, m->Ntp, m->Ne, m->d_efr_inc_ptr,

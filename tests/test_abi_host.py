@@ -150,3 +150,20 @@ def test_imex_stage_rejects_u_n_overlapping_the_stage_buffers():
     assert rc == -1 and "overlaps" in msg
     rc, msg = call(base, *far)
     assert rc == -1 and "host-only" in msg
+
+
+def test_instances_must_be_disconnected():
+    """Instances are independent meshes: a face joining elements of two
+    instances is refused; concatenated meshes are accepted."""
+    import fr_inputs as fi
+    d, _ = cylinder_desc(n_theta=12, n_r=4)
+    two = fi.concat_meshes([d, d])
+    hm = hp.Mesh(two, 2, host_only=True)
+    assert hm.info["n_instances"] == 2 and hm.Ne == 2 * 48
+    bad = dict(d)
+    bad["elem_instance"] = (np.arange(48) // 24).astype(np.int32)   # splits one mesh
+    bad["n_instances"] = 2
+    with pytest.raises(hp.HfrError, match="FR_E_MESH"):
+        hp.Mesh(bad, 2, host_only=True)
+    with pytest.raises(hp.HfrError, match="FR_E_INVALID"):
+        hm.set_instance_dt([1.0, 1.0])        # host-only mesh

@@ -174,3 +174,18 @@ def test_upsilon_flux_bitwise_single_valued():
         a = oracle.physics.rusanov(ph, uf[e0, l0], uf[e1, l1][::-1], m.S_face[e0, l0])
         b = oracle.physics.rusanov(ph, uf[e1, l1], uf[e0, l0][::-1], m.S_face[e1, l1])
         assert np.array_equal(a, -b[::-1])
+
+
+def test_damped_newton_takes_full_steps_when_they_are_admissible():
+    """The damping only halves a step that leaves a non-finite residual:
+    where every full step is admissible the damped and the plain Newton
+    iterations are the same, and the result solves the stage."""
+    m = c1_mesh(p=2, n=4, perturb=0.1, seed=4)
+    ph = Euler()
+    u, ustar = _stage_inputs(m, seed=3)
+    a = 0.05
+    h1, h2 = [], []
+    r1 = nw.solve_stage(m, ph, u, ustar, a, tol=1e-13, history=h1)
+    r2 = nw.solve_stage(m, ph, u, ustar, a, tol=1e-13, history=h2, damping=True)
+    assert r1[2] == r2[2] and np.array_equal(r1[0], r2[0]) and np.array_equal(r1[1], r2[1])
+    assert h1 == h2

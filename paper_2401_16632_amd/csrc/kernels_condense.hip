@@ -779,8 +779,16 @@ __global__ __launch_bounds__(256) void k_schur_lift(CondenseLaunch a, RefOps og)
 // Layout: W waves per element; wave w holds the 16-column tiles
 // c = w, w + W, ... of [A | pad | B] for all rows, as 16x16 accumulator
 // tiles (lane 16 g + i: column i; rows 4g + r (FP32) or g + 4r (FP64) of
-// register r).  The owner of panel j + 1 applies panel j to that tile first
-// and factors it while the other waves apply panel j to theirs.
+// register r).  The owner of panel j + 1 applies panel j to that tile
+// first, factors it, and applies panel j to its other tiles only in the
+// next period, before panel j + 1, so a period lasts one tile update and
+// one factorisation; the panel buffers rotate over three slots for that.
+// -G is kept in LDS with the columns of each row in the order
+// (c mod 4, c div 4) and U column by column in the same order, so the four
+// operands a lane feeds the four products of K = 16 are adjacent (one
+// 16-byte read per row tile in FP32).  A 128-bit mask of the panel's pivot
+// rows lets every wave skip the row tiles and register slots that hold no
+// pivot row when it extracts U.
 template <int P, typename T, int WSEL = 0>
 struct BlockShape {
     static constexpr int NP = P * P, n = 4 * NP, m = 16 * P, N = n + m;
@@ -799,26 +807,65 @@ struct BlockShape {
     static constexpr int CTW = (NCT + W - 1) / W;        // column tiles per wave
     static constexpr int TREGS = RT * CTW * 4 * words;   // accumulator registers
     static constexpr int RPL = (NPAD + 63) / 64;         // panel rows per lane
-    static constexpr int LDP = 17;                       // padded LDS row stride
-    // waves per SIMD the register budget is held to (512 registers)
-    static constexpr int WPE = TREGS + 64 + 16 * RPL * words <= 170 ? 3 : 2;
+    static constexpr int LDP = 17;                       // panel row stride
+    static constexpr int LDG = words == 1 ? 20 : 18;     // -G row / U column stride
+    static constexpr int NB = 3;                         // panel buffer slots
+    static constexpr int MW = (NPAD + 31) / 32;          // pivot-mask words
+    // waves per SIMD the register budget is held to (512 registers): the
+    // tiles, the owner's panel rows and about 48 registers of the rest
+    static constexpr int WPE = TREGS + 48 + 8 * RPL * words <= 168 ? 3 : 2;
 };
 
 template <typename T> struct MTile;
 template <> struct MTile<float> {
     typedef float V __attribute__((ext_vector_type(4)));
     __device__ static int row(int g, int r) { return 4 * g + r; }
+    // bits of a row tile's 16-bit mask held in register r by some lane
+    __device__ static unsigned rbits(int r) { return 0x1111u << r; }
     __device__ static V mfma(float a, float b, V c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static void load4(const float* p, float (&v)[4]) {
+        const float4 q = *reinterpret_cast<const float4*>(p);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    }
+    __device__ static void store4(float* p, float a, float b, float c, float d) {
+        *reinterpret_cast<float4*>(p) = make_float4(a, b, c, d);
     }
 };
 template <> struct MTile<double> {
     typedef double V __attribute__((ext_vector_type(4)));
     __device__ static int row(int g, int r) { return g + 4 * r; }
+    __device__ static unsigned rbits(int r) { return 0xfu << (4 * r); }
     __device__ static V mfma(double a, double b, V c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    __device__ static void load4(const double* p, double (&v)[4]) {
+        const double2 q0 = reinterpret_cast<const double2*>(p)[0];
+        const double2 q1 = reinterpret_cast<const double2*>(p)[1];
+        v[0] = q0.x; v[1] = q0.y; v[2] = q1.x; v[3] = q1.y;
+    }
+    __device__ static void store4(double* p, double a, double b, double c, double d) {
+        reinterpret_cast<double2*>(p)[0] = make_double2(a, b);
+        reinterpret_cast<double2*>(p)[1] = make_double2(c, d);
+    }
 };
+// a wave-uniform double kept in scalar registers
+__device__ __forceinline__ double uniform(double x) {
+    return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(x)),
+                            __builtin_amdgcn_readfirstlane(__double2loint(x)));
+}
+// the value of lane l (per lane)
+__device__ __forceinline__ float lane_shfl(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(4 * l, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_shfl(double v, int l) {
+    const int lo = __builtin_amdgcn_ds_bpermute(4 * l, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(4 * l, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+// slot of panel column (or U row) c in the operand order (c mod 4, c div 4)
+__device__ __forceinline__ int operand_slot(int c) { return (c & 3) * 4 + (c >> 2); }
 
 template <int P, typename T, int WSEL>
 __global__ __launch_bounds__((64 * BlockShape<P, T, WSEL>::W))
@@ -828,15 +875,18 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
     using M = MTile<T>;
     using V = typename M::V;
     constexpr int n = S::n, N = S::N, NPAD = S::NPAD, RT = S::RT, NCT = S::NCT;
-    constexpr int W = S::W, CTW = S::CTW, RPL = S::RPL, LDP = S::LDP;
+    constexpr int W = S::W, CTW = S::CTW, RPL = S::RPL, LDP = S::LDP, LDG = S::LDG;
+    constexpr int NB = S::NB, MW = S::MW;
     constexpr int NP = P * P;
-    __shared__ T gbuf[2][NPAD * LDP];         // -G of the last two panels
-    __shared__ T pbuf[NPAD * LDP];            // panel in row layout
-    __shared__ T ubuf[W][16 * LDP];           // U rows of one tile, per wave
-    __shared__ int pivs[2][16];
+    __shared__ __align__(16) T gbuf[NB][NPAD * LDG];  // -G of the last three panels
+    __shared__ __align__(16) T ubuf[W][16 * LDG];     // U of one tile, per wave
+    __shared__ T pbuf[NPAD * LDP];                    // panel in row layout
+    __shared__ int pivs[NB][16];
+    __shared__ unsigned pmask[NB][MW];                // pivot rows of the panel
     // per row: 1 + its position among the panel's pivots, 0 if none
-    __shared__ __align__(4) unsigned char posb[2][NPAD];
+    __shared__ __align__(4) unsigned char posb[NB][NPAD];
     __shared__ unsigned char used[NPAD];
+    __shared__ double rhol[NPAD];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = lane >> 4, i = lane & 15;
@@ -866,15 +916,10 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
         }
     }
     for (int r = threadIdx.x; r < NPAD; r += blockDim.x) used[r] = 0;
-    // right-hand side h (FP64) on wave 0, lane-per-row
-    double rho[RPL];
-#pragma unroll
-    for (int s = 0; s < RPL; ++s) {
-        const int row = lane + 64 * s;
-        rho[s] = (w == 0 && row < n)
-                     ? a.h[size_t(row & 3) * a.nimp * NP + size_t(k) * NP + (row >> 2)]
-                     : 0.0;
-    }
+    // right-hand side h (FP64), one value per row, updated by wave 0
+    for (int row = threadIdx.x; row < NPAD; row += blockDim.x)
+        rhol[row] = row < n ? a.h[size_t(row & 3) * a.nimp * NP + size_t(k) * NP + (row >> 2)]
+                            : 0.0;
     __syncthreads();
 
     auto wave_sync = [&]() {
@@ -891,8 +936,8 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
                 pbuf[(16 * t + M::row(g, r)) * LDP + i] = tile[t][r];
     };
     // ---- panel factorisation by its owner (panel in pbuf): 16 Jordan
-    // exchanges on the panel's columns, -G to gbuf[j & 1], pivots to
-    // pivs[j & 1] and posb[j & 1]
+    // exchanges on the panel's columns; -G, pivots, positions and the pivot
+    // mask to slot j mod 3
     auto factor = [&](int j) {
         wave_sync();
         T x[RPL][16];
@@ -910,39 +955,38 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
         int pos[RPL];
 #pragma unroll
         for (int s = 0; s < RPL; ++s) pos[s] = 0;
-        int pv[16];
+        int pvv = 0;                                   // lane cc: pivot row of exchange cc
+        bool fail = false;
+        T ipv = T(0);                                  // lane cc: 1 / pivot of exchange cc
 #pragma unroll
         for (int cc = 0; cc < 16; ++cc) {
+            // some row is always unused, so the maximum names one; a zero
+            // pivot is flagged and its exchange leaves the tableau as it is
+            // (the result is discarded)
             unsigned key = 0;
 #pragma unroll
             for (int s = 0; s < RPL; ++s) {
-                const unsigned ks = pivot_key32(float(fabs(x[s][cc])), lane + 64 * s);
+                const unsigned ks = pivot_key32z(float(fabs(x[s][cc])), lane + 64 * s);
                 if (!usd[s] && ks > key) key = ks;
             }
             key = wave_max_u32(key);
-            int p;
-            T ip;
-            if (key != 0) {
-                p = 255 - int(key & 0xffu);
-                T piv = T(1);
+            const int p = 255 - int(key & 0xffu);
+            const bool bad = key < 0x200u;
+            fail = fail || bad;
+            T piv = lane_value(x[0][cc], p & 63);
 #pragma unroll
-                for (int s = 0; s < RPL; ++s)
-                    if (RPL == 1 || s == (p >> 6)) piv = lane_value(x[s][cc], p & 63);
-                if constexpr (sizeof(T) == 4) ip = __builtin_amdgcn_rcpf(piv);
-                else ip = T(1) / piv;
-            } else {
-                // no nonzero candidate: flag it, take the lowest unused row
-                // and leave the tableau as it is (the result is discarded)
-                if (lane == 0) *a.pivot_fail = 1;
-                unsigned fk = 0;
-#pragma unroll
-                for (int s = 0; s < RPL; ++s)
-                    if (!usd[s]) fk = max(fk, unsigned(255 - (lane + 64 * s)));
-                fk = wave_max_u32(fk);
-                p = 255 - int(fk);
-                ip = T(0);
+            for (int s = 1; s < RPL; ++s) {
+                const T o = lane_value(x[s][cc], p & 63);
+                piv = (p >> 6) == s ? o : piv;
             }
-            pv[cc] = p;
+            T ip;
+            if constexpr (sizeof(T) == 4) ip = __builtin_amdgcn_rcpf(piv);
+            else ip = T(1) / piv;
+            ip = bad ? T(0) : ip;
+            ipv = lane == cc ? ip : ipv;
+            asm volatile("" : "+v"(ipv));              // keep the select here
+            pvv = lane == cc ? p : pvv;
+            asm volatile("" : "+v"(pvv));
             const int sp = p >> 6, lp = p & 63;
             T gsv[RPL];
 #pragma unroll
@@ -962,58 +1006,81 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
             for (int s = 0; s < RPL; ++s) {
                 const bool me = lane + 64 * s == p;
                 x[s][cc] = me ? T(-1) : gsv[s];
-                if (me) { usd[s] = true; sig[s] = -ip; pos[s] = cc + 1; }
+                usd[s] = usd[s] || me;
+                pos[s] = me ? cc + 1 : pos[s];
+                asm volatile("" : "+v"(pos[s]));
             }
         }
+        if (fail && lane == 0) *a.pivot_fail = 1;
         // -G: pivot rows scaled by their factors; the rows of P hold
         // T[P,K]^-1, the others T[:,K] T[P,K]^-1
-        const int jb = j & 1;
+        const int jb = j % NB;
         T* gb = gbuf[jb];
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) {
+            // every lane takes part in the permute: a lane outside the
+            // exchange mask would supply 0
+            const T ipl = lane_shfl(ipv, max(pos[s] - 1, 0));
+            sig[s] = pos[s] ? -ipl : T(1);
+        }
 #pragma unroll
         for (int s = 0; s < RPL; ++s) {
             const int row = lane + 64 * s;
             if (row < NPAD) {
+                const T f = -sig[s];
 #pragma unroll
-                for (int cc = 0; cc < 16; ++cc) gb[row * LDP + cc] = -(sig[s] * x[s][cc]);
+                for (int q = 0; q < 4; ++q)
+                    M::store4(gb + row * LDG + 4 * q, f * x[s][q], f * x[s][4 + q],
+                              f * x[s][8 + q], f * x[s][12 + q]);
                 if (usd[s]) used[row] = 1;
                 posb[jb][row] = (unsigned char)pos[s];
             }
+            const unsigned long long bm = __ballot(pos[s] != 0);
+            if (lane == 0) {
+                if (2 * s < MW) pmask[jb][2 * s] = unsigned(bm);
+                if (2 * s + 1 < MW) pmask[jb][2 * s + 1] = unsigned(bm >> 32);
+            }
         }
         if (lane < 16) {
-            int pl = pv[0];
-#pragma unroll
-            for (int cc = 1; cc < 16; ++cc) pl = (lane == cc) ? pv[cc] : pl;
-            pivs[jb][lane] = pl;
+            pivs[jb][lane] = pvv;
             const int col = 16 * j + lane;
-            if (col < n) a.piv[size_t(k) * n + col] = pl;
+            if (col < n) a.piv[size_t(k) * n + col] = pvv;
         }
     };
 
-    // one tile: its pivot rows to LDS (U) and cleared, then tile += (-G) U
-    // with the A operands -G(16 t + i, 4 kk + g) read from LDS
-    auto update_tile = [&](int jb, V (&tile)[RT]) {
+    // one tile and panel slot b: the tile's pivot rows to LDS (U) and
+    // cleared, then tile += (-G) U
+    auto update_tile = [&](int b, V (&tile)[RT]) {
         T* ub = ubuf[w];
+        unsigned pm[MW];
+#pragma unroll
+        for (int q = 0; q < MW; ++q) pm[q] = __builtin_amdgcn_readfirstlane(pmask[b][q]);
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
+            const unsigned msk = (pm[(16 * t) >> 5] >> ((16 * t) & 31)) & 0xffffu;
+            if (msk == 0) continue;                    // uniform
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int pos = posb[jb][16 * t + M::row(g, r)];
-                if (pos) {
-                    ub[(pos - 1) * LDP + i] = tile[t][r];
+                if ((msk & M::rbits(r)) == 0) continue;  // uniform
+                const int rl = M::row(g, r);
+                if ((msk >> rl) & 1u) {
+                    const int u = posb[b][16 * t + rl] - 1;
+                    ub[i * LDG + operand_slot(u)] = tile[t][r];
                     tile[t][r] = T(0);
                 }
             }
         }
         wave_sync();
         T bop[4];
+        M::load4(ub + i * LDG + 4 * g, bop);
+        const T* gb = gbuf[b];
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) bop[kk] = ub[(4 * kk + g) * LDP + i];
-        const T* gb = gbuf[jb];
+        for (int t = 0; t < RT; ++t) {
+            T aop[4];
+            M::load4(gb + (16 * t + i) * LDG + 4 * g, aop);
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-            for (int t = 0; t < RT; ++t)
-                tile[t] = M::mfma(gb[(16 * t + i) * LDP + 4 * kk + g], bop[kk], tile[t]);
+            for (int kk = 0; kk < 4; ++kk) tile[t] = M::mfma(aop[kk], bop[kk], tile[t]);
+        }
         wave_sync();                                   // ub free for the next tile
     };
 
@@ -1023,44 +1090,45 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
     }
     for (int j = 0; j < RT; ++j) {
         __syncthreads();                               // panel j published
-        const int jb = j & 1;
+        const int b = j % NB;
         const int j1 = j + 1;
         const bool ahead = j1 < RT && w == j1 % W;     // uniform
         if (ahead) {
-            // the next panel's tile first, then its factorisation
+            // the next panel's tile first, then its factorisation; panel j
+            // reaches this wave's other tiles in the next period
 #pragma unroll
             for (int q = 0; q < CTW; ++q)
                 if (q == j1 / W) {
-                    update_tile(jb, acc[q]);
+                    update_tile(b, acc[q]);
                     to_panel(acc[q]);
                 }
             factor(j1);
         }
+        const bool late = j > 0 && w == j % W;         // deferred panel j - 1
 #pragma unroll
         for (int q = 0; q < CTW; ++q) {
             const int c = w + W * q;
-            if (c > j && c < NCT && !(ahead && c == j1)) update_tile(jb, acc[q]);
+            if (c > j && c < NCT && !ahead) {
+#pragma unroll
+                for (int e = 0; e < 2; ++e)
+                    if (e == 1 || late) update_tile(e == 0 ? (j + NB - 1) % NB : b, acc[q]);
+            }
         }
         if (w == 0) {                                  // right-hand side
             double rp[16];
 #pragma unroll
-            for (int cc = 0; cc < 16; ++cc) {
-                const int p = pivs[jb][cc];
-                double v = rho[0];
-#pragma unroll
-                for (int s0 = 1; s0 < RPL; ++s0) v = ((p >> 6) == s0) ? rho[s0] : v;
-                rp[cc] = lane_value(v, p & 63);
-            }
-            const T* gb = gbuf[jb];
+            for (int cc = 0; cc < 16; ++cc) rp[cc] = uniform(rhol[pivs[b][cc]]);
+            wave_sync();
+            const T* gb = gbuf[b];
 #pragma unroll
             for (int s = 0; s < RPL; ++s) {
                 const int row = lane + 64 * s;
                 if (row < NPAD) {
-                    double v = posb[jb][row] ? 0.0 : rho[s];
+                    double v = posb[b][row] ? 0.0 : rhol[row];
 #pragma unroll
                     for (int cc = 0; cc < 16; ++cc)
-                        v = fma(double(gb[row * LDP + cc]), rp[cc], v);
-                    rho[s] = v;
+                        v = fma(double(gb[row * LDG + operand_slot(cc)]), rp[cc], v);
+                    rhol[row] = v;
                 }
             }
         }
@@ -1081,13 +1149,8 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
                 if (row < n) G[size_t(col) * N + row] = acc[q][t][r];
             }
     }
-    if (w == 0) {
-#pragma unroll
-        for (int s = 0; s < RPL; ++s) {
-            const int row = lane + 64 * s;
-            if (row < n) a.yr[size_t(k) * n + row] = rho[s];
-        }
-    }
+    __syncthreads();
+    for (int row = threadIdx.x; row < n; row += blockDim.x) a.yr[size_t(k) * n + row] = rhol[row];
 }
 
 template <int P, typename T>

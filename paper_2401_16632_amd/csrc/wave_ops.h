@@ -57,11 +57,13 @@ __device__ __forceinline__ double wave_sum(double x) {
     return lane_value(x, 63);
 }
 
-// Wave-wide maximum of a 32-bit key by the same DPP row operations; every
-// lane gets the maximum.
+// Wave-wide maximum of a 32-bit key by the same DPP row operations; the
+// maximum ends in lane 63 and is returned to every lane.  Lanes the DPP
+// control leaves out read 0, the identity of the unsigned maximum, so each
+// step is a single v_max_u32 with a DPP source.
 template <int CTRL, int ROWMASK>
 __device__ __forceinline__ unsigned key32_dpp(unsigned x) {
-    return unsigned(__builtin_amdgcn_update_dpp(int(x), int(x), CTRL, ROWMASK, 0xf, false));
+    return unsigned(__builtin_amdgcn_update_dpp(0, int(x), CTRL, ROWMASK, 0xf, true));
 }
 __device__ __forceinline__ unsigned wave_max_u32(unsigned x) {
     x = max(x, key32_dpp<0xb1, 0xf>(x));        // quad_perm [1,0,3,2]
@@ -79,6 +81,14 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned x) {
 __device__ __forceinline__ unsigned pivot_key32(float mag, int row) {
     const unsigned b = __float_as_uint(mag) & 0xffffff00u;
     return b ? (b | unsigned(255 - row)) : 0u;
+}
+
+// The same key, never 0 for a candidate: magnitudes whose kept bits are 0
+// (zero among them) rank below every other, lowest row first, so the
+// maximum is always a row; a key below 0x200 marks a zero pivot.
+__device__ __forceinline__ unsigned pivot_key32z(float mag, int row) {
+    const unsigned b = __float_as_uint(mag) & 0xffffff00u;
+    return (b ? b : 0x100u) | unsigned(255 - row);
 }
 
 // pivot key: |value| (as FP32, order-preserving bits) above the complement

@@ -392,11 +392,12 @@ _ORACLE_STEPS_B = {}
 
 @pytest.mark.parametrize("name", ["c1_p1", "c1_p2", "cyl_p3", "cyl_p4", "c1_p5"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_blocked_condensation_steps(name, precision):
+@pytest.mark.parametrize("kernel", ["blocked", "blocked_w8"])
+def test_blocked_condensation_steps(name, precision, kernel):
     """The element elimination in panels of 16 exchanges with the update of
     the rest of the tableau on matrix-core tiles (every padded block count
-    p = 1 to 5): two IMEX steps against the oracle, 1e-11 in FP64 and 1e-8
-    with FP32 tableaux."""
+    p = 1 to 5, four or eight waves per element): two IMEX steps against
+    the oracle, 1e-11 in FP64 and 1e-8 with FP32 tableaux."""
     pr, u = _build(name)
     if name.startswith("c1"):
         u = fi.isentropic_vortex(pr.om.x, pr.om.y)
@@ -411,9 +412,11 @@ def test_blocked_condensation_steps(name, precision):
             seq.append(uo)
         _ORACLE_STEPS_B[name] = seq
     s = hp.Solver(hm, precision=precision, precond=precision, rtol=1e-10,
-                  newton_tol=1e-13, max_iters=3000, condense="blocked")
+                  newton_tol=1e-13, max_iters=3000, condense=kernel)
+    assert s.condense_choice()[0] == kernel
     stp = hp.ImexStepper(hm, s, "HIMEX2C")
     ud = dev(soa(u))
+    print("blocked steps:", name, precision, kernel, flush=True)
     tol = 1e-11 if precision == "fp64" else 1e-8
     for k in range(2):
         un, stats = stp.step(ud, dt)

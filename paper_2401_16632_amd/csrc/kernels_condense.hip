@@ -958,56 +958,66 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
         int pvv = 0;                                   // lane cc: pivot row of exchange cc
         bool fail = false;
         T ipv = T(0);                                  // lane cc: 1 / pivot of exchange cc
-#pragma unroll
-        for (int cc = 0; cc < 16; ++cc) {
-            // some row is always unused, so the maximum names one; a zero
-            // pivot is flagged and its exchange leaves the tableau as it is
-            // (the result is discarded)
+        // pivot search of one column: some row is always unused, so the
+        // maximum names one; a zero pivot is flagged and its exchange
+        // leaves the tableau as it is (the result is discarded)
+        auto column_key = [&](int c) {
             unsigned key = 0;
 #pragma unroll
             for (int s = 0; s < RPL; ++s) {
-                const unsigned ks = pivot_key32z(float(fabs(x[s][cc])), lane + 64 * s);
+                const unsigned ks = pivot_key32z(float(fabs(x[s][c])), lane + 64 * s);
                 if (!usd[s] && ks > key) key = ks;
             }
-            key = wave_max_u32(key);
+            return wave_max_u32(key);
+        };
+        unsigned key = column_key(0);
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc) {
             const int p = 255 - int(key & 0xffu);
             const bool bad = key < 0x200u;
             fail = fail || bad;
-            T piv = lane_value(x[0][cc], p & 63);
+            const int sp = p >> 6, lp = p & 63;
+            // the pivot row into scalar registers: one read per column from
+            // the pivot's slot, chosen by a uniform branch
+            T u[16];
 #pragma unroll
-            for (int s = 1; s < RPL; ++s) {
-                const T o = lane_value(x[s][cc], p & 63);
-                piv = (p >> 6) == s ? o : piv;
-            }
+            for (int s0 = 0; s0 < RPL; ++s0)
+                if (sp == s0)
+#pragma unroll
+                    for (int c2 = 0; c2 < 16; ++c2) u[c2] = lane_value(x[s0][c2], lp);
             T ip;
-            if constexpr (sizeof(T) == 4) ip = __builtin_amdgcn_rcpf(piv);
-            else ip = T(1) / piv;
+            if constexpr (sizeof(T) == 4) ip = __builtin_amdgcn_rcpf(u[cc]);
+            else ip = T(1) / u[cc];
             ip = bad ? T(0) : ip;
             ipv = lane == cc ? ip : ipv;
             asm volatile("" : "+v"(ipv));              // keep the select here
             pvv = lane == cc ? p : pvv;
             asm volatile("" : "+v"(pvv));
-            const int sp = p >> 6, lp = p & 63;
             T gsv[RPL];
+            bool me[RPL];
 #pragma unroll
-            for (int s = 0; s < RPL; ++s)
-                gsv[s] = (lane + 64 * s == p) ? T(0) : x[s][cc] * ip;
+            for (int s = 0; s < RPL; ++s) {
+                me[s] = lane + 64 * s == p;
+                gsv[s] = me[s] ? T(0) : x[s][cc] * ip;
+                usd[s] = usd[s] || me[s];
+            }
+            // the next pivot column first, and its search, ahead of the
+            // other columns of this exchange
+            if (cc + 1 < 16) {
+#pragma unroll
+                for (int s = 0; s < RPL; ++s) x[s][cc + 1] = fma(-gsv[s], u[cc + 1], x[s][cc + 1]);
+                key = column_key(cc + 1);
+            }
 #pragma unroll
             for (int c2 = 0; c2 < 16; ++c2) {
-                if (c2 == cc) continue;
-                T src = x[0][c2];
+                if (c2 == cc || c2 == cc + 1) continue;
 #pragma unroll
-                for (int s0 = 1; s0 < RPL; ++s0) src = (sp == s0) ? x[s0][c2] : src;
-                const T u = lane_value(src, lp);
-#pragma unroll
-                for (int s = 0; s < RPL; ++s) x[s][c2] = fma(-gsv[s], u, x[s][c2]);
+                for (int s = 0; s < RPL; ++s) x[s][c2] = fma(-gsv[s], u[c2], x[s][c2]);
             }
 #pragma unroll
             for (int s = 0; s < RPL; ++s) {
-                const bool me = lane + 64 * s == p;
-                x[s][cc] = me ? T(-1) : gsv[s];
-                usd[s] = usd[s] || me;
-                pos[s] = me ? cc + 1 : pos[s];
+                x[s][cc] = me[s] ? T(-1) : gsv[s];
+                pos[s] = me[s] ? cc + 1 : pos[s];
                 asm volatile("" : "+v"(pos[s]));
             }
         }
@@ -1084,36 +1094,31 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
         wave_sync();                                   // ub free for the next tile
     };
 
-    if (w == 0) {
-        to_panel(acc[0]);
-        factor(0);
-    }
-    for (int j = 0; j < RT; ++j) {
-        __syncthreads();                               // panel j published
-        const int b = j % NB;
+    // Period j: panel j is published (none in period -1); the owner of
+    // panel j + 1 brings that panel's tile up to date and factors it.  One
+    // inlined copy of the factorisation and one tile update per register
+    // tile keep the code small enough for the instruction cache, which the
+    // elements resident on a CU share at different points of the kernel.
+    for (int j = -1; j < RT; ++j) {
+        if (j >= 0) __syncthreads();                   // panel j published
+        const int b = (j + NB) % NB;
         const int j1 = j + 1;
         const bool ahead = j1 < RT && w == j1 % W;     // uniform
-        if (ahead) {
-            // the next panel's tile first, then its factorisation; panel j
-            // reaches this wave's other tiles in the next period
-#pragma unroll
-            for (int q = 0; q < CTW; ++q)
-                if (q == j1 / W) {
-                    update_tile(b, acc[q]);
-                    to_panel(acc[q]);
-                }
-            factor(j1);
-        }
         const bool late = j > 0 && w == j % W;         // deferred panel j - 1
 #pragma unroll
         for (int q = 0; q < CTW; ++q) {
             const int c = w + W * q;
-            if (c > j && c < NCT && !ahead) {
-#pragma unroll
-                for (int e = 0; e < 2; ++e)
-                    if (e == 1 || late) update_tile(e == 0 ? (j + NB - 1) % NB : b, acc[q]);
-            }
+            // panels this tile takes now (e = 0: j - 1, e = 1: j): the
+            // owner of panel j + 1 updates only that panel's tile and
+            // leaves panel j to the next period for its other tiles
+            int e0 = 2;
+            if (j >= 0 && c > j && c < NCT) e0 = ahead ? (c == j1 ? 1 : 2) : (late ? 0 : 1);
+#pragma unroll 1
+            for (int e = e0; e < 2; ++e) update_tile(e == 0 ? (j + NB - 1) % NB : b, acc[q]);
+            if (ahead && c == j1) to_panel(acc[q]);
         }
+        if (ahead) factor(j1);
+        if (j < 0) continue;
         if (w == 0) {                                  // right-hand side
             double rp[16];
 #pragma unroll

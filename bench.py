@@ -141,11 +141,13 @@ DAMPING = False
 
 
 def run_form(hp, torch, mesh, u0, dt, precision, precond, steps, warmup,
-             newton_tol):
+             newton_tol, graph=False):
+    """graph: Newton iterations replayed as recorded graphs; the timed region
+    then runs without any event timer (timers select the eager queue)."""
     solver = hp.Solver(mesh, precision=precision, precond=precond,
                        restart=30, max_iters=400, rtol=1e-6,
                        newton_max_iters=30, newton_tol=newton_tol,
-                       condense=CONDENSE, damping=DAMPING)
+                       condense=CONDENSE, damping=DAMPING, graph=graph)
     stp = hp.ImexStepper(mesh, solver, "HIMEX2C")
     ud = torch.from_numpy(u0).cuda()
     u = ud.clone()
@@ -153,10 +155,11 @@ def run_form(hp, torch, mesh, u0, dt, precision, precond, steps, warmup,
         un, _ = stp.step(u, dt)
         u = un.clone()
     torch.cuda.synchronize()
-    # timed region: only the condensation sweep (the roofline kernel) is
+    # timed region: only the condensation (the roofline kernel) is
     # bracketed by events; every timed launch adds two event records
-    solver.timing(only=["condense"])
-    impl_ms, newton, gmres = [], [], []
+    if not graph:
+        solver.timing(only=["condense"])
+    impl_ms, newton, gmres, replays = [], [], [], 0
     t0 = time.perf_counter()
     for _ in range(steps):
         un, stats = stp.step(u, dt)
@@ -165,9 +168,10 @@ def run_form(hp, torch, mesh, u0, dt, precision, precond, steps, warmup,
             impl_ms.append(s["implicit_ms"])
             newton.append(s["newton_iters"])
             gmres.append(s["gmres_iters"])
+            replays += s["graph_replays"]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    timers = solver.timing(False)
+    timers = solver.timing(False) if not graph else None
     out = u.cpu().numpy()
 
     def timed_pass(only):
@@ -188,6 +192,7 @@ def run_form(hp, torch, mesh, u0, dt, precision, precond, steps, warmup,
     phases = timed_pass(None)
     choice, cand = solver.condense_choice()
     res = dict(wall_s=wall, impl_ms=impl_ms, newton=newton, gmres=gmres,
+               graph_replays=replays,
                timers=timers, phases=phases, hbm=hbm, state=out,
                workspace=solver.workspace_bytes,
                condense=dict(kernel=choice, candidates_ms=cand))
@@ -318,8 +323,11 @@ def explicit_bytes(mesh):
     return mesh.Nex * (2 * 4 * mesh.Np * 8 + 64 + 4 * 32)
 
 
-FORMS = {"fp32": ("fp32", "fp32"), "fp32_bf16": ("fp32", "bf16"),
-         "fp64": ("fp64", "fp64")}
+# form: (tableau precision, preconditioner storage, Newton iterations as
+# replayed graphs)
+FORMS = {"fp32": ("fp32", "fp32", False), "fp32_bf16": ("fp32", "bf16", False),
+         "fp32_graph": ("fp32", "fp32", True),
+         "fp64": ("fp64", "fp64", False)}
 
 
 def oracle_first_stage(name, threads):
@@ -370,7 +378,9 @@ def oracle_leg(hp, torch, name, forms):
     mesh, u0, dt, _ = build_case(hp, name)
     errs = {}
     for f in forms:
-        ug, uh = first_stage(hp, torch, mesh, u0, dt, *FORMS[f], 1e-12)
+        if FORMS[f][2]:                  # the graph form repeats an eager form
+            continue
+        ug, uh = first_stage(hp, torch, mesh, u0, dt, *FORMS[f][:2], 1e-12)
         ue = ug.reshape(4, mesh.Ne, mesh.Np)[:, om.imp_elems]
         uo = hp.soa_from_elements(u_im)
         num = np.abs(ue - uo).max(axis=(1, 2))
@@ -489,7 +499,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c3_small", "c5"])
-    ap.add_argument("--forms", default="fp32,fp32_bf16,fp64")
+    ap.add_argument("--forms", default="fp32,fp32_bf16,fp64,fp32_graph")
     ap.add_argument("--no-efr", action="store_true",
                     help="skip the interior-embedded trace forms")
     ap.add_argument("--newton-tol", type=float, default=1e-10)
@@ -528,8 +538,8 @@ def main():
             raise SystemExit(f"unknown form {f}")
     results = {}
     for f in forms:
-        results[f] = run_form(hp, torch, mesh, u0, dt, *FORMS[f], args.steps,
-                              args.warmup, args.newton_tol)
+        results[f] = run_form(hp, torch, mesh, u0, dt, *FORMS[f][:2], args.steps,
+                              args.warmup, args.newton_tol, graph=FORMS[f][2])
         r = results[f]
         print(f"# form {f}: wall {r['wall_s']:.3f} s, implicit ms/stage "
               f"{np.mean(r['impl_ms']):.3f}, newton {np.mean(r['newton']):.2f}, "
@@ -559,6 +569,12 @@ def main():
     }
     for f, rr in results.items():
         line[f"{f}_form"] = form_summary(mesh, rr, FORMS[f][0])
+        if FORMS[f][2]:
+            line[f"{f}_form"]["graph_replays_per_stage"] = (rr["graph_replays"] /
+                                                            len(rr["impl_ms"]))
+    if "fp32_graph" in results and "fp32" in results:
+        line["fp32_graph_equals_fp32"] = bool(np.array_equal(results["fp32_graph"]["state"],
+                                                             results["fp32"]["state"]))
     if "fp64" in results:
         for f in results:
             if f != "fp64":
@@ -576,7 +592,7 @@ def main():
         mesh_e, u0e, dte, _ = build_case(hp, args.workload, efr=True)
         efr_states = {}
         for f in ("fp32", "fp64"):
-            rr = run_form(hp, torch, mesh_e, u0e, dte, *FORMS[f], args.steps,
+            rr = run_form(hp, torch, mesh_e, u0e, dte, *FORMS[f][:2], args.steps,
                           args.warmup, args.newton_tol)
             efr_states[f] = rr["state"]
             line[f"efr_{f}_form"] = form_summary(mesh_e, rr, f)
@@ -590,7 +606,7 @@ def main():
         mesh_d, u0d, dtd, _ = build_case(hp, args.workload, physics="edac")
         edac_states = {}
         for f in ("fp32", "fp64"):
-            rr = run_form(hp, torch, mesh_d, u0d, dtd, *FORMS[f], args.steps,
+            rr = run_form(hp, torch, mesh_d, u0d, dtd, *FORMS[f][:2], args.steps,
                           args.warmup, args.newton_tol)
             edac_states[f] = rr["state"]
             line[f"edac_{f}_form"] = form_summary(mesh_d, rr, f)

@@ -259,6 +259,19 @@ typedef struct {
                                  guards impulsive starts at high local CFL,
                                  where a full step can leave the admissible
                                  states); 0: full steps only                  */
+    int32_t iteration_graph;  /* 1: inside Newton (Jacobian re-formed every
+                                 iteration, timers off) the elimination,
+                                 assembly, preconditioner set-up, the first
+                                 chunk of the trace solve and the checks of
+                                 the next iterate are recorded as a HIP graph
+                                 once per chunk length and stage arguments
+                                 and replayed on the caller's stream: the same
+                                 kernels in the same order as the eager queue,
+                                 hence the same results bit for bit; a solve
+                                 that needs more steps goes on eagerly.
+                                 The graphs name the stage buffers and the
+                                 workspace; rebinding the workspace drops
+                                 them.  0: eager launches only               */
 } hfr_opts;
 /* HFR_CK_SWEEP: register-resident Gauss-Jordan sweep on the vector ALUs, one
  * exchange per step; HFR_CK_BLOCKED: panels of 16 exchanges, the update of
@@ -281,6 +294,8 @@ typedef struct {
                                  stage, from its entry (queued work drained)
                                  to R_i ready: u*, initial trace, every
                                  Newton iteration, R_i                      */
+    int32_t graph_replays;    /* Newton iterations run as a replayed graph
+                                 (hfr_opts.iteration_graph)                 */
 } hfr_newton_stats;
 
 /*

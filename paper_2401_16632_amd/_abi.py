@@ -52,7 +52,8 @@ class HfrOpts(Structure):
                 ("newton_tol", c_double), ("keep_blocks", c_int32),
                 ("jacobian_lag", c_int32), ("gmres_cgs_passes", c_int32),
                 ("caller_workspace", c_int32), ("condense_kernel", c_int32),
-                ("newton_damping", c_int32)]
+                ("newton_damping", c_int32),
+                ("iteration_graph", c_int32)]
 
 
 class HfrSolveStats(Structure):
@@ -62,7 +63,8 @@ class HfrSolveStats(Structure):
 
 class HfrNewtonStats(Structure):
     _fields_ = [("newton_iters", c_int32), ("gmres_iters", c_int32),
-                ("residual", c_double), ("implicit_ms", c_double)]
+                ("residual", c_double), ("implicit_ms", c_double),
+                ("graph_replays", c_int32)]
 
 
 class ImexTableau(Structure):

@@ -202,7 +202,8 @@ class Solver:
     def __init__(self, mesh, precision="fp64", precond="fp64", restart=30,
                  max_iters=600, rtol=1e-10, newton_max_iters=25,
                  newton_tol=1e-13, keep_blocks=False, jacobian_lag=0,
-                 cgs_passes=1, workspace=None, condense="auto", damping=False):
+                 cgs_passes=1, workspace=None, condense="auto", damping=False,
+                 graph=False):
         """workspace: None (the library allocates its working memory) or
         "torch" (a uint8 CUDA tensor allocated here and bound with
         hfr_solver_bind_workspace; kept as self.workspace)."""
@@ -227,6 +228,7 @@ class Solver:
             raise ValueError(f"condense must be one of {sorted(ck)}")
         o.condense_kernel = ck[condense]
         o.newton_damping = 1 if damping else 0
+        o.iteration_graph = 1 if graph else 0
         self.opts = o
         self.workspace = None
         ws = ctypes.c_size_t()
@@ -408,7 +410,8 @@ class ImexStepper:
                 stats.append(dict(newton_iters=ns.newton_iters,
                                   gmres_iters=ns.gmres_iters,
                                   residual=ns.residual,
-                                  implicit_ms=ns.implicit_ms))
+                                  implicit_ms=ns.implicit_ms,
+                                  graph_replays=ns.graph_replays))
         if filter is not None:
             m.modal_filter(self.u, stream=stream, **filter)
         self.stats = stats

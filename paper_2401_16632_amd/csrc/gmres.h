@@ -17,6 +17,10 @@ struct GmresState {
     double inv_norm, beta, bnorm, target;
     double h1[kGmresMaxK], h2[kGmresMaxK];
     double cs[kGmresMaxK], sn[kGmresMaxK];
+    // publication counters: the restart kernel and the Newton norms kernel
+    // number what they publish from these, so a launch recorded once (in a
+    // graph) and replayed still publishes a fresh sequence number
+    long long pub_seq, norm_seq;
     double g[kGmresMaxK + 1];    // running right-hand side of the least squares
     double gf[kGmresMaxK + 1];   // rotated (final) right-hand side
     double H[(kGmresMaxK + 1) * kGmresMaxK];
@@ -63,8 +67,9 @@ hipError_t launch_precondition_matrix(int nblocks, int bs, const int* col,
                                       float* Lt32, hipStream_t st);
 // r = t - L x, beta = |r|, new cycle; cond: only if the cycle has ended
 // cap: the host ends the solve here (iteration cap)
+// (publishes the state with the next number of gs->pub_seq)
 hipError_t launch_gmres_restart(const GmresArgs& a, double* x,
-                                double* w, int first, int cond, int cap, long long seq,
+                                double* w, int first, int cond, int cap,
                                 hipStream_t st);
 hipError_t launch_arnoldi_product(const GmresArgs& a, int j, int fin_prev,
                                   const double* wcur, double* wnxt, hipStream_t st);

@@ -249,14 +249,15 @@ hipError_t launch_absmax(int N, const double* x, double* partial, int nblk,
 // mapped for the device), *go = 1 when the gate (if any) is open and either
 // exceeds the tolerance (NaN included), else 0; the tolerance is tol, or
 // tol * max(1, *tol_scale) with tol_scale (device memory) set, and is
-// written to out[2]; flags[0..1] copied to flags_out (if set); then seq is
-// written to seq_out (if set) behind a system-scope fence, so a host that
-// sees it sees the rest; partial needs 2048 doubles
+// written to out[2]; flags[0..1] copied to flags_out (if set); then the
+// next number of the device counter *seq_ctr is written to seq_out (if set)
+// behind a system-scope fence, so a host that sees it sees the rest;
+// partial needs 2048 doubles
 hipError_t launch_newton_norms(int Nx, const double* x, int Ny, const double* y,
                                double* partial, double tol, const double* tol_scale,
                                double* out, int* go,
                                const int* gate, const int* flags, int* flags_out,
-                               long long* seq_out, long long seq, hipStream_t st);
+                               long long* seq_out, long long* seq_ctr, hipStream_t st);
 hipError_t launch_trace_gather_g(int ntp, int P, const int* tpside,
                                  const double* gk, double* g,
                                  hipStream_t st);
@@ -266,7 +267,7 @@ hipError_t launch_gather_g_norms(int ntp, const int* tpside, const double* gk, d
                                  int Nx, const double* x, double* partial, double tol,
                                  const double* tol_scale, double* out, int* go,
                                  const int* gate, const int* flags,
-                                 int* flags_out, long long* seq_out, long long seq,
+                                 int* flags_out, long long* seq_out, long long* seq_ctr,
                                  hipStream_t st);
 
 }  // namespace hfr

@@ -700,7 +700,7 @@ __global__ __launch_bounds__(256) void k_gmres_residual(GmresArgs a,
 
 // beta = |r|, new cycle (one workgroup)
 __global__ __launch_bounds__(kThr) void k_gmres_restart(GmresArgs a, int first, int cond,
-                                                        int cap, long long seq) {
+                                                        int cap) {
     GmresState* gs = a.gs;
     __shared__ double fin[kGmresMaxK];
     const bool act = !cond || gs->done;            // uniform
@@ -752,6 +752,8 @@ __global__ __launch_bounds__(kThr) void k_gmres_restart(GmresArgs a, int first, 
         p->beta = gs->beta;
         p->bnorm = gs->bnorm;
         p->target = gs->target;
+        const long long seq = gs->pub_seq + 1;
+        gs->pub_seq = seq;
         __threadfence_system();
         *reinterpret_cast<volatile long long*>(&p->seq) = seq;
     }
@@ -977,12 +979,11 @@ hipError_t launch_precondition_matrix(int nblocks, int bs, const int* col,
 }
 
 hipError_t launch_gmres_restart(const GmresArgs& a, double* x,
-                                double* w, int first, int cond, int cap, long long seq,
+                                double* w, int first, int cond, int cap,
                                 hipStream_t st) {
     hipLaunchKernelGGL(k_gmres_residual, dim3(a.nblkA), dim3(256), 0, st, a, x,
                        w, first, cond);
-    hipLaunchKernelGGL(k_gmres_restart, dim3(1), dim3(kThr), 0, st, a, first, cond, cap,
-                       seq);
+    hipLaunchKernelGGL(k_gmres_restart, dim3(1), dim3(kThr), 0, st, a, first, cond, cap);
     return hipGetLastError();
 }
 

@@ -447,7 +447,7 @@ __global__ void k_absmax2_final(int nbx, int nby, const double* partial, double 
                                 const double* tol_scale,
                                 double* out, int* go, const int* gate,
                                 const int* flags, int* flags_out,
-                                long long* seq_out, long long seq) {
+                                long long* seq_out, long long* seq_ctr) {
     __shared__ double red[2][256];
     double mx = 0.0, my = 0.0;
     for (int i = threadIdx.x; i < nbx; i += blockDim.x) {
@@ -482,6 +482,8 @@ __global__ void k_absmax2_final(int nbx, int nby, const double* partial, double 
             flags_out[1] = flags[1];
         }
         if (seq_out) {                    // published after the values above
+            const long long seq = *seq_ctr + 1;
+            *seq_ctr = seq;
             __threadfence_system();
             *reinterpret_cast<volatile long long*>(seq_out) = seq;
         }
@@ -492,13 +494,13 @@ hipError_t launch_newton_norms(int Nx, const double* x, int Ny, const double* y,
                                double* partial, double tol, const double* tol_scale,
                                double* out, int* go,
                                const int* gate, const int* flags, int* flags_out,
-                               long long* seq_out, long long seq, hipStream_t st) {
+                               long long* seq_out, long long* seq_ctr, hipStream_t st) {
     const int nbx = std::min(1024, std::max(1, (Nx + kThreads - 1) / kThreads));
     const int nby = std::min(1024, std::max(1, (Ny + kThreads - 1) / kThreads));
     hipLaunchKernelGGL(k_absmax2_partial, dim3(nbx + nby), dim3(kThreads), 0, st, Nx, x,
                        nbx, Ny, y, partial);
     hipLaunchKernelGGL(k_absmax2_final, dim3(1), dim3(256), 0, st, nbx, nby, partial, tol,
-                       tol_scale, out, go, gate, flags, flags_out, seq_out, seq);
+                       tol_scale, out, go, gate, flags, flags_out, seq_out, seq_ctr);
     return hipGetLastError();
 }
 
@@ -698,14 +700,14 @@ hipError_t launch_gather_g_norms(int ntp, const int* tpside, const double* gk, d
                                  int Nx, const double* x, double* partial, double tol,
                                  const double* tol_scale, double* out, int* go,
                                  const int* gate, const int* flags,
-                                 int* flags_out, long long* seq_out, long long seq,
+                                 int* flags_out, long long* seq_out, long long* seq_ctr,
                                  hipStream_t st) {
     const int nbx = std::min(1024, std::max(1, (Nx + kThreads - 1) / kThreads));
     const int nby = std::min(1024, std::max(1, (4 * ntp + kThreads - 1) / kThreads));
     hipLaunchKernelGGL(k_gather_g_absmax, dim3(nbx + nby), dim3(kThreads), 0, st, ntp,
                        tpside, gk, g, Nx, x, nbx, partial);
     hipLaunchKernelGGL(k_absmax2_final, dim3(1), dim3(256), 0, st, nbx, nby, partial, tol,
-                       tol_scale, out, go, gate, flags, flags_out, seq_out, seq);
+                       tol_scale, out, go, gate, flags, flags_out, seq_out, seq_ctr);
     return hipGetLastError();
 }
 

@@ -111,6 +111,19 @@ struct hfr_solver_s {
     struct Pend { hipEvent_t a, b; int cat; };
     std::vector<Pend> pending;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+    // graph form of a Newton iteration: one recorded graph per first-chunk
+    // length and per stage arguments, replayed on the caller's stream
+    hipStream_t cst = nullptr;   // stream the graphs are recorded on
+    struct IterGraph {
+        int K;
+        const double* u;
+        const double* uhat;
+        const double* ustar;
+        double aii_dt;
+        hipGraph_t g;
+        hipGraphExec_t x;
+    };
+    std::vector<IterGraph> graphs;
 };
 
 namespace {
@@ -167,8 +180,19 @@ fr_status dalloc(T** p, size_t count, size_t& total) {
     return FR_OK;
 }
 
+void drop_graphs(hfr_solver_s* s) {
+    for (auto& g : s->graphs) {
+        (void)hipGraphExecDestroy(g.x);
+        (void)hipGraphDestroy(g.g);
+    }
+    s->graphs.clear();
+}
+
 void free_solver(hfr_solver_s* s) {
     tflush(s);
+    drop_graphs(s);
+    if (s->cst) (void)hipStreamDestroy(s->cst);
+    s->cst = nullptr;
     if (s->hpin) (void)hipHostFree(s->hpin);
     s->hpin = nullptr;
     for (auto& p : s->pool) {
@@ -186,6 +210,12 @@ void plan(hfr_solver_s* s, T** p, size_t count) {
     s->ws_items.push_back({reinterpret_cast<void**>(p), count * sizeof(T)});
 }
 
+constexpr int kPinDoubles = 64;
+constexpr int kPinGmres = 8;
+
+constexpr int kPinNormSeq = 3;    // long long at double slot 3
+constexpr int kPinFlags = 4;      // two int32 at double slot 4
+
 constexpr size_t ws_align(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Carves the working buffers from `base` (256-byte aligned pieces in plan
@@ -200,6 +230,11 @@ fr_status bind_internal(hfr_solver_s* s, char* base) {
         hipMemset(s->counters, 0, 16) != hipSuccess ||
         hipMemset(s->gs, 0, sizeof(GmresState)) != hipSuccess)
         return fail(FR_E_DEVICE, "clearing the solver workspace failed");
+    // the device publication counters restart from zero, and so do the
+    // host's expectations and the published marks
+    s->seq_norms = s->seq_gmres = 0;
+    if (s->hpin) std::memset(s->hpin, 0, sizeof(double) * kPinDoubles);
+    drop_graphs(s);                    // they name the old buffers
     s->have_factors = false;
     s->ws_bound = true;
     return FR_OK;
@@ -211,11 +246,6 @@ fr_status need_workspace(const hfr_solver_s* s) {
                                             "(hfr_solver_bind_workspace)");
 }
 
-constexpr int kPinDoubles = 64;
-constexpr int kPinGmres = 8;
-
-constexpr int kPinNormSeq = 3;    // long long at double slot 3
-constexpr int kPinFlags = 4;      // two int32 at double slot 4
 
 // Kernels write what the host reads (Newton norms, GMRES state) straight
 // into the pinned buffer, a sequence number last behind a system-scope
@@ -501,9 +531,11 @@ GmresArgs gmres_args(hfr_solver_s* s) {
 // chain (optional): work queued after every chunk's end-of-cycle kernels,
 // gated on the device by the solve's `finished` flag, that records the
 // readback mark itself; *chained tells whether it ran for a finished solve.
+// pre >= 0: the start and a first chunk of `pre` steps, with its end-of-cycle
+// kernels and the chain, are already queued (a replayed iteration graph)
 fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
                 hipStream_t st, const std::function<fr_status()>& chain = nullptr,
-                bool* chained = nullptr, bool verify = true) {
+                bool* chained = nullptr, bool verify = true, int pre = -1) {
     if (chained) *chained = false;
     const int N = s->N;
     hfr_solve_stats loc{};
@@ -521,8 +553,8 @@ fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
                   "readback size");
     GmresPublish hs{};
     // the restart kernel, last of every chunk's sequence, publishes the state
-    auto fetch = [&]() -> fr_status {
-        fr_status e = chain ? chain() : FR_OK;
+    auto fetch = [&](bool run_chain) -> fr_status {
+        fr_status e = chain && run_chain ? chain() : FR_OK;
         if (e) return e;
         // the chain publishes the norms after the restart kernel's state
         if (chain) e = wait_seq(s, s->hpin + kPinNormSeq, s->seq_norms, st);
@@ -534,13 +566,21 @@ fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
             return fail(FR_E_NONFINITE, "non-finite trace residual");
         return FR_OK;
     };
-    HIP_TRY(launch_gmres_restart(a, x, W0, 1, 0, 0, ++s->seq_gmres, st));
+    if (pre < 0) {
+        HIP_TRY(launch_gmres_restart(a, x, W0, 1, 0, 0, st));
+        ++s->seq_gmres;
+    }
     int launched = 0;
     int chunk = std::max(2, std::min(R, s->last_gmres_iters + 1));
     int cycles_seen = 0;
     int j = 0;
     fr_status e;
     for (;;) {
+        if (pre >= 0) {                          // the recorded first chunk
+            j = launched = pre;
+            pre = -1;
+            if ((e = fetch(false))) return e;
+        } else {
         const int steps = std::max(0, std::min(std::min(chunk, R - j), maxit - launched));
         for (int c = 0; c < steps; ++c, ++j) {
             double* wc = j % 2 ? W1 : W0;
@@ -555,8 +595,10 @@ fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
         // the update kernel first finishes the chunk's last column
         const int cap = launched >= maxit ? 1 : 0;
         HIP_TRY(launch_gmres_update(a, x, 1 - cap, steps > 0 ? j - 1 : -1, st));
-        HIP_TRY(launch_gmres_restart(a, x, W0, 0, 1 - cap, cap, ++s->seq_gmres, st));
-        if ((e = fetch())) return e;
+        HIP_TRY(launch_gmres_restart(a, x, W0, 0, 1 - cap, cap, st));
+        ++s->seq_gmres;
+        if ((e = fetch(true))) return e;
+        }
         if (hs.cycles != cycles_seen) {          // the cycle ended and restarted
             cycles_seen = hs.cycles;
             if (hs.finished) {
@@ -576,6 +618,30 @@ fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
     if (stats) *stats = loc;
     if (!hs.converged) return fail(FR_E_NOT_CONVERGED, "GMRES iteration cap reached");
     return FR_OK;
+}
+
+// The start of a solve inside Newton and its first chunk of K steps, as the
+// first round of gmres() queues them (estimate-trusting cycles, no iteration
+// cap inside the chunk), then the chain: the part of a Newton iteration a
+// graph records.
+fr_status gmres_first_chunk(hfr_solver_s* s, double* x, int K, hipStream_t q,
+                            const std::function<fr_status()>& chain) {
+    GmresArgs a = gmres_args(s);
+    a.verify = 0;
+    double* W0 = s->W;
+    double* W1 = s->W + s->N;
+    HIP_TRY(launch_gmres_restart(a, x, W0, 1, 0, 0, q));
+    ++s->seq_gmres;
+    for (int j = 0; j < K; ++j) {
+        double* wc = j % 2 ? W1 : W0;
+        double* wn = j % 2 ? W0 : W1;
+        HIP_TRY(launch_arnoldi_product(a, j, j == 0 ? 1 : 0, wc, wn, q));
+        HIP_TRY(launch_arnoldi_orth(a, j, wn, q));
+    }
+    HIP_TRY(launch_gmres_update(a, x, 1, K - 1, q));
+    HIP_TRY(launch_gmres_restart(a, x, W0, 0, 1, 0, q));
+    ++s->seq_gmres;
+    return chain();
 }
 
 // Process-wide choice of the Schur-only condensation kernel per (order,
@@ -667,22 +733,25 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
     // the pinned buffer, the readback mark, then (unless the Jacobian is
     // reused) the next linearisation's fill, which the device skips when the
     // norms pass the test or the gate is closed.
+    // the stream the chain below is queued on (the caller's, or the one an
+    // iteration graph is recorded on)
+    hipStream_t qs = st;
     auto queue_checks = [&](const int* gate) -> fr_status {
         // the HFR gather of g also takes the norms' partial maxima
-        fr_status e2 = residual_internal(s, u, uhat, ustar, aii_dt, nullptr, st, gate,
+        fr_status e2 = residual_internal(s, u, uhat, ustar, aii_dt, nullptr, qs, gate,
                                          m->efr);
         if (e2) return e2;
         if (m->efr)
             HIP_TRY(launch_newton_norms(nu, s->h, 4 * m->Ntp, s->g, s->scratch, rtol,
                                         s->dscale, s->dpin, s->go, gate, s->flags, flags_pub,
-                                        seq_pub,
-                                        ++s->seq_norms, st));
+                                        seq_pub, &s->gs->norm_seq, qs));
         else
             HIP_TRY(launch_gather_g_norms(m->Ntp, m->d_tpside, s->gk, s->g, nu, s->h,
                                           s->scratch, rtol, s->dscale, s->dpin, s->go, gate,
                                           s->flags,
-                                          flags_pub, seq_pub, ++s->seq_norms, st));
-        if (spec && (e2 = condense_fill(s, u, uhat, aii_dt, s->go, st, true))) return e2;
+                                          flags_pub, seq_pub, &s->gs->norm_seq, qs));
+        ++s->seq_norms;
+        if (spec && (e2 = condense_fill(s, u, uhat, aii_dt, s->go, qs, true))) return e2;
         return FR_OK;
     };
     // After each GMRES chunk the update of the Newton iterate and the next
@@ -690,12 +759,64 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
     // wait for the solve also covers them and the device does not idle.
     const int* gate = &s->gs->finished;
     auto after_solve = [&]() -> fr_status {
-        int tk = tbegin(s, HFR_T_RECOVER, st);
+        int tk = tbegin(s, HFR_T_RECOVER, qs);
         HIP_TRY(launch_recover_update(m->ops, m->efr, m->Nim, s->M, s->opts.precision,
                                       s->piv, s->yr, m->d_trace_map, s->duhat, s->du,
-                                      m->Ne, m->d_imp, u, 4 * m->Ntp, uhat, st, gate));
-        tend(s, tk, st);
+                                      m->Ne, m->d_imp, u, 4 * m->Ntp, uhat, qs, gate));
+        tend(s, tk, qs);
         return queue_checks(gate);
+    };
+    // Graph form (hfr_opts.iteration_graph): the linearisation's elimination,
+    // assembly and preconditioner, the start and first chunk of the trace
+    // solve, and the chain are recorded once per first-chunk length K and
+    // stage arguments, then replayed; the sequence numbers they publish come
+    // from device counters, so a replay is indistinguishable from the eager
+    // queue.  Later chunks of a solve that needs more than K steps are
+    // queued eagerly by gmres().
+    auto replay_iteration = [&](int K) -> fr_status {
+        hfr_solver_s::IterGraph* gr = nullptr;
+        for (auto& g : s->graphs)
+            if (g.K == K && g.u == u && g.uhat == uhat && g.ustar == ustar &&
+                g.aii_dt == aii_dt)
+                gr = &g;
+        if (!gr) {
+            if (!s->cst) HIP_TRY(hipStreamCreateWithFlags(&s->cst, hipStreamNonBlocking));
+            const long long sg = s->seq_gmres, sn = s->seq_norms;
+            qs = s->cst;
+            HIP_TRY(hipStreamBeginCapture(s->cst, hipStreamCaptureModeThreadLocal));
+            fr_status e2 = condense_internal(s, u, uhat, aii_dt, s->cst, true, true);
+            if (!e2) e2 = gmres_first_chunk(s, s->duhat, K, s->cst, after_solve);
+            hipGraph_t g = nullptr;
+            const hipError_t ce = hipStreamEndCapture(s->cst, &g);
+            qs = st;
+            s->seq_gmres = sg;                 // counted again at each replay
+            s->seq_norms = sn;
+            if (e2 || ce != hipSuccess || !g) {
+                if (g) (void)hipGraphDestroy(g);
+                return e2 ? e2 : fail(FR_E_DEVICE, std::string("recording the Newton "
+                                                               "iteration: ") +
+                                                       hipGetErrorString(ce));
+            }
+            hipGraphExec_t x = nullptr;
+            const hipError_t ie = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+            if (ie != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                return fail(FR_E_DEVICE, std::string("hipGraphInstantiate: ") +
+                                             hipGetErrorString(ie));
+            }
+            if (s->graphs.size() >= 8) {       // keep a handful (K, stage pointers)
+                (void)hipGraphExecDestroy(s->graphs.front().x);
+                (void)hipGraphDestroy(s->graphs.front().g);
+                s->graphs.erase(s->graphs.begin());
+            }
+            s->graphs.push_back({K, u, uhat, ustar, aii_dt, g, x});
+            gr = &s->graphs.back();
+        }
+        HIP_TRY(hipGraphLaunch(gr->x, st));
+        s->seq_gmres += 2;                     // the two restart kernels
+        s->seq_norms += 1;                     // the chain's norms
+        ++loc.graph_replays;
+        return FR_OK;
     };
     // damped Newton: a step that leaves a non-finite residual is halved (at
     // most seven times) by moving the iterate back along du, duhat
@@ -737,14 +858,22 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         }
         const bool relin = lag <= 0 || !s->have_factors ||
                            (it == 0 && (s->stage_calls % lag) == 0);
+        int pre = -1;
         if (relin) {
             // first Schur-only linearisation with the automatic choice: pick
             // the condensation kernel (the tableaux are filled again after)
             if (spec && s->ck < 0 && s->opts.condense_kernel == HFR_CK_AUTO &&
                 (e = tune_condense(s, u, uhat, aii_dt, st)))
                 return e;
-            // factors that are never reused need only the Schur part
-            if ((e = condense_internal(s, u, uhat, aii_dt, st, spec, lag <= 0))) return e;
+            const int K = std::max(2, std::min(s->restart, s->last_gmres_iters + 1));
+            if (spec && s->opts.iteration_graph && !s->timing && s->N > 0 &&
+                K < s->opts.gmres_max_iters) {
+                if ((e = replay_iteration(K))) return e;
+                pre = K;
+            } else {
+                // factors that are never reused need only the Schur part
+                if ((e = condense_internal(s, u, uhat, aii_dt, st, spec, lag <= 0))) return e;
+            }
             s->have_factors = lag > 0;
         } else {
             if ((e = recondense_rhs_internal(s, st))) return e;
@@ -754,7 +883,7 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         int tk = tbegin(s, HFR_T_TRACE_SOLVE, st);
         // inside Newton a cycle whose residual estimate is on target ends the
         // solve (the FP64 residuals of the next iterate are checked anyway)
-        e = gmres(s, s->duhat, &ks, st, after_solve, &chained, false);
+        e = gmres(s, s->duhat, &ks, st, after_solve, &chained, false, pre);
         tend(s, tk, st);
         if (s->verbose)
             fprintf(stderr, "[hfr]   gmres its %d restarts %d relres %.3e status %d\n",
@@ -802,7 +931,8 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
         o->jacobian_lag < 0 || o->gmres_cgs_passes < 0 || o->gmres_cgs_passes > 2 ||
         (o->caller_workspace != 0 && o->caller_workspace != 1) ||
         o->condense_kernel < HFR_CK_AUTO || o->condense_kernel > HFR_CK_BLOCKED_W8 ||
-        (o->newton_damping != 0 && o->newton_damping != 1))
+        (o->newton_damping != 0 && o->newton_damping != 1) ||
+        (o->iteration_graph != 0 && o->iteration_graph != 1))
         return fail(FR_E_INVALID, "bad tolerance or iteration cap");
     auto s = new hfr_solver_s();
     s->mesh = mesh;

@@ -101,6 +101,16 @@ hipError_t launch_efr_transform(const RefOps& ops, int nimp, void* M,
     return hipGetLastError();
 }
 
+__device__ __forceinline__ void load4_aligned(const float* p, float (&q)[4]) {
+    const float4 x = *reinterpret_cast<const float4*>(p);
+    q[0] = x.x; q[1] = x.y; q[2] = x.z; q[3] = x.w;
+}
+__device__ __forceinline__ void load4_aligned(const double* p, double (&q)[4]) {
+    const double2 x = reinterpret_cast<const double2*>(p)[0];
+    const double2 y = reinterpret_cast<const double2*>(p)[1];
+    q[0] = x.x; q[1] = x.y; q[2] = y.x; q[3] = y.y;
+}
+
 // node blocks (4x4, column-major) of L from the transformed element Schur
 // blocks, then t = -g - sum over node slots of sum_q phi_i(x_q) z
 template <typename T>
@@ -110,19 +120,38 @@ __global__ void k_efr_assemble(RefOps og, EfrAssembleLaunch a) {
     __syncthreads();
     const int N = a.n + a.m, P = a.P;
     const T* M = reinterpret_cast<const T*>(a.M);
-    const long nb = long(a.nblocks) * 16;
-    for (long idx = blockIdx.x * long(blockDim.x) + threadIdx.x; idx < nb;
-         idx += long(gridDim.x) * blockDim.x) {
-        const int b = int(idx >> 4), rc = int(idx & 15);
-        const int v = rc & 3, w = rc >> 2;
-        double val = 0.0;
+    // one thread per node block: each contribution is a 4x4 sub-block of an
+    // element's Schur block, four columns of four adjacent entries (16-byte
+    // aligned: N, n and the slot offsets are multiples of 4)
+    for (long b = blockIdx.x * long(blockDim.x) + threadIdx.x; b < a.nblocks;
+         b += long(gridDim.x) * blockDim.x) {
+        double val[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) val[e] = 0.0;
         for (int c = a.cptr[b]; c < a.cptr[b + 1]; ++c) {
             const int* ct = a.contrib + 3 * size_t(c);
-            const size_t row = a.n + ct[1] * 4 + v, col = a.n + ct[2] * 4 + w;
-            val += double(M[size_t(ct[0]) * N * N + col * N + row]);
+            const T* src = M + size_t(ct[0]) * N * N + size_t(a.n + ct[2] * 4) * N +
+                           a.n + ct[1] * 4;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                T q[4];
+                load4_aligned(src + size_t(w) * N, q);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) val[4 * w + v] += double(q[v]);
+            }
         }
-        if (a.L64) a.L64[idx] = val;
-        if (a.L32) a.L32[idx] = float(val);
+        if (a.L64) {
+#pragma unroll
+            for (int e = 0; e < 16; e += 2)
+                *reinterpret_cast<double2*>(a.L64 + 16 * b + e) = make_double2(val[e], val[e + 1]);
+        }
+        if (a.L32) {
+#pragma unroll
+            for (int e = 0; e < 16; e += 4)
+                *reinterpret_cast<float4*>(a.L32 + 16 * b + e) =
+                    make_float4(float(val[e]), float(val[e + 1]), float(val[e + 2]),
+                                float(val[e + 3]));
+        }
     }
     const long nt = long(a.nnodes) * 4;
     for (long idx = blockIdx.x * long(blockDim.x) + threadIdx.x; idx < nt;
@@ -142,7 +171,7 @@ __global__ void k_efr_assemble(RefOps og, EfrAssembleLaunch a) {
 
 hipError_t launch_efr_assemble(const RefOps& ops, const EfrAssembleLaunch& a,
                                hipStream_t st) {
-    long work = std::max(long(a.nblocks) * 16, long(a.nnodes) * 4);
+    long work = std::max(long(a.nblocks), long(a.nnodes) * 4);
     if (work == 0) return hipSuccess;
     int grid = std::min(blocks_for(work), 65536);
     if (a.precision == HFR_PREC_FP64)

@@ -814,6 +814,14 @@ struct BlockShape {
     // waves per SIMD the register budget is held to (512 registers): the
     // tiles, the owner's panel rows and about 48 registers of the rest
     static constexpr int WPE = TREGS + 48 + 8 * RPL * words <= 168 ? 3 : 2;
+    // LDS of the elimination (-G slots, U per wave, the panel), reused by
+    // the Schur lift of the epilogue (flux Jacobians, A^-1 r, X)
+    static constexpr int NF = 4 * P, LDX = n + 1;
+    static constexpr size_t ELIM_BYTES =
+        sizeof(T) * (size_t(NB) * NPAD * LDG + size_t(W) * 16 * LDG + size_t(NPAD) * LDP);
+    static constexpr size_t LIFT_BYTES =
+        sizeof(double) * (2 * NF * 16 + n) + sizeof(T) * size_t(m) * LDX;
+    static constexpr size_t SMEM = ELIM_BYTES > LIFT_BYTES ? ELIM_BYTES : LIFT_BYTES;
 };
 
 template <typename T> struct MTile;
@@ -878,10 +886,17 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
     constexpr int W = S::W, CTW = S::CTW, RPL = S::RPL, LDP = S::LDP, LDG = S::LDG;
     constexpr int NB = S::NB, MW = S::MW;
     constexpr int NP = P * P;
-    __shared__ __align__(16) T gbuf[NB][NPAD * LDG];  // -G of the last three panels
-    __shared__ __align__(16) T ubuf[W][16 * LDG];     // U of one tile, per wave
-    __shared__ T pbuf[NPAD * LDP];                    // panel in row layout
+    __shared__ __align__(16) unsigned char smem[S::SMEM];
+    // -G of the last three panels, U of one tile per wave, the panel in row
+    // layout
+    T (*gbuf)[NPAD * LDG] = reinterpret_cast<T (*)[NPAD * LDG]>(smem);
+    T (*ubuf)[16 * LDG] = reinterpret_cast<T (*)[16 * LDG]>(
+        smem + sizeof(T) * size_t(NB) * NPAD * LDG);
+    T* pbuf = reinterpret_cast<T*>(smem + sizeof(T) * (size_t(NB) * NPAD * LDG +
+                                                       size_t(W) * 16 * LDG));
     __shared__ int pivs[NB][16];
+    __shared__ short kinv[NPAD];                      // row -> its unknown
+    __shared__ int trf[4];                            // faces on the trace
     __shared__ unsigned pmask[NB][MW];                // pivot rows of the panel
     // per row: 1 + its position among the panel's pivots, 0 if none
     __shared__ __align__(4) unsigned char posb[NB][NPAD];
@@ -1054,7 +1069,10 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
         if (lane < 16) {
             pivs[jb][lane] = pvv;
             const int col = 16 * j + lane;
-            if (col < n) a.piv[size_t(k) * n + col] = pvv;
+            if (col < n) {
+                a.piv[size_t(k) * n + col] = pvv;
+                kinv[pvv] = short(col);
+            }
         }
     };
 
@@ -1156,22 +1174,105 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
     }
     __syncthreads();
     for (int row = threadIdx.x; row < n; row += blockDim.x) a.yr[size_t(k) * n + row] = rhol[row];
+
+    // ---- the Schur lift (k_schur_lift, in place of its launch): X and
+    // A^-1 r in unknown order and the face-point flux Jacobians to the LDS
+    // the elimination has finished with, then L = D + C X and z = C A^-1 r
+    constexpr int NF = S::NF, LDX = S::LDX, m = S::m;
+    double* fu = reinterpret_cast<double*>(smem);
+    double* fh = fu + NF * 16;
+    double* ys = fh + NF * 16;
+    T* xs = reinterpret_cast<T*>(ys + n);
+    {
+        const double* lin = a.lin + size_t(k) * 2 * NF * 16;
+        for (int e = threadIdx.x; e < NF * 16; e += blockDim.x) {
+            fu[e] = lin[e];
+            fh[e] = lin[NF * 16 + e];
+        }
+        if (threadIdx.x < 4)
+            trf[threadIdx.x] = a.finfo[size_t(a.imp_list[k]) * 4 + threadIdx.x].role == ROLE_HFR;
+        for (int row = threadIdx.x; row < n; row += blockDim.x) ys[kinv[row]] = rhol[row];
+#pragma unroll
+        for (int q = 0; q < CTW; ++q) {
+            const int c = w + W * q;
+            if (c < RT || c >= NCT) continue;          // uniform
+            const int b = 16 * (c - RT) + i;
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * t + M::row(g, r);
+                    if (row < n) xs[b * LDX + kinv[row]] = acc[q][t][r];
+                }
+        }
+    }
+    __syncthreads();
+    // one (face point, column) pair per thread and pass: the four rows of
+    // the face point in that column (16-byte store)
+    for (int idx = threadIdx.x; idx < NF * (m + 1); idx += blockDim.x) {
+        const int fq = idx % NF, b = idx / NF;    // b == m: the z column
+        const int f = fq / P, q = fq - f * P;
+        double out[4];
+        if (!trf[f]) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) out[v] = (b == fq * 4 + v) ? 1.0 : 0.0;
+        } else {
+            double sw[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int l = 0; l < P; ++l) {
+                int pt;
+                double c;
+                if (f == 0) { pt = l * P + q; c = og.lm[l]; }
+                else if (f == 1) { pt = q * P + l; c = og.lp[l]; }
+                else if (f == 2) { pt = l * P + (P - 1 - q); c = og.lp[l]; }
+                else { pt = (P - 1 - q) * P + l; c = og.lm[l]; }
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    sw[v] += c * (b < m ? double(xs[b * LDX + pt * 4 + v]) : ys[pt * 4 + v]);
+            }
+            const double wq = og.w[q];
+            const bool diag = (b >> 2) == fq;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double acc2 = diag ? fh[fq * 16 + v * 4 + (b & 3)] : 0.0;
+#pragma unroll
+                for (int w2 = 0; w2 < 4; ++w2) acc2 += fu[fq * 16 + v * 4 + w2] * sw[w2];
+                out[v] = wq * acc2;
+            }
+        }
+        if (b < m) {
+            T* dst = G + size_t(n + b) * N + n + fq * 4;
+            if constexpr (sizeof(T) == 4) {
+                *reinterpret_cast<float4*>(dst) = make_float4(float(out[0]), float(out[1]),
+                                                              float(out[2]), float(out[3]));
+            } else {
+                reinterpret_cast<double2*>(dst)[0] = make_double2(out[0], out[1]);
+                reinterpret_cast<double2*>(dst)[1] = make_double2(out[2], out[3]);
+            }
+        } else {
+            double* zz = a.z + size_t(k) * m + fq * 4;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) zz[v] = trf[f] ? out[v] : 0.0;
+        }
+    }
 }
 
 template <int P, typename T>
 static hipError_t launch_sweep(const RefOps& o, const CondenseLaunch& a,
                                hipStream_t st) {
     if (a.schur_only && a.yr) {
-        if (a.blocked == 2)
+        // the blocked kernels end with the Schur lift themselves
+        if (a.blocked == 2) {
             hipLaunchKernelGGL((k_condense_blocked<P, T, 8>), dim3(a.nimp),
                                dim3(64 * BlockShape<P, T, 8>::W), 0, st, a, o);
-        else if (a.blocked)
+        } else if (a.blocked) {
             hipLaunchKernelGGL((k_condense_blocked<P, T, 0>), dim3(a.nimp),
                                dim3(64 * BlockShape<P, T, 0>::W), 0, st, a, o);
-        else
+        } else {
             hipLaunchKernelGGL((k_condense_sweep<P, T, true>), dim3(a.nimp),
                                dim3(64 * SweepShape<P, T, true>::W), 0, st, a, o);
-        hipLaunchKernelGGL((k_schur_lift<P, T>), dim3(a.nimp), dim3(256), 0, st, a, o);
+            hipLaunchKernelGGL((k_schur_lift<P, T>), dim3(a.nimp), dim3(256), 0, st, a, o);
+        }
     } else {
         hipLaunchKernelGGL((k_condense_sweep<P, T, false>), dim3(a.nimp),
                            dim3(64 * SweepShape<P, T, false>::W), 0, st, a, o);

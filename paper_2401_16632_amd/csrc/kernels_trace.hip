@@ -146,60 +146,11 @@ hipError_t launch_assemble(const AssembleLaunch& a, hipStream_t st) {
 }
 
 // ---- block-Jacobi: invert the diagonal block of every trace face -------
-// One wave per face, four faces per workgroup: lane r holds row r of the
-// BS x BS block in registers and BS Jordan exchanges with partial pivoting
-// (wave-wide DPP argmax, pivot row by v_readlane) turn it into the inverse
-// with row and column permutations, T[p_k][j] = Inv[k][p_j]; pivot rows are
-// kept unscaled with their factor -1/pivot applied at the store.
-template <int BS>
-__global__ __launch_bounds__(256) void k_block_inverse(int ntf, const int* diag_blk,
-                                                       const double* L64,
-                                                       const float* L32, int pc,
-                                                       void* out, int* fail) {
-    const int lane = threadIdx.x & 63;
-    const int F = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (F >= ntf) return;                          // whole wave
-    const size_t blk = size_t(diag_blk[F]) * BS * BS;
-    double t[BS];
-#pragma unroll
-    for (int c = 0; c < BS; ++c) {
-        const size_t i = blk + size_t(c) * BS + min(lane, BS - 1);   // in bounds
-        const double v = L64 ? L64[i] : double(L32[i]);
-        t[c] = lane < BS ? v : 0.0;
-    }
-    double sig = 1.0;
-    bool used = lane >= BS;
-    int pos = 0;
-    int pj[BS];
-#pragma unroll
-    for (int k = 0; k < BS; ++k) {
-        const unsigned long long key =
-            wave_max_key(used ? 0ull : pivot_key(float(fabs(t[k])), lane));
-        if ((key >> 32) == 0) {
-            if (lane == 0) *fail = 1;
-            return;                                // uniform
-        }
-        const int p = __builtin_amdgcn_readfirstlane(int(0xffffffffu - unsigned(key)));
-        pj[k] = p;
-        const double ipv = 1.0 / lane_value(t[k], p);
-        const double g = (lane == p) ? 0.0 : t[k] * ipv;
-#pragma unroll
-        for (int j = 0; j < BS; ++j) t[j] = fma(-g, lane_value(t[j], p), t[j]);
-        t[k] = (lane == p) ? -1.0 : g;
-        if (lane == p) { used = true; sig = -ipv; pos = k; }
-    }
-    // store column-major: out[F][b][a] = Inv[a][b], Inv[pos][p_j] = sig t[j]
-    if (lane >= BS) return;
-    const size_t o = size_t(F) * BS * BS + pos;
-#pragma unroll
-    for (int j = 0; j < BS; ++j) {
-        const double v = sig * t[j];
-        const size_t i = o + size_t(pj[j]) * BS;
-        if (pc == HFR_PC_FP64) reinterpret_cast<double*>(out)[i] = v;
-        else if (pc == HFR_PC_FP32) reinterpret_cast<float*>(out)[i] = float(v);
-        else reinterpret_cast<uint16_t*>(out)[i] = f2bf(float(v));
-    }
-}
+// Lane r of a group holds row r of the BS x BS block in registers and BS
+// Jordan exchanges with partial pivoting (DPP argmax over the group, pivot
+// row through LDS) turn it into the inverse with row and column
+// permutations, T[p_k][j] = Inv[k][p_j]; pivot rows are kept unscaled with
+// their factor -1/pivot applied at the store.
 
 // Blocks of at most 16 rows: four blocks per wave, one per row of 16 lanes
 // (lane r of a row holds row r of its block).  The pivot search is a
@@ -305,14 +256,126 @@ __global__ __launch_bounds__(256) void k_block_inverse16(int ntf, const int* dia
     }
 }
 
+// Blocks of 17 to 32 rows: two blocks per wave, one per half of 32 lanes.
+// The pivot search is the 16-lane DPP maximum, then row 0 into row 1 and
+// row 2 into row 3 (row_bcast:15), read back from lanes 31 and 63; the
+// pivot row is passed through LDS as for the 16-row blocks.
+__device__ __forceinline__ unsigned long long half32_max_key(unsigned long long x, int half) {
+    x = row16_max_key(x);
+    x = key_max(x, key_dpp<0x142, 0xa>(x));     // row_bcast:15 into rows 1, 3
+    const int lo = int(unsigned(x)), hi = int(unsigned(x >> 32));
+    const unsigned long long a =
+        (static_cast<unsigned long long>(unsigned(__builtin_amdgcn_readlane(hi, 31))) << 32) |
+        unsigned(__builtin_amdgcn_readlane(lo, 31));
+    const unsigned long long b =
+        (static_cast<unsigned long long>(unsigned(__builtin_amdgcn_readlane(hi, 63))) << 32) |
+        unsigned(__builtin_amdgcn_readlane(lo, 63));
+    return half ? b : a;
+}
+__device__ __forceinline__ unsigned half32_max_u32(unsigned x, int half) {
+    x = row16_max_u32(x);
+    x = max(x, key32_dpp<0x142, 0xa>(x));       // row_bcast:15 into rows 1, 3
+    const unsigned a = unsigned(__builtin_amdgcn_readlane(int(x), 31));
+    const unsigned b = unsigned(__builtin_amdgcn_readlane(int(x), 63));
+    return half ? b : a;
+}
+
+template <int BS, typename C>
+__global__ __launch_bounds__(256) void k_block_inverse32(int ntf, const int* diag_blk,
+                                                         const double* L64,
+                                                         const float* L32, int pc,
+                                                         void* out, int* fail) {
+    static_assert(BS > 16 && BS <= 32, "two blocks per wave need 16 < BS <= 32");
+    __shared__ C prow[4][2][BS];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int half = lane >> 5, r = lane & 31;
+    const int F = (blockIdx.x * 4 + wv) * 2 + half;
+    const bool valid = F < ntf;
+    const size_t blk = valid ? size_t(diag_blk[F]) * BS * BS : 0;
+    C t[BS];
+#pragma unroll
+    for (int c = 0; c < BS; ++c) {
+        const size_t i = blk + size_t(c) * BS + min(r, BS - 1);   // in bounds
+        C v = c == r ? C(1) : C(0);
+        if (valid) v = L64 ? C(L64[i]) : C(L32[i]);
+        t[c] = r < BS ? v : C(0);
+    }
+    C sig = C(1);
+    bool used = r >= BS, bad = false;
+    int pos = 0;
+    int pj[BS];
+#pragma unroll
+    for (int k = 0; k < BS; ++k) {
+        int p;
+        if constexpr (sizeof(C) == 8) {
+            const unsigned long long key =
+                half32_max_key(used ? 0ull : pivot_key(float(fabs(t[k])), r), half);
+            p = int(0xffffffffu - unsigned(key));
+            if ((key >> 32) == 0) {                 // no nonzero candidate
+                bad = true;
+                p = 0;
+            }
+        } else {
+            const unsigned key =
+                half32_max_u32(used ? 0u : pivot_key32(float(fabs(t[k])), r), half);
+            p = 255 - int(key & 0xffu);
+            if (key == 0) {                         // no nonzero candidate
+                bad = true;
+                p = 0;
+            }
+        }
+        pj[k] = p;
+        if (r == p) {
+#pragma unroll
+            for (int j = 0; j < BS; ++j) prow[wv][half][j] = t[j];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        C u[BS];
+#pragma unroll
+        for (int j = 0; j < BS; ++j) u[j] = prow[wv][half][j];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        C ipv;
+        if constexpr (sizeof(C) == 8) ipv = bad ? 0.0 : 1.0 / u[k];
+        else ipv = bad ? 0.f : __builtin_amdgcn_rcpf(u[k]);
+        const C g = (r == p) ? C(0) : t[k] * ipv;
+#pragma unroll
+        for (int j = 0; j < BS; ++j) t[j] = fma(-g, u[j], t[j]);
+        t[k] = (r == p) ? C(-1) : g;
+        if (r == p) { used = true; sig = -ipv; pos = k; }
+    }
+    if (bad && valid && r == 0) *fail = 1;
+    if (!valid || r >= BS) return;
+    // store column-major: out[F][b][a] = Inv[a][b], Inv[pos][p_j] = sig t[j]
+    const size_t o = size_t(F) * BS * BS + pos;
+#pragma unroll
+    for (int j = 0; j < BS; ++j) {
+        const C v = sig * t[j];
+        const size_t i = o + size_t(pj[j]) * BS;
+        if (pc == HFR_PC_FP64) reinterpret_cast<double*>(out)[i] = double(v);
+        else if (pc == HFR_PC_FP32) reinterpret_cast<float*>(out)[i] = float(v);
+        else reinterpret_cast<uint16_t*>(out)[i] = f2bf(float(v));
+    }
+}
+
 hipError_t launch_block_inverse_impl(int ntf, int bs, const int* diag_blk,
                                      const double* L64, const float* L32,
                                      int pc, void* out, int* fail,
                                      hipStream_t st) {
     if (ntf == 0) return hipSuccess;
-    const dim3 grid((ntf + 3) / 4), blk(256);
+    const dim3 blk(256);
     const dim3 grid16((ntf + 15) / 16);            // four blocks per wave
+    const dim3 grid32((ntf + 7) / 8);              // two blocks per wave
     const bool f64 = pc == HFR_PC_FP64;
+#define HFR_INV32(B)                                                                          \
+    if (f64) hipLaunchKernelGGL((k_block_inverse32<B, double>), grid32, blk, 0, st, ntf,     \
+                                diag_blk, L64, L32, pc, out, fail);                          \
+    else hipLaunchKernelGGL((k_block_inverse32<B, float>), grid32, blk, 0, st, ntf,          \
+                            diag_blk, L64, L32, pc, out, fail);                              \
+    break;
 #define HFR_INV16(B)                                                                          \
     if (f64) hipLaunchKernelGGL((k_block_inverse16<B, double>), grid16, blk, 0, st, ntf,     \
                                 diag_blk, L64, L32, pc, out, fail);                          \
@@ -324,11 +387,12 @@ hipError_t launch_block_inverse_impl(int ntf, int bs, const int* diag_blk,
         case 8: HFR_INV16(8)
         case 12: HFR_INV16(12)
         case 16: HFR_INV16(16)
-        case 20: hipLaunchKernelGGL(k_block_inverse<20>, grid, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
-        case 24: hipLaunchKernelGGL(k_block_inverse<24>, grid, blk, 0, st, ntf, diag_blk, L64, L32, pc, out, fail); break;
+        case 20: HFR_INV32(20)
+        case 24: HFR_INV32(24)
         default: return hipErrorInvalidValue;
     }
 #undef HFR_INV16
+#undef HFR_INV32
     return hipGetLastError();
 }
 

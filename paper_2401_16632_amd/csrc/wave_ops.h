@@ -14,9 +14,8 @@ __device__ __forceinline__ double lane_value(double x, int l) {
     return __hiloint2double(hi, lo);
 }
 
-// Wave-wide maximum of a 64-bit key by DPP row operations (quad swaps,
-// half-row and row mirrors, then the row broadcasts 15 and 31); the
-// maximum ends in lane 63.
+// Maximum of 64-bit keys and one DPP step on them (both halves moved; lanes
+// the control leaves out keep their own key)
 __device__ __forceinline__ unsigned long long key_max(unsigned long long a,
                                                       unsigned long long b) {
     return a > b ? a : b;
@@ -27,17 +26,6 @@ __device__ __forceinline__ unsigned long long key_dpp(unsigned long long x) {
     const unsigned l2 = unsigned(__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xf, false));
     const unsigned h2 = unsigned(__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xf, false));
     return (static_cast<unsigned long long>(h2) << 32) | l2;
-}
-__device__ __forceinline__ unsigned long long wave_max_key(unsigned long long x) {
-    x = key_max(x, key_dpp<0xb1, 0xf>(x));      // quad_perm [1,0,3,2]
-    x = key_max(x, key_dpp<0x4e, 0xf>(x));      // quad_perm [2,3,0,1]
-    x = key_max(x, key_dpp<0x141, 0xf>(x));     // row_half_mirror
-    x = key_max(x, key_dpp<0x140, 0xf>(x));     // row_mirror
-    x = key_max(x, key_dpp<0x142, 0xa>(x));     // row_bcast:15
-    x = key_max(x, key_dpp<0x143, 0xc>(x));     // row_bcast:31
-    const int lo = __builtin_amdgcn_readlane(int(unsigned(x)), 63);
-    const int hi = __builtin_amdgcn_readlane(int(unsigned(x >> 32)), 63);
-    return (static_cast<unsigned long long>(unsigned(hi)) << 32) | unsigned(lo);
 }
 // Wave-wide sum of a double by the same DPP row operations (lanes outside
 // the row mask add zero), in a fixed order; every lane gets the sum.

@@ -151,7 +151,8 @@ def test_element_factorisation(name, precision):
 @pytest.mark.parametrize("name,precision,precond,tol", [
     ("c1_p2", "fp64", "fp64", 1e-13), ("cyl_p3", "fp64", "fp64", 1e-13),
     ("cyl_p3", "fp32", "fp32", 1e-6), ("cyl_p3", "fp32", "bf16", 1e-2),
-    ("cyl_p4", "fp64", "fp64", 1e-13)])
+    ("cyl_p4", "fp64", "fp64", 1e-13), ("cyl_p4", "fp32", "fp32", 1e-6),
+    ("c1_p5", "fp64", "fp64", 1e-13), ("c1_p5", "fp32", "bf16", 1e-2)])
 def test_block_jacobi_inverse(name, precision, precond, tol):
     """The preconditioner blocks invert the oracle's diagonal face blocks of
     L: backward error |X D - I| / (bs |X| |D|) within a few units of the

@@ -268,7 +268,9 @@ def roofline(form, mesh, timers, precision, workload="c2", phases=None, ck="swee
     ems, ecnt = src["explicit"]
     if dom == "condense":
         # the element elimination and the Schur complement from C's
-        # structure (two launches per linearisation, timed together)
+        # structure (one launch per linearisation with the blocked kernel,
+        # which ends with the lift; the sweep is followed by its own lift
+        # launch, timed together)
         fl = condense_flops(n, m) * mesh.Nim
         avg = cms / max(1, ccnt) * 1e-3
         pk = PEAK["fp32_tflops"] if precision == "fp32" else PEAK["fp64_tflops"]
@@ -276,7 +278,9 @@ def roofline(form, mesh, timers, precision, workload="c2", phases=None, ck="swee
         kname = CK_KERNEL.get(ck, "k_condense_sweep")
         traffic = (measured_traffic(workload, f"{kname}<{mesh.P}, float")
                    if precision == "fp32" else None)
-        return dict(kernel=f"condense ({kname} + k_schur_lift)",
+        label = (f"{kname} (elimination + Schur lift)" if kname == "k_condense_blocked"
+                 else f"condense ({kname} + k_schur_lift)")
+        return dict(kernel=label,
                     bound="mfma" if kname == "k_condense_blocked" else "alu",
                     achieved=ach, peak=pk,
                     unit="TFLOP/s", frac=ach / pk, traffic=traffic,

@@ -106,6 +106,13 @@ struct ResidualLaunch {
 hipError_t launch_residual(const RefOps& ops, const ResidualLaunch& a,
                            hipStream_t st);
 
+// The blocked Schur-only elimination forms the rows of A and B itself
+// (no tableau fill) in FP32 up to p = 4; elsewhere its register budget
+// leaves no room and it reads the filled tableau.
+constexpr bool blocked_fuses_fill(int P, int precision) {
+    return precision == HFR_PREC_FP32 && P <= 5;
+}
+
 struct CondenseLaunch {
     const int* imp_list;     // implicit element ids
     int nimp;

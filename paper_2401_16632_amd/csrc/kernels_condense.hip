@@ -221,14 +221,12 @@ struct SweepShape {
 // Consecutive threads take consecutive row blocks of one block column, so
 // every 16- or 32-byte store of a block column is contiguous.
 template <int P>
-__device__ __forceinline__ void block_entries(int br, int bc, const RefOps& o,
-                                              const CondShared<P>& sh,
-                                              double E[4][4]) {
+__device__ __forceinline__ void block_column(int br, int bc, int cc, const RefOps& o,
+                                             const CondShared<P>& sh, double out[4]) {
+    // column cc of the 4x4 point block (br, bc): out[v] = E[v][cc]
     constexpr int NP = P * P;
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) E[v][c] = 0.0;
+    for (int v = 0; v < 4; ++v) out[v] = 0.0;
     if (br < NP) {
         const int i = br % P, j = br / P;
         const double cij = sh.c[br];
@@ -250,23 +248,19 @@ __device__ __forceinline__ void block_entries(int br, int bc, const RefOps& o,
             }
             if (kk == j || l == i) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        const int z = v * 4 + c;
-                        double acc = 0.0;
-                        if (kk == j)
-                            acc += a1 * sh.Af[bc][z] + b1 * sh.Fu[1 * P + j][z] +
-                                   c1 * sh.Fu[3 * P + (P - 1 - j)][z];
-                        if (l == i)
-                            acc += a2 * sh.Ag[bc][z] + b2 * sh.Fu[0 * P + i][z] +
-                                   c2 * sh.Fu[2 * P + (P - 1 - i)][z];
-                        E[v][c] = cij * acc;
-                    }
+                for (int v = 0; v < 4; ++v) {
+                    const int z = v * 4 + cc;
+                    double acc = 0.0;
+                    if (kk == j)
+                        acc += a1 * sh.Af[bc][z] + b1 * sh.Fu[1 * P + j][z] +
+                               c1 * sh.Fu[3 * P + (P - 1 - j)][z];
+                    if (l == i)
+                        acc += a2 * sh.Ag[bc][z] + b2 * sh.Fu[0 * P + i][z] +
+                               c2 * sh.Fu[2 * P + (P - 1 - i)][z];
+                    out[v] = cij * acc;
+                }
             }
-            if (bc == br)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) E[v][v] += 1.0;
+            if (bc == br) out[cc] += 1.0;
         } else {
             const int tb = bc - NP, f2 = tb / P, q2 = tb % P;
             if (!sh.tr[f2]) return;
@@ -277,16 +271,12 @@ __device__ __forceinline__ void block_entries(int br, int bc, const RefOps& o,
             else { if (q2 == P - 1 - i) coef = o.cr[j]; }
             if (coef == 0.0) return;
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) E[v][c] = cij * coef * sh.Fh[tb][v * 4 + c];
+            for (int v = 0; v < 4; ++v) out[v] = cij * coef * sh.Fh[tb][v * 4 + cc];
         }
     } else {
         const int ta = br - NP, f = ta / P, q = ta % P;
         if (!sh.tr[f]) {
-            if (bc == br)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) E[v][v] = 1.0;
+            if (bc == br) out[cc] = 1.0;
             return;
         }
         const double wq = o.w[q];
@@ -299,15 +289,24 @@ __device__ __forceinline__ void block_entries(int br, int bc, const RefOps& o,
             else { if (l == P - 1 - q) coef = o.lp[kk]; }
             if (coef == 0.0) return;
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) E[v][c] = wq * coef * sh.Fu[ta][v * 4 + c];
+            for (int v = 0; v < 4; ++v) out[v] = wq * coef * sh.Fu[ta][v * 4 + cc];
         } else if (bc == br) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) E[v][c] = wq * sh.Fh[ta][v * 4 + c];
+            for (int v = 0; v < 4; ++v) out[v] = wq * sh.Fh[ta][v * 4 + cc];
         }
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void block_entries(int br, int bc, const RefOps& o,
+                                              const CondShared<P>& sh,
+                                              double E[4][4]) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        double col[4];
+        block_column<P>(br, bc, c, o, sh, col);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) E[v][c] = col[v];
     }
 }
 
@@ -821,7 +820,13 @@ struct BlockShape {
         sizeof(T) * (size_t(NB) * NPAD * LDG + size_t(W) * 16 * LDG + size_t(NPAD) * LDP);
     static constexpr size_t LIFT_BYTES =
         sizeof(double) * (2 * NF * 16 + n) + sizeof(T) * size_t(m) * LDX;
-    static constexpr size_t SMEM = ELIM_BYTES > LIFT_BYTES ? ELIM_BYTES : LIFT_BYTES;
+    // and before the panels, by the element linearisation (operator
+    // table and flux Jacobians) the tiles are formed from
+    static constexpr bool FUSE = blocked_fuses_fill(P, words == 1 ? HFR_PREC_FP32 : HFR_PREC_FP64);
+    static constexpr size_t OPS_BYTES = (sizeof(RefOps) + 15) / 16 * 16;
+    static constexpr size_t FILL_BYTES = OPS_BYTES + sizeof(CondShared<P>);
+    static constexpr size_t SMEM0 = ELIM_BYTES > LIFT_BYTES ? ELIM_BYTES : LIFT_BYTES;
+    static constexpr size_t SMEM = FUSE && FILL_BYTES > SMEM0 ? FILL_BYTES : SMEM0;
 };
 
 template <typename T> struct MTile;
@@ -908,8 +913,66 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
     const int k = blockIdx.x;
     T* G = reinterpret_cast<T*>(a.M) + size_t(k) * N * N;
 
-    // ---- load: tile (t, c) of [A | pad | B] (dummy unknowns: identity)
+    // ---- the element linearisation in LDS (the region the panels take
+    // later), then tile (t, c) of [A | pad | B] straight from it: the rows of
+    // A and B of the tableau fill, entry for entry, formed in registers
+    // (dummy unknowns: identity); the face-point flux Jacobians go to a.lin
+    // for the lift at the end
     V acc[CTW][RT];
+    if constexpr (S::FUSE) {
+    {
+        RefOps& os = *reinterpret_cast<RefOps*>(smem);
+        copy_ref_ops(os, og);
+    }
+    __syncthreads();
+    const RefOps& os = *reinterpret_cast<const RefOps*>(smem);
+    CondShared<P>& sh = *reinterpret_cast<CondShared<P>*>(smem + S::OPS_BYTES);
+    element_linearisation<P>(a, os, k, sh);            // ends with a barrier
+    {
+        double* lin = a.lin + size_t(k) * 2 * 4 * P * 16;
+        for (int e2 = threadIdx.x; e2 < 4 * P * 16; e2 += blockDim.x) {
+            lin[e2] = sh.Fu[e2 >> 4][e2 & 15];
+            lin[4 * P * 16 + e2] = sh.Fh[e2 >> 4][e2 & 15];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < CTW; ++q) {
+        const int c = w + W * q;
+        const int ci = 16 * c + i;                     // internal column
+        const bool dcol = ci >= n && ci < NPAD;
+        // block column and component of the global column (A or B)
+        const int bc = ci < n ? ci >> 2 : NP + ((ci - NPAD) >> 2);
+        const int cc = (ci < n ? ci : ci - NPAD) & 3;
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            if constexpr (sizeof(T) == 4) {
+                // rows 4g + r: the four variables of point 4t + g
+                const int br = 4 * t + g;
+                double col[4] = {0.0, 0.0, 0.0, 0.0};
+                if (c < NCT && !dcol && 16 * t + 4 * g < n) block_column<P>(br, bc, cc, os, sh, col);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * t + M::row(g, r);
+                    T v = T(col[r]);
+                    if (c < NCT && row >= n && dcol && row == ci) v = T(1);
+                    acc[q][t][r] = v;
+                }
+            } else {
+                // rows g + 4r: variable g of point 4t + r
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * t + M::row(g, r);
+                    double col[4] = {0.0, 0.0, 0.0, 0.0};
+                    if (c < NCT && !dcol && row < n) block_column<P>(row >> 2, bc, cc, os, sh, col);
+                    T v = T(col[g]);
+                    if (c < NCT && row >= n && dcol && row == ci) v = T(1);
+                    acc[q][t][r] = v;
+                }
+            }
+        }
+    }
+    } else {
+    // the rows of A and B as the tableau fill wrote them (column-major)
 #pragma unroll
     for (int q = 0; q < CTW; ++q) {
         const int c = w + W * q;
@@ -929,6 +992,7 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
                 acc[q][t][r] = v;
             }
         }
+    }
     }
     for (int r = threadIdx.x; r < NPAD; r += blockDim.x) used[r] = 0;
     // right-hand side h (FP64), one value per row, updated by wave 0

@@ -376,6 +376,15 @@ CondenseLaunch condense_launch(hfr_solver_s* s, const double* u,
     return c;
 }
 
+// The Schur-only elimination in use forms the rows of A and B itself: no
+// tableau fill is queued for it (unless the blocks are kept for inspection,
+// which the fill writes).
+bool fused_fill(const hfr_solver_s* s) {
+    const int ck = s->ck > 0 ? s->ck : s->opts.condense_kernel;
+    return (ck == HFR_CK_BLOCKED || ck == HFR_CK_BLOCKED_W8) &&
+           blocked_fuses_fill(s->mesh->P, s->opts.precision) && !s->blocks_copy;
+}
+
 // Fill of the element tableaus; with `go`, every workgroup returns at entry
 // when the device flag says the Newton iteration has converged.
 // schur: the input of the Schur-only sweep (rows of A and B, and the
@@ -402,7 +411,7 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
                             bool schur_only = false) {
     fr_mesh_s* m = s->mesh;
     if (m->Nim == 0) return FR_OK;
-    if (!fill_done) {
+    if (!fill_done && !(schur_only && fused_fill(s))) {
         fr_status e = condense_fill(s, u, uhat, aii_dt, nullptr, st, schur_only);
         if (e) return e;
     }
@@ -645,9 +654,10 @@ fr_status gmres_first_chunk(hfr_solver_s* s, double* x, int K, hipStream_t q,
 }
 
 // Process-wide choice of the Schur-only condensation kernel per (order,
-// precision), measured once: each candidate eliminates the same freshly
-// filled tableaux (the first linearisation of a Newton solve) and the fastest
-// is kept for every later solver of that shape.
+// precision), measured once on the first linearisation of a Newton solve:
+// each candidate is timed with the tableau fill it needs (none for a
+// blocked kernel that forms the rows of A and B itself), and the fastest is
+// kept for every later solver of that shape.
 std::mutex g_tune_mutex;
 std::map<std::pair<int, int>, std::pair<int, std::array<double, 3>>> g_tuned;
 
@@ -677,13 +687,18 @@ fr_status tune_condense(hfr_solver_s* s, const double* u, const double* uhat,
         s->ck = cand[c];
         float best = 1e30f;
         for (int rep = 0; rep < 2 && !e; ++rep) {   // the first run warms up
-            if ((e = condense_fill(s, u, uhat, aii_dt, nullptr, st, true))) break;
+            // each candidate timed with the fill it needs
+            if (hipEventRecord(e0, st) != hipSuccess) {
+                e = fail(FR_E_DEVICE, "condensation tuning launch failed");
+                break;
+            }
+            if (!fused_fill(s) && (e = condense_fill(s, u, uhat, aii_dt, nullptr, st, true)))
+                break;
             CondenseLaunch cl = condense_launch(s, u, uhat, aii_dt);
             cl.yr = s->yr;
             cl.z = s->zz;
             cl.schur_only = 1;
-            if (hipEventRecord(e0, st) != hipSuccess ||
-                launch_condense(m->ops, cl, st) != hipSuccess ||
+            if (launch_condense(m->ops, cl, st) != hipSuccess ||
                 hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
                 e = fail(FR_E_DEVICE, "condensation tuning launch failed");
                 break;
@@ -705,8 +720,8 @@ fr_status tune_condense(hfr_solver_s* s, const double* u, const double* uhat,
         if (ms[c] < ms[bi]) bi = c;
     s->ck = cand[bi];
     for (int i = 0; i < 3; ++i) s->tune_ms[i] = ms[i];
-    // leave a fresh fill for the linearisation that follows
-    if ((e = condense_fill(s, u, uhat, aii_dt, nullptr, st, true))) return e;
+    // leave a fresh fill for the linearisation that follows (if it needs one)
+    if (!fused_fill(s) && (e = condense_fill(s, u, uhat, aii_dt, nullptr, st, true))) return e;
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     g_tuned[key] = std::make_pair(s->ck, ms);
     return FR_OK;
@@ -751,7 +766,9 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
                                           s->flags,
                                           flags_pub, seq_pub, &s->gs->norm_seq, qs));
         ++s->seq_norms;
-        if (spec && (e2 = condense_fill(s, u, uhat, aii_dt, s->go, qs, true))) return e2;
+        if (spec && !fused_fill(s) &&
+            (e2 = condense_fill(s, u, uhat, aii_dt, s->go, qs, true)))
+            return e2;
         return FR_OK;
     };
     // After each GMRES chunk the update of the Newton iterate and the next

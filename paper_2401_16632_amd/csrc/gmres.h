@@ -65,6 +65,13 @@ hipError_t launch_precondition_matrix(int nblocks, int bs, const int* col,
                                       const double* L64, const float* L32,
                                       int pc, const void* Dinv, double* Lt64,
                                       float* Lt32, hipStream_t st);
+// L and Lt = L Dinv of every block in one pass from the element tableaux
+// (face blocks of 20 and 24: orders with assemble_precondition_fused); the
+// diagonal blocks of L and Dinv must be in place, and a.blk_list null
+bool assemble_precondition_fused(int P);
+hipError_t launch_assemble_precondition(const AssembleLaunch& a, const int* col, int pc,
+                                        const void* Dinv, double* Lt64, float* Lt32,
+                                        hipStream_t st);
 // r = t - L x, beta = |r|, new cycle; cond: only if the cycle has ended
 // cap: the host ends the solve here (iteration cap)
 // (publishes the state with the next number of gs->pub_seq)

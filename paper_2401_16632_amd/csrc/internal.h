@@ -167,8 +167,9 @@ hipError_t launch_rhs64(int P, int nimp, const void* M, int precision,
                         double* z, hipStream_t st);
 
 struct AssembleLaunch {
-    int nblocks;             // BSR blocks
-    const int* blk_contrib;  // [nblocks][2][3]: imp, lf_row*2+side_row, lf_col*2+side_col (-1 none)
+    int nblocks;             // BSR blocks (or entries of blk_list)
+    const int* blk_contrib;  // [blocks][2][3]: imp, lf_row*2+side_row, lf_col*2+side_col (-1 none)
+    const int* blk_list;     // null: blocks 0..nblocks-1; else the blocks assembled
     int ntf;
     const int* tside;        // [Ntf][2][2]: imp, lf*2+side (-1 none) per side
     const void* M;
@@ -181,6 +182,14 @@ struct AssembleLaunch {
     const double* z;         // [Nim][m]  C A^-1 r per element
 };
 hipError_t launch_assemble(const AssembleLaunch& a, hipStream_t st);
+// the diagonal blocks of L read by the block-Jacobi inverse straight from
+// the element tableaux (blocks of 20 and 24): the block's contributions as
+// in AssembleLaunch; M null: read the assembled blocks of L
+struct DiagGather {
+    const int* blk_contrib;
+    const void* M;           // FP64 tableaux when L64 is given, else FP32
+    int n, m;
+};
 
 hipError_t launch_spmv(int ntf, int bs, const int* rowptr, const int* col,
                        const double* L64, const float* L32, const double* x,

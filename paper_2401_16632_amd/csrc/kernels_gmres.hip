@@ -759,10 +759,54 @@ __global__ __launch_bounds__(kThr) void k_gmres_restart(GmresArgs a, int first, 
     }
 }
 
+// four consecutive entries as one 16-byte access (FP32) or two (FP64)
+template <typename T> struct Vec4Load;
+template <> struct Vec4Load<float> {
+    __device__ static void get(const float* p, double (&v)[4]) {
+        const float4 x = *reinterpret_cast<const float4*>(p);
+        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    }
+    __device__ static void put(float* p, const double (&v)[4]) {
+        *reinterpret_cast<float4*>(p) = make_float4(float(v[0]), float(v[1]), float(v[2]), float(v[3]));
+    }
+    __device__ static void copy(float* d, const float* s) {
+        *reinterpret_cast<float4*>(d) = *reinterpret_cast<const float4*>(s);
+    }
+};
+template <> struct Vec4Load<double> {
+    __device__ static void get(const double* p, double (&v)[4]) {
+        const double2 x = reinterpret_cast<const double2*>(p)[0];
+        const double2 y = reinterpret_cast<const double2*>(p)[1];
+        v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
+    }
+    __device__ static void put(double* p, const double (&v)[4]) {
+        reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
+        reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
+    }
+    __device__ static void copy(double* d, const double* s) {
+        reinterpret_cast<double2*>(d)[0] = reinterpret_cast<const double2*>(s)[0];
+        reinterpret_cast<double2*>(d)[1] = reinterpret_cast<const double2*>(s)[1];
+    }
+};
+
 __device__ __forceinline__ double load_pc(const double* d, size_t i) { return d[i]; }
 __device__ __forceinline__ double load_pc(const float* d, size_t i) { return double(d[i]); }
 __device__ __forceinline__ double load_pc(const uint16_t* d, size_t i) {
     return double(__uint_as_float(uint32_t(d[i]) << 16));     // BF16 -> FP32
+}
+// four consecutive preconditioner entries (16, 32 or 8 bytes, aligned)
+__device__ __forceinline__ void load4_pc(const double* d, double (&v)[4]) {
+    Vec4Load<double>::get(d, v);
+}
+__device__ __forceinline__ void load4_pc(const float* d, double (&v)[4]) {
+    Vec4Load<float>::get(d, v);
+}
+__device__ __forceinline__ void load4_pc(const uint16_t* d, double (&v)[4]) {
+    const uint2 x = *reinterpret_cast<const uint2*>(d);
+    v[0] = double(__uint_as_float(x.x << 16));
+    v[1] = double(__uint_as_float(x.x & 0xffff0000u));
+    v[2] = double(__uint_as_float(x.y << 16));
+    v[3] = double(__uint_as_float(x.y & 0xffff0000u));
 }
 
 // ---- Lt = L Dinv (per block: Lt_FG = L_FG Dinv_G) -------------------------
@@ -913,6 +957,166 @@ __global__ __launch_bounds__(256) void k_precondition_matrix2x2(int nblocks, con
                 }
             }
         }
+}
+
+// Assembly and preconditioning in one pass (eq:assembly, then Lt = L Dinv)
+// for block sizes 20 and 24: each wave gathers its block of L from the at
+// most two element Schur blocks in the tableaux (as the assembly does: four
+// rows of one column per 16-byte read, the sum formed in FP64 and rounded
+// once), stores it, stages it in LDS and multiplies it by the column face's
+// inverse diagonal block on the same 2 x 2 tiles as
+// k_precondition_matrix2x2, so L is read from the tableaux once instead of
+// being written, read back and multiplied.  The diagonal blocks and their
+// inverses must already exist (assembled and inverted first); their L
+// blocks are rewritten with the same values.
+template <int BS, int P, typename TL, typename TD>
+__global__ __launch_bounds__(256) void k_assemble_precondition(AssembleLaunch a, const int* col,
+                                                               const TD* Dinv, TL* Lout,
+                                                               TL* Lt) {
+    static_assert(BS == 4 * P && BS > 16 && BS <= 32, "2x2 tiles of 16");
+    constexpr int BB = BS * BS, KC = BS / 4, CH = BS * P;   // 4-row pieces per block
+    constexpr int Q = BB / 4;                      // 4-entry pieces of a block
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int p = blockIdx.x * 4 + wv;
+    __shared__ __align__(16) TL lsh[4][BB];        // L (column-major), then Lt (row-major)
+    __shared__ __align__(16) TL dsh[4][BB];        // Dinv (column-major)
+    if (p >= a.nblocks) return;                    // whole wave
+    const int i = lane & 15, g = lane >> 4;
+    const size_t N = size_t(a.n + a.m);
+    const TL* M = reinterpret_cast<const TL*>(a.M);
+    const size_t lb = size_t(p) * BB;
+    // the column face's Dinv block does not depend on the gather: issued first
+    const size_t db = size_t(col[p]) * BB;
+#pragma unroll
+    for (int e0 = 0; e0 < Q; e0 += 64) {
+        const int e = e0 + lane;
+        if (e < Q) {
+            double v[4];
+            load4_pc(Dinv + db + 4 * size_t(e), v);
+            Vec4Load<TL>::put(&dsh[wv][4 * e], v);
+        }
+    }
+    int imp[2], lr[2], sr[2], lc[2], sc[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int* ct = a.blk_contrib + (size_t(p) * 2 + c) * 3;
+        imp[c] = ct[0];
+        lr[c] = ct[1] >> 1;
+        sr[c] = ct[1] & 1;
+        lc[c] = ct[2] >> 1;
+        sc[c] = ct[2] & 1;
+    }
+    // piece e: column b = e / P, rows 4 qa .. 4 qa + 3 with qa = e mod P
+#pragma unroll
+    for (int e0 = 0; e0 < CH; e0 += 64) {
+        const int e = e0 + lane;
+        if (e < CH) {
+            const int b = e / P, qa = e - b * P, qb = b >> 2, wb = b & 3;
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                if (imp[c] < 0) continue;
+                const size_t row = size_t(a.n) + (lr[c] * P + (sr[c] ? P - 1 - qa : qa)) * 4;
+                const size_t cl = size_t(a.n) + (lc[c] * P + (sc[c] ? P - 1 - qb : qb)) * 4 + wb;
+                double w[4];
+                Vec4Load<TL>::get(M + size_t(imp[c]) * N * N + cl * N + row, w);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] += w[r];
+            }
+            TL* dst = &lsh[wv][b * BS + 4 * qa];
+            Vec4Load<TL>::put(Lout + lb + size_t(b) * BS + 4 * qa, v);
+            Vec4Load<TL>::put(dst, v);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // A operands L(16 ti + i, 4 kk + g), B operands Dinv(4 kk + g, 16 tj + i);
+    // rows and columns past BS are zero
+    TL av[2][KC], bv[2][KC];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            const int x = 16 * t + i;
+            const TL va = lsh[wv][(4 * kk + g) * BS + min(x, BS - 1)];
+            const TL vb = dsh[wv][min(x, BS - 1) * BS + 4 * kk + g];
+            av[t][kk] = x < BS ? va : TL(0);
+            bv[t][kk] = x < BS ? vb : TL(0);
+        }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // the product tiles go to LDS row-major and leave as 16-byte pieces
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) {
+            if constexpr (sizeof(TL) == 4) {
+                mf4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kk = 0; kk < KC; ++kk)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ti][kk], bv[tj][kk], acc, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int ar = 16 * ti + 4 * g + r, b = 16 * tj + i;
+                    if (ar < BS && b < BS) lsh[wv][ar * BS + b] = acc[r];
+                }
+            } else {
+                md4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kk = 0; kk < KC; ++kk)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti][kk], bv[tj][kk], acc, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int ar = 16 * ti + g + 4 * r, b = 16 * tj + i;
+                    if (ar < BS && b < BS) lsh[wv][ar * BS + b] = acc[r];
+                }
+            }
+        }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int e0 = 0; e0 < Q; e0 += 64) {
+        const int e = e0 + lane;
+        if (e < Q) Vec4Load<TL>::copy(Lt + lb + 4 * size_t(e), &lsh[wv][4 * e]);
+    }
+}
+
+template <int P, typename TL>
+static void launch_ap_t(const AssembleLaunch& a, const int* col, int pc, const void* Dinv,
+                        TL* Lout, TL* Lt, hipStream_t st) {
+    constexpr int BS = 4 * P;
+    const dim3 grid((a.nblocks + 3) / 4), blk(256);
+    if (pc == HFR_PC_FP64)
+        hipLaunchKernelGGL((k_assemble_precondition<BS, P, TL, double>), grid, blk, 0, st, a,
+                           col, reinterpret_cast<const double*>(Dinv), Lout, Lt);
+    else if (pc == HFR_PC_FP32)
+        hipLaunchKernelGGL((k_assemble_precondition<BS, P, TL, float>), grid, blk, 0, st, a,
+                           col, reinterpret_cast<const float*>(Dinv), Lout, Lt);
+    else
+        hipLaunchKernelGGL((k_assemble_precondition<BS, P, TL, uint16_t>), grid, blk, 0, st, a,
+                           col, reinterpret_cast<const uint16_t*>(Dinv), Lout, Lt);
+}
+
+bool assemble_precondition_fused(int P) { return P == 5 || P == 6; }
+
+hipError_t launch_assemble_precondition(const AssembleLaunch& a, const int* col, int pc,
+                                        const void* Dinv, double* Lt64, float* Lt32,
+                                        hipStream_t st) {
+    if (a.nblocks == 0) return hipSuccess;
+    if (!assemble_precondition_fused(a.P) || a.blk_list) return hipErrorInvalidValue;
+    const bool f64 = a.precision == HFR_PREC_FP64;
+    if (f64 ? !(a.L64 && Lt64) : !(a.L32 && Lt32)) return hipErrorInvalidValue;
+    if (a.P == 5) {
+        if (f64) launch_ap_t<5, double>(a, col, pc, Dinv, a.L64, Lt64, st);
+        else launch_ap_t<5, float>(a, col, pc, Dinv, a.L32, Lt32, st);
+    } else {
+        if (f64) launch_ap_t<6, double>(a, col, pc, Dinv, a.L64, Lt64, st);
+        else launch_ap_t<6, float>(a, col, pc, Dinv, a.L32, Lt32, st);
+    }
+    return hipGetLastError();
 }
 
 template <int BS, typename TL>

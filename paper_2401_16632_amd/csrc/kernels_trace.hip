@@ -72,8 +72,9 @@ __global__ __launch_bounds__(256) void k_assemble4(AssembleLaunch a) {
     const long total = long(a.nblocks) * per;
     for (long idx = blockIdx.x * long(blockDim.x) + threadIdx.x; idx < total;
          idx += long(gridDim.x) * blockDim.x) {
-        const int blk = int(idx / per);
-        const int rem = int(idx - long(blk) * per);
+        const int bi = int(idx / per);
+        const int rem = int(idx - long(bi) * per);
+        const int blk = a.blk_list ? a.blk_list[bi] : bi;
         const int b = rem / P, qa = rem - b * P;   // column, point of the rows
         const int qb = b >> 2, wb = b & 3;
         double val[4] = {0.0, 0.0, 0.0, 0.0};
@@ -284,7 +285,8 @@ template <int BS, typename C>
 __global__ __launch_bounds__(256) void k_block_inverse32(int ntf, const int* diag_blk,
                                                          const double* L64,
                                                          const float* L32, int pc,
-                                                         void* out, int* fail) {
+                                                         void* out, int* fail,
+                                                         DiagGather dg) {
     static_assert(BS > 16 && BS <= 32, "two blocks per wave need 16 < BS <= 32");
     __shared__ C prow[4][2][BS];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -293,12 +295,45 @@ __global__ __launch_bounds__(256) void k_block_inverse32(int ntf, const int* dia
     const bool valid = F < ntf;
     const size_t blk = valid ? size_t(diag_blk[F]) * BS * BS : 0;
     C t[BS];
+    if (dg.M) {
+        // the block summed from the element tableaux as the assembly forms it
+        // (FP64 sum rounded to the storage precision of L)
+        constexpr int P = BS / 4;
+        const size_t N = size_t(dg.n + dg.m);
+        const int rr = min(r, BS - 1), qa = rr >> 2;
+        double acc[BS];
 #pragma unroll
-    for (int c = 0; c < BS; ++c) {
-        const size_t i = blk + size_t(c) * BS + min(r, BS - 1);   // in bounds
-        C v = c == r ? C(1) : C(0);
-        if (valid) v = L64 ? C(L64[i]) : C(L32[i]);
-        t[c] = r < BS ? v : C(0);
+        for (int c = 0; c < BS; ++c) acc[c] = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            const int* ct = dg.blk_contrib + (blk / (BS * BS) * 2 + cc) * 3;
+            const int imp = valid ? ct[0] : -1;
+            if (imp < 0) continue;
+            const int lr = ct[1] >> 1, sr = ct[1] & 1, lc = ct[2] >> 1, sc = ct[2] & 1;
+            const size_t row = size_t(dg.n) + (lr * P + (sr ? P - 1 - qa : qa)) * 4 + (rr & 3);
+#pragma unroll
+            for (int c = 0; c < BS; ++c) {
+                const int qb = c >> 2;
+                const size_t cl = size_t(dg.n) + (lc * P + (sc ? P - 1 - qb : qb)) * 4 + (c & 3);
+                const size_t o = size_t(imp) * N * N + cl * N + row;
+                acc[c] += L64 ? reinterpret_cast<const double*>(dg.M)[o]
+                              : double(reinterpret_cast<const float*>(dg.M)[o]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < BS; ++c) {
+            C v = c == r ? C(1) : C(0);
+            if (valid) v = L64 ? C(acc[c]) : C(float(acc[c]));
+            t[c] = r < BS ? v : C(0);
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < BS; ++c) {
+            const size_t i = blk + size_t(c) * BS + min(r, BS - 1);   // in bounds
+            C v = c == r ? C(1) : C(0);
+            if (valid) v = L64 ? C(L64[i]) : C(L32[i]);
+            t[c] = r < BS ? v : C(0);
+        }
     }
     C sig = C(1);
     bool used = r >= BS, bad = false;
@@ -364,7 +399,9 @@ __global__ __launch_bounds__(256) void k_block_inverse32(int ntf, const int* dia
 hipError_t launch_block_inverse_impl(int ntf, int bs, const int* diag_blk,
                                      const double* L64, const float* L32,
                                      int pc, void* out, int* fail,
-                                     hipStream_t st) {
+                                     hipStream_t st, const DiagGather* dgp) {
+    const DiagGather dg = dgp ? *dgp : DiagGather{};
+    if (dg.M && bs != 20 && bs != 24) return hipErrorInvalidValue;
     if (ntf == 0) return hipSuccess;
     const dim3 blk(256);
     const dim3 grid16((ntf + 15) / 16);            // four blocks per wave
@@ -372,9 +409,9 @@ hipError_t launch_block_inverse_impl(int ntf, int bs, const int* diag_blk,
     const bool f64 = pc == HFR_PC_FP64;
 #define HFR_INV32(B)                                                                          \
     if (f64) hipLaunchKernelGGL((k_block_inverse32<B, double>), grid32, blk, 0, st, ntf,     \
-                                diag_blk, L64, L32, pc, out, fail);                          \
+                                diag_blk, L64, L32, pc, out, fail, dg);                      \
     else hipLaunchKernelGGL((k_block_inverse32<B, float>), grid32, blk, 0, st, ntf,          \
-                            diag_blk, L64, L32, pc, out, fail);                              \
+                            diag_blk, L64, L32, pc, out, fail, dg);                          \
     break;
 #define HFR_INV16(B)                                                                          \
     if (f64) hipLaunchKernelGGL((k_block_inverse16<B, double>), grid16, blk, 0, st, ntf,     \

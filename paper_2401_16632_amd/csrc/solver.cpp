@@ -23,7 +23,7 @@ namespace hfr {
 hipError_t launch_block_inverse_impl(int ntf, int bs, const int* diag_blk,
                                      const double* L64, const float* L32,
                                      int pc, void* out, int* fail,
-                                     hipStream_t st);
+                                     hipStream_t st, const DiagGather* dg = nullptr);
 hipError_t launch_trace_average_ops(const RefOps& o, int ntp, int Ne,
                                     const int* tpside, const int* imp_list,
                                     const double* u, double* uhat,
@@ -430,35 +430,47 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
         fr_status ea = efr_assemble(s, true, st);
         tend(s, tk, st);
         if (ea) return ea;
-    } else {
+    }
+    // HFR face blocks of 20 and 24: the assembly forms t only, the
+    // block-Jacobi inverse gathers the diagonal blocks from the tableaux, and
+    // L is gathered with Lt = L Dinv after that
+    const bool fuse_pc = !m->efr && assemble_precondition_fused(m->P);
     AssembleLaunch a{};
-    a.nblocks = s->nblocks;
-    a.blk_contrib = s->contrib;
-    a.ntf = m->Ntf;
-    a.tside = s->tside;
-    a.M = s->M;
-    a.precision = s->opts.precision;
-    a.P = m->P;
-    a.n = s->n;
-    a.m = s->m;
-    a.L64 = s->L64;
-    a.L32 = s->L32;
-    a.t = s->t;
-    a.g = s->g;
-    a.z = s->zz;
-    tk = tbegin(s, HFR_T_ASSEMBLE, st);
-    HIP_TRY(launch_assemble(a, st));
-    tend(s, tk, st);
+    if (!m->efr) {
+        a.nblocks = fuse_pc ? 0 : s->nblocks;
+        a.blk_contrib = s->contrib;
+        a.ntf = m->Ntf;
+        a.tside = s->tside;
+        a.M = s->M;
+        a.precision = s->opts.precision;
+        a.P = m->P;
+        a.n = s->n;
+        a.m = s->m;
+        a.L64 = s->L64;
+        a.L32 = s->L32;
+        a.t = s->t;
+        a.g = s->g;
+        a.z = s->zz;
+        tk = tbegin(s, HFR_T_ASSEMBLE, st);
+        HIP_TRY(launch_assemble(a, st));
+        tend(s, tk, st);
     }
     tk = tbegin(s, HFR_T_PCSETUP, st);
+    const DiagGather dg{s->contrib, s->M, s->n, s->m};
     HIP_TRY(launch_block_inverse_impl(s->nbr, s->bs, s->diag_blk, s->L64,
                                       s->L64 ? nullptr : s->L32,
                                       s->opts.precond, s->Dinv, s->flags + 1,
-                                      st));
-    HIP_TRY(launch_precondition_matrix(s->nblocks, s->bs, s->col, s->L64,
-                                       s->L64 ? nullptr : s->L32,
-                                       s->opts.precond, s->Dinv, s->Lt64,
-                                       s->Lt32, st));
+                                      st, fuse_pc ? &dg : nullptr));
+    if (fuse_pc) {
+        a.nblocks = s->nblocks;
+        HIP_TRY(launch_assemble_precondition(a, s->col, s->opts.precond, s->Dinv,
+                                             s->Lt64, s->Lt32, st));
+    } else {
+        HIP_TRY(launch_precondition_matrix(s->nblocks, s->bs, s->col, s->L64,
+                                           s->L64 ? nullptr : s->L32,
+                                           s->opts.precond, s->Dinv, s->Lt64,
+                                           s->Lt32, st));
+    }
     tend(s, tk, st);
     return FR_OK;
 }

@@ -607,11 +607,13 @@ hipError_t launch_newton_norms(int Nx, const double* x, int Ny, const double* y,
 
 // ---- recovery (eq:localproblems) from the swept element tableau:
 // du[k] = (A^-1 r)[k] - (A^-1 B duhat_loc)[k] = y~[p_k] + T[p_k][n:N] duhat_loc
-// with y~ from the FP64 right-hand-side pass (pivot-row order).  One wave
-// per element, four elements per workgroup; lane l computes the unknowns
-// l, l + 64, ...  With nu set the same launch also applies the Newton update:
-// every element adds du to its state in u, and the workgroups past the
-// elements' add duhat to uhat (neither u nor uhat is read by the recovery).
+// with y~ from the FP64 right-hand-side pass (pivot-row order).  One
+// workgroup per element: thread (c, g) takes rows 4g .. 4g+3 of the columns
+// c, c + CS, ... of T[:, n:N] as 16-byte reads, the CS partial sums meet in
+// LDS, and thread r forms unknown r from pivot row p_r.  With nu set the
+// same launch also applies the Newton update: every element adds du to its
+// state in u, and the workgroups past the elements' add duhat to uhat
+// (neither u nor uhat is read by the recovery).
 struct NewtonUpdate {
     double* u;              // [4][Ne][Np] state (null: recovery only)
     const int* imp_list;
@@ -628,41 +630,51 @@ __global__ __launch_bounds__(256) void k_recover(RefOps o, int efr, int nimp,
                                                  double* du, const int* gate,
                                                  NewtonUpdate nu) {
     constexpr int NP = P * P, n = 4 * NP, m = 16 * P, N = n + m;
-    __shared__ double sloc[4][m];
+    constexpr int RG = NP;                          // groups of four rows
+    constexpr int CS = (256 / RG < m ? 256 / RG : m);   // column sets
+    __shared__ double sloc[m];
+    __shared__ double part[CS][n];
     if (gate && *gate == 0) return;               // uniform over the grid
-    const int nbe = (nimp + 3) / 4;
-    if (int(blockIdx.x) >= nbe) {                 // trace part of the update
-        const long i = (long(blockIdx.x) - nbe) * blockDim.x + threadIdx.x;
+    if (int(blockIdx.x) >= nimp) {                // trace part of the update
+        const long i = (long(blockIdx.x) - nimp) * blockDim.x + threadIdx.x;
         if (i < nu.ntp4) nu.uhat[i] += duhat[i];
         return;                                   // uniform over the workgroup
     }
-    __shared__ double gi[P * P];
-    for (int t = threadIdx.x; t < P * P; t += blockDim.x) gi[t] = o.gi[t];
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int k = blockIdx.x * 4 + wv;
-    if (k >= nimp) return;
-    for (int b = lane; b < m; b += 64) {
+    const int k = blockIdx.x, t = threadIdx.x;
+    if (t < m) {
+        const int b = t;
         const int f = b / (4 * P), q = (b >> 2) % P, w = b & 3;
         const int* tm = trace_map + (size_t(k) * 4 + f) * P;
         double v = 0.0;
         if (efr) {
             // trace at the flux point from the face's GLL nodes
             if (tm[0] >= 0)
-                for (int i = 0; i < P; ++i) v += gi[q * P + i] * duhat[size_t(tm[i]) * 4 + w];
+                for (int i = 0; i < P; ++i) v += o.gi[q * P + i] * duhat[size_t(tm[i]) * 4 + w];
         } else if (tm[q] >= 0) {
             v = duhat[size_t(tm[q]) * 4 + w];
         }
-        sloc[wv][b] = v;
+        sloc[b] = v;
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const T* Mk = M + size_t(k) * N * N + size_t(n) * N;
-    for (int row = lane; row < n; row += 64) {
+    __syncthreads();
+    if (t < RG * CS) {
+        const int c = t / RG, g = t - c * RG;
+        const T* Mk = M + size_t(k) * N * N + size_t(n) * N + 4 * g;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int b = c; b < m; b += CS) {
+            double x[4];
+            Vec4<T>::get(Mk + size_t(b) * N, x);
+            const double s = sloc[b];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r] += x[r] * s;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part[c][4 * g + r] = acc[r];
+    }
+    __syncthreads();
+    for (int row = t; row < n; row += blockDim.x) {
         const int pr = piv[size_t(k) * n + row];
         double acc = yr[size_t(k) * n + pr];
-        for (int b = 0; b < m; ++b) acc += double(Mk[size_t(b) * N + pr]) * sloc[wv][b];
+        for (int c = 0; c < CS; ++c) acc += part[c][pr];
         du[size_t(row & 3) * nimp * NP + size_t(k) * NP + (row >> 2)] = acc;
         if (nu.u)
             nu.u[size_t(row & 3) * nu.Ne * NP + size_t(nu.imp_list[k]) * NP + (row >> 2)] += acc;
@@ -676,7 +688,7 @@ static hipError_t launch_recover_t(const RefOps& o, int efr, int nimp, const T* 
                                    double* du, const int* gate, const NewtonUpdate& nu,
                                    hipStream_t st) {
     const int nbt = nu.u ? int((nu.ntp4 + 255) / 256) : 0;
-    const dim3 grid((nimp + 3) / 4 + nbt), blk(256);
+    const dim3 grid(nimp + nbt), blk(256);
 #define HFR_RC(PP) hipLaunchKernelGGL((k_recover<T, PP>), grid, blk, 0, st, o, efr, nimp, M, piv, yr, trace_map, duhat, du, gate, nu); break;
     switch (o.P) {
         case 2: HFR_RC(2)

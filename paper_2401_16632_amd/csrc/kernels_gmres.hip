@@ -1239,7 +1239,12 @@ hipError_t launch_arnoldi_orth(const GmresArgs& a, int j, double* wnxt,
 
 hipError_t launch_gmres_update(const GmresArgs& a, double* x, int cond, int jfin,
                                hipStream_t st) {
-    hipLaunchKernelGGL(k_gmres_update, dim3(a.nblk), dim3(kThr), 0, st, a, x, cond, jfin);
+    // one sub-chunk of faces per workgroup (the update writes no partial
+    // sums, so its decomposition is free; it reads a.nblk partials)
+    GmresArgs u = a;
+    u.fpb = std::max(1, kThr / a.bs);
+    const int grid = std::max(1, (a.ntf + u.fpb - 1) / u.fpb);
+    hipLaunchKernelGGL(k_gmres_update, dim3(grid), dim3(kThr), 0, st, u, x, cond, jfin);
     return hipGetLastError();
 }
 

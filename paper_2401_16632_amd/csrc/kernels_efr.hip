@@ -48,6 +48,23 @@ hipError_t launch_efr_gather_g(const RefOps& ops, int nnodes, const int* inc_ptr
     return hipGetLastError();
 }
 
+__device__ __forceinline__ void load4_aligned(const float* p, float (&q)[4]) {
+    const float4 x = *reinterpret_cast<const float4*>(p);
+    q[0] = x.x; q[1] = x.y; q[2] = x.z; q[3] = x.w;
+}
+__device__ __forceinline__ void load4_aligned(const double* p, double (&q)[4]) {
+    const double2 x = reinterpret_cast<const double2*>(p)[0];
+    const double2 y = reinterpret_cast<const double2*>(p)[1];
+    q[0] = x.x; q[1] = x.y; q[2] = y.x; q[3] = y.y;
+}
+__device__ __forceinline__ void store4_aligned(float* p, const float (&q)[4]) {
+    *reinterpret_cast<float4*>(p) = make_float4(q[0], q[1], q[2], q[3]);
+}
+__device__ __forceinline__ void store4_aligned(double* p, const double (&q)[4]) {
+    reinterpret_cast<double2*>(p)[0] = make_double2(q[0], q[1]);
+    reinterpret_cast<double2*>(p)[1] = make_double2(q[2], q[3]);
+}
+
 // In place on the Schur block of element blockIdx.x (rows/columns n..n+m of
 // the column-major N x N tableau, N = n + m): first every row's P values of
 // a (face, variable) column group become sum_q' L[r][(f,q',w)] phi_i'(x_q'),
@@ -89,9 +106,75 @@ __global__ void k_efr_transform(RefOps og, int nimp, T* M, int n, int m) {
     }
 }
 
+// The same two passes on a copy of the Schur block in LDS (row stride
+// m + 4): the block is read and written once, as 16-byte pieces.
+template <typename T>
+__global__ __launch_bounds__(256) void k_efr_transform_lds(RefOps og, int nimp, T* M, int n,
+                                                           int m) {
+    extern __shared__ __align__(16) unsigned char efr_dyn[];
+    T* sL = reinterpret_cast<T*>(efr_dyn);
+    __shared__ double gi[kMaxP * kMaxP];
+    for (int t = threadIdx.x; t < kMaxP * kMaxP; t += blockDim.x) gi[t] = og.gi[t];
+    const int P = og.P, N = n + m, S = m + 4, m4 = m / 4;
+    const int k = blockIdx.x;
+    T* L = M + size_t(k) * N * N + size_t(n) * N + n;   // L[r][c] = L[c*N + r]
+    for (int t = threadIdx.x; t < m * m4; t += blockDim.x) {
+        const int c = t / m4, r = (t - c * m4) * 4;
+        T q[4];
+        load4_aligned(L + size_t(c) * N + r, q);
+        store4_aligned(sL + c * S + r, q);
+    }
+    __syncthreads();
+    const int groups = m / P;                            // (face, variable) groups
+    double x[kMaxP], y[kMaxP];
+    // columns: thread per (row, column group)
+    for (int t = threadIdx.x; t < m * groups; t += blockDim.x) {
+        const int r = t % m, gc = t / m;
+        const int f = gc >> 2, w = gc & 3;
+        for (int q = 0; q < P; ++q) x[q] = double(sL[((f * P + q) * 4 + w) * S + r]);
+        for (int i = 0; i < P; ++i) {
+            double acc = 0.0;
+            for (int q = 0; q < P; ++q) acc += x[q] * gi[q * P + i];
+            y[i] = acc;
+        }
+        for (int i = 0; i < P; ++i) sL[((f * P + i) * 4 + w) * S + r] = T(y[i]);
+    }
+    __syncthreads();
+    // rows: thread per (column, row group)
+    for (int t = threadIdx.x; t < m * groups; t += blockDim.x) {
+        const int gr = t % groups, c = t / groups;
+        const int f = gr >> 2, v = gr & 3;
+        for (int q = 0; q < P; ++q) x[q] = double(sL[c * S + (f * P + q) * 4 + v]);
+        for (int i = 0; i < P; ++i) {
+            double acc = 0.0;
+            for (int q = 0; q < P; ++q) acc += gi[q * P + i] * x[q];
+            y[i] = acc;
+        }
+        for (int i = 0; i < P; ++i) sL[c * S + (f * P + i) * 4 + v] = T(y[i]);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < m * m4; t += blockDim.x) {
+        const int c = t / m4, r = (t - c * m4) * 4;
+        T q[4];
+        load4_aligned(sL + c * S + r, q);
+        store4_aligned(L + size_t(c) * N + r, q);
+    }
+}
+
 hipError_t launch_efr_transform(const RefOps& ops, int nimp, void* M,
                                 int precision, int n, int m, hipStream_t st) {
     if (nimp == 0) return hipSuccess;
+    const size_t sc = precision == HFR_PREC_FP64 ? 8 : 4;
+    const size_t lds = sc * size_t(m) * (m + 4);
+    if (lds <= 64 * 1024) {
+        if (precision == HFR_PREC_FP64)
+            hipLaunchKernelGGL(k_efr_transform_lds<double>, dim3(nimp), dim3(kThreads), lds,
+                               st, ops, nimp, reinterpret_cast<double*>(M), n, m);
+        else
+            hipLaunchKernelGGL(k_efr_transform_lds<float>, dim3(nimp), dim3(kThreads), lds,
+                               st, ops, nimp, reinterpret_cast<float*>(M), n, m);
+        return hipGetLastError();
+    }
     if (precision == HFR_PREC_FP64)
         hipLaunchKernelGGL(k_efr_transform<double>, dim3(nimp), dim3(kThreads), 0, st,
                            ops, nimp, reinterpret_cast<double*>(M), n, m);
@@ -101,15 +184,6 @@ hipError_t launch_efr_transform(const RefOps& ops, int nimp, void* M,
     return hipGetLastError();
 }
 
-__device__ __forceinline__ void load4_aligned(const float* p, float (&q)[4]) {
-    const float4 x = *reinterpret_cast<const float4*>(p);
-    q[0] = x.x; q[1] = x.y; q[2] = x.z; q[3] = x.w;
-}
-__device__ __forceinline__ void load4_aligned(const double* p, double (&q)[4]) {
-    const double2 x = reinterpret_cast<const double2*>(p)[0];
-    const double2 y = reinterpret_cast<const double2*>(p)[1];
-    q[0] = x.x; q[1] = x.y; q[2] = y.x; q[3] = y.y;
-}
 
 // node blocks (4x4, column-major) of L from the transformed element Schur
 // blocks, then t = -g - sum over node slots of sum_q phi_i(x_q) z

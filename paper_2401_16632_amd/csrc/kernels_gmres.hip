@@ -841,6 +841,39 @@ __global__ __launch_bounds__(256) void k_precondition_matrix(int nblocks, const 
     }
 }
 
+// bs = 4 (the node blocks of the interior-embedded trace): one thread per
+// block row, the same FP64 sums in the same order as k_precondition_matrix;
+// the four threads of a block read its 16 entries of L and of Dinv together
+// and the row leaves as one 16-byte (FP32) or two (FP64) stores.
+template <typename TL, typename TD>
+__global__ __launch_bounds__(256) void k_precondition_matrix4(int nblocks, const int* col,
+                                                              const TL* L, const TD* Dinv,
+                                                              TL* Lt) {
+    const long t = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= 4 * long(nblocks)) return;
+    const int p = int(t >> 2), a = int(t & 3);
+    const size_t lb = size_t(p) * 16, db = size_t(col[p]) * 16;
+    double l[4], d[16];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) l[c] = double(L[lb + 4 * c + a]);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) d[i] = load_pc(Dinv, db + i);   // Dinv(c, b) at 4 b + c
+    double acc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        acc[b] = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[b] = fma(l[c], d[4 * b + c], acc[b]);
+    }
+    if constexpr (sizeof(TL) == 4) {
+        *reinterpret_cast<float4*>(Lt + lb + 4 * a) =
+            make_float4(float(acc[0]), float(acc[1]), float(acc[2]), float(acc[3]));
+    } else {
+        reinterpret_cast<double2*>(Lt + lb + 4 * a)[0] = make_double2(acc[0], acc[1]);
+        reinterpret_cast<double2*>(Lt + lb + 4 * a)[1] = make_double2(acc[2], acc[3]);
+    }
+}
+
 // bs = 16: the same product on 16x16x4 matrix-core tiles, one wave per
 // block, K = 16 in four steps.  Operands: lane l = 16 g + i holds
 // L(i, 4kk + g) (a contiguous 64-value slice of the column-major block) and
@@ -1132,6 +1165,19 @@ static void launch_pm_t(int nblocks, const int* col, const TL* L, int pc,
                                nblocks, col, L, reinterpret_cast<const float*>(Dinv), Lt);
         else
             hipLaunchKernelGGL((k_precondition_matrix2x2<BS, TL, uint16_t>), grid, blk, 0, st,
+                               nblocks, col, L, reinterpret_cast<const uint16_t*>(Dinv), Lt);
+        return;
+    }
+    if constexpr (BS == 4) {
+        const dim3 g4((4 * long(nblocks) + 255) / 256);
+        if (pc == HFR_PC_FP64)
+            hipLaunchKernelGGL((k_precondition_matrix4<TL, double>), g4, blk, 0, st, nblocks,
+                               col, L, reinterpret_cast<const double*>(Dinv), Lt);
+        else if (pc == HFR_PC_FP32)
+            hipLaunchKernelGGL((k_precondition_matrix4<TL, float>), g4, blk, 0, st, nblocks,
+                               col, L, reinterpret_cast<const float*>(Dinv), Lt);
+        else
+            hipLaunchKernelGGL((k_precondition_matrix4<TL, uint16_t>), g4, blk, 0, st,
                                nblocks, col, L, reinterpret_cast<const uint16_t*>(Dinv), Lt);
         return;
     }

@@ -3,8 +3,9 @@
 //
 // Right block-Jacobi preconditioning is folded into the matrix once per
 // linearisation: Lt = L Dinv (Dinv = inverse of each trace face's diagonal
-// block, Lt stored row-major per block so that a row is one contiguous
-// vector load), so an Arnoldi step is one block-sparse product.  One Arnoldi
+// block, Lt stored per block by 16-byte row pieces so that the lanes of a
+// block's rows read adjacent pieces), so an Arnoldi step is one block-sparse
+// product.  One Arnoldi
 // step is two kernels (three with a second Gram-Schmidt pass) and no host
 // synchronisation:
 //   A: finish column j-1 (norm from the last pass's partials, Givens
@@ -161,25 +162,35 @@ __device__ void givens_column(const GmresArgs& a, int jc, double hn, bool write,
     g.gf = c * g.gj;
 }
 
+// Position of entry (a, b) of a bs x bs block of Lt: rows are cut into
+// 16-byte pieces (four FP32 or two FP64 entries) and the block holds piece
+// 0 of every row, then piece 1, ...
+template <typename T>
+__device__ __forceinline__ size_t lt_at(int a, int b, int bs) {
+    constexpr int CW = 16 / int(sizeof(T));
+    return (size_t(b / CW) * bs + a) * CW + (b % CW);
+}
+
 // Block-sparse product over rows [r0, r1) of the block's faces: 64 rows at a
 // time (up to 8 passes), thread group `part` takes blocks part, part+4, ...
-// of a row, the four shares are added in LDS.  Row-major blocks (Lt) are
-// read as contiguous vectors; column-major blocks (L) column by column
-// (consecutive lanes read consecutive rows of a column).
-// row aa of row-major block p times x's segment c, added to acc: all loads
+// of a row, the four shares are added in LDS.  Preconditioned blocks (Lt)
+// are stored by 16-byte row pieces, piece-major (lt_at), so the lanes of
+// consecutive rows read consecutive pieces; column-major blocks (L) are
+// read column by column (consecutive lanes read consecutive rows).
+// row aa of block p of Lt times x's segment c, added to acc: all loads
 // issued before the first FMA (block size fixed at compile time)
 template <int BS, typename T>
 __device__ __forceinline__ double row_block(const T* M, const double* x, int c, int p,
                                             int aa, double acc) {
     const double2* x2 = reinterpret_cast<const double2*>(x + size_t(c) * BS);
-    const T* row = M + (size_t(p) * BS + aa) * BS;
+    const T* blk = M + size_t(p) * BS * BS;
     double2 xv[BS / 2];
 #pragma unroll
     for (int b = 0; b < BS / 2; ++b) xv[b] = x2[b];
     if constexpr (sizeof(T) == 8) {
         double2 l[BS / 2];
 #pragma unroll
-        for (int b = 0; b < BS / 2; ++b) l[b] = reinterpret_cast<const double2*>(row)[b];
+        for (int b = 0; b < BS / 2; ++b) l[b] = reinterpret_cast<const double2*>(blk)[b * BS + aa];
 #pragma unroll
         for (int b = 0; b < BS / 2; ++b) {
             acc = fma(l[b].x, xv[b].x, acc);
@@ -188,7 +199,7 @@ __device__ __forceinline__ double row_block(const T* M, const double* x, int c, 
     } else {
         float4 l[BS / 4];
 #pragma unroll
-        for (int b = 0; b < BS / 4; ++b) l[b] = reinterpret_cast<const float4*>(row)[b];
+        for (int b = 0; b < BS / 4; ++b) l[b] = reinterpret_cast<const float4*>(blk)[b * BS + aa];
 #pragma unroll
         for (int b = 0; b < BS / 4; ++b) {
             acc = fma(double(l[b].x), xv[2 * b].x, acc);
@@ -200,7 +211,7 @@ __device__ __forceinline__ double row_block(const T* M, const double* x, int c, 
     return acc;
 }
 
-// The same share for row-major blocks of size BS through the padded table
+// The same share for blocks of Lt of size BS through the padded table
 // a.ell of the block rows (trace faces, or trace nodes in EFR): {block
 // index, block column} of row F's k-th block at F * kmax + k, {-1, -1} past
 // its end, so the block and column indices
@@ -250,19 +261,19 @@ __device__ __forceinline__ double row_share(const GmresArgs& a, const T* M,
     double acc = 0.0;
     for (int p = pb + part; p < p1; p += 4) {
         const double2* x2 = reinterpret_cast<const double2*>(x + size_t(a.col[p]) * bs);
-        if (ROW_MAJOR) {
-            const T* row = M + (size_t(p) * bs + aa) * bs;
+        if (ROW_MAJOR) {                           // Lt: 16-byte pieces, piece-major
+            const T* blk = M + size_t(p) * bs * bs;
             if constexpr (sizeof(T) == 8) {
-                const double2* l2 = reinterpret_cast<const double2*>(row);
+                const double2* l2 = reinterpret_cast<const double2*>(blk);
                 for (int b = 0; b < bs / 2; ++b) {
-                    const double2 l = l2[b], xv = x2[b];
+                    const double2 l = l2[b * bs + aa], xv = x2[b];
                     acc = fma(double(l.x), xv.x, acc);
                     acc = fma(double(l.y), xv.y, acc);
                 }
             } else {
-                const float4* l4 = reinterpret_cast<const float4*>(row);
+                const float4* l4 = reinterpret_cast<const float4*>(blk);
                 for (int b = 0; b < bs / 4; ++b) {
-                    const float4 l = l4[b];
+                    const float4 l = l4[b * bs + aa];
                     const double2 x0 = x2[2 * b], x1 = x2[2 * b + 1];
                     acc = fma(double(l.x), x0.x, acc);
                     acc = fma(double(l.y), x0.y, acc);
@@ -812,7 +823,7 @@ __device__ __forceinline__ void load4_pc(const uint16_t* d, double (&v)[4]) {
 // ---- Lt = L Dinv (per block: Lt_FG = L_FG Dinv_G) -------------------------
 // One wave per block, four blocks per workgroup; both factors staged in LDS
 // (FP64, Dinv transposed), each lane forms BS*BS/64 entries of the product.
-// L and Dinv are column-major per block; Lt is written row-major.
+// L and Dinv are column-major per block; Lt is written by 16-byte row pieces (lt_at).
 template <int BS, typename TL, typename TD>
 __global__ __launch_bounds__(256) void k_precondition_matrix(int nblocks, const int* col,
                                                              const TL* L, const TD* Dinv,
@@ -837,7 +848,7 @@ __global__ __launch_bounds__(256) void k_precondition_matrix(int nblocks, const 
         double acc = 0.0;
 #pragma unroll
         for (int c = 0; c < BS; ++c) acc = fma(sL[wv][c * BS + a], sD[wv][c * BS + b], acc);
-        Lt[lb + i] = TL(acc);
+        Lt[lb + lt_at<TL>(a, b, BS)] = TL(acc);
     }
 }
 
@@ -865,12 +876,12 @@ __global__ __launch_bounds__(256) void k_precondition_matrix4(int nblocks, const
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[b] = fma(l[c], d[4 * b + c], acc[b]);
     }
-    if constexpr (sizeof(TL) == 4) {
-        *reinterpret_cast<float4*>(Lt + lb + 4 * a) =
+    if constexpr (sizeof(TL) == 4) {                // one piece: the row
+        *reinterpret_cast<float4*>(Lt + lb + lt_at<float>(a, 0, 4)) =
             make_float4(float(acc[0]), float(acc[1]), float(acc[2]), float(acc[3]));
-    } else {
-        reinterpret_cast<double2*>(Lt + lb + 4 * a)[0] = make_double2(acc[0], acc[1]);
-        reinterpret_cast<double2*>(Lt + lb + 4 * a)[1] = make_double2(acc[2], acc[3]);
+    } else {                                       // pieces (a, 0..1) and (a, 2..3)
+        *reinterpret_cast<double2*>(Lt + lb + lt_at<double>(a, 0, 4)) = make_double2(acc[0], acc[1]);
+        *reinterpret_cast<double2*>(Lt + lb + lt_at<double>(a, 2, 4)) = make_double2(acc[2], acc[3]);
     }
 }
 
@@ -916,7 +927,7 @@ __global__ __launch_bounds__(256) void k_precondition_matrix16(int nblocks, cons
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], b, acc, 0, 0, 0);
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Lt[lb + (4 * g + r) * 16 + i] = acc[r];
+        for (int r = 0; r < 4; ++r) Lt[lb + lt_at<TL>(4 * g + r, i, 16)] = acc[r];
     } else {
         md4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -925,7 +936,7 @@ __global__ __launch_bounds__(256) void k_precondition_matrix16(int nblocks, cons
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk], b, acc, 0, 0, 0);
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Lt[lb + (g + 4 * r) * 16 + i] = acc[r];
+        for (int r = 0; r < 4; ++r) Lt[lb + lt_at<TL>(g + 4 * r, i, 16)] = acc[r];
     }
 }
 
@@ -976,7 +987,7 @@ __global__ __launch_bounds__(256) void k_precondition_matrix2x2(int nblocks, con
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int a = 16 * ti + 4 * g + r, b = 16 * tj + i;
-                    if (a < BS && b < BS) Lt[lb + size_t(a) * BS + b] = acc[r];
+                    if (a < BS && b < BS) Lt[lb + lt_at<TL>(a, b, BS)] = acc[r];
                 }
             } else {
                 md4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -986,7 +997,7 @@ __global__ __launch_bounds__(256) void k_precondition_matrix2x2(int nblocks, con
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int a = 16 * ti + g + 4 * r, b = 16 * tj + i;
-                    if (a < BS && b < BS) Lt[lb + size_t(a) * BS + b] = acc[r];
+                    if (a < BS && b < BS) Lt[lb + lt_at<TL>(a, b, BS)] = acc[r];
                 }
             }
         }
@@ -1110,10 +1121,16 @@ __global__ __launch_bounds__(256) void k_assemble_precondition(AssembleLaunch a,
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // piece e of Lt: 16 bytes of row e mod BS at piece e div BS
+    constexpr int CW = 16 / int(sizeof(TL)), QW = BB / CW;
 #pragma unroll
-    for (int e0 = 0; e0 < Q; e0 += 64) {
+    for (int e0 = 0; e0 < QW; e0 += 64) {
         const int e = e0 + lane;
-        if (e < Q) Vec4Load<TL>::copy(Lt + lb + 4 * size_t(e), &lsh[wv][4 * e]);
+        if (e < QW) {
+            const int c = e / BS, ar = e - c * BS;
+            *reinterpret_cast<float4*>(Lt + lb + size_t(e) * CW) =
+                *reinterpret_cast<const float4*>(&lsh[wv][ar * BS + c * CW]);
+        }
     }
 }
 

@@ -940,77 +940,15 @@ __global__ __launch_bounds__(256) void k_precondition_matrix16(int nblocks, cons
     }
 }
 
-// bs = 20 and 24: the same product on 2 x 2 zero-padded 16x16 tiles per
-// block (rows and columns 0..15 and 16..BS-1), K = BS in BS/4 steps of
-// 16x16x4 tiles; operands read straight from the column-major blocks.
-template <int BS, typename TL, typename TD>
-__global__ __launch_bounds__(256) void k_precondition_matrix2x2(int nblocks, const int* col,
-                                                                const TL* L, const TD* Dinv,
-                                                                TL* Lt) {
-    static_assert(BS > 16 && BS <= 32 && BS % 4 == 0, "2x2 tiles of 16");
-    constexpr int BB = BS * BS, KC = BS / 4;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int p = blockIdx.x * 4 + wv;
-    if (p >= nblocks) return;                      // whole wave
-    const int i = lane & 15, g = lane >> 4;
-    const size_t lb = size_t(p) * BB;
-    // A operands: L(16 ti + i, 4 kk + g); rows past BS are zero
-    TL av[2][KC];
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
-            const int a = 16 * ti + i;
-            const TL v = L[lb + size_t(4 * kk + g) * BS + min(a, BS - 1)];
-            av[ti][kk] = a < BS ? v : TL(0);
-        }
-    const size_t db = size_t(col[p]) * BB;
-    // B operands: Dinv(4 kk + g, 16 tj + i); columns past BS are zero
-    TL bv[2][KC];
-#pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
-            const int b = 16 * tj + i;
-            const TL v = TL(load_pc(Dinv, db + size_t(min(b, BS - 1)) * BS + 4 * kk + g));
-            bv[tj][kk] = b < BS ? v : TL(0);
-        }
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < 2; ++tj) {
-            if constexpr (sizeof(TL) == 4) {
-                mf4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int kk = 0; kk < KC; ++kk)
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ti][kk], bv[tj][kk], acc, 0, 0, 0);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int a = 16 * ti + 4 * g + r, b = 16 * tj + i;
-                    if (a < BS && b < BS) Lt[lb + lt_at<TL>(a, b, BS)] = acc[r];
-                }
-            } else {
-                md4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int kk = 0; kk < KC; ++kk)
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti][kk], bv[tj][kk], acc, 0, 0, 0);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int a = 16 * ti + g + 4 * r, b = 16 * tj + i;
-                    if (a < BS && b < BS) Lt[lb + lt_at<TL>(a, b, BS)] = acc[r];
-                }
-            }
-        }
-}
-
 // Assembly and preconditioning in one pass (eq:assembly, then Lt = L Dinv)
 // for block sizes 20 and 24: each wave gathers its block of L from the at
 // most two element Schur blocks in the tableaux (as the assembly does: four
 // rows of one column per 16-byte read, the sum formed in FP64 and rounded
 // once), stores it, stages it in LDS and multiplies it by the column face's
-// inverse diagonal block on the same 2 x 2 tiles as
-// k_precondition_matrix2x2, so L is read from the tableaux once instead of
-// being written, read back and multiplied.  The diagonal blocks and their
+// inverse diagonal block on 2 x 2 zero-padded 16x16 tiles (rows and
+// columns 0..15 and 16..BS-1, K = BS in BS/4 steps of 16x16x4), so L is
+// read from the tableaux once instead of being written, read back and
+// multiplied.  The diagonal blocks and their
 // inverses must already exist (assembled and inverted first); their L
 // blocks are rewritten with the same values.
 template <int BS, int P, typename TL, typename TD>
@@ -1173,18 +1111,6 @@ template <int BS, typename TL>
 static void launch_pm_t(int nblocks, const int* col, const TL* L, int pc,
                         const void* Dinv, TL* Lt, hipStream_t st) {
     const dim3 grid((nblocks + 3) / 4), blk(256);
-    if constexpr (BS == 20 || BS == 24) {
-        if (pc == HFR_PC_FP64)
-            hipLaunchKernelGGL((k_precondition_matrix2x2<BS, TL, double>), grid, blk, 0, st,
-                               nblocks, col, L, reinterpret_cast<const double*>(Dinv), Lt);
-        else if (pc == HFR_PC_FP32)
-            hipLaunchKernelGGL((k_precondition_matrix2x2<BS, TL, float>), grid, blk, 0, st,
-                               nblocks, col, L, reinterpret_cast<const float*>(Dinv), Lt);
-        else
-            hipLaunchKernelGGL((k_precondition_matrix2x2<BS, TL, uint16_t>), grid, blk, 0, st,
-                               nblocks, col, L, reinterpret_cast<const uint16_t*>(Dinv), Lt);
-        return;
-    }
     if constexpr (BS == 4) {
         const dim3 g4((4 * long(nblocks) + 255) / 256);
         if (pc == HFR_PC_FP64)
@@ -1229,8 +1155,8 @@ static hipError_t launch_pm(int nblocks, int bs, const int* col, const TL* L, in
         case 8: launch_pm_t<8>(nblocks, col, L, pc, Dinv, Lt, st); break;
         case 12: launch_pm_t<12>(nblocks, col, L, pc, Dinv, Lt, st); break;
         case 16: launch_pm_t<16>(nblocks, col, L, pc, Dinv, Lt, st); break;
-        case 20: launch_pm_t<20>(nblocks, col, L, pc, Dinv, Lt, st); break;
-        case 24: launch_pm_t<24>(nblocks, col, L, pc, Dinv, Lt, st); break;
+        // 20 and 24: assembled and preconditioned together
+        // (launch_assemble_precondition)
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -260,7 +260,10 @@ __global__ __launch_bounds__(256) void k_block_inverse16(int ntf, const int* dia
 // Blocks of 17 to 32 rows: two blocks per wave, one per half of 32 lanes.
 // The pivot search is the 16-lane DPP maximum, then row 0 into row 1 and
 // row 2 into row 3 (row_bcast:15), read back from lanes 31 and 63; the
-// pivot row is passed through LDS as for the 16-row blocks.
+// pivot row is passed through LDS as for the 16-row blocks.  These are the
+// face blocks of p = 4 and 5, whose L is assembled together with L Dinv
+// afterwards: each lane sums its row of the diagonal block from the element
+// tableaux (dg) instead of reading an assembled L.
 __device__ __forceinline__ unsigned long long half32_max_key(unsigned long long x, int half) {
     x = row16_max_key(x);
     x = key_max(x, key_dpp<0x142, 0xa>(x));     // row_bcast:15 into rows 1, 3
@@ -295,7 +298,7 @@ __global__ __launch_bounds__(256) void k_block_inverse32(int ntf, const int* dia
     const bool valid = F < ntf;
     const size_t blk = valid ? size_t(diag_blk[F]) * BS * BS : 0;
     C t[BS];
-    if (dg.M) {
+    {
         // the block summed from the element tableaux as the assembly forms it
         // (FP64 sum rounded to the storage precision of L)
         constexpr int P = BS / 4;
@@ -324,14 +327,6 @@ __global__ __launch_bounds__(256) void k_block_inverse32(int ntf, const int* dia
         for (int c = 0; c < BS; ++c) {
             C v = c == r ? C(1) : C(0);
             if (valid) v = L64 ? C(acc[c]) : C(float(acc[c]));
-            t[c] = r < BS ? v : C(0);
-        }
-    } else {
-#pragma unroll
-        for (int c = 0; c < BS; ++c) {
-            const size_t i = blk + size_t(c) * BS + min(r, BS - 1);   // in bounds
-            C v = c == r ? C(1) : C(0);
-            if (valid) v = L64 ? C(L64[i]) : C(L32[i]);
             t[c] = r < BS ? v : C(0);
         }
     }
@@ -401,7 +396,9 @@ hipError_t launch_block_inverse_impl(int ntf, int bs, const int* diag_blk,
                                      int pc, void* out, int* fail,
                                      hipStream_t st, const DiagGather* dgp) {
     const DiagGather dg = dgp ? *dgp : DiagGather{};
-    if (dg.M && bs != 20 && bs != 24) return hipErrorInvalidValue;
+    // blocks of 20 and 24 rows are gathered from the tableaux, the others
+    // read from the assembled L
+    if ((bs == 20 || bs == 24) != (dg.M != nullptr)) return hipErrorInvalidValue;
     if (ntf == 0) return hipSuccess;
     const dim3 blk(256);
     const dim3 grid16((ntf + 15) / 16);            // four blocks per wave

@@ -66,8 +66,8 @@ hipError_t launch_precondition_matrix(int nblocks, int bs, const int* col,
                                       int pc, const void* Dinv, double* Lt64,
                                       float* Lt32, hipStream_t st);
 // L and Lt = L Dinv of every block in one pass from the element tableaux
-// (face blocks of 20 and 24: orders with assemble_precondition_fused); the
-// diagonal blocks of L and Dinv must be in place, and a.blk_list null
+// (face blocks of 16, 20 and 24: orders with assemble_precondition_fused);
+// Dinv must be in place, and a.blk_list null
 bool assemble_precondition_fused(int P);
 hipError_t launch_assemble_precondition(const AssembleLaunch& a, const int* col, int pc,
                                         const void* Dinv, double* Lt64, float* Lt32,

@@ -941,12 +941,12 @@ __global__ __launch_bounds__(256) void k_precondition_matrix16(int nblocks, cons
 }
 
 // Assembly and preconditioning in one pass (eq:assembly, then Lt = L Dinv)
-// for block sizes 20 and 24: each wave gathers its block of L from the at
+// for block sizes 16, 20 and 24: each wave gathers its block of L from the at
 // most two element Schur blocks in the tableaux (as the assembly does: four
 // rows of one column per 16-byte read, the sum formed in FP64 and rounded
 // once), stores it, stages it in LDS and multiplies it by the column face's
-// inverse diagonal block on 2 x 2 zero-padded 16x16 tiles (rows and
-// columns 0..15 and 16..BS-1, K = BS in BS/4 steps of 16x16x4), so L is
+// inverse diagonal block on 16x16 tiles (one, or 2 x 2 zero-padded: rows
+// and columns 0..15 and 16..BS-1; K = BS in BS/4 steps of 16x16x4), so L is
 // read from the tableaux once instead of being written, read back and
 // multiplied.  The diagonal blocks and their
 // inverses must already exist (assembled and inverted first); their L
@@ -955,8 +955,9 @@ template <int BS, int P, typename TL, typename TD>
 __global__ __launch_bounds__(256) void k_assemble_precondition(AssembleLaunch a, const int* col,
                                                                const TD* Dinv, TL* Lout,
                                                                TL* Lt) {
-    static_assert(BS == 4 * P && BS > 16 && BS <= 32, "2x2 tiles of 16");
+    static_assert(BS == 4 * P && BS >= 16 && BS <= 32, "one or 2 x 2 tiles of 16");
     constexpr int BB = BS * BS, KC = BS / 4, CH = BS * P;   // 4-row pieces per block
+    constexpr int NT = BS > 16 ? 2 : 1;            // 16x16 tiles per block side
     constexpr int Q = BB / 4;                      // 4-entry pieces of a block
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int p = blockIdx.x * 4 + wv;
@@ -1015,9 +1016,9 @@ __global__ __launch_bounds__(256) void k_assemble_precondition(AssembleLaunch a,
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // A operands L(16 ti + i, 4 kk + g), B operands Dinv(4 kk + g, 16 tj + i);
     // rows and columns past BS are zero
-    TL av[2][KC], bv[2][KC];
+    TL av[NT][KC], bv[NT][KC];
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) {
             const int x = 16 * t + i;
@@ -1031,9 +1032,9 @@ __global__ __launch_bounds__(256) void k_assemble_precondition(AssembleLaunch a,
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // the product tiles go to LDS row-major and leave as 16-byte pieces
 #pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
+    for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < 2; ++tj) {
+        for (int tj = 0; tj < NT; ++tj) {
             if constexpr (sizeof(TL) == 4) {
                 mf4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -1088,7 +1089,7 @@ static void launch_ap_t(const AssembleLaunch& a, const int* col, int pc, const v
                            col, reinterpret_cast<const uint16_t*>(Dinv), Lout, Lt);
 }
 
-bool assemble_precondition_fused(int P) { return P == 5 || P == 6; }
+bool assemble_precondition_fused(int P) { return P == 4 || P == 5 || P == 6; }
 
 hipError_t launch_assemble_precondition(const AssembleLaunch& a, const int* col, int pc,
                                         const void* Dinv, double* Lt64, float* Lt32,
@@ -1097,7 +1098,10 @@ hipError_t launch_assemble_precondition(const AssembleLaunch& a, const int* col,
     if (!assemble_precondition_fused(a.P) || a.blk_list) return hipErrorInvalidValue;
     const bool f64 = a.precision == HFR_PREC_FP64;
     if (f64 ? !(a.L64 && Lt64) : !(a.L32 && Lt32)) return hipErrorInvalidValue;
-    if (a.P == 5) {
+    if (a.P == 4) {
+        if (f64) launch_ap_t<4, double>(a, col, pc, Dinv, a.L64, Lt64, st);
+        else launch_ap_t<4, float>(a, col, pc, Dinv, a.L32, Lt32, st);
+    } else if (a.P == 5) {
         if (f64) launch_ap_t<5, double>(a, col, pc, Dinv, a.L64, Lt64, st);
         else launch_ap_t<5, float>(a, col, pc, Dinv, a.L32, Lt32, st);
     } else {

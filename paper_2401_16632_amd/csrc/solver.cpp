@@ -431,13 +431,16 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
         tend(s, tk, st);
         if (ea) return ea;
     }
-    // HFR face blocks of 20 and 24: the assembly forms t only, the
-    // block-Jacobi inverse gathers the diagonal blocks from the tableaux, and
-    // L is gathered with Lt = L Dinv after that
+    // HFR face blocks of 16, 20 and 24: the assembly forms t only (and the
+    // diagonal blocks at 16, which the 16-row inverse reads; at 20 and 24
+    // the inverse gathers them from the tableaux itself), and L is gathered
+    // with Lt = L Dinv after the inverses
     const bool fuse_pc = !m->efr && assemble_precondition_fused(m->P);
+    const bool gather_diag = fuse_pc && (s->bs == 20 || s->bs == 24);
     AssembleLaunch a{};
     if (!m->efr) {
-        a.nblocks = fuse_pc ? 0 : s->nblocks;
+        a.nblocks = !fuse_pc ? s->nblocks : gather_diag ? 0 : s->nbr;
+        a.blk_list = fuse_pc && !gather_diag ? s->diag_blk : nullptr;
         a.blk_contrib = s->contrib;
         a.ntf = m->Ntf;
         a.tside = s->tside;
@@ -460,9 +463,10 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
     HIP_TRY(launch_block_inverse_impl(s->nbr, s->bs, s->diag_blk, s->L64,
                                       s->L64 ? nullptr : s->L32,
                                       s->opts.precond, s->Dinv, s->flags + 1,
-                                      st, fuse_pc ? &dg : nullptr));
+                                      st, gather_diag ? &dg : nullptr));
     if (fuse_pc) {
         a.nblocks = s->nblocks;
+        a.blk_list = nullptr;
         HIP_TRY(launch_assemble_precondition(a, s->col, s->opts.precond, s->Dinv,
                                              s->Lt64, s->Lt32, st));
     } else {

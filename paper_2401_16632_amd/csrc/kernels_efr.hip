@@ -107,15 +107,15 @@ __global__ void k_efr_transform(RefOps og, int nimp, T* M, int n, int m) {
 }
 
 // The same two passes on a copy of the Schur block in LDS (row stride
-// m + 4): the block is read and written once, as 16-byte pieces.
-template <typename T>
-__global__ __launch_bounds__(256) void k_efr_transform_lds(RefOps og, int nimp, T* M, int n,
-                                                           int m) {
+// m + 4): the block is read and written once, as 16-byte pieces.  The order
+// is fixed at compile time, so a thread's P values stay in registers.
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_efr_transform_lds(RefOps og, int nimp, T* M) {
+    constexpr int n = 4 * P * P, m = 16 * P, N = n + m, S = m + 4, m4 = m / 4;
     extern __shared__ __align__(16) unsigned char efr_dyn[];
     T* sL = reinterpret_cast<T*>(efr_dyn);
-    __shared__ double gi[kMaxP * kMaxP];
-    for (int t = threadIdx.x; t < kMaxP * kMaxP; t += blockDim.x) gi[t] = og.gi[t];
-    const int P = og.P, N = n + m, S = m + 4, m4 = m / 4;
+    __shared__ double gi[P * P];
+    for (int t = threadIdx.x; t < P * P; t += blockDim.x) gi[t] = og.gi[t];
     const int k = blockIdx.x;
     T* L = M + size_t(k) * N * N + size_t(n) * N + n;   // L[r][c] = L[c*N + r]
     for (int t = threadIdx.x; t < m * m4; t += blockDim.x) {
@@ -125,18 +125,22 @@ __global__ __launch_bounds__(256) void k_efr_transform_lds(RefOps og, int nimp, 
         store4_aligned(sL + c * S + r, q);
     }
     __syncthreads();
-    const int groups = m / P;                            // (face, variable) groups
-    double x[kMaxP], y[kMaxP];
+    constexpr int groups = m / P;                        // (face, variable) groups
+    double x[P], y[P];
     // columns: thread per (row, column group)
     for (int t = threadIdx.x; t < m * groups; t += blockDim.x) {
         const int r = t % m, gc = t / m;
         const int f = gc >> 2, w = gc & 3;
+#pragma unroll
         for (int q = 0; q < P; ++q) x[q] = double(sL[((f * P + q) * 4 + w) * S + r]);
+#pragma unroll
         for (int i = 0; i < P; ++i) {
             double acc = 0.0;
+#pragma unroll
             for (int q = 0; q < P; ++q) acc += x[q] * gi[q * P + i];
             y[i] = acc;
         }
+#pragma unroll
         for (int i = 0; i < P; ++i) sL[((f * P + i) * 4 + w) * S + r] = T(y[i]);
     }
     __syncthreads();
@@ -144,12 +148,16 @@ __global__ __launch_bounds__(256) void k_efr_transform_lds(RefOps og, int nimp, 
     for (int t = threadIdx.x; t < m * groups; t += blockDim.x) {
         const int gr = t % groups, c = t / groups;
         const int f = gr >> 2, v = gr & 3;
+#pragma unroll
         for (int q = 0; q < P; ++q) x[q] = double(sL[c * S + (f * P + q) * 4 + v]);
+#pragma unroll
         for (int i = 0; i < P; ++i) {
             double acc = 0.0;
+#pragma unroll
             for (int q = 0; q < P; ++q) acc += gi[q * P + i] * x[q];
             y[i] = acc;
         }
+#pragma unroll
         for (int i = 0; i < P; ++i) sL[c * S + (f * P + i) * 4 + v] = T(y[i]);
     }
     __syncthreads();
@@ -161,19 +169,32 @@ __global__ __launch_bounds__(256) void k_efr_transform_lds(RefOps og, int nimp, 
     }
 }
 
+template <typename T>
+static hipError_t launch_efr_transform_lds(const RefOps& ops, int nimp, T* M, size_t lds,
+                                           hipStream_t st) {
+#define HFR_ET(PP) hipLaunchKernelGGL((k_efr_transform_lds<T, PP>), dim3(nimp), dim3(kThreads), \
+                                      lds, st, ops, nimp, M); break;
+    switch (ops.P) {
+        case 2: HFR_ET(2)
+        case 3: HFR_ET(3)
+        case 4: HFR_ET(4)
+        case 5: HFR_ET(5)
+        case 6: HFR_ET(6)
+        default: return hipErrorInvalidValue;
+    }
+#undef HFR_ET
+    return hipGetLastError();
+}
+
 hipError_t launch_efr_transform(const RefOps& ops, int nimp, void* M,
                                 int precision, int n, int m, hipStream_t st) {
     if (nimp == 0) return hipSuccess;
     const size_t sc = precision == HFR_PREC_FP64 ? 8 : 4;
     const size_t lds = sc * size_t(m) * (m + 4);
-    if (lds <= 64 * 1024) {
+    if (lds <= 64 * 1024 && n == 4 * ops.P * ops.P && m == 16 * ops.P) {
         if (precision == HFR_PREC_FP64)
-            hipLaunchKernelGGL(k_efr_transform_lds<double>, dim3(nimp), dim3(kThreads), lds,
-                               st, ops, nimp, reinterpret_cast<double*>(M), n, m);
-        else
-            hipLaunchKernelGGL(k_efr_transform_lds<float>, dim3(nimp), dim3(kThreads), lds,
-                               st, ops, nimp, reinterpret_cast<float*>(M), n, m);
-        return hipGetLastError();
+            return launch_efr_transform_lds(ops, nimp, reinterpret_cast<double*>(M), lds, st);
+        return launch_efr_transform_lds(ops, nimp, reinterpret_cast<float*>(M), lds, st);
     }
     if (precision == HFR_PREC_FP64)
         hipLaunchKernelGGL(k_efr_transform<double>, dim3(nimp), dim3(kThreads), 0, st,

@@ -276,8 +276,10 @@ typedef struct {
 /* HFR_CK_SWEEP: register-resident Gauss-Jordan sweep on the vector ALUs, one
  * exchange per step; HFR_CK_BLOCKED: panels of 16 exchanges, the update of
  * the rest of the tableau a product on the 16x16x4 matrix-core tiles (4 or
- * more waves per element); HFR_CK_BLOCKED_W8: the same with 8 waves per
- * element; HFR_CK_AUTO: the library's choice for the order and precision. */
+ * more waves per element), the Schur complement formed in the same launch,
+ * and in FP32 up to p = 4 the element linearisation as well (no separate
+ * tableau fill); HFR_CK_BLOCKED_W8: the same with 8 waves per element;
+ * HFR_CK_AUTO: the library's choice for the order and precision. */
 enum { HFR_CK_AUTO = 0, HFR_CK_SWEEP = 1, HFR_CK_BLOCKED = 2, HFR_CK_BLOCKED_W8 = 3 };
 
 typedef struct {
@@ -455,23 +457,27 @@ fr_status hfr_get_preconditioner(hfr_solver_t s, void* dinv, void* stream);
  * candidates (sweep, blocked, blocked with 8 waves; milliseconds per launch
  * on the solver's first linearisation, -1 if not measured).  With
  * hfr_opts.condense_kernel = HFR_CK_AUTO the solver measures every candidate
- * once per (order, precision) and process, on the tableaux of its first
- * Schur-only linearisation (filled again for each), and keeps the fastest;
+ * once per (order, precision) and process, on its first Schur-only
+ * linearisation (each candidate timed with the tableau fill it needs), and
+ * keeps the fastest;
  * later solvers of the same order and precision reuse that choice.
  */
 fr_status hfr_condense_choice(hfr_solver_t s, int32_t* kernel, double* candidate_ms);
 
 #define HFR_TIMING_SELECT 0x10000
 enum { HFR_T_RESIDUAL = 0,   /* hybridized residual kernel                 */
-       HFR_T_CONDENSE = 1,   /* element Jordan sweep kernel (condensation) */
-       HFR_T_ASSEMBLE = 2,   /* block-sparse assembly kernel               */
-       HFR_T_PCSETUP = 3,    /* block-Jacobi inversion kernel              */
+       HFR_T_CONDENSE = 1,   /* element elimination kernel (condensation;
+                                with the linearisation where fused)       */
+       HFR_T_ASSEMBLE = 2,   /* block-sparse assembly kernel (t only where
+                                L is formed with L Dinv, p = 3..5 HFR)    */
+       HFR_T_PCSETUP = 3,    /* block-Jacobi inversion and L Dinv kernels  */
        HFR_T_SPMV = 4,       /* Arnoldi product kernel (block-sparse
                                 product + first projection)               */
        HFR_T_TRACE_SOLVE = 5,/* whole trace solve (all Krylov kernels)     */
        HFR_T_RECOVER = 6,    /* local recovery kernel                      */
        HFR_T_EXPLICIT = 7,   /* explicit residual kernel (via imex_stage)  */
-       HFR_T_FILL = 8,       /* element linearisation + tableau fill kernel */
+       HFR_T_FILL = 8,       /* element linearisation + tableau fill kernel
+                                (where not fused into the elimination)    */
        HFR_NTIMERS = 9 };
 fr_status hfr_timing(hfr_solver_t s, int32_t enable, double* ms,
                      int64_t* counts);

@@ -272,6 +272,20 @@ typedef struct {
                                  The graphs name the stage buffers and the
                                  workspace; rebinding the workspace drops
                                  them.  0: eager launches only               */
+    double gmres_forcing_max; /* 0: every trace solve inside Newton to
+                                 gmres_rtol.  In [gmres_rtol, 1): inexact
+                                 Newton; the k-th solve of a stage stops at
+                                 the relative residual eta_k = 0.1 max(r_k
+                                 (r_k/r_{k-1})^2, tol) / r_k clamped to
+                                 [gmres_rtol, gmres_forcing_max], with r_k =
+                                 max(|h|inf, |g|inf) of the current iterate
+                                 and tol the Newton tolerance (the quadratic
+                                 model of the next residual, so the linear
+                                 error stays below it); eta_0 =
+                                 gmres_forcing_max.  Formed on the device
+                                 with the Newton norms.  The converged stage
+                                 is the same to the Newton tolerance;
+                                 hfr_trace_solve always uses gmres_rtol      */
 } hfr_opts;
 /* HFR_CK_SWEEP: register-resident Gauss-Jordan sweep on the vector ALUs, one
  * exchange per step; HFR_CK_BLOCKED: panels of 16 exchanges, the update of

@@ -53,7 +53,7 @@ class HfrOpts(Structure):
                 ("jacobian_lag", c_int32), ("gmres_cgs_passes", c_int32),
                 ("caller_workspace", c_int32), ("condense_kernel", c_int32),
                 ("newton_damping", c_int32),
-                ("iteration_graph", c_int32)]
+                ("iteration_graph", c_int32), ("gmres_forcing_max", c_double)]
 
 
 class HfrSolveStats(Structure):

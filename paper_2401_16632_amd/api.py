@@ -203,10 +203,11 @@ class Solver:
                  max_iters=600, rtol=1e-10, newton_max_iters=25,
                  newton_tol=1e-13, keep_blocks=False, jacobian_lag=0,
                  cgs_passes=1, workspace=None, condense="auto", damping=False,
-                 graph=False):
+                 graph=False, forcing=0.0):
         """workspace: None (the library allocates its working memory) or
         "torch" (a uint8 CUDA tensor allocated here and bound with
-        hfr_solver_bind_workspace; kept as self.workspace)."""
+        hfr_solver_bind_workspace; kept as self.workspace).  forcing:
+        hfr_opts.gmres_forcing_max (0: every solve inside Newton to rtol)."""
         lib = load_library()
         self.mesh = mesh
         o = _abi.HfrOpts()
@@ -229,6 +230,7 @@ class Solver:
         o.condense_kernel = ck[condense]
         o.newton_damping = 1 if damping else 0
         o.iteration_graph = 1 if graph else 0
+        o.gmres_forcing_max = float(forcing)
         self.opts = o
         self.workspace = None
         ws = ctypes.c_size_t()

@@ -15,6 +15,8 @@ struct GmresState {
                              // step saw it (read by the update kernel, whose
                              // workgroup 0 may set done itself)
     double inv_norm, beta, bnorm, target;
+    double nres, eta;        // inexact-Newton forcing: last Newton residual and
+                             // the relative tolerance of the next solve
     double h1[kGmresMaxK], h2[kGmresMaxK];
     double cs[kGmresMaxK], sn[kGmresMaxK];
     // publication counters: the restart kernel and the Newton norms kernel
@@ -34,6 +36,8 @@ struct GmresArgs {
                              // target ends the solve without the FP64 true
                              // residual (the Newton loop checks its residuals)
     double rtol;
+    const double* eta;       // set: the relative tolerance is *eta (the
+                             // forcing term of the Newton iteration), not rtol
     size_t ldv;
     const int* rowptr;
     const int* col;

@@ -269,11 +269,22 @@ hipError_t launch_absmax(int N, const double* x, double* partial, int nblk,
 // next number of the device counter *seq_ctr is written to seq_out (if set)
 // behind a system-scope fence, so a host that sees it sees the rest;
 // partial needs 2048 doubles
+// Inexact-Newton forcing (optional, hist null: none): with the norms the
+// final kernel forms the relative tolerance of the next trace solve,
+// eta = 0.1 max(r_k (r_k / r_{k-1})^2, tol) / r_k clamped to [lo, hi]
+// (the quadratic model of the next residual; eta = hi at the first check of
+// a stage), r_k = max(|h|inf, |g|inf); hist[0] keeps r_k, hist[1] eta.
+struct Forcing {
+    double* hist;
+    double lo, hi;
+    int first;
+};
 hipError_t launch_newton_norms(int Nx, const double* x, int Ny, const double* y,
                                double* partial, double tol, const double* tol_scale,
                                double* out, int* go,
                                const int* gate, const int* flags, int* flags_out,
-                               long long* seq_out, long long* seq_ctr, hipStream_t st);
+                               long long* seq_out, long long* seq_ctr, hipStream_t st,
+                               Forcing fc = Forcing{nullptr, 0.0, 0.0, 0});
 hipError_t launch_trace_gather_g(int ntp, int P, const int* tpside,
                                  const double* gk, double* g,
                                  hipStream_t st);
@@ -284,6 +295,6 @@ hipError_t launch_gather_g_norms(int ntp, const int* tpside, const double* gk, d
                                  const double* tol_scale, double* out, int* go,
                                  const int* gate, const int* flags,
                                  int* flags_out, long long* seq_out, long long* seq_ctr,
-                                 hipStream_t st);
+                                 hipStream_t st, Forcing fc = Forcing{nullptr, 0.0, 0.0, 0});
 
 }  // namespace hfr

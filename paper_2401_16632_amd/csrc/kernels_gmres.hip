@@ -732,7 +732,7 @@ __global__ __launch_bounds__(kThr) void k_gmres_restart(GmresArgs a, int first, 
             const double beta = sqrt(fin[0]);
             if (first) {
                 gs->bnorm = beta;
-                gs->target = a.rtol * beta;
+                gs->target = (a.eta ? *a.eta : a.rtol) * beta;
                 gs->iters = 0;
                 gs->cycles = 0;
             } else {

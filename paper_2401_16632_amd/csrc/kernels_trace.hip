@@ -545,7 +545,7 @@ __global__ void k_absmax2_final(int nbx, int nby, const double* partial, double 
                                 const double* tol_scale,
                                 double* out, int* go, const int* gate,
                                 const int* flags, int* flags_out,
-                                long long* seq_out, long long* seq_ctr) {
+                                long long* seq_out, long long* seq_ctr, Forcing fc) {
     __shared__ double red[2][256];
     double mx = 0.0, my = 0.0;
     for (int i = threadIdx.x; i < nbx; i += blockDim.x) {
@@ -575,6 +575,17 @@ __global__ void k_absmax2_final(int nbx, int nby, const double* partial, double 
         out[2] = tol;
         const bool open = !gate || *gate != 0;
         *go = (open && !(red[0][0] <= tol && red[1][0] <= tol)) ? 1 : 0;
+        if (fc.hist && open) {
+            const double r = fmax(red[0][0], red[1][0]);
+            const double rp = fc.hist[0];
+            double eta = fc.hi;
+            if (!fc.first && r > 0.0 && rp > 0.0 && r < rp) {
+                const double q = r / rp;
+                eta = fmin(fc.hi, fmax(fc.lo, 0.1 * fmax(r * q * q, tol) / r));
+            }
+            fc.hist[0] = r;
+            fc.hist[1] = eta;
+        }
         if (flags_out) {
             flags_out[0] = flags[0];
             flags_out[1] = flags[1];
@@ -592,13 +603,14 @@ hipError_t launch_newton_norms(int Nx, const double* x, int Ny, const double* y,
                                double* partial, double tol, const double* tol_scale,
                                double* out, int* go,
                                const int* gate, const int* flags, int* flags_out,
-                               long long* seq_out, long long* seq_ctr, hipStream_t st) {
+                               long long* seq_out, long long* seq_ctr, hipStream_t st,
+                               Forcing fc) {
     const int nbx = std::min(1024, std::max(1, (Nx + kThreads - 1) / kThreads));
     const int nby = std::min(1024, std::max(1, (Ny + kThreads - 1) / kThreads));
     hipLaunchKernelGGL(k_absmax2_partial, dim3(nbx + nby), dim3(kThreads), 0, st, Nx, x,
                        nbx, Ny, y, partial);
     hipLaunchKernelGGL(k_absmax2_final, dim3(1), dim3(256), 0, st, nbx, nby, partial, tol,
-                       tol_scale, out, go, gate, flags, flags_out, seq_out, seq_ctr);
+                       tol_scale, out, go, gate, flags, flags_out, seq_out, seq_ctr, fc);
     return hipGetLastError();
 }
 
@@ -811,13 +823,13 @@ hipError_t launch_gather_g_norms(int ntp, const int* tpside, const double* gk, d
                                  const double* tol_scale, double* out, int* go,
                                  const int* gate, const int* flags,
                                  int* flags_out, long long* seq_out, long long* seq_ctr,
-                                 hipStream_t st) {
+                                 hipStream_t st, Forcing fc) {
     const int nbx = std::min(1024, std::max(1, (Nx + kThreads - 1) / kThreads));
     const int nby = std::min(1024, std::max(1, (4 * ntp + kThreads - 1) / kThreads));
     hipLaunchKernelGGL(k_gather_g_absmax, dim3(nbx + nby), dim3(kThreads), 0, st, ntp,
                        tpside, gk, g, Nx, x, nbx, partial);
     hipLaunchKernelGGL(k_absmax2_final, dim3(1), dim3(256), 0, st, nbx, nby, partial, tol,
-                       tol_scale, out, go, gate, flags, flags_out, seq_out, seq_ctr);
+                       tol_scale, out, go, gate, flags, flags_out, seq_out, seq_ctr, fc);
     return hipGetLastError();
 }
 

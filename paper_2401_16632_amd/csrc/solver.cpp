@@ -71,6 +71,8 @@ struct hfr_solver_s {
     float* Lt32 = nullptr;
     double* W = nullptr;     // 2 x N Arnoldi work vectors
     GmresState* gs = nullptr;
+    bool forcing = false;    // inside Newton with hfr_opts.gmres_forcing_max > 0:
+                             // each trace solve to the device's forcing term
     double* part = nullptr;
     double* part2 = nullptr;
     double* part3 = nullptr;
@@ -525,6 +527,7 @@ GmresArgs gmres_args(hfr_solver_s* s) {
     a.restart = s->restart;
     a.pc = s->opts.precond;
     a.rtol = s->opts.gmres_rtol;
+    a.eta = s->forcing ? &s->gs->eta : nullptr;
     a.ldv = size_t(s->N);
     a.rowptr = s->rowptr;
     a.col = s->col;
@@ -749,6 +752,12 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
     fr_mesh_s* m = s->mesh;
     hfr_newton_stats loc{};
     const int nu = 4 * m->Nim * m->Np;
+    // trace solves inside this Newton iteration take the forcing term
+    s->forcing = s->opts.gmres_forcing_max > 0.0;
+    struct ForcingOff {
+        hfr_solver_s* s;
+        ~ForcingOff() { s->forcing = false; }
+    } forcing_off{s};
     // the tolerance newton_tol * max(1, |u*|) is formed on the device by the
     // norms kernel and published with the norms (no readback here)
     HIP_TRY(launch_absmax(nu, ustar, s->scratch, std::min(1024, std::max(1, (nu + 255) / 256)),
@@ -767,7 +776,14 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
     // the stream the chain below is queued on (the caller's, or the one an
     // iteration graph is recorded on)
     hipStream_t qs = st;
-    auto queue_checks = [&](const int* gate) -> fr_status {
+    // the forcing term of the next trace solve is formed with the norms
+    // (first: the stage's first check, which starts the residual history)
+    auto forcing = [&](bool first) {
+        return s->forcing ? Forcing{&s->gs->nres, s->opts.gmres_rtol,
+                                    s->opts.gmres_forcing_max, first ? 1 : 0}
+                          : Forcing{nullptr, 0.0, 0.0, 0};
+    };
+    auto queue_checks = [&](const int* gate, bool first = false) -> fr_status {
         // the HFR gather of g also takes the norms' partial maxima
         fr_status e2 = residual_internal(s, u, uhat, ustar, aii_dt, nullptr, qs, gate,
                                          m->efr);
@@ -775,12 +791,13 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         if (m->efr)
             HIP_TRY(launch_newton_norms(nu, s->h, 4 * m->Ntp, s->g, s->scratch, rtol,
                                         s->dscale, s->dpin, s->go, gate, s->flags, flags_pub,
-                                        seq_pub, &s->gs->norm_seq, qs));
+                                        seq_pub, &s->gs->norm_seq, qs, forcing(first)));
         else
             HIP_TRY(launch_gather_g_norms(m->Ntp, m->d_tpside, s->gk, s->g, nu, s->h,
                                           s->scratch, rtol, s->dscale, s->dpin, s->go, gate,
                                           s->flags,
-                                          flags_pub, seq_pub, &s->gs->norm_seq, qs));
+                                          flags_pub, seq_pub, &s->gs->norm_seq, qs,
+                                          forcing(first)));
         ++s->seq_norms;
         if (spec && !fused_fill(s) &&
             (e2 = condense_fill(s, u, uhat, aii_dt, s->go, qs, true)))
@@ -857,7 +874,7 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
     int halvings = 0;
     bool queued = false;
     for (int it = 0;; ++it) {
-        if (!queued && (e = queue_checks(nullptr))) return e;
+        if (!queued && (e = queue_checks(nullptr, it == 0))) return e;
         queued = false;
         if ((e = wait_seq(s, s->hpin + kPinNormSeq, s->seq_norms, st))) return e;
         const double hmax = s->hpin[0], gmax = s->hpin[1];
@@ -965,7 +982,10 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
         (o->caller_workspace != 0 && o->caller_workspace != 1) ||
         o->condense_kernel < HFR_CK_AUTO || o->condense_kernel > HFR_CK_BLOCKED_W8 ||
         (o->newton_damping != 0 && o->newton_damping != 1) ||
-        (o->iteration_graph != 0 && o->iteration_graph != 1))
+        (o->iteration_graph != 0 && o->iteration_graph != 1) ||
+        !(o->gmres_forcing_max >= 0.0) ||
+        (o->gmres_forcing_max > 0.0 &&
+         !(o->gmres_forcing_max >= o->gmres_rtol && o->gmres_forcing_max < 1.0)))
         return fail(FR_E_INVALID, "bad tolerance or iteration cap");
     auto s = new hfr_solver_s();
     s->mesh = mesh;

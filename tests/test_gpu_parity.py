@@ -295,7 +295,8 @@ def test_imex_steps_fp64_cylinder_two_passes():
 def test_solver_rejects_bad_options():
     pr, _ = _build("c1_p1")
     for kw in (dict(cgs_passes=3), dict(cgs_passes=-1), dict(jacobian_lag=-1),
-               dict(restart=0)):
+               dict(restart=0), dict(forcing=-1e-3), dict(forcing=1.0),
+               dict(rtol=1e-6, forcing=1e-7)):
         with pytest.raises(hp.HfrError):
             hp.Solver(pr.hm, **kw)
 
@@ -386,6 +387,39 @@ def test_imex_steps_fp32_condensation_high_order(name, pc):
         ud = un.clone()
         err = rel_err(unsoa(host(ud), hm.Ne, pr.P), _ORACLE_STEPS[name][k])
         assert err <= 1e-8, (k, err, stats)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-8)])
+def test_imex_steps_with_forcing(precision, tol):
+    """Inexact Newton (hfr_opts.gmres_forcing_max): the trace solves of a
+    stage stop at the device's forcing term instead of the fixed tolerance.
+    Two IMEX steps of the 24x8 p = 4 cylinder at the local-CFL time step
+    match the oracle as without it, with fewer Krylov iterations."""
+    pr, u = _build("cyl_p4")
+    dt = _cfl_dt(pr)
+    hm = pr.hm
+    if "cyl_p4" not in _ORACLE_STEPS:
+        uo, seq = u.copy(), []
+        for _ in range(2):
+            uo, _ = oimex.imex_step(pr.om, pr.ph, oimex.himex2c(), uo, dt, tol=1e-13)
+            seq.append(uo)
+        _ORACLE_STEPS["cyl_p4"] = seq
+    its = {}
+    for forcing in (0.0, 1e-3):
+        print("forcing case:", precision, forcing, flush=True)
+        s = hp.Solver(hm, precision=precision, precond=precision, rtol=1e-10,
+                      newton_tol=1e-13, max_iters=3000, forcing=forcing)
+        stp = hp.ImexStepper(hm, s, "HIMEX2C")
+        ud = dev(soa(u))
+        its[forcing] = 0
+        for k in range(2):
+            un, stats = stp.step(ud, dt)
+            ud = un.clone()
+            its[forcing] += sum(st["gmres_iters"] for st in stats)
+            err = rel_err(unsoa(host(ud), hm.Ne, pr.P), _ORACLE_STEPS["cyl_p4"][k])
+            assert err <= tol, (forcing, k, err, stats)
+        s.close()
+    assert its[1e-3] < its[0.0], its
 
 
 _ORACLE_STEPS_B = {}

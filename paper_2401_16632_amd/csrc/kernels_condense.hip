@@ -815,7 +815,9 @@ struct BlockShape {
     static constexpr int WPE = TREGS + 48 + 8 * RPL * words <= 168 ? 3 : 2;
     // LDS of the elimination (-G slots, U per wave, the panel), reused by
     // the Schur lift of the epilogue (flux Jacobians, A^-1 r, X)
-    static constexpr int NF = 4 * P, LDX = n + 1;
+    // X in the lift: column-major with a row stride of n + 4 (16-byte
+    // aligned rows of four unknowns of a point)
+    static constexpr int NF = 4 * P, LDX = n + 4;
     static constexpr size_t ELIM_BYTES =
         sizeof(T) * (size_t(NB) * NPAD * LDG + size_t(W) * 16 * LDG + size_t(NPAD) * LDP);
     static constexpr size_t LIFT_BYTES =
@@ -1271,36 +1273,56 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
         }
     }
     __syncthreads();
-    // one (face point, column) pair per thread and pass: the four rows of
-    // the face point in that column (16-byte store)
-    for (int idx = threadIdx.x; idx < NF * (m + 1); idx += blockDim.x) {
-        const int fq = idx % NF, b = idx / NF;    // b == m: the z column
+    // each thread one face point fq and the columns b = b0, b0 + GF, ... (b
+    // == m: the z column): the face point's flux Jacobian, line points and
+    // interpolation weights stay in registers, the four rows of a line point
+    // in a column come in one 16-byte (FP32) read, and the four rows of the
+    // face point go out in one store
+    constexpr int GF = 64 * W / NF;                  // threads per face point
+    if (threadIdx.x < GF * NF) {
+        const int fq = threadIdx.x % NF, b0 = threadIdx.x / NF;
         const int f = fq / P, q = fq - f * P;
+        const bool tr = trf[f] != 0;
+        const double wq = og.w[q];
+        int pt[P];
+        double cl[P];
+#pragma unroll
+        for (int l = 0; l < P; ++l) {
+            if (f == 0) { pt[l] = l * P + q; cl[l] = og.lm[l]; }
+            else if (f == 1) { pt[l] = q * P + l; cl[l] = og.lp[l]; }
+            else if (f == 2) { pt[l] = l * P + (P - 1 - q); cl[l] = og.lp[l]; }
+            else { pt[l] = (P - 1 - q) * P + l; cl[l] = og.lm[l]; }
+        }
+        double fr[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) fr[e] = fu[fq * 16 + e];
+    for (int b = b0; b <= m; b += GF) {
         double out[4];
-        if (!trf[f]) {
+        if (!tr) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) out[v] = (b == fq * 4 + v) ? 1.0 : 0.0;
         } else {
             double sw[4] = {0.0, 0.0, 0.0, 0.0};
+            if (b < m) {
 #pragma unroll
-            for (int l = 0; l < P; ++l) {
-                int pt;
-                double c;
-                if (f == 0) { pt = l * P + q; c = og.lm[l]; }
-                else if (f == 1) { pt = q * P + l; c = og.lp[l]; }
-                else if (f == 2) { pt = l * P + (P - 1 - q); c = og.lp[l]; }
-                else { pt = (P - 1 - q) * P + l; c = og.lm[l]; }
+                for (int l = 0; l < P; ++l) {
+                    T xv[4];
+                    M::load4(xs + b * LDX + pt[l] * 4, xv);
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    sw[v] += c * (b < m ? double(xs[b * LDX + pt * 4 + v]) : ys[pt * 4 + v]);
+                    for (int v = 0; v < 4; ++v) sw[v] += cl[l] * double(xv[v]);
+                }
+            } else {
+#pragma unroll
+                for (int l = 0; l < P; ++l)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) sw[v] += cl[l] * ys[pt[l] * 4 + v];
             }
-            const double wq = og.w[q];
             const bool diag = (b >> 2) == fq;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 double acc2 = diag ? fh[fq * 16 + v * 4 + (b & 3)] : 0.0;
 #pragma unroll
-                for (int w2 = 0; w2 < 4; ++w2) acc2 += fu[fq * 16 + v * 4 + w2] * sw[w2];
+                for (int w2 = 0; w2 < 4; ++w2) acc2 += fr[v * 4 + w2] * sw[w2];
                 out[v] = wq * acc2;
             }
         }
@@ -1316,8 +1338,9 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
         } else {
             double* zz = a.z + size_t(k) * m + fq * 4;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) zz[v] = trf[f] ? out[v] : 0.0;
+            for (int v = 0; v < 4; ++v) zz[v] = tr ? out[v] : 0.0;
         }
+    }
     }
 }
 

@@ -945,6 +945,69 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
         // block column and component of the global column (A or B)
         const int bc = ci < n ? ci >> 2 : NP + ((ci - NPAD) >> 2);
         const int cc = (ci < n ? ci : ci - NPAD) & 3;
+        if constexpr (sizeof(T) == 4) {
+        if (c < RT) {                                  // uniform: columns of A
+            // the lane's column point (l, kk) couples to the row points of
+            // its row line (j == kk) and column line (i == l) only, so the
+            // operand blocks of both (column cc) are the same for every row
+            // tile: the terms of block_column with them loaded once
+            const bool real = ci < n;
+            const int bq = real ? bc : 0;
+            const int l = bq % P, kk = bq / P;
+            double af[4], ag[4], fr1[4], fl1[4], fb2[4], ft2[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int z = v * 4 + cc;
+                af[v] = sh.Af[bq][z];
+                ag[v] = sh.Ag[bq][z];
+                fr1[v] = sh.Fu[1 * P + kk][z];
+                fl1[v] = sh.Fu[3 * P + (P - 1 - kk)][z];
+                fb2[v] = sh.Fu[0 * P + l][z];
+                ft2[v] = sh.Fu[2 * P + (P - 1 - l)][z];
+            }
+            const double lpl = os.lp[l], lml = os.lm[l], lpk = os.lp[kk], lmk = os.lm[kk];
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                // rows 4g + r: the four variables of point br = 4t + g
+                const int br = 4 * t + g;
+                double col[4] = {0.0, 0.0, 0.0, 0.0};
+                if (real && br < NP) {
+                    const int pi = br % P, pj = br / P;
+                    const bool rl = kk == pj, cl = l == pi;
+                    if (rl || cl) {
+                        const double cij = sh.c[br];
+                        double a1 = 0, b1 = 0, c1 = 0, a2 = 0, b2 = 0, c2 = 0;
+                        if (rl) {
+                            b1 = os.cr[pi] * lpl;
+                            c1 = os.cl[pi] * lml;
+                            a1 = os.D[pi * P + l] - b1 + c1;
+                        }
+                        if (cl) {
+                            b2 = os.cl[pj] * lmk;
+                            c2 = os.cr[pj] * lpk;
+                            a2 = os.D[pj * P + kk] + b2 - c2;
+                        }
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            double s2 = 0.0;
+                            if (rl) s2 += a1 * af[v] + b1 * fr1[v] + c1 * fl1[v];
+                            if (cl) s2 += a2 * ag[v] + b2 * fb2[v] + c2 * ft2[v];
+                            col[v] = cij * s2;
+                        }
+                    }
+                    if (bc == br) col[cc] += 1.0;
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * t + M::row(g, r);
+                    T v = T(col[r]);
+                    if (row >= n && dcol && row == ci) v = T(1);
+                    acc[q][t][r] = v;
+                }
+            }
+            continue;
+        }
+        }
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
             if constexpr (sizeof(T) == 4) {

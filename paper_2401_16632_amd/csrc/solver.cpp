@@ -84,6 +84,11 @@ struct hfr_solver_s {
     double* zz = nullptr;    // [Nim][m]  C A^-1 r (FP64)
     bool have_factors = false;
     int last_gmres_iters = 4;
+    // Krylov iterations of the k-th trace solve of the last Newton solve
+    // (k < 8; 0 unknown): the first chunk of the k-th solve of the next one
+    // is sized from it (with a forcing term the counts rise within a stage)
+    int newton_solve_iters[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int chunk_hint = 0;      // > 0: the first chunk of the next solve
     bool verbose = false;
     int stage_calls = 0;
     double* V = nullptr;     // (restart+1) x N
@@ -599,7 +604,8 @@ fr_status gmres(hfr_solver_s* s, double* x, hfr_solve_stats* stats,
         ++s->seq_gmres;
     }
     int launched = 0;
-    int chunk = std::max(2, std::min(R, s->last_gmres_iters + 1));
+    int chunk = std::max(2, std::min(R, s->chunk_hint > 0 ? s->chunk_hint
+                                                          : s->last_gmres_iters + 1));
     int cycles_seen = 0;
     int j = 0;
     fr_status e;
@@ -756,7 +762,10 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
     s->forcing = s->opts.gmres_forcing_max > 0.0;
     struct ForcingOff {
         hfr_solver_s* s;
-        ~ForcingOff() { s->forcing = false; }
+        ~ForcingOff() {
+            s->forcing = false;
+            s->chunk_hint = 0;
+        }
     } forcing_off{s};
     // the tolerance newton_tol * max(1, |u*|) is formed on the device by the
     // norms kernel and published with the norms (no readback here)
@@ -906,6 +915,11 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
             if (stats) *stats = loc;
             return fail(FR_E_NOT_CONVERGED, "Newton did not converge");
         }
+        {
+            const int prev = it < 8 ? s->newton_solve_iters[it] : 0;
+            s->chunk_hint = std::max(2, std::min(s->restart,
+                                                 (prev > 0 ? prev : s->last_gmres_iters) + 1));
+        }
         const bool relin = lag <= 0 || !s->have_factors ||
                            (it == 0 && (s->stage_calls % lag) == 0);
         int pre = -1;
@@ -915,7 +929,7 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
             if (spec && s->ck < 0 && s->opts.condense_kernel == HFR_CK_AUTO &&
                 (e = tune_condense(s, u, uhat, aii_dt, st)))
                 return e;
-            const int K = std::max(2, std::min(s->restart, s->last_gmres_iters + 1));
+            const int K = std::max(2, std::min(s->restart, s->chunk_hint));
             if (spec && s->opts.iteration_graph && !s->timing && s->N > 0 &&
                 K < s->opts.gmres_max_iters) {
                 if ((e = replay_iteration(K))) return e;
@@ -934,6 +948,8 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         // inside Newton a cycle whose residual estimate is on target ends the
         // solve (the FP64 residuals of the next iterate are checked anyway)
         e = gmres(s, s->duhat, &ks, st, after_solve, &chained, false, pre);
+        s->chunk_hint = 0;
+        if (it < 8) s->newton_solve_iters[it] = ks.iterations;
         tend(s, tk, st);
         if (s->verbose)
             fprintf(stderr, "[hfr]   gmres its %d restarts %d relres %.3e status %d\n",

@@ -1102,6 +1102,30 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
         int pvv = 0;                                   // lane cc: pivot row of exchange cc
         bool fail = false;
         T ipv = T(0);                                  // lane cc: 1 / pivot of exchange cc
+        // The padding columns of the last panel (n .. NPAD-1) are identity
+        // columns whose only nonzero is their own padding row, decoupled from
+        // the element's rows and columns: the exchange of each pivots on that
+        // row with factor 1 and changes nothing else, so its outcome is
+        // written here and the loop below skips it.
+        constexpr int NR = n - 16 * (RT - 1);          // real columns, last panel
+        const bool pad = NR < 16 && j == RT - 1;       // uniform
+        if (pad) {
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) {
+                const int row = lane + 64 * s;
+                if (row >= n && row < NPAD) {
+                    usd[s] = true;
+                    pos[s] = row - 16 * j + 1;
+                }
+#pragma unroll
+                for (int cc = NR; cc < 16; ++cc)
+                    if (row == 16 * j + cc) x[s][cc] = T(-1);
+            }
+            if (lane >= NR && lane < 16) {
+                pvv = 16 * j + lane;
+                ipv = T(1);
+            }
+        }
         // pivot search of one column: some row is always unused, so the
         // maximum names one; a zero pivot is flagged and its exchange
         // leaves the tableau as it is (the result is discarded)
@@ -1117,6 +1141,7 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
         unsigned key = column_key(0);
 #pragma unroll
         for (int cc = 0; cc < 16; ++cc) {
+            if (cc >= NR && pad) continue;             // uniform: written above
             const int p = 255 - int(key & 0xffu);
             const bool bad = key < 0x200u;
             fail = fail || bad;

@@ -1007,6 +1007,35 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
             }
             continue;
         }
+        if (c < NCT) {                                 // uniform: columns of B
+            // the lane's trace column (face f2, point q2): a row point couples
+            // to it only on the grid line through q2 normal to face f2, with
+            // the lifting weight of its side; face flux Jacobian column cc
+            // loaded once, the rest branch-free as above
+            const int tb = bc - NP, f2 = tb / P, q2 = tb - f2 * P;
+            const bool tr = sh.tr[f2] != 0;
+            double fh[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) fh[v] = sh.Fh[tb][v * 4 + cc];
+            const bool right = f2 == 1 || f2 == 2;       // cr (else cl)
+            const bool by_i = f2 == 1 || f2 == 3;        // weight of point i (else j)
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                const int br = 4 * t + g;
+                const bool rowok = br < NP;
+                const int brc = rowok ? br : 0;
+                const int pi = brc % P, pj = brc / P;
+                const bool on = tr && rowok &&
+                                ((f2 == 1 && q2 == pj) || (f2 == 3 && q2 == P - 1 - pj) ||
+                                 (f2 == 0 && q2 == pi) || (f2 == 2 && q2 == P - 1 - pi));
+                const int wi = by_i ? pi : pj;
+                const double cw = right ? os.cr[wi] : os.cl[wi];
+                const double f = on ? sh.c[brc] * cw : 0.0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[q][t][r] = T(f * fh[r]);
+            }
+            continue;
+        }
         }
 #pragma unroll
         for (int t = 0; t < RT; ++t) {

@@ -217,11 +217,15 @@ fr_status fr_modal_filter(fr_mesh_t mesh, const fr_filter_params* prm,
 /* Implicit (hybridized) stage                                             */
 /* ----------------------------------------------------------------------- */
 
-enum { HFR_PREC_FP64 = 0,   /* element tableaux swept in FP64              */
+enum { HFR_PREC_FP64 = 0,   /* element tableaux eliminated in FP64         */
        HFR_PREC_FP32 = 1 }; /* element tableaux (A^-1 B, Schur complement)
-                               formed and stored in FP32 by the vector-ALU
-                               Gauss-Jordan sweep; the condensed right-hand
-                               side is accumulated in FP64                 */
+                               formed and stored in FP32, by the kernel
+                               hfr_opts.condense_kernel selects: the
+                               vector-ALU Gauss-Jordan sweep, or panels of
+                               16 exchanges whose updates of the rest of the
+                               tableau run on FP32 matrix-core tiles; the
+                               condensed right-hand side is accumulated in
+                               FP64                                        */
 enum { HFR_PC_FP64 = 0, HFR_PC_FP32 = 1, HFR_PC_BF16 = 2 };
 
 typedef struct {

@@ -316,6 +316,12 @@ typedef struct {
                                  Newton iteration, R_i                      */
     int32_t graph_replays;    /* Newton iterations run as a replayed graph
                                  (hfr_opts.iteration_graph)                 */
+    int32_t queued_linearisations; /* Newton iterations whose condensation
+                                 was queued behind the previous iterate's
+                                 checks, before the host read them (blocked
+                                 elimination kernel, no timers, graphs or
+                                 damping; the device skips such a launch
+                                 when the checks pass)                      */
 } hfr_newton_stats;
 
 /*

@@ -64,7 +64,7 @@ class HfrSolveStats(Structure):
 class HfrNewtonStats(Structure):
     _fields_ = [("newton_iters", c_int32), ("gmres_iters", c_int32),
                 ("residual", c_double), ("implicit_ms", c_double),
-                ("graph_replays", c_int32)]
+                ("graph_replays", c_int32), ("queued_linearisations", c_int32)]
 
 
 class ImexTableau(Structure):

@@ -413,7 +413,8 @@ class ImexStepper:
                                   gmres_iters=ns.gmres_iters,
                                   residual=ns.residual,
                                   implicit_ms=ns.implicit_ms,
-                                  graph_replays=ns.graph_replays))
+                                  graph_replays=ns.graph_replays,
+                                  queued_linearisations=ns.queued_linearisations))
         if filter is not None:
             m.modal_filter(self.u, stream=stream, **filter)
         self.stats = stats

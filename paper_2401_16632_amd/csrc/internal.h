@@ -263,7 +263,7 @@ hipError_t launch_absmax(int N, const double* x, double* partial, int nblk,
                          double* out, hipStream_t st);
 // Newton test: out[0] = max |x|, out[1] = max |y| (out may be host memory
 // mapped for the device), *go = 1 when the gate (if any) is open and either
-// exceeds the tolerance (NaN included), else 0; the tolerance is tol, or
+// exceeds the tolerance, both being finite, else 0; the tolerance is tol, or
 // tol * max(1, *tol_scale) with tol_scale (device memory) set, and is
 // written to out[2]; flags[0..1] copied to flags_out (if set); then the
 // next number of the device counter *seq_ctr is written to seq_out (if set)

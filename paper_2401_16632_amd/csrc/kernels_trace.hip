@@ -538,8 +538,8 @@ __global__ void k_absmax2_partial(int Nx, const double* x, int nbx, int Ny,
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// both maxima -> out[0], out[1] (host-visible), *go = 0 iff both <= tol or
-// the gate is closed; the two failure flags are copied to flags_out.  With
+// both maxima -> out[0], out[1] (host-visible), *go = 0 iff both <= tol,
+// either is not finite or the gate is closed; the two failure flags are copied to flags_out.  With
 // tol_scale set the test uses tol * max(1, *tol_scale), written to out[2].
 __global__ void k_absmax2_final(int nbx, int nby, const double* partial, double tol,
                                 const double* tol_scale,
@@ -574,7 +574,10 @@ __global__ void k_absmax2_final(int nbx, int nby, const double* partial, double 
         out[1] = red[1][0];
         out[2] = tol;
         const bool open = !gate || *gate != 0;
-        *go = (open && !(red[0][0] <= tol && red[1][0] <= tol)) ? 1 : 0;
+        // a non-finite residual closes the gate too: the host stops (or
+        // damps the step) and no linearisation queued behind may run on it
+        const bool fin = isfinite(red[0][0]) && isfinite(red[1][0]);
+        *go = (open && fin && !(red[0][0] <= tol && red[1][0] <= tol)) ? 1 : 0;
         if (fc.hist && open) {
             const double r = fmax(red[0][0], red[1][0]);
             const double rp = fc.hist[0];

@@ -89,6 +89,11 @@ struct hfr_solver_s {
     // is sized from it (with a forcing term the counts rise within a stage)
     int newton_solve_iters[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int chunk_hint = 0;      // > 0: the first chunk of the next solve
+    // linearisations of the last Newton solve; while an iteration index is
+    // below it the fused condensation of that iteration is queued with the
+    // checks, gated on the device by their outcome (spec_condensed)
+    int newton_prev_iters = 0;
+    bool spec_condensed = false;
     bool verbose = false;
     int stage_calls = 0;
     double* V = nullptr;     // (restart+1) x N
@@ -412,23 +417,28 @@ fr_status condense_fill(hfr_solver_s* s, const double* u, const double* uhat,
 
 // Sweep, assembly and preconditioner; fill_done: the fill of (u, uhat) has
 // already been queued.
+// condensed: the fused condensation of (u, uhat) is already queued (gated
+// on the device); only the assembly and the preconditioner follow.
 fr_status condense_internal(hfr_solver_s* s, const double* u,
                             const double* uhat, double aii_dt,
                             hipStream_t st, bool fill_done = false,
-                            bool schur_only = false) {
+                            bool schur_only = false, bool condensed = false) {
     fr_mesh_s* m = s->mesh;
     if (m->Nim == 0) return FR_OK;
-    if (!fill_done && !(schur_only && fused_fill(s))) {
-        fr_status e = condense_fill(s, u, uhat, aii_dt, nullptr, st, schur_only);
-        if (e) return e;
+    if (!condensed) {
+        if (!fill_done && !(schur_only && fused_fill(s))) {
+            fr_status e = condense_fill(s, u, uhat, aii_dt, nullptr, st, schur_only);
+            if (e) return e;
+        }
+        CondenseLaunch c = condense_launch(s, u, uhat, aii_dt);
+        const int tc = tbegin(s, HFR_T_CONDENSE, st);
+        c.yr = s->yr;                   // the sweep also forms the FP64 right-hand side
+        c.z = s->zz;
+        c.schur_only = schur_only ? 1 : 0;
+        HIP_TRY(launch_condense(m->ops, c, st));
+        tend(s, tc, st);
     }
-    CondenseLaunch c = condense_launch(s, u, uhat, aii_dt);
-    int tk = tbegin(s, HFR_T_CONDENSE, st);
-    c.yr = s->yr;                       // the sweep also forms the FP64 right-hand side
-    c.z = s->zz;
-    c.schur_only = schur_only ? 1 : 0;
-    HIP_TRY(launch_condense(m->ops, c, st));
-    tend(s, tk, st);
+    int tk = -1;
     if (s->nbr == 0) return FR_OK;
     if (m->efr) {
         tk = tbegin(s, HFR_T_ASSEMBLE, st);
@@ -765,6 +775,7 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         ~ForcingOff() {
             s->forcing = false;
             s->chunk_hint = 0;
+            s->spec_condensed = false;
         }
     } forcing_off{s};
     // the tolerance newton_tol * max(1, |u*|) is formed on the device by the
@@ -792,6 +803,20 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
                                     s->opts.gmres_forcing_max, first ? 1 : 0}
                           : Forcing{nullptr, 0.0, 0.0, 0};
     };
+    // index of the Newton iteration the checks queued next would precede
+    int it_next = 0;
+    // the condensation of the next iteration (the blocked kernel; its fill is
+    // queued above where it is not fused) queued right behind the checks
+    // (the device skips it when they pass or fail), so the host's
+    // reading of the norms does not leave the device idle: only while the
+    // last Newton solve suggests another iteration, and never with timers
+    // (they would time the skipped launches), recorded graphs or damping
+    auto speculate = [&]() {
+        const int ck = s->ck > 0 ? s->ck : s->opts.condense_kernel;
+        return spec && (ck == HFR_CK_BLOCKED || ck == HFR_CK_BLOCKED_W8) && !s->blocks_copy &&
+               !s->timing && !s->opts.iteration_graph && !s->opts.newton_damping &&
+               s->nbr > 0 && it_next < s->newton_prev_iters;
+    };
     auto queue_checks = [&](const int* gate, bool first = false) -> fr_status {
         // the HFR gather of g also takes the norms' partial maxima
         fr_status e2 = residual_internal(s, u, uhat, ustar, aii_dt, nullptr, qs, gate,
@@ -811,6 +836,15 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         if (spec && !fused_fill(s) &&
             (e2 = condense_fill(s, u, uhat, aii_dt, s->go, qs, true)))
             return e2;
+        if (speculate()) {
+            CondenseLaunch c = condense_launch(s, u, uhat, aii_dt);
+            c.yr = s->yr;
+            c.z = s->zz;
+            c.schur_only = 1;
+            c.go = s->go;
+            HIP_TRY(launch_condense(m->ops, c, qs));
+            s->spec_condensed = true;
+        }
         return FR_OK;
     };
     // After each GMRES chunk the update of the Newton iterate and the next
@@ -823,7 +857,7 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
                                       s->piv, s->yr, m->d_trace_map, s->duhat, s->du,
                                       m->Ne, m->d_imp, u, 4 * m->Ntp, uhat, qs, gate));
         tend(s, tk, qs);
-        return queue_checks(gate);
+        return queue_checks(gate);          // it_next: the iteration after this solve's
     };
     // Graph form (hfr_opts.iteration_graph): the linearisation's elimination,
     // assembly and preconditioner, the start and first chunk of the trace
@@ -883,6 +917,7 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
     int halvings = 0;
     bool queued = false;
     for (int it = 0;; ++it) {
+        it_next = it;
         if (!queued && (e = queue_checks(nullptr, it == 0))) return e;
         queued = false;
         if ((e = wait_seq(s, s->hpin + kPinNormSeq, s->seq_norms, st))) return e;
@@ -910,7 +945,10 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         }
         theta = 1.0;
         halvings = 0;
-        if (res <= tol) break;
+        if (res <= tol) {
+            s->newton_prev_iters = it;
+            break;
+        }
         if (it >= s->opts.newton_max_iters) {
             if (stats) *stats = loc;
             return fail(FR_E_NOT_CONVERGED, "Newton did not converge");
@@ -936,7 +974,11 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
                 pre = K;
             } else {
                 // factors that are never reused need only the Schur part
-                if ((e = condense_internal(s, u, uhat, aii_dt, st, spec, lag <= 0))) return e;
+                const bool queued_c = s->spec_condensed;
+                s->spec_condensed = false;
+                if (queued_c) ++loc.queued_linearisations;
+                if ((e = condense_internal(s, u, uhat, aii_dt, st, spec, lag <= 0, queued_c)))
+                    return e;
             }
             s->have_factors = lag > 0;
         } else {
@@ -947,6 +989,7 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         int tk = tbegin(s, HFR_T_TRACE_SOLVE, st);
         // inside Newton a cycle whose residual estimate is on target ends the
         // solve (the FP64 residuals of the next iterate are checked anyway)
+        it_next = it + 1;
         e = gmres(s, s->duhat, &ks, st, after_solve, &chained, false, pre);
         s->chunk_hint = 0;
         if (it < 8) s->newton_solve_iters[it] = ks.iterations;

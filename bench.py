@@ -161,7 +161,7 @@ def run_form(hp, torch, mesh, u0, dt, precision, precond, steps, warmup,
     torch.cuda.synchronize()
     # timed region: no event timers (with them the solver queues no
     # linearisation ahead of its Newton test, and each adds event records)
-    impl_ms, newton, gmres, replays = [], [], [], 0
+    impl_ms, newton, gmres, queued, replays = [], [], [], [], 0
     t0 = time.perf_counter()
     for _ in range(steps):
         un, stats = stp.step(u, dt)
@@ -170,6 +170,7 @@ def run_form(hp, torch, mesh, u0, dt, precision, precond, steps, warmup,
             impl_ms.append(s["implicit_ms"])
             newton.append(s["newton_iters"])
             gmres.append(s["gmres_iters"])
+            queued.append(s["queued_linearisations"])
             replays += s["graph_replays"]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -194,7 +195,7 @@ def run_form(hp, torch, mesh, u0, dt, precision, precond, steps, warmup,
     # phase breakdown from a separate, fully instrumented pass
     phases = timed_pass(None)
     choice, cand = solver.condense_choice()
-    res = dict(wall_s=wall, impl_ms=impl_ms, newton=newton, gmres=gmres,
+    res = dict(wall_s=wall, impl_ms=impl_ms, newton=newton, gmres=gmres, queued=queued,
                graph_replays=replays,
                timers=timers, phases=phases, hbm=hbm, state=out,
                workspace=solver.workspace_bytes,
@@ -486,6 +487,7 @@ def form_summary(mesh, rr, precision):
         "implicit_ms_per_stage": float(np.mean(rr["impl_ms"])),
         "newton_iters_per_stage": float(np.mean(rr["newton"])),
         "gmres_iters_per_stage": float(np.mean(rr["gmres"])),
+        "queued_linearisations_per_stage": float(np.mean(rr["queued"])),
         "hbm_kernels": hbm_kernels(mesh, rr, precision),
         "phase_ms_instrumented_pass": {k: v[0] for k, v in rr["phases"].items()},
         "phase_launches_instrumented_pass": {k: v[1] for k, v in rr["phases"].items()},

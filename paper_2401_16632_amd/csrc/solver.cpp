@@ -815,7 +815,8 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         const int ck = s->ck > 0 ? s->ck : s->opts.condense_kernel;
         return spec && (ck == HFR_CK_BLOCKED || ck == HFR_CK_BLOCKED_W8) && !s->blocks_copy &&
                !s->timing && !s->opts.iteration_graph && !s->opts.newton_damping &&
-               s->nbr > 0 && it_next < s->newton_prev_iters;
+               s->nbr > 0 && it_next < s->newton_prev_iters &&
+               it_next < s->opts.newton_max_iters;   // never one the cap would leave unused
     };
     auto queue_checks = [&](const int* gate, bool first = false) -> fr_status {
         // the HFR gather of g also takes the norms' partial maxima

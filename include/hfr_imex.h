@@ -451,7 +451,12 @@ fr_status hfr_get_blocks(hfr_solver_t s, double* blocks, void* stream);
  * After hfr_assemble_condense all four blocks are stored.  The Newton
  * solver with jacobian_lag = 0 never reuses the factors and stores only the
  * columns n+b (A^-1 B and the Schur complement): the first n columns then
- * hold no meaningful values. */
+ * hold no meaningful values.  With the blocked elimination and face blocks
+ * of 20 or 24 rows (p = 4, 5; not with FR_MESH_EFR) it stores the Schur
+ * complement instead at the start of the slot as 4 x 4 contiguous face
+ * sub-blocks (sub-block (lr, lc) column-major at (4 lc + lr) bs^2, bs =
+ * 4(p+1)), and then only A^-1 B at rows 0..n-1 of the columns n+b is
+ * meaningful. */
 fr_status hfr_get_factors(hfr_solver_t s, void* factors, int32_t* piv,
                           void* stream);
 /* Block-Jacobi preconditioner of the last linearisation (the trace solve of

@@ -152,7 +152,17 @@ struct CondenseLaunch {
     int blocked;             // schur_only: panels of 16 on the matrix cores
                              // (k_condense_blocked) instead of the sweep;
                              // 1: default waves per element, 2: eight
+    int compact_schur;       // blocked: the Schur complement L^k stored as
+                             // 4 x 4 contiguous face sub-blocks at the start
+                             // of the element's slot (schur_offset), where
+                             // the Schur-only path keeps nothing else
 };
+// compact Schur complement of an element (bs = 4P rows per face): entry
+// (row a, column b) of face sub-block (lr, lc), a and b in the element's
+// own point order, at this offset in the element's slot
+__host__ __device__ __forceinline__ size_t schur_offset(int bs, int lr, int lc, int a, int b) {
+    return (size_t(lc * 4 + lr) * bs + b) * bs + a;
+}
 // element linearisation and the tableau [A B; C D] (must precede
 // launch_condense, which sweeps the tableau in place)
 hipError_t launch_tableau_fill(const RefOps& ops, const CondenseLaunch& a,
@@ -180,6 +190,7 @@ struct AssembleLaunch {
     double* t;               // [Ntf*bs]  t = -g - sum_sides z
     const double* g;         // [Ntf*bs]  assembled transmission residual
     const double* z;         // [Nim][m]  C A^-1 r per element
+    int compact_schur;       // element Schur blocks at schur_offset
 };
 hipError_t launch_assemble(const AssembleLaunch& a, hipStream_t st);
 // the diagonal blocks of L read by the block-Jacobi inverse straight from
@@ -189,6 +200,7 @@ struct DiagGather {
     const int* blk_contrib;
     const void* M;           // FP64 tableaux when L64 is given, else FP32
     int n, m;
+    int compact_schur;       // element Schur blocks at schur_offset
 };
 
 hipError_t launch_spmv(int ntf, int bs, const int* rowptr, const int* col,

@@ -741,7 +741,9 @@ __global__ __launch_bounds__(256) void k_schur_lift(CondenseLaunch a, RefOps og)
             }
         }
         if (b < m) {
-            T* dst = G + size_t(n + b) * N + n + fq * 4;
+            T* dst = a.compact_schur
+                         ? G + schur_offset(4 * P, f, b / (4 * P), 4 * q, b % (4 * P))
+                         : G + size_t(n + b) * N + n + fq * 4;
             if constexpr (sizeof(T) == 4) {
                 *reinterpret_cast<float4*>(dst) = make_float4(float(out[0]), float(out[1]),
                                                               float(out[2]), float(out[3]));
@@ -1447,7 +1449,9 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
             }
         }
         if (b < m) {
-            T* dst = G + size_t(n + b) * N + n + fq * 4;
+            T* dst = a.compact_schur
+                         ? G + schur_offset(4 * P, f, b / (4 * P), 4 * q, b % (4 * P))
+                         : G + size_t(n + b) * N + n + fq * 4;
             if constexpr (sizeof(T) == 4) {
                 *reinterpret_cast<float4*>(dst) = make_float4(float(out[0]), float(out[1]),
                                                               float(out[2]), float(out[3]));

@@ -999,10 +999,15 @@ __global__ __launch_bounds__(256) void k_assemble_precondition(AssembleLaunch a,
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 if (imp[c] < 0) continue;
-                const size_t row = size_t(a.n) + (lr[c] * P + (sr[c] ? P - 1 - qa : qa)) * 4;
-                const size_t cl = size_t(a.n) + (lc[c] * P + (sc[c] ? P - 1 - qb : qb)) * 4 + wb;
+                const int ra = (sr[c] ? P - 1 - qa : qa) * 4;            // rows in face lr
+                const int cb = (sc[c] ? P - 1 - qb : qb) * 4 + wb;       // column in face lc
+                const size_t row = size_t(a.n) + lr[c] * 4 * P + ra;
+                const size_t cl = size_t(a.n) + lc[c] * 4 * P + cb;
                 double w[4];
-                Vec4Load<TL>::get(M + size_t(imp[c]) * N * N + cl * N + row, w);
+                Vec4Load<TL>::get(M + size_t(imp[c]) * N * N +
+                                      (a.compact_schur ? schur_offset(BS, lr[c], lc[c], ra, cb)
+                                                       : cl * N + row),
+                                  w);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) v[r] += w[r];
             }

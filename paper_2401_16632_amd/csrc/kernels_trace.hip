@@ -313,12 +313,16 @@ __global__ __launch_bounds__(256) void k_block_inverse32(int ntf, const int* dia
             const int imp = valid ? ct[0] : -1;
             if (imp < 0) continue;
             const int lr = ct[1] >> 1, sr = ct[1] & 1, lc = ct[2] >> 1, sc = ct[2] & 1;
-            const size_t row = size_t(dg.n) + (lr * P + (sr ? P - 1 - qa : qa)) * 4 + (rr & 3);
+            const int ra = (sr ? P - 1 - qa : qa) * 4 + (rr & 3);   // row in face lr
+            const size_t row = size_t(dg.n) + lr * 4 * P + ra;
 #pragma unroll
             for (int c = 0; c < BS; ++c) {
                 const int qb = c >> 2;
-                const size_t cl = size_t(dg.n) + (lc * P + (sc ? P - 1 - qb : qb)) * 4 + (c & 3);
-                const size_t o = size_t(imp) * N * N + cl * N + row;
+                const int cb = (sc ? P - 1 - qb : qb) * 4 + (c & 3);  // column in face lc
+                const size_t cl = size_t(dg.n) + lc * 4 * P + cb;
+                const size_t o = size_t(imp) * N * N +
+                                 (dg.compact_schur ? schur_offset(BS, lr, lc, ra, cb)
+                                                   : cl * N + row);
                 acc[c] += L64 ? reinterpret_cast<const double*>(dg.M)[o]
                               : double(reinterpret_cast<const float*>(dg.M)[o]);
             }

@@ -391,6 +391,17 @@ CondenseLaunch condense_launch(hfr_solver_s* s, const double* u,
 // The Schur-only elimination in use forms the rows of A and B itself: no
 // tableau fill is queued for it (unless the blocks are kept for inspection,
 // which the fill writes).
+// The Newton path (Schur-only) with the blocked elimination and face
+// blocks of 20 or 24 rows keeps each element Schur complement as contiguous
+// face sub-blocks (schur_offset): its only readers are then the gathering
+// block inverse and the fused assembly with L Dinv, which read whole
+// sub-blocks instead of 4(p+1)-entry column pieces of the tableau.
+bool compact_schur(const hfr_solver_s* s) {
+    const int ck = s->ck > 0 ? s->ck : s->opts.condense_kernel;
+    return !s->mesh->efr && assemble_precondition_fused(s->mesh->P) &&
+           (s->bs == 20 || s->bs == 24) && (ck == HFR_CK_BLOCKED || ck == HFR_CK_BLOCKED_W8);
+}
+
 bool fused_fill(const hfr_solver_s* s) {
     const int ck = s->ck > 0 ? s->ck : s->opts.condense_kernel;
     return (ck == HFR_CK_BLOCKED || ck == HFR_CK_BLOCKED_W8) &&
@@ -435,6 +446,7 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
         c.yr = s->yr;                   // the sweep also forms the FP64 right-hand side
         c.z = s->zz;
         c.schur_only = schur_only ? 1 : 0;
+        c.compact_schur = schur_only && compact_schur(s) ? 1 : 0;
         HIP_TRY(launch_condense(m->ops, c, st));
         tend(s, tc, st);
     }
@@ -454,7 +466,9 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
     // with Lt = L Dinv after the inverses
     const bool fuse_pc = !m->efr && assemble_precondition_fused(m->P);
     const bool gather_diag = fuse_pc && (s->bs == 20 || s->bs == 24);
+    const int cpt = schur_only && compact_schur(s) ? 1 : 0;
     AssembleLaunch a{};
+    a.compact_schur = cpt;
     if (!m->efr) {
         a.nblocks = !fuse_pc ? s->nblocks : gather_diag ? 0 : s->nbr;
         a.blk_list = fuse_pc && !gather_diag ? s->diag_blk : nullptr;
@@ -476,7 +490,7 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
         tend(s, tk, st);
     }
     tk = tbegin(s, HFR_T_PCSETUP, st);
-    const DiagGather dg{s->contrib, s->M, s->n, s->m};
+    const DiagGather dg{s->contrib, s->M, s->n, s->m, cpt};
     HIP_TRY(launch_block_inverse_impl(s->nbr, s->bs, s->diag_blk, s->L64,
                                       s->L64 ? nullptr : s->L32,
                                       s->opts.precond, s->Dinv, s->flags + 1,
@@ -842,6 +856,7 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
             c.yr = s->yr;
             c.z = s->zz;
             c.schur_only = 1;
+            c.compact_schur = compact_schur(s) ? 1 : 0;
             c.go = s->go;
             HIP_TRY(launch_condense(m->ops, c, qs));
             s->spec_condensed = true;

@@ -455,8 +455,8 @@ fr_status hfr_get_blocks(hfr_solver_t s, double* blocks, void* stream);
  * of 20 or 24 rows (p = 4, 5; not with FR_MESH_EFR) it stores the Schur
  * complement instead at the start of the slot as 4 x 4 contiguous face
  * sub-blocks (sub-block (lr, lc) column-major at (4 lc + lr) bs^2, bs =
- * 4(p+1)), and then only A^-1 B at rows 0..n-1 of the columns n+b is
- * meaningful. */
+ * 4(p+1)), followed by -A^-1 B (n x m, column-major, rows in the pivot
+ * order above); nothing else in the slot is then meaningful. */
 fr_status hfr_get_factors(hfr_solver_t s, void* factors, int32_t* piv,
                           void* stream);
 /* Block-Jacobi preconditioner of the last linearisation (the trace solve of

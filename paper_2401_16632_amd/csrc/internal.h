@@ -155,13 +155,19 @@ struct CondenseLaunch {
     int compact_schur;       // blocked: the Schur complement L^k stored as
                              // 4 x 4 contiguous face sub-blocks at the start
                              // of the element's slot (schur_offset), where
-                             // the Schur-only path keeps nothing else
+                             // the Schur-only path keeps nothing else, and
+                             // -A^-1 B after them (schur_x_offset)
 };
 // compact Schur complement of an element (bs = 4P rows per face): entry
 // (row a, column b) of face sub-block (lr, lc), a and b in the element's
 // own point order, at this offset in the element's slot
 __host__ __device__ __forceinline__ size_t schur_offset(int bs, int lr, int lc, int a, int b) {
     return (size_t(lc * 4 + lr) * bs + b) * bs + a;
+}
+// and -A^-1 B (n x m, column-major, row p_k holding unknown k) right after
+// the 16 face sub-blocks
+__host__ __device__ __forceinline__ size_t schur_x_offset(int bs) {
+    return size_t(16) * bs * bs;
 }
 // element linearisation and the tableau [A B; C D] (must precede
 // launch_condense, which sweeps the tableau in place)
@@ -209,16 +215,18 @@ hipError_t launch_spmv(int ntf, int bs, const int* rowptr, const int* col,
                        hipStream_t st);
 // recovery; with efr the trace at the flux points is interpolated from the
 // trace nodes of trace_map (GLL basis of ops)
+// compact: -A^-1 B at schur_x_offset (CondenseLaunch.compact_schur)
 hipError_t launch_recover(const RefOps& ops, bool efr, int nimp, const void* M,
                           int precision, const int* piv, const double* yr,
                           const int* trace_map, const double* duhat, double* du,
-                          hipStream_t st, const int* gate = nullptr);
+                          hipStream_t st, const int* gate = nullptr, bool compact = false);
 // recovery and the Newton update (u_im += du, uhat += duhat) in one launch
 hipError_t launch_recover_update(const RefOps& ops, bool efr, int nimp, const void* M,
                                  int precision, const int* piv, const double* yr,
                                  const int* trace_map, const double* duhat, double* du,
                                  int Ne, const int* imp_list, double* u, int ntp4,
-                                 double* uhat, hipStream_t st, const int* gate = nullptr);
+                                 double* uhat, hipStream_t st, const int* gate = nullptr,
+                                 bool compact = false);
 
 // ---- interior-embedded trace (kernels_efr.hip) ------------------------
 // g at the trace nodes: sum over each node's incidences (slot

@@ -1352,12 +1352,14 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
         const int c = w + W * q;
         if (c < RT || c >= NCT) continue;              // uniform
         const int col = n + 16 * (c - RT) + i;
+        T* xc = a.compact_schur ? G + schur_x_offset(4 * P) + size_t(col - n) * n
+                                : G + size_t(col) * N;
 #pragma unroll
         for (int t = 0; t < RT; ++t)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = 16 * t + M::row(g, r);
-                if (row < n) G[size_t(col) * N + row] = acc[q][t][r];
+                if (row < n) xc[row] = acc[q][t][r];
             }
     }
     __syncthreads();

@@ -644,7 +644,7 @@ __global__ __launch_bounds__(256) void k_recover(RefOps o, int efr, int nimp,
                                                  const int* trace_map,
                                                  const double* duhat,
                                                  double* du, const int* gate,
-                                                 NewtonUpdate nu) {
+                                                 NewtonUpdate nu, int compact) {
     constexpr int NP = P * P, n = 4 * NP, m = 16 * P, N = n + m;
     constexpr int RG = NP;                          // groups of four rows
     constexpr int CS = (256 / RG < m ? 256 / RG : m);   // column sets
@@ -674,11 +674,15 @@ __global__ __launch_bounds__(256) void k_recover(RefOps o, int efr, int nimp,
     __syncthreads();
     if (t < RG * CS) {
         const int c = t / RG, g = t - c * RG;
-        const T* Mk = M + size_t(k) * N * N + size_t(n) * N + 4 * g;
+        // -A^-1 B: the columns n.. of the tableau, or compact after the
+        // element's Schur sub-blocks
+        const size_t ldx = compact ? size_t(n) : N;
+        const T* Mk = M + size_t(k) * N * N + (compact ? schur_x_offset(4 * P) : size_t(n) * N) +
+                      4 * g;
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         for (int b = c; b < m; b += CS) {
             double x[4];
-            Vec4<T>::get(Mk + size_t(b) * N, x);
+            Vec4<T>::get(Mk + size_t(b) * ldx, x);
             const double s = sloc[b];
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[r] += x[r] * s;
@@ -702,10 +706,10 @@ static hipError_t launch_recover_t(const RefOps& o, int efr, int nimp, const T* 
                                    const int* piv, const double* yr,
                                    const int* trace_map, const double* duhat,
                                    double* du, const int* gate, const NewtonUpdate& nu,
-                                   hipStream_t st) {
+                                   hipStream_t st, bool compact) {
     const int nbt = nu.u ? int((nu.ntp4 + 255) / 256) : 0;
     const dim3 grid(nimp + nbt), blk(256);
-#define HFR_RC(PP) hipLaunchKernelGGL((k_recover<T, PP>), grid, blk, 0, st, o, efr, nimp, M, piv, yr, trace_map, duhat, du, gate, nu); break;
+#define HFR_RC(PP) hipLaunchKernelGGL((k_recover<T, PP>), grid, blk, 0, st, o, efr, nimp, M, piv, yr, trace_map, duhat, du, gate, nu, compact ? 1 : 0); break;
     switch (o.P) {
         case 2: HFR_RC(2)
         case 3: HFR_RC(3)
@@ -721,29 +725,30 @@ static hipError_t launch_recover_t(const RefOps& o, int efr, int nimp, const T* 
 hipError_t launch_recover(const RefOps& ops, bool efr, int nimp, const void* M,
                           int precision, const int* piv, const double* yr,
                           const int* trace_map, const double* duhat, double* du,
-                          hipStream_t st, const int* gate) {
+                          hipStream_t st, const int* gate, bool compact) {
     if (nimp == 0) return hipSuccess;
     const NewtonUpdate nu{nullptr, nullptr, 0, 0, nullptr};
     if (precision == HFR_PREC_FP64)
         return launch_recover_t(ops, efr ? 1 : 0, nimp, reinterpret_cast<const double*>(M),
-                                piv, yr, trace_map, duhat, du, gate, nu, st);
+                                piv, yr, trace_map, duhat, du, gate, nu, st, compact);
     return launch_recover_t(ops, efr ? 1 : 0, nimp, reinterpret_cast<const float*>(M),
-                            piv, yr, trace_map, duhat, du, gate, nu, st);
+                            piv, yr, trace_map, duhat, du, gate, nu, st, compact);
 }
 
 hipError_t launch_recover_update(const RefOps& ops, bool efr, int nimp, const void* M,
                                  int precision, const int* piv, const double* yr,
                                  const int* trace_map, const double* duhat, double* du,
                                  int Ne, const int* imp_list, double* u, int ntp4,
-                                 double* uhat, hipStream_t st, const int* gate) {
+                                 double* uhat, hipStream_t st, const int* gate,
+                                 bool compact) {
     if (nimp == 0)
         return launch_newton_update(0, 0, Ne, imp_list, du, u, ntp4, duhat, uhat, st, gate);
     const NewtonUpdate nu{u, imp_list, Ne, ntp4, uhat};
     if (precision == HFR_PREC_FP64)
         return launch_recover_t(ops, efr ? 1 : 0, nimp, reinterpret_cast<const double*>(M),
-                                piv, yr, trace_map, duhat, du, gate, nu, st);
+                                piv, yr, trace_map, duhat, du, gate, nu, st, compact);
     return launch_recover_t(ops, efr ? 1 : 0, nimp, reinterpret_cast<const float*>(M),
-                            piv, yr, trace_map, duhat, du, gate, nu, st);
+                            piv, yr, trace_map, duhat, du, gate, nu, st, compact);
 }
 
 // ---- Newton update: u_im += du (scatter), uhat += duhat -----------------

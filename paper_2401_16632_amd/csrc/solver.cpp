@@ -94,6 +94,8 @@ struct hfr_solver_s {
     // checks, gated on the device by their outcome (spec_condensed)
     int newton_prev_iters = 0;
     bool spec_condensed = false;
+    bool compact = false;    // the last condensation stored the compact layout
+                             // (CondenseLaunch.compact_schur): recovery reads it
     bool verbose = false;
     int stage_calls = 0;
     double* V = nullptr;     // (restart+1) x N
@@ -447,6 +449,7 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
         c.z = s->zz;
         c.schur_only = schur_only ? 1 : 0;
         c.compact_schur = schur_only && compact_schur(s) ? 1 : 0;
+        s->compact = c.compact_schur != 0;
         HIP_TRY(launch_condense(m->ops, c, st));
         tend(s, tc, st);
     }
@@ -857,6 +860,7 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
             c.z = s->zz;
             c.schur_only = 1;
             c.compact_schur = compact_schur(s) ? 1 : 0;
+            s->compact = c.compact_schur != 0;
             c.go = s->go;
             HIP_TRY(launch_condense(m->ops, c, qs));
             s->spec_condensed = true;
@@ -871,7 +875,8 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         int tk = tbegin(s, HFR_T_RECOVER, qs);
         HIP_TRY(launch_recover_update(m->ops, m->efr, m->Nim, s->M, s->opts.precision,
                                       s->piv, s->yr, m->d_trace_map, s->duhat, s->du,
-                                      m->Ne, m->d_imp, u, 4 * m->Ntp, uhat, qs, gate));
+                                      m->Ne, m->d_imp, u, 4 * m->Ntp, uhat, qs, gate,
+                                      s->compact));
         tend(s, tk, qs);
         return queue_checks(gate);          // it_next: the iteration after this solve's
     };
@@ -1020,7 +1025,8 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         } else {                               // no trace unknowns: no chain ran
             tk = tbegin(s, HFR_T_RECOVER, st);
             HIP_TRY(launch_recover(m->ops, m->efr, m->Nim, s->M, s->opts.precision, s->piv,
-                                   s->yr, m->d_trace_map, s->duhat, s->du, st));
+                                   s->yr, m->d_trace_map, s->duhat, s->du, st, nullptr,
+                                   s->compact));
             HIP_TRY(launch_newton_update(m->Np, m->Nim, m->Ne, m->d_imp, s->du, u,
                                          4 * m->Ntp, s->duhat, uhat, st));
             tend(s, tk, st);
@@ -1321,7 +1327,8 @@ extern "C" fr_status hfr_recover(hfr_solver_t s, const double* duhat,
     if (fr_status ew = need_workspace(s)) return ew;
     fr_mesh_s* m = s->mesh;
     HIP_TRY(launch_recover(m->ops, m->efr, m->Nim, s->M, s->opts.precision, s->piv, s->yr,
-                           m->d_trace_map, duhat, du, hipStream_t(stream)));
+                           m->d_trace_map, duhat, du, hipStream_t(stream), nullptr,
+                           s->compact));
     return FR_OK;
 }
 

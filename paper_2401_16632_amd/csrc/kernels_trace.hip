@@ -292,13 +292,68 @@ __global__ __launch_bounds__(256) void k_block_inverse32(int ntf, const int* dia
                                                          DiagGather dg) {
     static_assert(BS > 16 && BS <= 32, "two blocks per wave need 16 < BS <= 32");
     __shared__ C prow[4][2][BS];
+    __shared__ __align__(16) double gsh[4][2][BS * BS];   // compact gather
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int half = lane >> 5, r = lane & 31;
     const int F = (blockIdx.x * 4 + wv) * 2 + half;
     const bool valid = F < ntf;
     const size_t blk = valid ? size_t(diag_blk[F]) * BS * BS : 0;
     C t[BS];
-    {
+    if (dg.compact_schur) {                       // uniform over the grid
+        // the element Schur sub-blocks are contiguous: each contribution in
+        // 16-byte pieces (four rows of a point in one column, which stay
+        // four consecutive trace rows), summed in FP64 into the block in LDS
+        // in trace order (0, then the first side, then the second), then
+        // each lane takes its row
+        constexpr int P = BS / 4, BB = BS * BS;
+        const size_t N = size_t(dg.n + dg.m);
+        double* gs = &gsh[wv][half][0];
+        for (int e = r; e < BB; e += 32) gs[e] = 0.0;
+        auto wave_sync = [] {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
+        wave_sync();
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            const int* ct = dg.blk_contrib + (blk / BB * 2 + cc) * 3;
+            const int imp = valid ? ct[0] : -1;
+            if (imp >= 0) {
+                const int lr = ct[1] >> 1, sr = ct[1] & 1, lc = ct[2] >> 1, sc = ct[2] & 1;
+                const size_t src = size_t(imp) * N * N + schur_offset(BS, lr, lc, 0, 0);
+                for (int e = r; e < BB / 4; e += 32) {
+                    const int be = (4 * e) / BS, qe = ((4 * e) % BS) >> 2;   // element column, point
+                    const int tr = (sr ? P - 1 - qe : qe) * 4;
+                    const int tc = (sc ? P - 1 - (be >> 2) : (be >> 2)) * 4 + (be & 3);
+                    double v[4];
+                    if (L64) {
+                        const double2 x0 = reinterpret_cast<const double2*>(
+                            reinterpret_cast<const double*>(dg.M) + src + 4 * e)[0];
+                        const double2 x1 = reinterpret_cast<const double2*>(
+                            reinterpret_cast<const double*>(dg.M) + src + 4 * e)[1];
+                        v[0] = x0.x; v[1] = x0.y; v[2] = x1.x; v[3] = x1.y;
+                    } else {
+                        const float4 x = *reinterpret_cast<const float4*>(
+                            reinterpret_cast<const float*>(dg.M) + src + 4 * e);
+                        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+                    }
+                    double* d = gs + tc * BS + tr;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) d[k] += v[k];
+                }
+            }
+            wave_sync();
+        }
+        const int rr = min(r, BS - 1);
+#pragma unroll
+        for (int c = 0; c < BS; ++c) {
+            const double a2 = gs[c * BS + rr];
+            C v = c == r ? C(1) : C(0);
+            if (valid) v = L64 ? C(a2) : C(float(a2));
+            t[c] = r < BS ? v : C(0);
+        }
+    } else {
         // the block summed from the element tableaux as the assembly forms it
         // (FP64 sum rounded to the storage precision of L)
         constexpr int P = BS / 4;

@@ -399,6 +399,7 @@ def oracle_leg(hp, torch, name, forms):
                       f"on both sides; max over conserved variables of "
                       f"|u - u_oracle|_inf / |u_oracle|_inf over the implicit elements "
                       f"(and over the trace)")
+    mesh.close()
     return base, errs
 
 
@@ -618,6 +619,7 @@ def main():
                   f"gmres/stage {np.mean(rr['gmres']):.1f}", file=sys.stderr, flush=True)
         line["efr_fp32_vs_fp64_rel_err"] = rel_diff(efr_states["fp32"], efr_states["fp64"])
         line["hfr_trace_unknowns"] = 4 * mesh.Ntp
+        mesh_e.close()
     if not args.no_edac:
         # the same O-grid and partition with the EDAC equations (theta = 100)
         mesh_d, u0d, dtd, _ = build_case(hp, args.workload, physics="edac")
@@ -631,8 +633,10 @@ def main():
             print(f"# edac form {f}: implicit ms/stage {np.mean(rr['impl_ms']):.3f}, "
                   f"gmres/stage {np.mean(rr['gmres']):.1f}", file=sys.stderr, flush=True)
         line["edac_fp32_vs_fp64_rel_err"] = rel_diff(edac_states["fp32"], edac_states["fp64"])
+        mesh_d.close()
     if not args.no_filter:
         line["modal_filter"] = filter_rate(torch, mesh, u0)
+    mesh.close()
     if not args.no_cpu_baseline:
         print("# oracle leg", file=sys.stderr, flush=True)
         base, errs = oracle_leg(hp, torch, args.oracle_workload, forms)

@@ -831,6 +831,10 @@ struct BlockShape {
     static constexpr size_t FILL_BYTES = OPS_BYTES + sizeof(CondShared<P>);
     static constexpr size_t SMEM0 = ELIM_BYTES > LIFT_BYTES ? ELIM_BYTES : LIFT_BYTES;
     static constexpr size_t SMEM = FUSE && FILL_BYTES > SMEM0 ? FILL_BYTES : SMEM0;
+    // fused: the face-point flux Jacobians kept from the linearisation to
+    // the lift in LDS past everything else (no round trip through memory)
+    static constexpr size_t LINR_BYTES = FUSE ? sizeof(double) * 2 * NF * 16 : 0;
+    static constexpr size_t SMEM_ALL = SMEM + LINR_BYTES;
 };
 
 template <typename T> struct MTile;
@@ -895,7 +899,7 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
     constexpr int W = S::W, CTW = S::CTW, RPL = S::RPL, LDP = S::LDP, LDG = S::LDG;
     constexpr int NB = S::NB, MW = S::MW;
     constexpr int NP = P * P;
-    __shared__ __align__(16) unsigned char smem[S::SMEM];
+    __shared__ __align__(16) unsigned char smem[S::SMEM_ALL];
     // -G of the last three panels, U of one tile per wave, the panel in row
     // layout
     T (*gbuf)[NPAD * LDG] = reinterpret_cast<T (*)[NPAD * LDG]>(smem);
@@ -936,7 +940,7 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
     CondShared<P>& sh = *reinterpret_cast<CondShared<P>*>(smem + S::OPS_BYTES);
     element_linearisation<P>(a, os, k, sh);            // ends with a barrier
     {
-        double* lin = a.lin + size_t(k) * 2 * 4 * P * 16;
+        double* lin = reinterpret_cast<double*>(smem + S::SMEM);
         for (int e2 = threadIdx.x; e2 < 4 * P * 16; e2 += blockDim.x) {
             lin[e2] = sh.Fu[e2 >> 4][e2 & 15];
             lin[4 * P * 16 + e2] = sh.Fh[e2 >> 4][e2 & 15];
@@ -1369,15 +1373,20 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
     // A^-1 r in unknown order and the face-point flux Jacobians to the LDS
     // the elimination has finished with, then L = D + C X and z = C A^-1 r
     constexpr int NF = S::NF, LDX = S::LDX, m = S::m;
-    double* fu = reinterpret_cast<double*>(smem);
+    // fused: the flux Jacobians are in LDS already (past the regions the
+    // elimination and the lift use); else from the fill's copy in memory
+    double* fu = S::FUSE ? reinterpret_cast<double*>(smem + S::SMEM)
+                         : reinterpret_cast<double*>(smem);
     double* fh = fu + NF * 16;
-    double* ys = fh + NF * 16;
+    double* ys = S::FUSE ? reinterpret_cast<double*>(smem) : fh + NF * 16;
     T* xs = reinterpret_cast<T*>(ys + n);
     {
-        const double* lin = a.lin + size_t(k) * 2 * NF * 16;
-        for (int e = threadIdx.x; e < NF * 16; e += blockDim.x) {
-            fu[e] = lin[e];
-            fh[e] = lin[NF * 16 + e];
+        if constexpr (!S::FUSE) {
+            const double* lin = a.lin + size_t(k) * 2 * NF * 16;
+            for (int e = threadIdx.x; e < NF * 16; e += blockDim.x) {
+                fu[e] = lin[e];
+                fh[e] = lin[NF * 16 + e];
+            }
         }
         if (threadIdx.x < 4)
             trf[threadIdx.x] = a.finfo[size_t(a.imp_list[k]) * 4 + threadIdx.x].role == ROLE_HFR;

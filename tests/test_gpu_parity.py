@@ -481,3 +481,47 @@ def test_condense_autotuner_choice():
     s2 = hp.Solver(pr.hm, precision="fp32", precond="fp32")
     hp.ImexStepper(pr.hm, s2, "HIMEX2C").step(dev(soa(u)), dt)
     assert s2.condense_choice() == (name, ms)
+
+
+@pytest.mark.parametrize("name,precision", [("cyl_p4", "fp32"), ("cyl_p4", "fp64"),
+                                            ("c1_p5", "fp32")])
+def test_compact_factors_after_newton(name, precision):
+    """The compact element layout of the Newton path (blocked elimination,
+    face blocks of 20 and 24 rows) as hfr_get_factors documents it: the
+    Schur complement D - C A^-1 B as 4 x 4 column-major face sub-blocks at
+    the start of the slot, then -A^-1 B (n x m, column-major, row p_k
+    holding unknown k), checked with NumPy on the element blocks of the same
+    (last) linearisation of an IMEX step."""
+    pr, u = _build(name)
+    hm = pr.hm
+    dt = _cfl_dt(pr) if name.startswith("cyl") else 0.01
+    s = hp.Solver(hm, precision=precision, precond=precision, keep_blocks=True,
+                  condense="blocked", rtol=1e-10, newton_tol=1e-13, max_iters=3000)
+    stp = hp.ImexStepper(hm, s, "HIMEX2C")
+    stp.step(dev(soa(u)), dt)
+    n, m = s.n, s.m
+    bs, k2 = m // 4, (n + m) ** 2
+    blk = torch.zeros(hm.Nim * k2, dtype=torch.float64, device="cuda")
+    s.get_blocks(blk)
+    F, piv = s.get_factors()
+    torch.cuda.synchronize()
+    G = host(blk).reshape(hm.Nim, n + m, n + m)
+    raw = F.transpose(1, 2).reshape(hm.Nim, k2).double().cpu().numpy()   # slot order
+    piv = piv.cpu().numpy().astype(np.int64)
+    tol = 1e-10 if precision == "fp64" else 2e-4
+    for k in range(hm.Nim):
+        A, B, C, D = G[k, :n, :n], G[k, :n, n:], G[k, n:, :n], G[k, n:, n:]
+        X = np.linalg.solve(A, B)
+        S = D - C @ X
+        scale = max(1.0, np.abs(S).max())
+        for lr in range(4):
+            for lc in range(4):
+                o = (4 * lc + lr) * bs * bs
+                sub = raw[k, o:o + bs * bs].reshape(bs, bs).T
+                ref = S[lr * bs:(lr + 1) * bs, lc * bs:(lc + 1) * bs]
+                err = np.abs(sub - ref).max()
+                assert err <= tol * scale, (k, lr, lc, err)
+        o = 16 * bs * bs
+        Xc = raw[k, o:o + n * m].reshape(m, n).T
+        err = np.abs(Xc[piv[k], :] + X).max()
+        assert err <= tol * max(1.0, np.abs(X).max()), (k, err)

@@ -134,6 +134,7 @@ struct hfr_solver_s {
         const double* uhat;
         const double* ustar;
         double aii_dt;
+        const double* R_out;
         hipGraph_t g;
         hipGraphExec_t x;
     };
@@ -779,9 +780,12 @@ fr_status tune_condense(hfr_solver_s* s, const double* u, const double* uhat,
     return FR_OK;
 }
 
+// R_out (optional): every check of an iterate also writes R^im(u, uhat)
+// there, so on convergence it holds R_i of the converged iterate (the last
+// check's, the same kernel on the same arguments as a fresh evaluation)
 fr_status newton(hfr_solver_s* s, double* u, double* uhat,
                  const double* ustar, double aii_dt, hfr_newton_stats* stats,
-                 hipStream_t st) {
+                 hipStream_t st, double* R_out = nullptr) {
     fr_mesh_s* m = s->mesh;
     hfr_newton_stats loc{};
     const int nu = 4 * m->Nim * m->Np;
@@ -837,7 +841,7 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
     };
     auto queue_checks = [&](const int* gate, bool first = false) -> fr_status {
         // the HFR gather of g also takes the norms' partial maxima
-        fr_status e2 = residual_internal(s, u, uhat, ustar, aii_dt, nullptr, qs, gate,
+        fr_status e2 = residual_internal(s, u, uhat, ustar, aii_dt, R_out, qs, gate,
                                          m->efr);
         if (e2) return e2;
         if (m->efr)
@@ -891,7 +895,7 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
         hfr_solver_s::IterGraph* gr = nullptr;
         for (auto& g : s->graphs)
             if (g.K == K && g.u == u && g.uhat == uhat && g.ustar == ustar &&
-                g.aii_dt == aii_dt)
+                g.aii_dt == aii_dt && g.R_out == R_out)
                 gr = &g;
         if (!gr) {
             if (!s->cst) HIP_TRY(hipStreamCreateWithFlags(&s->cst, hipStreamNonBlocking));
@@ -923,7 +927,7 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
                 (void)hipGraphDestroy(s->graphs.front().g);
                 s->graphs.erase(s->graphs.begin());
             }
-            s->graphs.push_back({K, u, uhat, ustar, aii_dt, g, x});
+            s->graphs.push_back({K, u, uhat, ustar, aii_dt, R_out, g, x});
             gr = &s->graphs.back();
         }
         HIP_TRY(hipGraphLaunch(gr->x, st));
@@ -1497,10 +1501,9 @@ extern "C" fr_status imex_stage(fr_mesh_t mesh, hfr_solver_t s,
             HIP_TRY(launch_trace_average_ops(m->ops, m->Ntp, m->Ne, m->d_tpside,
                                              m->d_imp, stt->u, stt->uhat, st));
         hfr_newton_stats ns{};
-        e = newton(s, stt->u, stt->uhat, s->ustar, aii_dt, &ns, st);
-        if (!e)
-            e = residual_internal(s, stt->u, stt->uhat, s->ustar, aii_dt,
-                                  stt->R_im + (I - 1) * pim, st);
+        // R_i of the converged iterate comes with Newton's last check
+        e = newton(s, stt->u, stt->uhat, s->ustar, aii_dt, &ns, st,
+                   stt->R_im + (I - 1) * pim);
         const fr_status e2 = sync_check(st);
         ns.implicit_ms = std::chrono::duration<double, std::milli>(
                              std::chrono::steady_clock::now() - t0).count();

@@ -90,8 +90,9 @@ struct hfr_solver_s {
     int newton_solve_iters[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int chunk_hint = 0;      // > 0: the first chunk of the next solve
     // linearisations of the last Newton solve; while an iteration index is
-    // below it the fused condensation of that iteration is queued with the
-    // checks, gated on the device by their outcome (spec_condensed)
+    // below it the condensation of that iteration (blocked elimination) is
+    // queued with the checks, gated on the device by their outcome
+    // (spec_condensed: one is queued)
     int newton_prev_iters = 0;
     bool spec_condensed = false;
     bool compact = false;    // the last condensation stored the compact layout
@@ -789,16 +790,17 @@ fr_status newton(hfr_solver_s* s, double* u, double* uhat,
     fr_mesh_s* m = s->mesh;
     hfr_newton_stats loc{};
     const int nu = 4 * m->Nim * m->Np;
-    // trace solves inside this Newton iteration take the forcing term
+    // trace solves inside this Newton solve take the forcing term; the
+    // per-solve state is cleared however the solve ends
     s->forcing = s->opts.gmres_forcing_max > 0.0;
-    struct ForcingOff {
+    struct NewtonScope {
         hfr_solver_s* s;
-        ~ForcingOff() {
+        ~NewtonScope() {
             s->forcing = false;
             s->chunk_hint = 0;
             s->spec_condensed = false;
         }
-    } forcing_off{s};
+    } newton_scope{s};
     // the tolerance newton_tol * max(1, |u*|) is formed on the device by the
     // norms kernel and published with the norms (no readback here)
     HIP_TRY(launch_absmax(nu, ustar, s->scratch, std::min(1024, std::max(1, (nu + 255) / 256)),

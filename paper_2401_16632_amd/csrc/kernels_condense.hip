@@ -1020,7 +1020,8 @@ __attribute__((amdgpu_waves_per_eu(BlockShape<P, T, WSEL>::WPE))) void k_condens
             // the lane's trace column (face f2, point q2): a row point couples
             // to it only on the grid line through q2 normal to face f2, with
             // the lifting weight of its side; face flux Jacobian column cc
-            // loaded once, the rest branch-free as above
+            // loaded once, the coupling test and weight by selects (no
+            // branches per lane)
             const int tb = bc - NP, f2 = tb / P, q2 = tb - f2 * P;
             const bool tr = sh.tr[f2] != 0;
             double fh[4];

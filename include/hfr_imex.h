@@ -424,7 +424,10 @@ fr_status hfr_trace_solve(hfr_solver_t s, double* duhat,
 fr_status hfr_recover(hfr_solver_t s, const double* duhat, double* du,
                       void* stream);
 
-/* Inspection helpers (tests): y = L x with the assembled trace matrix;
+/* Inspection helpers (tests): y = L x with the assembled trace matrix (the
+ * Newton path with the compact element layout forms only L Dinv, and its
+ * restarts sum L x from the element sub-blocks; hfr_trace_matvec then forms
+ * L first);
  * copies of t [Ntp][4], h [4][Nim][Np], g [Ntp][4] of the last
  * hfr_assemble_condense (device pointers, any may be NULL); element blocks
  * kept with keep_blocks=1, FP64 row-major (n+m) x (n+m) per implicit

@@ -45,6 +45,11 @@ struct GmresArgs {
     int kmax;                // per row, {-1, -1} past its end (product kernel)
     const double* L64;       // original matrix (true residual)
     const float* L32;
+    // with L64 and L32 null: the true residual's L x from the element Schur
+    // sub-blocks (compact layout, schur_offset) and the block contributions
+    const void* Mel;
+    const int* econtrib;     // [blocks][2][3] as AssembleLaunch.blk_contrib
+    int nloc, mloc, el64;    // element block sizes n, m; Mel in FP64
     const double* Lt64;      // preconditioned matrix L Dinv
     const float* Lt32;
     const void* Dinv;
@@ -71,7 +76,8 @@ hipError_t launch_precondition_matrix(int nblocks, int bs, const int* col,
                                       float* Lt32, hipStream_t st);
 // L and Lt = L Dinv of every block in one pass from the element tableaux
 // (face blocks of 16, 20 and 24: orders with assemble_precondition_fused);
-// Dinv must be in place, and a.blk_list null
+// Dinv must be in place, and a.blk_list null; with a.L64 / a.L32 null only
+// Lt is written
 bool assemble_precondition_fused(int P);
 hipError_t launch_assemble_precondition(const AssembleLaunch& a, const int* col, int pc,
                                         const void* Dinv, double* Lt64, float* Lt32,

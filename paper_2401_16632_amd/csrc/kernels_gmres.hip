@@ -666,6 +666,36 @@ __global__ __launch_bounds__(kThr) void k_gmres_update(GmresArgs a, double* x, i
     }
 }
 
+// (L x)_r summed from the element Schur sub-blocks: every block (F, G) of
+// row F as the assembly forms it (the one or two element contributions,
+// each side's points in its own order), the part-th blocks of the row
+__device__ __forceinline__ double row_share_elem(const GmresArgs& a, const double* x, int r) {
+    const int bs = a.bs, P = bs / 4;
+    const int F = r / bs, aa = r - F * bs, qa = aa >> 2;
+    const int part = threadIdx.x >> 6;
+    const size_t N = size_t(a.nloc + a.mloc);
+    double acc = 0.0;
+    for (int p = a.rowptr[F] + part; p < a.rowptr[F + 1]; p += 4) {
+        const double* xg = x + size_t(a.col[p]) * bs;
+        for (int c = 0; c < 2; ++c) {
+            const int* ct = a.econtrib + (size_t(p) * 2 + c) * 3;
+            const int imp = ct[0];
+            if (imp < 0) continue;
+            const int lr = ct[1] >> 1, sr = ct[1] & 1, lc = ct[2] >> 1, sc = ct[2] & 1;
+            const int ra = (sr ? P - 1 - qa : qa) * 4 + (aa & 3);
+            const size_t base = size_t(imp) * N * N + schur_offset(bs, lr, lc, ra, 0);
+            for (int cc = 0; cc < bs; ++cc) {
+                const int qb = cc >> 2;
+                const size_t o = base + size_t((sc ? P - 1 - qb : qb) * 4 + (cc & 3)) * bs;
+                const double v = a.el64 ? reinterpret_cast<const double*>(a.Mel)[o]
+                                        : double(reinterpret_cast<const float*>(a.Mel)[o]);
+                acc = fma(v, xg[cc], acc);
+            }
+        }
+    }
+    return acc;
+}
+
 // ---- restart: r = t - L x (FP64), partial |r|^2 ---------------------------
 // Product decomposition of A (a.nblkA workgroups of 256 threads).
 // first: x is zeroed here (the solve starts from zero), r = t
@@ -688,7 +718,8 @@ __global__ __launch_bounds__(256) void k_gmres_residual(GmresArgs a,
             double acc = 0.0;
             if (r < r1)
                 acc = a.L64 ? row_share<false>(a, a.L64, x, r)
-                            : row_share<false>(a, a.L32, x, r);
+                      : a.L32 ? row_share<false>(a, a.L32, x, r)
+                              : row_share_elem(a, x, r);
             sacc[q][part][lr] = acc;
         }
         __syncthreads();
@@ -1012,7 +1043,7 @@ __global__ __launch_bounds__(256) void k_assemble_precondition(AssembleLaunch a,
                 for (int r = 0; r < 4; ++r) v[r] += w[r];
             }
             TL* dst = &lsh[wv][b * BS + 4 * qa];
-            Vec4Load<TL>::put(Lout + lb + size_t(b) * BS + 4 * qa, v);
+            if (Lout) Vec4Load<TL>::put(Lout + lb + size_t(b) * BS + 4 * qa, v);
             Vec4Load<TL>::put(dst, v);
         }
     }
@@ -1102,7 +1133,8 @@ hipError_t launch_assemble_precondition(const AssembleLaunch& a, const int* col,
     if (a.nblocks == 0) return hipSuccess;
     if (!assemble_precondition_fused(a.P) || a.blk_list) return hipErrorInvalidValue;
     const bool f64 = a.precision == HFR_PREC_FP64;
-    if (f64 ? !(a.L64 && Lt64) : !(a.L32 && Lt32)) return hipErrorInvalidValue;
+    // L itself is written only where given (a.L64 / a.L32; Lt always)
+    if (f64 ? !Lt64 : !Lt32) return hipErrorInvalidValue;
     if (a.P == 4) {
         if (f64) launch_ap_t<4, double>(a, col, pc, Dinv, a.L64, Lt64, st);
         else launch_ap_t<4, float>(a, col, pc, Dinv, a.L32, Lt32, st);

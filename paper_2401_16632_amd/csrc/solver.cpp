@@ -97,6 +97,10 @@ struct hfr_solver_s {
     bool spec_condensed = false;
     bool compact = false;    // the last condensation stored the compact layout
                              // (CondenseLaunch.compact_schur): recovery reads it
+    bool l_valid = true;     // L (unpreconditioned) formed for the last
+                             // linearisation: the compact Newton path forms only
+                             // L Dinv, the true residual then sums L x from the
+                             // element sub-blocks and hfr_trace_matvec forms L
     bool verbose = false;
     int stage_calls = 0;
     double* V = nullptr;     // (restart+1) x N
@@ -456,6 +460,7 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
         tend(s, tc, st);
     }
     int tk = -1;
+    s->l_valid = true;                  // unless the compact path below skips L
     if (s->nbr == 0) return FR_OK;
     if (m->efr) {
         tk = tbegin(s, HFR_T_ASSEMBLE, st);
@@ -503,8 +508,13 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
     if (fuse_pc) {
         a.nblocks = s->nblocks;
         a.blk_list = nullptr;
+        if (cpt) {                       // Newton reads L only at a restart
+            a.L64 = nullptr;
+            a.L32 = nullptr;
+        }
         HIP_TRY(launch_assemble_precondition(a, s->col, s->opts.precond, s->Dinv,
                                              s->Lt64, s->Lt32, st));
+        s->l_valid = !cpt;
     } else {
         HIP_TRY(launch_precondition_matrix(s->nblocks, s->bs, s->col, s->L64,
                                            s->L64 ? nullptr : s->L32,
@@ -512,6 +522,34 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
                                            s->Lt32, st));
     }
     tend(s, tk, st);
+    return FR_OK;
+}
+
+// L of the last linearisation where the compact Newton path formed only
+// L Dinv: the fused assembly again, from the element sub-blocks, with L
+// (Lt comes out the same)
+fr_status form_L(hfr_solver_s* s, hipStream_t st) {
+    if (s->l_valid) return FR_OK;
+    fr_mesh_s* m = s->mesh;
+    AssembleLaunch a{};
+    a.nblocks = s->nblocks;
+    a.blk_contrib = s->contrib;
+    a.ntf = m->Ntf;
+    a.tside = s->tside;
+    a.M = s->M;
+    a.precision = s->opts.precision;
+    a.P = m->P;
+    a.n = s->n;
+    a.m = s->m;
+    a.L64 = s->L64;
+    a.L32 = s->L32;
+    a.t = s->t;
+    a.g = s->g;
+    a.z = s->zz;
+    a.compact_schur = 1;
+    HIP_TRY(launch_assemble_precondition(a, s->col, s->opts.precond, s->Dinv, s->Lt64,
+                                         s->Lt32, st));
+    s->l_valid = true;
     return FR_OK;
 }
 
@@ -567,8 +605,13 @@ GmresArgs gmres_args(hfr_solver_s* s) {
     a.col = s->col;
     a.ell = s->ell;
     a.kmax = s->kmax;
-    a.L64 = s->L64;
-    a.L32 = s->L64 ? nullptr : s->L32;
+    a.L64 = s->l_valid ? s->L64 : nullptr;
+    a.L32 = s->l_valid && !s->L64 ? s->L32 : nullptr;
+    a.Mel = s->M;
+    a.econtrib = s->contrib;
+    a.nloc = s->n;
+    a.mloc = s->m;
+    a.el64 = s->opts.precision == HFR_PREC_FP64 ? 1 : 0;
     a.Lt64 = s->Lt64;
     a.Lt32 = s->Lt64 ? nullptr : s->Lt32;
     a.Dinv = s->Dinv;
@@ -1343,6 +1386,7 @@ extern "C" fr_status hfr_trace_matvec(hfr_solver_t s, const double* x,
     if (!s || (s->N && (!x || !y))) return fail(FR_E_INVALID, "null argument");
     if (fr_status ew = need_workspace(s)) return ew;
     fr_mesh_s* m = s->mesh;
+    if (fr_status el = form_L(s, hipStream_t(stream))) return el;
     HIP_TRY(launch_spmv(s->nbr, s->bs, s->rowptr, s->col, s->L64,
                         s->L64 ? nullptr : s->L32, x, y, 1.0, nullptr,
                         hipStream_t(stream)));

@@ -197,6 +197,11 @@ struct AssembleLaunch {
     const double* g;         // [Ntf*bs]  assembled transmission residual
     const double* z;         // [Nim][m]  C A^-1 r per element
     int compact_schur;       // element Schur blocks at schur_offset
+    // fused assembly with L Dinv by block column (null: by block): per trace
+    // face G (ntf of them) the ids of the blocks (F, G), kmax per face, -1
+    // past the last
+    const int* tcol;
+    int kmax;
 };
 hipError_t launch_assemble(const AssembleLaunch& a, hipStream_t st);
 // the diagonal blocks of L read by the block-Jacobi inverse straight from

@@ -22,6 +22,8 @@
 // are reduced in a fixed order by the consuming kernel, so results are
 // deterministic.  Once the cycle has converged every later kernel of the
 // cycle returns at entry.
+#include <type_traits>
+
 #include "internal.h"
 #include "gmres.h"
 #include "wave_ops.h"
@@ -982,7 +984,7 @@ __global__ __launch_bounds__(256) void k_precondition_matrix16(int nblocks, cons
 // multiplied.  The diagonal blocks and their
 // inverses must already exist (assembled and inverted first); their L
 // blocks are rewritten with the same values.
-template <int BS, int P, typename TL, typename TD>
+template <int BS, int P, typename TL, typename TD, bool CM>
 __global__ __launch_bounds__(256) void k_assemble_precondition(AssembleLaunch a, const int* col,
                                                                const TD* Dinv, TL* Lout,
                                                                TL* Lt) {
@@ -991,23 +993,38 @@ __global__ __launch_bounds__(256) void k_assemble_precondition(AssembleLaunch a,
     constexpr int NT = BS > 16 ? 2 : 1;            // 16x16 tiles per block side
     constexpr int Q = BB / 4;                      // 4-entry pieces of a block
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int p = blockIdx.x * 4 + wv;
     __shared__ __align__(16) TL lsh[4][BB];        // L (column-major), then Lt (row-major)
     __shared__ __align__(16) TL dsh[4][BB];        // Dinv (column-major)
-    if (p >= a.nblocks) return;                    // whole wave
     const int i = lane & 15, g = lane >> 4;
     const size_t N = size_t(a.n + a.m);
     const TL* M = reinterpret_cast<const TL*>(a.M);
-    const size_t lb = size_t(p) * BB;
-    // the column face's Dinv block does not depend on the gather: issued first
-    const size_t db = size_t(col[p]) * BB;
-#pragma unroll
-    for (int e0 = 0; e0 < Q; e0 += 64) {
-        const int e = e0 + lane;
-        if (e < Q) {
+    // column mode (a.tcol): the workgroup owns block column G = blockIdx.x,
+    // its Dinv staged once in LDS for the four waves, which take the
+    // column's blocks k = wv, wv + 4, ...; row mode: one block per wave,
+    // the wave stages its column face's Dinv itself
+    constexpr bool cm = CM;                         // a.tcol given
+    if constexpr (cm) {
+        const size_t db = size_t(blockIdx.x) * BB;
+        for (int e = threadIdx.x; e < Q; e += blockDim.x) {
             double v[4];
             load4_pc(Dinv + db + 4 * size_t(e), v);
-            Vec4Load<TL>::put(&dsh[wv][4 * e], v);
+            Vec4Load<TL>::put(&dsh[0][4 * e], v);
+        }
+        __syncthreads();
+    }
+    auto one_block = [&](const int p, const int ds) {   // ds: the dsh slot holding Dinv
+    const size_t lb = size_t(p) * BB;
+    if constexpr (!cm) {
+        // the column face's Dinv block does not depend on the gather: issued first
+        const size_t db = size_t(col[p]) * BB;
+#pragma unroll
+        for (int e0 = 0; e0 < Q; e0 += 64) {
+            const int e = e0 + lane;
+            if (e < Q) {
+                double v[4];
+                load4_pc(Dinv + db + 4 * size_t(e), v);
+                Vec4Load<TL>::put(&dsh[ds][4 * e], v);
+            }
         }
     }
     int imp[2], lr[2], sr[2], lc[2], sc[2];
@@ -1059,7 +1076,7 @@ __global__ __launch_bounds__(256) void k_assemble_precondition(AssembleLaunch a,
         for (int kk = 0; kk < KC; ++kk) {
             const int x = 16 * t + i;
             const TL va = lsh[wv][(4 * kk + g) * BS + min(x, BS - 1)];
-            const TL vb = dsh[wv][min(x, BS - 1) * BS + 4 * kk + g];
+            const TL vb = dsh[ds][min(x, BS - 1) * BS + 4 * kk + g];
             av[t][kk] = x < BS ? va : TL(0);
             bv[t][kk] = x < BS ? vb : TL(0);
         }
@@ -1107,22 +1124,54 @@ __global__ __launch_bounds__(256) void k_assemble_precondition(AssembleLaunch a,
                 *reinterpret_cast<const float4*>(&lsh[wv][ar * BS + c * CW]);
         }
     }
+    };
+    if constexpr (cm) {
+        const int* tc = a.tcol + size_t(blockIdx.x) * a.kmax;
+        for (int k = wv; k < a.kmax; k += 4) {
+            const int p = tc[k];
+            if (p < 0) break;                      // uniform over the wave
+            one_block(p, 0);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();       // lsh[wv] free for the next block
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    } else {
+        const int p = blockIdx.x * 4 + wv;
+        if (p < a.nblocks) one_block(p, wv);
+    }
+}
+
+template <int BS, int P, typename TL, bool CM>
+static void launch_ap_pc(const AssembleLaunch& a, dim3 grid, const int* col, int pc,
+                         const void* Dinv, TL* Lout, TL* Lt, hipStream_t st) {
+    const dim3 blk(256);
+    if (pc == HFR_PC_FP64)
+        hipLaunchKernelGGL((k_assemble_precondition<BS, P, TL, double, CM>), grid, blk, 0, st,
+                           a, col, reinterpret_cast<const double*>(Dinv), Lout, Lt);
+    else if (pc == HFR_PC_FP32)
+        hipLaunchKernelGGL((k_assemble_precondition<BS, P, TL, float, CM>), grid, blk, 0, st,
+                           a, col, reinterpret_cast<const float*>(Dinv), Lout, Lt);
+    else
+        hipLaunchKernelGGL((k_assemble_precondition<BS, P, TL, uint16_t, CM>), grid, blk, 0,
+                           st, a, col, reinterpret_cast<const uint16_t*>(Dinv), Lout, Lt);
 }
 
 template <int P, typename TL>
-static void launch_ap_t(const AssembleLaunch& a, const int* col, int pc, const void* Dinv,
+static void launch_ap_t(const AssembleLaunch& a0, const int* col, int pc, const void* Dinv,
                         TL* Lout, TL* Lt, hipStream_t st) {
     constexpr int BS = 4 * P;
-    const dim3 grid((a.nblocks + 3) / 4), blk(256);
-    if (pc == HFR_PC_FP64)
-        hipLaunchKernelGGL((k_assemble_precondition<BS, P, TL, double>), grid, blk, 0, st, a,
-                           col, reinterpret_cast<const double*>(Dinv), Lout, Lt);
-    else if (pc == HFR_PC_FP32)
-        hipLaunchKernelGGL((k_assemble_precondition<BS, P, TL, float>), grid, blk, 0, st, a,
-                           col, reinterpret_cast<const float*>(Dinv), Lout, Lt);
-    else
-        hipLaunchKernelGGL((k_assemble_precondition<BS, P, TL, uint16_t>), grid, blk, 0, st, a,
-                           col, reinterpret_cast<const uint16_t*>(Dinv), Lout, Lt);
+    // by block column only for FP32/BF16 L, where the Dinv re-reads are the
+    // traffic saved; FP64 L keeps one block per wave (a column's blocks
+    // spread unevenly over four waves)
+    constexpr bool CM = !std::is_same<TL, double>::value;
+    AssembleLaunch a = a0;
+    if (!CM) a.tcol = nullptr;
+    const dim3 grid(a.tcol ? a.ntf : (a.nblocks + 3) / 4), blk(256);
+    if (a.tcol) {
+        if constexpr (CM) launch_ap_pc<BS, P, TL, true>(a, grid, col, pc, Dinv, Lout, Lt, st);
+    } else {
+        launch_ap_pc<BS, P, TL, false>(a, grid, col, pc, Dinv, Lout, Lt, st);
+    }
 }
 
 bool assemble_precondition_fused(int P) { return P == 4 || P == 5 || P == 6; }

@@ -54,6 +54,8 @@ struct hfr_solver_s {
     double* du = nullptr;    // [4][Nim][Np]
     double* duhat = nullptr; // [N]
     int* rowptr = nullptr;
+    int* tcol = nullptr;     // [nbr][kmax] blocks (F, G) of block column G, -1
+                             // past the last (null: not every column fits)
     int* col = nullptr;
     int* ell = nullptr;      // rows padded to kmax {block, column} pairs
     int kmax = 0;
@@ -220,7 +222,7 @@ void free_solver(hfr_solver_s* s) {
         (void)hipEventDestroy(p.second);
     }
     s->pool.clear();
-    void* ptrs[] = {s->rowptr, s->col, s->ell, s->contrib, s->tside, s->diag_blk,
+    void* ptrs[] = {s->rowptr, s->tcol, s->col, s->ell, s->contrib, s->tside, s->diag_blk,
                     s->efr_cptr, s->efr_contrib, s->ws_owned};
     for (void* p : ptrs) (void)hipFree(p);
 }
@@ -508,6 +510,8 @@ fr_status condense_internal(hfr_solver_s* s, const double* u,
     if (fuse_pc) {
         a.nblocks = s->nblocks;
         a.blk_list = nullptr;
+        a.tcol = s->tcol;                // by block column (null: by block)
+        a.kmax = s->kmax;
         if (cpt) {                       // Newton reads L only at a restart
             a.L64 = nullptr;
             a.L32 = nullptr;
@@ -547,6 +551,8 @@ fr_status form_L(hfr_solver_s* s, hipStream_t st) {
     a.g = s->g;
     a.z = s->zz;
     a.compact_schur = 1;
+    a.tcol = s->tcol;
+    a.kmax = s->kmax;
     HIP_TRY(launch_assemble_precondition(a, s->col, s->opts.precond, s->Dinv, s->Lt64,
                                          s->Lt32, st));
     s->l_valid = true;
@@ -1200,6 +1206,22 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
             ell[2 * i] = p;
             ell[2 * i + 1] = col[p];
         }
+    // the blocks of each block column (HFR: the block pattern is that of
+    // face adjacency, symmetric, so a column holds at most kmax blocks)
+    std::vector<int> tcol;
+    if (!m->efr) {
+        tcol.assign(size_t(s->nbr) * std::max(1, s->kmax), -1);
+        std::vector<int> cnt(s->nbr, 0);
+        for (int a = 0; a < s->nbr && !tcol.empty(); ++a)
+            for (int p = rowptr[a]; p < rowptr[a + 1]; ++p) {
+                const int G = col[p];
+                if (cnt[G] >= s->kmax) {
+                    tcol.clear();
+                    break;
+                }
+                tcol[size_t(G) * s->kmax + cnt[G]++] = p;
+            }
+    }
     size_t& tot = s->table_bytes;
     const size_t scal = o->precision == HFR_PREC_FP64 ? 8 : 4;
     const size_t nimp = size_t(m->Nim), np4 = 4 * size_t(m->Np);
@@ -1207,6 +1229,7 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
     fr_status e;
     // read-only tables: library-owned
     if ((e = dalloc(&s->rowptr, rowptr.size(), tot)) ||
+        (e = dalloc(&s->tcol, tcol.size(), tot)) ||
         (e = dalloc(&s->col, col.size(), tot)) ||
         (e = dalloc(&s->ell, ell.size(), tot)) ||
         (e = dalloc(&s->contrib, contrib.size(), tot)) ||
@@ -1279,6 +1302,7 @@ extern "C" fr_status hfr_solver_create(fr_mesh_t mesh, const hfr_opts* o,
                          : hipMemcpy(d, h.data(), 4 * h.size(), hipMemcpyHostToDevice);
     };
     if (up(s->rowptr, rowptr) != hipSuccess || up(s->col, col) != hipSuccess ||
+        up(s->tcol, tcol) != hipSuccess ||
         up(s->ell, ell) != hipSuccess ||
         up(s->contrib, contrib) != hipSuccess || up(s->tside, tside) != hipSuccess ||
         up(s->diag_blk, diag) != hipSuccess ||
